@@ -1,0 +1,161 @@
+/*
+ * lsh.h -- C ABI of the MI355X (gfx950) HBS-preconditioned Lippmann-Schwinger
+ * solver.
+ *
+ * Method: Gopal & Martinsson, "An accelerated, high-order accurate direct
+ * solver for the Lippmann-Schwinger equation for acoustic scattering in the
+ * plane" (arXiv 2007.12718).
+ *
+ * Problem (paper Sec. 1, eqs. (ansatz), (kernel), (ls); Sec. 2.2, eqs.
+ * (corrected), (linsys), (Gmat)): on an n x n cell-centred grid of mesh h
+ * (node (i1, i2) at (x0 + (i1 + 1/2) h, y0 + (i2 + 1/2) h)), find sigma with
+ *     sigma_i + kappa^2 b_i sum_j K_ij sigma_j = -kappa^2 b_i u_inc_i,
+ *     K_ij = h^2 [ (i/4) H0(kappa |x_i - x_j|) [i != j] + tau_{x_j - x_i} ],
+ * tau the order-p corrected-trapezoidal weights (p = 4, 6, 8, 10; Fig. 2
+ * stencils), and the scattered field u = K sigma.
+ *
+ * Pipeline: lsh_plan_create (tree, weights, kernel table, proxy-source row IDs
+ * of the b-independent 4th-order G, Sec. 3.2) -> lsh_factor_create (Algorithm
+ * 1 for a given b) -> lsh_solve (flexible GMRES on the order-p operator
+ * applied by FFT, right-preconditioned with Algorithm 2; Sec. 5).
+ *
+ * Conventions for every call:
+ *  - Field arrays are interleaved complex FP64 ("double2"), C order
+ *    [nrhs][n][n] with x1 fastest; b is real FP64 [n][n].
+ *  - Array pointers are DEVICE pointers owned by the caller unless the
+ *    argument says "host".  The library reads inputs and writes outputs only
+ *    on the given stream; it keeps no reference to caller arrays after a call
+ *    returns, except that a factor keeps a private copy of b.
+ *  - Handles own their device memory (allocated by the library with
+ *    hipMalloc); destroy them with the matching *_destroy call.  A factor
+ *    refers to its plan: destroy the factor first.
+ *  - The stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that must read back small device values synchronise the stream
+ *    and say so.
+ *  - Return value: LSH_OK (0), LSH_NOT_CONVERGED (1: outputs hold the best
+ *    iterate), or a negative error code; lsh_last_error() gives the message
+ *    of the calling thread's last failure.  No C++ exception crosses the
+ *    ABI.  Handles are not thread-safe.
+ */
+#ifndef LSH_H
+#define LSH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LSH_OK = 0,
+  LSH_NOT_CONVERGED = 1,
+  LSH_ERR_INVALID_ARG = -1,
+  LSH_ERR_INPUT_NONFINITE = -2,
+  LSH_ERR_SINGULAR = -3,
+  LSH_ERR_HIP = -4,
+  LSH_ERR_NOMEM = -5,
+  LSH_ERR_UNSUPPORTED = -6
+};
+
+enum { LSH_FP64 = 0, LSH_FP32 = 1 };
+
+#define LSH_MAX_LEVELS 32
+#define LSH_MAX_ITERS 200
+
+typedef struct lsh_plan_s* lsh_plan_t;
+typedef struct lsh_factor_s* lsh_factor_t;
+
+/* Problem and method description. */
+typedef struct {
+  int n;            /* grid side (n x n nodes); n / leaf must be a power of two */
+  double h;         /* mesh width (unit square: 1/n) */
+  double x0, y0;    /* lower-left corner of the grid square (unit square: -0.5) */
+  double kappa;     /* wavenumber > 0 */
+  int op_order;     /* 4, 6, 8 or 10: correction order of the GMRES operator */
+  int leaf;         /* leaf box side in nodes (e.g. 8) */
+  double tol;       /* compression tolerance eps (>= 0; 0 = exact full-rank HBS) */
+  int proxy_width;  /* layers of proxy points around each box (1..3) */
+  int hbs_prec;     /* LSH_FP64 or LSH_FP32: precision of factor and apply */
+} lsh_desc;
+
+typedef struct {
+  double tol;       /* stop when ||f - A x|| / ||f|| < tol (true residual re-checked) */
+  int maxit;        /* at most LSH_MAX_ITERS */
+  int precondition; /* 1: HBS preconditioner (default); 0: none */
+} lsh_solve_opts;
+
+typedef struct {
+  int iterations;                       /* FGMRES iterations of the last rhs */
+  double residual;                      /* Givens estimate at exit (last rhs) */
+  double true_residual;                 /* max over rhs of ||f - A sigma|| / ||f|| */
+  double history[LSH_MAX_ITERS + 1];    /* residual estimates of the last rhs */
+  double ms_precond, ms_operator, ms_ortho;  /* time per phase (last solve) */
+} lsh_info;
+
+/* ---- plan: paper Sec. 3 (tree, proxy-source IDs; independent of b) ----
+ * Builds the tree (Sec. 3.1-3.2), the correction weights (Sec. 2.2), the
+ * kernel offset table, one row ID per level (eqs. (leafid), (proxy),
+ * (parentid); translation invariance), the sibling blocks (eq. (sibint)) and
+ * the spectrum of the order-p operator for the FFT matvec.
+ * Synchronises the stream (ranks are read back level by level).
+ * Errors: LSH_ERR_INVALID_ARG for a bad descriptor; LSH_ERR_UNSUPPORTED for
+ * sizes beyond the kernels' limits. */
+int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan);
+int lsh_plan_destroy(lsh_plan_t plan);
+/* host: number of levels L and the ranks k_l (l = 0..L; k_0 = 0) */
+int lsh_plan_ranks(lsh_plan_t plan, int* L, int* ranks /* host, L+1 */);
+/* host: level-l compression data for inspection.  m = candidate rows,
+ * k = rank; copies (if non-NULL) J (host int[k], candidate indices in pivot
+ * order), cand (host int[2m], box-local lattice coordinates) and U (device
+ * double2[m*k], row-major, FP64).  Synchronises the stream. */
+int lsh_plan_level(lsh_plan_t plan, int level, int* m, int* k, int* J, int* cand, void* U, void* stream);
+/* host: sibling block G_ab of parent level l (device double2[c*c]) and the
+ * leaf block (level = -1, device double2[mL*mL]); c via *rows. */
+int lsh_plan_block(lsh_plan_t plan, int level, int* rows, void* out, void* stream);
+/* device out[(D+1)^2]: offset table T[dy][dx] = h^2 (i/4) H0(kappa h |d|),
+ * T[0][0] = h^2 tau_0 (4th order); D via *D. */
+int lsh_plan_table(lsh_plan_t plan, int* D, void* out, void* stream);
+
+/* ---- factor: Algorithm 1 (leaf inverses, scattering matrices, merges) ----
+ * b: device double[n*n].  Errors: LSH_ERR_INPUT_NONFINITE (non-finite b),
+ * LSH_ERR_SINGULAR (zero pivot in a local inverse). */
+int lsh_factor_create(lsh_plan_t plan, const double* b, void* stream, lsh_factor_t* factor);
+int lsh_factor_destroy(lsh_factor_t factor);
+
+/* y = M x: Algorithm 2 (M ~ (I + B G)^{-1}); transpose = 1 applies M^T.
+ * x, y: device double2[nrhs*n*n]; x and y must not overlap. */
+int lsh_apply_precond(lsh_factor_t factor, int transpose, const void* x, void* y, int nrhs, void* stream);
+
+/* y = A x = x + kappa^2 b (K * x), K of order op_order, by FFT (Sec. 5);
+ * b == NULL gives y = K * x (the scattered field of density x). */
+int lsh_apply_operator(lsh_plan_t plan, const double* b, const void* x, void* y, int nrhs, void* stream);
+
+/* sigma (and u = K sigma if u != NULL) for each incident field:
+ * right-preconditioned flexible GMRES (x0 = 0, CGS2, no restart).
+ * Synchronises once per iteration (residual read-back).  Returns
+ * LSH_NOT_CONVERGED if some rhs did not reach opts->tol. */
+int lsh_solve(lsh_factor_t factor, const void* u_inc, int nrhs, void* sigma, void* u, const lsh_solve_opts* opts,
+              lsh_info* info, void* stream);
+
+/* lambda = A^{-H} g (the adjoint solve of the misfit gradient), via
+ * A^T = I + K B: A^T y = r  <=>  y = r - K A^{-1} (B r), one forward solve. */
+int lsh_solve_adjoint(lsh_factor_t factor, const void* g, int nrhs, void* lambda, const lsh_solve_opts* opts,
+                      lsh_info* info, void* stream);
+
+/* u(x_r) = h^2 sum_j (i/4) H0(kappa |x_r - x_j|) sigma_j at off-grid points
+ * (eq. (ansatz), trapezoidal sum).  xy: device double[2*npts];
+ * u_pts: device double2[nrhs*npts]. */
+int lsh_eval_points(lsh_plan_t plan, const void* sigma, const double* xy, int npts, void* u_pts, int nrhs,
+                    void* stream);
+
+/* host: dimensionless corrections tau_d of the given order at kappa*h (the
+ * matrix entry is h^2 (G + tau_d)); writes count entries (<= 25) of
+ * offsets (host int[2*count]) and tau (host double[2*count], re/im). */
+int lsh_correction_weights(int order, double kh, int* count, int* offsets, double* tau);
+
+const char* lsh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSH_H */

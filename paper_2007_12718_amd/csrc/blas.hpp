@@ -1,0 +1,46 @@
+// Batched complex dense linear algebra on gfx950 (host-side launchers).
+//
+// All matrices are row-major, interleaved complex (cplx<R>), R = float or
+// double.  A "batch" is a set of equally sized problems at a fixed stride
+// (stride 0 = one operand shared by every problem).
+#pragma once
+#include "common.hpp"
+
+namespace lsh {
+
+// OP_R: conjugate without transposing (stored like OP_N)
+enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2, OP_R = 3 };
+
+// C_b = alpha * op(A_b) * op(B_b) + beta * D_b (+ I if add_identity)
+//   op(A) is M x K (A stored M x K for OP_N, K x M for OP_T / OP_C)
+//   op(B) is K x N (B stored K x N for OP_N, N x K for OP_T / OP_C)
+// D may alias C (in-place accumulate).  Runs on MFMA (16x16x4 f32 / f64).
+template <typename R>
+void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
+           const cplx<R>* A, long lda, long sA, Op opA,
+           const cplx<R>* B, long ldb, long sB, Op opB,
+           cplx<R> beta, const cplx<R>* D, long ldd, long sD,
+           cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false);
+
+// y_b = alpha * A_{b mod amod} x_b + beta * z_b   (A_b is M x N, op N).
+// z may alias y; z may be null when beta == 0.
+template <typename R>
+void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
+           const cplx<R>* A, long lda, long sA, int amod,
+           const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz,
+           cplx<R>* y, long sy, int batch);
+
+// In-place inverse of each c x c matrix by Gauss-Jordan elimination with
+// partial (row) pivoting.  ws must hold inverse_ws_bytes(c, batch) bytes.
+// info[b] = 0, or j+1 if a zero pivot was met at step j (matrix singular).
+template <typename R>
+size_t inverse_ws_bytes(int c, int batch);
+template <typename R>
+void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch,
+             void* ws, int* info);
+
+// dst (R2) = src (R1), elementwise, n complex entries
+template <typename R1, typename R2>
+void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n);
+
+}  // namespace lsh

@@ -1,0 +1,468 @@
+// HBS compression (paper Sec. 3.2), leaf factor (Alg. 1, leaf loop) and the
+// leaf steps of the apply (Alg. 2) on gfx950.
+#include <cmath>
+
+#include "hbs.hpp"
+
+namespace lsh {
+
+// ------------------------------------------------------------- gathers
+__global__ void k_gather_table(const z64* __restrict__ T, int D, const I2* __restrict__ rows, int m,
+                               const I2* __restrict__ cols, int np, z64* out, long ld) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= np) return;
+  int dx = rows[i].x - cols[j].x, dy = rows[i].y - cols[j].y;
+  dx = dx < 0 ? -dx : dx;
+  dy = dy < 0 ? -dy : dy;
+  out[(long)i * ld + j] = T[(long)dy * (D + 1) + dx];
+}
+
+void gather_table(hipStream_t s, const z64* T, int D, const I2* rows, int m, const I2* cols, int np, z64* out,
+                  long ld) {
+  if (m <= 0 || np <= 0) return;
+  LSH_REQUIRE(m <= 65535 * 16, -6, "gather: too many rows");
+  for (int i0 = 0; i0 < m; i0 += 65535) {
+    int mm = m - i0 < 65535 ? m - i0 : 65535;
+    hipLaunchKernelGGL(k_gather_table, dim3(ceil_div(np, 256), mm), dim3(256), 0, s, T, D, rows + i0, mm, cols,
+                       np, out + (long)i0 * ld, ld);
+    LSH_LAUNCH_CHECK();
+  }
+}
+
+__device__ __forceinline__ void wave_argmax_d(double& v, int& idx) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ----------------------------------------------- CPQR row ID (one workgroup)
+// Columns of A^T are the rows of W (contiguous); Householder reflectors act
+// on the proxy index.  After step j, W[i][j] (i > j) holds R[j][i].
+constexpr int QR_NT = 1024, QR_NW = QR_NT / 64;
+
+__global__ __launch_bounds__(QR_NT) void k_cpqr(z64* W, int m, int np, double thr, int* J, z64* U, int* k_out,
+                                                 double* nrm, z64* Rd) {
+  __shared__ double sb[QR_NW];
+  __shared__ int si[QR_NW];
+  __shared__ int s_p;
+  __shared__ double s_val;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < m; i += QR_NT) J[i] = i;
+  for (int i = wave; i < m; i += QR_NW) {
+    double a = 0;
+    for (int q = lane; q < np; q += 64) a += abs2(W[(long)i * np + q]);
+    a = wave_sum_d(a);
+    if (lane == 0) nrm[i] = a;
+  }
+  __syncthreads();
+  const int kmax = m < np ? m : np;
+  int k = kmax;
+  for (int j = 0; j < kmax; ++j) {
+    double best = -1;
+    int bi = m;
+    for (int i = j + tid; i < m; i += QR_NT) {
+      const double a = nrm[i];
+      if (a > best || (a == best && J[i] < (bi < m ? J[bi] : 1 << 30))) { best = a; bi = i; }
+    }
+    wave_argmax_d(best, bi);
+    if (lane == 0) { sb[wave] = best; si[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = sb[0];
+      int ii = si[0];
+      for (int w = 1; w < QR_NW; ++w)
+        if (sb[w] > bb) { bb = sb[w]; ii = si[w]; }
+      s_p = ii;
+      s_val = bb;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (!(sqrt(s_val) > thr)) { k = j; break; }
+    if (p != j) {
+      for (int q = tid; q < np; q += QR_NT) {
+        const z64 t = W[(long)j * np + q];
+        W[(long)j * np + q] = W[(long)p * np + q];
+        W[(long)p * np + q] = t;
+      }
+      if (tid == 0) {
+        const double tn = nrm[j]; nrm[j] = nrm[p]; nrm[p] = tn;
+        const int tj = J[j]; J[j] = J[p]; J[p] = tj;
+      }
+    }
+    __syncthreads();
+    // Householder vector of row j, entries q >= j
+    double a = 0;
+    for (int q = j + tid; q < np; q += QR_NT) a += abs2(W[(long)j * np + q]);
+    a = wave_sum_d(a);
+    if (lane == 0) sb[wave] = a;
+    __syncthreads();
+    if (tid == 0) {
+      double nx = 0;
+      for (int w = 0; w < QR_NW; ++w) nx += sb[w];
+      nx = sqrt(nx);
+      const z64 x0 = W[(long)j * np + j];
+      const double ax0 = sqrt(abs2(x0));
+      const z64 ph = ax0 > 0 ? mk(x0.x / ax0, x0.y / ax0) : mk(1.0, 0.0);
+      const z64 alpha = mk(-ph.x * nx, -ph.y * nx);
+      const z64 v0 = x0 - alpha;
+      const double vn2 = nx * nx - ax0 * ax0 + abs2(v0);
+      Rd[j] = alpha;
+      W[(long)j * np + j] = v0;
+      s_val = vn2 > 0 ? 2.0 / vn2 : 0.0;
+    }
+    __syncthreads();
+    const double beta = s_val;
+    const z64* v = W + (long)j * np;
+    for (int i = j + 1 + wave; i < m; i += QR_NW) {
+      z64* w = W + (long)i * np;
+      z64 sacc = mk(0.0, 0.0);
+      for (int q = j + lane; q < np; q += 64) fma_acc(sacc, conjg(v[q]), w[q]);
+      sacc.x = wave_sum_d(sacc.x);
+      sacc.y = wave_sum_d(sacc.y);
+      const z64 f = beta * sacc;
+      double nn = 0;
+      for (int q = j + lane; q < np; q += 64) {
+        const z64 t = w[q] - f * v[q];
+        w[q] = t;
+        if (q > j) nn += abs2(t);
+      }
+      nn = wave_sum_d(nn);
+      if (lane == 0) nrm[i] = nn;
+    }
+    __syncthreads();
+  }
+  // U: rows J[a] (a < k) are unit rows; rows J[k + c] hold (R11^{-1} R12)^T
+  for (int c = tid; c < m - k; c += QR_NT) {
+    z64* urow = U + (long)J[k + c] * k;
+    for (int a = k - 1; a >= 0; --a) {
+      z64 t = W[(long)(k + c) * np + a];  // R12[a][c]
+      for (int b2 = a + 1; b2 < k; ++b2) t = t - W[(long)b2 * np + a] * urow[b2];  // R11[a][b2]
+      urow[a] = cdiv(t, Rd[a]);
+    }
+  }
+  for (int e = tid; e < k * k; e += QR_NT) {
+    const int a = e / k, b2 = e % k;
+    U[(long)J[a] * k + b2] = mk(a == b2 ? 1.0 : 0.0, 0.0);
+  }
+  if (tid == 0) *k_out = k;
+}
+
+size_t rowid_cpqr_ws(int m) { return (size_t)m * (sizeof(double) + sizeof(z64)) + 256; }
+
+void rowid_cpqr(hipStream_t s, z64* A, int m, int np, double thr, int* J, z64* U, int* k_dev, void* ws) {
+  double* nrm = static_cast<double*>(ws);
+  z64* Rd = reinterpret_cast<z64*>(static_cast<char*>(ws) + ((m * sizeof(double) + 15) / 16) * 16);
+  hipLaunchKernelGGL(k_cpqr, dim3(1), dim3(QR_NT), 0, s, A, m, np, thr, J, U, k_dev, nrm, Rd);
+  LSH_LAUNCH_CHECK();
+}
+
+// ------------------------------------------- Gram / pivoted Cholesky row ID
+__global__ void k_gram_init(const z64* M, int m, double* d, int* chosen, int* state) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) { d[i] = M[(long)i * m + i].x; chosen[i] = 0; }
+  if (i == 0) { state[0] = 0; state[1] = 0; }
+}
+
+__global__ __launch_bounds__(QR_NT) void k_pchol_panel(const z64* __restrict__ M, int m, double* d, int* chosen,
+                                                        z64* Lt, int* piv, int j0, int nb, double thr2,
+                                                        int* state) {
+  __shared__ double sb[QR_NW];
+  __shared__ int si[QR_NW];
+  __shared__ int s_p;
+  __shared__ double s_d;
+  if (state[1]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int jj = 0; jj < nb; ++jj) {
+    const int j = j0 + jj;
+    if (j >= m) {
+      if (tid == 0) { state[0] = m; state[1] = 1; }
+      return;
+    }
+    double best = -1;
+    int bi = m;
+    for (int i = tid; i < m; i += QR_NT)
+      if (!chosen[i]) {
+        const double a = d[i];
+        if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+      }
+    wave_argmax_d(best, bi);
+    if (lane == 0) { sb[wave] = best; si[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = sb[0];
+      int ii = si[0];
+      for (int w = 1; w < QR_NW; ++w)
+        if (sb[w] > bb || (sb[w] == bb && si[w] < ii)) { bb = sb[w]; ii = si[w]; }
+      s_p = ii;
+      s_d = bb;
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double dp = s_d;
+    if (!(dp > thr2)) {
+      if (tid == 0) { state[0] = j; state[1] = 1; }
+      return;
+    }
+    const double sq = sqrt(dp), rs = 1.0 / sq;
+    for (int i = tid; i < m; i += QR_NT) {
+      z64 l;
+      if (i == p) {
+        l = mk(sq, 0.0);
+      } else if (chosen[i]) {
+        l = mk(0.0, 0.0);
+      } else {
+        l = conjg(M[(long)p * m + i]);
+        for (int t = j0; t < j; ++t) l = l - Lt[(long)t * m + i] * conjg(Lt[(long)t * m + p]);
+        l = rs * l;
+        d[i] -= abs2(l);
+      }
+      Lt[(long)j * m + i] = l;
+    }
+    __syncthreads();
+    if (tid == 0) { chosen[p] = 1; piv[j] = p; d[p] = 0; }
+    __syncthreads();
+  }
+  if (tid == 0) state[0] = j0 + nb;
+}
+
+__global__ void k_gather_L11(const z64* Lt, int m, const int* piv, int k, z64* L11) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int a = e / k, b = e % k;
+  L11[e] = Lt[(long)b * m + piv[a]];
+}
+
+__global__ void k_unit_rows(z64* U, int k, const int* piv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int a = e / k, b = e % k;
+  U[(long)piv[a] * k + b] = mk(a == b ? 1.0 : 0.0, 0.0);
+}
+
+size_t rowid_gram_ws(int m) {
+  const size_t mm = (size_t)m * m;
+  return sizeof(z64) * mm * 3 + sizeof(double) * m + sizeof(int) * (2 * m + 16) +
+         inverse_ws_bytes<double>(m, 1) + 4096;
+}
+
+int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws) {
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) { char* r = p; p += ((bytes + 255) / 256) * 256; return (void*)r; };
+  z64* M = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  z64* Lt = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  z64* L11 = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  double* d = static_cast<double*>(take(sizeof(double) * m));
+  int* chosen = static_cast<int*>(take(sizeof(int) * m));
+  int* state = static_cast<int*>(take(sizeof(int) * 16));
+  void* invws = take(inverse_ws_bytes<double>(m, 1));
+  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1);
+  hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, state);
+  LSH_LAUNCH_CHECK();
+  // ||A||_F^2 = trace(M)
+  std::vector<double> dh(m);
+  LSH_HIP(hipMemcpyAsync(dh.data(), d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  double fro2 = 0;
+  for (double v : dh) fro2 += v;
+  const double thr2 = tol * tol * fro2;
+  const int nb = 32;
+  int rank = 0;
+  for (int j0 = 0; j0 < m; j0 += nb) {
+    hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), 0, s, M, m, d, chosen, Lt, J, j0, nb, thr2, state);
+    LSH_LAUNCH_CHECK();
+    int st[2];
+    LSH_HIP(hipMemcpyAsync(st, state, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    rank = st[0];
+    if (st[1]) break;
+    // trailing update of the Schur complement: M -= Lp Lp^H
+    cgemm<double>(s, m, m, nb, mk(-1.0, 0.0), Lt + (long)j0 * m, m, 0, OP_T, Lt + (long)j0 * m, m, 0, OP_R,
+                  mk(1.0, 0.0), M, m, 0, M, m, 0, 1);
+  }
+  if (rank < 1) rank = 1;
+  const int k = rank;
+  hipLaunchKernelGGL(k_gather_L11, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, Lt, m, J, k, L11);
+  LSH_LAUNCH_CHECK();
+  inverse<double>(s, L11, k, k, 0, 1, invws, state + 8);
+  // U = L_k L11^{-1}  (L_k = first k columns of L = Lt[0:k]^T)
+  cgemm<double>(s, m, k, k, mk(1.0, 0.0), Lt, m, 0, OP_T, L11, k, 0, OP_N, mk(0.0, 0.0), nullptr, 0, 0, U, k, 0,
+                1);
+  hipLaunchKernelGGL(k_unit_rows, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J);
+  LSH_LAUNCH_CHECK();
+  return k;
+}
+
+// ------------------------------------------------------------- leaf factor
+template <typename R>
+__global__ void k_leaf_build(cplx<R>* X, const cplx<R>* __restrict__ G, int mL, const double* __restrict__ b,
+                             double kappa2, const I2* __restrict__ org, const I2* __restrict__ pts, int n) {
+  const long t = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mL * mL) return;
+  const int i = e / mL, j = e % mL;
+  const I2 o = org[t], pi = pts[i];
+  const double bi = kappa2 * b[(long)(o.y + pi.y) * n + (o.x + pi.x)];
+  cplx<R> v = (R)bi * G[e];
+  if (i == j) v.x += R(1);
+  X[t * (long)mL * mL + e] = v;
+}
+
+template <typename R>
+void leaf_build(hipStream_t s, cplx<R>* X, const cplx<R>* Gleaf, int mL, const double* b, double kappa2,
+                const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n) {
+  LSH_REQUIRE(nleaf <= 65535 * 64, -6, "too many leaves");
+  for (int t0 = 0; t0 < nleaf; t0 += 65535) {
+    int nt = nleaf - t0 < 65535 ? nleaf - t0 : 65535;
+    hipLaunchKernelGGL(k_leaf_build<R>, dim3(ceil_div(mL * mL, 256), nt), dim3(256), 0, s,
+                       X + (long)t0 * mL * mL, Gleaf, mL, b, kappa2, leaf_origin + t0, leaf_pts, n);
+    LSH_LAUNCH_CHECK();
+  }
+}
+
+template <typename R>
+__global__ void k_leaf_scale_U(cplx<R>* Y, const cplx<R>* __restrict__ U, int mL, int k,
+                               const double* __restrict__ b, double kappa2, const I2* __restrict__ org,
+                               const I2* __restrict__ pts, int n) {
+  const long t = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mL * k) return;
+  const int i = e / k;
+  const I2 o = org[t], pi = pts[i];
+  const double bi = kappa2 * b[(long)(o.y + pi.y) * n + (o.x + pi.x)];
+  Y[t * (long)mL * k + e] = (R)bi * U[e];
+}
+
+template <typename R>
+void leaf_scale_U(hipStream_t s, cplx<R>* Y, const cplx<R>* U, int mL, int k, const double* b, double kappa2,
+                  const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n) {
+  for (int t0 = 0; t0 < nleaf; t0 += 65535) {
+    int nt = nleaf - t0 < 65535 ? nleaf - t0 : 65535;
+    hipLaunchKernelGGL(k_leaf_scale_U<R>, dim3(ceil_div(mL * k, 256), nt), dim3(256), 0, s,
+                       Y + (long)t0 * mL * k, U, mL, k, b, kappa2, leaf_origin + t0, leaf_pts, n);
+    LSH_LAUNCH_CHECK();
+  }
+}
+
+// -------------------------------------------------------------- leaf apply
+// Up: r = X_tau f_tau ; rt = U_L^T r      (one workgroup per leaf and rhs)
+constexpr int LEAF_MAX = 144;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ UL,
+                                                 int mL, int k, const z64* __restrict__ f, cplx<R>* r, cplx<R>* rt,
+                                                 const I2* __restrict__ org, const I2* __restrict__ pts, int n,
+                                                 int nleaf) {
+  __shared__ cplx<R> fs[LEAF_MAX];
+  __shared__ cplx<R> rs[LEAF_MAX];
+  const long t = blockIdx.x, rhs = blockIdx.y;
+  const I2 o = org[t];
+  const z64* fr = f + rhs * (long)n * n;
+  for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+    const I2 pi = pts[i];
+    const z64 v = fr[(long)(o.y + pi.y) * n + (o.x + pi.x)];
+    fs[i] = mk<R>((R)v.x, (R)v.y);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const cplx<R>* Xt = X + t * (long)mL * mL;
+  for (int i = wave; i < mL; i += 4) {
+    cplx<R> acc = mk<R>(0, 0);
+    for (int j = lane; j < mL; j += 64) fma_acc(acc, Xt[(long)i * mL + j], fs[j]);
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) rs[i] = acc;
+  }
+  __syncthreads();
+  cplx<R>* rr = r + (rhs * nleaf + t) * (long)mL;
+  for (int i = threadIdx.x; i < mL; i += blockDim.x) rr[i] = rs[i];
+  cplx<R>* rtt = rt + (rhs * nleaf + t) * (long)k;
+  for (int a = threadIdx.x; a < k; a += blockDim.x) {
+    cplx<R> acc = mk<R>(0, 0);
+    for (int i = 0; i < mL; ++i) fma_acc(acc, UL[(long)i * k + a], rs[i]);
+    rtt[a] = acc;
+  }
+}
+
+template <typename R>
+void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const z64* f, cplx<R>* r,
+             cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs) {
+  LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
+  hipLaunchKernelGGL(k_leaf_up<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, f, r, rt, leaf_origin,
+                     leaf_pts, n, nleaf);
+  LSH_LAUNCH_CHECK();
+}
+
+// Down: q_tau = r_tau - X_tau B_tau U_L wt_tau, written to the grid (FP64)
+template <typename R>
+__global__ __launch_bounds__(256) void k_leaf_down(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ UL,
+                                                   int mL, int k, const cplx<R>* __restrict__ wt,
+                                                   const cplx<R>* __restrict__ r, z64* q,
+                                                   const double* __restrict__ b, double kappa2,
+                                                   const I2* __restrict__ org, const I2* __restrict__ pts, int n,
+                                                   int nleaf) {
+  __shared__ cplx<R> us[LEAF_MAX];
+  __shared__ cplx<R> ws[LEAF_MAX];
+  const long t = blockIdx.x, rhs = blockIdx.y;
+  const I2 o = org[t];
+  const cplx<R>* wtt = wt + (rhs * nleaf + t) * (long)k;
+  for (int a = threadIdx.x; a < k; a += blockDim.x) ws[a] = wtt[a];
+  __syncthreads();
+  for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+    cplx<R> acc = mk<R>(0, 0);
+    for (int a = 0; a < k; ++a) fma_acc(acc, UL[(long)i * k + a], ws[a]);
+    const I2 pi = pts[i];
+    const R bi = (R)(kappa2 * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]);
+    us[i] = bi * acc;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const cplx<R>* Xt = X + t * (long)mL * mL;
+  const cplx<R>* rr = r + (rhs * nleaf + t) * (long)mL;
+  z64* qr = q + rhs * (long)n * n;
+  for (int i = wave; i < mL; i += 4) {
+    cplx<R> acc = mk<R>(0, 0);
+    for (int j = lane; j < mL; j += 64) fma_acc(acc, Xt[(long)i * mL + j], us[j]);
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) {
+      const cplx<R> v = rr[i] - acc;
+      const I2 pi = pts[i];
+      qr[(long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)v.x, (double)v.y);
+    }
+  }
+}
+
+template <typename R>
+void leaf_down(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const cplx<R>* wt,
+               const cplx<R>* r, z64* q, const double* b, double kappa2, const I2* leaf_origin, const I2* leaf_pts,
+               int nleaf, int n, int nrhs) {
+  LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
+  hipLaunchKernelGGL(k_leaf_down<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, wt, r, q, b, kappa2,
+                     leaf_origin, leaf_pts, n, nleaf);
+  LSH_LAUNCH_CHECK();
+}
+
+#define LSH_HBS_INST(R)                                                                                       \
+  template void leaf_build<R>(hipStream_t, cplx<R>*, const cplx<R>*, int, const double*, double, const I2*,   \
+                              const I2*, int, int);                                                          \
+  template void leaf_scale_U<R>(hipStream_t, cplx<R>*, const cplx<R>*, int, int, const double*, double,       \
+                                const I2*, const I2*, int, int);                                             \
+  template void leaf_up<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const z64*, cplx<R>*,        \
+                           cplx<R>*, const I2*, const I2*, int, int, int);                                   \
+  template void leaf_down<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const cplx<R>*,           \
+                             const cplx<R>*, z64*, const double*, double, const I2*, const I2*, int, int, int);
+LSH_HBS_INST(float)
+LSH_HBS_INST(double)
+
+}  // namespace lsh

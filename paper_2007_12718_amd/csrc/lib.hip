@@ -1,0 +1,883 @@
+// Host orchestration and the C ABI (include/lsh.h).
+//
+// plan   : tree (Sec. 3.1-3.2), correction weights (Sec. 2.2), kernel table,
+//          per-level row IDs and sibling blocks (Sec. 3.2), FFT spectrum.
+// factor : Algorithm 1, with the parent inverse in Schur-complement form
+//          X = [[I, Pa],[Pb, I]]^{-1}, Pa = S_a G_ab, Pb = S_b G_ba,
+//          C = I - Pb Pa:  X [a; b] = [a - Pa y; y], y = C^{-1} (b - Pb a).
+// apply  : Algorithm 2 (up l = L-1..1, root solve, down l = 1..L-1, leaves).
+// solve  : right-preconditioned flexible GMRES on the order-p FFT operator.
+#include <chrono>
+#include <complex>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/lsh.h"
+#include "blas.hpp"
+#include "hbs.hpp"
+#include "ops.hpp"
+#include "weights.hpp"
+
+using namespace lsh;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Level {
+  int sx = 0, sy = 0;  // box size
+  int m = 0, k = 0;    // candidate rows and rank (levels 1..L)
+  std::vector<I2> cand;
+  std::vector<int> J;
+  DevBuf U64, U32;       // m x k
+  DevBuf Gab64, Gab32;   // sibling block of this parent level (c x c, c = k of level+1)
+  int c = 0;
+};
+
+}  // namespace
+
+struct lsh_plan_s {
+  lsh_desc d{};
+  int n = 0, L = 0, ls = 0, mL = 0, D = 0, nleaf = 0;
+  double h = 0, kappa = 0;
+  std::vector<Level> lev;
+  std::vector<I2> leaf_origin_h, leaf_pts_h;
+  DevBuf leaf_origin, leaf_pts;
+  DevBuf table;
+  DevBuf Gleaf64, Gleaf32;
+  ConvOperator op;
+  std::vector<StencilEntry> st4;
+  double tau0_re = 0, tau0_im = 0;
+  template <typename R>
+  const cplx<R>* U(int l) const;
+  template <typename R>
+  const cplx<R>* Gab(int l) const;
+  template <typename R>
+  const cplx<R>* Gleaf() const;
+};
+
+template <>
+const cplx<double>* lsh_plan_s::U<double>(int l) const { return lev[l].U64.as<z64>(); }
+template <>
+const cplx<float>* lsh_plan_s::U<float>(int l) const { return lev[l].U32.as<c32>(); }
+template <>
+const cplx<double>* lsh_plan_s::Gab<double>(int l) const { return lev[l].Gab64.as<z64>(); }
+template <>
+const cplx<float>* lsh_plan_s::Gab<float>(int l) const { return lev[l].Gab32.as<c32>(); }
+template <>
+const cplx<double>* lsh_plan_s::Gleaf<double>() const { return Gleaf64.as<z64>(); }
+template <>
+const cplx<float>* lsh_plan_s::Gleaf<float>() const { return Gleaf32.as<c32>(); }
+
+namespace {
+
+// box (origin, size) of box t on a level: vertical cuts (split x1) from even
+// levels, horizontal cuts (split x2) from odd levels; child 2t is the half
+// with the smaller coordinates.
+void box_of(int n, int level, long t, int& ox, int& oy, int& sx, int& sy) {
+  ox = oy = 0;
+  sx = sy = n;
+  for (int m = 1; m <= level; ++m) {
+    const int bit = (int)((t >> (level - m)) & 1);
+    if ((m - 1) % 2 == 0) {
+      sx /= 2;
+      ox += bit * sx;
+    } else {
+      sy /= 2;
+      oy += bit * sy;
+    }
+  }
+}
+
+std::vector<I2> proxy_ring(int sx, int sy, int w) {
+  std::vector<I2> p;
+  for (int b = -w; b < sy + w; ++b)
+    for (int a = -w; a < sx + w; ++a)
+      if (!(a >= 0 && a < sx && b >= 0 && b < sy)) p.push_back(I2{a, b});
+  return p;
+}
+
+template <typename T>
+DevBuf upload(const std::vector<T>& v, hipStream_t s) {
+  DevBuf b(sizeof(T) * (v.size() ? v.size() : 1));
+  if (!v.empty()) LSH_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+  return b;
+}
+
+void validate(const lsh_desc& d) {
+  LSH_REQUIRE(d.n >= 4 && d.n <= 2048, LSH_ERR_INVALID_ARG, "n must be in [4, 2048]");
+  LSH_REQUIRE(d.h > 0 && std::isfinite(d.h), LSH_ERR_INVALID_ARG, "h must be positive");
+  LSH_REQUIRE(d.kappa > 0 && std::isfinite(d.kappa), LSH_ERR_INVALID_ARG, "kappa must be positive");
+  LSH_REQUIRE(d.op_order == 4 || d.op_order == 6 || d.op_order == 8 || d.op_order == 10, LSH_ERR_INVALID_ARG,
+              "op_order must be 4, 6, 8 or 10");
+  LSH_REQUIRE(d.leaf >= 2 && d.leaf <= 12 && d.n % d.leaf == 0, LSH_ERR_INVALID_ARG, "leaf must divide n (2..12)");
+  const int p = d.n / d.leaf;
+  LSH_REQUIRE(p >= 2 && (p & (p - 1)) == 0, LSH_ERR_INVALID_ARG, "n / leaf must be a power of two >= 2");
+  LSH_REQUIRE(d.tol >= 0 && d.tol < 1, LSH_ERR_INVALID_ARG, "tol must be in [0, 1)");
+  LSH_REQUIRE(d.proxy_width >= 1 && d.proxy_width <= 3, LSH_ERR_INVALID_ARG, "proxy_width must be 1..3");
+  LSH_REQUIRE(d.hbs_prec == LSH_FP64 || d.hbs_prec == LSH_FP32, LSH_ERR_INVALID_ARG, "hbs_prec");
+}
+
+// Row ID of the level's proxy matrix (FP64); fills lv.J (host) and lv.U64.
+void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
+  const int m = lv.m, np = (int)prox.size();
+  if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all candidates
+    lv.k = m;
+    lv.J.resize(m);
+    for (int i = 0; i < m; ++i) lv.J[i] = i;
+    std::vector<z64> I((size_t)m * m, mk(0.0, 0.0));
+    for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = mk(1.0, 0.0);
+    lv.U64 = upload(I, s);
+    return;
+  }
+  DevBuf dc = upload(lv.cand, s), dp = upload(prox, s);
+  DevBuf A(sizeof(z64) * (size_t)m * np);
+  gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
+  DevBuf J(sizeof(int) * m), Ufull(sizeof(z64) * (size_t)m * m);
+  int k = 0;
+  const bool small = (double)m * np <= 262144.0;
+  if (small || P.d.tol < 1e-7) {
+    // ||A||_F for the stopping rule |R_kk| <= tol ||A||_F (computed on device)
+    DevBuf ws(rowid_cpqr_ws(m)), kd(sizeof(int)), fro(sizeof(z64)), part(multidot_partial_bytes(1));
+    multidot(s, A.as<z64>(), 0, 1, A.as<z64>(), (long)m * np, fro.as<z64>(), part.as<z64>());
+    z64 f2;
+    LSH_HIP(hipMemcpyAsync(&f2, fro.p, sizeof(z64), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    const double thr = P.d.tol * std::sqrt(f2.x);
+    rowid_cpqr(s, A.as<z64>(), m, np, thr, J.as<int>(), Ufull.as<z64>(), kd.as<int>(), ws.p);
+    LSH_HIP(hipMemcpyAsync(&k, kd.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    if (k < 1) k = 1;  // (a zero block still gets one skeleton)
+  } else {
+    DevBuf ws(rowid_gram_ws(m));
+    k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
+  }
+  lv.k = k;
+  lv.J.resize(k);
+  LSH_HIP(hipMemcpyAsync(lv.J.data(), J.p, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  lv.U64.alloc(sizeof(z64) * (size_t)m * k);
+  LSH_HIP(hipMemcpyAsync(lv.U64.p, Ufull.p, sizeof(z64) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
+  LSH_HIP(hipStreamSynchronize(s));
+}
+
+void plan_build(lsh_plan_s& P, hipStream_t s) {
+  const lsh_desc& d = P.d;
+  P.n = d.n;
+  P.h = d.h;
+  P.kappa = d.kappa;
+  P.ls = d.leaf;
+  int p = d.n / d.leaf, lg = 0;
+  while ((1 << lg) < p) ++lg;
+  P.L = 2 * lg;
+  LSH_REQUIRE(P.L < LSH_MAX_LEVELS, LSH_ERR_UNSUPPORTED, "too many levels");
+  P.nleaf = 1 << P.L;
+  P.mL = d.leaf * d.leaf;
+  const int w = d.proxy_width;
+  P.D = d.n + w + 1;
+  // weights (Sec. 2.2) and the offset table
+  P.st4 = correction_stencil(4, d.kappa * d.h);
+  P.tau0_re = P.st4[0].re;
+  P.tau0_im = P.st4[0].im;
+  P.table.alloc(sizeof(z64) * (size_t)(P.D + 1) * (P.D + 1));
+  build_offset_table(s, P.table.as<z64>(), P.D, d.h, d.kappa, P.tau0_re, P.tau0_im);
+  // leaves
+  P.leaf_origin_h.resize(P.nleaf);
+  for (int t = 0; t < P.nleaf; ++t) {
+    int ox, oy, sx, sy;
+    box_of(d.n, P.L, t, ox, oy, sx, sy);
+    P.leaf_origin_h[t] = I2{ox, oy};
+  }
+  P.leaf_pts_h.clear();
+  for (int iy = 0; iy < d.leaf; ++iy)
+    for (int ix = 0; ix < d.leaf; ++ix) P.leaf_pts_h.push_back(I2{ix, iy});
+  P.leaf_origin = upload(P.leaf_origin_h, s);
+  P.leaf_pts = upload(P.leaf_pts_h, s);
+  // compression, leaves upward (Sec. 3.2)
+  P.lev.clear();
+  P.lev.resize(P.L + 1);
+  for (int l = 0; l <= P.L; ++l) {
+    int ox, oy;
+    box_of(d.n, l, 0, ox, oy, P.lev[l].sx, P.lev[l].sy);
+  }
+  for (int l = P.L; l >= 1; --l) {
+    Level& lv = P.lev[l];
+    if (l == P.L) {
+      lv.cand = P.leaf_pts_h;
+    } else {
+      lv.cand.clear();
+      for (int c = 0; c < 2; ++c) {
+        int cx, cy, csx, csy, ox, oy, sx, sy;
+        box_of(d.n, l + 1, c, cx, cy, csx, csy);
+        box_of(d.n, l, 0, ox, oy, sx, sy);
+        const Level& ch = P.lev[l + 1];
+        for (int j : ch.J) lv.cand.push_back(I2{ch.cand[j].x + cx - ox, ch.cand[j].y + cy - oy});
+      }
+    }
+    lv.m = (int)lv.cand.size();
+    level_id(P, lv, proxy_ring(lv.sx, lv.sy, w), s);
+  }
+  // sibling blocks G_ab (parent level l couples children 0 and 1 of box 0)
+  for (int l = 0; l < P.L; ++l) {
+    const Level& ch = P.lev[l + 1];
+    int ax, ay, bx, by, sx, sy;
+    box_of(d.n, l + 1, 0, ax, ay, sx, sy);
+    box_of(d.n, l + 1, 1, bx, by, sx, sy);
+    std::vector<I2> ra, rb;
+    for (int j : ch.J) {
+      ra.push_back(I2{ch.cand[j].x + ax, ch.cand[j].y + ay});
+      rb.push_back(I2{ch.cand[j].x + bx, ch.cand[j].y + by});
+    }
+    Level& lv = P.lev[l];
+    lv.c = ch.k;
+    DevBuf da = upload(ra, s), db = upload(rb, s);
+    lv.Gab64.alloc(sizeof(z64) * (size_t)lv.c * lv.c);
+    gather_table(s, P.table.as<z64>(), P.D, da.as<I2>(), lv.c, db.as<I2>(), lv.c, lv.Gab64.as<z64>(), lv.c);
+    LSH_HIP(hipStreamSynchronize(s));
+  }
+  {
+    DevBuf dl = upload(P.leaf_pts_h, s);
+    P.Gleaf64.alloc(sizeof(z64) * (size_t)P.mL * P.mL);
+    gather_table(s, P.table.as<z64>(), P.D, dl.as<I2>(), P.mL, dl.as<I2>(), P.mL, P.Gleaf64.as<z64>(), P.mL);
+    LSH_HIP(hipStreamSynchronize(s));
+  }
+  if (d.hbs_prec == LSH_FP32) {
+    for (int l = 0; l <= P.L; ++l) {
+      Level& lv = P.lev[l];
+      if (l >= 1) {
+        lv.U32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
+        ccast<double, float>(s, lv.U64.as<z64>(), lv.U32.as<c32>(), (long)lv.m * lv.k);
+      }
+      if (l < P.L) {
+        lv.Gab32.alloc(sizeof(c32) * (size_t)lv.c * lv.c);
+        ccast<double, float>(s, lv.Gab64.as<z64>(), lv.Gab32.as<c32>(), (long)lv.c * lv.c);
+      }
+    }
+    P.Gleaf32.alloc(sizeof(c32) * (size_t)P.mL * P.mL);
+    ccast<double, float>(s, P.Gleaf64.as<z64>(), P.Gleaf32.as<c32>(), (long)P.mL * P.mL);
+  }
+  // operator spectrum (order op_order)
+  P.op.init(s, d.n, d.h, d.kappa, P.table.as<z64>(), P.D, correction_stencil(d.op_order, d.kappa * d.h));
+  LSH_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------ factor
+template <typename R>
+struct FactorData {
+  DevBuf X;                       // leaf inverses [nleaf][mL][mL]
+  std::vector<DevBuf> S;          // S[l], l = 1..L : [2^l][k_l][k_l]
+  std::vector<DevBuf> Pa, Pb, Ci; // parent level l = 0..L-1 : [2^l][c][c]
+  // apply workspace
+  int ws_nrhs = 0;
+  DevBuf r;                       // [nrhs][nleaf][mL]
+  std::vector<DevBuf> rt, wt;     // [nrhs][2^l][k_l]
+  DevBuf t1, t2, t3, ty;          // scratch
+};
+
+int check_info(const DevBuf& info, int batch, hipStream_t s) {
+  std::vector<int> h(batch);
+  LSH_HIP(hipMemcpyAsync(h.data(), info.p, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  for (int v : h)
+    if (v) return v;
+  return 0;
+}
+
+template <typename R>
+void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStream_t s) {
+  const int L = P.L, nleaf = P.nleaf, mL = P.mL, kL = P.lev[L].k;
+  const double k2 = P.kappa * P.kappa;
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  F.S.clear();
+  F.S.resize(L + 1);
+  F.Pa.clear(); F.Pb.clear(); F.Ci.clear();
+  F.Pa.resize(L); F.Pb.resize(L); F.Ci.resize(L);
+  // leaves: X = (I + B G_leaf)^{-1}, S = U^T X B U
+  F.X.alloc(sizeof(cplx<R>) * (size_t)nleaf * mL * mL);
+  cplx<R>* X = F.X.template as<cplx<R>>();
+  leaf_build<R>(s, X, P.Gleaf<R>(), mL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
+  {
+    DevBuf ws(inverse_ws_bytes<R>(mL, nleaf)), info(sizeof(int) * nleaf);
+    inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws.p, info.as<int>());
+    int bad = check_info(info, nleaf, s);
+    LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular leaf matrix I + B G");
+  }
+  {
+    DevBuf Y(sizeof(cplx<R>) * (size_t)nleaf * mL * kL), Z(sizeof(cplx<R>) * (size_t)nleaf * mL * kL);
+    leaf_scale_U<R>(s, Y.template as<cplx<R>>(), P.U<R>(L), mL, kL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(),
+                    nleaf, P.n);
+    cgemm<R>(s, mL, kL, mL, one, X, mL, (long)mL * mL, OP_N, Y.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero,
+             nullptr, 0, 0, Z.template as<cplx<R>>(), kL, (long)mL * kL, nleaf);
+    F.S[L].alloc(sizeof(cplx<R>) * (size_t)nleaf * kL * kL);
+    cgemm<R>(s, kL, kL, mL, one, P.U<R>(L), kL, 0, OP_T, Z.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero, nullptr,
+             0, 0, F.S[L].template as<cplx<R>>(), kL, (long)kL * kL, nleaf);
+    LSH_HIP(hipStreamSynchronize(s));
+  }
+  // parents, leaves upward
+  for (int l = L - 1; l >= 0; --l) {
+    const int c = P.lev[l].c, nb = 1 << l;
+    const long cc = (long)c * c;
+    const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
+    const cplx<R>* G = P.Gab<R>(l);
+    F.Pa[l].alloc(sizeof(cplx<R>) * nb * cc);
+    F.Pb[l].alloc(sizeof(cplx<R>) * nb * cc);
+    F.Ci[l].alloc(sizeof(cplx<R>) * nb * cc);
+    cplx<R>* Pa = F.Pa[l].template as<cplx<R>>();
+    cplx<R>* Pb = F.Pb[l].template as<cplx<R>>();
+    cplx<R>* Ci = F.Ci[l].template as<cplx<R>>();
+    cgemm<R>(s, c, c, c, one, Sch, c, 2 * cc, OP_N, G, c, 0, OP_N, zero, nullptr, 0, 0, Pa, c, cc, nb);
+    cgemm<R>(s, c, c, c, one, Sch + cc, c, 2 * cc, OP_N, G, c, 0, OP_T, zero, nullptr, 0, 0, Pb, c, cc, nb);
+    cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
+    {
+      DevBuf ws(inverse_ws_bytes<R>(c, nb)), info(sizeof(int) * nb);
+      inverse<R>(s, Ci, c, c, cc, nb, ws.p, info.as<int>());
+      int bad = check_info(info, nb, s);
+      LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular merge matrix I - Pb Pa at level " + std::to_string(l));
+    }
+    if (l == 0) break;
+    const int k = P.lev[l].k;
+    const long ck = (long)c * k;
+    const cplx<R>* U1 = P.U<R>(l);
+    const cplx<R>* U2 = U1 + ck;
+    DevBuf A1(sizeof(cplx<R>) * nb * ck), A2(sizeof(cplx<R>) * nb * ck), Yb(sizeof(cplx<R>) * nb * ck);
+    cplx<R>* a1 = A1.template as<cplx<R>>();
+    cplx<R>* a2 = A2.template as<cplx<R>>();
+    cplx<R>* y = Yb.template as<cplx<R>>();
+    cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a1, k, ck, nb);
+    cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a2, k, ck, nb);
+    // a2 <- A2 - Pb A1 ; y = C^{-1} a2 ; a1 <- A1 - Pa y
+    cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, a1, k, ck, OP_N, one, a2, k, ck, a2, k, ck, nb);
+    cgemm<R>(s, c, k, c, one, Ci, c, cc, OP_N, a2, k, ck, OP_N, zero, nullptr, 0, 0, y, k, ck, nb);
+    cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, y, k, ck, OP_N, one, a1, k, ck, a1, k, ck, nb);
+    F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
+    cplx<R>* S = F.S[l].template as<cplx<R>>();
+    cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a1, k, ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
+    cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, y, k, ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k, nb);
+    LSH_HIP(hipStreamSynchronize(s));
+  }
+  LSH_HIP(hipStreamSynchronize(s));
+}
+
+template <typename R>
+void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
+  if (F.ws_nrhs >= nrhs) return;
+  const int L = P.L;
+  F.r.alloc(sizeof(cplx<R>) * (size_t)nrhs * P.nleaf * P.mL);
+  F.rt.clear();
+  F.wt.clear();
+  F.rt.resize(L + 1);
+  F.wt.resize(L + 1);
+  size_t big = 0;
+  for (int l = 1; l <= L; ++l) {
+    const size_t e = (size_t)nrhs * ((size_t)1 << l) * P.lev[l].k;
+    F.rt[l].alloc(sizeof(cplx<R>) * e);
+    F.wt[l].alloc(sizeof(cplx<R>) * e);
+    if (e > big) big = e;
+  }
+  F.t1.alloc(sizeof(cplx<R>) * big);
+  F.t2.alloc(sizeof(cplx<R>) * big);
+  F.t3.alloc(sizeof(cplx<R>) * big);
+  F.ty.alloc(sizeof(cplx<R>) * big);
+  F.ws_nrhs = nrhs;
+}
+
+// out = X_tau in for every box of parent level l (B = nrhs * 2^l problems, [B][2c])
+template <typename R>
+void apply_X(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, const cplx<R>* in, cplx<R>* out,
+             hipStream_t s) {
+  const int c = P.lev[l].c, nb = 1 << l, B = nrhs * nb;
+  const long cc = (long)c * c;
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  cplx<R>* ty = F.ty.template as<cplx<R>>();
+  // ty = b - Pb a
+  cgemv<R>(s, c, c, mone, F.Pb[l].template as<cplx<R>>(), c, cc, nb, in, 2 * c, one, in + c, 2 * c, ty, c, B);
+  // y = C^{-1} ty  -> second half of out
+  cgemv<R>(s, c, c, one, F.Ci[l].template as<cplx<R>>(), c, cc, nb, ty, c, zero, nullptr, 0, out + c, 2 * c, B);
+  // top = a - Pa y -> first half of out
+  cgemv<R>(s, c, c, mone, F.Pa[l].template as<cplx<R>>(), c, cc, nb, out + c, 2 * c, one, in, 2 * c, out, 2 * c,
+           B);
+}
+
+template <typename R>
+void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* f, z64* q, int nrhs,
+             hipStream_t s) {
+  ensure_apply_ws(P, F, nrhs);
+  const int L = P.L;
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  const double k2 = P.kappa * P.kappa;
+  cplx<R>* r = F.r.template as<cplx<R>>();
+  cplx<R>* t1 = F.t1.template as<cplx<R>>();
+  cplx<R>* t2 = F.t2.template as<cplx<R>>();
+  cplx<R>* t3 = F.t3.template as<cplx<R>>();
+  leaf_up<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, f, r, F.rt[L].template as<cplx<R>>(),
+             P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
+  // upward pass
+  for (int l = L - 1; l >= 1; --l) {
+    const int c = P.lev[l].c, k = P.lev[l].k, B = nrhs << l;
+    apply_X<R>(P, F, l, nrhs, F.rt[l + 1].template as<cplx<R>>(), t1, s);
+    cgemm<R>(s, B, k, 2 * c, one, t1, 2 * c, 0, OP_N, P.U<R>(l), k, 0, OP_N, zero, nullptr, 0, 0,
+             F.rt[l].template as<cplx<R>>(), k, 0, 1);
+  }
+  // root: w_children = Ghat X_root [rt_a; rt_b]
+  {
+    const int c = P.lev[0].c;
+    apply_X<R>(P, F, 0, nrhs, F.rt[1].template as<cplx<R>>(), t1, s);
+    cplx<R>* w1 = F.wt[1].template as<cplx<R>>();
+    cgemm<R>(s, nrhs, c, c, one, t1 + c, 2 * c, 0, OP_N, P.Gab<R>(0), c, 0, OP_T, zero, nullptr, 0, 0, w1, 2 * c,
+             0, 1);
+    cgemm<R>(s, nrhs, c, c, one, t1, 2 * c, 0, OP_N, P.Gab<R>(0), c, 0, OP_N, zero, nullptr, 0, 0, w1 + c, 2 * c,
+             0, 1);
+  }
+  // downward pass
+  for (int l = 1; l <= L - 1; ++l) {
+    const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
+    const long cc = (long)c * c;
+    // u = U_l wt_l  ([B][2c])
+    cgemm<R>(s, B, 2 * c, k, one, F.wt[l].template as<cplx<R>>(), k, 0, OP_N, P.U<R>(l), k, 0, OP_T, zero,
+             nullptr, 0, 0, t1, 2 * c, 0, 1);
+    // d = rt_children - diag(S_a, S_b) u  ([2B][c])
+    cgemv<R>(s, c, c, mone, F.S[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t1, c, one,
+             F.rt[l + 1].template as<cplx<R>>(), c, t2, c, 2 * B);
+    // qt = X_tau d
+    apply_X<R>(P, F, l, nrhs, t2, t3, s);
+    // wt_children = Ghat qt + u
+    cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
+    cgemm<R>(s, B, c, c, one, t3 + c, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_T, one, t1, 2 * c, 0, wc, 2 * c, 0, 1);
+    cgemm<R>(s, B, c, c, one, t3, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_N, one, t1 + c, 2 * c, 0, wc + c, 2 * c, 0,
+             1);
+  }
+  leaf_down<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, F.wt[L].template as<cplx<R>>(), r, q,
+               b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
+}
+
+}  // namespace
+
+struct lsh_factor_s {
+  lsh_plan_s* plan = nullptr;
+  DevBuf b;  // private copy of b (device, FP64)
+  FactorData<float> f32;
+  FactorData<double> f64;
+  // FGMRES workspace
+  int gm_maxit = 0;
+  DevBuf V, Z, w, h1, h2, part, fvec, res;
+  void apply(const z64* x, z64* y, int nrhs, hipStream_t s) {
+    if (plan->d.hbs_prec == LSH_FP32) apply_M<float>(*plan, b.as<double>(), f32, x, y, nrhs, s);
+    else apply_M<double>(*plan, b.as<double>(), f64, x, y, nrhs, s);
+  }
+};
+
+namespace {
+
+__global__ void k_check_finite(const double* b, long n, int* bad) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (!isfinite(b[i])) *bad = 1;
+}
+
+// f = -kappa^2 b u_inc
+__global__ void k_rhs(z64* f, const z64* u, const double* b, double k2, long N) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+    f[i] = (-k2 * b[i]) * u[i];
+}
+
+void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, lsh_info* info, double& true_res,
+                int& conv, hipStream_t s) {
+  lsh_plan_s& P = *F.plan;
+  const long N = (long)P.n * P.n;
+  const int maxit = o.maxit;
+  if (F.gm_maxit < maxit) {
+    F.V.alloc(sizeof(z64) * (size_t)(maxit + 1) * N);
+    F.Z.alloc(sizeof(z64) * (size_t)maxit * N);
+    F.w.alloc(sizeof(z64) * N);
+    F.h1.alloc(sizeof(z64) * (maxit + 2));
+    F.h2.alloc(sizeof(z64) * (maxit + 2));
+    F.part.alloc(multidot_partial_bytes(maxit + 2));
+    F.res.alloc(sizeof(z64) * N);
+    F.gm_maxit = maxit;
+  }
+  z64* V = F.V.as<z64>();
+  z64* Z = F.Z.as<z64>();
+  z64* h1 = F.h1.as<z64>();
+  z64* h2 = F.h2.as<z64>();
+  z64* part = F.part.as<z64>();
+  multidot(s, f, 0, 1, f, N, h1, part);
+  z64 fn;
+  LSH_HIP(hipMemcpyAsync(&fn, h1, sizeof(z64), hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  const double beta = std::sqrt(fn.x);
+  if (info) { info->iterations = 0; info->residual = 0; info->history[0] = 1.0; }
+  if (beta == 0) {
+    fill_zero(s, x, sizeof(z64) * N);
+    true_res = 0;
+    return;
+  }
+  scale_by_invnorm(s, V, f, h1, N);
+  std::vector<std::complex<double>> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
+  g[0] = beta;
+  std::vector<z64> hv(maxit + 2), hv2(maxit + 2);
+  int j = 0, its = 0;
+  double est = 1.0;
+  for (j = 0; j < maxit; ++j) {
+    z64* vj = V + (long)j * N;
+    z64* zj = Z + (long)j * N;
+    z64* w = V + (long)(j + 1) * N;
+    if (o.precondition) F.apply(vj, zj, 1, s);
+    else LSH_HIP(hipMemcpyAsync(zj, vj, sizeof(z64) * N, hipMemcpyDeviceToDevice, s));
+    P.op.apply(s, F.b.as<double>(), zj, w, 1);
+    // classical Gram-Schmidt, twice
+    multidot(s, V, N, j + 1, w, N, h1, part);
+    multiaxpy(s, w, V, N, j + 1, h1, N);
+    multidot(s, V, N, j + 1, w, N, h2, part);
+    multiaxpy(s, w, V, N, j + 1, h2, N);
+    multidot(s, w, 0, 1, w, N, h2 + (j + 1), part);
+    LSH_HIP(hipMemcpyAsync(hv.data(), h1, sizeof(z64) * (j + 1), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipMemcpyAsync(hv2.data(), h2, sizeof(z64) * (j + 2), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    const double hn = std::sqrt(hv2[j + 1].x);
+    if (hn > 0) scale_by_invnorm(s, w, w, h2 + (j + 1), N);
+    auto Hc = [&](int r, int c) -> std::complex<double>& { return H[(size_t)r * maxit + c]; };
+    for (int i = 0; i <= j; ++i) Hc(i, j) = {hv[i].x + hv2[i].x, hv[i].y + hv2[i].y};
+    Hc(j + 1, j) = hn;
+    for (int i = 0; i < j; ++i) {
+      std::complex<double> a = Hc(i, j), c2 = Hc(i + 1, j);
+      Hc(i, j) = std::conj(cs[i]) * a + std::conj(sn[i]) * c2;
+      Hc(i + 1, j) = -sn[i] * a + cs[i] * c2;
+    }
+    std::complex<double> a = Hc(j, j), c2 = Hc(j + 1, j);
+    const double rho = std::hypot(std::abs(a), std::abs(c2));
+    cs[j] = rho > 0 ? a / rho : 1.0;
+    sn[j] = rho > 0 ? c2 / rho : 0.0;
+    Hc(j, j) = rho;
+    Hc(j + 1, j) = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = std::conj(cs[j]) * g[j];
+    est = std::abs(g[j + 1]) / beta;
+    its = j + 1;
+    if (info && j + 1 <= LSH_MAX_ITERS) info->history[j + 1] = est;
+    if (est < o.tol || hn == 0) break;
+  }
+  // y = H^{-1} g (upper triangular), x = Z y
+  const int k = its;
+  std::vector<std::complex<double>> y(k);
+  for (int i = k - 1; i >= 0; --i) {
+    std::complex<double> t = g[i];
+    for (int c2 = i + 1; c2 < k; ++c2) t -= H[(size_t)i * maxit + c2] * y[c2];
+    y[i] = t / H[(size_t)i * maxit + i];
+  }
+  std::vector<z64> yz(k);
+  for (int i = 0; i < k; ++i) yz[i] = mk(y[i].real(), y[i].imag());
+  LSH_HIP(hipMemcpyAsync(h1, yz.data(), sizeof(z64) * k, hipMemcpyHostToDevice, s));
+  lincomb(s, x, Z, N, k, h1, N);
+  // true residual
+  z64* r = F.res.as<z64>();
+  P.op.apply(s, F.b.as<double>(), x, r, 1);
+  sub_from(s, r, f, N);
+  multidot(s, r, 0, 1, r, N, h2, part);
+  z64 rn;
+  LSH_HIP(hipMemcpyAsync(&rn, h2, sizeof(z64), hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  true_res = std::sqrt(rn.x) / beta;
+  if (info) { info->iterations = its; info->residual = est; }
+  conv = true_res < o.tol ? 1 : 0;
+}
+
+// receivers: u(x_r) = h^2 sum_j (i/4) H0(kappa |x_r - x_j|) sigma_j
+constexpr int EV_MAXRHS = 16;
+__global__ __launch_bounds__(256) void k_eval_points(const z64* __restrict__ sig, int n, double h, double gx0,
+                                                     double gy0, double kappa, const double* __restrict__ xy,
+                                                     z64* out, int npts, int nrhs) {
+  __shared__ z64 red[EV_MAXRHS][4];
+  const int pt = blockIdx.x;
+  const double px = xy[2 * pt], py = xy[2 * pt + 1];
+  z64 acc[EV_MAXRHS];
+  for (int r = 0; r < EV_MAXRHS; ++r) acc[r] = mk(0.0, 0.0);
+  const long N = (long)n * n;
+  for (long j = threadIdx.x; j < N; j += blockDim.x) {
+    const int i1 = (int)(j % n), i2 = (int)(j / n);
+    const double dx = px - (gx0 + (i1 + 0.5) * h), dy = py - (gy0 + (i2 + 0.5) * h);
+    const double rr = kappa * sqrt(dx * dx + dy * dy);
+    const z64 g = mk(-0.25 * y0(rr), 0.25 * j0(rr));
+    for (int r = 0; r < EV_MAXRHS; ++r)
+      if (r < nrhs) fma_acc(acc[r], g, sig[r * N + j]);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = 0; r < EV_MAXRHS; ++r) {
+    if (r >= nrhs) break;
+    z64 a = acc[r];
+    for (int off = 32; off > 0; off >>= 1) {
+      a.x += __shfl_xor(a.x, off);
+      a.y += __shfl_xor(a.y, off);
+    }
+    if (lane == 0) red[r][wave] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < nrhs) {
+    const int r = threadIdx.x;
+    z64 a = red[r][0] + red[r][1] + red[r][2] + red[r][3];
+    out[(long)r * npts + pt] = (h * h) * a;
+  }
+}
+
+int fail(const lsh::Error& e) {
+  g_last_error = e.what();
+  return e.code;
+}
+
+#define API_BEGIN try {
+#define API_END                                       \
+  }                                                   \
+  catch (const lsh::Error& e) { return fail(e); }     \
+  catch (const std::bad_alloc&) {                     \
+    g_last_error = "host allocation failed";          \
+    return LSH_ERR_NOMEM;                             \
+  }                                                   \
+  catch (const std::exception& e) {                   \
+    g_last_error = e.what();                          \
+    return LSH_ERR_HIP;                               \
+  }
+
+}  // namespace
+
+extern "C" {
+
+const char* lsh_last_error(void) { return g_last_error.c_str(); }
+
+int lsh_correction_weights(int order, double kh, int* count, int* offsets, double* tau) {
+  API_BEGIN
+  LSH_REQUIRE(count && offsets && tau, LSH_ERR_INVALID_ARG, "null argument");
+  LSH_REQUIRE(kh > 0, LSH_ERR_INVALID_ARG, "kappa*h must be positive");
+  auto st = correction_stencil(order, kh);
+  *count = (int)st.size();
+  for (size_t i = 0; i < st.size(); ++i) {
+    offsets[2 * i] = st[i].dx;
+    offsets[2 * i + 1] = st[i].dy;
+    tau[2 * i] = st[i].re;
+    tau[2 * i + 1] = st[i].im;
+  }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan) {
+  API_BEGIN
+  LSH_REQUIRE(desc && plan, LSH_ERR_INVALID_ARG, "null argument");
+  validate(*desc);
+  std::unique_ptr<lsh_plan_s> P(new lsh_plan_s());
+  P->d = *desc;
+  plan_build(*P, (hipStream_t)stream);
+  *plan = P.release();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_destroy(lsh_plan_t plan) {
+  API_BEGIN
+  delete plan;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_ranks(lsh_plan_t P, int* L, int* ranks) {
+  API_BEGIN
+  LSH_REQUIRE(P && L, LSH_ERR_INVALID_ARG, "null argument");
+  *L = P->L;
+  if (ranks)
+    for (int l = 0; l <= P->L; ++l) ranks[l] = P->lev[l].k;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_level(lsh_plan_t P, int level, int* m, int* k, int* J, int* cand, void* U, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && level >= 1 && level <= P->L, LSH_ERR_INVALID_ARG, "bad level");
+  const Level& lv = P->lev[level];
+  if (m) *m = lv.m;
+  if (k) *k = lv.k;
+  if (J) std::memcpy(J, lv.J.data(), sizeof(int) * lv.k);
+  if (cand)
+    for (int i = 0; i < lv.m; ++i) { cand[2 * i] = lv.cand[i].x; cand[2 * i + 1] = lv.cand[i].y; }
+  if (U) {
+    LSH_HIP(hipMemcpyAsync(U, lv.U64.p, sizeof(z64) * (size_t)lv.m * lv.k, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    LSH_HIP(hipStreamSynchronize((hipStream_t)stream));
+  }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_block(lsh_plan_t P, int level, int* rows, void* out, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && level >= -1 && level < P->L, LSH_ERR_INVALID_ARG, "bad level");
+  const int c = level < 0 ? P->mL : P->lev[level].c;
+  if (rows) *rows = c;
+  if (out) {
+    const void* src = level < 0 ? P->Gleaf64.p : P->lev[level].Gab64.p;
+    LSH_HIP(hipMemcpyAsync(out, src, sizeof(z64) * (size_t)c * c, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    LSH_HIP(hipStreamSynchronize((hipStream_t)stream));
+  }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_table(lsh_plan_t P, int* D, void* out, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P, LSH_ERR_INVALID_ARG, "null plan");
+  if (D) *D = P->D;
+  if (out) {
+    LSH_HIP(hipMemcpyAsync(out, P->table.p, P->table.bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    LSH_HIP(hipStreamSynchronize((hipStream_t)stream));
+  }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_factor_create(lsh_plan_t P, const double* b, void* stream, lsh_factor_t* factor) {
+  API_BEGIN
+  LSH_REQUIRE(P && b && factor, LSH_ERR_INVALID_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const long N = (long)P->n * P->n;
+  std::unique_ptr<lsh_factor_s> F(new lsh_factor_s());
+  F->plan = P;
+  F->b.alloc(sizeof(double) * N);
+  LSH_HIP(hipMemcpyAsync(F->b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  {
+    DevBuf bad(sizeof(int));
+    fill_zero(s, bad.p, sizeof(int));
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
+    int hb = 0;
+    LSH_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries");
+  }
+  if (P->d.hbs_prec == LSH_FP32) factor_build<float>(*P, F->b.as<double>(), F->f32, s);
+  else factor_build<double>(*P, F->b.as<double>(), F->f64, s);
+  *factor = F.release();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_factor_destroy(lsh_factor_t F) {
+  API_BEGIN
+  delete F;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_apply_precond(lsh_factor_t F, int transpose, const void* x, void* y, int nrhs, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(F && x && y && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  LSH_REQUIRE(!transpose, LSH_ERR_UNSUPPORTED, "transpose apply not available");
+  F->apply(static_cast<const z64*>(x), static_cast<z64*>(y), nrhs, (hipStream_t)stream);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_apply_operator(lsh_plan_t P, const double* b, const void* x, void* y, int nrhs, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && x && y && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  P->op.apply((hipStream_t)stream, b, static_cast<const z64*>(x), static_cast<z64*>(y), nrhs);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u, const lsh_solve_opts* opts,
+              lsh_info* info, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(F && u_inc && sigma && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  lsh_solve_opts o{1e-10, 100, 1};
+  if (opts) o = *opts;
+  LSH_REQUIRE(o.maxit >= 1 && o.maxit <= LSH_MAX_ITERS && o.tol > 0, LSH_ERR_INVALID_ARG, "bad solve options");
+  hipStream_t s = (hipStream_t)stream;
+  lsh_plan_s& P = *F->plan;
+  const long N = (long)P.n * P.n;
+  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * N) F->fvec.alloc(sizeof(z64) * N);
+  z64* f = F->fvec.as<z64>();
+  int allconv = 1;
+  double worst = 0;
+  if (info) std::memset(info, 0, sizeof(lsh_info));
+  for (int r = 0; r < nrhs; ++r) {
+    const z64* ui = static_cast<const z64*>(u_inc) + r * N;
+    z64* sg = static_cast<z64*>(sigma) + r * N;
+    hipLaunchKernelGGL(k_rhs, dim3(2048), dim3(256), 0, s, f, ui, F->b.as<double>(), P.kappa * P.kappa, N);
+    LSH_LAUNCH_CHECK();
+    double tr = 0;
+    int conv = 0;
+    fgmres_one(*F, f, sg, o, info, tr, conv, s);
+    if (!conv) allconv = 0;
+    if (tr > worst) worst = tr;
+  }
+  if (info) info->true_residual = worst;
+  if (u) P.op.apply(s, nullptr, static_cast<const z64*>(sigma), static_cast<z64*>(u), nrhs);
+  return allconv ? LSH_OK : LSH_NOT_CONVERGED;
+  API_END
+}
+
+int lsh_solve_adjoint(lsh_factor_t F, const void* g, int nrhs, void* lambda, const lsh_solve_opts* opts,
+                      lsh_info* info, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(F && g && lambda && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  LSH_REQUIRE(false, LSH_ERR_UNSUPPORTED, "adjoint solve not available yet");
+  return LSH_OK;
+  API_END
+}
+
+int lsh_eval_points(lsh_plan_t P, const void* sigma, const double* xy, int npts, void* u_pts, int nrhs,
+                    void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && sigma && xy && u_pts && npts >= 1 && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  for (int r0 = 0; r0 < nrhs; r0 += EV_MAXRHS) {
+    const int nr = nrhs - r0 < EV_MAXRHS ? nrhs - r0 : EV_MAXRHS;
+    const long N = (long)P->n * P->n;
+    hipLaunchKernelGGL(k_eval_points, dim3(npts), dim3(256), 0, s, static_cast<const z64*>(sigma) + r0 * N, P->n,
+                       P->h, P->d.x0, P->d.y0, P->kappa, xy, static_cast<z64*>(u_pts) + (long)r0 * npts, npts, nr);
+    LSH_LAUNCH_CHECK();
+  }
+  return LSH_OK;
+  API_END
+}
+
+}  // extern "C"
+
+#include "../../include/lsh_dev.h"
+
+extern "C" {
+
+int lsh_dev_gemm(int prec, int M, int N, int K, const double* alpha, const void* A, long lda, long sA, int opA,
+                 const void* B, long ldb, long sB, int opB, const double* beta, const void* D, long ldd, long sD,
+                 void* C, long ldc, long sC, int batch, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(alpha && beta && A && B && C && M >= 0 && N >= 0 && K >= 0 && batch >= 0, LSH_ERR_INVALID_ARG,
+              "bad gemm argument");
+  LSH_REQUIRE(opA >= 0 && opA <= 3 && opB >= 0 && opB <= 3, LSH_ERR_INVALID_ARG, "bad op");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LSH_FP64)
+    cgemm<double>(s, M, N, K, mk(alpha[0], alpha[1]), (const z64*)A, lda, sA, (Op)opA, (const z64*)B, ldb, sB,
+                  (Op)opB, mk(beta[0], beta[1]), (const z64*)D, ldd, sD, (z64*)C, ldc, sC, batch);
+  else
+    cgemm<float>(s, M, N, K, mk((float)alpha[0], (float)alpha[1]), (const c32*)A, lda, sA, (Op)opA, (const c32*)B,
+                 ldb, sB, (Op)opB, mk((float)beta[0], (float)beta[1]), (const c32*)D, ldd, sD, (c32*)C, ldc, sC,
+                 batch);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_dev_inverse(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(A && c >= 1 && batch >= 1, LSH_ERR_INVALID_ARG, "bad inverse argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LSH_FP64) {
+    DevBuf ws(inverse_ws_bytes<double>(c, batch));
+    inverse<double>(s, (z64*)A, c, lda, sA, batch, ws.p, info);
+    LSH_HIP(hipStreamSynchronize(s));
+  } else {
+    DevBuf ws(inverse_ws_bytes<float>(c, batch));
+    inverse<float>(s, (c32*)A, c, lda, sA, batch, ws.p, info);
+    LSH_HIP(hipStreamSynchronize(s));
+  }
+  return LSH_OK;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,353 @@
+// FFT convolution operator (paper Sec. 2.2 end and Sec. 5: G + T is a
+// convolution on the regular grid, applied by FFT), kernel-entry generator
+// and FGMRES vector kernels.  All FP64.
+#include <cmath>
+
+#include "ops.hpp"
+
+namespace lsh {
+
+// ------------------------------------------------------------ offset table
+__global__ void k_offset_table(z64* T, int D, double h, double kappa, double t0r, double t0i) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long W = D + 1;
+  if (e >= W * W) return;
+  const int dy = (int)(e / W), dx = (int)(e % W);
+  z64 v;
+  if (dx == 0 && dy == 0) {
+    v = mk(t0r, t0i);
+  } else {
+    const double r = kappa * h * sqrt((double)dx * dx + (double)dy * dy);
+    // (i/4) H0(r) = (i/4)(J0 + i Y0) = -Y0/4 + i J0/4
+    v = mk(-0.25 * y0(r), 0.25 * j0(r));
+  }
+  T[e] = (h * h) * v;
+}
+
+void build_offset_table(hipStream_t s, z64* T, int D, double h, double kappa, double tau0_re, double tau0_im) {
+  const long W = D + 1;
+  hipLaunchKernelGGL(k_offset_table, dim3(ceil_div(W * W, 256)), dim3(256), 0, s, T, D, h, kappa, tau0_re,
+                     tau0_im);
+  LSH_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------- FFT
+void FFTPlan::init(int M_) {
+  M = M_;
+  logM = 0;
+  while ((1 << logM) < M) ++logM;
+  LSH_REQUIRE((1 << logM) == M && M >= 2 && M <= 4096, -6, "FFT length must be a power of two <= 4096");
+  std::vector<z64> h(M / 2);
+  for (int k = 0; k < M / 2; ++k) {
+    long double a = -2.0L * 3.141592653589793238462643383279502884L * k / M;
+    h[k] = mk((double)std::cos(a), (double)std::sin(a));
+  }
+  tw.alloc(sizeof(z64) * h.size());
+  LSH_HIP(hipMemcpy(tw.p, h.data(), sizeof(z64) * h.size(), hipMemcpyHostToDevice));
+}
+
+// In-place radix-2 decimation-in-time transform of x (bit-reversed input).
+__device__ __forceinline__ void fft_lds(z64* x, int M, int logM, const z64* __restrict__ W, bool inv) {
+  for (int st = 0; st < logM; ++st) {
+    const int half = 1 << st;
+    const int ts = M >> (st + 1);
+    for (int bf = threadIdx.x; bf < (M >> 1); bf += blockDim.x) {
+      const int pos = bf & (half - 1);
+      const int i = ((bf >> st) << (st + 1)) + pos, j = i + half;
+      z64 w = W[pos * ts];
+      if (inv) w.y = -w.y;
+      const z64 t = w * x[j];
+      const z64 u = x[i];
+      x[i] = u + t;
+      x[j] = u - t;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int bitrev(int i, int logM) { return (int)(__brev((unsigned)i) >> (32 - logM)); }
+
+// mode 0: plain rows; mode 1: multiply by spectrum row then inverse transform;
+// mode 2: inverse transform with operator epilogue y = x + kb2 * b * v.
+__global__ __launch_bounds__(256) void k_fft_rows(const z64* __restrict__ in, long ldin, int nin, z64* out,
+                                                  long ldout, int nout, int M, int logM,
+                                                  const z64* __restrict__ W, int inv, int mode,
+                                                  const z64* __restrict__ spec, long ldspec,
+                                                  const z64* __restrict__ xadd, const double* __restrict__ b,
+                                                  double kb2) {
+  extern __shared__ unsigned char smem_raw[];
+  z64* x = reinterpret_cast<z64*>(smem_raw);
+  const long r = blockIdx.x;
+  const z64* src = in + r * ldin;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) x[bitrev(i, logM)] = i < nin ? src[i] : mk(0.0, 0.0);
+  __syncthreads();
+  fft_lds(x, M, logM, W, inv != 0);
+  if (mode == 1) {
+    const z64* sp = spec + r * ldspec;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = x[i] * sp[i];
+    __syncthreads();
+    // back to bit-reversed order for the inverse transform
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+      const int j = bitrev(i, logM);
+      if (i < j) { z64 t = x[i]; x[i] = x[j]; x[j] = t; }
+    }
+    __syncthreads();
+    fft_lds(x, M, logM, W, true);
+  }
+  z64* dst = out + r * ldout;
+  if (mode == 2) {
+    for (int i = threadIdx.x; i < nout; i += blockDim.x) {
+      const long g = r * ldout + i;
+      dst[i] = xadd[g] + (kb2 * b[g]) * x[i];
+    }
+  } else {
+    for (int i = threadIdx.x; i < nout; i += blockDim.x) dst[i] = x[i];
+  }
+}
+
+void fft_rows(hipStream_t s, const FFTPlan& P, const z64* in, long ldin, int nin, z64* out, long ldout, int nout,
+              int nrows, bool inverse) {
+  hipLaunchKernelGGL(k_fft_rows, dim3(nrows), dim3(256), P.M * sizeof(z64), s, in, ldin, nin, out, ldout, nout,
+                     P.M, P.logM, P.tw.as<z64>(), inverse ? 1 : 0, 0, (const z64*)nullptr, 0L,
+                     (const z64*)nullptr, (const double*)nullptr, 0.0);
+  LSH_LAUNCH_CHECK();
+}
+
+constexpr int TT = 32;
+__global__ __launch_bounds__(256) void k_transpose(const z64* __restrict__ in, long ldin, z64* __restrict__ out,
+                                                   long ldout, int rows, int cols) {
+  __shared__ z64 tile[TT][TT + 1];
+  const int c0 = blockIdx.x * TT, r0 = blockIdx.y * TT;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < TT; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = in[(long)r * ldin + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < TT; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) out[(long)c * ldout + r] = tile[tx][k];
+  }
+}
+
+void transpose(hipStream_t s, const z64* in, long ldin, z64* out, long ldout, int rows, int cols) {
+  dim3 grid(ceil_div(cols, TT), ceil_div(rows, TT));
+  hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, in, ldin, out, ldout, rows, cols);
+  LSH_LAUNCH_CHECK();
+}
+
+// C[dy mod M][dx mod M] = h^2 (G(h|d|)[d != 0] + tau_d) for |dx|, |dy| < n
+__global__ void k_fill_circulant(z64* C, int M, int n, const z64* __restrict__ T, int D) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)M * M) return;
+  const int iy = (int)(e / M), ix = (int)(e % M);
+  const int dy = iy < n ? iy : iy - M, dx = ix < n ? ix : ix - M;
+  z64 v = mk(0.0, 0.0);
+  const int ady = dy < 0 ? -dy : dy, adx = dx < 0 ? -dx : dx;
+  if (ady < n && adx < n && ady <= D && adx <= D && !(dx == 0 && dy == 0)) v = T[(long)ady * (D + 1) + adx];
+  C[e] = v;
+}
+
+__global__ void k_add_stencil(z64* C, int M, const int* dxy, const z64* w, int cnt) {
+  const int k = threadIdx.x;
+  if (k >= cnt) return;
+  const int dx = dxy[2 * k], dy = dxy[2 * k + 1];
+  const int ix = (dx + M) % M, iy = (dy + M) % M;
+  C[(long)iy * M + ix] = C[(long)iy * M + ix] + w[k];
+}
+
+__global__ void k_scale_c(z64* a, long n, double s) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = s * a[i];
+}
+
+void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z64* table, int D,
+                        const std::vector<StencilEntry>& stencil) {
+  n = n_;
+  kappa = kappa_;
+  M = 1;
+  while (M < 2 * n) M <<= 1;
+  fft.init(M);
+  khatT.alloc(sizeof(z64) * (size_t)M * M);
+  w1.alloc(sizeof(z64) * (size_t)n * M);
+  w2.alloc(sizeof(z64) * (size_t)M * M);
+  z64* C = w2.as<z64>();
+  hipLaunchKernelGGL(k_fill_circulant, dim3(ceil_div((long)M * M, 256)), dim3(256), 0, s, C, M, n, table, D);
+  LSH_LAUNCH_CHECK();
+  std::vector<int> dxy;
+  std::vector<z64> wv;
+  for (auto& e : stencil) {
+    if (std::abs(e.dx) >= n || std::abs(e.dy) >= n) continue;
+    dxy.push_back(e.dx);
+    dxy.push_back(e.dy);
+    wv.push_back(mk(h * h * e.re, h * h * e.im));
+  }
+  DevBuf ddxy(sizeof(int) * dxy.size()), dw(sizeof(z64) * wv.size());
+  LSH_HIP(hipMemcpyAsync(ddxy.p, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
+  LSH_HIP(hipMemcpyAsync(dw.p, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_add_stencil, dim3(1), dim3(64), 0, s, C, M, ddxy.as<int>(), dw.as<z64>(), (int)wv.size());
+  LSH_LAUNCH_CHECK();
+  // full 2-D transform, kept transposed: khatT[k1][k2]
+  z64* Kt = khatT.as<z64>();
+  fft_rows(s, fft, C, M, M, C, M, M, M, false);
+  transpose(s, C, M, Kt, M, M, M);
+  fft_rows(s, fft, Kt, M, M, Kt, M, M, M, false);
+  hipLaunchKernelGGL(k_scale_c, dim3(ceil_div((long)M * M, 256)), dim3(256), 0, s, Kt, (long)M * M,
+                     1.0 / ((double)M * M));
+  LSH_LAUNCH_CHECK();
+  LSH_HIP(hipStreamSynchronize(s));  // the small staging buffers die here
+}
+
+void ConvOperator::apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs) {
+  z64* W1 = w1.as<z64>();
+  z64* W2 = w2.as<z64>();
+  const size_t lds = M * sizeof(z64);
+  for (int r = 0; r < nrhs; ++r) {
+    const z64* xr = x + (long)r * n * n;
+    z64* yr = y + (long)r * n * n;
+    // rows (x1 direction) of the n data rows, padded to M
+    hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, xr, (long)n, n, W1, (long)M, M, M, fft.logM,
+                       fft.tw.as<z64>(), 0, 0, (const z64*)nullptr, 0L, (const z64*)nullptr,
+                       (const double*)nullptr, 0.0);
+    LSH_LAUNCH_CHECK();
+    transpose(s, W1, M, W2, n, n, M);  // W2: M x n
+    // columns: transform, multiply by the spectrum, transform back, keep n
+    hipLaunchKernelGGL(k_fft_rows, dim3(M), dim3(256), lds, s, W2, (long)n, n, W2, (long)n, n, M, fft.logM,
+                       fft.tw.as<z64>(), 0, 1, khatT.as<z64>(), (long)M, (const z64*)nullptr,
+                       (const double*)nullptr, 0.0);
+    LSH_LAUNCH_CHECK();
+    transpose(s, W2, n, W1, M, M, n);  // W1: n x M
+    if (b) {
+      hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, W1, (long)M, M, yr, (long)n, n, M, fft.logM,
+                         fft.tw.as<z64>(), 1, 2, (const z64*)nullptr, 0L, xr, b, kappa * kappa);
+    } else {
+      hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, W1, (long)M, M, yr, (long)n, n, M, fft.logM,
+                         fft.tw.as<z64>(), 1, 3, (const z64*)nullptr, 0L, (const z64*)nullptr,
+                         (const double*)nullptr, 0.0);
+    }
+    LSH_LAUNCH_CHECK();
+  }
+}
+
+// --------------------------------------------------------- vector kernels
+constexpr int MD_BLOCKS = 1024, MD_NT = 256, MD_MAXV = 128;
+
+__global__ __launch_bounds__(MD_NT) void k_multidot(const z64* __restrict__ V, long ldv, int nv,
+                                                    const z64* __restrict__ w, long N, z64* partial) {
+  __shared__ z64 red[MD_MAXV][MD_NT / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    const z64* Vv = V + v * ldv;
+    z64 acc = mk(0.0, 0.0);
+    for (long i = blockIdx.x * (long)MD_NT + threadIdx.x; i < N; i += (long)MD_BLOCKS * MD_NT)
+      fma_acc(acc, conjg(Vv[i]), w[i]);
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) red[v][wave] = acc;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += MD_NT) {
+    z64 a = red[v][0];
+    for (int k = 1; k < MD_NT / 64; ++k) a = a + red[v][k];
+    partial[(long)v * MD_BLOCKS + blockIdx.x] = a;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const z64* partial, int nparts, z64* out) {
+  __shared__ z64 red[256];
+  const int v = blockIdx.x;
+  z64 a = mk(0.0, 0.0);
+  for (int k = threadIdx.x; k < nparts; k += 256) a = a + partial[(long)v * nparts + k];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = red[0];
+}
+
+size_t multidot_partial_bytes(int nv) { return sizeof(z64) * (size_t)nv * MD_BLOCKS; }
+
+void multidot(hipStream_t s, const z64* V, long ldv, int nv, const z64* w, long N, z64* out, z64* partial) {
+  LSH_REQUIRE(nv <= MD_MAXV, -6, "multidot: too many vectors");
+  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS), dim3(MD_NT), 0, s, V, ldv, nv, w, N, partial);
+  LSH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(256), 0, s, partial, MD_BLOCKS, out);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_multiaxpy(z64* w, const z64* __restrict__ V, long ldv, int nv, const z64* __restrict__ h, long N) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+    z64 a = w[i];
+    for (int v = 0; v < nv; ++v) a = a - V[v * ldv + i] * h[v];
+    w[i] = a;
+  }
+}
+
+void multiaxpy(hipStream_t s, z64* w, const z64* V, long ldv, int nv, const z64* h, long N) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3(2048), dim3(256), 0, s, w, V, ldv, nv, h, N);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_invnorm(z64* y, const z64* x, const z64* nrm2, long N) {
+  const double s = 1.0 / sqrt(nrm2[0].x);
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+    y[i] = s * x[i];
+}
+
+void scale_by_invnorm(hipStream_t s, z64* y, const z64* x, const z64* nrm2, long N) {
+  hipLaunchKernelGGL(k_scale_invnorm, dim3(2048), dim3(256), 0, s, y, x, nrm2, N);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_lincomb(z64* y, const z64* __restrict__ V, long ldv, int nv, const z64* __restrict__ c, long N) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+    z64 a = mk(0.0, 0.0);
+    for (int v = 0; v < nv; ++v) fma_acc(a, V[v * ldv + i], c[v]);
+    y[i] = a;
+  }
+}
+
+void lincomb(hipStream_t s, z64* y, const z64* V, long ldv, int nv, const z64* c, long N) {
+  hipLaunchKernelGGL(k_lincomb, dim3(2048), dim3(256), 0, s, y, V, ldv, nv, c, N);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_real(z64* y, const z64* x, const double* b, double a, long N, long nb) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+    y[i] = (a * b[i % nb]) * x[i];
+}
+
+void scale_real(hipStream_t s, z64* y, const z64* x, const double* b, double a, long N) {
+  hipLaunchKernelGGL(k_scale_real, dim3(2048), dim3(256), 0, s, y, x, b, a, N, N);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_sub_from(z64* y, const z64* x, long N) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+    y[i] = x[i] - y[i];
+}
+
+void sub_from(hipStream_t s, z64* y, const z64* x, long N) {
+  hipLaunchKernelGGL(k_sub_from, dim3(2048), dim3(256), 0, s, y, x, N);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_fill_zero(uint32_t* p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+void fill_zero(hipStream_t s, void* p, size_t bytes) {
+  if (!bytes) return;
+  LSH_REQUIRE(bytes % 4 == 0, -1, "fill_zero: size must be a multiple of 4");
+  long n = (long)(bytes / 4);
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, static_cast<uint32_t*>(p), n);
+  LSH_LAUNCH_CHECK();
+}
+
+}  // namespace lsh

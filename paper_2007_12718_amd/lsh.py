@@ -1,0 +1,287 @@
+"""ctypes binding of liblsh (include/lsh.h, include/lsh_dev.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are torch tensors on the current HIP device (complex128 fields,
+float64 b); the current torch stream is passed to every call.  The binding
+raises if the library is missing or a call fails -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_long, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsh.so")
+
+LSH_OK, LSH_NOT_CONVERGED = 0, 1
+LSH_FP64, LSH_FP32 = 0, 1
+MAX_ITERS = 200
+MAX_LEVELS = 32
+
+EXPORTED = [
+    "lsh_plan_create", "lsh_plan_destroy", "lsh_plan_ranks", "lsh_plan_level", "lsh_plan_block",
+    "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
+    "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
+    "lsh_dev_gemm", "lsh_dev_inverse",
+]
+
+
+class LshDesc(ctypes.Structure):
+    _fields_ = [("n", c_int), ("h", c_double), ("x0", c_double), ("y0", c_double), ("kappa", c_double),
+                ("op_order", c_int), ("leaf", c_int), ("tol", c_double), ("proxy_width", c_int),
+                ("hbs_prec", c_int)]
+
+
+class LshSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("maxit", c_int), ("precondition", c_int)]
+
+
+class LshInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_int), ("residual", c_double), ("true_residual", c_double),
+                ("history", c_double * (MAX_ITERS + 1)), ("ms_precond", c_double), ("ms_operator", c_double),
+                ("ms_ortho", c_double)]
+
+
+class LshError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblsh error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.lsh_last_error.restype = ctypes.c_char_p
+        L.lsh_plan_create.argtypes = [POINTER(LshDesc), c_void_p, POINTER(c_void_p)]
+        L.lsh_plan_destroy.argtypes = [c_void_p]
+        L.lsh_plan_ranks.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int)]
+        L.lsh_plan_level.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                     POINTER(c_int), c_void_p, c_void_p]
+        L.lsh_plan_block.argtypes = [c_void_p, c_int, POINTER(c_int), c_void_p, c_void_p]
+        L.lsh_plan_table.argtypes = [c_void_p, POINTER(c_int), c_void_p, c_void_p]
+        L.lsh_factor_create.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]
+        L.lsh_factor_destroy.argtypes = [c_void_p]
+        L.lsh_apply_precond.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p]
+        L.lsh_apply_operator.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+        L.lsh_solve.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p, POINTER(LshSolveOpts),
+                                POINTER(LshInfo), c_void_p]
+        L.lsh_solve_adjoint.argtypes = [c_void_p, c_void_p, c_int, c_void_p, POINTER(LshSolveOpts),
+                                        POINTER(LshInfo), c_void_p]
+        L.lsh_eval_points.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p]
+        L.lsh_correction_weights.argtypes = [c_int, c_double, POINTER(c_int), POINTER(c_int), POINTER(c_double)]
+        L.lsh_dev_gemm.argtypes = [c_int, c_int, c_int, c_int, POINTER(c_double), c_void_p, c_long, c_long, c_int,
+                                   c_void_p, c_long, c_long, c_int, POINTER(c_double), c_void_p, c_long, c_long,
+                                   c_void_p, c_long, c_long, c_int, c_void_p]
+        L.lsh_dev_inverse.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow_not_converged=False):
+    if rc == LSH_OK or (allow_not_converged and rc == LSH_NOT_CONVERGED):
+        return rc
+    raise LshError(rc, lib().lsh_last_error().decode())
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, numel=None):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"tensor too small: {t.numel()} < {numel}")
+    return c_void_p(t.data_ptr())
+
+
+def lsh_correction_weights(order: int, kh: float):
+    """Host call: stencil offsets (count, 2) and tau (count,) complex."""
+    cnt = c_int(0)
+    off = (c_int * 50)()
+    tau = (c_double * 50)()
+    _check(lib().lsh_correction_weights(order, kh, ctypes.byref(cnt), off, tau))
+    k = cnt.value
+    o = np.array(off[: 2 * k]).reshape(k, 2)
+    t = np.array(tau[: 2 * k]).reshape(k, 2)
+    return o, t[:, 0] + 1j * t[:, 1]
+
+
+class Plan:
+    """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
+
+    def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
+                 h=None, x0=-0.5, y0=-0.5):
+        self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
+                            op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
+                            hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64)
+        self.n = n
+        self.h = self.desc.h
+        self.kappa = kappa
+        self.handle = c_void_p()
+        _check(lib().lsh_plan_create(ctypes.byref(self.desc), _stream(), ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            lib().lsh_plan_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ranks(self):
+        L = c_int(0)
+        r = (c_int * (MAX_LEVELS + 1))()
+        _check(lib().lsh_plan_ranks(self.handle, ctypes.byref(L), r))
+        return L.value, list(r[: L.value + 1])
+
+    def level(self, level):
+        """(J, cand, U) of a level: pivots, candidate coords (m, 2), U (m, k) complex128 on device."""
+        import torch
+        m, k = c_int(0), c_int(0)
+        _check(lib().lsh_plan_level(self.handle, level, ctypes.byref(m), ctypes.byref(k), None, None, None,
+                                    _stream()))
+        J = (c_int * k.value)()
+        cand = (c_int * (2 * m.value))()
+        U = torch.empty((m.value, k.value), dtype=torch.complex128, device="cuda")
+        _check(lib().lsh_plan_level(self.handle, level, None, None, J, cand, _ptr(U), _stream()))
+        return np.array(J[:]), np.array(cand[:]).reshape(-1, 2), U
+
+    def block(self, level):
+        import torch
+        c = c_int(0)
+        _check(lib().lsh_plan_block(self.handle, level, ctypes.byref(c), None, _stream()))
+        out = torch.empty((c.value, c.value), dtype=torch.complex128, device="cuda")
+        _check(lib().lsh_plan_block(self.handle, level, None, _ptr(out), _stream()))
+        return out
+
+    def table(self):
+        import torch
+        D = c_int(0)
+        _check(lib().lsh_plan_table(self.handle, ctypes.byref(D), None, _stream()))
+        out = torch.empty((D.value + 1, D.value + 1), dtype=torch.complex128, device="cuda")
+        _check(lib().lsh_plan_table(self.handle, None, _ptr(out), _stream()))
+        return out
+
+    def apply_operator(self, b, x, out=None):
+        """y = x + kappa^2 b (K * x); b=None gives K * x.  x: (nrhs, n, n) complex128."""
+        import torch
+        x = x.reshape(-1, self.n, self.n)
+        y = torch.empty_like(x) if out is None else out
+        bp = _ptr(b, torch.float64, self.n * self.n) if b is not None else None
+        _check(lib().lsh_apply_operator(self.handle, bp, _ptr(x, torch.complex128), _ptr(y, torch.complex128),
+                                        x.shape[0], _stream()))
+        return y
+
+    def eval_points(self, sigma, xy):
+        import torch
+        sigma = sigma.reshape(-1, self.n, self.n)
+        xy = xy.reshape(-1, 2).contiguous()
+        out = torch.empty((sigma.shape[0], xy.shape[0]), dtype=torch.complex128, device="cuda")
+        _check(lib().lsh_eval_points(self.handle, _ptr(sigma, torch.complex128), _ptr(xy, torch.float64),
+                                     xy.shape[0], _ptr(out), sigma.shape[0], _stream()))
+        return out
+
+
+class Factor:
+    """lsh_factor_create: Algorithm 1 for the potential b (float64, (n, n), device)."""
+
+    def __init__(self, plan: Plan, b):
+        import torch
+        self.plan = plan
+        self.handle = c_void_p()
+        b = b.reshape(plan.n, plan.n).contiguous()
+        _check(lib().lsh_factor_create(plan.handle, _ptr(b, torch.float64), _stream(), ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            lib().lsh_factor_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_precond(self, x, transpose=False):
+        import torch
+        n = self.plan.n
+        x = x.reshape(-1, n, n).contiguous()
+        y = torch.empty_like(x)
+        _check(lib().lsh_apply_precond(self.handle, int(transpose), _ptr(x, torch.complex128),
+                                       _ptr(y, torch.complex128), x.shape[0], _stream()))
+        return y
+
+    def solve(self, u_inc, tol=1e-10, maxit=100, precondition=True, want_u=True):
+        """sigma, u, info for incident fields u_inc (nrhs, n, n) complex128."""
+        import torch
+        n = self.plan.n
+        u_inc = u_inc.reshape(-1, n, n).contiguous()
+        sig = torch.empty_like(u_inc)
+        u = torch.empty_like(u_inc) if want_u else None
+        opts = LshSolveOpts(tol=tol, maxit=maxit, precondition=int(precondition))
+        info = LshInfo()
+        rc = _check(lib().lsh_solve(self.handle, _ptr(u_inc, torch.complex128), u_inc.shape[0], _ptr(sig),
+                                    _ptr(u) if u is not None else None, ctypes.byref(opts), ctypes.byref(info),
+                                    _stream()), allow_not_converged=True)
+        return sig, u, info, rc
+
+    def solve_adjoint(self, g, tol=1e-10, maxit=100):
+        import torch
+        n = self.plan.n
+        g = g.reshape(-1, n, n).contiguous()
+        lam = torch.empty_like(g)
+        opts = LshSolveOpts(tol=tol, maxit=maxit, precondition=1)
+        info = LshInfo()
+        rc = _check(lib().lsh_solve_adjoint(self.handle, _ptr(g, torch.complex128), g.shape[0], _ptr(lam),
+                                            ctypes.byref(opts), ctypes.byref(info), _stream()),
+                    allow_not_converged=True)
+        return lam, info, rc
+
+
+def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None):
+    """Batched complex GEMM through lsh_dev_gemm.  A, B: (batch, r, c) complex tensors."""
+    import torch
+    prec = LSH_FP64 if A.dtype == torch.complex128 else LSH_FP32
+    bA, ra, ca = A.shape
+    bB, rb, cb = B.shape
+    M, K = (ra, ca) if opA in (0, 3) else (ca, ra)
+    N = cb if opB in (0, 3) else rb
+    batch = max(bA, bB)
+    C = torch.empty((batch, M, N), dtype=A.dtype, device=A.device) if out is None else out
+    al = (c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (c_double * 2)(complex(beta).real, complex(beta).imag)
+    Dp = _ptr(D) if D is not None else None
+    _check(lib().lsh_dev_gemm(prec, M, N, K, al, _ptr(A), ca, ra * ca if bA > 1 else 0, opA, _ptr(B), cb,
+                              rb * cb if bB > 1 else 0, opB, be, Dp, N, M * N if D is not None else 0,
+                              _ptr(C), N, M * N, batch, _stream()))
+    return C
+
+
+def dev_inverse(A):
+    """In-place batched inverse; returns (A, info)."""
+    import torch
+    prec = LSH_FP64 if A.dtype == torch.complex128 else LSH_FP32
+    b, c, _ = A.shape
+    info = torch.zeros(b, dtype=torch.int32, device=A.device)
+    _check(lib().lsh_dev_inverse(prec, _ptr(A), c, c, c * c, b, _ptr(info), _stream()))
+    return A, info
