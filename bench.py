@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Time-to-1e-10 residual (HBS build + GMRES) on one MI355X.
+
+One step = the whole hot path on one input: lsh_plan_create (tree, weights,
+kernel table, per-level proxy row IDs, FFT spectrum) + lsh_factor_create
+(Algorithm 1) + lsh_solve (flexible GMRES on the 10th-order FFT operator,
+right-preconditioned by Algorithm 2) to a relative residual < 1e-10.  Inputs
+(b, u_inc) are resident in HBM before the timed region starts.
+
+Default workload: n = 1024 (N = 1,048,576), kappa = 200 pi (100 wavelengths,
+~10 points per wavelength), b a seeded random Fourier field (|k| <= 20 cycles
+per unit) scaled to [-1, 0.9], plane wave exp(i kappa x1), HBS at tol 1e-4
+with 4th-order corrections (leaf 8x8, proxy width 2), GMRES operator with
+10th-order corrections.  The headline value is the FP32-HBS form; the FP64-HBS
+form is timed beside it.
+
+Prints one JSON line (rank 0).  --gpus N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-HBS comparison form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=256, help="grid side of the oracle's timed sample")
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel hipEvent records")
+    return ap.parse_args()
+
+
+def workload(n):
+    import numpy as np
+    import synth
+    return synth.largest(n=n, kappa=200 * np.pi * n / 1024)
+
+
+def run_step(lsh, w, b_d, u_d, prec, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width, prec=prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    F = lsh.Factor(P, b_d)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sig, _, info, rc = F.solve(u_d, tol=w.gmres_tol, maxit=100, want_u=False)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out = {"plan_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "total_s": t3 - t0,
+           "iterations": info.iterations, "true_residual": info.true_residual, "rc": rc,
+           "ranks": P.ranks()[1]}
+    F.close()
+    P.close()
+    del sig
+    return out
+
+
+def roofline(lsh):
+    """Dominant instrumented kernel over the timed region, against its peak."""
+    best = None
+    for name in lsh.lsh_profile_names():
+        n, ms, work = lsh.lsh_profile_query(name)
+        if n and (best is None or ms > best[2]):
+            best = (name, n, ms, work)
+    if best is None:
+        return None
+    name, n, ms, work = best
+    if name.startswith("cgemm") or name.startswith("inverse"):
+        peak = PEAK_FP32_TFLOPS if name.endswith("f32") else PEAK_FP64_TFLOPS
+        achieved = work / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "launches": n, "ms_total": ms,
+                "work_per_launch": work / n}
+    achieved = work / (ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "launches": n, "ms_total": ms,
+            "work_per_launch": work / n}
+
+
+def kernel_table(lsh):
+    rows = {}
+    for name in lsh.lsh_profile_names():
+        n, ms, work = lsh.lsh_profile_query(name)
+        rows[name] = {"launches": n, "ms": round(ms, 3), "work": work}
+    return rows
+
+
+def cpu_baseline(n_full, n_sample):
+    """The oracle (numpy/scipy, as written) on a bounded sample: the same
+    workload family at n_sample (same kappa*h), plan + build + FGMRES to 1e-10;
+    scaled to n_full by the O(N^{3/2}) = O(n^3) cost of the method."""
+    import numpy as np
+    from oracle import dense, fftop, gmres, hbs
+    w = workload(n_sample)
+    hbs.Compression(16, w.kappa, 8, w.tol, w.proxy_width)  # warm the weight constants
+    t0 = time.perf_counter()
+    C = hbs.Compression(w.n, w.kappa, w.leaf, w.tol, w.proxy_width)
+    M = hbs.Inverse(C, w.b)
+    F = fftop.FFTOperator(w.n, w.kappa, w.op_order)
+    f = dense.rhs(w.b, w.u_inc, w.kappa)
+    x, it, hist = gmres.fgmres(lambda v: F.apply(w.b, v).reshape(-1), M.apply, f, w.gmres_tol, 100)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    scale = (n_full / n_sample) ** 3
+    return {"value": dt * scale, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle plan+build+FGMRES at n={n_sample} (N={n_sample ** 2}, same kappa*h), "
+                      f"{dt:.2f} s measured, {it} iterations, scaled by (n/{n_sample})^3 = {scale:.0f} "
+                      f"to n={n_full}; host cpu_count={os.cpu_count()}"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md but not built)"}))
+        return 2
+    import numpy as np
+    import torch
+    from paper_2007_12718_amd import lsh
+
+    torch.cuda.set_device(0)
+    w = workload(a.n)
+    b_d = torch.from_numpy(w.b).cuda()
+    u_d = torch.from_numpy(w.u_inc).cuda()
+    forms = ["fp32"] + ([] if a.no_fp64 else ["fp64"])
+    for _ in range(a.warmup):
+        for prec in forms:
+            r = run_step(lsh, w, b_d, u_d, prec, torch)
+            print(f"# warmup {prec}: {json.dumps(r)}", file=sys.stderr, flush=True)
+    results = {}
+    prof = None
+    for prec in forms:
+        steps = []
+        if prec == "fp32" and not a.no_profile:
+            lsh.lsh_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(a.steps):
+            r = run_step(lsh, w, b_d, u_d, prec, torch)
+            steps.append(r)
+            print(f"# step {k} {prec}: {json.dumps(r)}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if prec == "fp32" and not a.no_profile:
+            prof = {"roofline": roofline(lsh), "kernels": kernel_table(lsh)}
+            lsh.lsh_profile_enable(False)
+        med = sorted(steps, key=lambda r: r["total_s"])[len(steps) // 2]
+        results[prec] = {"wall_s": wall, "ms_per_step": 1e3 * wall / a.steps, "median": med}
+    head = results["fp32"]
+    out = {
+        "metric": "time-to-1e-10 residual (HBS build+GMRES), FP32-HBS vs FP64-HBS, N~1M",
+        "value": head["ms_per_step"] / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 HBS + c128 GMRES",
+        "data": "synthetic",
+        "config": {"workload": f"fourier-{w.n}: n={w.n} (N={w.n ** 2}), kappa={w.kappa:.4f}, "
+                               f"b random Fourier field |k|<=20 cycles in [-1,0.9], plane wave, "
+                               f"HBS 4th order tol={w.tol} leaf={w.leaf} proxy_width={w.proxy_width}, "
+                               f"operator order {w.op_order}, GMRES tol {w.gmres_tol}",
+                   "hbs_prec": "fp32", "phases_s": {k: head["median"][k] for k in
+                                                    ("plan_s", "factor_s", "solve_s", "total_s")},
+                   "iterations": head["median"]["iterations"],
+                   "true_residual": head["median"]["true_residual"],
+                   "ranks": head["median"]["ranks"]},
+    }
+    if "fp64" in results:
+        r64 = results["fp64"]
+        out["fp64_hbs"] = {"value": r64["ms_per_step"] / 1e3, "unit": "s",
+                           "phases_s": {k: r64["median"][k] for k in ("plan_s", "factor_s", "solve_s", "total_s")},
+                           "iterations": r64["median"]["iterations"],
+                           "true_residual": r64["median"]["true_residual"],
+                           "speedup_fp32_over_fp64": r64["ms_per_step"] / head["ms_per_step"]}
+    if prof:
+        out["roofline"] = prof["roofline"]
+        out["kernels"] = prof["kernels"]
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w.n, min(a.cpu_n, w.n))
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

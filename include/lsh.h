@@ -153,6 +153,18 @@ int lsh_eval_points(lsh_plan_t plan, const void* sigma, const double* xy, int np
  * offsets (host int[2*count]) and tau (host double[2*count], re/im). */
 int lsh_correction_weights(int order, double kh, int* count, int* offsets, double* tau);
 
+/* ---- tracing: per-kernel hipEvent timing (off by default) ----
+ * lsh_profile_enable(1) clears the records and starts recording a start/stop
+ * event pair around each instrumented launch (on the launch's stream),
+ * tagged with the launch's algorithmic work (flops for cgemm_* / inverse_*,
+ * bytes for the bandwidth-bound kernels).  lsh_profile_query synchronises
+ * the device and returns, for one kernel name, the number of launches, the
+ * summed event time (ms) and the summed work.  lsh_profile_names writes the
+ * recorded names, ';'-separated, into buf (host char[cap]). */
+int lsh_profile_enable(int on);
+int lsh_profile_query(const char* name, int* launches, double* ms, double* work);
+int lsh_profile_names(char* buf, int cap);
+
 const char* lsh_last_error(void);
 
 #ifdef __cplusplus

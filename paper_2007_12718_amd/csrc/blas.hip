@@ -4,6 +4,7 @@
 // real 16x16x4 MFMAs (Re += ArBr - AiBi, Im += ArBi + AiBr) on LDS-staged
 // 64x64 tiles; four 64-wide wavefronts each own a 32x32 quarter of the tile.
 #include "blas.hpp"
+#include "prof.hpp"
 
 namespace lsh {
 
@@ -147,6 +148,7 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            cplx<R> beta, const cplx<R>* D, long ldd, long sD,
            cplx<R>* C, long ldc, long sC, int batch, bool add_identity) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
+  ProfScope ps(sizeof(R) == 4 ? "cgemm_f32" : "cgemm_f64", s, 8.0 * M * N * K * (double)batch);
   GemmP<R> P;
   P.M = M; P.N = N; P.K = K; P.alpha = alpha; P.beta = beta;
   P.A = A; P.lda = lda; P.sA = sA; P.opA = opA;
@@ -207,6 +209,10 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
            cplx<R>* y, long sy, int batch) {
   if (M <= 0 || batch <= 0) return;
   LSH_REQUIRE((size_t)N * sizeof(cplx<R>) <= 65536, -6, "cgemv: row length too large for LDS staging");
+  // algorithmic bytes: every distinct matrix once, x, z and y once per problem
+  const int nmat = amod < batch ? amod : batch;
+  ProfScope ps(sizeof(R) == 4 ? "cgemv_f32" : "cgemv_f64", s,
+               (double)sizeof(cplx<R>) * ((double)nmat * M * N + (double)batch * (N + (z ? 2.0 : 1.0) * M)));
   LSH_REQUIRE(ceil_div(M, GV_ROWS) <= 65535, -6, "cgemv: too many rows");
   dim3 grid(batch, ceil_div(M, GV_ROWS));
   hipLaunchKernelGGL(k_cgemv<R>, grid, dim3(256), N * sizeof(cplx<R>), s, M, N, alpha, A, lda, sA,
@@ -482,6 +488,7 @@ size_t inverse_ws_bytes(int c, int batch) {
 template <typename R>
 void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, void* ws, int* info) {
   if (c <= 0 || batch <= 0) return;
+  ProfScope ps(sizeof(R) == 4 ? "inverse_f32" : "inverse_f64", s, 8.0 * (double)c * c * c * batch);
   if (info) hipLaunchKernelGGL(k_zero_int, dim3(ceil_div(batch, 256)), dim3(256), 0, s, info, batch);
   const size_t lds = small_inv_lds<R>(c);
   if (lds <= 65536) {

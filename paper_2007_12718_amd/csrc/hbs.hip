@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "hbs.hpp"
+#include "prof.hpp"
 
 namespace lsh {
 
@@ -157,6 +158,7 @@ __global__ __launch_bounds__(QR_NT) void k_cpqr(z64* W, int m, int np, double th
 size_t rowid_cpqr_ws(int m) { return (size_t)m * (sizeof(double) + sizeof(z64)) + 256; }
 
 void rowid_cpqr(hipStream_t s, z64* A, int m, int np, double thr, int* J, z64* U, int* k_dev, void* ws) {
+  ProfScope ps("cpqr", s, 16.0 * (double)m * np);
   double* nrm = static_cast<double*>(ws);
   z64* Rd = reinterpret_cast<z64*>(static_cast<char*>(ws) + ((m * sizeof(double) + 15) / 16) * 16);
   hipLaunchKernelGGL(k_cpqr, dim3(1), dim3(QR_NT), 0, s, A, m, np, thr, J, U, k_dev, nrm, Rd);
@@ -275,7 +277,10 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
   const int nb = 32;
   int rank = 0;
   for (int j0 = 0; j0 < m; j0 += nb) {
-    hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), 0, s, M, m, d, chosen, Lt, J, j0, nb, thr2, state);
+    {
+      ProfScope ps("pchol_panel", s, 16.0 * (double)m * nb);
+      hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), 0, s, M, m, d, chosen, Lt, J, j0, nb, thr2, state);
+    }
     LSH_LAUNCH_CHECK();
     int st[2];
     LSH_HIP(hipMemcpyAsync(st, state, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
@@ -396,6 +401,8 @@ template <typename R>
 void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const z64* f, cplx<R>* r,
              cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
+  ProfScope ps("leaf_up", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (2.0 * mL + k)) +
+                                 16.0 * nrhs * (double)nleaf * mL);
   hipLaunchKernelGGL(k_leaf_up<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, f, r, rt, leaf_origin,
                      leaf_pts, n, nleaf);
   LSH_LAUNCH_CHECK();
@@ -448,6 +455,8 @@ void leaf_down(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k
                const cplx<R>* r, z64* q, const double* b, double kappa2, const I2* leaf_origin, const I2* leaf_pts,
                int nleaf, int n, int nrhs) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
+  ProfScope ps("leaf_down", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (mL + k)) +
+                                   (16.0 + 8.0) * nrhs * (double)nleaf * mL);
   hipLaunchKernelGGL(k_leaf_down<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, wt, r, q, b, kappa2,
                      leaf_origin, leaf_pts, n, nleaf);
   LSH_LAUNCH_CHECK();

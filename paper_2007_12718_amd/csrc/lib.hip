@@ -19,7 +19,16 @@
 #include "blas.hpp"
 #include "hbs.hpp"
 #include "ops.hpp"
+#include "prof.hpp"
 #include "weights.hpp"
+
+namespace lsh {
+namespace prof {
+void set(bool enable);
+int query(const char* name, int* launches, double* ms, double* work);
+std::string names();
+}  // namespace prof
+}  // namespace lsh
 
 using namespace lsh;
 
@@ -642,6 +651,31 @@ int fail(const lsh::Error& e) {
 extern "C" {
 
 const char* lsh_last_error(void) { return g_last_error.c_str(); }
+
+int lsh_profile_enable(int on) {
+  API_BEGIN
+  prof::set(on != 0);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_profile_query(const char* name, int* launches, double* ms, double* work) {
+  API_BEGIN
+  LSH_REQUIRE(name, LSH_ERR_INVALID_ARG, "null name");
+  prof::query(name, launches, ms, work);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_profile_names(char* buf, int cap) {
+  API_BEGIN
+  LSH_REQUIRE(buf && cap > 0, LSH_ERR_INVALID_ARG, "bad buffer");
+  std::string s = prof::names();
+  std::strncpy(buf, s.c_str(), cap - 1);
+  buf[cap - 1] = 0;
+  return LSH_OK;
+  API_END
+}
 
 int lsh_correction_weights(int order, double kh, int* count, int* offsets, double* tau) {
   API_BEGIN

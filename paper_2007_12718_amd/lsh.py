@@ -25,7 +25,7 @@ EXPORTED = [
     "lsh_plan_create", "lsh_plan_destroy", "lsh_plan_ranks", "lsh_plan_level", "lsh_plan_block",
     "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
-    "lsh_dev_gemm", "lsh_dev_inverse",
+    "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
 ]
 
 
@@ -82,6 +82,9 @@ def lib():
                                    c_void_p, c_long, c_long, c_int, POINTER(c_double), c_void_p, c_long, c_long,
                                    c_void_p, c_long, c_long, c_int, c_void_p]
         L.lsh_dev_inverse.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p]
+        L.lsh_profile_enable.argtypes = [c_int]
+        L.lsh_profile_query.argtypes = [ctypes.c_char_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]
+        L.lsh_profile_names.argtypes = [ctypes.c_char_p, c_int]
         _lib = L
     return _lib
 
@@ -285,3 +288,20 @@ def dev_inverse(A):
     info = torch.zeros(b, dtype=torch.int32, device=A.device)
     _check(lib().lsh_dev_inverse(prec, _ptr(A), c, c, c * c, b, _ptr(info), _stream()))
     return A, info
+
+
+def lsh_profile_enable(on=True):
+    _check(lib().lsh_profile_enable(int(on)))
+
+
+def lsh_profile_query(name):
+    """(launches, total ms, total algorithmic work) of one kernel name."""
+    n, ms, w = c_int(0), c_double(0), c_double(0)
+    _check(lib().lsh_profile_query(name.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
+    return n.value, ms.value, w.value
+
+
+def lsh_profile_names():
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().lsh_profile_names(buf, 4096))
+    return [x for x in buf.value.decode().split(";") if x]
