@@ -46,73 +46,108 @@ struct GemmP {
   int addI;
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 16, GPAD = 16;
+// Tile: 2 x 2 wavefronts, each owning WM x WN blocks of 16 x 16 outputs, so the
+// workgroup tile is (32 WM) x (32 WN); K advances 16 at a time.  LDS holds
+// separate real / imaginary planes laid out [row][k] with stride 17, which
+// keeps both the coalesced global->LDS stores and the MFMA operand reads
+// (16 rows x 4 k per instruction) within one extra bank conflict.  The next
+// K tile is prefetched into registers while the current one is multiplied.
+constexpr int GBK = 16, GLD = GBK + 1;
 
-template <typename R>
+template <typename R, int WM, int WN>
 __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
   using M4 = Mfma<R>;
   using acc_t = typename M4::acc_t;
-  __shared__ R sAr[GBK][GBM + GPAD], sAi[GBK][GBM + GPAD];
-  __shared__ R sBr[GBK][GBN + GPAD], sBi[GBK][GBN + GPAD];
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int EA = BM * GBK / 256, EB = BN * GBK / 256;
+  __shared__ R sAr[BM][GLD], sAi[BM][GLD];
+  __shared__ R sBr[BN][GLD], sBi[BN][GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const long b = blockIdx.z;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const cplx<R>* A = P.A + b * P.sA;
   const cplx<R>* B = P.B + b * P.sB;
-  acc_t cr[2][2], ci[2][2];
+  const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
+  const bool aC = (P.opA == OP_C || P.opA == OP_R), bC = (P.opB == OP_C || P.opB == OP_R);
+  acc_t cr[WM][WN], ci[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { cr[i][j][r] = 0; ci[i][j][r] = 0; }
-
-  for (int k0 = 0; k0 < P.K; k0 += GBK) {
+  cplx<R> ra[EA], rb[EB];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * 256;
       int m, k;
-      const bool aN = (P.opA == OP_N || P.opA == OP_R);
       if (aN) { m = idx / GBK; k = idx % GBK; }
-      else { k = idx / GBM; m = idx % GBM; }
-      cplx<R> v = mk<R>(0, 0);
+      else { k = idx / BM; m = idx % BM; }
       const int gm = m0 + m, gk = k0 + k;
-      if (gm < P.M && gk < P.K) {
-        v = aN ? A[(long)gm * P.lda + gk] : A[(long)gk * P.lda + gm];
-        if (P.opA == OP_C || P.opA == OP_R) v.y = -v.y;
-      }
-      sAr[k][m] = v.x;
-      sAi[k][m] = v.y;
-      int n;
-      const bool bN = (P.opB == OP_N || P.opB == OP_R);
-      if (bN) { k = idx / GBN; n = idx % GBN; }
-      else { n = idx / GBK; k = idx % GBK; }
-      cplx<R> w = mk<R>(0, 0);
-      const int gn = n0 + n, gk2 = k0 + k;
-      if (gn < P.N && gk2 < P.K) {
-        w = bN ? B[(long)gk2 * P.ldb + gn] : B[(long)gn * P.ldb + gk2];
-        if (P.opB == OP_C || P.opB == OP_R) w.y = -w.y;
-      }
-      sBr[k][n] = w.x;
-      sBi[k][n] = w.y;
+      cplx<R> v = mk<R>(0, 0);
+      if (gm < P.M && gk < P.K) v = aN ? A[(long)gm * P.lda + gk] : A[(long)gk * P.lda + gm];
+      if (aC) v.y = -v.y;
+      ra[e] = v;
     }
-    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      int n, k;
+      if (bN) { k = idx / BN; n = idx % BN; }
+      else { n = idx / GBK; k = idx % GBK; }
+      const int gn = n0 + n, gk = k0 + k;
+      cplx<R> v = mk<R>(0, 0);
+      if (gn < P.N && gk < P.K) v = bN ? B[(long)gk * P.ldb + gn] : B[(long)gn * P.ldb + gk];
+      if (bC) v.y = -v.y;
+      rb[e] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      int m, k;
+      if (aN) { m = idx / GBK; k = idx % GBK; }
+      else { k = idx / BM; m = idx % BM; }
+      sAr[m][k] = ra[e].x;
+      sAi[m][k] = ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      int n, k;
+      if (bN) { k = idx / BN; n = idx % BN; }
+      else { n = idx / GBK; k = idx % GBK; }
+      sBr[n][k] = rb[e].x;
+      sBi[n][k] = rb[e].y;
+    }
+  };
+  load(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < P.K; k0 += GBK) {
+    const bool more = k0 + GBK < P.K;
+    if (more) load(k0 + GBK);
 #pragma unroll
     for (int kk = 0; kk < GBK / 4; ++kk) {
       const int k = kk * 4 + (lane >> 4);
-      R ar[2], ai[2], br[2], bi[2];
+      R ar[WM], ai[WM], br[WN], bi[WN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = sAr[k][wm * 32 + i * 16 + (lane & 15)];
-        ai[i] = sAi[k][wm * 32 + i * 16 + (lane & 15)];
-        br[i] = sBr[k][wn * 32 + i * 16 + (lane & 15)];
-        bi[i] = sBi[k][wn * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < WM; ++i) {
+        ar[i] = sAr[wm * 16 * WM + i * 16 + (lane & 15)][k];
+        ai[i] = sAi[wm * 16 * WM + i * 16 + (lane & 15)][k];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < WN; ++j) {
+        br[j] = sBr[wn * 16 * WN + j * 16 + (lane & 15)][k];
+        bi[j] = sBi[wn * 16 * WN + j * 16 + (lane & 15)][k];
+      }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
           cr[i][j] = M4::op(ar[i], br[j], cr[i][j]);
           cr[i][j] = M4::op(-ai[i], bi[j], cr[i][j]);
           ci[i][j] = M4::op(ar[i], bi[j], ci[i][j]);
@@ -120,18 +155,22 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
         }
     }
     __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
   }
   cplx<R>* C = P.C + b * P.sC;
   const cplx<R>* D = P.D ? P.D + b * P.sD : nullptr;
   const bool useD = D && (P.beta.x != R(0) || P.beta.y != R(0));
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + M4::row(lane, r);
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        const int m = m0 + wm * 16 * WM + i * 16 + M4::row(lane, r);
+        const int n = n0 + wn * 16 * WN + j * 16 + (lane & 15);
         if (m < P.M && n < P.N) {
           cplx<R> v = P.alpha * mk<R>(cr[i][j][r], ci[i][j][r]);
           if (useD) v = v + P.beta * D[(long)m * P.ldd + n];
@@ -139,6 +178,21 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
           C[(long)m * P.ldc + n] = v;
         }
       }
+}
+
+template <typename R, int WM, int WN>
+static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, const cplx<R>* B, const cplx<R>* D,
+                        cplx<R>* C, long sA, long sB, long sD, long sC, int batch) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    GemmP<R> Q = P;
+    Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
+    if (D) Q.D = D + b0 * sD;
+    dim3 grid(ceil_div(P.N, BN), ceil_div(P.M, BM), nb);
+    hipLaunchKernelGGL((k_cgemm<R, WM, WN>), grid, dim3(256), 0, s, Q);
+    LSH_LAUNCH_CHECK();
+  }
 }
 
 template <typename R>
@@ -155,14 +209,13 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
   P.B = B; P.ldb = ldb; P.sB = sB; P.opB = opB;
   P.D = D; P.ldd = ldd; P.sD = sD;
   P.C = C; P.ldc = ldc; P.sC = sC; P.addI = add_identity ? 1 : 0;
-  for (int b0 = 0; b0 < batch; b0 += 65535) {
-    int nb = batch - b0 < 65535 ? batch - b0 : 65535;
-    GemmP<R> Q = P;
-    Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
-    if (D) Q.D = D + b0 * sD;
-    dim3 grid(ceil_div(N, GBN), ceil_div(M, GBM), nb);
-    hipLaunchKernelGGL(k_cgemm<R>, grid, dim3(256), 0, s, Q);
-    LSH_LAUNCH_CHECK();
+  // large tiles when they still leave a few waves of workgroups in flight
+  const double big_tiles = (double)ceil_div(M, 128) * ceil_div(N, sizeof(R) == 4 ? 128 : 64) * batch;
+  if (M >= 128 && N >= 64 && K >= 32 && big_tiles >= 128) {
+    if (sizeof(R) == 4) launch_gemm<R, 4, 4>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    else launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+  } else {
+    launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
 }
 
@@ -217,6 +270,58 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
   dim3 grid(batch, ceil_div(M, GV_ROWS));
   hipLaunchKernelGGL(k_cgemv<R>, grid, dim3(256), N * sizeof(cplx<R>), s, M, N, alpha, A, lda, sA,
                      amod > 0 ? amod : 1, x, sx, beta, z, sz, y, sy);
+  LSH_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------ shared-matrix multi-GEMV
+// One wavefront per row of Mat (lanes stride the row), up to MG_VEC vectors
+// accumulated in registers; X is read through the caches by every wave.
+constexpr int MG_VEC = 8;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cmgemv(int Rr, int C, cplx<R> alpha, const cplx<R>* __restrict__ Mat,
+                                                long ldm, const cplx<R>* __restrict__ X, long ldx, cplx<R> beta,
+                                                const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + wave;
+  if (i >= Rr) return;
+  const cplx<R>* row = Mat + (long)i * ldm;
+  for (int b0 = 0; b0 < nvec; b0 += MG_VEC) {
+    const int nb = nvec - b0 < MG_VEC ? nvec - b0 : MG_VEC;
+    cplx<R> acc[MG_VEC];
+#pragma unroll
+    for (int v = 0; v < MG_VEC; ++v) acc[v] = mk<R>(0, 0);
+    for (int j = lane; j < C; j += 64) {
+      const cplx<R> a = row[j];
+#pragma unroll
+      for (int v = 0; v < MG_VEC; ++v)
+        if (v < nb) fma_acc(acc[v], a, X[(long)(b0 + v) * ldx + j]);
+    }
+#pragma unroll
+    for (int v = 0; v < MG_VEC; ++v) {
+      if (v >= nb) break;
+      cplx<R> a = acc[v];
+      for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_xor(a.x, off);
+        a.y += __shfl_xor(a.y, off);
+      }
+      if (lane == 0) {
+        cplx<R> r = alpha * a;
+        if (Z && (beta.x != R(0) || beta.y != R(0))) r = r + beta * Z[(long)(b0 + v) * ldz + i];
+        Y[(long)(b0 + v) * ldy + i] = r;
+      }
+    }
+  }
+}
+
+template <typename R>
+void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
+            cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+  if (Rr <= 0 || nvec <= 0) return;
+  ProfScope ps(sizeof(R) == 4 ? "cmgemv_f32" : "cmgemv_f64", s,
+               (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * (C + (Z ? 2.0 : 1.0) * Rr)));
+  hipLaunchKernelGGL(k_cmgemv<R>, dim3(ceil_div(Rr, 4)), dim3(256), 0, s, Rr, C, alpha, Mat, ldm, X, ldx, beta, Z,
+                     ldz, Y, ldy, nvec);
   LSH_LAUNCH_CHECK();
 }
 
@@ -522,6 +627,21 @@ void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, voi
   LSH_LAUNCH_CHECK();
 }
 
+template <typename R>
+__global__ void k_ctranspose(const cplx<R>* in, int rows, int cols, cplx<R>* out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e % cols);
+  out[(long)c * rows + r] = in[e];
+}
+
+template <typename R>
+void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(k_ctranspose<R>, dim3(ceil_div((long)rows * cols, 256)), dim3(256), 0, s, in, rows, cols, out);
+  LSH_LAUNCH_CHECK();
+}
+
 template <typename R1, typename R2>
 __global__ void k_ccast(const cplx<R1>* src, cplx<R2>* dst, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -542,6 +662,9 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
                          long, long, Op, cplx<R>, const cplx<R>*, long, long, cplx<R>*, long, long, int, bool); \
   template void cgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, long, int, const cplx<R>*, long, \
                          cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                               \
+  template void cmgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, const cplx<R>*, long, cplx<R>, \
+                          const cplx<R>*, long, cplx<R>*, long, int);                                        \
+  template void ctranspose<R>(hipStream_t, const cplx<R>*, int, int, cplx<R>*);                             \
   template size_t inverse_ws_bytes<R>(int, int);                                                           \
   template void inverse<R>(hipStream_t, cplx<R>*, int, long, long, int, void*, int*);
 LSH_INST(float)

@@ -30,6 +30,14 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
            const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz,
            cplx<R>* y, long sy, int batch);
 
+// Shared-matrix multi-vector product (rows of Mat streamed once):
+//   Y[b][i] = alpha * sum_j Mat[i][j] X[b][j] + beta * Z[b][i],  b < nvec,
+// Mat R x C row-major (ld ldm); X, Y, Z rows at strides ldx, ldy, ldz.
+// Z may be null when beta == 0; Y must not overlap X.
+template <typename R>
+void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
+            cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec);
+
 // In-place inverse of each c x c matrix by Gauss-Jordan elimination with
 // partial (row) pivoting.  ws must hold inverse_ws_bytes(c, batch) bytes.
 // info[b] = 0, or j+1 if a zero pivot was met at step j (matrix singular).
@@ -38,6 +46,10 @@ size_t inverse_ws_bytes(int c, int batch);
 template <typename R>
 void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch,
              void* ws, int* info);
+
+// out (cols x rows) = in^T (rows x cols), row-major
+template <typename R>
+void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out);
 
 // dst (R2) = src (R1), elementwise, n complex entries
 template <typename R1, typename R2>

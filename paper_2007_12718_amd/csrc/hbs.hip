@@ -1,5 +1,7 @@
 // HBS compression (paper Sec. 3.2), leaf factor (Alg. 1, leaf loop) and the
 // leaf steps of the apply (Alg. 2) on gfx950.
+#include <hip/hip_cooperative_groups.h>
+
 #include <cmath>
 
 #include "hbs.hpp"
@@ -234,24 +236,154 @@ __global__ __launch_bounds__(QR_NT) void k_pchol_panel(const z64* __restrict__ M
   if (tid == 0) state[0] = j0 + nb;
 }
 
+// L11[a][b] = L(piv[a], b) for a, b < k (lower triangular in pivot order)
+// Cooperative panel: G workgroups own contiguous row slices (<= PC_RPW rows,
+// their panel entries kept in LDS); one grid-wide sync per pivot.  Candidate
+// (d, index) slots are double buffered by step parity.
+constexpr int PC_NT = 256, PC_RPW = 112, PC_NB = 32;
+
+__global__ __launch_bounds__(PC_NT) void k_pchol_coop(const z64* __restrict__ M, int m, double* d, int* chosen,
+                                                      z64* Lt, int* piv, int j0, int nb, double thr2, int* state,
+                                                      double* cval, int* cidx) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  __shared__ z64 Lp[PC_RPW][PC_NB];
+  __shared__ double ds[PC_RPW];
+  __shared__ int cs[PC_RPW];
+  __shared__ z64 lpiv[PC_NB];
+  __shared__ double wv[PC_NT / 64];
+  __shared__ int wi[PC_NT / 64];
+  __shared__ int s_p;
+  __shared__ double s_d;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (state[1]) return;  // uniform: written only by earlier launches
+  const int rpw = (m + G - 1) / G;
+  const int r0 = g * rpw, r1 = (r0 + rpw < m) ? r0 + rpw : m;
+  for (int i = r0 + tid; i < r1; i += PC_NT) {
+    ds[i - r0] = d[i];
+    cs[i - r0] = chosen[i];
+  }
+  __syncthreads();
+  auto local_argmax = [&](int slot) {
+    double best = -1;
+    int bi = m;
+    for (int i = r0 + tid; i < r1; i += PC_NT)
+      if (!cs[i - r0]) {
+        const double a = ds[i - r0];
+        if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+      }
+    wave_argmax_d(best, bi);
+    if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = wv[0];
+      int ii = wi[0];
+      for (int w = 1; w < PC_NT / 64; ++w)
+        if (wv[w] > bb || (wv[w] == bb && wi[w] < ii)) { bb = wv[w]; ii = wi[w]; }
+      cval[slot * G + g] = bb;
+      cidx[slot * G + g] = ii;
+    }
+  };
+  local_argmax(0);
+  grid.sync();
+  int jj = 0;
+  for (; jj < nb; ++jj) {
+    const int j = j0 + jj;
+    if (j >= m) break;
+    if (tid == 0) {
+      const int slot = jj & 1;
+      double bb = cval[slot * G];
+      int ii = cidx[slot * G];
+      for (int w = 1; w < G; ++w) {
+        const double v = cval[slot * G + w];
+        const int x = cidx[slot * G + w];
+        if (v > bb || (v == bb && x < ii)) { bb = v; ii = x; }
+      }
+      s_p = ii;
+      s_d = bb;
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double dp = s_d;
+    if (!(dp > thr2)) {  // uniform: every workgroup read the same slots
+      if (g == 0 && tid == 0) { state[0] = j; state[1] = 1; }
+      break;
+    }
+    for (int t = tid; t < jj; t += PC_NT) lpiv[t] = Lt[(long)(j0 + t) * m + p];
+    __syncthreads();
+    const double sq = sqrt(dp), rs = 1.0 / sq;
+    for (int i = r0 + tid; i < r1; i += PC_NT) {
+      z64 l;
+      if (i == p) {
+        l = mk(sq, 0.0);
+        cs[i - r0] = 1;
+        ds[i - r0] = 0;
+        piv[j] = p;
+      } else if (cs[i - r0]) {
+        l = mk(0.0, 0.0);
+      } else {
+        l = conjg(M[(long)p * m + i]);
+        for (int t = 0; t < jj; ++t) l = l - Lp[i - r0][t] * conjg(lpiv[t]);
+        l = rs * l;
+        ds[i - r0] -= abs2(l);
+      }
+      Lp[i - r0][jj] = l;
+      Lt[(long)j * m + i] = l;
+    }
+    __syncthreads();
+    local_argmax((jj + 1) & 1);
+    grid.sync();
+  }
+  for (int i = r0 + tid; i < r1; i += PC_NT) {
+    d[i] = ds[i - r0];
+    chosen[i] = cs[i - r0];
+  }
+  if (jj == nb && g == 0 && tid == 0) state[0] = j0 + nb;
+  if (j0 + jj >= m && g == 0 && tid == 0) { state[0] = m; state[1] = 1; }
+}
+
 __global__ void k_gather_L11(const z64* Lt, int m, const int* piv, int k, z64* L11) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * k) return;
-  const int a = e / k, b = e % k;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)k * k) return;
+  const int a = (int)(e / k), b = (int)(e % k);
   L11[e] = Lt[(long)b * m + piv[a]];
 }
 
-__global__ void k_unit_rows(z64* U, int k, const int* piv) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * k) return;
-  const int a = e / k, b = e % k;
-  U[(long)piv[a] * k + b] = mk(a == b ? 1.0 : 0.0, 0.0);
+// Lr[r][t] = L(rest[r], t)
+__global__ void k_gather_rows(const z64* Lt, int m, const int* rest, int nr, int k, z64* Lr) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)nr * k) return;
+  const int r = (int)(e / k), t = (int)(e % k);
+  Lr[e] = Lt[(long)t * m + rest[r]];
+}
+
+// D[q] = diagonal block q of L11 (nb x nb), identity-padded past k
+__global__ void k_diag_blocks(const z64* L11, int k, int nb, z64* D, int nblk) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)nblk * nb * nb) return;
+  const int q = (int)(e / ((long)nb * nb)), rr = (int)((e / nb) % nb), cc = (int)(e % nb);
+  const int gi = q * nb + rr, gj = q * nb + cc;
+  z64 v = mk(0.0, 0.0);
+  if (gi < k && gj < k) v = L11[(long)gi * k + gj];
+  else if (rr == cc) v = mk(1.0, 0.0);
+  D[e] = v;
+}
+
+// U[piv[a]] = e_a ; U[rest[r]] = X[r]
+__global__ void k_scatter_U(z64* U, int k, const int* piv, const int* rest, int nr, const z64* X) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)(k + nr) * k;
+  if (e >= tot) return;
+  const int row = (int)(e / k), b = (int)(e % k);
+  if (row < k) U[(long)piv[row] * k + b] = mk(row == b ? 1.0 : 0.0, 0.0);
+  else U[(long)rest[row - k] * k + b] = X[(long)(row - k) * k + b];
 }
 
 size_t rowid_gram_ws(int m) {
   const size_t mm = (size_t)m * m;
-  return sizeof(z64) * mm * 3 + sizeof(double) * m + sizeof(int) * (2 * m + 16) +
-         inverse_ws_bytes<double>(m, 1) + 4096;
+  return sizeof(z64) * mm * 4 + sizeof(double) * m + sizeof(int) * (3 * m + 16) +
+         inverse_ws_bytes<double>(64, m / 64 + 1) + sizeof(z64) * (size_t)(m / 64 + 1) * 64 * 64 +
+         (sizeof(double) + sizeof(int)) * 512 + 16384;
 }
 
 int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws) {
@@ -260,10 +392,14 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
   z64* M = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
   z64* Lt = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
   z64* L11 = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  z64* Lr = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
   double* d = static_cast<double*>(take(sizeof(double) * m));
   int* chosen = static_cast<int*>(take(sizeof(int) * m));
+  int* rest = static_cast<int*>(take(sizeof(int) * m));
   int* state = static_cast<int*>(take(sizeof(int) * 16));
-  void* invws = take(inverse_ws_bytes<double>(m, 1));
+  const int DB = 64;
+  z64* Dinv = static_cast<z64*>(take(sizeof(z64) * (size_t)(m / DB + 1) * DB * DB));
+  void* invws = take(inverse_ws_bytes<double>(DB, m / DB + 1));
   cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1);
   hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, state);
   LSH_LAUNCH_CHECK();
@@ -274,12 +410,28 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
   double fro2 = 0;
   for (double v : dh) fro2 += v;
   const double thr2 = tol * tol * fro2;
-  const int nb = 32;
+  const int nb = PC_NB;
   int rank = 0;
+  // cooperative launch needs every workgroup resident at once
+  bool coop_ok = ceil_div(m, PC_RPW) <= 240;
+  double* cval = static_cast<double*>(take(sizeof(double) * 2 * 256));
+  int* cidx = static_cast<int*>(take(sizeof(int) * 2 * 256));
   for (int j0 = 0; j0 < m; j0 += nb) {
     {
       ProfScope ps("pchol_panel", s, 16.0 * (double)m * nb);
-      hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), 0, s, M, m, d, chosen, Lt, J, j0, nb, thr2, state);
+      bool done = false;
+      if (coop_ok) {
+        int G = ceil_div(m, PC_RPW);
+        const z64* Mc = M;
+        int mm = m, jj0 = j0, nbb = nb;
+        double t2 = thr2;
+        void* args[] = {(void*)&Mc, &mm, &d, &chosen, &Lt, &J, &jj0, &nbb, &t2, &state, &cval, &cidx};
+        hipError_t e = hipLaunchCooperativeKernel((const void*)k_pchol_coop, dim3(G), dim3(PC_NT), args, 0, s);
+        if (e == hipSuccess) done = true;
+        else { (void)hipGetLastError(); coop_ok = false; }
+      }
+      if (!done)
+        hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), 0, s, M, m, d, chosen, Lt, J, j0, nb, thr2, state);
     }
     LSH_LAUNCH_CHECK();
     int st[2];
@@ -291,15 +443,44 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
     cgemm<double>(s, m, m, nb, mk(-1.0, 0.0), Lt + (long)j0 * m, m, 0, OP_T, Lt + (long)j0 * m, m, 0, OP_R,
                   mk(1.0, 0.0), M, m, 0, M, m, 0, 1);
   }
-  if (rank < 1) rank = 1;
-  const int k = rank;
+  const int k = rank < 1 ? 1 : rank;
+  // U(piv, :) = I and U(rest, :) = L(rest, 0:k) L11^{-1}: X L11 = Lr solved by
+  // column blocks from the right (L11 lower triangular).
+  std::vector<int> ph(k), rh;
+  LSH_HIP(hipMemcpyAsync(ph.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<char> used(m, 0);
+    for (int v : ph) used[v] = 1;
+    for (int i = 0; i < m; ++i)
+      if (!used[i]) rh.push_back(i);
+  }
+  const int nr = (int)rh.size();
+  if (nr) LSH_HIP(hipMemcpyAsync(rest, rh.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_gather_L11, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, Lt, m, J, k, L11);
   LSH_LAUNCH_CHECK();
-  inverse<double>(s, L11, k, k, 0, 1, invws, state + 8);
-  // U = L_k L11^{-1}  (L_k = first k columns of L = Lt[0:k]^T)
-  cgemm<double>(s, m, k, k, mk(1.0, 0.0), Lt, m, 0, OP_T, L11, k, 0, OP_N, mk(0.0, 0.0), nullptr, 0, 0, U, k, 0,
-                1);
-  hipLaunchKernelGGL(k_unit_rows, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J);
+  if (nr) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div((long)nr * k, 256)), dim3(256), 0, s, Lt, m, rest, nr, k, Lr);
+    LSH_LAUNCH_CHECK();
+    const int nblk = ceil_div(k, DB);
+    hipLaunchKernelGGL(k_diag_blocks, dim3(ceil_div((long)nblk * DB * DB, 256)), dim3(256), 0, s, L11, k, DB, Dinv,
+                       nblk);
+    LSH_LAUNCH_CHECK();
+    inverse<double>(s, Dinv, DB, DB, (long)DB * DB, nblk, invws, nullptr);
+    z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
+    for (int q = nblk - 1; q >= 0; --q) {
+      const int b0 = q * DB, b1 = (b0 + DB < k) ? b0 + DB : k, w = b1 - b0;
+      if (b1 < k)  // Lr(:, B) -= X(:, b1:k) L11(b1:k, B)
+        cgemm<double>(s, nr, w, k - b1, mk(-1.0, 0.0), X + b1, k, 0, OP_N, L11 + (long)b1 * k + b0, k, 0, OP_N,
+                      mk(1.0, 0.0), Lr + b0, k, 0, Lr + b0, k, 0, 1);
+      // X(:, B) = Lr(:, B) L11(B, B)^{-1}
+      cgemm<double>(s, nr, w, w, mk(1.0, 0.0), Lr + b0, k, 0, OP_N, Dinv + (long)q * DB * DB, DB, 0, OP_N,
+                    mk(0.0, 0.0), nullptr, 0, 0, X + b0, k, 0, 1);
+    }
+    hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)(k + nr) * k, 256)), dim3(256), 0, s, U, k, J, rest, nr, X);
+  } else {
+    hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J, rest, 0, L11);
+  }
   LSH_LAUNCH_CHECK();
   return k;
 }

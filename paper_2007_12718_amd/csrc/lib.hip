@@ -42,7 +42,9 @@ struct Level {
   std::vector<I2> cand;
   std::vector<int> J;
   DevBuf U64, U32;       // m x k
+  DevBuf Ut64, Ut32;     // k x m (transpose, for row-streamed products)
   DevBuf Gab64, Gab32;   // sibling block of this parent level (c x c, c = k of level+1)
+  DevBuf Gabt64, Gabt32; // its transpose
   int c = 0;
 };
 
@@ -66,7 +68,20 @@ struct lsh_plan_s {
   const cplx<R>* Gab(int l) const;
   template <typename R>
   const cplx<R>* Gleaf() const;
+  template <typename R>
+  const cplx<R>* Ut(int l) const;
+  template <typename R>
+  const cplx<R>* Gabt(int l) const;
 };
+
+template <>
+const cplx<double>* lsh_plan_s::Ut<double>(int l) const { return lev[l].Ut64.as<z64>(); }
+template <>
+const cplx<float>* lsh_plan_s::Ut<float>(int l) const { return lev[l].Ut32.as<c32>(); }
+template <>
+const cplx<double>* lsh_plan_s::Gabt<double>(int l) const { return lev[l].Gabt64.as<z64>(); }
+template <>
+const cplx<float>* lsh_plan_s::Gabt<float>(int l) const { return lev[l].Gabt32.as<c32>(); }
 
 template <>
 const cplx<double>* lsh_plan_s::U<double>(int l) const { return lev[l].U64.as<z64>(); }
@@ -147,8 +162,9 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
   gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
   DevBuf J(sizeof(int) * m), Ufull(sizeof(z64) * (size_t)m * m);
   int k = 0;
-  const bool small = (double)m * np <= 262144.0;
-  if (small || P.d.tol < 1e-7) {
+  // Gram + pivoted Cholesky squares the conditioning: FP64 resolves the
+  // stopping rule only while tol stays above ~1e-7; below that, CPQR.
+  if (P.d.tol < 1e-7) {
     // ||A||_F for the stopping rule |R_kk| <= tol ||A||_F (computed on device)
     DevBuf ws(rowid_cpqr_ws(m)), kd(sizeof(int)), fro(sizeof(z64)), part(multidot_partial_bytes(1));
     multidot(s, A.as<z64>(), 0, 1, A.as<z64>(), (long)m * np, fro.as<z64>(), part.as<z64>());
@@ -266,6 +282,26 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
     }
     P.Gleaf32.alloc(sizeof(c32) * (size_t)P.mL * P.mL);
     ccast<double, float>(s, P.Gleaf64.as<z64>(), P.Gleaf32.as<c32>(), (long)P.mL * P.mL);
+  }
+  // transposed copies for the row-streamed shared products of the apply
+  for (int l = 0; l <= P.L; ++l) {
+    Level& lv = P.lev[l];
+    if (l >= 1) {
+      lv.Ut64.alloc(sizeof(z64) * (size_t)lv.m * lv.k);
+      ctranspose<double>(s, lv.U64.as<z64>(), lv.m, lv.k, lv.Ut64.as<z64>());
+      if (d.hbs_prec == LSH_FP32) {
+        lv.Ut32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
+        ctranspose<float>(s, lv.U32.as<c32>(), lv.m, lv.k, lv.Ut32.as<c32>());
+      }
+    }
+    if (l < P.L) {
+      lv.Gabt64.alloc(sizeof(z64) * (size_t)lv.c * lv.c);
+      ctranspose<double>(s, lv.Gab64.as<z64>(), lv.c, lv.c, lv.Gabt64.as<z64>());
+      if (d.hbs_prec == LSH_FP32) {
+        lv.Gabt32.alloc(sizeof(c32) * (size_t)lv.c * lv.c);
+        ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
+      }
+    }
   }
   // operator spectrum (order op_order)
   P.op.init(s, d.n, d.h, d.kappa, P.table.as<z64>(), P.D, correction_stencil(d.op_order, d.kappa * d.h));
@@ -409,6 +445,10 @@ void apply_X(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, const cplx<
            B);
 }
 
+// below this many box vectors the shared products stream the matrix rows
+// (multi-vector GEMV); above it they are MFMA GEMMs
+constexpr int SKINNY = 32;
+
 template <typename R>
 void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* f, z64* q, int nrhs,
              hipStream_t s) {
@@ -426,26 +466,32 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
   for (int l = L - 1; l >= 1; --l) {
     const int c = P.lev[l].c, k = P.lev[l].k, B = nrhs << l;
     apply_X<R>(P, F, l, nrhs, F.rt[l + 1].template as<cplx<R>>(), t1, s);
-    cgemm<R>(s, B, k, 2 * c, one, t1, 2 * c, 0, OP_N, P.U<R>(l), k, 0, OP_N, zero, nullptr, 0, 0,
-             F.rt[l].template as<cplx<R>>(), k, 0, 1);
+    // rt_l = U_l^T xv
+    if (B <= SKINNY)
+      cmgemv<R>(s, k, 2 * c, one, P.Ut<R>(l), 2 * c, t1, 2 * c, zero, nullptr, 0, F.rt[l].template as<cplx<R>>(), k,
+                B);
+    else
+      cgemm<R>(s, B, k, 2 * c, one, t1, 2 * c, 0, OP_N, P.U<R>(l), k, 0, OP_N, zero, nullptr, 0, 0,
+               F.rt[l].template as<cplx<R>>(), k, 0, 1);
   }
   // root: w_children = Ghat X_root [rt_a; rt_b]
   {
     const int c = P.lev[0].c;
     apply_X<R>(P, F, 0, nrhs, F.rt[1].template as<cplx<R>>(), t1, s);
     cplx<R>* w1 = F.wt[1].template as<cplx<R>>();
-    cgemm<R>(s, nrhs, c, c, one, t1 + c, 2 * c, 0, OP_N, P.Gab<R>(0), c, 0, OP_T, zero, nullptr, 0, 0, w1, 2 * c,
-             0, 1);
-    cgemm<R>(s, nrhs, c, c, one, t1, 2 * c, 0, OP_N, P.Gab<R>(0), c, 0, OP_N, zero, nullptr, 0, 0, w1 + c, 2 * c,
-             0, 1);
+    cmgemv<R>(s, c, c, one, P.Gab<R>(0), c, t1 + c, 2 * c, zero, nullptr, 0, w1, 2 * c, nrhs);
+    cmgemv<R>(s, c, c, one, P.Gabt<R>(0), c, t1, 2 * c, zero, nullptr, 0, w1 + c, 2 * c, nrhs);
   }
   // downward pass
   for (int l = 1; l <= L - 1; ++l) {
     const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
     const long cc = (long)c * c;
     // u = U_l wt_l  ([B][2c])
-    cgemm<R>(s, B, 2 * c, k, one, F.wt[l].template as<cplx<R>>(), k, 0, OP_N, P.U<R>(l), k, 0, OP_T, zero,
-             nullptr, 0, 0, t1, 2 * c, 0, 1);
+    if (B <= SKINNY)
+      cmgemv<R>(s, 2 * c, k, one, P.U<R>(l), k, F.wt[l].template as<cplx<R>>(), k, zero, nullptr, 0, t1, 2 * c, B);
+    else
+      cgemm<R>(s, B, 2 * c, k, one, F.wt[l].template as<cplx<R>>(), k, 0, OP_N, P.U<R>(l), k, 0, OP_T, zero,
+               nullptr, 0, 0, t1, 2 * c, 0, 1);
     // d = rt_children - diag(S_a, S_b) u  ([2B][c])
     cgemv<R>(s, c, c, mone, F.S[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t1, c, one,
              F.rt[l + 1].template as<cplx<R>>(), c, t2, c, 2 * B);
@@ -453,9 +499,14 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     apply_X<R>(P, F, l, nrhs, t2, t3, s);
     // wt_children = Ghat qt + u
     cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
-    cgemm<R>(s, B, c, c, one, t3 + c, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_T, one, t1, 2 * c, 0, wc, 2 * c, 0, 1);
-    cgemm<R>(s, B, c, c, one, t3, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_N, one, t1 + c, 2 * c, 0, wc + c, 2 * c, 0,
-             1);
+    if (B <= SKINNY) {
+      cmgemv<R>(s, c, c, one, P.Gab<R>(l), c, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B);
+      cmgemv<R>(s, c, c, one, P.Gabt<R>(l), c, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c, B);
+    } else {
+      cgemm<R>(s, B, c, c, one, t3 + c, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_T, one, t1, 2 * c, 0, wc, 2 * c, 0, 1);
+      cgemm<R>(s, B, c, c, one, t3, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_N, one, t1 + c, 2 * c, 0, wc + c, 2 * c, 0,
+               1);
+    }
   }
   leaf_down<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, F.wt[L].template as<cplx<R>>(), r, q,
                b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);

@@ -72,15 +72,16 @@ def test_operator_matches_dense(n, order, use_b):
         assert np.abs(y[r].reshape(-1) - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-def test_level_ids_valid_and_ranks_match_oracle(small):
+@pytest.mark.parametrize("n,tol,width", [(32, 1e-10, 3), (64, 1e-4, 2), (128, 1e-5, 2)])
+def test_level_ids_valid_and_ranks_match_oracle(n, tol, width):
     """The pivots are not unique (the boxes and proxy rings are symmetric, so
     column norms tie exactly); what is unique is the rank.  Each level's ID
-    must hold U[J] = I and approximate the proxy matrix to the tolerance."""
+    must hold U[J] = I and approximate the proxy matrix to the tolerance.
+    tol 1e-10 runs the CPQR path, the others the Gram / pivoted-Cholesky path."""
     from paper_2007_12718_amd import lsh
-    w = small[0]
-    tol = 1e-10
-    P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=tol, proxy_width=3, prec="fp64")
-    C = hbs.Compression(w.n, w.kappa, 8, tol, 3)
+    w = synth.small(n)
+    P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=tol, proxy_width=width, prec="fp64")
+    C = hbs.Compression(w.n, w.kappa, 8, tol, width)
     L, ranks = P.ranks()
     assert L == C.tree.L
     assert np.array_equal(P.level(L)[1], C.cand[L])
@@ -90,7 +91,7 @@ def test_level_ids_valid_and_ranks_match_oracle(small):
         assert abs(len(J) - C.ranks()[l]) <= 2, (l, len(J), C.ranks()[l])
         assert np.array_equal(U[J], np.eye(len(J)))
         ox, oy, sx, sy = C.tree.box(l, 0)
-        A = C.gblock(cand, hbs.proxy_ring(sx, sy, 3))
+        A = C.gblock(cand, hbs.proxy_ring(sx, sy, width))
         assert np.linalg.norm(A - U @ A[J]) <= 10 * tol * np.linalg.norm(A), l
 
 
