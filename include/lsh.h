@@ -137,8 +137,12 @@ int lsh_apply_operator(lsh_plan_t plan, const double* b, const void* x, void* y,
 int lsh_solve(lsh_factor_t factor, const void* u_inc, int nrhs, void* sigma, void* u, const lsh_solve_opts* opts,
               lsh_info* info, void* stream);
 
-/* lambda = A^{-H} g (the adjoint solve of the misfit gradient), via
- * A^T = I + K B: A^T y = r  <=>  y = r - K A^{-1} (B r), one forward solve. */
+/* lambda = A^{-H} g (the adjoint solve of a misfit gradient; not in the
+ * paper, derived from eq. (linsys)).  Since K is complex symmetric,
+ * A^H lambda = g  <=>  A^T conj(lambda) = conj(g) with A^T = I + K B; this is
+ * solved by the same flexible GMRES on the transposed FFT operator,
+ * right-preconditioned by M^T (Algorithm 2 transposed).  Synchronises once
+ * per iteration. */
 int lsh_solve_adjoint(lsh_factor_t factor, const void* g, int nrhs, void* lambda, const lsh_solve_opts* opts,
                       lsh_info* info, void* stream);
 
@@ -147,6 +151,21 @@ int lsh_solve_adjoint(lsh_factor_t factor, const void* g, int nrhs, void* lambda
  * u_pts: device double2[nrhs*npts]. */
 int lsh_eval_points(lsh_plan_t plan, const void* sigma, const double* xy, int npts, void* u_pts, int nrhs,
                     void* stream);
+
+/* out[m][j] = h^2 sum_r conj((i/4) H0(kappa |x_r - x_j|)) g[m][r]: the
+ * adjoint of lsh_eval_points.  g: device double2[nrhs*npts]; out: device
+ * double2[nrhs*n*n]. */
+int lsh_eval_points_adjoint(lsh_plan_t plan, const void* g_pts, const double* xy, int npts, void* out, int nrhs,
+                            void* stream);
+
+/* grad[k] = -kappa^2 Re sum_m conj(lambda[m][k]) (u_inc[m][k] + u[m][k]):
+ * the derivative of a real misfit L with respect to b (differentiating
+ * eq. (linsys): d sigma = -kappa^2 A^{-1} (db * u_tot)), given
+ * lambda = A^{-H} g with g the conjugate-Wirtinger gradient 2 dL/d conj(sigma),
+ * the incident fields u_inc and the scattered fields u = K sigma (device
+ * double2[nrhs*n*n]); grad: device double[n*n]. */
+int lsh_grad_b(lsh_plan_t plan, const void* lambda, const void* u_inc, const void* u, int nrhs, double* grad,
+               void* stream);
 
 /* host: dimensionless corrections tau_d of the given order at kappa*h (the
  * matrix entry is h^2 (G + tau_d)); writes count entries (<= 25) of

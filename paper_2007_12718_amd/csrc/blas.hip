@@ -628,17 +628,20 @@ void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, voi
 }
 
 template <typename R>
-__global__ void k_ctranspose(const cplx<R>* in, int rows, int cols, cplx<R>* out) {
+__global__ void k_ctranspose(const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= (long)rows * cols) return;
-  const int r = (int)(e / cols), c = (int)(e % cols);
-  out[(long)c * rows + r] = in[e];
+  const long per = (long)rows * cols;
+  if (e >= per * batch) return;
+  const long bb = e / per, q = e % per;
+  const int r = (int)(q / cols), c = (int)(q % cols);
+  out[bb * per + (long)c * rows + r] = in[e];
 }
 
 template <typename R>
-void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out) {
-  if (rows <= 0 || cols <= 0) return;
-  hipLaunchKernelGGL(k_ctranspose<R>, dim3(ceil_div((long)rows * cols, 256)), dim3(256), 0, s, in, rows, cols, out);
+void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch) {
+  if (rows <= 0 || cols <= 0 || batch <= 0) return;
+  hipLaunchKernelGGL(k_ctranspose<R>, dim3(ceil_div((long)rows * cols * batch, 256)), dim3(256), 0, s, in, rows,
+                     cols, out, batch);
   LSH_LAUNCH_CHECK();
 }
 
@@ -664,7 +667,7 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
                          cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                               \
   template void cmgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, const cplx<R>*, long, cplx<R>, \
                           const cplx<R>*, long, cplx<R>*, long, int);                                        \
-  template void ctranspose<R>(hipStream_t, const cplx<R>*, int, int, cplx<R>*);                             \
+  template void ctranspose<R>(hipStream_t, const cplx<R>*, int, int, cplx<R>*, long);                       \
   template size_t inverse_ws_bytes<R>(int, int);                                                           \
   template void inverse<R>(hipStream_t, cplx<R>*, int, long, long, int, void*, int*);
 LSH_INST(float)

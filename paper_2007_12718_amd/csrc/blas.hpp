@@ -47,9 +47,9 @@ template <typename R>
 void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch,
              void* ws, int* info);
 
-// out (cols x rows) = in^T (rows x cols), row-major
+// out_b (cols x rows) = in_b^T (rows x cols), row-major, batch of contiguous matrices
 template <typename R>
-void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out);
+void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch = 1);
 
 // dst (R2) = src (R1), elementwise, n complex entries
 template <typename R1, typename R2>

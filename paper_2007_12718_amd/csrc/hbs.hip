@@ -544,7 +544,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ UL,
                                                  int mL, int k, const z64* __restrict__ f, cplx<R>* r, cplx<R>* rt,
                                                  const I2* __restrict__ org, const I2* __restrict__ pts, int n,
-                                                 int nleaf) {
+                                                 int nleaf, const double* __restrict__ b, double sb) {
   __shared__ cplx<R> fs[LEAF_MAX];
   __shared__ cplx<R> rs[LEAF_MAX];
   const long t = blockIdx.x, rhs = blockIdx.y;
@@ -568,8 +568,18 @@ __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, 
     if (lane == 0) rs[i] = acc;
   }
   __syncthreads();
-  cplx<R>* rr = r + (rhs * nleaf + t) * (long)mL;
-  for (int i = threadIdx.x; i < mL; i += blockDim.x) rr[i] = rs[i];
+  if (r) {
+    cplx<R>* rr = r + (rhs * nleaf + t) * (long)mL;
+    for (int i = threadIdx.x; i < mL; i += blockDim.x) rr[i] = rs[i];
+  }
+  if (b) {  // transpose pass: rs <- sb * b .* rs before U_L^T
+    __syncthreads();
+    for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+      const I2 pi = pts[i];
+      rs[i] = (R)(sb * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]) * rs[i];
+    }
+    __syncthreads();
+  }
   cplx<R>* rtt = rt + (rhs * nleaf + t) * (long)k;
   for (int a = threadIdx.x; a < k; a += blockDim.x) {
     cplx<R> acc = mk<R>(0, 0);
@@ -580,12 +590,13 @@ __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, 
 
 template <typename R>
 void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const z64* f, cplx<R>* r,
-             cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs) {
+             cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs, const double* b,
+             double sb) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
   ProfScope ps("leaf_up", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (2.0 * mL + k)) +
                                  16.0 * nrhs * (double)nleaf * mL);
   hipLaunchKernelGGL(k_leaf_up<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, f, r, rt, leaf_origin,
-                     leaf_pts, n, nleaf);
+                     leaf_pts, n, nleaf, b, sb);
   LSH_LAUNCH_CHECK();
 }
 
@@ -643,13 +654,65 @@ void leaf_down(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k
   LSH_LAUNCH_CHECK();
 }
 
+// Transpose pass, leaves: q_tau = X_tau^T (g_tau + U_L rb_tau) (X given transposed)
+template <typename R>
+__global__ __launch_bounds__(256) void k_leaf_tdown(const cplx<R>* __restrict__ XT, const cplx<R>* __restrict__ UL,
+                                                    int mL, int k, const cplx<R>* __restrict__ w,
+                                                    const z64* __restrict__ g, z64* q, const I2* __restrict__ org,
+                                                    const I2* __restrict__ pts, int n, int nleaf) {
+  __shared__ cplx<R> us[LEAF_MAX];
+  __shared__ cplx<R> ws[LEAF_MAX];
+  const long t = blockIdx.x, rhs = blockIdx.y;
+  const I2 o = org[t];
+  const cplx<R>* wt = w + (rhs * nleaf + t) * (long)k;
+  for (int a = threadIdx.x; a < k; a += blockDim.x) ws[a] = wt[a];
+  __syncthreads();
+  const z64* gr = g + rhs * (long)n * n;
+  for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+    cplx<R> acc = mk<R>(0, 0);
+    for (int a = 0; a < k; ++a) fma_acc(acc, UL[(long)i * k + a], ws[a]);
+    const I2 pi = pts[i];
+    const z64 gv = gr[(long)(o.y + pi.y) * n + (o.x + pi.x)];
+    us[i] = acc + mk<R>((R)gv.x, (R)gv.y);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const cplx<R>* Xt = XT + t * (long)mL * mL;
+  z64* qr = q + rhs * (long)n * n;
+  for (int i = wave; i < mL; i += 4) {
+    cplx<R> acc = mk<R>(0, 0);
+    for (int j = lane; j < mL; j += 64) fma_acc(acc, Xt[(long)i * mL + j], us[j]);
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) {
+      const I2 pi = pts[i];
+      qr[(long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)acc.x, (double)acc.y);
+    }
+  }
+}
+
+template <typename R>
+void leaf_tdown(hipStream_t s, const cplx<R>* XT, const cplx<R>* UL, int mL, int k, const cplx<R>* w, const z64* g,
+                z64* q, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs) {
+  LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
+  ProfScope ps("leaf_tdown", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (mL + k)) +
+                                    32.0 * nrhs * (double)nleaf * mL);
+  hipLaunchKernelGGL(k_leaf_tdown<R>, dim3(nleaf, nrhs), dim3(256), 0, s, XT, UL, mL, k, w, g, q, leaf_origin,
+                     leaf_pts, n, nleaf);
+  LSH_LAUNCH_CHECK();
+}
+
 #define LSH_HBS_INST(R)                                                                                       \
   template void leaf_build<R>(hipStream_t, cplx<R>*, const cplx<R>*, int, const double*, double, const I2*,   \
                               const I2*, int, int);                                                          \
   template void leaf_scale_U<R>(hipStream_t, cplx<R>*, const cplx<R>*, int, int, const double*, double,       \
                                 const I2*, const I2*, int, int);                                             \
   template void leaf_up<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const z64*, cplx<R>*,        \
-                           cplx<R>*, const I2*, const I2*, int, int, int);                                   \
+                           cplx<R>*, const I2*, const I2*, int, int, int, const double*, double);           \
+  template void leaf_tdown<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const cplx<R>*, const z64*,  \
+                              z64*, const I2*, const I2*, int, int, int);                                    \
   template void leaf_down<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const cplx<R>*,           \
                              const cplx<R>*, z64*, const double*, double, const I2*, const I2*, int, int, int);
 LSH_HBS_INST(float)

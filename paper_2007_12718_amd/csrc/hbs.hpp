@@ -38,7 +38,12 @@ void leaf_scale_U(hipStream_t s, cplx<R>* Y, const cplx<R>* U, int mL, int k, co
 // Apply, leaf level.  f, q: FP64 grid vectors [nrhs][n][n].
 template <typename R>
 void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const z64* f, cplx<R>* r,
-             cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs);
+             cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs,
+             const double* b = nullptr, double sb = 0);
+// transpose pass, leaves: q = X^T (g + U_L w), XT = X transposed per leaf
+template <typename R>
+void leaf_tdown(hipStream_t s, const cplx<R>* XT, const cplx<R>* UL, int mL, int k, const cplx<R>* w, const z64* g,
+                z64* q, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs);
 template <typename R>
 void leaf_down(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const cplx<R>* wt,
                const cplx<R>* r, z64* q, const double* b, double kappa2, const I2* leaf_origin,

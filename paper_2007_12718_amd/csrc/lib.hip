@@ -319,6 +319,12 @@ struct FactorData {
   DevBuf r;                       // [nrhs][nleaf][mL]
   std::vector<DevBuf> rt, wt;     // [nrhs][2^l][k_l]
   DevBuf t1, t2, t3, ty;          // scratch
+  // transposed per-box matrices for M^T (built on first use)
+  bool has_T = false;
+  DevBuf XT;
+  std::vector<DevBuf> ST, PaT, PbT, CiT;
+  std::vector<DevBuf> vb;         // transpose pass: per parent level [nrhs][2^l][2c]
+  int vb_nrhs = 0;
 };
 
 int check_info(const DevBuf& info, int batch, hipStream_t s) {
@@ -431,18 +437,47 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
 // out = X_tau in for every box of parent level l (B = nrhs * 2^l problems, [B][2c])
 template <typename R>
 void apply_X(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, const cplx<R>* in, cplx<R>* out,
-             hipStream_t s) {
+             hipStream_t s, bool transposed = false) {
   const int c = P.lev[l].c, nb = 1 << l, B = nrhs * nb;
   const long cc = (long)c * c;
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
   cplx<R>* ty = F.ty.template as<cplx<R>>();
+  // X = [[I, Pa], [Pb, I]]^{-1};  X^T has the same form with Pa -> Pb^T, Pb -> Pa^T, C^{-1} -> C^{-T}
+  const cplx<R>* Pa = (transposed ? F.PbT[l] : F.Pa[l]).template as<cplx<R>>();
+  const cplx<R>* Pb = (transposed ? F.PaT[l] : F.Pb[l]).template as<cplx<R>>();
+  const cplx<R>* Ci = (transposed ? F.CiT[l] : F.Ci[l]).template as<cplx<R>>();
   // ty = b - Pb a
-  cgemv<R>(s, c, c, mone, F.Pb[l].template as<cplx<R>>(), c, cc, nb, in, 2 * c, one, in + c, 2 * c, ty, c, B);
+  cgemv<R>(s, c, c, mone, Pb, c, cc, nb, in, 2 * c, one, in + c, 2 * c, ty, c, B);
   // y = C^{-1} ty  -> second half of out
-  cgemv<R>(s, c, c, one, F.Ci[l].template as<cplx<R>>(), c, cc, nb, ty, c, zero, nullptr, 0, out + c, 2 * c, B);
+  cgemv<R>(s, c, c, one, Ci, c, cc, nb, ty, c, zero, nullptr, 0, out + c, 2 * c, B);
   // top = a - Pa y -> first half of out
-  cgemv<R>(s, c, c, mone, F.Pa[l].template as<cplx<R>>(), c, cc, nb, out + c, 2 * c, one, in, 2 * c, out, 2 * c,
-           B);
+  cgemv<R>(s, c, c, mone, Pa, c, cc, nb, out + c, 2 * c, one, in, 2 * c, out, 2 * c, B);
+}
+
+template <typename R>
+void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
+  if (F.has_T) return;
+  const int L = P.L;
+  F.XT.alloc(F.X.bytes);
+  ctranspose<R>(s, F.X.template as<cplx<R>>(), P.mL, P.mL, F.XT.template as<cplx<R>>(), P.nleaf);
+  F.ST.clear(); F.PaT.clear(); F.PbT.clear(); F.CiT.clear();
+  F.ST.resize(L + 1); F.PaT.resize(L); F.PbT.resize(L); F.CiT.resize(L);
+  for (int l = 1; l <= L; ++l) {
+    const int k = P.lev[l].k;
+    F.ST[l].alloc(F.S[l].bytes);
+    ctranspose<R>(s, F.S[l].template as<cplx<R>>(), k, k, F.ST[l].template as<cplx<R>>(), 1L << l);
+  }
+  for (int l = 0; l < L; ++l) {
+    const int c = P.lev[l].c;
+    F.PaT[l].alloc(F.Pa[l].bytes);
+    F.PbT[l].alloc(F.Pb[l].bytes);
+    F.CiT[l].alloc(F.Ci[l].bytes);
+    ctranspose<R>(s, F.Pa[l].template as<cplx<R>>(), c, c, F.PaT[l].template as<cplx<R>>(), 1L << l);
+    ctranspose<R>(s, F.Pb[l].template as<cplx<R>>(), c, c, F.PbT[l].template as<cplx<R>>(), 1L << l);
+    ctranspose<R>(s, F.Ci[l].template as<cplx<R>>(), c, c, F.CiT[l].template as<cplx<R>>(), 1L << l);
+  }
+  LSH_HIP(hipStreamSynchronize(s));
+  F.has_T = true;
 }
 
 // below this many box vectors the shared products stream the matrix rows
@@ -512,6 +547,77 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
                b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
 }
 
+// q = M^T g: the steps of Algorithm 2 transposed, in reverse order.
+template <typename R>
+void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* g, z64* q, int nrhs,
+              hipStream_t s) {
+  ensure_apply_ws(P, F, nrhs);
+  ensure_transposed(P, F, s);
+  const int L = P.L;
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  const double k2 = P.kappa * P.kappa;
+  if (F.vb_nrhs < nrhs) {
+    F.vb.clear();
+    F.vb.resize(L);
+    for (int l = 1; l < L; ++l) F.vb[l].alloc(sizeof(cplx<R>) * (size_t)nrhs * ((size_t)1 << l) * 2 * P.lev[l].c);
+    F.vb_nrhs = nrhs;
+  }
+  cplx<R>* t1 = F.t1.template as<cplx<R>>();
+  cplx<R>* t2 = F.t2.template as<cplx<R>>();
+  cplx<R>* t3 = F.t3.template as<cplx<R>>();
+  // leaves: wb_L = -U_L^T B X^T g
+  leaf_up<R>(s, F.XT.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, g, nullptr,
+             F.wt[L].template as<cplx<R>>(), P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs, b, -k2);
+  // transposed downward pass, leaves upward
+  for (int l = L - 1; l >= 1; --l) {
+    const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
+    const long cc = (long)c * c;
+    const cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
+    cplx<R>* vb = F.vb[l].template as<cplx<R>>();
+    // vb = Ghat wc
+    if (B <= SKINNY) {
+      cmgemv<R>(s, c, c, one, P.Gab<R>(l), c, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B);
+      cmgemv<R>(s, c, c, one, P.Gabt<R>(l), c, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B);
+    } else {
+      cgemm<R>(s, B, c, c, one, wc + c, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_T, zero, nullptr, 0, 0, vb, 2 * c, 0, 1);
+      cgemm<R>(s, B, c, c, one, wc, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_N, zero, nullptr, 0, 0, vb + c, 2 * c, 0,
+               1);
+    }
+    // t3 = X^T vb ; t2 = wc - diag(S_a^T, S_b^T) t3
+    apply_X<R>(P, F, l, nrhs, vb, t3, s, true);
+    cgemv<R>(s, c, c, mone, F.ST[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t3, c, one, wc, c, t2, c, 2 * B);
+    // wb_l = U_l^T t2
+    if (B <= SKINNY)
+      cmgemv<R>(s, k, 2 * c, one, P.Ut<R>(l), 2 * c, t2, 2 * c, zero, nullptr, 0, F.wt[l].template as<cplx<R>>(), k,
+                B);
+    else
+      cgemm<R>(s, B, k, 2 * c, one, t2, 2 * c, 0, OP_N, P.U<R>(l), k, 0, OP_N, zero, nullptr, 0, 0,
+               F.wt[l].template as<cplx<R>>(), k, 0, 1);
+  }
+  // root: rb_1 = X_root^T Ghat wb_1
+  {
+    const int c = P.lev[0].c;
+    const cplx<R>* wc = F.wt[1].template as<cplx<R>>();
+    cmgemv<R>(s, c, c, one, P.Gab<R>(0), c, wc + c, 2 * c, zero, nullptr, 0, t1, 2 * c, nrhs);
+    cmgemv<R>(s, c, c, one, P.Gabt<R>(0), c, wc, 2 * c, zero, nullptr, 0, t1 + c, 2 * c, nrhs);
+    apply_X<R>(P, F, 0, nrhs, t1, F.rt[1].template as<cplx<R>>(), s, true);
+  }
+  // transposed upward pass: rb_children = X^T (vb + U_l rb_l)
+  for (int l = 1; l <= L - 1; ++l) {
+    const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
+    const cplx<R>* vb = F.vb[l].template as<cplx<R>>();
+    if (B <= SKINNY)
+      cmgemv<R>(s, 2 * c, k, one, P.U<R>(l), k, F.rt[l].template as<cplx<R>>(), k, one, vb, 2 * c, t1, 2 * c, B);
+    else
+      cgemm<R>(s, B, 2 * c, k, one, F.rt[l].template as<cplx<R>>(), k, 0, OP_N, P.U<R>(l), k, 0, OP_T, one, vb,
+               2 * c, 0, t1, 2 * c, 0, 1);
+    apply_X<R>(P, F, l, nrhs, t1, F.rt[l + 1].template as<cplx<R>>(), s, true);
+  }
+  // leaves: q = X^T (g + U_L rb_L)
+  leaf_tdown<R>(s, F.XT.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, F.rt[L].template as<cplx<R>>(), g, q,
+                P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
+}
+
 }  // namespace
 
 struct lsh_factor_s {
@@ -522,9 +628,14 @@ struct lsh_factor_s {
   // FGMRES workspace
   int gm_maxit = 0;
   DevBuf V, Z, w, h1, h2, part, fvec, res;
-  void apply(const z64* x, z64* y, int nrhs, hipStream_t s) {
-    if (plan->d.hbs_prec == LSH_FP32) apply_M<float>(*plan, b.as<double>(), f32, x, y, nrhs, s);
-    else apply_M<double>(*plan, b.as<double>(), f64, x, y, nrhs, s);
+  void apply(const z64* x, z64* y, int nrhs, hipStream_t s, bool transpose = false) {
+    if (plan->d.hbs_prec == LSH_FP32) {
+      if (transpose) apply_MT<float>(*plan, b.as<double>(), f32, x, y, nrhs, s);
+      else apply_M<float>(*plan, b.as<double>(), f32, x, y, nrhs, s);
+    } else {
+      if (transpose) apply_MT<double>(*plan, b.as<double>(), f64, x, y, nrhs, s);
+      else apply_M<double>(*plan, b.as<double>(), f64, x, y, nrhs, s);
+    }
   }
 };
 
@@ -541,8 +652,10 @@ __global__ void k_rhs(z64* f, const z64* u, const double* b, double k2, long N) 
     f[i] = (-k2 * b[i]) * u[i];
 }
 
+// Right-preconditioned flexible GMRES on A (or on A^T = I + K B with M^T
+// when transposed), x0 = 0, CGS2, Givens rotations on the host.
 void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, lsh_info* info, double& true_res,
-                int& conv, hipStream_t s) {
+                int& conv, hipStream_t s, bool transposed = false) {
   lsh_plan_s& P = *F.plan;
   const long N = (long)P.n * P.n;
   const int maxit = o.maxit;
@@ -582,9 +695,9 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
     z64* vj = V + (long)j * N;
     z64* zj = Z + (long)j * N;
     z64* w = V + (long)(j + 1) * N;
-    if (o.precondition) F.apply(vj, zj, 1, s);
+    if (o.precondition) F.apply(vj, zj, 1, s, transposed);
     else LSH_HIP(hipMemcpyAsync(zj, vj, sizeof(z64) * N, hipMemcpyDeviceToDevice, s));
-    P.op.apply(s, F.b.as<double>(), zj, w, 1);
+    P.op.apply(s, F.b.as<double>(), zj, w, 1, transposed);
     // classical Gram-Schmidt, twice
     multidot(s, V, N, j + 1, w, N, h1, part);
     multiaxpy(s, w, V, N, j + 1, h1, N);
@@ -631,7 +744,7 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
   lincomb(s, x, Z, N, k, h1, N);
   // true residual
   z64* r = F.res.as<z64>();
-  P.op.apply(s, F.b.as<double>(), x, r, 1);
+  P.op.apply(s, F.b.as<double>(), x, r, 1, transposed);
   sub_from(s, r, f, N);
   multidot(s, r, 0, 1, r, N, h2, part);
   z64 rn;
@@ -679,6 +792,40 @@ __global__ __launch_bounds__(256) void k_eval_points(const z64* __restrict__ sig
   }
 }
 
+// out[m][j] = h^2 sum_r conj(G(|x_r - x_j|)) g[m][r]  (adjoint of the receiver map)
+__global__ __launch_bounds__(256) void k_eval_points_adj(const z64* __restrict__ g, int npts, int nrhs, int n,
+                                                         double h, double gx0, double gy0, double kappa,
+                                                         const double* __restrict__ xy, z64* out) {
+  const long N = (long)n * n;
+  const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int i1 = (int)(j % n), i2 = (int)(j / n);
+  const double px = gx0 + (i1 + 0.5) * h, py = gy0 + (i2 + 0.5) * h;
+  z64 acc[EV_MAXRHS];
+  for (int m = 0; m < EV_MAXRHS; ++m) acc[m] = mk(0.0, 0.0);
+  for (int r = 0; r < npts; ++r) {
+    const double dx = xy[2 * r] - px, dy = xy[2 * r + 1] - py;
+    const double rr = kappa * sqrt(dx * dx + dy * dy);
+    const z64 gc = mk(-0.25 * y0(rr), -0.25 * j0(rr));  // conj((i/4) H0)
+    for (int m = 0; m < EV_MAXRHS; ++m)
+      if (m < nrhs) fma_acc(acc[m], gc, g[(long)m * npts + r]);
+  }
+  for (int m = 0; m < nrhs; ++m) out[m * N + j] = (h * h) * acc[m];
+}
+
+// grad[k] = -kappa^2 Re sum_m conj(lambda[m][k]) (u_inc[m][k] + u[m][k])
+__global__ void k_grad_b(const z64* __restrict__ lam, const z64* __restrict__ uinc, const z64* __restrict__ us,
+                         int nrhs, long N, double k2, double* grad) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+    double a = 0;
+    for (int m = 0; m < nrhs; ++m) {
+      const z64 l = lam[m * N + i], u = uinc[m * N + i] + us[m * N + i];
+      a += l.x * u.x + l.y * u.y;
+    }
+    grad[i] = -k2 * a;
+  }
+}
+
 int fail(const lsh::Error& e) {
   g_last_error = e.what();
   return e.code;
@@ -702,6 +849,35 @@ int fail(const lsh::Error& e) {
 extern "C" {
 
 const char* lsh_last_error(void) { return g_last_error.c_str(); }
+
+int lsh_eval_points_adjoint(lsh_plan_t P, const void* g_pts, const double* xy, int npts, void* out, int nrhs,
+                            void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && g_pts && xy && out && npts >= 1 && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const long N = (long)P->n * P->n;
+  for (int r0 = 0; r0 < nrhs; r0 += EV_MAXRHS) {
+    const int nr = nrhs - r0 < EV_MAXRHS ? nrhs - r0 : EV_MAXRHS;
+    hipLaunchKernelGGL(k_eval_points_adj, dim3(ceil_div(N, 256)), dim3(256), 0, s,
+                       static_cast<const z64*>(g_pts) + (long)r0 * npts, npts, nr, P->n, P->h, P->d.x0, P->d.y0,
+                       P->kappa, xy, static_cast<z64*>(out) + r0 * N);
+    LSH_LAUNCH_CHECK();
+  }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_grad_b(lsh_plan_t P, const void* lambda, const void* u_inc, const void* u, int nrhs, double* grad,
+               void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && lambda && u_inc && u && grad && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  const long N = (long)P->n * P->n;
+  hipLaunchKernelGGL(k_grad_b, dim3(2048), dim3(256), 0, (hipStream_t)stream, static_cast<const z64*>(lambda),
+                     static_cast<const z64*>(u_inc), static_cast<const z64*>(u), nrhs, N, P->kappa * P->kappa, grad);
+  LSH_LAUNCH_CHECK();
+  return LSH_OK;
+  API_END
+}
 
 int lsh_profile_enable(int on) {
   API_BEGIN
@@ -852,8 +1028,7 @@ int lsh_factor_destroy(lsh_factor_t F) {
 int lsh_apply_precond(lsh_factor_t F, int transpose, const void* x, void* y, int nrhs, void* stream) {
   API_BEGIN
   LSH_REQUIRE(F && x && y && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
-  LSH_REQUIRE(!transpose, LSH_ERR_UNSUPPORTED, "transpose apply not available");
-  F->apply(static_cast<const z64*>(x), static_cast<z64*>(y), nrhs, (hipStream_t)stream);
+  F->apply(static_cast<const z64*>(x), static_cast<z64*>(y), nrhs, (hipStream_t)stream, transpose != 0);
   return LSH_OK;
   API_END
 }
@@ -902,8 +1077,30 @@ int lsh_solve_adjoint(lsh_factor_t F, const void* g, int nrhs, void* lambda, con
                       lsh_info* info, void* stream) {
   API_BEGIN
   LSH_REQUIRE(F && g && lambda && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
-  LSH_REQUIRE(false, LSH_ERR_UNSUPPORTED, "adjoint solve not available yet");
-  return LSH_OK;
+  lsh_solve_opts o{1e-10, 100, 1};
+  if (opts) o = *opts;
+  LSH_REQUIRE(o.maxit >= 1 && o.maxit <= LSH_MAX_ITERS && o.tol > 0, LSH_ERR_INVALID_ARG, "bad solve options");
+  hipStream_t s = (hipStream_t)stream;
+  lsh_plan_s& P = *F->plan;
+  const long N = (long)P.n * P.n;
+  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * N) F->fvec.alloc(sizeof(z64) * N);
+  z64* f = F->fvec.as<z64>();
+  int allconv = 1;
+  double worst = 0;
+  if (info) std::memset(info, 0, sizeof(lsh_info));
+  // A^H lambda = g  <=>  A^T conj(lambda) = conj(g),  A^T = I + K B (K symmetric)
+  for (int r = 0; r < nrhs; ++r) {
+    z64* lr = static_cast<z64*>(lambda) + r * N;
+    conj_copy(s, f, static_cast<const z64*>(g) + r * N, N);
+    double tr = 0;
+    int conv = 0;
+    fgmres_one(*F, f, lr, o, info, tr, conv, s, true);
+    conj_copy(s, lr, lr, N);
+    if (!conv) allconv = 0;
+    if (tr > worst) worst = tr;
+  }
+  if (info) info->true_residual = worst;
+  return allconv ? LSH_OK : LSH_NOT_CONVERGED;
   API_END
 }
 

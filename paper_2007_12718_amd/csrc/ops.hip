@@ -69,18 +69,23 @@ __device__ __forceinline__ void fft_lds(z64* x, int M, int logM, const z64* __re
 __device__ __forceinline__ int bitrev(int i, int logM) { return (int)(__brev((unsigned)i) >> (32 - logM)); }
 
 // mode 0: plain rows; mode 1: multiply by spectrum row then inverse transform;
-// mode 2: inverse transform with operator epilogue y = x + kb2 * b * v.
+// mode 2: epilogue y = x + kb2 * b * v; mode 4: epilogue y = x + v.
+// preb (optional): the input row is scaled by prek * preb on load.
 __global__ __launch_bounds__(256) void k_fft_rows(const z64* __restrict__ in, long ldin, int nin, z64* out,
                                                   long ldout, int nout, int M, int logM,
                                                   const z64* __restrict__ W, int inv, int mode,
                                                   const z64* __restrict__ spec, long ldspec,
                                                   const z64* __restrict__ xadd, const double* __restrict__ b,
-                                                  double kb2) {
+                                                  double kb2, const double* __restrict__ preb, double prek) {
   extern __shared__ unsigned char smem_raw[];
   z64* x = reinterpret_cast<z64*>(smem_raw);
   const long r = blockIdx.x;
   const z64* src = in + r * ldin;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) x[bitrev(i, logM)] = i < nin ? src[i] : mk(0.0, 0.0);
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    z64 v = i < nin ? src[i] : mk(0.0, 0.0);
+    if (preb && i < nin) v = (prek * preb[r * ldin + i]) * v;
+    x[bitrev(i, logM)] = v;
+  }
   __syncthreads();
   fft_lds(x, M, logM, W, inv != 0);
   if (mode == 1) {
@@ -101,6 +106,8 @@ __global__ __launch_bounds__(256) void k_fft_rows(const z64* __restrict__ in, lo
       const long g = r * ldout + i;
       dst[i] = xadd[g] + (kb2 * b[g]) * x[i];
     }
+  } else if (mode == 4) {
+    for (int i = threadIdx.x; i < nout; i += blockDim.x) dst[i] = xadd[r * ldout + i] + x[i];
   } else {
     for (int i = threadIdx.x; i < nout; i += blockDim.x) dst[i] = x[i];
   }
@@ -110,7 +117,7 @@ void fft_rows(hipStream_t s, const FFTPlan& P, const z64* in, long ldin, int nin
               int nrows, bool inverse) {
   hipLaunchKernelGGL(k_fft_rows, dim3(nrows), dim3(256), P.M * sizeof(z64), s, in, ldin, nin, out, ldout, nout,
                      P.M, P.logM, P.tw.as<z64>(), inverse ? 1 : 0, 0, (const z64*)nullptr, 0L,
-                     (const z64*)nullptr, (const double*)nullptr, 0.0);
+                     (const z64*)nullptr, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0);
   LSH_LAUNCH_CHECK();
 }
 
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(256) void k_transpose(const z64* __restrict__ in, l
   }
 }
 
-void transpose(hipStream_t s, const z64* in, long ldin, z64* out, long ldout, int rows, int cols) {
+void transpose_z(hipStream_t s, const z64* in, long ldin, z64* out, long ldout, int rows, int cols) {
   dim3 grid(ceil_div(cols, TT), ceil_div(rows, TT));
   hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, in, ldin, out, ldout, rows, cols);
   LSH_LAUNCH_CHECK();
@@ -191,7 +198,7 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
   // full 2-D transform, kept transposed: khatT[k1][k2]
   z64* Kt = khatT.as<z64>();
   fft_rows(s, fft, C, M, M, C, M, M, M, false);
-  transpose(s, C, M, Kt, M, M, M);
+  transpose_z(s, C, M, Kt, M, M, M);
   fft_rows(s, fft, Kt, M, M, Kt, M, M, M, false);
   hipLaunchKernelGGL(k_scale_c, dim3(ceil_div((long)M * M, 256)), dim3(256), 0, s, Kt, (long)M * M,
                      1.0 / ((double)M * M));
@@ -199,35 +206,31 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
   LSH_HIP(hipStreamSynchronize(s));  // the small staging buffers die here
 }
 
-void ConvOperator::apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs) {
+void ConvOperator::apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs, bool transpose) {
   // algorithmic bytes: read x (and b), write y, read the spectrum once
   ProfScope ps("fft_operator", s, (double)nrhs * (16.0 * 2 * n * n + (b ? 8.0 * n * n : 0.0)) + 16.0 * M * M);
   z64* W1 = w1.as<z64>();
   z64* W2 = w2.as<z64>();
   const size_t lds = M * sizeof(z64);
+  const double k2 = kappa * kappa;
+  const z64* nz = nullptr;
+  const double* nd = nullptr;
   for (int r = 0; r < nrhs; ++r) {
     const z64* xr = x + (long)r * n * n;
     z64* yr = y + (long)r * n * n;
-    // rows (x1 direction) of the n data rows, padded to M
+    // rows (x1 direction) of the n data rows, padded to M (A^T: scaled by kappa^2 b first)
     hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, xr, (long)n, n, W1, (long)M, M, M, fft.logM,
-                       fft.tw.as<z64>(), 0, 0, (const z64*)nullptr, 0L, (const z64*)nullptr,
-                       (const double*)nullptr, 0.0);
+                       fft.tw.as<z64>(), 0, 0, nz, 0L, nz, nd, 0.0, (transpose && b) ? b : nd, k2);
     LSH_LAUNCH_CHECK();
-    transpose(s, W1, M, W2, n, n, M);  // W2: M x n
+    transpose_z(s, W1, M, W2, n, n, M);  // W2: M x n
     // columns: transform, multiply by the spectrum, transform back, keep n
     hipLaunchKernelGGL(k_fft_rows, dim3(M), dim3(256), lds, s, W2, (long)n, n, W2, (long)n, n, M, fft.logM,
-                       fft.tw.as<z64>(), 0, 1, khatT.as<z64>(), (long)M, (const z64*)nullptr,
-                       (const double*)nullptr, 0.0);
+                       fft.tw.as<z64>(), 0, 1, khatT.as<z64>(), (long)M, nz, nd, 0.0, nd, 0.0);
     LSH_LAUNCH_CHECK();
-    transpose(s, W2, n, W1, M, M, n);  // W1: n x M
-    if (b) {
-      hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, W1, (long)M, M, yr, (long)n, n, M, fft.logM,
-                         fft.tw.as<z64>(), 1, 2, (const z64*)nullptr, 0L, xr, b, kappa * kappa);
-    } else {
-      hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, W1, (long)M, M, yr, (long)n, n, M, fft.logM,
-                         fft.tw.as<z64>(), 1, 3, (const z64*)nullptr, 0L, (const z64*)nullptr,
-                         (const double*)nullptr, 0.0);
-    }
+    transpose_z(s, W2, n, W1, M, M, n);  // W1: n x M
+    const int mode = !b ? 3 : (transpose ? 4 : 2);
+    hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, W1, (long)M, M, yr, (long)n, n, M, fft.logM,
+                       fft.tw.as<z64>(), 1, mode, nz, 0L, b ? xr : nz, b, k2, nd, 0.0);
     LSH_LAUNCH_CHECK();
   }
 }
@@ -338,6 +341,16 @@ __global__ void k_sub_from(z64* y, const z64* x, long N) {
 
 void sub_from(hipStream_t s, z64* y, const z64* x, long N) {
   hipLaunchKernelGGL(k_sub_from, dim3(2048), dim3(256), 0, s, y, x, N);
+  LSH_LAUNCH_CHECK();
+}
+
+__global__ void k_conj(z64* y, const z64* x, long N) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+    y[i] = conjg(x[i]);
+}
+
+void conj_copy(hipStream_t s, z64* y, const z64* x, long N) {
+  hipLaunchKernelGGL(k_conj, dim3(2048), dim3(256), 0, s, y, x, N);
   LSH_LAUNCH_CHECK();
 }
 

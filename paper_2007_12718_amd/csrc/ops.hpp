@@ -17,7 +17,7 @@ struct FFTPlan {
 void fft_rows(hipStream_t s, const FFTPlan& P, const z64* in, long ldin, int nin, z64* out, long ldout,
               int nout, int nrows, bool inverse);
 // out[c][r] = in[r][c]
-void transpose(hipStream_t s, const z64* in, long ldin, z64* out, long ldout, int rows, int cols);
+void transpose_z(hipStream_t s, const z64* in, long ldin, z64* out, long ldout, int rows, int cols);
 
 // y = x + kappa^2 b (K * x) (and the plain convolution u = K * x) with the
 // zero-padded circulant embedding of size M x M, M = 2^k >= 2n.
@@ -29,8 +29,9 @@ struct ConvOperator {
   DevBuf w1, w2;    // n x M and M x n work arrays
   void init(hipStream_t s, int n_, double h, double kappa_, const z64* table, int D,
             const std::vector<StencilEntry>& stencil);
-  // b == nullptr: y = K * x ; otherwise y = x + kappa^2 b (K * x)
-  void apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs);
+  // b == nullptr: y = K * x ; otherwise y = x + kappa^2 b (K * x), or with
+  // transpose the transposed operator y = x + K * (kappa^2 b x)
+  void apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs, bool transpose = false);
 };
 
 // Offset table T[dy][dx] = h^2 (i/4) H0(kappa h |d|) for 0 <= dx, dy <= D,
@@ -53,5 +54,7 @@ void scale_real(hipStream_t s, z64* y, const z64* x, const double* b, double a, 
 // y = x - y
 void sub_from(hipStream_t s, z64* y, const z64* x, long N);
 void fill_zero(hipStream_t s, void* p, size_t bytes);
+// y = conj(x)
+void conj_copy(hipStream_t s, z64* y, const z64* x, long N);
 
 }  // namespace lsh

@@ -26,6 +26,7 @@ EXPORTED = [
     "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
     "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
+    "lsh_eval_points_adjoint", "lsh_grad_b",
 ]
 
 
@@ -59,6 +60,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        # torch ships its own HIP runtime; load it first so that liblsh's
+        # libamdhip64 dependency resolves to that same copy (one runtime per
+        # process, shared device memory and streams).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.lsh_last_error.restype = ctypes.c_char_p
         L.lsh_plan_create.argtypes = [POINTER(LshDesc), c_void_p, POINTER(c_void_p)]
@@ -82,6 +87,8 @@ def lib():
                                    c_void_p, c_long, c_long, c_int, POINTER(c_double), c_void_p, c_long, c_long,
                                    c_void_p, c_long, c_long, c_int, c_void_p]
         L.lsh_dev_inverse.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p]
+        L.lsh_eval_points_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p]
+        L.lsh_grad_b.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]
         L.lsh_profile_enable.argtypes = [c_int]
         L.lsh_profile_query.argtypes = [ctypes.c_char_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]
         L.lsh_profile_names.argtypes = [ctypes.c_char_p, c_int]
@@ -204,6 +211,29 @@ class Plan:
         return out
 
 
+    def eval_points_adjoint(self, g, xy):
+        """out[m] = E^H g[m] on the grid (adjoint of eval_points)."""
+        import torch
+        g = g.reshape(-1, xy.reshape(-1, 2).shape[0]).contiguous()
+        xy = xy.reshape(-1, 2).contiguous()
+        out = torch.empty((g.shape[0], self.n, self.n), dtype=torch.complex128, device="cuda")
+        _check(lib().lsh_eval_points_adjoint(self.handle, _ptr(g, torch.complex128), _ptr(xy, torch.float64),
+                                             xy.shape[0], _ptr(out), g.shape[0], _stream()))
+        return out
+
+    def grad_b(self, lam, u_inc, u):
+        """-kappa^2 Re sum_m conj(lam_m) (u_inc_m + u_m), shape (n, n) float64."""
+        import torch
+        n = self.n
+        lam = lam.reshape(-1, n, n).contiguous()
+        u_inc = u_inc.reshape(-1, n, n).contiguous()
+        u = u.reshape(-1, n, n).contiguous()
+        out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        _check(lib().lsh_grad_b(self.handle, _ptr(lam, torch.complex128), _ptr(u_inc, torch.complex128),
+                                _ptr(u, torch.complex128), lam.shape[0], _ptr(out), _stream()))
+        return out
+
+
 class Factor:
     """lsh_factor_create: Algorithm 1 for the potential b (float64, (n, n), device)."""
 
@@ -305,3 +335,56 @@ def lsh_profile_names():
     buf = ctypes.create_string_buffer(4096)
     _check(lib().lsh_profile_names(buf, 4096))
     return [x for x in buf.value.decode().split(";") if x]
+
+
+def receiver_field(b, u_inc, xy, plan: Plan, tol=1e-10, maxit=100):
+    """Scattered field at off-grid receivers, differentiable in b.
+
+    Forward: Algorithm 1 for b, preconditioned FGMRES for sigma, then
+    u(x_r) = h^2 sum_j G(x_r - x_j) sigma_j.  Backward (the adjoint method):
+    g = E^H dL/du*, lambda = A^{-H} g by the transposed-HBS-preconditioned
+    solve, dL/db = -kappa^2 Re sum_m conj(lambda_m) u_tot_m.  All steps run in
+    liblsh; this function only routes the tensors.
+    """
+    return _ReceiverField.apply(b, u_inc, xy, plan, tol, maxit)
+
+
+def _autograd_function():
+    import torch
+
+    class ReceiverField(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, b, u_inc, xy, plan, tol, maxit):
+            F = Factor(plan, b.detach())
+            sig, u, info, rc = F.solve(u_inc.detach(), tol=tol, maxit=maxit)
+            if rc != LSH_OK:
+                raise LshError(rc, "forward solve did not converge")
+            ur = plan.eval_points(sig, xy)
+            ctx.F, ctx.plan, ctx.tol, ctx.maxit = F, plan, tol, maxit
+            ctx.save_for_backward(u_inc.detach(), u, xy)
+            return ur
+
+        @staticmethod
+        def backward(ctx, grad_ur):
+            u_inc, u, xy = ctx.saved_tensors
+            g = ctx.plan.eval_points_adjoint(grad_ur.contiguous(), xy)
+            lam, info, rc = ctx.F.solve_adjoint(g, tol=ctx.tol, maxit=ctx.maxit)
+            if rc != LSH_OK:
+                raise LshError(rc, "adjoint solve did not converge")
+            gb = ctx.plan.grad_b(lam, u_inc, u)
+            return gb, None, None, None, None, None
+
+    return ReceiverField
+
+
+class _Lazy:
+    fn = None
+
+    @classmethod
+    def apply(cls, *args):
+        if cls.fn is None:
+            cls.fn = _autograd_function()
+        return cls.fn.apply(*args)
+
+
+_ReceiverField = _Lazy
