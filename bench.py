@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=256, help="grid side of the oracle's timed sample")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel hipEvent records")
+    ap.add_argument("--separate", action="store_true",
+                    help="lsh_plan_create + lsh_factor_create instead of the pipelined lsh_build")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 256 MiB device copy first (counter calibration for rocprofv3 --pmc)")
     return ap.parse_args()
 
 
@@ -52,19 +56,26 @@ def workload(n):
     return synth.largest(n=n, kappa=200 * np.pi * n / 1024)
 
 
-def run_step(lsh, w, b_d, u_d, prec, torch):
+def run_step(lsh, w, b_d, u_d, prec, torch, separate=False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width, prec=prec)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    F = lsh.Factor(P, b_d)
+    if separate:  # lsh_plan_create then lsh_factor_create
+        P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width,
+                     prec=prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F = lsh.Factor(P, b_d)
+    else:  # lsh_build: the same plan and factor, pipelined by level
+        P, F = lsh.build(w.n, w.kappa, b_d, op_order=w.op_order, leaf=w.leaf, tol=w.tol,
+                         proxy_width=w.proxy_width, prec=prec)
+        t1 = None
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     sig, _, info, rc = F.solve(u_d, tol=w.gmres_tol, maxit=100, want_u=False)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    out = {"plan_s": t1 - t0, "factor_s": t2 - t1, "solve_s": t3 - t2, "total_s": t3 - t0,
+    out = {"build_s": t2 - t0, "plan_s": (t1 - t0) if t1 else None, "factor_s": (t2 - t1) if t1 else None,
+           "solve_s": t3 - t2, "total_s": t3 - t0,
            "iterations": info.iterations, "true_residual": info.true_residual, "rc": rc,
            "ranks": P.ranks()[1]}
     F.close()
@@ -77,14 +88,16 @@ def roofline(lsh):
     """Dominant instrumented kernel over the timed region, against its peak."""
     best = None
     for name in lsh.lsh_profile_names():
+        if name.startswith("op_"):  # composite operations are not single kernels
+            continue
         n, ms, work = lsh.lsh_profile_query(name)
         if n and (best is None or ms > best[2]):
             best = (name, n, ms, work)
     if best is None:
         return None
     name, n, ms, work = best
-    if name.startswith("cgemm") or name.startswith("inverse"):
-        peak = PEAK_FP32_TFLOPS if name.endswith("f32") else PEAK_FP64_TFLOPS
+    if name.startswith("cgemm"):
+        peak = PEAK_FP32_TFLOPS if "_f32" in name else PEAK_FP64_TFLOPS
         achieved = work / (ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None, "launches": n, "ms_total": ms,
@@ -93,6 +106,23 @@ def roofline(lsh):
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": None, "launches": n, "ms_total": ms,
             "work_per_launch": work / n}
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2007_12718_amd", "csrc", rec["source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def kernel_table(lsh):
@@ -141,13 +171,19 @@ def main():
     from paper_2007_12718_amd import lsh
 
     torch.cuda.set_device(0)
+    if a.calib_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workload(a.n)
     b_d = torch.from_numpy(w.b).cuda()
     u_d = torch.from_numpy(w.u_inc).cuda()
     forms = ["fp32"] + ([] if a.no_fp64 else ["fp64"])
     for _ in range(a.warmup):
         for prec in forms:
-            r = run_step(lsh, w, b_d, u_d, prec, torch)
+            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate)
             print(f"# warmup {prec}: {json.dumps(r)}", file=sys.stderr, flush=True)
     results = {}
     prof = None
@@ -158,7 +194,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(a.steps):
-            r = run_step(lsh, w, b_d, u_d, prec, torch)
+            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate)
             steps.append(r)
             print(f"# step {k} {prec}: {json.dumps(r)}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -187,7 +223,7 @@ def main():
                                f"HBS 4th order tol={w.tol} leaf={w.leaf} proxy_width={w.proxy_width}, "
                                f"operator order {w.op_order}, GMRES tol {w.gmres_tol}",
                    "hbs_prec": "fp32", "phases_s": {k: head["median"][k] for k in
-                                                    ("plan_s", "factor_s", "solve_s", "total_s")},
+                                                    ("build_s", "plan_s", "factor_s", "solve_s", "total_s")},
                    "iterations": head["median"]["iterations"],
                    "true_residual": head["median"]["true_residual"],
                    "ranks": head["median"]["ranks"]},
@@ -195,11 +231,13 @@ def main():
     if "fp64" in results:
         r64 = results["fp64"]
         out["fp64_hbs"] = {"value": r64["ms_per_step"] / 1e3, "unit": "s",
-                           "phases_s": {k: r64["median"][k] for k in ("plan_s", "factor_s", "solve_s", "total_s")},
+                           "phases_s": {k: r64["median"][k] for k in ("build_s", "plan_s", "factor_s", "solve_s", "total_s")},
                            "iterations": r64["median"]["iterations"],
                            "true_residual": r64["median"]["true_residual"],
                            "speedup_fp32_over_fp64": r64["ms_per_step"] / head["ms_per_step"]}
     if prof:
+        if prof["roofline"]:
+            prof["roofline"]["traffic"] = committed_traffic(prof["roofline"]["kernel"])
         out["roofline"] = prof["roofline"]
         out["kernels"] = prof["kernels"]
     if not a.no_cpu_baseline:

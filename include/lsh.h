@@ -120,6 +120,14 @@ int lsh_plan_table(lsh_plan_t plan, int* D, void* out, void* stream);
  * b: device double[n*n].  Errors: LSH_ERR_INPUT_NONFINITE (non-finite b),
  * LSH_ERR_SINGULAR (zero pivot in a local inverse). */
 int lsh_factor_create(lsh_plan_t plan, const double* b, void* stream, lsh_factor_t* factor);
+
+/* Plan and factor in one call, pipelined by level: the factor of level l
+ * (Algorithm 1) starts as soon as the row ID and sibling block of level l
+ * exist (Sec. 3.2 builds them leaves-up, like Algorithm 1), so the
+ * latency-bound pivot loops of the compression overlap the factor's matrix
+ * products.  Same results as lsh_plan_create + lsh_factor_create; destroy
+ * the factor, then the plan.  Synchronises the stream before returning. */
+int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* plan, lsh_factor_t* factor);
 int lsh_factor_destroy(lsh_factor_t factor);
 
 /* y = M x: Algorithm 2 (M ~ (I + B G)^{-1}); transpose = 1 applies M^T.

@@ -3,6 +3,8 @@
 // Complex products run on the real matrix cores: each complex k-step is four
 // real 16x16x4 MFMAs (Re += ArBr - AiBi, Im += ArBi + AiBr) on LDS-staged
 // 64x64 tiles; four 64-wide wavefronts each own a 32x32 quarter of the tile.
+#include <cstdlib>
+
 #include "blas.hpp"
 #include "prof.hpp"
 
@@ -44,6 +46,7 @@ struct GemmP {
   cplx<R>* C;
   long ldc, sC;
   int addI;
+  const int* skip;  // optional device flag: the whole launch is a no-op when *skip != 0
 };
 
 // Tile: 2 x 2 wavefronts, each owning WM x WN blocks of 16 x 16 outputs, so the
@@ -60,12 +63,22 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
   using acc_t = typename M4::acc_t;
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int EA = BM * GBK / 256, EB = BN * GBK / 256;
+  if (P.skip && *P.skip) return;  // uniform across the launch
   __shared__ R sAr[BM][GLD], sAi[BM][GLD];
   __shared__ R sBr[BN][GLD], sBi[BN][GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long b = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // renumber them to give each XCD a contiguous run of tiles (neighbouring
+  // tiles share A rows / B columns in that XCD's L2).
+  const long T = (long)gridDim.x * gridDim.y * gridDim.z;
+  long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+  const long T8 = (T / 8) * 8;
+  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
+  const int tn = (int)(L % gridDim.x);
+  const int tm = (int)((L / gridDim.x) % gridDim.y);
+  const long b = L / ((long)gridDim.x * gridDim.y);
+  const int m0 = tm * BM, n0 = tn * BN;
   const cplx<R>* A = P.A + b * P.sA;
   const cplx<R>* B = P.B + b * P.sB;
   const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
@@ -184,8 +197,11 @@ template <typename R, int WM, int WN>
 static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, const cplx<R>* B, const cplx<R>* D,
                         cplx<R>* C, long sA, long sB, long sD, long sC, int batch) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
+  const char* name = sizeof(R) == 4 ? (BM == 128 ? "cgemm_f32_128x128" : "cgemm_f32_64x64")
+                                    : (BM == 128 ? "cgemm_f64_128x64" : "cgemm_f64_64x64");
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb);
     GemmP<R> Q = P;
     Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
     if (D) Q.D = D + b0 * sD;
@@ -200,10 +216,10 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            const cplx<R>* A, long lda, long sA, Op opA,
            const cplx<R>* B, long ldb, long sB, Op opB,
            cplx<R> beta, const cplx<R>* D, long ldd, long sD,
-           cplx<R>* C, long ldc, long sC, int batch, bool add_identity) {
+           cplx<R>* C, long ldc, long sC, int batch, bool add_identity, const int* skip) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
-  ProfScope ps(sizeof(R) == 4 ? "cgemm_f32" : "cgemm_f64", s, 8.0 * M * N * K * (double)batch);
   GemmP<R> P;
+  P.skip = skip;
   P.M = M; P.N = N; P.K = K; P.alpha = alpha; P.beta = beta;
   P.A = A; P.lda = lda; P.sA = sA; P.opA = opA;
   P.B = B; P.ldb = ldb; P.sB = sB; P.opB = opB;
@@ -402,179 +418,284 @@ __global__ __launch_bounds__(256) void k_inv_small(cplx<R>* A, int c, long lda, 
   if (tid == 0 && info) info[b] = s_bad;
 }
 
-// Large matrices: blocked in-place Gauss-Jordan.  Per block K of NB columns:
-//  1. k_gj_panel: one workgroup per matrix keeps the c x NB panel in
-//     registers, chooses NB pivots by partial pivoting among the unused rows,
-//     and applies the NB elementary Gauss-Jordan steps to the panel (which
-//     ends up holding the K columns of the block's elimination operator E);
-//  2. k_gj_swap: applies the row interchanges to the other columns, copies
-//     rows K of the other columns to T (nb x c, zero in K) and writes
-//     F = E(:,K) - I(:,K);
-//  3. GEMM: A += F T  (updates every column outside K).
-// At the end the row interchanges are undone as column interchanges.
-constexpr int GJ_NB = 8, GJ_NT = 1024;
+// Large matrices: two-level blocked in-place Gauss-Jordan without row
+// interchanges.  The pivot of column j is the largest |a_ij|^2 among the rows
+// not yet used as pivots (partial pivoting); that row p_j stays where it is.
+// One elementary step E_j = I + w_j e_{p_j}^T makes column j the unit vector
+// e_{p_j}; in place, column j receives E_j's column p_j instead (1/pivot in
+// row p_j, -a_ij/pivot elsewhere) and every other column is updated.  With
+// Q = [e_{p_0} .. e_{p_{c-1}}] the array ends as S = E Q where E A = Q, so
+//     A^{-1} = Q^T S Q^T,   A^{-1}[a][b] = S[p_a][pinv_b].
+// Blocking: slabs of NB2 columns, panels of NB columns within a slab.
+//  1. k_gj_panel: one workgroup per matrix holds the c x NB panel in
+//     registers (loaded and stored through LDS so that the global accesses
+//     are coalesced) and applies its NB steps.  One barrier per column: each
+//     wave posts its best candidate row and key, every thread reduces the
+//     posts itself.
+//  2. k_gj_gather + GEMM on the rest of the slab: the block's steps combine to
+//     E_K = I + F R_K^T (R_K selects rows p_K, F = S(:,K) - I(:,p_K)), so
+//     slab += F T with T = slab rows p_K (zero in the panel's columns).
+//  3. After the slab: the same with the slab's NB2 steps on every column
+//     outside it, one GEMM of depth NB2.
+//  4. k_gj_unperm: the permutation above, through a copy.
+constexpr int GJ_NT = 1024;
+constexpr int GJ_NB2_DEFAULT = 64, GJ_NB2_MAX = 256;
+constexpr int GJ_STAGE_BYTES = 32768;
 
-template <typename R, int RPT>
+static int gj_nb2() {
+  static int v = [] {
+    const char* e = getenv("LSH_GJ_NB2");
+    int x = e ? atoi(e) : GJ_NB2_DEFAULT;
+    if (x < 8) x = 8;
+    if (x > GJ_NB2_MAX) x = GJ_NB2_MAX;
+    return x & ~7;
+  }();
+  return v;
+}
+
+// Pivot search keys: a 64-bit integer whose maximum is the largest |a|^2
+// and, among equal values, the smallest row.  Non-negative IEEE values order
+// like their bit patterns.  FP32: value bits above the complemented row.
+// FP64: the value's top 51 bits above 8191 - row (rows < 4096; values equal in
+// those bits count as ties).  A NaN value counts as 0.  Every key of a
+// candidate row is nonzero; 0 = no candidate.
+template <typename R>
+struct PivKey;
+template <>
+struct PivKey<float> {
+  static __device__ __forceinline__ unsigned long long make(float a, int i) {
+    return ((unsigned long long)(a >= 0.f ? __float_as_uint(a) : 0u) << 32) | (unsigned)(~i);
+  }
+  static __device__ __forceinline__ int row(unsigned long long k) { return (int)(~(unsigned)k); }
+};
+template <>
+struct PivKey<double> {
+  static __device__ __forceinline__ unsigned long long make(double a, int i) {
+    const unsigned long long v = a >= 0.0 ? (unsigned long long)__double_as_longlong(a) : 0ull;
+    return (v & ~0x1FFFull) | (unsigned)(0x1FFF - i);
+  }
+  static __device__ __forceinline__ int row(unsigned long long k) { return 0x1FFF - (int)(k & 0x1FFF); }
+};
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(k, off);
+    k = o > k ? o : k;
+  }
+  return k;
+}
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a - f p with four fused multiply-adds
+template <typename R>
+__device__ __forceinline__ cplx<R> cfms(cplx<R> a, cplx<R> f, cplx<R> p) {
+  return mk<R>(fmaR(f.y, p.y, fmaR(-f.x, p.x, a.x)), fmaR(-f.y, p.x, fmaR(-f.x, p.y, a.y)));
+}
+
+// Workgroup barrier that orders LDS only: the panel kernel's global stores
+// (pivot records, the panel itself) are read by later launches only, so the
+// barrier need not wait for them.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Staging rounds move GJ_KR(R) x blockDim elements of the row-major panel
+// between global memory (coalesced) and the row owners (through LDS).
+template <typename R>
+constexpr int gj_kr() { return GJ_STAGE_BYTES / (GJ_NT * (int)sizeof(cplx<R>)); }
+
+template <typename R, int RPT, int NB>
 __global__ __launch_bounds__(GJ_NT) void k_gj_panel(cplx<R>* A, int c, long lda, long sA, int j0, int* perm,
-                                                    int* info) {
-  __shared__ cplx<R> prow[GJ_NB];
-  __shared__ cplx<R> rowbuf[2][GJ_NB];
-  __shared__ R wbest[GJ_NT / 64];
-  __shared__ int widx[GJ_NT / 64];
-  __shared__ int s_p;
+                                                    int* used, int* info) {
+  constexpr int KR = gj_kr<R>();
+  __shared__ cplx<R> stg[KR * GJ_NT];
+  __shared__ cplx<R> cand[2][GJ_NT / 64][NB];  // each wave's best candidate row (double-buffered)
+  __shared__ unsigned long long ckey[2][GJ_NT / 64];
   const long b = blockIdx.x;
   cplx<R>* Ab = A + b * sA;
   int* pb = perm + b * c;
+  int* ub = used + b * c;
+  const int nt = blockDim.x, nw = nt >> 6;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nb = (c - j0) < GJ_NB ? (c - j0) : GJ_NB;
-  cplx<R> P[RPT][GJ_NB];
+  const int nb = (c - j0) < NB ? (c - j0) : NB;
+  const int ne = c * NB;     // panel elements, row-major
+  const int S = KR * nt;     // elements per staging round (a multiple of NB)
+  const int nrounds = (ne + S - 1) / S;
+  cplx<R> P[RPT][NB];
+  bool avail[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int i = tid + r * GJ_NT;
+    const int i = tid + r * nt;
+    avail[r] = i < c && !ub[i];
 #pragma unroll
-    for (int q = 0; q < GJ_NB; ++q)
-      P[r][q] = (i < c && q < nb) ? Ab[(long)i * lda + j0 + q] : mk<R>(0, 0);
+    for (int q = 0; q < NB; ++q) P[r][q] = mk<R>(0, 0);
   }
-  for (int jj = 0; jj < nb; ++jj) {
-    const int j = j0 + jj;
-    R best = -1;
-    int bi = c;
+  {
+    cplx<R> V[KR], Vn[KR];
+    auto fetch = [&](cplx<R>(&v)[KR], int lo) {
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * GJ_NT;
-      if (i >= j && i < c) {
-        cplx<R> v = P[r][0];
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q)
-          if (q == jj) v = P[r][q];
-        const R a = abs2(v);
-        if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+      for (int k = 0; k < KR; ++k) {
+        const int e = lo + tid + k * nt, q = e & (NB - 1);
+        v[k] = (e < ne && q < nb) ? Ab[(long)(e / NB) * lda + j0 + q] : mk<R>(0, 0);
       }
-    }
-    wave_argmax(best, bi);
-    if (lane == 0) { wbest[wave] = best; widx[wave] = bi; }
-    __syncthreads();
-    if (tid < 64) {
-      R bb = tid < GJ_NT / 64 ? wbest[tid] : R(-1);
-      int ii = tid < GJ_NT / 64 ? widx[tid] : c;
-      wave_argmax(bb, ii);
-      if (tid == 0) {
-        s_p = ii;
-        pb[j] = ii;
-        if (!(bb > R(0)) && info && info[b] == 0) info[b] = j + 1;
+    };
+    fetch(V, 0);
+    for (int rd = 0; rd < nrounds; ++rd) {
+      const int lo = rd * S;
+      if (rd + 1 < nrounds) fetch(Vn, lo + S);  // next round in flight meanwhile
+#pragma unroll
+      for (int k = 0; k < KR; ++k) stg[tid + k * nt] = V[k];
+      lds_sync();
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int o = (tid + r * nt) * NB - lo;
+        if (o >= 0 && o < S && o < ne - lo)
+#pragma unroll
+          for (int q = 0; q < NB; ++q) P[r][q] = stg[o + q];
       }
+      lds_sync();
+#pragma unroll
+      for (int k = 0; k < KR; ++k) V[k] = Vn[k];
     }
-    __syncthreads();
-    const int p = s_p;
-    // publish rows j and p, then swap them
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * GJ_NT;
-      if (i == j)
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) rowbuf[0][q] = P[r][q];
-      if (i == p)
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) rowbuf[1][q] = P[r][q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * GJ_NT;
-      if (i == j && p != j)
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) P[r][q] = rowbuf[1][q];
-      if (i == p && p != j)
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) P[r][q] = rowbuf[0][q];
-    }
-    if (tid < GJ_NB) prow[tid] = rowbuf[1][tid];  // the new row j
-    __syncthreads();
-    cplx<R> piv = prow[0];
-#pragma unroll
-    for (int q = 0; q < GJ_NB; ++q)
-      if (q == jj) piv = prow[q];
-    const cplx<R> rp = crecip(piv);
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * GJ_NT;
-      if (i >= c) continue;
-      if (i == j) {
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) P[r][q] = (q == jj) ? rp : prow[q] * rp;
-      } else {
-        cplx<R> f = P[r][0];
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q)
-          if (q == jj) f = P[r][q];
-        const cplx<R> fr = f * rp;
-#pragma unroll
-        for (int q = 0; q < GJ_NB; ++q) P[r][q] = (q == jj) ? mk<R>(0, 0) - fr : P[r][q] - fr * prow[q];
-      }
-    }
-    __syncthreads();
   }
+  // the column loop is unrolled so that every register index is static
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int i = tid + r * GJ_NT;
-    if (i < c)
+  for (int jj = 0; jj < NB; ++jj) {
+    if (jj >= nb) break;
+    const int j = j0 + jj, buf = jj & 1;
+    unsigned long long key = 0;
 #pragma unroll
-      for (int q = 0; q < GJ_NB; ++q)
-        if (q < nb) Ab[(long)i * lda + j0 + q] = P[r][q];
-  }
-}
-
-template <typename R>
-__global__ void k_gj_swap(cplx<R>* A, int c, long lda, long sA, int j0, int nb, const int* perm,
-                          cplx<R>* T, cplx<R>* F) {
-  const long b = blockIdx.y;
-  cplx<R>* Ab = A + b * sA;
-  const int* pb = perm + b * c;
-  cplx<R>* Tb = T + b * (long)GJ_NB * c;
-  cplx<R>* Fb = F + b * (long)c * GJ_NB;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < c) {
-    const bool inK = (k >= j0 && k < j0 + nb);
-    if (!inK)
-      for (int q = 0; q < nb; ++q) {
-        const int j = j0 + q, p = pb[j];
-        if (p != j) {
-          cplx<R> t = Ab[(long)j * lda + k];
-          Ab[(long)j * lda + k] = Ab[(long)p * lda + k];
-          Ab[(long)p * lda + k] = t;
+    for (int r = 0; r < RPT; ++r)
+      if (avail[r]) {
+        const unsigned long long k = PivKey<R>::make(abs2(P[r][jj]), tid + r * nt);
+        key = k > key ? k : key;
+      }
+    key = wave_max_u64(key);
+    const int bi = key ? PivKey<R>::row(key) : -1;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+      if (tid + r * nt == bi)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) cand[buf][wave][q] = P[r][q];
+    if (lane == 0) ckey[buf][wave] = key;
+    lds_sync();
+    // block maximum: lane l reads wave (l mod 16)'s post, four exchange steps
+    unsigned long long kb = (lane & 15) < nw ? ckey[buf][lane & 15] : 0ull;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(kb, off);
+      kb = o > kb ? o : kb;
+    }
+    // fewer than c pivots are in use, so some row is a candidate (kb != 0);
+    // row p is held by thread p mod nt, so its post is that thread's wave's
+    const int p = PivKey<R>::row(kb);
+    const int pw = (p % nt) >> 6;
+    cplx<R> pr[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) pr[q] = cand[buf][pw][q];
+    if (tid == 0) {
+      pb[j] = p;
+      ub[p] = 1;
+      if (!(abs2(pr[jj]) > R(0)) && info && info[b] == 0) info[b] = j + 1;
+    }
+    const cplx<R> rp = crecip(pr[jj]);
+    // every row as a non-pivot row; the pivot row is overwritten below
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const cplx<R> fr = P[r][jj] * rp;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) P[r][q] = (q == jj) ? mk<R>(0, 0) - fr : cfms(P[r][q], fr, pr[q]);
+    }
+    if (wave == pw) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (tid + r * nt == p) {
+#pragma unroll
+          for (int q = 0; q < NB; ++q) P[r][q] = (q == jj) ? rp : pr[q] * rp;
+          avail[r] = false;
         }
-      }
-    for (int q = 0; q < GJ_NB; ++q)
-      Tb[(long)q * c + k] = (!inK && q < nb) ? Ab[(long)(j0 + q) * lda + k] : mk<R>(0, 0);
-    // F = panel - I(:,K), row k of F
-    for (int q = 0; q < GJ_NB; ++q) {
-      cplx<R> v = q < nb ? Ab[(long)k * lda + j0 + q] : mk<R>(0, 0);
-      if (q < nb && k == j0 + q) v.x -= R(1);
-      Fb[(long)k * GJ_NB + q] = v;
     }
+  }
+  // rows to LDS, then coalesced stores (never waited for inside the kernel)
+  for (int rd = 0; rd < nrounds; ++rd) {
+    const int lo = rd * S;
+    lds_sync();
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int o = (tid + r * nt) * NB - lo;
+      if (o >= 0 && o < S && o < ne - lo)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) stg[o + q] = P[r][q];
+    }
+    lds_sync();
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int e = lo + tid + k * nt, q = e & (NB - 1);
+      if (e < ne && q < nb) Ab[(long)(e / NB) * lda + j0 + q] = stg[tid + k * nt];
+    }
+  }
+}
+
+// Block K = columns [kb, kb+nbk) with pivot rows perm[kb ..]:
+//   T[q][t] = A[perm[kb+q]][cs+t] for the columns cs+t (t < ncol) outside K,
+//             0 inside K (ld ncol);
+//   F[i][q] = A[i][kb+q] - [i == perm[kb+q]]   (ld nbk).
+// Both index spaces run along contiguous memory.
+template <typename R>
+__global__ void k_gj_gather(const cplx<R>* A, int c, long lda, long sA, int kb, int nbk, int cs, int ncol,
+                            const int* perm, cplx<R>* T, cplx<R>* F) {
+  const long b = blockIdx.y;
+  const cplx<R>* Ab = A + b * sA;
+  const int* pb = perm + b * c + kb;
+  const long nT = (long)nbk * ncol, nF = (long)c * nbk;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nT + nF; e += (long)gridDim.x * blockDim.x) {
+    if (e < nT) {
+      const int q = (int)(e / ncol), t = (int)(e % ncol), k = cs + t;
+      T[b * nT + e] = (k >= kb && k < kb + nbk) ? mk<R>(0, 0) : Ab[(long)pb[q] * lda + k];
+    } else {
+      const long f = e - nT;
+      const int i = (int)(f / nbk), q = (int)(f % nbk);
+      cplx<R> v = Ab[(long)i * lda + kb + q];
+      if (i == pb[q]) v.x -= R(1);
+      F[b * nF + f] = v;
+    }
+  }
+}
+
+// tmp[a][b] = S[perm[a]][pinv[b]] (pinv[perm[j]] = j), then copied back
+template <typename R>
+__global__ void k_gj_pinv(const int* perm, int* pinv, int c, int batch) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)c * batch) return;
+  const long b = e / c;
+  pinv[b * c + perm[e]] = (int)(e % c);
+}
+
+template <typename R>
+__global__ void k_gj_unperm(const cplx<R>* A, int c, long lda, long sA, const int* perm, const int* pinv,
+                            cplx<R>* tmp) {
+  const long b = blockIdx.y;
+  const long n = (long)c * c;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int a = (int)(e / c), bb = (int)(e % c);
+    tmp[b * n + e] = A[b * sA + (long)perm[b * c + a] * lda + pinv[b * c + bb]];
   }
 }
 
 template <typename R>
-__global__ void k_gj_colperm(cplx<R>* A, int c, long lda, long sA, const int* perm) {
+__global__ void k_gj_copyback(cplx<R>* A, int c, long lda, long sA, const cplx<R>* tmp) {
   const long b = blockIdx.y;
-  cplx<R>* Ab = A + b * sA;
-  const int* pb = perm + b * c;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c) return;
-  cplx<R>* row = Ab + (long)i * lda;
-  for (int j = c - 1; j >= 0; --j) {
-    const int p = pb[j];
-    if (p != j) {
-      cplx<R> t = row[j];
-      row[j] = row[p];
-      row[p] = t;
-    }
-  }
+  const long n = (long)c * c;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    A[b * sA + (e / c) * lda + (e % c)] = tmp[b * n + e];
 }
 
-__global__ void k_zero_int(int* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero_int(int* p, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
 
@@ -583,18 +704,42 @@ static size_t small_inv_lds(int c) {
   return (size_t)c * c * sizeof(cplx<R>);
 }
 
+// blocked-path workspace per matrix: perm, pinv, used (int c each), T (NB2 x c),
+// F (c x NB2), the copy for the final permutation (c x c)
+template <typename R>
+static size_t gj_ws_per_matrix(int c) {
+  return 3 * (size_t)c * sizeof(int) + (2 * (size_t)gj_nb2() * c + (size_t)c * c) * sizeof(cplx<R>);
+}
+
 template <typename R>
 size_t inverse_ws_bytes(int c, int batch) {
   if (small_inv_lds<R>(c) <= 65536) return (size_t)batch * c * sizeof(int) + 256;
-  // perm (int c) + T (NB x c) + F (c x NB) per matrix
-  return (size_t)batch * ((size_t)c * sizeof(int) + 2 * (size_t)GJ_NB * c * sizeof(cplx<R>)) + 256;
+  return (size_t)batch * gj_ws_per_matrix<R>(c) + 8 * 256;
+}
+
+template <typename R, int NB>
+static void gj_panel_launch(hipStream_t s, int rpt, int nt, cplx<R>* A, int c, long lda, long sA, int j0,
+                            int* perm, int* used, int batch, int* info) {
+  const size_t lds = 0;
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL((k_gj_panel<R, 1, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
+    case 2: hipLaunchKernelGGL((k_gj_panel<R, 2, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
+    case 3: hipLaunchKernelGGL((k_gj_panel<R, 3, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
+    default: hipLaunchKernelGGL((k_gj_panel<R, 4, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
+  }
+  LSH_LAUNCH_CHECK();
+}
+
+static int grid_for(long n) {
+  const long g = (n + 255) / 256;
+  return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
 
 template <typename R>
 void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, void* ws, int* info) {
   if (c <= 0 || batch <= 0) return;
-  ProfScope ps(sizeof(R) == 4 ? "inverse_f32" : "inverse_f64", s, 8.0 * (double)c * c * c * batch);
-  if (info) hipLaunchKernelGGL(k_zero_int, dim3(ceil_div(batch, 256)), dim3(256), 0, s, info, batch);
+  ProfScope ps(sizeof(R) == 4 ? "op_inverse_f32" : "op_inverse_f64", s, 8.0 * (double)c * c * c * batch);
+  if (info) hipLaunchKernelGGL(k_zero_int, dim3(ceil_div(batch, 256)), dim3(256), 0, s, info, (long)batch);
   const size_t lds = small_inv_lds<R>(c);
   if (lds <= 65536) {
     int* permg = static_cast<int*>(ws);
@@ -604,26 +749,59 @@ void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, voi
   }
   LSH_REQUIRE(c <= 4 * GJ_NT, -6, "inverse: matrix order above 4096 is not supported");
   LSH_REQUIRE(batch <= 65535, -6, "inverse: batch too large for the blocked path");
-  int* perm = static_cast<int*>(ws);
-  cplx<R>* T = reinterpret_cast<cplx<R>*>(static_cast<char*>(ws) +
-                                          (((size_t)batch * c * sizeof(int) + 255) / 256) * 256);
-  cplx<R>* F = T + (size_t)batch * GJ_NB * c;
+  const int NB2 = gj_nb2();
+  char* w = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) {
+    char* p = w;
+    w += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  int* perm = reinterpret_cast<int*>(take((size_t)batch * c * sizeof(int)));
+  int* pinv = reinterpret_cast<int*>(take((size_t)batch * c * sizeof(int)));
+  int* used = reinterpret_cast<int*>(take((size_t)batch * c * sizeof(int)));
+  cplx<R>* T = reinterpret_cast<cplx<R>*>(take((size_t)batch * NB2 * c * sizeof(cplx<R>)));
+  cplx<R>* F = reinterpret_cast<cplx<R>*>(take((size_t)batch * NB2 * c * sizeof(cplx<R>)));
+  cplx<R>* tmp = reinterpret_cast<cplx<R>*>(take((size_t)batch * c * c * sizeof(cplx<R>)));
+  hipLaunchKernelGGL(k_zero_int, dim3(ceil_div((long)batch * c, 256)), dim3(256), 0, s, used, (long)batch * c);
+  LSH_LAUNCH_CHECK();
   const int rpt = ceil_div(c, GJ_NT);
-  for (int j0 = 0; j0 < c; j0 += GJ_NB) {
-    const int nb = (c - j0) < GJ_NB ? (c - j0) : GJ_NB;
-    switch (rpt) {
-      case 1: hipLaunchKernelGGL((k_gj_panel<R, 1>), dim3(batch), dim3(GJ_NT), 0, s, A, c, lda, sA, j0, perm, info); break;
-      case 2: hipLaunchKernelGGL((k_gj_panel<R, 2>), dim3(batch), dim3(GJ_NT), 0, s, A, c, lda, sA, j0, perm, info); break;
-      case 3: hipLaunchKernelGGL((k_gj_panel<R, 3>), dim3(batch), dim3(GJ_NT), 0, s, A, c, lda, sA, j0, perm, info); break;
-      default: hipLaunchKernelGGL((k_gj_panel<R, 4>), dim3(batch), dim3(GJ_NT), 0, s, A, c, lda, sA, j0, perm, info); break;
+  const int nt = ceil_div(ceil_div(c, rpt), 64) * 64;
+  // panel width: 8 columns, 4 for FP64 with more than one row per thread (register budget)
+  const int NB = (sizeof(R) == 8 && rpt > 1) ? 4 : 8;
+  const cplx<R> one = mk<R>(1, 0);
+  for (int s0 = 0; s0 < c; s0 += NB2) {
+    const int w2 = (c - s0) < NB2 ? (c - s0) : NB2;
+    for (int j0 = s0; j0 < s0 + w2; j0 += NB) {
+      const int nb = (s0 + w2 - j0) < NB ? (s0 + w2 - j0) : NB;
+      if (NB == 8) gj_panel_launch<R, 8>(s, rpt, nt, A, c, lda, sA, j0, perm, used, batch, info);
+      else gj_panel_launch<R, 4>(s, rpt, nt, A, c, lda, sA, j0, perm, used, batch, info);
+      if (w2 > nb) {  // the rest of the slab
+        hipLaunchKernelGGL(k_gj_gather<R>, dim3(grid_for((long)(nb + c) * w2), batch), dim3(256), 0, s, A, c, lda,
+                           sA, j0, nb, s0, w2, perm, T, F);
+        LSH_LAUNCH_CHECK();
+        cgemm<R>(s, c, w2, nb, one, F, nb, (long)c * nb, OP_N, T, w2, (long)nb * w2, OP_N, one, A + s0, lda, sA,
+                 A + s0, lda, sA, batch);
+      }
     }
-    LSH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gj_swap<R>, dim3(ceil_div(c, 256), batch), dim3(256), 0, s, A, c, lda, sA, j0, nb, perm, T, F);
-    LSH_LAUNCH_CHECK();
-    cgemm<R>(s, c, c, GJ_NB, mk<R>(1, 0), F, GJ_NB, (long)c * GJ_NB, OP_N, T, c, (long)GJ_NB * c, OP_N,
-             mk<R>(1, 0), A, lda, sA, A, lda, sA, batch);
+    if (c > w2) {  // every column outside the slab, depth w2
+      hipLaunchKernelGGL(k_gj_gather<R>, dim3(grid_for((long)2 * w2 * c), batch), dim3(256), 0, s, A, c, lda, sA,
+                         s0, w2, 0, c, perm, T, F);
+      LSH_LAUNCH_CHECK();
+      if (s0 > 0)
+        cgemm<R>(s, c, s0, w2, one, F, w2, (long)c * w2, OP_N, T, c, (long)w2 * c, OP_N, one, A, lda, sA, A, lda,
+                 sA, batch);
+      const int e = s0 + w2;
+      if (e < c)
+        cgemm<R>(s, c, c - e, w2, one, F, w2, (long)c * w2, OP_N, T + e, c, (long)w2 * c, OP_N, one, A + e, lda,
+                 sA, A + e, lda, sA, batch);
+    }
   }
-  hipLaunchKernelGGL(k_gj_colperm<R>, dim3(ceil_div(c, 256), batch), dim3(256), 0, s, A, c, lda, sA, perm);
+  hipLaunchKernelGGL(k_gj_pinv<R>, dim3(ceil_div((long)batch * c, 256)), dim3(256), 0, s, perm, pinv, c, batch);
+  LSH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gj_unperm<R>, dim3(grid_for((long)c * c), batch), dim3(256), 0, s, A, c, lda, sA, perm,
+                     pinv, tmp);
+  LSH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gj_copyback<R>, dim3(grid_for((long)c * c), batch), dim3(256), 0, s, A, c, lda, sA, tmp);
   LSH_LAUNCH_CHECK();
 }
 
@@ -662,7 +840,8 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
 
 #define LSH_INST(R)                                                                                        \
   template void cgemm<R>(hipStream_t, int, int, int, cplx<R>, const cplx<R>*, long, long, Op, const cplx<R>*, \
-                         long, long, Op, cplx<R>, const cplx<R>*, long, long, cplx<R>*, long, long, int, bool); \
+                         long, long, Op, cplx<R>, const cplx<R>*, long, long, cplx<R>*, long, long, int, bool, \
+                         const int*);                                                                      \
   template void cgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, long, int, const cplx<R>*, long, \
                          cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                               \
   template void cmgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, const cplx<R>*, long, cplx<R>, \

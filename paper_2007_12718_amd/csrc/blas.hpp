@@ -15,12 +15,13 @@ enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2, OP_R = 3 };
 //   op(A) is M x K (A stored M x K for OP_N, K x M for OP_T / OP_C)
 //   op(B) is K x N (B stored K x N for OP_N, N x K for OP_T / OP_C)
 // D may alias C (in-place accumulate).  Runs on MFMA (16x16x4 f32 / f64).
+// skip (optional, device): when *skip != 0 at launch time the call does nothing.
 template <typename R>
 void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            const cplx<R>* A, long lda, long sA, Op opA,
            const cplx<R>* B, long ldb, long sB, Op opB,
            cplx<R> beta, const cplx<R>* D, long ldd, long sD,
-           cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false);
+           cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false, const int* skip = nullptr);
 
 // y_b = alpha * A_{b mod amod} x_b + beta * z_b   (A_b is M x N, op N).
 // z may alias y; z may be null when beta == 0.

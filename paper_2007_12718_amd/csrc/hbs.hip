@@ -3,6 +3,7 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include "hbs.hpp"
 #include "prof.hpp"
@@ -174,69 +175,116 @@ __global__ void k_gram_init(const z64* M, int m, double* d, int* chosen, int* st
   if (i == 0) { state[0] = 0; state[1] = 0; }
 }
 
+// One-workgroup panel of nb <= PCH_NB pivots.  Per pivot: block argmax of the
+// Schur diagonal over unchosen rows, then the new column
+//   l_i = (conj(M[p][i]) - sum_{t in panel} L[i][t] conj(L[p][t])) / sqrt(d_p)
+// where each thread first issues all its panel loads (independent, in
+// registers) and the pivot row's panel entries come from LDS.
+constexpr int PCH_NB = 32, PCH_MAXM = 4096;
+
 __global__ __launch_bounds__(QR_NT) void k_pchol_panel(const z64* __restrict__ M, int m, double* d, int* chosen,
                                                         z64* Lt, int* piv, int j0, int nb, double thr2,
                                                         int* state) {
+  constexpr int RPT = PCH_MAXM / QR_NT;  // rows per thread
+  extern __shared__ unsigned char smem_raw[];
+  double* ds = reinterpret_cast<double*>(smem_raw);        // Schur diagonal (m)
+  unsigned char* cs = smem_raw + sizeof(double) * m;        // chosen flags (m)
   __shared__ double sb[QR_NW];
   __shared__ int si[QR_NW];
   __shared__ int s_p;
   __shared__ double s_d;
+  __shared__ z64 lpc[PCH_NB];  // conj(L[p][t]) for the panel columns so far
   if (state[1]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int jj = 0; jj < nb; ++jj) {
+  for (int i = tid; i < m; i += QR_NT) {
+    ds[i] = d[i];
+    cs[i] = (unsigned char)chosen[i];
+  }
+  __syncthreads();
+  int jj = 0;
+  bool stop = false;
+  for (; jj < nb; ++jj) {
     const int j = j0 + jj;
     if (j >= m) {
       if (tid == 0) { state[0] = m; state[1] = 1; }
-      return;
+      stop = true;
+      break;
     }
     double best = -1;
     int bi = m;
-    for (int i = tid; i < m; i += QR_NT)
-      if (!chosen[i]) {
-        const double a = d[i];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * QR_NT;
+      if (i < m && !cs[i]) {
+        const double a = ds[i];
         if (a > best || (a == best && i < bi)) { best = a; bi = i; }
       }
+    }
     wave_argmax_d(best, bi);
     if (lane == 0) { sb[wave] = best; si[wave] = bi; }
     __syncthreads();
-    if (tid == 0) {
-      double bb = sb[0];
-      int ii = si[0];
-      for (int w = 1; w < QR_NW; ++w)
-        if (sb[w] > bb || (sb[w] == bb && si[w] < ii)) { bb = sb[w]; ii = si[w]; }
-      s_p = ii;
-      s_d = bb;
+    if (tid < 64) {  // final reduction by one wave, then stage the pivot's panel row
+      double bb = tid < QR_NW ? sb[tid] : -1.0;
+      int ii = tid < QR_NW ? si[tid] : m;
+      wave_argmax_d(bb, ii);
+      if (tid == 0) { s_p = ii; s_d = bb; }
+      if (tid < jj && ii < m) lpc[tid] = conjg(Lt[(long)(j0 + tid) * m + ii]);
     }
     __syncthreads();
     const int p = s_p;
     const double dp = s_d;
     if (!(dp > thr2)) {
       if (tid == 0) { state[0] = j; state[1] = 1; }
-      return;
+      stop = true;
+      break;
     }
     const double sq = sqrt(dp), rs = 1.0 / sq;
-    for (int i = tid; i < m; i += QR_NT) {
-      z64 l;
-      if (i == p) {
-        l = mk(sq, 0.0);
-      } else if (chosen[i]) {
-        l = mk(0.0, 0.0);
-      } else {
-        l = conjg(M[(long)p * m + i]);
-        for (int t = j0; t < j; ++t) l = l - Lt[(long)t * m + i] * conjg(Lt[(long)t * m + p]);
-        l = rs * l;
-        d[i] -= abs2(l);
+    // issue every row's loads before any arithmetic
+    z64 l[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * QR_NT;
+      l[r] = (i < m) ? conjg(M[(long)p * m + i]) : mk(0.0, 0.0);
+    }
+    for (int t0 = 0; t0 < jj; t0 += 4) {
+      z64 v[RPT][4];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = tid + r * QR_NT;
+          v[r][t] = (i < m && t0 + t < jj) ? Lt[(long)(j0 + t0 + t) * m + i] : mk(0.0, 0.0);
+        }
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t0 + t < jj) l[r] = l[r] - v[r][t] * lpc[t0 + t];
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * QR_NT;
+      if (i >= m) continue;
+      z64 li;
+      if (i == p) li = mk(sq, 0.0);
+      else if (cs[i]) li = mk(0.0, 0.0);
+      else {
+        li = rs * l[r];
+        ds[i] -= abs2(li);
       }
-      Lt[(long)j * m + i] = l;
+      Lt[(long)j * m + i] = li;
     }
     __syncthreads();
-    if (tid == 0) { chosen[p] = 1; piv[j] = p; d[p] = 0; }
+    if (tid == 0) { cs[p] = 1; piv[j] = p; ds[p] = 0; }
     __syncthreads();
   }
-  if (tid == 0) state[0] = j0 + nb;
+  for (int i = tid; i < m; i += QR_NT) {
+    d[i] = ds[i];
+    chosen[i] = cs[i];
+  }
+  if (!stop && tid == 0) state[0] = j0 + nb;
 }
 
-// L11[a][b] = L(piv[a], b) for a, b < k (lower triangular in pivot order)
 // Cooperative panel: G workgroups own contiguous row slices (<= PC_RPW rows,
 // their panel entries kept in LDS); one grid-wide sync per pivot.  Candidate
 // (d, index) slots are double buffered by step parity.
@@ -387,6 +435,7 @@ size_t rowid_gram_ws(int m) {
 }
 
 int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws) {
+  LSH_REQUIRE(m <= PCH_MAXM, -6, "row ID: more than 4096 candidate rows in one level");
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t bytes) { char* r = p; p += ((bytes + 255) / 256) * 256; return (void*)r; };
   z64* M = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
@@ -410,12 +459,26 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
   double fro2 = 0;
   for (double v : dh) fro2 += v;
   const double thr2 = tol * tol * fro2;
-  const int nb = PC_NB;
+  static const int nb = [] {
+    const char* e = std::getenv("LSH_PCHOL_NB");
+    int v = e ? std::atoi(e) : 16;
+    return (v >= 4 && v <= PC_NB && v <= PCH_NB) ? v : 16;
+  }();
   int rank = 0;
-  // cooperative launch needs every workgroup resident at once
-  bool coop_ok = ceil_div(m, PC_RPW) <= 240;
+  // one-workgroup panels by default (per-pivot cost is one workgroup's L2
+  // stream of the panel, ~m * nb / 2 entries); LSH_COOP=1 selects the
+  // cooperative multi-workgroup panel (one grid sync per pivot), which
+  // profilers may fail to finalise after.
+  static const bool coop_env = [] {
+    const char* e = std::getenv("LSH_COOP");
+    return e && e[0] == '1';
+  }();
+  bool coop_ok = coop_env && ceil_div(m, PC_RPW) <= 240;
   double* cval = static_cast<double*>(take(sizeof(double) * 2 * 256));
   int* cidx = static_cast<int*>(take(sizeof(int) * 2 * 256));
+  // All panels and trailing updates are queued at once: each panel kernel
+  // returns at entry once state[1] (done) is set, and each update is skipped
+  // through the same flag, so the host reads the rank once per level.
   for (int j0 = 0; j0 < m; j0 += nb) {
     {
       ProfScope ps("pchol_panel", s, 16.0 * (double)m * nb);
@@ -431,17 +494,19 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
         else { (void)hipGetLastError(); coop_ok = false; }
       }
       if (!done)
-        hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), 0, s, M, m, d, chosen, Lt, J, j0, nb, thr2, state);
+        hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), (size_t)m * (sizeof(double) + 1), s, M, m, d, chosen,
+                           Lt, J, j0, nb, thr2, state);
     }
     LSH_LAUNCH_CHECK();
+    if (j0 + nb < m)  // trailing update of the Schur complement: M -= Lp Lp^H
+      cgemm<double>(s, m, m, nb, mk(-1.0, 0.0), Lt + (long)j0 * m, m, 0, OP_T, Lt + (long)j0 * m, m, 0, OP_R,
+                    mk(1.0, 0.0), M, m, 0, M, m, 0, 1, false, state + 1);
+  }
+  {
     int st[2];
     LSH_HIP(hipMemcpyAsync(st, state, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     rank = st[0];
-    if (st[1]) break;
-    // trailing update of the Schur complement: M -= Lp Lp^H
-    cgemm<double>(s, m, m, nb, mk(-1.0, 0.0), Lt + (long)j0 * m, m, 0, OP_T, Lt + (long)j0 * m, m, 0, OP_R,
-                  mk(1.0, 0.0), M, m, 0, M, m, 0, 1);
   }
   const int k = rank < 1 ? 1 : rank;
   // U(piv, :) = I and U(rest, :) = L(rest, 0:k) L11^{-1}: X L11 = Lr solved by

@@ -11,7 +11,11 @@
 #include <complex>
 #include <cmath>
 #include <cstring>
+#include <condition_variable>
+#include <exception>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -188,7 +192,11 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
   LSH_HIP(hipStreamSynchronize(s));
 }
 
-void plan_build(lsh_plan_s& P, hipStream_t s) {
+// Plan in three phases so that the factor can follow it level by level:
+// plan_init (weights, table, leaf geometry), plan_level(l) for l = L..0 (the
+// row ID of level l and the sibling block of parent level l, in the working
+// precision and transposed), plan_finish (the FFT spectrum).
+void plan_init(lsh_plan_s& P, hipStream_t s) {
   const lsh_desc& d = P.d;
   P.n = d.n;
   P.h = d.h;
@@ -200,8 +208,7 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
   LSH_REQUIRE(P.L < LSH_MAX_LEVELS, LSH_ERR_UNSUPPORTED, "too many levels");
   P.nleaf = 1 << P.L;
   P.mL = d.leaf * d.leaf;
-  const int w = d.proxy_width;
-  P.D = d.n + w + 1;
+  P.D = d.n + d.proxy_width + 1;
   // weights (Sec. 2.2) and the offset table
   P.st4 = correction_stencil(4, d.kappa * d.h);
   P.tau0_re = P.st4[0].re;
@@ -220,32 +227,59 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
     for (int ix = 0; ix < d.leaf; ++ix) P.leaf_pts_h.push_back(I2{ix, iy});
   P.leaf_origin = upload(P.leaf_origin_h, s);
   P.leaf_pts = upload(P.leaf_pts_h, s);
-  // compression, leaves upward (Sec. 3.2)
   P.lev.clear();
   P.lev.resize(P.L + 1);
   for (int l = 0; l <= P.L; ++l) {
     int ox, oy;
     box_of(d.n, l, 0, ox, oy, P.lev[l].sx, P.lev[l].sy);
   }
-  for (int l = P.L; l >= 1; --l) {
+  P.Gleaf64.alloc(sizeof(z64) * (size_t)P.mL * P.mL);
+  gather_table(s, P.table.as<z64>(), P.D, P.leaf_pts.as<I2>(), P.mL, P.leaf_pts.as<I2>(), P.mL, P.Gleaf64.as<z64>(),
+               P.mL);
+  if (d.hbs_prec == LSH_FP32) {
+    P.Gleaf32.alloc(sizeof(c32) * (size_t)P.mL * P.mL);
+    ccast<double, float>(s, P.Gleaf64.as<z64>(), P.Gleaf32.as<c32>(), (long)P.mL * P.mL);
+  }
+  LSH_HIP(hipStreamSynchronize(s));
+}
+
+// row ID of level l (needs level l + 1)
+void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
+  const lsh_desc& d = P.d;
+  const bool f32 = d.hbs_prec == LSH_FP32;
+  if (l >= 1) {  // row ID of level l (Sec. 3.2)
     Level& lv = P.lev[l];
     if (l == P.L) {
       lv.cand = P.leaf_pts_h;
     } else {
       lv.cand.clear();
+      int ox, oy, sx, sy;
+      box_of(d.n, l, 0, ox, oy, sx, sy);
       for (int c = 0; c < 2; ++c) {
-        int cx, cy, csx, csy, ox, oy, sx, sy;
+        int cx, cy, csx, csy;
         box_of(d.n, l + 1, c, cx, cy, csx, csy);
-        box_of(d.n, l, 0, ox, oy, sx, sy);
         const Level& ch = P.lev[l + 1];
         for (int j : ch.J) lv.cand.push_back(I2{ch.cand[j].x + cx - ox, ch.cand[j].y + cy - oy});
       }
     }
     lv.m = (int)lv.cand.size();
-    level_id(P, lv, proxy_ring(lv.sx, lv.sy, w), s);
+    level_id(P, lv, proxy_ring(lv.sx, lv.sy, d.proxy_width), s);
+    lv.Ut64.alloc(sizeof(z64) * (size_t)lv.m * lv.k);
+    ctranspose<double>(s, lv.U64.as<z64>(), lv.m, lv.k, lv.Ut64.as<z64>());
+    if (f32) {
+      lv.U32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
+      ccast<double, float>(s, lv.U64.as<z64>(), lv.U32.as<c32>(), (long)lv.m * lv.k);
+      lv.Ut32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
+      ctranspose<float>(s, lv.U32.as<c32>(), lv.m, lv.k, lv.Ut32.as<c32>());
+    }
   }
-  // sibling blocks G_ab (parent level l couples children 0 and 1 of box 0)
-  for (int l = 0; l < P.L; ++l) {
+}
+
+// sibling block of parent level l (needs the skeletons of level l + 1)
+void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
+  const lsh_desc& d = P.d;
+  const bool f32 = d.hbs_prec == LSH_FP32;
+  if (l < P.L) {  // sibling block G_ab of parent level l (eq. (sibint)): children 0 and 1 of box 0
     const Level& ch = P.lev[l + 1];
     int ax, ay, bx, by, sx, sy;
     box_of(d.n, l + 1, 0, ax, ay, sx, sy);
@@ -258,54 +292,37 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
     Level& lv = P.lev[l];
     lv.c = ch.k;
     DevBuf da = upload(ra, s), db = upload(rb, s);
-    lv.Gab64.alloc(sizeof(z64) * (size_t)lv.c * lv.c);
+    const long cc = (long)lv.c * lv.c;
+    lv.Gab64.alloc(sizeof(z64) * cc);
     gather_table(s, P.table.as<z64>(), P.D, da.as<I2>(), lv.c, db.as<I2>(), lv.c, lv.Gab64.as<z64>(), lv.c);
-    LSH_HIP(hipStreamSynchronize(s));
-  }
-  {
-    DevBuf dl = upload(P.leaf_pts_h, s);
-    P.Gleaf64.alloc(sizeof(z64) * (size_t)P.mL * P.mL);
-    gather_table(s, P.table.as<z64>(), P.D, dl.as<I2>(), P.mL, dl.as<I2>(), P.mL, P.Gleaf64.as<z64>(), P.mL);
-    LSH_HIP(hipStreamSynchronize(s));
-  }
-  if (d.hbs_prec == LSH_FP32) {
-    for (int l = 0; l <= P.L; ++l) {
-      Level& lv = P.lev[l];
-      if (l >= 1) {
-        lv.U32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
-        ccast<double, float>(s, lv.U64.as<z64>(), lv.U32.as<c32>(), (long)lv.m * lv.k);
-      }
-      if (l < P.L) {
-        lv.Gab32.alloc(sizeof(c32) * (size_t)lv.c * lv.c);
-        ccast<double, float>(s, lv.Gab64.as<z64>(), lv.Gab32.as<c32>(), (long)lv.c * lv.c);
-      }
+    lv.Gabt64.alloc(sizeof(z64) * cc);
+    ctranspose<double>(s, lv.Gab64.as<z64>(), lv.c, lv.c, lv.Gabt64.as<z64>());
+    if (f32) {
+      lv.Gab32.alloc(sizeof(c32) * cc);
+      ccast<double, float>(s, lv.Gab64.as<z64>(), lv.Gab32.as<c32>(), cc);
+      lv.Gabt32.alloc(sizeof(c32) * cc);
+      ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
     }
-    P.Gleaf32.alloc(sizeof(c32) * (size_t)P.mL * P.mL);
-    ccast<double, float>(s, P.Gleaf64.as<z64>(), P.Gleaf32.as<c32>(), (long)P.mL * P.mL);
+    LSH_HIP(hipStreamSynchronize(s));  // the staging buffers die here
   }
-  // transposed copies for the row-streamed shared products of the apply
-  for (int l = 0; l <= P.L; ++l) {
-    Level& lv = P.lev[l];
-    if (l >= 1) {
-      lv.Ut64.alloc(sizeof(z64) * (size_t)lv.m * lv.k);
-      ctranspose<double>(s, lv.U64.as<z64>(), lv.m, lv.k, lv.Ut64.as<z64>());
-      if (d.hbs_prec == LSH_FP32) {
-        lv.Ut32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
-        ctranspose<float>(s, lv.U32.as<c32>(), lv.m, lv.k, lv.Ut32.as<c32>());
-      }
-    }
-    if (l < P.L) {
-      lv.Gabt64.alloc(sizeof(z64) * (size_t)lv.c * lv.c);
-      ctranspose<double>(s, lv.Gab64.as<z64>(), lv.c, lv.c, lv.Gabt64.as<z64>());
-      if (d.hbs_prec == LSH_FP32) {
-        lv.Gabt32.alloc(sizeof(c32) * (size_t)lv.c * lv.c);
-        ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
-      }
-    }
-  }
+}
+
+void plan_level(lsh_plan_s& P, int l, hipStream_t s) {
+  plan_sibling(P, l, s);
+  plan_id(P, l, s);
+}
+
+void plan_finish(lsh_plan_s& P, hipStream_t s) {
+  const lsh_desc& d = P.d;
   // operator spectrum (order op_order)
   P.op.init(s, d.n, d.h, d.kappa, P.table.as<z64>(), P.D, correction_stencil(d.op_order, d.kappa * d.h));
   LSH_HIP(hipStreamSynchronize(s));
+}
+
+void plan_build(lsh_plan_s& P, hipStream_t s) {
+  plan_init(P, s);
+  for (int l = P.L; l >= 0; --l) plan_level(P, l, s);
+  plan_finish(P, s);
 }
 
 // ------------------------------------------------------------ factor
@@ -336,15 +353,21 @@ int check_info(const DevBuf& info, int batch, hipStream_t s) {
   return 0;
 }
 
+// Algorithm 1 in stages: factor_leaves (needs plan level L), then
+// factor_level(l) for l = L-1..0 (needs plan level l).
 template <typename R>
-void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStream_t s) {
+void factor_init(const lsh_plan_s& P, FactorData<R>& F) {
+  F.S.clear();
+  F.S.resize(P.L + 1);
+  F.Pa.clear(); F.Pb.clear(); F.Ci.clear();
+  F.Pa.resize(P.L); F.Pb.resize(P.L); F.Ci.resize(P.L);
+}
+
+template <typename R>
+void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStream_t s) {
   const int L = P.L, nleaf = P.nleaf, mL = P.mL, kL = P.lev[L].k;
   const double k2 = P.kappa * P.kappa;
-  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
-  F.S.clear();
-  F.S.resize(L + 1);
-  F.Pa.clear(); F.Pb.clear(); F.Ci.clear();
-  F.Pa.resize(L); F.Pb.resize(L); F.Ci.resize(L);
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0);
   // leaves: X = (I + B G_leaf)^{-1}, S = U^T X B U
   F.X.alloc(sizeof(cplx<R>) * (size_t)nleaf * mL * mL);
   cplx<R>* X = F.X.template as<cplx<R>>();
@@ -355,60 +378,85 @@ void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStr
     int bad = check_info(info, nleaf, s);
     LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular leaf matrix I + B G");
   }
-  {
-    DevBuf Y(sizeof(cplx<R>) * (size_t)nleaf * mL * kL), Z(sizeof(cplx<R>) * (size_t)nleaf * mL * kL);
-    leaf_scale_U<R>(s, Y.template as<cplx<R>>(), P.U<R>(L), mL, kL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(),
-                    nleaf, P.n);
-    cgemm<R>(s, mL, kL, mL, one, X, mL, (long)mL * mL, OP_N, Y.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero,
-             nullptr, 0, 0, Z.template as<cplx<R>>(), kL, (long)mL * kL, nleaf);
-    F.S[L].alloc(sizeof(cplx<R>) * (size_t)nleaf * kL * kL);
-    cgemm<R>(s, kL, kL, mL, one, P.U<R>(L), kL, 0, OP_T, Z.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero, nullptr,
-             0, 0, F.S[L].template as<cplx<R>>(), kL, (long)kL * kL, nleaf);
-    LSH_HIP(hipStreamSynchronize(s));
-  }
-  // parents, leaves upward
-  for (int l = L - 1; l >= 0; --l) {
-    const int c = P.lev[l].c, nb = 1 << l;
-    const long cc = (long)c * c;
-    const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
-    const cplx<R>* G = P.Gab<R>(l);
-    F.Pa[l].alloc(sizeof(cplx<R>) * nb * cc);
-    F.Pb[l].alloc(sizeof(cplx<R>) * nb * cc);
-    F.Ci[l].alloc(sizeof(cplx<R>) * nb * cc);
-    cplx<R>* Pa = F.Pa[l].template as<cplx<R>>();
-    cplx<R>* Pb = F.Pb[l].template as<cplx<R>>();
-    cplx<R>* Ci = F.Ci[l].template as<cplx<R>>();
-    cgemm<R>(s, c, c, c, one, Sch, c, 2 * cc, OP_N, G, c, 0, OP_N, zero, nullptr, 0, 0, Pa, c, cc, nb);
-    cgemm<R>(s, c, c, c, one, Sch + cc, c, 2 * cc, OP_N, G, c, 0, OP_T, zero, nullptr, 0, 0, Pb, c, cc, nb);
-    cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
-    {
-      DevBuf ws(inverse_ws_bytes<R>(c, nb)), info(sizeof(int) * nb);
-      inverse<R>(s, Ci, c, c, cc, nb, ws.p, info.as<int>());
-      int bad = check_info(info, nb, s);
-      LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular merge matrix I - Pb Pa at level " + std::to_string(l));
-    }
-    if (l == 0) break;
-    const int k = P.lev[l].k;
-    const long ck = (long)c * k;
-    const cplx<R>* U1 = P.U<R>(l);
-    const cplx<R>* U2 = U1 + ck;
-    DevBuf A1(sizeof(cplx<R>) * nb * ck), A2(sizeof(cplx<R>) * nb * ck), Yb(sizeof(cplx<R>) * nb * ck);
-    cplx<R>* a1 = A1.template as<cplx<R>>();
-    cplx<R>* a2 = A2.template as<cplx<R>>();
-    cplx<R>* y = Yb.template as<cplx<R>>();
-    cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a1, k, ck, nb);
-    cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a2, k, ck, nb);
-    // a2 <- A2 - Pb A1 ; y = C^{-1} a2 ; a1 <- A1 - Pa y
-    cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, a1, k, ck, OP_N, one, a2, k, ck, a2, k, ck, nb);
-    cgemm<R>(s, c, k, c, one, Ci, c, cc, OP_N, a2, k, ck, OP_N, zero, nullptr, 0, 0, y, k, ck, nb);
-    cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, y, k, ck, OP_N, one, a1, k, ck, a1, k, ck, nb);
-    F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
-    cplx<R>* S = F.S[l].template as<cplx<R>>();
-    cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a1, k, ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
-    cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, y, k, ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k, nb);
-    LSH_HIP(hipStreamSynchronize(s));
-  }
+  DevBuf Y(sizeof(cplx<R>) * (size_t)nleaf * mL * kL), Z(sizeof(cplx<R>) * (size_t)nleaf * mL * kL);
+  leaf_scale_U<R>(s, Y.template as<cplx<R>>(), P.U<R>(L), mL, kL, b, k2, P.leaf_origin.as<I2>(),
+                  P.leaf_pts.as<I2>(), nleaf, P.n);
+  cgemm<R>(s, mL, kL, mL, one, X, mL, (long)mL * mL, OP_N, Y.template as<cplx<R>>(), kL, (long)mL * kL, OP_N,
+           zero, nullptr, 0, 0, Z.template as<cplx<R>>(), kL, (long)mL * kL, nleaf);
+  F.S[L].alloc(sizeof(cplx<R>) * (size_t)nleaf * kL * kL);
+  cgemm<R>(s, kL, kL, mL, one, P.U<R>(L), kL, 0, OP_T, Z.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero,
+           nullptr, 0, 0, F.S[L].template as<cplx<R>>(), kL, (long)kL * kL, nleaf);
   LSH_HIP(hipStreamSynchronize(s));
+}
+
+// merge of parent level l: P_a, P_b, C^{-1} (needs G_ab of level l)
+template <typename R>
+void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  const int c = P.lev[l].c, nb = 1 << l;
+  const long cc = (long)c * c;
+  const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
+  const cplx<R>* G = P.Gab<R>(l);
+  F.Pa[l].alloc(sizeof(cplx<R>) * nb * cc);
+  F.Pb[l].alloc(sizeof(cplx<R>) * nb * cc);
+  F.Ci[l].alloc(sizeof(cplx<R>) * nb * cc);
+  cplx<R>* Pa = F.Pa[l].template as<cplx<R>>();
+  cplx<R>* Pb = F.Pb[l].template as<cplx<R>>();
+  cplx<R>* Ci = F.Ci[l].template as<cplx<R>>();
+  cgemm<R>(s, c, c, c, one, Sch, c, 2 * cc, OP_N, G, c, 0, OP_N, zero, nullptr, 0, 0, Pa, c, cc, nb);
+  cgemm<R>(s, c, c, c, one, Sch + cc, c, 2 * cc, OP_N, G, c, 0, OP_T, zero, nullptr, 0, 0, Pb, c, cc, nb);
+  cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
+  {
+    DevBuf ws(inverse_ws_bytes<R>(c, nb)), info(sizeof(int) * nb);
+    inverse<R>(s, Ci, c, c, cc, nb, ws.p, info.as<int>());
+    int bad = check_info(info, nb, s);
+    LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular merge matrix I - Pb Pa at level " + std::to_string(l));
+  }
+}
+
+// scattering matrices of level l (needs U_l)
+template <typename R>
+void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  if (l == 0) return;
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  const int c = P.lev[l].c, nb = 1 << l;
+  const long cc = (long)c * c;
+  const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
+  const cplx<R>* Pa = F.Pa[l].template as<cplx<R>>();
+  const cplx<R>* Pb = F.Pb[l].template as<cplx<R>>();
+  const cplx<R>* Ci = F.Ci[l].template as<cplx<R>>();
+  const int k = P.lev[l].k;
+  const long ck = (long)c * k;
+  const cplx<R>* U1 = P.U<R>(l);
+  const cplx<R>* U2 = U1 + ck;
+  DevBuf A1(sizeof(cplx<R>) * nb * ck), A2(sizeof(cplx<R>) * nb * ck), Yb(sizeof(cplx<R>) * nb * ck);
+  cplx<R>* a1 = A1.template as<cplx<R>>();
+  cplx<R>* a2 = A2.template as<cplx<R>>();
+  cplx<R>* y = Yb.template as<cplx<R>>();
+  cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a1, k, ck, nb);
+  cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a2, k, ck, nb);
+  // a2 <- A2 - Pb A1 ; y = C^{-1} a2 ; a1 <- A1 - Pa y
+  cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, a1, k, ck, OP_N, one, a2, k, ck, a2, k, ck, nb);
+  cgemm<R>(s, c, k, c, one, Ci, c, cc, OP_N, a2, k, ck, OP_N, zero, nullptr, 0, 0, y, k, ck, nb);
+  cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, y, k, ck, OP_N, one, a1, k, ck, a1, k, ck, nb);
+  F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
+  cplx<R>* S = F.S[l].template as<cplx<R>>();
+  cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a1, k, ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
+  cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, y, k, ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k, nb);
+  LSH_HIP(hipStreamSynchronize(s));  // scratch A1, A2, Y die here
+}
+
+template <typename R>
+void factor_level(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  factor_merge(P, F, l, s);
+  factor_scatter(P, F, l, s);
+}
+
+template <typename R>
+void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStream_t s) {
+  factor_init(P, F);
+  factor_leaves(P, b, F, s);
+  for (int l = P.L - 1; l >= 0; --l) factor_level(P, F, l, s);
 }
 
 template <typename R>
@@ -1013,6 +1061,119 @@ int lsh_factor_create(lsh_plan_t P, const double* b, void* stream, lsh_factor_t*
   }
   if (P->d.hbs_prec == LSH_FP32) factor_build<float>(*P, F->b.as<double>(), F->f32, s);
   else factor_build<double>(*P, F->b.as<double>(), F->f64, s);
+  *factor = F.release();
+  return LSH_OK;
+  API_END
+}
+
+// Plan and factor pipelined by level: the plan runs level by level in a host
+// thread on its own stream (its row IDs are latency-bound pivot loops), and
+// the factor of level l starts on the caller's stream as soon as plan level l
+// is recorded.
+int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* plan, lsh_factor_t* factor) {
+  API_BEGIN
+  LSH_REQUIRE(desc && b && plan && factor, LSH_ERR_INVALID_ARG, "null argument");
+  validate(*desc);
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<lsh_plan_s> P(new lsh_plan_s());
+  P->d = *desc;
+  std::unique_ptr<lsh_factor_s> F(new lsh_factor_s());
+  F->plan = P.get();
+  const long N = (long)desc->n * desc->n;
+  F->b.alloc(sizeof(double) * N);
+  LSH_HIP(hipMemcpyAsync(F->b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  {
+    DevBuf bad(sizeof(int));
+    fill_zero(s, bad.p, sizeof(int));
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
+    int hb = 0;
+    LSH_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries");
+  }
+  int dev = 0;
+  LSH_HIP(hipGetDevice(&dev));
+  hipStream_t ps = nullptr;
+  LSH_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t st;
+    ~StreamGuard() { if (st) (void)hipStreamDestroy(st); }
+  } sg{ps};
+  plan_init(*P, ps);
+  const int L = P->L;
+  std::vector<hipEvent_t> ev(2 * L + 3, nullptr);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
+  struct EventGuard {
+    std::vector<hipEvent_t>& v;
+    ~EventGuard() { for (auto e : v) if (e) (void)hipEventDestroy(e); }
+  } eg{ev};
+  for (auto& e : ev) LSH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  std::mutex mu;
+  std::condition_variable cv;
+  int doneU = L + 1, doneG = L + 1;  // lowest level with U_l / G_l ready; -2 = failed
+  bool finished = false, failed = false;
+  std::exception_ptr err;
+  std::thread th([&] {
+    try {
+      LSH_HIP(hipSetDevice(dev));
+      for (int l = L; l >= 0; --l) {
+        if (l < L) {
+          plan_sibling(*P, l, ps);
+          LSH_HIP(hipEventRecord(ev[L + 1 + l], ps));
+          { std::lock_guard<std::mutex> g(mu); doneG = l; }
+          cv.notify_all();
+        }
+        if (l >= 1) {
+          plan_id(*P, l, ps);
+          LSH_HIP(hipEventRecord(ev[l], ps));
+          { std::lock_guard<std::mutex> g(mu); doneU = l; }
+          cv.notify_all();
+        }
+      }
+      plan_finish(*P, ps);
+      LSH_HIP(hipEventRecord(ev[2 * L + 2], ps));
+      { std::lock_guard<std::mutex> g(mu); finished = true; }
+    } catch (...) {
+      std::lock_guard<std::mutex> g(mu);
+      err = std::current_exception();
+      failed = true;
+    }
+    cv.notify_all();
+  });
+  // wait until U_l (kind 0) or G_l (kind 1) exists; false if the plan failed
+  auto wait_for = [&](int l, int kind) -> bool {
+    std::unique_lock<std::mutex> g(mu);
+    cv.wait(g, [&] { return failed || finished || (kind ? doneG : doneU) <= l; });
+    return !failed;
+  };
+  std::exception_ptr ferr;
+  try {
+    auto run = [&](auto& FD) {
+      factor_init(*P, FD);
+      if (!wait_for(L, 0)) return;
+      LSH_HIP(hipStreamWaitEvent(s, ev[L], 0));
+      factor_leaves(*P, F->b.template as<double>(), FD, s);
+      for (int l = L - 1; l >= 0; --l) {
+        if (!wait_for(l, 1)) return;  // G_l: the merge overlaps the row ID of level l
+        LSH_HIP(hipStreamWaitEvent(s, ev[L + 1 + l], 0));
+        factor_merge(*P, FD, l, s);
+        if (l >= 1) {
+          if (!wait_for(l, 0)) return;
+          LSH_HIP(hipStreamWaitEvent(s, ev[l], 0));
+          factor_scatter(*P, FD, l, s);
+        }
+      }
+    };
+    if (desc->hbs_prec == LSH_FP32) run(F->f32);
+    else run(F->f64);
+  } catch (...) {
+    ferr = std::current_exception();
+  }
+  th.join();
+  if (err) std::rethrow_exception(err);
+  if (ferr) std::rethrow_exception(ferr);
+  LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 2], 0));
+  LSH_HIP(hipStreamSynchronize(s));
+  *plan = P.release();
   *factor = F.release();
   return LSH_OK;
   API_END

@@ -208,7 +208,7 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
 
 void ConvOperator::apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs, bool transpose) {
   // algorithmic bytes: read x (and b), write y, read the spectrum once
-  ProfScope ps("fft_operator", s, (double)nrhs * (16.0 * 2 * n * n + (b ? 8.0 * n * n : 0.0)) + 16.0 * M * M);
+  ProfScope ps("op_fft_operator", s, (double)nrhs * (16.0 * 2 * n * n + (b ? 8.0 * n * n : 0.0)) + 16.0 * M * M);
   z64* W1 = w1.as<z64>();
   z64* W2 = w2.as<z64>();
   const size_t lds = M * sizeof(z64);
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const z64* partial, int
 size_t multidot_partial_bytes(int nv) { return sizeof(z64) * (size_t)nv * MD_BLOCKS; }
 
 void multidot(hipStream_t s, const z64* V, long ldv, int nv, const z64* w, long N, z64* out, z64* partial) {
-  ProfScope ps("multidot", s, 16.0 * (double)N * (nv + 1));
+  ProfScope ps("op_multidot", s, 16.0 * (double)N * (nv + 1));
   LSH_REQUIRE(nv <= MD_MAXV, -6, "multidot: too many vectors");
   hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS), dim3(MD_NT), 0, s, V, ldv, nv, w, N, partial);
   LSH_LAUNCH_CHECK();

@@ -1,6 +1,7 @@
 // Per-kernel hipEvent timing (off by default): each instrumented launch
 // records a start/stop event pair on its own stream plus the launch's
-// algorithmic work (flops or bytes, as the launcher defines it).
+// algorithmic work (flops or bytes, as the launcher defines it).  Names that
+// start with "op_" cover a composite operation (several kernels).
 #pragma once
 #include <hip/hip_runtime.h>
 

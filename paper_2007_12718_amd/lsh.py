@@ -26,7 +26,7 @@ EXPORTED = [
     "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
     "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
-    "lsh_eval_points_adjoint", "lsh_grad_b",
+    "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build",
 ]
 
 
@@ -75,6 +75,7 @@ def lib():
         L.lsh_plan_table.argtypes = [c_void_p, POINTER(c_int), c_void_p, c_void_p]
         L.lsh_factor_create.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]
         L.lsh_factor_destroy.argtypes = [c_void_p]
+        L.lsh_build.argtypes = [POINTER(LshDesc), c_void_p, c_void_p, POINTER(c_void_p), POINTER(c_void_p)]
         L.lsh_apply_precond.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p]
         L.lsh_apply_operator.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
         L.lsh_solve.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p, POINTER(LshSolveOpts),
@@ -136,7 +137,7 @@ class Plan:
     """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
 
     def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
-                 h=None, x0=-0.5, y0=-0.5):
+                 h=None, x0=-0.5, y0=-0.5, _create=True):
         self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
                             op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
                             hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64)
@@ -144,7 +145,8 @@ class Plan:
         self.h = self.desc.h
         self.kappa = kappa
         self.handle = c_void_p()
-        _check(lib().lsh_plan_create(ctypes.byref(self.desc), _stream(), ctypes.byref(self.handle)))
+        if _create:
+            _check(lib().lsh_plan_create(ctypes.byref(self.desc), _stream(), ctypes.byref(self.handle)))
 
     def close(self):
         if self.handle:
@@ -237,10 +239,13 @@ class Plan:
 class Factor:
     """lsh_factor_create: Algorithm 1 for the potential b (float64, (n, n), device)."""
 
-    def __init__(self, plan: Plan, b):
+    def __init__(self, plan: Plan, b, _handle=None):
         import torch
         self.plan = plan
         self.handle = c_void_p()
+        if _handle is not None:
+            self.handle = _handle
+            return
         b = b.reshape(plan.n, plan.n).contiguous()
         _check(lib().lsh_factor_create(plan.handle, _ptr(b, torch.float64), _stream(), ctypes.byref(self.handle)))
 
@@ -289,6 +294,17 @@ class Factor:
                                             ctypes.byref(opts), ctypes.byref(info), _stream()),
                     allow_not_converged=True)
         return lam, info, rc
+
+
+def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5):
+    """lsh_build: plan and factor pipelined by level; returns (Plan, Factor)."""
+    import torch
+    P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, _create=False)
+    fh = c_void_p()
+    b = b.reshape(n, n).contiguous()
+    _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), _stream(), ctypes.byref(P.handle),
+                           ctypes.byref(fh)))
+    return P, Factor(P, None, _handle=fh)
 
 
 def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None):

@@ -46,13 +46,15 @@ def test_gemm_shared_operand_and_large_batch():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("c", [1, 7, 64, 90, 131, 300, 1100])
+@pytest.mark.parametrize("c", [1, 7, 64, 90, 131, 300, 1100, 2100, 3077])
 def test_inverse_matches_definition(prec, c):
+    """Sizes span the LDS path, one slab, several slabs with a ragged last
+    slab and panel, and one to four rows per thread in the panel kernel."""
     import torch
     from paper_2007_12718_amd import lsh
     rng = np.random.default_rng(c)
     dt = np.complex128 if prec == "fp64" else np.complex64
-    B = 3
+    B = 3 if c < 2000 else 2
     A = _rand((B, c, c), rng, np.complex128) / np.sqrt(c) + 2 * np.eye(c)
     A[1] = A[1][rng.permutation(c)]  # needs row pivoting
     Ai, info = lsh.dev_inverse(torch.from_numpy(A.astype(dt)).cuda())
@@ -71,3 +73,23 @@ def test_inverse_reports_singular():
     A[1, 5, 5] = 0
     _, info = lsh.dev_inverse(torch.from_numpy(A).cuda())
     assert info.cpu().tolist()[0] == 0 and info.cpu().tolist()[1] == 6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_inverse_reports_singular_blocked(prec):
+    """A zero column stays zero under every elimination step, so the first
+    zero pivot is at that column (1-based in info).  The singular matrix
+    comes first in the batch: the following matrix, stored right after it,
+    must come out exact (no write outside the singular matrix's rows)."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    rng = np.random.default_rng(5)
+    c = 200
+    A = _rand((2, c, c), rng, np.complex128) / np.sqrt(c) + 2 * np.eye(c)
+    A[0, :, 150] = 0
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    Ai, info = lsh.dev_inverse(torch.from_numpy(A.astype(dt)).cuda())
+    assert info.cpu().tolist() == [151, 0]
+    ref = np.linalg.inv(A[1])
+    tol = 1e-12 if prec == "fp64" else 5e-5
+    assert np.abs(Ai[1].cpu().numpy() - ref).max() <= tol * np.abs(ref).max() * 4

@@ -194,3 +194,21 @@ def test_eval_points_matches_oracle():
     E = dense.receiver_matrix(n, kappa, pts)
     ref = sig.reshape(3, -1) @ E.T
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pipelined_build_equals_separate_calls(prec):
+    """lsh_build (plan and factor overlapped by level) computes exactly what
+    lsh_plan_create + lsh_factor_create compute."""
+    from paper_2007_12718_amd import lsh
+    n, kappa = 64, 2 * np.pi * 6
+    b = synth.bumps(n, np.random.default_rng(9))
+    P1 = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
+    F1 = lsh.Factor(P1, cuda(b))
+    P2, F2 = lsh.build(n, kappa, cuda(b), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
+    assert P1.ranks() == P2.ranks()
+    x = np.random.default_rng(1).standard_normal((1, n, n)) + 0j
+    assert np.array_equal(F1.apply_precond(cuda(x)).cpu().numpy(), F2.apply_precond(cuda(x)).cpu().numpy())
+    s1 = F1.solve(cuda(synth.plane_wave(n, kappa)[None]), tol=1e-12)[0].cpu().numpy()
+    s2 = F2.solve(cuda(synth.plane_wave(n, kappa)[None]), tol=1e-12)[0].cpu().numpy()
+    assert np.array_equal(s1, s2)
