@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-HBS comparison form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=256, help="grid side of the oracle's timed sample")
+    ap.add_argument("--cpu-n", type=int, default=512, help="grid side of the oracle's timed sample")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel hipEvent records")
     ap.add_argument("--separate", action="store_true",
                     help="lsh_plan_create + lsh_factor_create instead of the pipelined lsh_build")

@@ -3,6 +3,7 @@
 // Complex products run on the real matrix cores: each complex k-step is four
 // real 16x16x4 MFMAs (Re += ArBr - AiBi, Im += ArBi + AiBr) on LDS-staged
 // 64x64 tiles; four 64-wide wavefronts each own a 32x32 quarter of the tile.
+#include <cmath>
 #include <cstdlib>
 
 #include "blas.hpp"
@@ -193,6 +194,173 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
       }
 }
 
+// FP32 variant on the 32x32x2 matrix instruction (the higher-throughput FP32
+// shape): 2 x 2 wavefronts, each owning WM x WN blocks of 32 x 32 outputs, so
+// the workgroup tile is (64 WM) x (64 WN), K advancing 16 per LDS tile.  The
+// sum over k inside one instruction does not care which k each lane group
+// supplies, so lane group g (lanes 32g .. 32g+31) takes k = 8g + s at step s:
+// each lane then reads its operands for four steps with one 16-byte LDS load
+// per plane.  Row stride 20 floats keeps those loads free of bank conflicts.
+// Accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+constexpr int X32_LDK = GBK + 4;
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {
+  typedef float f16v __attribute__((ext_vector_type(16)));
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  constexpr int BM = 64 * WM, BN = 64 * WN;
+  constexpr int EA = BM * GBK / 256, EB = BN * GBK / 256;
+  if (P.skip && *P.skip) return;  // uniform across the launch
+  __shared__ __align__(16) float sAr[BM][X32_LDK], sAi[BM][X32_LDK];
+  __shared__ __align__(16) float sBr[BN][X32_LDK], sBi[BN][X32_LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int g = lane >> 5, l32 = lane & 31;
+  // XCD-aware tile order (see k_cgemm)
+  const long T = (long)gridDim.x * gridDim.y * gridDim.z;
+  long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+  const long T8 = (T / 8) * 8;
+  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
+  const int tn = (int)(L % gridDim.x);
+  const int tm = (int)((L / gridDim.x) % gridDim.y);
+  const long b = L / ((long)gridDim.x * gridDim.y);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const cplx<float>* A = P.A + b * P.sA;
+  const cplx<float>* B = P.B + b * P.sB;
+  const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
+  const bool aC = (P.opA == OP_C || P.opA == OP_R), bC = (P.opB == OP_C || P.opB == OP_R);
+  f16v cr[WM][WN], ci[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0; ci[i][j][r] = 0; }
+  cplx<float> ra[EA], rb[EB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      int m, k;
+      if (aN) { m = idx / GBK; k = idx % GBK; }
+      else { k = idx / BM; m = idx % BM; }
+      const int gm = m0 + m, gk = k0 + k;
+      cplx<float> v = mk<float>(0, 0);
+      if (gm < P.M && gk < P.K) v = aN ? A[(long)gm * P.lda + gk] : A[(long)gk * P.lda + gm];
+      if (aC) v.y = -v.y;
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      int n, k;
+      if (bN) { k = idx / BN; n = idx % BN; }
+      else { n = idx / GBK; k = idx % GBK; }
+      const int gn = n0 + n, gk = k0 + k;
+      cplx<float> v = mk<float>(0, 0);
+      if (gn < P.N && gk < P.K) v = bN ? B[(long)gk * P.ldb + gn] : B[(long)gn * P.ldb + gk];
+      if (bC) v.y = -v.y;
+      rb[e] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + e * 256;
+      int m, k;
+      if (aN) { m = idx / GBK; k = idx % GBK; }
+      else { k = idx / BM; m = idx % BM; }
+      sAr[m][k] = ra[e].x;
+      sAi[m][k] = ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + e * 256;
+      int n, k;
+      if (bN) { k = idx / BN; n = idx % BN; }
+      else { n = idx / GBK; k = idx % GBK; }
+      sBr[n][k] = rb[e].x;
+      sBi[n][k] = rb[e].y;
+    }
+  };
+  load(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < P.K; k0 += GBK) {
+    const bool more = k0 + GBK < P.K;
+    if (more) load(k0 + GBK);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // two halves of four k steps
+      f4v ar[WM], ai[WM], nai[WM], br[WN], bi[WN];
+      const int kq = 8 * g + 4 * h;
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int row = wm * 32 * WM + i * 32 + l32;
+        ar[i] = *reinterpret_cast<const f4v*>(&sAr[row][kq]);
+        ai[i] = *reinterpret_cast<const f4v*>(&sAi[row][kq]);
+        nai[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int col = wn * 32 * WN + j * 32 + l32;
+        br[j] = *reinterpret_cast<const f4v*>(&sBr[col][kq]);
+        bi[j] = *reinterpret_cast<const f4v*>(&sBi[col][kq]);
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st], br[j][st], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st], bi[j][st], ci[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(nai[i][st], bi[j][st], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i][st], br[j][st], ci[i][j], 0, 0, 0);
+          }
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+  cplx<float>* C = P.C + b * P.sC;
+  const cplx<float>* D = P.D ? P.D + b * P.sD : nullptr;
+  const bool useD = D && (P.beta.x != 0.f || P.beta.y != 0.f);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm * 32 * WM + i * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+        const int n = n0 + wn * 32 * WN + j * 32 + l32;
+        if (m < P.M && n < P.N) {
+          cplx<float> v = P.alpha * mk<float>(cr[i][j][r], ci[i][j][r]);
+          if (useD) v = v + P.beta * D[(long)m * P.ldd + n];
+          if (P.addI && m == n) v.x += 1.f;
+          C[(long)m * P.ldc + n] = v;
+        }
+      }
+}
+
+template <int WM, int WN>
+static void launch_gemm_x32(hipStream_t s, const GemmP<float>& P, const cplx<float>* A, const cplx<float>* B,
+                            const cplx<float>* D, cplx<float>* C, long sA, long sB, long sD, long sC, int batch) {
+  constexpr int BM = 64 * WM, BN = 64 * WN;
+  const char* name = BM == 128 ? (BN == 128 ? "cgemm_f32_128x128" : "cgemm_f32_128x64") : "cgemm_f32_64x64";
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb);
+    GemmP<float> Q = P;
+    Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
+    if (D) Q.D = D + b0 * sD;
+    dim3 grid(ceil_div(P.N, BN), ceil_div(P.M, BM), nb);
+    hipLaunchKernelGGL((k_cgemm_x32<WM, WN>), grid, dim3(256), 0, s, Q);
+    LSH_LAUNCH_CHECK();
+  }
+}
+
 template <typename R, int WM, int WN>
 static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, const cplx<R>* B, const cplx<R>* D,
                         cplx<R>* C, long sA, long sB, long sD, long sC, int batch) {
@@ -211,6 +379,33 @@ static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, cons
   }
 }
 
+// FP32 tile choice by a wave-quantisation model: a launch takes
+// ceil(tiles / (256 CUs x resident workgroups per CU)) rounds, and a full
+// round costs (resident workgroups x tile area) / (per-CU efficiency of that
+// tile).  Residency and efficiency per tile come from the register/LDS budget
+// and a sweep of square and batched shapes (128x128: 2 resident, 128x64: 3,
+// 64x64: 5).  LSH_GEMM_TILE=0/1/2 forces a tile.
+struct TileModel { int bm, bn, resident; double eff; };
+static const TileModel kF32Tiles[3] = {{128, 128, 2, 0.56}, {128, 64, 3, 0.63}, {64, 64, 5, 0.64}};
+
+static int f32_tile(int M, int N, int batch) {
+  static const int forced = [] {
+    const char* e = getenv("LSH_GEMM_TILE");
+    return e ? atoi(e) : -1;
+  }();
+  if (forced >= 0 && forced <= 2) return forced;
+  int best = 2;
+  double bt = 1e300;
+  for (int t = 0; t < 3; ++t) {
+    const TileModel& tm = kF32Tiles[t];
+    const double tiles = (double)ceil_div(M, tm.bm) * ceil_div(N, tm.bn) * batch;
+    const double rounds = std::ceil(tiles / (256.0 * tm.resident));
+    const double cost = rounds * tm.resident * tm.bm * tm.bn / tm.eff;
+    if (cost < bt * 0.999) { bt = cost; best = t; }
+  }
+  return best;
+}
+
 template <typename R>
 void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            const cplx<R>* A, long lda, long sA, Op opA,
@@ -227,11 +422,15 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
   P.C = C; P.ldc = ldc; P.sC = sC; P.addI = add_identity ? 1 : 0;
   // large tiles when they still leave a few waves of workgroups in flight
   const double big_tiles = (double)ceil_div(M, 128) * ceil_div(N, sizeof(R) == 4 ? 128 : 64) * batch;
-  if (M >= 128 && N >= 64 && K >= 32 && big_tiles >= 128) {
-    if (sizeof(R) == 4) launch_gemm<R, 4, 4>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
-    else launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+  if constexpr (sizeof(R) == 4) {
+    switch (f32_tile(M, N, batch)) {
+      case 0: launch_gemm_x32<2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch); break;
+      case 1: launch_gemm_x32<2, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch); break;
+      default: launch_gemm_x32<1, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch); break;
+    }
   } else {
-    launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    if (M >= 128 && N >= 64 && K >= 32 && big_tiles >= 128) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
 }
 

@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <vector>
+
 #include "hbs.hpp"
+#include "ops.hpp"
 #include "prof.hpp"
 
 namespace lsh {
@@ -425,6 +428,543 @@ __global__ void k_scatter_U(z64* U, int k, const int* piv, const int* rest, int 
   const int row = (int)(e / k), b = (int)(e % k);
   if (row < k) U[(long)piv[row] * k + b] = mk(row == b ? 1.0 : 0.0, 0.0);
   else U[(long)rest[row - k] * k + b] = X[(long)(row - k) * k + b];
+}
+
+// ------------------------------------ block-pivoted left-looking Cholesky
+// The panels above take one pivot per workgroup-wide step and keep the whole
+// Schur complement M - L L^H up to date (a rank-nb update of all m x m
+// entries per panel).  The block variant below takes up to BP_NP pivots per
+// step and never forms the trailing Schur complement:
+//  1. candidates C = the BP_B unchosen rows with the largest Schur diagonal
+//     d_i (radix selection), and dout = the largest d_i outside C;
+//  2. S_C = M[C,C] - L[C,:] L[C,:]^H;
+//  3. greedy pivoted Cholesky of S_C in one workgroup: pivots P, factor L_PP
+//     and its inverse;
+//  4. the new columns L[:, P] = (M[:, P] - L L[P,:]^H) L_PP^{-H} and
+//     d_i -= |L[i, P]|^2.
+// Step 3 stops before a pivot whose Schur diagonal falls below dout:
+// diagonals only decrease, so every pivot taken is the greedy pivot over all
+// rows, and the pivot sequence, the stopping point and the rank are those of
+// one-at-a-time greedy pivoting (up to ties).  All step state (rank so far,
+// pivot count, done flag) lives on the device: the host queues steps in
+// batches and reads the done flag once per batch; a step queued after the
+// end returns at entry.
+constexpr int BP_B = 48, BP_NP = 32, BP_KC = 64, BP_SUB = 32, BP_SEL = 4096;
+// state words (int): 0 rank j, 1 done, 2 pivots of this step, 3 candidates,
+// 4..5 dout (double), 6 error flag, 8..8+BP_B candidate rows
+constexpr int BPS_J = 0, BPS_DONE = 1, BPS_NP = 2, BPS_NC = 3, BPS_DOUT = 4, BPS_ERR = 6, BPS_CAND = 8,
+              BPS_WORDS = 128;
+static_assert(BPS_CAND + BP_B <= BPS_WORDS - 4, "candidate rows overflow the step state");
+
+__device__ __forceinline__ unsigned long long bp_key(double d, int i) {
+  return d > 0.0 ? (((unsigned long long)__double_as_longlong(d) & ~0xFFFull) | (unsigned)(0xFFF - i)) : 0ull;
+}
+
+// Candidates: the BP_B largest keys (unchosen rows, d > 0) by an 8-pass
+// most-significant-digit radix selection of the BP_B-th largest key, then
+// the <= BP_B keys at or above it, sorted descending.
+__global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* chosen, int m, double thr2,
+                                                    int* st) {
+  __shared__ unsigned int hist[256];
+  __shared__ unsigned long long s_prefix, s_mask;
+  __shared__ int s_rank, s_cnt;
+  __shared__ unsigned long long ck[64];
+  __shared__ unsigned long long s_below;
+  if (st[BPS_DONE]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the previous step's pivots join the rank here (every later kernel of
+  // this step reads the rank after this kernel has ended)
+  {
+    const int jn = st[BPS_J] + st[BPS_NP];
+    __syncthreads();
+    if (tid == 0) {
+      st[BPS_J] = jn;
+      st[BPS_NP] = 0;
+      if (jn >= m) st[BPS_DONE] = 1;
+    }
+    if (jn >= m) return;
+  }
+  unsigned long long key[BP_SEL / 1024];
+  int nz = 0;
+#pragma unroll
+  for (int r = 0; r < BP_SEL / 1024; ++r) {
+    const int i = tid + r * 1024;
+    key[r] = (i < m && !chosen[i]) ? bp_key(d[i], i) : 0ull;
+    nz += key[r] != 0;
+  }
+  if (tid == 0) { s_prefix = 0; s_mask = 0; s_rank = BP_B; s_cnt = 0; s_below = 0; }
+  // total nonzero keys: when at most BP_B, every one is a candidate
+  for (int off = 32; off > 0; off >>= 1) nz += __shfl_xor(nz, off);
+  __shared__ int wz[16];
+  if (lane == 0) wz[wave] = nz;
+  __syncthreads();
+  int total = 0;
+  for (int w = 0; w < 16; ++w) total += wz[w];
+  unsigned long long thr = 1;  // keys >= thr are candidates
+  if (total > BP_B) {
+    for (int pass = 7; pass >= 0; --pass) {
+      const int sh = 8 * pass;
+      for (int b = tid; b < 256; b += 1024) hist[b] = 0;
+      __syncthreads();
+      const unsigned long long pre = s_prefix, msk = s_mask;
+#pragma unroll
+      for (int r = 0; r < BP_SEL / 1024; ++r)
+        if (key[r] && (key[r] & msk) == pre) atomicAdd(&hist[(key[r] >> sh) & 255], 1u);
+      __syncthreads();
+      if (wave == 0) {
+        // bins from the top: lane l holds bins 255-4l .. 252-4l
+        unsigned int c[4], sum = 0;
+        for (int q = 0; q < 4; ++q) { c[q] = hist[255 - 4 * lane - q]; sum += c[q]; }
+        unsigned int inc = sum;  // inclusive prefix over lanes
+        for (int off = 1; off < 64; off <<= 1) {
+          const unsigned int o = __shfl_up(inc, off);
+          if (lane >= off) inc += o;
+        }
+        const unsigned int exc = inc - sum;
+        const int rank = s_rank;
+        if ((int)exc < rank && rank <= (int)inc) {
+          unsigned int run = exc;
+          for (int q = 0; q < 4; ++q) {
+            if (rank <= (int)(run + c[q])) {
+              const unsigned long long digit = 255 - 4 * lane - q;
+              s_prefix = pre | (digit << sh);
+              s_mask = msk | (255ull << sh);
+              s_rank = rank - (int)run;
+              break;
+            }
+            run += c[q];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    thr = s_prefix;
+  }
+  // gather the candidates and the largest key below them
+  unsigned long long below = 0;
+#pragma unroll
+  for (int r = 0; r < BP_SEL / 1024; ++r) {
+    if (key[r] >= thr && key[r]) {
+      const int slot = atomicAdd(&s_cnt, 1);
+      if (slot < 64) ck[slot] = key[r];
+    } else if (key[r] > below) {
+      below = key[r];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(below, off);
+    below = o > below ? o : below;
+  }
+  if (lane == 0) atomicMax(&s_below, below);
+  __syncthreads();
+  if (wave == 0) {
+    const int cnt = s_cnt < BP_B ? s_cnt : BP_B;
+    unsigned long long k = lane < cnt ? ck[lane] : 0ull;
+    // bitonic sort of 64 keys across the wave, descending
+    for (int size = 2; size <= 64; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const unsigned long long o = __shfl_xor(k, stride);
+        const bool up = (lane & size) == 0;  // descending blocks
+        const bool lower = (lane & stride) == 0;
+        const bool takeMax = (up == lower);
+        k = takeMax ? (o > k ? o : k) : (o < k ? o : k);
+      }
+    const int row = k ? 0xFFF - (int)(k & 0xFFF) : -1;
+    if (lane < BP_B) st[BPS_CAND + lane] = row;
+    int valid = (lane < BP_B && row >= 0 && d[row] > thr2) ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) valid += __shfl_xor(valid, off);
+    if (lane == 0) {
+      st[BPS_NC] = valid;
+      const unsigned long long kb = s_below;
+      reinterpret_cast<double*>(st + BPS_DOUT)[0] = kb ? d[0xFFF - (int)(kb & 0xFFF)] : 0.0;
+      if (valid == 0) st[BPS_DONE] = 1;
+    }
+  }
+}
+
+// S_C partial sums over depth chunk c (BP_KC deep, staged BP_SUB at a time):
+// part[c][a][b] = sum_{t in chunk, t < j} L(C_a, t) conj(L(C_b, t)).
+__global__ __launch_bounds__(256) void k_bp_sc(const z64* Lt, int m, const int* st, z64* part) {
+  __shared__ z64 Lc[BP_SUB][BP_B + 1];
+  constexpr int PER = BP_B * BP_B / 256;
+  if (st[BPS_DONE]) return;
+  const int j = st[BPS_J], nc = st[BPS_NC];
+  const int c = blockIdx.x, t0 = c * BP_KC;
+  if (t0 >= j) return;
+  const int tid = threadIdx.x;
+  const int* cand = st + BPS_CAND;
+  z64 acc[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) acc[r] = mk(0.0, 0.0);
+  const int tend = (j - t0) < BP_KC ? j : t0 + BP_KC;
+  for (int s0 = t0; s0 < tend; s0 += BP_SUB) {
+    __syncthreads();
+    for (int e = tid; e < BP_SUB * BP_B; e += 256) {
+      const int t = e / BP_B, a = e % BP_B;
+      Lc[t][a] = (a < nc && s0 + t < tend) ? Lt[(long)(s0 + t) * m + cand[a]] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + r * 256, a = e / BP_B, b = e % BP_B;
+      z64 v = acc[r];
+      for (int t = 0; t < BP_SUB; ++t) v = v + Lc[t][a] * conjg(Lc[t][b]);
+      acc[r] = v;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) part[(long)c * BP_B * BP_B + tid + r * 256] = acc[r];
+}
+
+// Greedy pivoted Cholesky of the candidate block S (first nc rows valid)
+// while the pivot exceeds thr2 and, after the first, is not below dout; at
+// most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
+// pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
+// pivot qualifies.
+__global__ __launch_bounds__(256) void k_bp_chol(const z64* M, int m, const z64* part, double thr2, int* J, int* st,
+                                                 z64* Lpp, z64* Linv) {
+  __shared__ z64 S[BP_B][BP_B + 1];
+  __shared__ z64 Lb[BP_B][BP_NP];  // Cholesky columns for every candidate row
+  __shared__ int piv[BP_NP];
+  __shared__ int picked[BP_B];
+  __shared__ int s_p, s_np;
+  __shared__ double s_d;
+  if (st[BPS_DONE]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nc = st[BPS_NC], j = st[BPS_J];
+  const double dout = reinterpret_cast<const double*>(st + BPS_DOUT)[0];
+  const int* cand = st + BPS_CAND;
+  // S_C = M[C,C] - (sum of the depth-chunk partial products)
+  const int nch = (j + BP_KC - 1) / BP_KC;
+  for (int e = tid; e < BP_B * BP_B; e += 256) {
+    const int a = e / BP_B, b = e % BP_B;
+    z64 v = mk(0.0, 0.0);
+    if (a < nc && b < nc) {
+      v = M[(long)cand[a] * m + cand[b]];
+      for (int c = 0; c < nch; ++c) v = v - part[(long)c * BP_B * BP_B + e];
+    }
+    S[a][b] = v;
+  }
+  for (int a = tid; a < BP_B; a += 256) picked[a] = 0;
+  for (int e = tid; e < BP_B * BP_NP; e += 256) Lb[e / BP_NP][e % BP_NP] = mk(0.0, 0.0);
+  if (tid == 0) s_np = 0;
+  __syncthreads();
+  for (int t = 0; t < BP_NP; ++t) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = BP_B;
+      if (lane < nc && !picked[lane]) { best = S[lane][lane].x; bi = lane; }
+      wave_argmax_d(best, bi);
+      if (lane == 0) {
+        s_p = bi;
+        s_d = best;
+        // rows outside the block have Schur diagonal <= dout (diagonals only
+        // decrease), so while best >= dout this is the greedy pivot of all rows
+        if (best > thr2 && bi < nc && (t == 0 || best >= dout)) {
+          picked[bi] = 1;
+          piv[t] = bi;
+          s_np = t + 1;
+        }
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double dp = s_d;
+    if (!(dp > thr2) || p >= nc || (t > 0 && dp < dout)) break;
+    const double lpp = sqrt(dp), rl = 1.0 / lpp;
+    // column t and the Schur update read only row/column p, which neither writes
+    for (int a = tid; a < nc; a += 256)
+      if (a == p || !picked[a]) Lb[a][t] = a == p ? mk(lpp, 0.0) : rl * S[a][p];
+    for (int e = tid; e < nc * nc; e += 256) {
+      const int a = e / nc, b = e % nc;
+      if (a != p && b != p) S[a][b] = S[a][b] - (rl * S[a][p]) * conjg(rl * S[b][p]);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int np = s_np;
+  for (int e = tid; e < BP_NP * BP_NP; e += 256) {
+    const int q = e / BP_NP, r = e % BP_NP;
+    Lpp[e] = (q < np && r <= q) ? Lb[piv[q]][r] : mk(0.0, 0.0);
+  }
+  // Linv = Lpp^{-1}: forward substitution, one column per thread, in LDS
+  // (reusing the storage of S, no longer read)
+  __syncthreads();
+  static_assert(BP_NP * (BP_NP + 1) <= BP_B * (BP_B + 1), "S too small for Linv");
+  z64(*Xs)[BP_NP + 1] = reinterpret_cast<z64(*)[BP_NP + 1]>(&S[0][0]);
+  if (tid < BP_NP) {
+    const int c = tid;
+    for (int q = 0; q < BP_NP; ++q) {
+      z64 v = mk(0.0, 0.0);
+      if (q >= c && q < np && c < np) {
+        z64 acc = q == c ? mk(1.0, 0.0) : mk(0.0, 0.0);
+        for (int r = c; r < q; ++r) acc = acc - Lb[piv[q]][r] * Xs[r][c];
+        v = acc * crecip(Lb[piv[q]][q]);
+      }
+      Xs[q][c] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < BP_NP * BP_NP; e += 256) Linv[e] = Xs[e / BP_NP][e % BP_NP];
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (tid < np) {
+    const int row = cand[piv[tid]];
+    if (row < 0 || row >= m) s_bad = 1;  // (cannot happen: candidates are rows)
+    J[j + tid] = row;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st[BPS_NP] = s_bad ? 0 : np;
+    if (np == 0 || s_bad) st[BPS_DONE] = 1;
+    if (s_bad) st[BPS_ERR] = 1;
+  }
+}
+
+// Wt partial sums over depth chunk c (BP_KC deep): part[c][q][i] =
+// sum_{t in chunk, t < j} conj(L(P_q, t)) L(i, t) for q < np.  Thread per
+// unchosen row i (chosen rows get zeros later); the pivot rows' values in
+// LDS, 2 BP_SUB depths at a time; NQ accumulators (the pivot count rounded
+// up to a multiple of 8).
+template <int NQ>
+__device__ __forceinline__ void bp_wt_body(const z64* Lt, const int* Pq, int m, int j, int np, int c, bool live,
+                                           int i, z64 (*Lp)[BP_NP], z64* part) {
+  const int tid = threadIdx.x, t0 = c * BP_KC;
+  z64 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = mk(0.0, 0.0);
+  const int tend = (j - t0) < BP_KC ? j : t0 + BP_KC;
+  for (int s0 = t0; s0 < tend; s0 += 2 * BP_SUB) {
+    __syncthreads();
+    for (int e = tid; e < 2 * BP_SUB * NQ; e += 256) {
+      const int t = e / NQ, q = e % NQ;
+      Lp[t][q] = (q < np && s0 + t < tend) ? conjg(Lt[(long)(s0 + t) * m + Pq[q]]) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (live) {
+      const int tn = (tend - s0) < 2 * BP_SUB ? (tend - s0) : 2 * BP_SUB;
+      for (int t = 0; t < tn; ++t) {
+        const z64 l = Lt[(long)(s0 + t) * m + i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + Lp[t][q] * l;
+      }
+    }
+  }
+  if (!live) return;
+  z64* pc = part + (long)c * BP_NP * m;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (q < np) pc[(long)q * m + i] = acc[q];
+}
+
+__global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, const int* chosen, int m, const int* st,
+                                               z64* part) {
+  __shared__ z64 Lp[BP_SUB * 2][BP_NP];
+  if (st[BPS_DONE]) return;
+  const int j = st[BPS_J], np = st[BPS_NP];
+  const int c = blockIdx.y;
+  if (c * BP_KC >= j) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool live = i < m && !chosen[i];
+  const int* Pq = J + j;
+  if (np <= 8) bp_wt_body<8>(Lt, Pq, m, j, np, c, live, i, Lp, part);
+  else if (np <= 16) bp_wt_body<16>(Lt, Pq, m, j, np, c, live, i, Lp, part);
+  else if (np <= 24) bp_wt_body<24>(Lt, Pq, m, j, np, c, live, i, Lp, part);
+  else bp_wt_body<32>(Lt, Pq, m, j, np, c, live, i, Lp, part);
+}
+
+// New factor rows Lt[j+q][i] = sum_q' conj(Linv[q][q']) W[q'][i] with
+// W[q'][i] = conj(M[P_q'][i]) - sum_c part[c][q'][i]; then rows already
+// chosen get exact zeros, the pivot rows get Lpp exactly, other rows have
+// their Schur diagonal reduced, and the pivots are marked chosen.
+__global__ __launch_bounds__(256) void k_bp_newcols(z64* Lt, const z64* M, int m, const int* J, const z64* part,
+                                                    const z64* Lpp, const z64* Linv, int* chosen, double* d,
+                                                    const int* st) {
+  __shared__ z64 Li[BP_NP][BP_NP];
+  if (st[BPS_DONE]) return;
+  const int j = st[BPS_J], np = st[BPS_NP];
+  const int nch = (j + BP_KC - 1) / BP_KC;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < BP_NP * BP_NP; e += 256) Li[e / BP_NP][e % BP_NP] = conjg(Linv[e]);
+  __syncthreads();
+  const int i = blockIdx.x * 256 + tid;
+  if (i >= m) return;
+  const int* Pq = J + j;
+  int q0 = -1;
+  for (int q = 0; q < np; ++q)
+    if (Pq[q] == i) q0 = q;
+  if (q0 >= 0) {
+    for (int q = 0; q < np; ++q) Lt[(long)(j + q) * m + i] = Lpp[q0 * BP_NP + q];
+    chosen[i] = 1;
+    d[i] = 0.0;
+    return;
+  }
+  if (chosen[i]) {
+    for (int q = 0; q < np; ++q) Lt[(long)(j + q) * m + i] = mk(0.0, 0.0);
+    return;
+  }
+  z64 w[BP_NP];
+#pragma unroll
+  for (int q = 0; q < BP_NP; ++q) {
+    z64 v = mk(0.0, 0.0);
+    if (q < np) {
+      v = conjg(M[(long)Pq[q] * m + i]);
+      for (int c = 0; c < nch; ++c) v = v - part[((long)c * BP_NP + q) * m + i];
+    }
+    w[q] = v;
+  }
+  double sd = 0.0;
+  for (int q = 0; q < np; ++q) {
+    z64 v = mk(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < BP_NP; ++r)
+      if (r <= q) v = v + Li[q][r] * w[r];
+    Lt[(long)(j + q) * m + i] = v;
+    sd += abs2(v);
+  }
+  d[i] -= sd;
+}
+
+size_t rowid_bp_ws(int m) {
+  const size_t mm = (size_t)m * m, mp = (size_t)m + BP_KC;
+  const size_t nch = mp / BP_KC + 1;
+  return sizeof(z64) * (mm + mp * m + 2 * mm) + sizeof(double) * m + sizeof(int) * (3 * m + BPS_WORDS) +
+         sizeof(z64) * (BP_B * BP_B + 2 * BP_NP * BP_NP + nch * BP_B * BP_B + nch * (size_t)BP_NP * m) +
+         inverse_ws_bytes<double>(64, m / 64 + 1) + sizeof(z64) * (size_t)(m / 64 + 1) * 64 * 64 + 32 * 256;
+}
+
+static int grid_of(long n) {
+  const long g = (n + 255) / 256;
+  return (int)(g < 2048 ? (g > 0 ? g : 1) : 2048);
+}
+
+// U = L(rest, 0:k) L11^{-1} with U(J) = I, from the column-major factor Lt
+// (shared by both Gram paths)
+static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64* U, int* rest, z64* L11, z64* Lr,
+                        z64* Dinv, void* invws) {
+  const int DB = 64;
+  std::vector<int> ph(k), rh;
+  LSH_HIP(hipMemcpyAsync(ph.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<char> used(m, 0);
+    for (int v : ph) used[v] = 1;
+    for (int i = 0; i < m; ++i)
+      if (!used[i]) rh.push_back(i);
+  }
+  const int nr = (int)rh.size();
+  if (nr) LSH_HIP(hipMemcpyAsync(rest, rh.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_gather_L11, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, Lt, m, J, k, L11);
+  LSH_LAUNCH_CHECK();
+  if (nr) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div((long)nr * k, 256)), dim3(256), 0, s, Lt, m, rest, nr, k, Lr);
+    LSH_LAUNCH_CHECK();
+    const int nblk = ceil_div(k, DB);
+    hipLaunchKernelGGL(k_diag_blocks, dim3(ceil_div((long)nblk * DB * DB, 256)), dim3(256), 0, s, L11, k, DB, Dinv,
+                       nblk);
+    LSH_LAUNCH_CHECK();
+    inverse<double>(s, Dinv, DB, DB, (long)DB * DB, nblk, invws, nullptr);
+    z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
+    for (int q = nblk - 1; q >= 0; --q) {
+      const int b0 = q * DB, b1 = (b0 + DB < k) ? b0 + DB : k, w = b1 - b0;
+      if (b1 < k)  // Lr(:, B) -= X(:, b1:k) L11(b1:k, B)
+        cgemm<double>(s, nr, w, k - b1, mk(-1.0, 0.0), X + b1, k, 0, OP_N, L11 + (long)b1 * k + b0, k, 0, OP_N,
+                      mk(1.0, 0.0), Lr + b0, k, 0, Lr + b0, k, 0, 1);
+      // X(:, B) = Lr(:, B) L11(B, B)^{-1}
+      cgemm<double>(s, nr, w, w, mk(1.0, 0.0), Lr + b0, k, 0, OP_N, Dinv + (long)q * DB * DB, DB, 0, OP_N,
+                    mk(0.0, 0.0), nullptr, 0, 0, X + b0, k, 0, 1);
+    }
+    hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)(k + nr) * k, 256)), dim3(256), 0, s, U, k, J, rest, nr, X);
+  } else {
+    hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J, rest, 0, L11);
+  }
+  LSH_LAUNCH_CHECK();
+}
+
+int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws) {
+  LSH_REQUIRE(m <= BP_SEL, -6, "row ID: more than 4096 candidate rows in one level");
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) { char* r = p; p += ((bytes + 255) / 256) * 256; return (void*)r; };
+  const size_t mp = (size_t)m + BP_KC;
+  const int nch = (int)(mp / BP_KC) + 1;
+  z64* M = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  z64* Lt = static_cast<z64*>(take(sizeof(z64) * mp * m));
+  z64* L11 = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  z64* Lr = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
+  double* d = static_cast<double*>(take(sizeof(double) * m));
+  int* chosen = static_cast<int*>(take(sizeof(int) * m));
+  int* rest = static_cast<int*>(take(sizeof(int) * m));
+  int* st = static_cast<int*>(take(sizeof(int) * BPS_WORDS));
+  z64* Lpp = static_cast<z64*>(take(sizeof(z64) * BP_NP * BP_NP));
+  z64* Linv = static_cast<z64*>(take(sizeof(z64) * BP_NP * BP_NP));
+  z64* partS = static_cast<z64*>(take(sizeof(z64) * (size_t)nch * BP_B * BP_B));
+  z64* partW = static_cast<z64*>(take(sizeof(z64) * (size_t)nch * BP_NP * m));
+  const int DB = 64;
+  z64* Dinv = static_cast<z64*>(take(sizeof(z64) * (size_t)(m / DB + 1) * DB * DB));
+  void* invws = take(inverse_ws_bytes<double>(DB, m / DB + 1));
+  // Gram matrix and its diagonal; the factor starts at zero
+  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1);
+  fill_zero(s, Lt, sizeof(z64) * mp * m);
+  fill_zero(s, st, sizeof(int) * BPS_WORDS);
+  hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, st + BPS_WORDS - 4);
+  LSH_LAUNCH_CHECK();
+  std::vector<double> dh(m);
+  LSH_HIP(hipMemcpyAsync(dh.data(), d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  double fro2 = 0;
+  for (double v : dh) fro2 += v;
+  const double thr2 = tol * tol * fro2;
+  const int gm = ceil_div(m, 256);
+  // steps in batches; the first batches are short (the first step alone
+  // can take every pivot of a small block)
+  int batch = 4, host_st[2] = {0, 0};
+  while (true) {
+    for (int b = 0; b < batch; ++b) {
+      {
+        ProfScope ps("bp_select", s, 16.0 * m);
+        hipLaunchKernelGGL(k_bp_select, dim3(1), dim3(1024), 0, s, d, chosen, m, thr2, st);
+      }
+      LSH_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_bp_sc, dim3(nch), dim3(256), 0, s, Lt, m, st, partS);
+      LSH_LAUNCH_CHECK();
+      {
+        ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(256), 0, s, M, m, partS, thr2, J, st, Lpp, Linv);
+      }
+      LSH_LAUNCH_CHECK();
+      {
+        ProfScope ps("bp_wt", s, 16.0 * m * m);
+        hipLaunchKernelGGL(k_bp_wt, dim3(gm, nch), dim3(256), 0, s, Lt, J, chosen, m, st, partW);
+      }
+      LSH_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_bp_newcols, dim3(gm), dim3(256), 0, s, Lt, M, m, J, partW, Lpp, Linv, chosen, d, st);
+      LSH_LAUNCH_CHECK();
+    }
+    LSH_HIP(hipMemcpyAsync(host_st, st, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    if (host_st[BPS_DONE]) break;
+    batch = batch < 32 ? batch * 2 : 32;
+  }
+  int j = 0;
+  {
+    int hs[8];
+    LSH_HIP(hipMemcpyAsync(hs, st, sizeof(int) * 8, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    LSH_REQUIRE(hs[BPS_ERR] == 0, -4, "row ID: pivot row out of range");
+    j = hs[BPS_J] + hs[BPS_NP];  // (pivots of a step not yet advanced)
+  }
+  if (j < 1) {  // a zero block still gets one skeleton: row 0, U = e_0
+    const int zero = 0;
+    const z64 one = mk(1.0, 0.0);
+    LSH_HIP(hipMemcpyAsync(J, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    fill_zero(s, U, sizeof(z64) * (size_t)m);
+    LSH_HIP(hipMemcpyAsync(U, &one, sizeof(z64), hipMemcpyHostToDevice, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    return 1;
+  }
+  gram_interp(s, Lt, m, j, J, U, rest, L11, Lr, Dinv, invws);
+  return j;
 }
 
 size_t rowid_gram_ws(int m) {

@@ -27,6 +27,13 @@ size_t rowid_cpqr_ws(int m);
 int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws);
 size_t rowid_gram_ws(int m);
 
+// Gram path with block pivoting (left-looking, up to 32 pivots per step,
+// chosen among the 48 largest Schur diagonals only while they remain the
+// greedy choice over all rows): the greedy pivots and stopping rule.
+// Returns the rank (synchronises on the stream once per step).
+int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws);
+size_t rowid_bp_ws(int m);
+
 // Leaf factor helpers (R = working precision)
 template <typename R>
 void leaf_build(hipStream_t s, cplx<R>* X, const cplx<R>* Gleaf, int mL, const double* b, double kappa2,

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <complex>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <condition_variable>
 #include <exception>
@@ -181,8 +182,17 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     LSH_HIP(hipStreamSynchronize(s));
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
   } else {
-    DevBuf ws(rowid_gram_ws(m));
-    k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
+    // one-pivot-at-a-time panels by default; LSH_ROWID=block selects the
+    // block-pivoted left-looking variant (the same greedy pivots)
+    const char* e = std::getenv("LSH_ROWID");
+    const bool block = e && std::string(e) == "block";
+    if (!block) {
+      DevBuf ws(rowid_gram_ws(m));
+      k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
+    } else {
+      DevBuf ws(rowid_bp_ws(m));
+      k = rowid_bp(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
+    }
   }
   lv.k = k;
   lv.J.resize(k);
