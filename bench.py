@@ -47,6 +47,9 @@ def parse():
                     help="lsh_plan_create + lsh_factor_create instead of the pipelined lsh_build")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="instead of the headline run: time the factor of this many uneven instances "
+                         "(sides 64..256, 5-20 wavelengths), batched (lsh_batch_factor) against one by one")
     return ap.parse_args()
 
 
@@ -160,6 +163,58 @@ def cpu_baseline(n_full, n_sample):
                       f"to n={n_full}; host cpu_count={os.cpu_count()}"}
 
 
+def batched_run(a):
+    """Factor time of many uneven instances: one grouped launch per level step
+    (lsh_batch_factor) against lsh_factor_create per instance; plans are
+    built beforehand (b-independent), solves are per instance either way."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2007_12718_amd import lsh
+    ws = synth.batched(a.batched)
+    plans = [lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=2, prec="fp32")
+             for w in ws]
+    bs = [torch.from_numpy(w.b).cuda() for w in ws]
+    res = {}
+    for mode in ("separate", "batched"):
+        times = []
+        for k in range(a.warmup + a.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "batched":
+                fs = lsh.batch_factor(plans, bs)
+            else:
+                fs = [lsh.Factor(P, b) for P, b in zip(plans, bs)]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if k >= a.warmup:
+                times.append(dt)
+            for F in fs:
+                F.close()
+        res[mode] = sorted(times)[len(times) // 2]
+        print(f"# {mode}: {times}", file=sys.stderr, flush=True)
+    # one solve per instance with the batched factors (FP64 FGMRES to 1e-10)
+    fs = lsh.batch_factor(plans, bs)
+    its, worst = [], 0.0
+    for w, F in zip(ws, fs):
+        _, _, info, rc = F.solve(torch.from_numpy(w.u_inc).cuda(), tol=1e-10, maxit=100, want_u=False)
+        its.append(info.iterations)
+        worst = max(worst, info.true_residual)
+        F.close()
+    sizes = {}
+    for w in ws:
+        sizes[w.n] = sizes.get(w.n, 0) + 1
+    out = {"metric": "batched HBS factor time, uneven instances", "value": res["batched"], "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "separate_s": res["separate"], "speedup": res["separate"] / res["batched"],
+           "dtype": "c64 HBS", "data": "synthetic",
+           "config": {"workload": f"batched-{a.batched}: sides {sizes}, kappa = 2 pi U[5,20], 10 bumps clipped at "
+                                  f"0.95, HBS 4th order tol 1e-4, FP32", "iterations": its,
+                      "max_true_residual": worst}}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -171,6 +226,8 @@ def main():
     from paper_2007_12718_amd import lsh
 
     torch.cuda.set_device(0)
+    if a.batched:
+        return batched_run(a)
     if a.calib_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

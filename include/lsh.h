@@ -130,6 +130,20 @@ int lsh_factor_create(lsh_plan_t plan, const double* b, void* stream, lsh_factor
 int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* plan, lsh_factor_t* factor);
 int lsh_factor_destroy(lsh_factor_t factor);
 
+/* Algorithm 1 for ninst independent problems at once (many uneven instances:
+ * different grids, wavenumbers and ranks).  plans: host array of ninst plans;
+ * b: host array of ninst device pointers (double[n_i*n_i]); factors: host
+ * array receiving ninst handles, each usable like one from
+ * lsh_factor_create (destroy each; a factor refers to its plan).  For FP32
+ * plans the levels are aligned from the leaves (level L_i - d of every
+ * instance at step d) and each product and inverse of a step is one grouped
+ * launch over all instances' boxes; the results equal per-instance
+ * lsh_factor_create bitwise.  FP64 plans are factored one by one.
+ * Synchronises the stream.  Errors: as lsh_factor_create (the message names
+ * the instance); on error no handle is returned. */
+int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b, void* stream,
+                     lsh_factor_t* factors);
+
 /* y = M x: Algorithm 2 (M ~ (I + B G)^{-1}); transpose = 1 applies M^T.
  * x, y: device double2[nrhs*n*n]; x and y must not overlap. */
 int lsh_apply_precond(lsh_factor_t factor, int transpose, const void* x, void* y, int nrhs, void* stream);

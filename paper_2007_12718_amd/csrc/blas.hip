@@ -204,27 +204,18 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
 // Accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 constexpr int X32_LDK = GBK + 4;
 
+// One (64 WM) x (64 WN) output tile of problem b of P, at (m0, n0).
 template <int WM, int WN>
-__global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {
+__device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, int m0, int n0) {
   typedef float f16v __attribute__((ext_vector_type(16)));
   typedef float f4v __attribute__((ext_vector_type(4)));
   constexpr int BM = 64 * WM, BN = 64 * WN;
   constexpr int EA = BM * GBK / 256, EB = BN * GBK / 256;
-  if (P.skip && *P.skip) return;  // uniform across the launch
   __shared__ __align__(16) float sAr[BM][X32_LDK], sAi[BM][X32_LDK];
   __shared__ __align__(16) float sBr[BN][X32_LDK], sBi[BN][X32_LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int g = lane >> 5, l32 = lane & 31;
-  // XCD-aware tile order (see k_cgemm)
-  const long T = (long)gridDim.x * gridDim.y * gridDim.z;
-  long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
-  const long T8 = (T / 8) * 8;
-  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
-  const int tn = (int)(L % gridDim.x);
-  const int tm = (int)((L / gridDim.x) % gridDim.y);
-  const long b = L / ((long)gridDim.x * gridDim.y);
-  const int m0 = tm * BM, n0 = tn * BN;
   const cplx<float>* A = P.A + b * P.sA;
   const cplx<float>* B = P.B + b * P.sB;
   const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
@@ -345,6 +336,46 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {
 }
 
 template <int WM, int WN>
+__global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {
+  constexpr int BM = 64 * WM, BN = 64 * WN;
+  if (P.skip && *P.skip) return;  // uniform across the launch
+  // XCD-aware tile order (see k_cgemm)
+  const long T = (long)gridDim.x * gridDim.y * gridDim.z;
+  long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+  const long T8 = (T / 8) * 8;
+  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
+  const int tn = (int)(L % gridDim.x);
+  const int tm = (int)((L / gridDim.x) % gridDim.y);
+  const long b = L / ((long)gridDim.x * gridDim.y);
+  cgemm_x32_tile<WM, WN>(P, b, tm * BM, tn * BN);
+}
+
+// Grouped form: problem g of the table has tiles_m x tiles_n x batch tiles
+// starting at flat tile index tile0; one workgroup per tile of every problem.
+struct GemmGroupDev {
+  GemmP<float> p;
+  int batch, tiles_m, tiles_n;
+  long tile0;
+};
+
+__global__ __launch_bounds__(256, 5) void k_cgemm_x32_grouped(const GemmGroupDev* G, int ng) {
+  const long L = blockIdx.x + (long)gridDim.x * blockIdx.y;
+  int lo = 0, hi = ng - 1;  // last group with tile0 <= L
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (G[mid].tile0 <= L) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmGroupDev& gd = G[lo];
+  const long t = L - gd.tile0;
+  if (t >= (long)gd.tiles_m * gd.tiles_n * gd.batch) return;
+  const int tn = (int)(t % gd.tiles_n);
+  const int tm = (int)((t / gd.tiles_n) % gd.tiles_m);
+  const long b = t / ((long)gd.tiles_n * gd.tiles_m);
+  cgemm_x32_tile<1, 1>(gd.p, b, tm * 64, tn * 64);
+}
+
+template <int WM, int WN>
 static void launch_gemm_x32(hipStream_t s, const GemmP<float>& P, const cplx<float>* A, const cplx<float>* B,
                             const cplx<float>* D, cplx<float>* C, long sA, long sB, long sD, long sC, int batch) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
@@ -432,6 +463,40 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
     if (M >= 128 && N >= 64 && K >= 32 && big_tiles >= 128) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
+}
+
+void cgemm_grouped(hipStream_t s, const std::vector<GemmItem>& items, DevBuf& dev) {
+  std::vector<GemmGroupDev> h;
+  long tiles = 0;
+  double flops = 0;
+  for (const GemmItem& it : items) {
+    if (it.M <= 0 || it.N <= 0 || it.batch <= 0) continue;
+    GemmGroupDev g;
+    GemmP<float>& P = g.p;
+    P.M = it.M; P.N = it.N; P.K = it.K; P.alpha = it.alpha; P.beta = it.beta;
+    P.A = it.A; P.lda = it.lda; P.sA = it.sA; P.opA = it.opA;
+    P.B = it.B; P.ldb = it.ldb; P.sB = it.sB; P.opB = it.opB;
+    P.D = it.D; P.ldd = it.ldd; P.sD = it.sD;
+    P.C = it.C; P.ldc = it.ldc; P.sC = it.sC; P.addI = it.addI ? 1 : 0; P.skip = nullptr;
+    g.batch = it.batch;
+    g.tiles_m = ceil_div(it.M, 64);
+    g.tiles_n = ceil_div(it.N, 64);
+    g.tile0 = tiles;
+    tiles += (long)g.tiles_m * g.tiles_n * g.batch;
+    flops += 8.0 * it.M * it.N * it.K * it.batch;
+    h.push_back(g);
+  }
+  if (h.empty()) return;
+  const size_t bytes = sizeof(GemmGroupDev) * h.size();
+  if (dev.bytes < bytes) dev.alloc(bytes);
+  LSH_HIP(hipMemcpyAsync(dev.p, h.data(), bytes, hipMemcpyHostToDevice, s));
+  ProfScope ps("cgemm_f32_grouped", s, flops);
+  const long gx = tiles < 65535 ? tiles : 65535;
+  const dim3 grid((unsigned)gx, (unsigned)((tiles + gx - 1) / gx));
+  hipLaunchKernelGGL(k_cgemm_x32_grouped, grid, dim3(256), 0, s, dev.as<GemmGroupDev>(), (int)h.size());
+  LSH_LAUNCH_CHECK();
+  // the table must outlive the copy: pageable copies are staged before
+  // hipMemcpyAsync returns, so the host vector may go out of scope here
 }
 
 // ---------------------------------------------------------------- GEMV
@@ -551,15 +616,13 @@ __device__ void wave_argmax(R& v, int& idx) {
   }
 }
 
+// One c x c matrix in LDS (one workgroup); perm: c ints of global scratch.
 template <typename R>
-__global__ __launch_bounds__(256) void k_inv_small(cplx<R>* A, int c, long lda, long sA, int* info, int* permg) {
+__device__ void inv_small_body(cplx<R>* Ab, int c, long lda, int* infob, int* perm) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R>* S = reinterpret_cast<cplx<R>*>(smem_raw);  // c*c
   __shared__ int s_piv;
   __shared__ int s_bad;
-  const long b = blockIdx.x;
-  cplx<R>* Ab = A + b * sA;
-  int* perm = permg + b * c;  // row interchanges (global scratch, one row per matrix)
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < c * c; e += nt) S[e] = Ab[(long)(e / c) * lda + (e % c)];
   if (tid == 0) s_bad = 0;
@@ -614,7 +677,13 @@ __global__ __launch_bounds__(256) void k_inv_small(cplx<R>* A, int c, long lda, 
     __syncthreads();
   }
   for (int e = tid; e < c * c; e += nt) Ab[(long)(e / c) * lda + (e % c)] = S[e];
-  if (tid == 0 && info) info[b] = s_bad;
+  if (tid == 0 && infob) *infob = s_bad;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_inv_small(cplx<R>* A, int c, long lda, long sA, int* info, int* permg) {
+  const long b = blockIdx.x;
+  inv_small_body<R>(A + b * sA, c, lda, info ? info + b : nullptr, permg + b * c);
 }
 
 // Large matrices: two-level blocked in-place Gauss-Jordan without row
@@ -708,16 +777,11 @@ template <typename R>
 constexpr int gj_kr() { return GJ_STAGE_BYTES / (GJ_NT * (int)sizeof(cplx<R>)); }
 
 template <typename R, int RPT, int NB>
-__global__ __launch_bounds__(GJ_NT) void k_gj_panel(cplx<R>* A, int c, long lda, long sA, int j0, int* perm,
-                                                    int* used, int* info) {
+__device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int j0, int* pb, int* ub, int* infob) {
   constexpr int KR = gj_kr<R>();
   __shared__ cplx<R> stg[KR * GJ_NT];
   __shared__ cplx<R> cand[2][GJ_NT / 64][NB];  // each wave's best candidate row (double-buffered)
   __shared__ unsigned long long ckey[2][GJ_NT / 64];
-  const long b = blockIdx.x;
-  cplx<R>* Ab = A + b * sA;
-  int* pb = perm + b * c;
-  int* ub = used + b * c;
   const int nt = blockDim.x, nw = nt >> 6;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = (c - j0) < NB ? (c - j0) : NB;
@@ -799,7 +863,7 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_panel(cplx<R>* A, int c, long lda,
     if (tid == 0) {
       pb[j] = p;
       ub[p] = 1;
-      if (!(abs2(pr[jj]) > R(0)) && info && info[b] == 0) info[b] = j + 1;
+      if (!(abs2(pr[jj]) > R(0)) && infob && *infob == 0) *infob = j + 1;
     }
     const cplx<R> rp = crecip(pr[jj]);
     // every row as a non-pivot row; the pivot row is overwritten below
@@ -839,30 +903,43 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_panel(cplx<R>* A, int c, long lda,
   }
 }
 
+template <typename R, int RPT, int NB>
+__global__ __launch_bounds__(GJ_NT) void k_gj_panel(cplx<R>* A, int c, long lda, long sA, int j0, int* perm,
+                                                    int* used, int* info) {
+  const long b = blockIdx.x;
+  gj_panel_body<R, RPT, NB>(A + b * sA, c, lda, j0, perm + b * c, used + b * c, info ? info + b : nullptr);
+}
+
 // Block K = columns [kb, kb+nbk) with pivot rows perm[kb ..]:
 //   T[q][t] = A[perm[kb+q]][cs+t] for the columns cs+t (t < ncol) outside K,
 //             0 inside K (ld ncol);
 //   F[i][q] = A[i][kb+q] - [i == perm[kb+q]]   (ld nbk).
 // Both index spaces run along contiguous memory.
+// (Tb, Fb: this matrix's T and F; pb: its pivot rows of the block, perm + kb)
 template <typename R>
-__global__ void k_gj_gather(const cplx<R>* A, int c, long lda, long sA, int kb, int nbk, int cs, int ncol,
-                            const int* perm, cplx<R>* T, cplx<R>* F) {
-  const long b = blockIdx.y;
-  const cplx<R>* Ab = A + b * sA;
-  const int* pb = perm + b * c + kb;
+__device__ __forceinline__ void gj_gather_body(const cplx<R>* Ab, int c, long lda, int kb, int nbk, int cs,
+                                               int ncol, const int* pb, cplx<R>* Tb, cplx<R>* Fb) {
   const long nT = (long)nbk * ncol, nF = (long)c * nbk;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nT + nF; e += (long)gridDim.x * blockDim.x) {
     if (e < nT) {
       const int q = (int)(e / ncol), t = (int)(e % ncol), k = cs + t;
-      T[b * nT + e] = (k >= kb && k < kb + nbk) ? mk<R>(0, 0) : Ab[(long)pb[q] * lda + k];
+      Tb[e] = (k >= kb && k < kb + nbk) ? mk<R>(0, 0) : Ab[(long)pb[q] * lda + k];
     } else {
       const long f = e - nT;
       const int i = (int)(f / nbk), q = (int)(f % nbk);
       cplx<R> v = Ab[(long)i * lda + kb + q];
       if (i == pb[q]) v.x -= R(1);
-      F[b * nF + f] = v;
+      Fb[f] = v;
     }
   }
+}
+
+template <typename R>
+__global__ void k_gj_gather(const cplx<R>* A, int c, long lda, long sA, int kb, int nbk, int cs, int ncol,
+                            const int* perm, cplx<R>* T, cplx<R>* F) {
+  const long b = blockIdx.y;
+  gj_gather_body<R>(A + b * sA, c, lda, kb, nbk, cs, ncol, perm + b * c + kb, T + b * (long)nbk * ncol,
+                    F + b * (long)c * nbk);
 }
 
 // tmp[a][b] = S[perm[a]][pinv[b]] (pinv[perm[j]] = j), then copied back
@@ -1002,6 +1079,228 @@ void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, voi
   LSH_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_gj_copyback<R>, dim3(grid_for((long)c * c), batch), dim3(256), 0, s, A, c, lda, sA, tmp);
   LSH_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------ grouped FP32 inverses
+// Many batches of different orders in one set of launches: every kernel
+// walks a device table of the items and one workgroup (or a block row of
+// workgroups) per matrix of every item; an item whose order is past the
+// current column step returns at once.  Per matrix the arithmetic is the
+// one of inverse<float>(), so each result is bitwise the separate call's.
+struct InvDev {
+  c32* A;
+  int c, batch;
+  long lda, sA;
+  int* info;
+  int *perm, *pinv, *used;
+  c32 *T, *F, *tmp;
+  long mat0;  // first global matrix index of this item
+};
+
+__device__ __forceinline__ int inv_item_of(const InvDev* G, int ng, long gm) {
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (G[mid].mat0 <= gm) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_inv_small_grouped(const InvDev* G, int ng) {
+  const long gm = blockIdx.x;
+  const InvDev& it = G[inv_item_of(G, ng, gm)];
+  const long b = gm - it.mat0;
+  inv_small_body<float>(it.A + b * it.sA, it.c, it.lda, it.info ? it.info + b : nullptr, it.perm + b * it.c);
+}
+
+__global__ void k_inv_grouped_init(const InvDev* G, int ng) {
+  const long gm = blockIdx.y;
+  const InvDev& it = G[inv_item_of(G, ng, gm)];
+  const long b = gm - it.mat0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < it.c; i += gridDim.x * blockDim.x) it.used[b * it.c + i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && it.info) it.info[b] = 0;
+}
+
+// panel j0 of slab s0 (items with j0 inside their slab)
+__global__ __launch_bounds__(GJ_NT) void k_gj_panel_grouped(const InvDev* G, int ng, int s0, int nb2, int j0) {
+  const long gm = blockIdx.x;
+  const InvDev& it = G[inv_item_of(G, ng, gm)];
+  const int c = it.c, se = (s0 + nb2) < c ? s0 + nb2 : c;
+  if (j0 >= se) return;
+  const long b = gm - it.mat0;
+  gj_panel_body<float, 1, 8>(it.A + b * it.sA, c, it.lda, j0, it.perm + b * c, it.used + b * c,
+                             it.info ? it.info + b : nullptr);
+}
+
+// mode 0: the rest of slab s0 after panel j0 (block [j0, j0+nb), columns of
+// the slab); mode 1: every column outside slab s0 (block = the slab)
+__global__ void k_gj_gather_grouped(const InvDev* G, int ng, int mode, int s0, int nb2, int j0) {
+  const long gm = blockIdx.y;
+  const InvDev& it = G[inv_item_of(G, ng, gm)];
+  const int c = it.c;
+  if (s0 >= c) return;
+  const int w2 = (c - s0) < nb2 ? c - s0 : nb2;
+  int kb, nbk, cs, ncol;
+  if (mode == 0) {
+    if (j0 >= s0 + w2) return;
+    nbk = (s0 + w2 - j0) < 8 ? s0 + w2 - j0 : 8;
+    if (w2 <= nbk) return;
+    kb = j0; cs = s0; ncol = w2;
+  } else {
+    if (c <= w2) return;
+    kb = s0; nbk = w2; cs = 0; ncol = c;
+  }
+  const long b = gm - it.mat0;
+  gj_gather_body<float>(it.A + b * it.sA, c, it.lda, kb, nbk, cs, ncol, it.perm + b * c + kb,
+                        it.T + b * (long)nbk * ncol, it.F + b * (long)c * nbk);
+}
+
+__global__ void k_gj_unperm_grouped(const InvDev* G, int ng, int phase) {
+  const long gm = blockIdx.y;
+  const InvDev& it = G[inv_item_of(G, ng, gm)];
+  const int c = it.c;
+  const long b = gm - it.mat0;
+  const int* pb = it.perm + b * c;
+  int* qb = it.pinv + b * c;
+  const long n = (long)c * c;
+  c32* Ab = it.A + b * it.sA;
+  c32* tb = it.tmp + b * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (phase == 0 ? c : n);
+       e += (long)gridDim.x * blockDim.x) {
+    if (phase == 0) qb[pb[e]] = (int)e;
+    else if (phase == 1) tb[e] = Ab[(long)pb[e / c] * it.lda + qb[e % c]];
+    else Ab[(e / c) * it.lda + (e % c)] = tb[e];
+  }
+}
+
+size_t inverse_grouped_ws_bytes(const std::vector<InvItem>& items) {
+  size_t t = 0;
+  for (const InvItem& it : items) {
+    const size_t c = it.c, b = it.batch;
+    if (small_inv_lds<float>(it.c) <= 65536) t += ((b * c * sizeof(int) + 255) / 256) * 256;
+    else t += ((3 * b * c * sizeof(int) + 255) / 256) * 256 +
+              ((b * (2 * (size_t)gj_nb2() * c + c * c) * sizeof(c32) + 255) / 256) * 256 + 4 * 256;
+  }
+  return t + 256;
+}
+
+void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws, DevBuf& table) {
+  const int NB2 = gj_nb2();
+  std::vector<InvDev> small, blocked;
+  std::vector<const InvItem*> big;
+  char* w = static_cast<char*>(ws);
+  auto take = [&](size_t bytes) {
+    char* p = w;
+    w += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  long msmall = 0, mblocked = 0;
+  int cmax_small = 0, cmax_blocked = 0;
+  double flops = 0;
+  for (const InvItem& it : items) {
+    if (it.c <= 0 || it.batch <= 0) continue;
+    flops += 8.0 * it.c * it.c * it.c * it.batch;
+    InvDev d{};
+    d.A = it.A; d.c = it.c; d.batch = it.batch; d.lda = it.lda; d.sA = it.sA; d.info = it.info;
+    if (small_inv_lds<float>(it.c) <= 65536) {
+      d.perm = reinterpret_cast<int*>(take((size_t)it.batch * it.c * sizeof(int)));
+      d.mat0 = msmall;
+      msmall += it.batch;
+      cmax_small = it.c > cmax_small ? it.c : cmax_small;
+      small.push_back(d);
+    } else if (it.c <= GJ_NT) {
+      const size_t bc = (size_t)it.batch * it.c;
+      d.perm = reinterpret_cast<int*>(take(3 * bc * sizeof(int)));
+      d.pinv = d.perm + bc;
+      d.used = d.pinv + bc;
+      d.T = reinterpret_cast<c32*>(take(sizeof(c32) * bc * NB2));
+      d.F = reinterpret_cast<c32*>(take(sizeof(c32) * bc * NB2));
+      d.tmp = reinterpret_cast<c32*>(take(sizeof(c32) * bc * it.c));
+      d.mat0 = mblocked;
+      mblocked += it.batch;
+      cmax_blocked = it.c > cmax_blocked ? it.c : cmax_blocked;
+      blocked.push_back(d);
+    } else {
+      big.push_back(&it);
+    }
+  }
+  ProfScope ps("op_inverse_f32_grouped", s, flops);
+  LSH_REQUIRE(msmall <= 2147483647L && mblocked <= 65535, -6, "grouped inverse: too many matrices");
+  const size_t bytes = sizeof(InvDev) * (small.size() + blocked.size());
+  if (bytes && table.bytes < bytes) table.alloc(bytes);
+  InvDev* Ts = table.as<InvDev>();
+  InvDev* Tb = Ts + small.size();
+  if (!small.empty()) {
+    LSH_HIP(hipMemcpyAsync(Ts, small.data(), sizeof(InvDev) * small.size(), hipMemcpyHostToDevice, s));
+    for (const InvDev& d : small)
+      if (d.info) hipLaunchKernelGGL(k_zero_int, dim3(ceil_div((long)d.batch, 256)), dim3(256), 0, s, d.info, (long)d.batch);
+    hipLaunchKernelGGL(k_inv_small_grouped, dim3((unsigned)msmall), dim3(256),
+                       small_inv_lds<float>(cmax_small), s, Ts, (int)small.size());
+    LSH_LAUNCH_CHECK();
+  }
+  if (!blocked.empty()) {
+    const int ng = (int)blocked.size();
+    LSH_HIP(hipMemcpyAsync(Tb, blocked.data(), sizeof(InvDev) * ng, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_inv_grouped_init, dim3(ceil_div(cmax_blocked, 256), (unsigned)mblocked), dim3(256), 0, s,
+                       Tb, ng);
+    LSH_LAUNCH_CHECK();
+    const int nt = ceil_div(cmax_blocked, 64) * 64;
+    const c32 one = mk<float>(1, 0);
+    std::vector<GemmItem> gi;
+    DevBuf gtab;
+    std::vector<DevBuf> keep;  // GEMM tables of earlier steps stay alive until the end
+    auto gemms = [&](std::vector<GemmItem>& v) {
+      if (v.empty()) return;
+      keep.emplace_back();
+      cgemm_grouped(s, v, keep.back());
+      v.clear();
+    };
+    for (int s0 = 0; s0 < cmax_blocked; s0 += NB2) {
+      for (int j0 = s0; j0 < s0 + NB2 && j0 < cmax_blocked; j0 += 8) {
+        hipLaunchKernelGGL(k_gj_panel_grouped, dim3((unsigned)mblocked), dim3(nt), 0, s, Tb, ng, s0, NB2, j0);
+        LSH_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gj_gather_grouped, dim3(64, (unsigned)mblocked), dim3(256), 0, s, Tb, ng, 0, s0, NB2,
+                           j0);
+        LSH_LAUNCH_CHECK();
+        for (const InvDev& d : blocked) {
+          if (s0 >= d.c) continue;
+          const int w2 = (d.c - s0) < NB2 ? d.c - s0 : NB2;
+          if (j0 >= s0 + w2) continue;
+          const int nb = (s0 + w2 - j0) < 8 ? s0 + w2 - j0 : 8;
+          if (w2 <= nb) continue;
+          gi.push_back({d.c, w2, nb, one, one, d.F, nb, (long)d.c * nb, OP_N, d.T, w2, (long)nb * w2, OP_N,
+                        d.A + s0, d.lda, d.sA, d.A + s0, d.lda, d.sA, d.batch, false});
+        }
+        gemms(gi);
+      }
+      hipLaunchKernelGGL(k_gj_gather_grouped, dim3(64, (unsigned)mblocked), dim3(256), 0, s, Tb, ng, 1, s0, NB2, 0);
+      LSH_LAUNCH_CHECK();
+      for (const InvDev& d : blocked) {
+        if (s0 >= d.c) continue;
+        const int w2 = (d.c - s0) < NB2 ? d.c - s0 : NB2;
+        if (d.c <= w2) continue;
+        if (s0 > 0)
+          gi.push_back({d.c, s0, w2, one, one, d.F, w2, (long)d.c * w2, OP_N, d.T, d.c, (long)w2 * d.c, OP_N, d.A,
+                        d.lda, d.sA, d.A, d.lda, d.sA, d.batch, false});
+        const int e = s0 + w2;
+        if (e < d.c)
+          gi.push_back({d.c, d.c - e, w2, one, one, d.F, w2, (long)d.c * w2, OP_N, d.T + e, d.c, (long)w2 * d.c,
+                        OP_N, d.A + e, d.lda, d.sA, d.A + e, d.lda, d.sA, d.batch, false});
+      }
+      gemms(gi);
+    }
+    for (int phase = 0; phase < 3; ++phase) {
+      hipLaunchKernelGGL(k_gj_unperm_grouped, dim3(64, (unsigned)mblocked), dim3(256), 0, s, Tb, ng, phase);
+      LSH_LAUNCH_CHECK();
+    }
+    LSH_HIP(hipStreamSynchronize(s));  // the GEMM tables in keep die here
+  }
+  for (const InvItem* it : big) {
+    DevBuf wsb(inverse_ws_bytes<float>(it->c, it->batch));
+    inverse<float>(s, it->A, it->c, it->lda, it->sA, it->batch, wsb.p, it->info);
+    LSH_HIP(hipStreamSynchronize(s));
+  }
 }
 
 template <typename R>

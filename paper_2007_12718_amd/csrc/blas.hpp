@@ -4,6 +4,8 @@
 // double.  A "batch" is a set of equally sized problems at a fixed stride
 // (stride 0 = one operand shared by every problem).
 #pragma once
+#include <vector>
+
 #include "common.hpp"
 
 namespace lsh {
@@ -22,6 +24,22 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            const cplx<R>* B, long ldb, long sB, Op opB,
            cplx<R> beta, const cplx<R>* D, long ldd, long sD,
            cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false, const int* skip = nullptr);
+
+// Many batched FP32 GEMMs of different shapes in one launch (64 x 64 tiles,
+// the same arithmetic as cgemm<float>, so each result is bitwise that of
+// the separate call).  dev: device buffer for the problem table (grown as
+// needed; keep it alive until the stream has run the launch).
+struct GemmItem {
+  int M, N, K;
+  c32 alpha, beta;
+  const c32* A; long lda, sA; Op opA;
+  const c32* B; long ldb, sB; Op opB;
+  const c32* D; long ldd, sD;
+  c32* C; long ldc, sC;
+  int batch;
+  bool addI;
+};
+void cgemm_grouped(hipStream_t s, const std::vector<GemmItem>& items, DevBuf& dev);
 
 // y_b = alpha * A_{b mod amod} x_b + beta * z_b   (A_b is M x N, op N).
 // z may alias y; z may be null when beta == 0.
@@ -47,6 +65,20 @@ size_t inverse_ws_bytes(int c, int batch);
 template <typename R>
 void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch,
              void* ws, int* info);
+
+// Many FP32 inverse batches of different orders at once (the LDS path for
+// small orders and the blocked path for orders <= 1024 each in one set of
+// launches; larger orders fall back to inverse()).  Same results as
+// inverse<float>() per item.  Synchronises the stream.
+struct InvItem {
+  c32* A;
+  int c;
+  long lda, sA;
+  int batch;
+  int* info;  // batch ints (may be null)
+};
+size_t inverse_grouped_ws_bytes(const std::vector<InvItem>& items);
+void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws, DevBuf& table);
 
 // out_b (cols x rows) = in_b^T (rows x cols), row-major, batch of contiguous matrices
 template <typename R>

@@ -1189,6 +1189,230 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   API_END
 }
 
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 for many instances at once (FP32 factors): the levels are
+// aligned from the leaves, and every step of a level (each product, the
+// inverses) is one grouped launch over the instances that have that level.
+void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
+  const int n_inst = (int)Fs.size();
+  const c32 one = mk<float>(1, 0), zero = mk<float>(0, 0), mone = mk<float>(-1, 0);
+  DevBuf gtab, itab;
+  std::vector<GemmItem> gi;
+  auto run_gemms = [&](DevBuf& tab) {
+    cgemm_grouped(s, gi, tab);
+    gi.clear();
+  };
+  int Lmax = 0;
+  for (auto* F : Fs) {
+    factor_init<float>(*F->plan, F->f32);
+    Lmax = F->plan->L > Lmax ? F->plan->L : Lmax;
+  }
+  // leaves: X = (I + B G_leaf)^{-1}, S = U^T X B U
+  std::vector<DevBuf> Yb(n_inst), Zb(n_inst), infos(n_inst);
+  std::vector<InvItem> inv;
+  for (int i = 0; i < n_inst; ++i) {
+    const lsh_plan_s& P = *Fs[i]->plan;
+    FactorData<float>& F = Fs[i]->f32;
+    const int nleaf = P.nleaf, mL = P.mL;
+    F.X.alloc(sizeof(c32) * (size_t)nleaf * mL * mL);
+    leaf_build<float>(s, F.X.as<c32>(), P.Gleaf<float>(), mL, Fs[i]->b.as<double>(), P.kappa * P.kappa,
+                      P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
+    infos[i].alloc(sizeof(int) * nleaf);
+    inv.push_back({F.X.as<c32>(), mL, (long)mL, (long)mL * mL, nleaf, infos[i].as<int>()});
+  }
+  {
+    DevBuf ws(inverse_grouped_ws_bytes(inv));
+    inverse_grouped(s, inv, ws.p, itab);
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    LSH_REQUIRE(!check_info(infos[i], Fs[i]->plan->nleaf, s), LSH_ERR_SINGULAR,
+                "singular leaf matrix I + B G (instance " + std::to_string(i) + ")");
+  }
+  inv.clear();
+  for (int i = 0; i < n_inst; ++i) {
+    const lsh_plan_s& P = *Fs[i]->plan;
+    FactorData<float>& F = Fs[i]->f32;
+    const int nleaf = P.nleaf, mL = P.mL, kL = P.lev[P.L].k;
+    Yb[i].alloc(sizeof(c32) * (size_t)nleaf * mL * kL);
+    Zb[i].alloc(sizeof(c32) * (size_t)nleaf * mL * kL);
+    leaf_scale_U<float>(s, Yb[i].as<c32>(), P.U<float>(P.L), mL, kL, Fs[i]->b.as<double>(), P.kappa * P.kappa,
+                        P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
+    gi.push_back({mL, kL, mL, one, zero, F.X.as<c32>(), mL, (long)mL * mL, OP_N, Yb[i].as<c32>(), kL,
+                  (long)mL * kL, OP_N, nullptr, 0, 0, Zb[i].as<c32>(), kL, (long)mL * kL, nleaf, false});
+  }
+  run_gemms(gtab);
+  for (int i = 0; i < n_inst; ++i) {
+    const lsh_plan_s& P = *Fs[i]->plan;
+    FactorData<float>& F = Fs[i]->f32;
+    const int nleaf = P.nleaf, mL = P.mL, kL = P.lev[P.L].k;
+    F.S[P.L].alloc(sizeof(c32) * (size_t)nleaf * kL * kL);
+    gi.push_back({kL, kL, mL, one, zero, P.U<float>(P.L), kL, 0, OP_T, Zb[i].as<c32>(), kL, (long)mL * kL, OP_N,
+                  nullptr, 0, 0, F.S[P.L].as<c32>(), kL, (long)kL * kL, nleaf, false});
+  }
+  DevBuf gtab2;
+  run_gemms(gtab2);
+  LSH_HIP(hipStreamSynchronize(s));
+  Yb.clear(); Zb.clear();
+  // levels, aligned from the leaves
+  for (int dpt = 1; dpt <= Lmax; ++dpt) {
+    std::vector<int> act;
+    for (int i = 0; i < n_inst; ++i)
+      if (Fs[i]->plan->L - dpt >= 0) act.push_back(i);
+    std::vector<DevBuf> tabs(9);
+    auto lev = [&](int i) { return Fs[i]->plan->L - dpt; };
+    for (int i : act) {  // allocations of this level
+      const lsh_plan_s& P = *Fs[i]->plan;
+      FactorData<float>& F = Fs[i]->f32;
+      const int l = lev(i), c = P.lev[l].c, nb = 1 << l;
+      const long cc = (long)c * c;
+      F.Pa[l].alloc(sizeof(c32) * nb * cc);
+      F.Pb[l].alloc(sizeof(c32) * nb * cc);
+      F.Ci[l].alloc(sizeof(c32) * nb * cc);
+    }
+    // P_a = S_a G_ab ; P_b = S_b G_ab^T
+    for (int i : act) {
+      const lsh_plan_s& P = *Fs[i]->plan;
+      FactorData<float>& F = Fs[i]->f32;
+      const int l = lev(i), c = P.lev[l].c, nb = 1 << l;
+      const long cc = (long)c * c;
+      const c32* Sch = F.S[l + 1].as<c32>();
+      gi.push_back({c, c, c, one, zero, Sch, c, 2 * cc, OP_N, P.Gab<float>(l), c, 0, OP_N, nullptr, 0, 0,
+                    F.Pa[l].as<c32>(), c, cc, nb, false});
+      gi.push_back({c, c, c, one, zero, Sch + cc, c, 2 * cc, OP_N, P.Gab<float>(l), c, 0, OP_T, nullptr, 0, 0,
+                    F.Pb[l].as<c32>(), c, cc, nb, false});
+    }
+    run_gemms(tabs[0]);
+    // C = I - P_b P_a
+    for (int i : act) {
+      const lsh_plan_s& P = *Fs[i]->plan;
+      FactorData<float>& F = Fs[i]->f32;
+      const int l = lev(i), c = P.lev[l].c, nb = 1 << l;
+      const long cc = (long)c * c;
+      gi.push_back({c, c, c, mone, zero, F.Pb[l].as<c32>(), c, cc, OP_N, F.Pa[l].as<c32>(), c, cc, OP_N, nullptr,
+                    0, 0, F.Ci[l].as<c32>(), c, cc, nb, true});
+    }
+    run_gemms(tabs[1]);
+    // C^{-1}
+    std::vector<DevBuf> linfo(n_inst);
+    for (int i : act) {
+      const lsh_plan_s& P = *Fs[i]->plan;
+      FactorData<float>& F = Fs[i]->f32;
+      const int l = lev(i), c = P.lev[l].c, nb = 1 << l;
+      linfo[i].alloc(sizeof(int) * nb);
+      inv.push_back({F.Ci[l].as<c32>(), c, (long)c, (long)c * c, nb, linfo[i].as<int>()});
+    }
+    {
+      DevBuf ws(inverse_grouped_ws_bytes(inv));
+      inverse_grouped(s, inv, ws.p, itab);
+    }
+    inv.clear();
+    for (int i : act)
+      LSH_REQUIRE(!check_info(linfo[i], 1 << lev(i), s), LSH_ERR_SINGULAR,
+                  "singular merge matrix I - Pb Pa at level " + std::to_string(lev(i)) + " (instance " +
+                      std::to_string(i) + ")");
+    // scattering matrices (not at the root)
+    std::vector<DevBuf> A1(n_inst), A2(n_inst), Yl(n_inst);
+    bool any = false;
+    for (int i : act) {
+      const lsh_plan_s& P = *Fs[i]->plan;
+      const int l = lev(i);
+      if (l == 0) continue;
+      any = true;
+      const int c = P.lev[l].c, nb = 1 << l, k = P.lev[l].k;
+      const long ck = (long)c * k;
+      A1[i].alloc(sizeof(c32) * nb * ck);
+      A2[i].alloc(sizeof(c32) * nb * ck);
+      Yl[i].alloc(sizeof(c32) * nb * ck);
+      Fs[i]->f32.S[l].alloc(sizeof(c32) * nb * (long)k * k);
+    }
+    if (any) {
+      auto each = [&](auto&& fn) {
+        for (int i : act) {
+          const lsh_plan_s& P = *Fs[i]->plan;
+          const int l = lev(i);
+          if (l == 0) continue;
+          const int c = P.lev[l].c, nb = 1 << l, k = P.lev[l].k;
+          fn(i, P, Fs[i]->f32, l, c, nb, k, (long)c * c, (long)c * k);
+        }
+      };
+      each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
+        const c32* Sch = F.S[l + 1].as<c32>();
+        const c32* U1 = P.U<float>(l);
+        gi.push_back({c, k, c, one, zero, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, nullptr, 0, 0, A1[i].as<c32>(), k,
+                      ck, nb, false});
+        gi.push_back({c, k, c, one, zero, Sch + cc, c, 2 * cc, OP_N, U1 + ck, k, 0, OP_N, nullptr, 0, 0,
+                      A2[i].as<c32>(), k, ck, nb, false});
+      });
+      run_gemms(tabs[2]);
+      each([&](int i, const lsh_plan_s&, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
+        gi.push_back({c, k, c, mone, one, F.Pb[l].as<c32>(), c, cc, OP_N, A1[i].as<c32>(), k, ck, OP_N,
+                      A2[i].as<c32>(), k, ck, A2[i].as<c32>(), k, ck, nb, false});
+      });
+      run_gemms(tabs[3]);
+      each([&](int i, const lsh_plan_s&, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
+        gi.push_back({c, k, c, one, zero, F.Ci[l].as<c32>(), c, cc, OP_N, A2[i].as<c32>(), k, ck, OP_N, nullptr, 0,
+                      0, Yl[i].as<c32>(), k, ck, nb, false});
+      });
+      run_gemms(tabs[4]);
+      each([&](int i, const lsh_plan_s&, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
+        gi.push_back({c, k, c, mone, one, F.Pa[l].as<c32>(), c, cc, OP_N, Yl[i].as<c32>(), k, ck, OP_N,
+                      A1[i].as<c32>(), k, ck, A1[i].as<c32>(), k, ck, nb, false});
+      });
+      run_gemms(tabs[5]);
+      each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long, long ck) {
+        gi.push_back({k, k, c, one, zero, P.U<float>(l), k, 0, OP_T, A1[i].as<c32>(), k, ck, OP_N, nullptr, 0, 0,
+                      F.S[l].as<c32>(), k, (long)k * k, nb, false});
+      });
+      run_gemms(tabs[6]);
+      each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long, long ck) {
+        gi.push_back({k, k, c, one, one, P.U<float>(l) + ck, k, 0, OP_T, Yl[i].as<c32>(), k, ck, OP_N,
+                      F.S[l].as<c32>(), k, (long)k * k, F.S[l].as<c32>(), k, (long)k * k, nb, false});
+      });
+      run_gemms(tabs[7]);
+    }
+    LSH_HIP(hipStreamSynchronize(s));  // scratch and tables of this level die here
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b, void* stream,
+                     lsh_factor_t* factors) {
+  API_BEGIN
+  LSH_REQUIRE(ninst >= 1 && plans && b && factors, LSH_ERR_INVALID_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<std::unique_ptr<lsh_factor_s>> own;
+  std::vector<lsh_factor_s*> f32;
+  for (int i = 0; i < ninst; ++i) {
+    lsh_plan_s* P = plans[i];
+    LSH_REQUIRE(P && b[i], LSH_ERR_INVALID_ARG, "null plan or b");
+    const long N = (long)P->n * P->n;
+    std::unique_ptr<lsh_factor_s> F(new lsh_factor_s());
+    F->plan = P;
+    F->b.alloc(sizeof(double) * N);
+    LSH_HIP(hipMemcpyAsync(F->b.p, b[i], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    DevBuf bad(sizeof(int));
+    fill_zero(s, bad.p, sizeof(int));
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
+    int hb = 0;
+    LSH_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries (instance " + std::to_string(i) + ")");
+    if (P->d.hbs_prec == LSH_FP32) f32.push_back(F.get());
+    else factor_build<double>(*P, F->b.as<double>(), F->f64, s);  // FP64 instances: one at a time
+    own.push_back(std::move(F));
+  }
+  if (!f32.empty()) batch_factor_f32(f32, s);
+  for (int i = 0; i < ninst; ++i) factors[i] = own[i].release();
+  return LSH_OK;
+  API_END
+}
+
 int lsh_factor_destroy(lsh_factor_t F) {
   API_BEGIN
   delete F;

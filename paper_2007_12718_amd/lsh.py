@@ -26,7 +26,7 @@ EXPORTED = [
     "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
     "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
-    "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build",
+    "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor",
 ]
 
 
@@ -76,6 +76,7 @@ def lib():
         L.lsh_factor_create.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]
         L.lsh_factor_destroy.argtypes = [c_void_p]
         L.lsh_build.argtypes = [POINTER(LshDesc), c_void_p, c_void_p, POINTER(c_void_p), POINTER(c_void_p)]
+        L.lsh_batch_factor.argtypes = [c_int, POINTER(c_void_p), POINTER(c_void_p), c_void_p, POINTER(c_void_p)]
         L.lsh_apply_precond.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p]
         L.lsh_apply_operator.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
         L.lsh_solve.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p, POINTER(LshSolveOpts),
@@ -305,6 +306,20 @@ def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32"
     _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), _stream(), ctypes.byref(P.handle),
                            ctypes.byref(fh)))
     return P, Factor(P, None, _handle=fh)
+
+
+def batch_factor(plans, bs):
+    """lsh_batch_factor: Algorithm 1 for many instances at once (each level's
+    products and inverses grouped over all instances); returns one Factor per
+    plan."""
+    import torch
+    n = len(plans)
+    bs = [b.reshape(p.n, p.n).contiguous() for p, b in zip(plans, bs)]
+    ph = (c_void_p * n)(*[p.handle.value for p in plans])
+    bp = (c_void_p * n)(*[_ptr(b, torch.float64).value for b in bs])
+    fh = (c_void_p * n)()
+    _check(lib().lsh_batch_factor(n, ph, bp, _stream(), fh))
+    return [Factor(p, None, _handle=c_void_p(fh[i])) for i, p in enumerate(plans)]
 
 
 def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None):
