@@ -48,6 +48,7 @@ struct GemmP {
   long ldc, sC;
   int addI;
   const int* skip;  // optional device flag: the whole launch is a no-op when *skip != 0
+  int lower;        // 1: only tiles that reach the diagonal or below it (M == N)
 };
 
 // Tile: 2 x 2 wavefronts, each owning WM x WN blocks of 16 x 16 outputs, so the
@@ -75,11 +76,14 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
   const long T = (long)gridDim.x * gridDim.y * gridDim.z;
   long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
   const long T8 = (T / 8) * 8;
-  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
+  // (lower-triangle mode keeps round-robin order: contiguous row bands per
+  // XCD would leave the bottom band with nearly all the work)
+  if (L < T8 && !P.lower) L = (L % 8) * (T / 8) + L / 8;
   const int tn = (int)(L % gridDim.x);
   const int tm = (int)((L / gridDim.x) % gridDim.y);
   const long b = L / ((long)gridDim.x * gridDim.y);
   const int m0 = tm * BM, n0 = tn * BN;
+  if (P.lower && n0 >= m0 + BM) return;  // strictly above the diagonal
   const cplx<R>* A = P.A + b * P.sA;
   const cplx<R>* B = P.B + b * P.sB;
   const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
@@ -343,10 +347,11 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {
   const long T = (long)gridDim.x * gridDim.y * gridDim.z;
   long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
   const long T8 = (T / 8) * 8;
-  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
+  if (L < T8 && !P.lower) L = (L % 8) * (T / 8) + L / 8;
   const int tn = (int)(L % gridDim.x);
   const int tm = (int)((L / gridDim.x) % gridDim.y);
   const long b = L / ((long)gridDim.x * gridDim.y);
+  if (P.lower && tn * BN >= (tm + 1) * BM) return;  // strictly above the diagonal
   cgemm_x32_tile<WM, WN>(P, b, tm * BM, tn * BN);
 }
 
@@ -442,10 +447,12 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            const cplx<R>* A, long lda, long sA, Op opA,
            const cplx<R>* B, long ldb, long sB, Op opB,
            cplx<R> beta, const cplx<R>* D, long ldd, long sD,
-           cplx<R>* C, long ldc, long sC, int batch, bool add_identity, const int* skip) {
+           cplx<R>* C, long ldc, long sC, int batch, bool add_identity, const int* skip, bool lower) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
+  LSH_REQUIRE(!lower || M == N, -1, "cgemm: lower-triangle mode needs a square result");
   GemmP<R> P;
   P.skip = skip;
+  P.lower = lower ? 1 : 0;
   P.M = M; P.N = N; P.K = K; P.alpha = alpha; P.beta = beta;
   P.A = A; P.lda = lda; P.sA = sA; P.opA = opA;
   P.B = B; P.ldb = ldb; P.sB = sB; P.opB = opB;
@@ -477,7 +484,7 @@ void cgemm_grouped(hipStream_t s, const std::vector<GemmItem>& items, DevBuf& de
     P.A = it.A; P.lda = it.lda; P.sA = it.sA; P.opA = it.opA;
     P.B = it.B; P.ldb = it.ldb; P.sB = it.sB; P.opB = it.opB;
     P.D = it.D; P.ldd = it.ldd; P.sD = it.sD;
-    P.C = it.C; P.ldc = it.ldc; P.sC = it.sC; P.addI = it.addI ? 1 : 0; P.skip = nullptr;
+    P.C = it.C; P.ldc = it.ldc; P.sC = it.sC; P.addI = it.addI ? 1 : 0; P.skip = nullptr; P.lower = 0;
     g.batch = it.batch;
     g.tiles_m = ceil_div(it.M, 64);
     g.tiles_n = ceil_div(it.N, 64);
@@ -498,6 +505,34 @@ void cgemm_grouped(hipStream_t s, const std::vector<GemmItem>& items, DevBuf& de
   // the table must outlive the copy: pageable copies are staged before
   // hipMemcpyAsync returns, so the host vector may go out of scope here
 }
+
+// C[i][j] = conj(C[j][i]) for j > i (32 x 32 tiles through LDS)
+template <typename R>
+__global__ __launch_bounds__(256) void k_mirror_lower(cplx<R>* C, int n, long ldc) {
+  __shared__ cplx<R> t[32][33];
+  const int tr = blockIdx.y, tc = blockIdx.x;  // destination tile (row tr, column tc), tc >= tr
+  if (tc < tr) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {  // source: rows of tile (tc, tr)
+    const int i = tc * 32 + r, j = tr * 32 + tx;
+    t[r][tx] = (i < n && j < n) ? C[(long)i * ldc + j] : mk<R>(0, 0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = tr * 32 + r, j = tc * 32 + tx;
+    if (i < n && j < n && j > i) C[(long)i * ldc + j] = conjg(t[tx][r]);
+  }
+}
+
+template <typename R>
+void mirror_lower(hipStream_t s, cplx<R>* C, int n, long ldc) {
+  if (n <= 1) return;
+  const int nt = ceil_div(n, 32);
+  hipLaunchKernelGGL(k_mirror_lower<R>, dim3(nt, nt), dim3(256), 0, s, C, n, ldc);
+  LSH_LAUNCH_CHECK();
+}
+template void mirror_lower<double>(hipStream_t, cplx<double>*, int, long);
+template void mirror_lower<float>(hipStream_t, cplx<float>*, int, long);
 
 // ---------------------------------------------------------------- GEMV
 // One wavefront per row, lanes stride the row (coalesced); x_b staged in LDS.
@@ -1339,7 +1374,7 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
 #define LSH_INST(R)                                                                                        \
   template void cgemm<R>(hipStream_t, int, int, int, cplx<R>, const cplx<R>*, long, long, Op, const cplx<R>*, \
                          long, long, Op, cplx<R>, const cplx<R>*, long, long, cplx<R>*, long, long, int, bool, \
-                         const int*);                                                                      \
+                         const int*, bool);                                                                \
   template void cgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, long, int, const cplx<R>*, long, \
                          cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                               \
   template void cmgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, const cplx<R>*, long, cplx<R>, \

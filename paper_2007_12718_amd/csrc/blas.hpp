@@ -18,12 +18,19 @@ enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2, OP_R = 3 };
 //   op(B) is K x N (B stored K x N for OP_N, N x K for OP_T / OP_C)
 // D may alias C (in-place accumulate).  Runs on MFMA (16x16x4 f32 / f64).
 // skip (optional, device): when *skip != 0 at launch time the call does nothing.
+// lower (M == N): compute only the output tiles that reach the diagonal or
+// lie below it (for Hermitian products, with mirror_lower afterwards).
 template <typename R>
 void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            const cplx<R>* A, long lda, long sA, Op opA,
            const cplx<R>* B, long ldb, long sB, Op opB,
            cplx<R> beta, const cplx<R>* D, long ldd, long sD,
-           cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false, const int* skip = nullptr);
+           cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false, const int* skip = nullptr,
+           bool lower = false);
+
+// C[i][j] = conj(C[j][i]) for j > i: completes a Hermitian matrix from its lower triangle
+template <typename R>
+void mirror_lower(hipStream_t s, cplx<R>* C, int n, long ldc);
 
 // Many batched FP32 GEMMs of different shapes in one launch (64 x 64 tiles,
 // the same arithmetic as cgemm<float>, so each result is bitwise that of

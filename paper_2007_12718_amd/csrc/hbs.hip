@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <functional>
 #include <vector>
 
 #include "hbs.hpp"
@@ -449,7 +450,7 @@ __global__ void k_scatter_U(z64* U, int k, const int* piv, const int* rest, int 
 // pivot count, done flag) lives on the device: the host queues steps in
 // batches and reads the done flag once per batch; a step queued after the
 // end returns at entry.
-constexpr int BP_B = 48, BP_NP = 32, BP_KC = 64, BP_SUB = 32, BP_SEL = 4096;
+constexpr int BP_B = 48, BP_NP = 32, BP_KC = 128, BP_KCS = 64, BP_SUB = 32, BP_SEL = 4096;
 // state words (int): 0 rank j, 1 done, 2 pivots of this step, 3 candidates,
 // 4..5 dout (double), 6 error flag, 8..8+BP_B candidate rows
 constexpr int BPS_J = 0, BPS_DONE = 1, BPS_NP = 2, BPS_NC = 3, BPS_DOUT = 4, BPS_ERR = 6, BPS_CAND = 8,
@@ -582,38 +583,69 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
   }
 }
 
-// S_C partial sums over depth chunk c (BP_KC deep, staged BP_SUB at a time):
-// part[c][a][b] = sum_{t in chunk, t < j} L(C_a, t) conj(L(C_b, t)).
+// S_C partial sums: blockIdx.x = depth chunk c (BP_KCS deep, staged BP_SUB
+// at a time), blockIdx.y = output quadrant (rows a0.., columns b0.., each
+// BP_B / 2 wide): part[c][a][b] = sum_{t in chunk, t < j} L(C_a, t) conj(L(C_b, t)).
 __global__ __launch_bounds__(256) void k_bp_sc(const z64* Lt, int m, const int* st, z64* part) {
-  __shared__ z64 Lc[BP_SUB][BP_B + 1];
-  constexpr int PER = BP_B * BP_B / 256;
+  constexpr int H = BP_B / 2, PER = (H * H + 255) / 256;
+  __shared__ z64 La[BP_SUB][H + 1], Lb2[BP_SUB][H + 1];
   if (st[BPS_DONE]) return;
   const int j = st[BPS_J], nc = st[BPS_NC];
-  const int c = blockIdx.x, t0 = c * BP_KC;
+  const int c = blockIdx.x, t0 = c * BP_KCS;
   if (t0 >= j) return;
+  const int a0 = (blockIdx.y >> 1) * H, b0 = (blockIdx.y & 1) * H;
   const int tid = threadIdx.x;
   const int* cand = st + BPS_CAND;
   z64 acc[PER];
 #pragma unroll
   for (int r = 0; r < PER; ++r) acc[r] = mk(0.0, 0.0);
-  const int tend = (j - t0) < BP_KC ? j : t0 + BP_KC;
+  const int tend = (j - t0) < BP_KCS ? j : t0 + BP_KCS;
   for (int s0 = t0; s0 < tend; s0 += BP_SUB) {
     __syncthreads();
-    for (int e = tid; e < BP_SUB * BP_B; e += 256) {
-      const int t = e / BP_B, a = e % BP_B;
-      Lc[t][a] = (a < nc && s0 + t < tend) ? Lt[(long)(s0 + t) * m + cand[a]] : mk(0.0, 0.0);
+    for (int e = tid; e < 2 * BP_SUB * H; e += 256) {
+      const int half = e / (BP_SUB * H), f = e % (BP_SUB * H), t = f / H, a = f % H;
+      const int row = (half ? b0 : a0) + a;
+      const z64 v = (row < nc && s0 + t < tend) ? Lt[(long)(s0 + t) * m + cand[row]] : mk(0.0, 0.0);
+      if (half) Lb2[t][a] = v;
+      else La[t][a] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + r * 256, a = e / BP_B, b = e % BP_B;
-      z64 v = acc[r];
-      for (int t = 0; t < BP_SUB; ++t) v = v + Lc[t][a] * conjg(Lc[t][b]);
-      acc[r] = v;
+      const int e = tid + r * 256;
+      if (e < H * H) {
+        const int a = e / H, b = e % H;
+        z64 v = acc[r];
+        for (int t = 0; t < BP_SUB; ++t) v = v + La[t][a] * conjg(Lb2[t][b]);
+        acc[r] = v;
+      }
     }
   }
 #pragma unroll
-  for (int r = 0; r < PER; ++r) part[(long)c * BP_B * BP_B + tid + r * 256] = acc[r];
+  for (int r = 0; r < PER; ++r) {
+    const int e = tid + r * 256;
+    if (e < H * H) {
+      const int a = a0 + e / H, b = b0 + e % H;
+      part[(long)c * BP_B * BP_B + a * BP_B + b] = acc[r];
+    }
+  }
+}
+
+// S_C = M[C,C] - sum_c part[c]  (rows/columns past the candidates: zero)
+__global__ void k_bp_sc_reduce(const z64* M, int m, const z64* part, const int* st, z64* S) {
+  if (st[BPS_DONE]) return;
+  const int j = st[BPS_J], nc = st[BPS_NC];
+  const int nch = (j + BP_KCS - 1) / BP_KCS;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= BP_B * BP_B) return;
+  const int a = e / BP_B, b = e % BP_B;
+  const int* cand = st + BPS_CAND;
+  z64 v = mk(0.0, 0.0);
+  if (a < nc && b < nc) {
+    v = M[(long)cand[a] * m + cand[b]];
+    for (int c = 0; c < nch; ++c) v = v - part[(long)c * BP_B * BP_B + e];
+  }
+  S[e] = v;
 }
 
 // Greedy pivoted Cholesky of the candidate block S (first nc rows valid)
@@ -621,8 +653,8 @@ __global__ __launch_bounds__(256) void k_bp_sc(const z64* Lt, int m, const int* 
 // most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
 // pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
 // pivot qualifies.
-__global__ __launch_bounds__(256) void k_bp_chol(const z64* M, int m, const z64* part, double thr2, int* J, int* st,
-                                                 z64* Lpp, z64* Linv) {
+__global__ __launch_bounds__(256) void k_bp_chol(const z64* Sg, int m, double thr2, int* J, int* st, z64* Lpp,
+                                                 z64* Linv) {
   __shared__ z64 S[BP_B][BP_B + 1];
   __shared__ z64 Lb[BP_B][BP_NP];  // Cholesky columns for every candidate row
   __shared__ int piv[BP_NP];
@@ -634,17 +666,7 @@ __global__ __launch_bounds__(256) void k_bp_chol(const z64* M, int m, const z64*
   const int nc = st[BPS_NC], j = st[BPS_J];
   const double dout = reinterpret_cast<const double*>(st + BPS_DOUT)[0];
   const int* cand = st + BPS_CAND;
-  // S_C = M[C,C] - (sum of the depth-chunk partial products)
-  const int nch = (j + BP_KC - 1) / BP_KC;
-  for (int e = tid; e < BP_B * BP_B; e += 256) {
-    const int a = e / BP_B, b = e % BP_B;
-    z64 v = mk(0.0, 0.0);
-    if (a < nc && b < nc) {
-      v = M[(long)cand[a] * m + cand[b]];
-      for (int c = 0; c < nch; ++c) v = v - part[(long)c * BP_B * BP_B + e];
-    }
-    S[a][b] = v;
-  }
+  for (int e = tid; e < BP_B * BP_B; e += 256) S[e / BP_B][e % BP_B] = Sg[e];
   for (int a = tid; a < BP_B; a += 256) picked[a] = 0;
   for (int e = tid; e < BP_B * BP_NP; e += 256) Lb[e / BP_NP][e % BP_NP] = mk(0.0, 0.0);
   if (tid == 0) s_np = 0;
@@ -675,9 +697,9 @@ __global__ __launch_bounds__(256) void k_bp_chol(const z64* M, int m, const z64*
     // column t and the Schur update read only row/column p, which neither writes
     for (int a = tid; a < nc; a += 256)
       if (a == p || !picked[a]) Lb[a][t] = a == p ? mk(lpp, 0.0) : rl * S[a][p];
-    for (int e = tid; e < nc * nc; e += 256) {
-      const int a = e / nc, b = e % nc;
-      if (a != p && b != p) S[a][b] = S[a][b] - (rl * S[a][p]) * conjg(rl * S[b][p]);
+    for (int e = tid; e < BP_B * BP_B; e += 256) {
+      const int a = e / BP_B, b = e % BP_B;  // (constant divisor)
+      if (a < nc && b < nc && a != p && b != p) S[a][b] = S[a][b] - (rl * S[a][p]) * conjg(rl * S[b][p]);
     }
     __syncthreads();
   }
@@ -744,10 +766,14 @@ __device__ __forceinline__ void bp_wt_body(const z64* Lt, const int* Pq, int m, 
     __syncthreads();
     if (live) {
       const int tn = (tend - s0) < 2 * BP_SUB ? (tend - s0) : 2 * BP_SUB;
-      for (int t = 0; t < tn; ++t) {
-        const z64 l = Lt[(long)(s0 + t) * m + i];
+      for (int tb = 0; tb < tn; tb += 8) {  // eight independent loads in flight
+        z64 l[8];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + Lp[t][q] * l;
+        for (int u = 0; u < 8; ++u) l[u] = tb + u < tn ? Lt[(long)(s0 + tb + u) * m + i] : mk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + Lp[tb + u][q] * l[u];
       }
     }
   }
@@ -777,60 +803,72 @@ __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, cons
 // New factor rows Lt[j+q][i] = sum_q' conj(Linv[q][q']) W[q'][i] with
 // W[q'][i] = conj(M[P_q'][i]) - sum_c part[c][q'][i]; then rows already
 // chosen get exact zeros, the pivot rows get Lpp exactly, other rows have
-// their Schur diagonal reduced, and the pivots are marked chosen.
-__global__ __launch_bounds__(256) void k_bp_newcols(z64* Lt, const z64* M, int m, const int* J, const z64* part,
-                                                    const z64* Lpp, const z64* Linv, int* chosen, double* d,
-                                                    const int* st) {
-  __shared__ z64 Li[BP_NP][BP_NP];
+// their Schur diagonal reduced, and the pivots are marked chosen.  A
+// workgroup takes 32 rows i; thread (q, i) forms W[q][i] (its chunk sum
+// spread over all threads), the products go through LDS.
+constexpr int BP_NCR = 32;
+static_assert(BP_NCR == BP_NP && BP_NCR * BP_NP == 1024, "one thread per (pivot, row) pair");
+__global__ __launch_bounds__(1024) void k_bp_newcols(z64* Lt, const z64* M, int m, const int* J, const z64* part,
+                                                     const z64* Lpp, const z64* Linv, int* chosen, double* d,
+                                                     const int* st) {
+  __shared__ z64 W[BP_NP][BP_NCR + 1];
+  __shared__ z64 Li[BP_NP][BP_NP + 1];
+  __shared__ double sd[BP_NP][BP_NCR + 1];
   if (st[BPS_DONE]) return;
   const int j = st[BPS_J], np = st[BPS_NP];
   const int nch = (j + BP_KC - 1) / BP_KC;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < BP_NP * BP_NP; e += 256) Li[e / BP_NP][e % BP_NP] = conjg(Linv[e]);
-  __syncthreads();
-  const int i = blockIdx.x * 256 + tid;
-  if (i >= m) return;
+  const int tid = threadIdx.x, q = tid / BP_NCR, ii = tid % BP_NCR;
+  const int i = blockIdx.x * BP_NCR + ii;
   const int* Pq = J + j;
-  int q0 = -1;
-  for (int q = 0; q < np; ++q)
-    if (Pq[q] == i) q0 = q;
-  if (q0 >= 0) {
-    for (int q = 0; q < np; ++q) Lt[(long)(j + q) * m + i] = Lpp[q0 * BP_NP + q];
-    chosen[i] = 1;
-    d[i] = 0.0;
-    return;
-  }
-  if (chosen[i]) {
-    for (int q = 0; q < np; ++q) Lt[(long)(j + q) * m + i] = mk(0.0, 0.0);
-    return;
-  }
-  z64 w[BP_NP];
-#pragma unroll
-  for (int q = 0; q < BP_NP; ++q) {
-    z64 v = mk(0.0, 0.0);
-    if (q < np) {
-      v = conjg(M[(long)Pq[q] * m + i]);
-      for (int c = 0; c < nch; ++c) v = v - part[((long)c * BP_NP + q) * m + i];
+  Li[q][ii] = conjg(Linv[q * BP_NP + ii]);  // (BP_NCR == BP_NP: one entry per thread)
+  z64 w = mk(0.0, 0.0);
+  if (i < m && q < np && !chosen[i]) {
+    w = conjg(M[(long)Pq[q] * m + i]);
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+      const z64 p0 = part[((long)(c + 0) * BP_NP + q) * m + i], p1 = part[((long)(c + 1) * BP_NP + q) * m + i];
+      const z64 p2 = part[((long)(c + 2) * BP_NP + q) * m + i], p3 = part[((long)(c + 3) * BP_NP + q) * m + i];
+      w = w - p0;
+      w = w - p1;
+      w = w - p2;
+      w = w - p3;
     }
-    w[q] = v;
+    for (; c < nch; ++c) w = w - part[((long)c * BP_NP + q) * m + i];
   }
-  double sd = 0.0;
-  for (int q = 0; q < np; ++q) {
-    z64 v = mk(0.0, 0.0);
-#pragma unroll
-    for (int r = 0; r < BP_NP; ++r)
-      if (r <= q) v = v + Li[q][r] * w[r];
+  W[q][ii] = w;
+  __syncthreads();
+  const bool live = i < m;
+  int q0 = -1;
+  for (int r = 0; r < np; ++r)
+    if (live && Pq[r] == i) q0 = r;
+  const bool was_chosen = live && chosen[i] != 0;
+  z64 v = mk(0.0, 0.0);
+  if (live && q < np) {
+    if (q0 >= 0) v = Lpp[q0 * BP_NP + q];
+    else if (!was_chosen)
+      for (int r = 0; r <= q; ++r) v = v + Li[q][r] * W[r][ii];
     Lt[(long)(j + q) * m + i] = v;
-    sd += abs2(v);
   }
-  d[i] -= sd;
+  sd[q][ii] = abs2(v);
+  __syncthreads();
+  if (live && q == 0) {
+    if (q0 >= 0) {
+      chosen[i] = 1;
+      d[i] = 0.0;
+    } else if (!was_chosen) {
+      double t = 0.0;
+      for (int r = 0; r < np; ++r) t += sd[r][ii];
+      d[i] -= t;
+    }
+  }
 }
 
 size_t rowid_bp_ws(int m) {
   const size_t mm = (size_t)m * m, mp = (size_t)m + BP_KC;
   const size_t nch = mp / BP_KC + 1;
   return sizeof(z64) * (mm + mp * m + 2 * mm) + sizeof(double) * m + sizeof(int) * (3 * m + BPS_WORDS) +
-         sizeof(z64) * (BP_B * BP_B + 2 * BP_NP * BP_NP + nch * BP_B * BP_B + nch * (size_t)BP_NP * m) +
+         sizeof(z64) * (BP_B * BP_B + 2 * BP_NP * BP_NP + (mp / BP_KCS + 1) * BP_B * BP_B +
+                        nch * (size_t)BP_NP * m) +
          inverse_ws_bytes<double>(64, m / 64 + 1) + sizeof(z64) * (size_t)(m / 64 + 1) * 64 * 64 + 32 * 256;
 }
 
@@ -866,15 +904,23 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
     LSH_LAUNCH_CHECK();
     inverse<double>(s, Dinv, DB, DB, (long)DB * DB, nblk, invws, nullptr);
     z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
-    for (int q = nblk - 1; q >= 0; --q) {
-      const int b0 = q * DB, b1 = (b0 + DB < k) ? b0 + DB : k, w = b1 - b0;
-      if (b1 < k)  // Lr(:, B) -= X(:, b1:k) L11(b1:k, B)
-        cgemm<double>(s, nr, w, k - b1, mk(-1.0, 0.0), X + b1, k, 0, OP_N, L11 + (long)b1 * k + b0, k, 0, OP_N,
-                      mk(1.0, 0.0), Lr + b0, k, 0, Lr + b0, k, 0, 1);
-      // X(:, B) = Lr(:, B) L11(B, B)^{-1}
-      cgemm<double>(s, nr, w, w, mk(1.0, 0.0), Lr + b0, k, 0, OP_N, Dinv + (long)q * DB * DB, DB, 0, OP_N,
-                    mk(0.0, 0.0), nullptr, 0, 0, X + b0, k, 0, 1);
-    }
+    // X L11 = Lr, recursively on column halves (L11 lower triangular):
+    // X(:, right) first, then Lr(:, left) -= X(:, right) L11(right, left),
+    // then X(:, left); diagonal blocks of DB columns use their inverses
+    std::function<void(int, int)> solve = [&](int q0, int q1) {  // diagonal blocks q0 .. q1-1
+      const int c0 = q0 * DB, c1 = (q1 * DB < k) ? q1 * DB : k;
+      if (q1 - q0 == 1) {  // X(:, B) = Lr(:, B) L11(B, B)^{-1}
+        cgemm<double>(s, nr, c1 - c0, c1 - c0, mk(1.0, 0.0), Lr + c0, k, 0, OP_N, Dinv + (long)q0 * DB * DB, DB, 0,
+                      OP_N, mk(0.0, 0.0), nullptr, 0, 0, X + c0, k, 0, 1);
+        return;
+      }
+      const int qm = (q0 + q1) / 2, cm = qm * DB;
+      solve(qm, q1);
+      cgemm<double>(s, nr, cm - c0, c1 - cm, mk(-1.0, 0.0), X + cm, k, 0, OP_N, L11 + (long)cm * k + c0, k, 0, OP_N,
+                    mk(1.0, 0.0), Lr + c0, k, 0, Lr + c0, k, 0, 1);
+      solve(q0, qm);
+    };
+    solve(0, nblk);
     hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)(k + nr) * k, 256)), dim3(256), 0, s, U, k, J, rest, nr, X);
   } else {
     hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J, rest, 0, L11);
@@ -887,7 +933,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t bytes) { char* r = p; p += ((bytes + 255) / 256) * 256; return (void*)r; };
   const size_t mp = (size_t)m + BP_KC;
-  const int nch = (int)(mp / BP_KC) + 1;
+  const int nch = (int)(mp / BP_KC) + 1, nchS = (int)(mp / BP_KCS) + 1;
   z64* M = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
   z64* Lt = static_cast<z64*>(take(sizeof(z64) * mp * m));
   z64* L11 = static_cast<z64*>(take(sizeof(z64) * (size_t)m * m));
@@ -898,13 +944,16 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64
   int* st = static_cast<int*>(take(sizeof(int) * BPS_WORDS));
   z64* Lpp = static_cast<z64*>(take(sizeof(z64) * BP_NP * BP_NP));
   z64* Linv = static_cast<z64*>(take(sizeof(z64) * BP_NP * BP_NP));
-  z64* partS = static_cast<z64*>(take(sizeof(z64) * (size_t)nch * BP_B * BP_B));
+  z64* Sc = static_cast<z64*>(take(sizeof(z64) * BP_B * BP_B));
+  z64* partS = static_cast<z64*>(take(sizeof(z64) * (size_t)nchS * BP_B * BP_B));
   z64* partW = static_cast<z64*>(take(sizeof(z64) * (size_t)nch * BP_NP * m));
   const int DB = 64;
   z64* Dinv = static_cast<z64*>(take(sizeof(z64) * (size_t)(m / DB + 1) * DB * DB));
   void* invws = take(inverse_ws_bytes<double>(DB, m / DB + 1));
   // Gram matrix and its diagonal; the factor starts at zero
-  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1);
+  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1,
+                false, nullptr, true);  // Hermitian: lower tiles, then the mirror
+  mirror_lower<double>(s, M, m, m);
   fill_zero(s, Lt, sizeof(z64) * mp * m);
   fill_zero(s, st, sizeof(int) * BPS_WORDS);
   hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, st + BPS_WORDS - 4);
@@ -926,11 +975,13 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64
         hipLaunchKernelGGL(k_bp_select, dim3(1), dim3(1024), 0, s, d, chosen, m, thr2, st);
       }
       LSH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_bp_sc, dim3(nch), dim3(256), 0, s, Lt, m, st, partS);
+      hipLaunchKernelGGL(k_bp_sc, dim3(nchS, 4), dim3(256), 0, s, Lt, m, st, partS);
+      LSH_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_bp_sc_reduce, dim3(ceil_div(BP_B * BP_B, 256)), dim3(256), 0, s, M, m, partS, st, Sc);
       LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
-        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(256), 0, s, M, m, partS, thr2, J, st, Lpp, Linv);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(256), 0, s, Sc, m, thr2, J, st, Lpp, Linv);
       }
       LSH_LAUNCH_CHECK();
       {
@@ -938,7 +989,8 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64
         hipLaunchKernelGGL(k_bp_wt, dim3(gm, nch), dim3(256), 0, s, Lt, J, chosen, m, st, partW);
       }
       LSH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_bp_newcols, dim3(gm), dim3(256), 0, s, Lt, M, m, J, partW, Lpp, Linv, chosen, d, st);
+      hipLaunchKernelGGL(k_bp_newcols, dim3(ceil_div(m, BP_NCR)), dim3(1024), 0, s, Lt, M, m, J, partW, Lpp, Linv,
+                         chosen, d, st);
       LSH_LAUNCH_CHECK();
     }
     LSH_HIP(hipMemcpyAsync(host_st, st, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
@@ -989,7 +1041,9 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
   const int DB = 64;
   z64* Dinv = static_cast<z64*>(take(sizeof(z64) * (size_t)(m / DB + 1) * DB * DB));
   void* invws = take(inverse_ws_bytes<double>(DB, m / DB + 1));
-  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1);
+  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1,
+                false, nullptr, true);  // Hermitian: lower tiles, then the mirror
+  mirror_lower<double>(s, M, m, m);
   hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, state);
   LSH_LAUNCH_CHECK();
   // ||A||_F^2 = trace(M)
@@ -1073,15 +1127,23 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
     LSH_LAUNCH_CHECK();
     inverse<double>(s, Dinv, DB, DB, (long)DB * DB, nblk, invws, nullptr);
     z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
-    for (int q = nblk - 1; q >= 0; --q) {
-      const int b0 = q * DB, b1 = (b0 + DB < k) ? b0 + DB : k, w = b1 - b0;
-      if (b1 < k)  // Lr(:, B) -= X(:, b1:k) L11(b1:k, B)
-        cgemm<double>(s, nr, w, k - b1, mk(-1.0, 0.0), X + b1, k, 0, OP_N, L11 + (long)b1 * k + b0, k, 0, OP_N,
-                      mk(1.0, 0.0), Lr + b0, k, 0, Lr + b0, k, 0, 1);
-      // X(:, B) = Lr(:, B) L11(B, B)^{-1}
-      cgemm<double>(s, nr, w, w, mk(1.0, 0.0), Lr + b0, k, 0, OP_N, Dinv + (long)q * DB * DB, DB, 0, OP_N,
-                    mk(0.0, 0.0), nullptr, 0, 0, X + b0, k, 0, 1);
-    }
+    // X L11 = Lr, recursively on column halves (L11 lower triangular):
+    // X(:, right) first, then Lr(:, left) -= X(:, right) L11(right, left),
+    // then X(:, left); diagonal blocks of DB columns use their inverses
+    std::function<void(int, int)> solve = [&](int q0, int q1) {  // diagonal blocks q0 .. q1-1
+      const int c0 = q0 * DB, c1 = (q1 * DB < k) ? q1 * DB : k;
+      if (q1 - q0 == 1) {  // X(:, B) = Lr(:, B) L11(B, B)^{-1}
+        cgemm<double>(s, nr, c1 - c0, c1 - c0, mk(1.0, 0.0), Lr + c0, k, 0, OP_N, Dinv + (long)q0 * DB * DB, DB, 0,
+                      OP_N, mk(0.0, 0.0), nullptr, 0, 0, X + c0, k, 0, 1);
+        return;
+      }
+      const int qm = (q0 + q1) / 2, cm = qm * DB;
+      solve(qm, q1);
+      cgemm<double>(s, nr, cm - c0, c1 - cm, mk(-1.0, 0.0), X + cm, k, 0, OP_N, L11 + (long)cm * k + c0, k, 0, OP_N,
+                    mk(1.0, 0.0), Lr + c0, k, 0, Lr + c0, k, 0, 1);
+      solve(q0, qm);
+    };
+    solve(0, nblk);
     hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)(k + nr) * k, 256)), dim3(256), 0, s, U, k, J, rest, nr, X);
   } else {
     hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J, rest, 0, L11);

@@ -182,10 +182,10 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     LSH_HIP(hipStreamSynchronize(s));
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
   } else {
-    // one-pivot-at-a-time panels by default; LSH_ROWID=block selects the
-    // block-pivoted left-looking variant (the same greedy pivots)
+    // block-pivoted left-looking Cholesky by default; LSH_ROWID=panel selects
+    // the one-pivot-at-a-time panels (the same greedy pivots)
     const char* e = std::getenv("LSH_ROWID");
-    const bool block = e && std::string(e) == "block";
+    const bool block = !(e && std::string(e) == "panel");
     if (!block) {
       DevBuf ws(rowid_gram_ws(m));
       k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
