@@ -106,6 +106,48 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// Stream-ordered scratch (hipMallocAsync / hipFreeAsync on one stream): no
+// device-wide synchronisation on release, unlike hipFree.  The device's
+// default pool keeps freed memory for reuse (release threshold raised once).
+inline void retain_async_pool() {
+  static bool done = [] {
+    int dev = 0;
+    hipMemPool_t pool;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    return true;
+  }();
+  (void)done;
+}
+
+struct AsyncBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  AsyncBuf() = default;
+  AsyncBuf(size_t n, hipStream_t st) { alloc(n, st); }
+  void alloc(size_t n, hipStream_t st) {
+    release();
+    retain_async_pool();
+    s = st;
+    bytes = n;
+    if (n) LSH_HIP(hipMallocAsync(&p, n, st));
+  }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~AsyncBuf() { release(); }
+  AsyncBuf(const AsyncBuf&) = delete;
+  AsyncBuf& operator=(const AsyncBuf&) = delete;
+  AsyncBuf(AsyncBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s) { o.p = nullptr; o.bytes = 0; }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
 inline int ceil_div(long a, long b) { return int((a + b - 1) / b); }
 
 }  // namespace lsh

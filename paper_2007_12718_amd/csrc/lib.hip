@@ -136,6 +136,14 @@ DevBuf upload(const std::vector<T>& v, hipStream_t s) {
   return b;
 }
 
+// scratch copy of a host vector, freed in stream order
+template <typename T>
+AsyncBuf upload_async(const std::vector<T>& v, hipStream_t s) {
+  AsyncBuf b(sizeof(T) * (v.size() ? v.size() : 1), s);
+  if (!v.empty()) LSH_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+  return b;
+}
+
 void validate(const lsh_desc& d) {
   LSH_REQUIRE(d.n >= 4 && d.n <= 2048, LSH_ERR_INVALID_ARG, "n must be in [4, 2048]");
   LSH_REQUIRE(d.h > 0 && std::isfinite(d.h), LSH_ERR_INVALID_ARG, "h must be positive");
@@ -162,16 +170,16 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     lv.U64 = upload(I, s);
     return;
   }
-  DevBuf dc = upload(lv.cand, s), dp = upload(prox, s);
-  DevBuf A(sizeof(z64) * (size_t)m * np);
+  AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
+  AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
   gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
-  DevBuf J(sizeof(int) * m), Ufull(sizeof(z64) * (size_t)m * m);
+  AsyncBuf J(sizeof(int) * m, s), Ufull(sizeof(z64) * (size_t)m * m, s);
   int k = 0;
   // Gram + pivoted Cholesky squares the conditioning: FP64 resolves the
   // stopping rule only while tol stays above ~1e-7; below that, CPQR.
   if (P.d.tol < 1e-7) {
     // ||A||_F for the stopping rule |R_kk| <= tol ||A||_F (computed on device)
-    DevBuf ws(rowid_cpqr_ws(m)), kd(sizeof(int)), fro(sizeof(z64)), part(multidot_partial_bytes(1));
+    AsyncBuf ws(rowid_cpqr_ws(m), s), kd(sizeof(int), s), fro(sizeof(z64), s), part(multidot_partial_bytes(1), s);
     multidot(s, A.as<z64>(), 0, 1, A.as<z64>(), (long)m * np, fro.as<z64>(), part.as<z64>());
     z64 f2;
     LSH_HIP(hipMemcpyAsync(&f2, fro.p, sizeof(z64), hipMemcpyDeviceToHost, s));
@@ -187,10 +195,10 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     const char* e = std::getenv("LSH_ROWID");
     const bool block = !(e && std::string(e) == "panel");
     if (!block) {
-      DevBuf ws(rowid_gram_ws(m));
+      AsyncBuf ws(rowid_gram_ws(m), s);
       k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
     } else {
-      DevBuf ws(rowid_bp_ws(m));
+      AsyncBuf ws(rowid_bp_ws(m), s);
       k = rowid_bp(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
     }
   }
@@ -301,7 +309,7 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
     }
     Level& lv = P.lev[l];
     lv.c = ch.k;
-    DevBuf da = upload(ra, s), db = upload(rb, s);
+    AsyncBuf da = upload_async(ra, s), db = upload_async(rb, s);
     const long cc = (long)lv.c * lv.c;
     lv.Gab64.alloc(sizeof(z64) * cc);
     gather_table(s, P.table.as<z64>(), P.D, da.as<I2>(), lv.c, db.as<I2>(), lv.c, lv.Gab64.as<z64>(), lv.c);
@@ -352,7 +360,28 @@ struct FactorData {
   std::vector<DevBuf> ST, PaT, PbT, CiT;
   std::vector<DevBuf> vb;         // transpose pass: per parent level [nrhs][2^l][2c]
   int vb_nrhs = 0;
+  // singularity flags of the local inverses, read back once when the factor ends
+  std::vector<DevBuf> info;
+  std::vector<int> info_n;
+  std::vector<std::string> info_what;
 };
+
+// Read back every pending singularity flag (one synchronisation) and raise
+// on the first singular local matrix.
+template <typename R>
+void factor_check(FactorData<R>& F, hipStream_t s) {
+  std::vector<std::vector<int>> h(F.info.size());
+  for (size_t q = 0; q < F.info.size(); ++q) {
+    h[q].resize(F.info_n[q]);
+    LSH_HIP(hipMemcpyAsync(h[q].data(), F.info[q].p, sizeof(int) * F.info_n[q], hipMemcpyDeviceToHost, s));
+  }
+  LSH_HIP(hipStreamSynchronize(s));
+  for (size_t q = 0; q < h.size(); ++q)
+    for (int v : h[q]) LSH_REQUIRE(!v, LSH_ERR_SINGULAR, F.info_what[q]);
+  F.info.clear();
+  F.info_n.clear();
+  F.info_what.clear();
+}
 
 int check_info(const DevBuf& info, int batch, hipStream_t s) {
   std::vector<int> h(batch);
@@ -383,12 +412,13 @@ void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipSt
   cplx<R>* X = F.X.template as<cplx<R>>();
   leaf_build<R>(s, X, P.Gleaf<R>(), mL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
   {
-    DevBuf ws(inverse_ws_bytes<R>(mL, nleaf)), info(sizeof(int) * nleaf);
-    inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws.p, info.as<int>());
-    int bad = check_info(info, nleaf, s);
-    LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular leaf matrix I + B G");
+    AsyncBuf ws(inverse_ws_bytes<R>(mL, nleaf), s);
+    F.info.emplace_back(sizeof(int) * nleaf);
+    F.info_n.push_back(nleaf);
+    F.info_what.push_back("singular leaf matrix I + B G");
+    inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws.p, F.info.back().template as<int>());
   }
-  DevBuf Y(sizeof(cplx<R>) * (size_t)nleaf * mL * kL), Z(sizeof(cplx<R>) * (size_t)nleaf * mL * kL);
+  AsyncBuf Y(sizeof(cplx<R>) * (size_t)nleaf * mL * kL, s), Z(sizeof(cplx<R>) * (size_t)nleaf * mL * kL, s);
   leaf_scale_U<R>(s, Y.template as<cplx<R>>(), P.U<R>(L), mL, kL, b, k2, P.leaf_origin.as<I2>(),
                   P.leaf_pts.as<I2>(), nleaf, P.n);
   cgemm<R>(s, mL, kL, mL, one, X, mL, (long)mL * mL, OP_N, Y.template as<cplx<R>>(), kL, (long)mL * kL, OP_N,
@@ -396,7 +426,6 @@ void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipSt
   F.S[L].alloc(sizeof(cplx<R>) * (size_t)nleaf * kL * kL);
   cgemm<R>(s, kL, kL, mL, one, P.U<R>(L), kL, 0, OP_T, Z.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero,
            nullptr, 0, 0, F.S[L].template as<cplx<R>>(), kL, (long)kL * kL, nleaf);
-  LSH_HIP(hipStreamSynchronize(s));
 }
 
 // merge of parent level l: P_a, P_b, C^{-1} (needs G_ab of level l)
@@ -417,10 +446,11 @@ void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   cgemm<R>(s, c, c, c, one, Sch + cc, c, 2 * cc, OP_N, G, c, 0, OP_T, zero, nullptr, 0, 0, Pb, c, cc, nb);
   cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
   {
-    DevBuf ws(inverse_ws_bytes<R>(c, nb)), info(sizeof(int) * nb);
-    inverse<R>(s, Ci, c, c, cc, nb, ws.p, info.as<int>());
-    int bad = check_info(info, nb, s);
-    LSH_REQUIRE(!bad, LSH_ERR_SINGULAR, "singular merge matrix I - Pb Pa at level " + std::to_string(l));
+    AsyncBuf ws(inverse_ws_bytes<R>(c, nb), s);
+    F.info.emplace_back(sizeof(int) * nb);
+    F.info_n.push_back(nb);
+    F.info_what.push_back("singular merge matrix I - Pb Pa at level " + std::to_string(l));
+    inverse<R>(s, Ci, c, c, cc, nb, ws.p, F.info.back().template as<int>());
   }
 }
 
@@ -439,7 +469,7 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
   const long ck = (long)c * k;
   const cplx<R>* U1 = P.U<R>(l);
   const cplx<R>* U2 = U1 + ck;
-  DevBuf A1(sizeof(cplx<R>) * nb * ck), A2(sizeof(cplx<R>) * nb * ck), Yb(sizeof(cplx<R>) * nb * ck);
+  AsyncBuf A1(sizeof(cplx<R>) * nb * ck, s), A2(sizeof(cplx<R>) * nb * ck, s), Yb(sizeof(cplx<R>) * nb * ck, s);
   cplx<R>* a1 = A1.template as<cplx<R>>();
   cplx<R>* a2 = A2.template as<cplx<R>>();
   cplx<R>* y = Yb.template as<cplx<R>>();
@@ -453,8 +483,7 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
   cplx<R>* S = F.S[l].template as<cplx<R>>();
   cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a1, k, ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
   cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, y, k, ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k, nb);
-  LSH_HIP(hipStreamSynchronize(s));  // scratch A1, A2, Y die here
-}
+}  // (scratch freed in stream order)
 
 template <typename R>
 void factor_level(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
@@ -467,6 +496,7 @@ void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStr
   factor_init(P, F);
   factor_leaves(P, b, F, s);
   for (int l = P.L - 1; l >= 0; --l) factor_level(P, F, l, s);
+  factor_check(F, s);
 }
 
 template <typename R>
@@ -1172,6 +1202,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
           factor_scatter(*P, FD, l, s);
         }
       }
+      factor_check(FD, s);
     };
     if (desc->hbs_prec == LSH_FP32) run(F->f32);
     else run(F->f64);
