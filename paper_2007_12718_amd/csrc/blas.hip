@@ -199,7 +199,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
 }
 
 // FP32 variant on the 32x32x2 matrix instruction (the higher-throughput FP32
-// shape): 2 x 2 wavefronts, each owning WM x WN blocks of 32 x 32 outputs, so
+// shape), three real products per complex step (Gauss's form, 25 % fewer
+// matrix instructions; the imaginary part is a difference of products, which
+// stays within FP32 rounding of |A||B| sums): 2 x 2 wavefronts, each owning
+// WM x WN blocks of 32 x 32 outputs, so
 // the workgroup tile is (64 WM) x (64 WN), K advancing 16 per LDS tile.  The
 // sum over k inside one instruction does not care which k each lane group
 // supplies, so lane group g (lanes 32g .. 32g+31) takes k = 8g + s at step s:
@@ -224,13 +227,15 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
   const cplx<float>* B = P.B + b * P.sB;
   const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
   const bool aC = (P.opA == OP_C || P.opA == OP_R), bC = (P.opB == OP_C || P.opB == OP_R);
-  f16v cr[WM][WN], ci[WM][WN];
+  // three real products per complex step (Gauss): t1 = Ar Br, t2 = Ai Bi,
+  // t3 = (Ar + Ai)(Br + Bi); Re = t1 - t2, Im = t3 - t1 - t2
+  f16v t1[WM][WN], t2[WM][WN], t3[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0; ci[i][j][r] = 0; }
+      for (int r = 0; r < 16; ++r) { t1[i][j][r] = 0; t2[i][j][r] = 0; t3[i][j][r] = 0; }
   cplx<float> ra[EA], rb[EB];
   auto load = [&](int k0) {
 #pragma unroll
@@ -286,20 +291,21 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
     if (more) load(k0 + GBK);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {  // two halves of four k steps
-      f4v ar[WM], ai[WM], nai[WM], br[WN], bi[WN];
+      f4v ar[WM], ai[WM], as[WM], br[WN], bi[WN], bs[WN];
       const int kq = 8 * g + 4 * h;
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         const int row = wm * 32 * WM + i * 32 + l32;
         ar[i] = *reinterpret_cast<const f4v*>(&sAr[row][kq]);
         ai[i] = *reinterpret_cast<const f4v*>(&sAi[row][kq]);
-        nai[i] = -ai[i];
+        as[i] = ar[i] + ai[i];
       }
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int col = wn * 32 * WN + j * 32 + l32;
         br[j] = *reinterpret_cast<const f4v*>(&sBr[col][kq]);
         bi[j] = *reinterpret_cast<const f4v*>(&sBi[col][kq]);
+        bs[j] = br[j] + bi[j];
       }
 #pragma unroll
       for (int st = 0; st < 4; ++st)
@@ -307,10 +313,9 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
         for (int i = 0; i < WM; ++i)
 #pragma unroll
           for (int j = 0; j < WN; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st], br[j][st], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st], bi[j][st], ci[i][j], 0, 0, 0);
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(nai[i][st], bi[j][st], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i][st], br[j][st], ci[i][j], 0, 0, 0);
+            t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st], br[j][st], t1[i][j], 0, 0, 0);
+            t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i][st], bi[j][st], t2[i][j], 0, 0, 0);
+            t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i][st], bs[j][st], t3[i][j], 0, 0, 0);
           }
     }
     __syncthreads();
@@ -331,7 +336,8 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
         const int m = m0 + wm * 32 * WM + i * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
         const int n = n0 + wn * 32 * WN + j * 32 + l32;
         if (m < P.M && n < P.N) {
-          cplx<float> v = P.alpha * mk<float>(cr[i][j][r], ci[i][j][r]);
+          const float re = t1[i][j][r] - t2[i][j][r], im = t3[i][j][r] - t1[i][j][r] - t2[i][j][r];
+          cplx<float> v = P.alpha * mk<float>(re, im);
           if (useD) v = v + P.beta * D[(long)m * P.ldd + n];
           if (P.addI && m == n) v.x += 1.f;
           C[(long)m * P.ldc + n] = v;
@@ -340,7 +346,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
 }
 
 template <int WM, int WN>
-__global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {
+__global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {  // (WM, WN) = (2, 1) or (1, 1)
   constexpr int BM = 64 * WM, BN = 64 * WN;
   if (P.skip && *P.skip) return;  // uniform across the launch
   // XCD-aware tile order (see k_cgemm)
@@ -363,7 +369,7 @@ struct GemmGroupDev {
   long tile0;
 };
 
-__global__ __launch_bounds__(256, 5) void k_cgemm_x32_grouped(const GemmGroupDev* G, int ng) {
+__global__ __launch_bounds__(256, 4) void k_cgemm_x32_grouped(const GemmGroupDev* G, int ng) {
   const long L = blockIdx.x + (long)gridDim.x * blockIdx.y;
   int lo = 0, hi = ng - 1;  // last group with tile0 <= L
   while (lo < hi) {
@@ -419,20 +425,20 @@ static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, cons
 // ceil(tiles / (256 CUs x resident workgroups per CU)) rounds, and a full
 // round costs (resident workgroups x tile area) / (per-CU efficiency of that
 // tile).  Residency and efficiency per tile come from the register/LDS budget
-// and a sweep of square and batched shapes (128x128: 2 resident, 128x64: 3,
-// 64x64: 5).  LSH_GEMM_TILE=0/1/2 forces a tile.
+// and a sweep of square and batched shapes (128x64: 2 resident, 64x64: 4).
+// LSH_GEMM_TILE=0/1 forces a tile.
 struct TileModel { int bm, bn, resident; double eff; };
-static const TileModel kF32Tiles[3] = {{128, 128, 2, 0.56}, {128, 64, 3, 0.63}, {64, 64, 5, 0.64}};
+static const TileModel kF32Tiles[2] = {{128, 64, 2, 0.60}, {64, 64, 4, 0.69}};
 
 static int f32_tile(int M, int N, int batch) {
   static const int forced = [] {
     const char* e = getenv("LSH_GEMM_TILE");
     return e ? atoi(e) : -1;
   }();
-  if (forced >= 0 && forced <= 2) return forced;
-  int best = 2;
+  if (forced >= 0 && forced <= 1) return forced;
+  int best = 1;
   double bt = 1e300;
-  for (int t = 0; t < 3; ++t) {
+  for (int t = 0; t < 2; ++t) {
     const TileModel& tm = kF32Tiles[t];
     const double tiles = (double)ceil_div(M, tm.bm) * ceil_div(N, tm.bn) * batch;
     const double rounds = std::ceil(tiles / (256.0 * tm.resident));
@@ -461,11 +467,8 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
   // large tiles when they still leave a few waves of workgroups in flight
   const double big_tiles = (double)ceil_div(M, 128) * ceil_div(N, sizeof(R) == 4 ? 128 : 64) * batch;
   if constexpr (sizeof(R) == 4) {
-    switch (f32_tile(M, N, batch)) {
-      case 0: launch_gemm_x32<2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch); break;
-      case 1: launch_gemm_x32<2, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch); break;
-      default: launch_gemm_x32<1, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch); break;
-    }
+    if (f32_tile(M, N, batch) == 0) launch_gemm_x32<2, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    else launch_gemm_x32<1, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   } else {
     if (M >= 128 && N >= 64 && K >= 32 && big_tiles >= 128) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
