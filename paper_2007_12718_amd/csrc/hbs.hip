@@ -653,23 +653,23 @@ __global__ void k_bp_sc_reduce(const z64* M, int m, const z64* part, const int* 
 // most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
 // pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
 // pivot qualifies.
-__global__ __launch_bounds__(256) void k_bp_chol(const z64* Sg, int m, double thr2, int* J, int* st, z64* Lpp,
-                                                 z64* Linv) {
+__global__ __launch_bounds__(1024) void k_bp_chol(const z64* Sg, int m, double thr2, int* J, int* st, z64* Lpp,
+                                                  z64* Linv) {
   __shared__ z64 S[BP_B][BP_B + 1];
   __shared__ z64 Lb[BP_B][BP_NP];  // Cholesky columns for every candidate row
   __shared__ int piv[BP_NP];
   __shared__ int picked[BP_B];
-  __shared__ int s_p, s_np;
+  __shared__ int s_p, s_np, s_bad;
   __shared__ double s_d;
   if (st[BPS_DONE]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nc = st[BPS_NC], j = st[BPS_J];
   const double dout = reinterpret_cast<const double*>(st + BPS_DOUT)[0];
   const int* cand = st + BPS_CAND;
-  for (int e = tid; e < BP_B * BP_B; e += 256) S[e / BP_B][e % BP_B] = Sg[e];
-  for (int a = tid; a < BP_B; a += 256) picked[a] = 0;
-  for (int e = tid; e < BP_B * BP_NP; e += 256) Lb[e / BP_NP][e % BP_NP] = mk(0.0, 0.0);
-  if (tid == 0) s_np = 0;
+  for (int e = tid; e < BP_B * BP_B; e += 1024) S[e / BP_B][e % BP_B] = Sg[e];
+  for (int a = tid; a < BP_B; a += 1024) picked[a] = 0;
+  for (int e = tid; e < BP_B * BP_NP; e += 1024) Lb[e / BP_NP][e % BP_NP] = mk(0.0, 0.0);
+  if (tid == 0) { s_np = 0; s_bad = 0; }
   __syncthreads();
   for (int t = 0; t < BP_NP; ++t) {
     if (wave == 0) {
@@ -695,42 +695,37 @@ __global__ __launch_bounds__(256) void k_bp_chol(const z64* Sg, int m, double th
     if (!(dp > thr2) || p >= nc || (t > 0 && dp < dout)) break;
     const double lpp = sqrt(dp), rl = 1.0 / lpp;
     // column t and the Schur update read only row/column p, which neither writes
-    for (int a = tid; a < nc; a += 256)
+    for (int a = tid; a < nc; a += 1024)
       if (a == p || !picked[a]) Lb[a][t] = a == p ? mk(lpp, 0.0) : rl * S[a][p];
-    for (int e = tid; e < BP_B * BP_B; e += 256) {
+    for (int e = tid; e < BP_B * BP_B; e += 1024) {
       const int a = e / BP_B, b = e % BP_B;  // (constant divisor)
       if (a < nc && b < nc && a != p && b != p) S[a][b] = S[a][b] - (rl * S[a][p]) * conjg(rl * S[b][p]);
     }
     __syncthreads();
   }
-  __syncthreads();
   const int np = s_np;
-  for (int e = tid; e < BP_NP * BP_NP; e += 256) {
+  for (int e = tid; e < BP_NP * BP_NP; e += 1024) {
     const int q = e / BP_NP, r = e % BP_NP;
     Lpp[e] = (q < np && r <= q) ? Lb[piv[q]][r] : mk(0.0, 0.0);
   }
-  // Linv = Lpp^{-1}: forward substitution, one column per thread, in LDS
-  // (reusing the storage of S, no longer read)
-  __syncthreads();
-  static_assert(BP_NP * (BP_NP + 1) <= BP_B * (BP_B + 1), "S too small for Linv");
-  z64(*Xs)[BP_NP + 1] = reinterpret_cast<z64(*)[BP_NP + 1]>(&S[0][0]);
-  if (tid < BP_NP) {
-    const int c = tid;
-    for (int q = 0; q < BP_NP; ++q) {
-      z64 v = mk(0.0, 0.0);
-      if (q >= c && q < np && c < np) {
-        z64 acc = q == c ? mk(1.0, 0.0) : mk(0.0, 0.0);
-        for (int r = c; r < q; ++r) acc = acc - Lb[piv[q]][r] * Xs[r][c];
-        v = acc * crecip(Lb[piv[q]][q]);
+  // Linv = Lpp^{-1}, column c by the 32 lanes of group c (lane r holds
+  // X[r][c]); X[q][c] = -(sum_{c <= r < q} L[q][r] X[r][c]) / L[q][q]
+  {
+    const int c = tid >> 5, r = tid & 31;
+    z64 x = mk(0.0, 0.0);
+    if (c < np) {
+      if (r == c) x = crecip(Lb[piv[c]][c]);
+      for (int q = c + 1; q < np; ++q) {
+        z64 v = (r >= c && r < q) ? Lb[piv[q]][r] * x : mk(0.0, 0.0);
+        for (int off = 16; off > 0; off >>= 1) {
+          v.x += __shfl_xor(v.x, off);
+          v.y += __shfl_xor(v.y, off);
+        }
+        if (r == q) x = mk(0.0, 0.0) - v * crecip(Lb[piv[q]][q]);
       }
-      Xs[q][c] = v;
     }
+    Linv[r * BP_NP + c] = (c < np && r < np) ? x : mk(0.0, 0.0);
   }
-  __syncthreads();
-  for (int e = tid; e < BP_NP * BP_NP; e += 256) Linv[e] = Xs[e / BP_NP][e % BP_NP];
-  __shared__ int s_bad;
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
   if (tid < np) {
     const int row = cand[piv[tid]];
     if (row < 0 || row >= m) s_bad = 1;  // (cannot happen: candidates are rows)
@@ -981,7 +976,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64
       LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
-        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(256), 0, s, Sc, m, thr2, J, st, Lpp, Linv);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(1024), 0, s, Sc, m, thr2, J, st, Lpp, Linv);
       }
       LSH_LAUNCH_CHECK();
       {
