@@ -558,8 +558,18 @@ __global__ __launch_bounds__(256) void k_cgemv(int M, int N, cplx<R> alpha,
     const int i = blockIdx.y * GV_ROWS + wave * (GV_ROWS / 4) + rr;
     if (i >= M) break;
     const cplx<R>* row = Ab + (long)i * lda;
-    cplx<R> acc = mk<R>(0, 0);
-    for (int j = lane; j < N; j += 64) fma_acc(acc, row[j], xs[j]);
+    // eight independent loads in flight per lane, four partial sums
+    cplx<R> a4[4] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
+    int j = lane;
+    for (; j + 7 * 64 < N; j += 8 * 64) {
+      cplx<R> v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = row[j + u * 64];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) fma_acc(a4[u & 3], v[u], xs[j + u * 64]);
+    }
+    for (; j < N; j += 64) fma_acc(a4[0], row[j], xs[j]);
+    cplx<R> acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       acc.x += __shfl_xor(acc.x, off);
@@ -609,7 +619,18 @@ __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int C, cplx<R> alpha, co
     cplx<R> acc[MG_VEC];
 #pragma unroll
     for (int v = 0; v < MG_VEC; ++v) acc[v] = mk<R>(0, 0);
-    for (int j = lane; j < C; j += 64) {
+    int j = lane;
+    for (; j + 3 * 64 < C; j += 4 * 64) {  // four matrix loads in flight per lane
+      cplx<R> a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = row[j + u * 64];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < MG_VEC; ++v)
+          if (v < nb) fma_acc(acc[v], a[u], X[(long)(b0 + v) * ldx + j + u * 64]);
+    }
+    for (; j < C; j += 64) {
       const cplx<R> a = row[j];
 #pragma unroll
       for (int v = 0; v < MG_VEC; ++v)
