@@ -28,7 +28,10 @@
  *    returns, except that a factor keeps a private copy of b.
  *  - Handles own their device memory (allocated by the library with
  *    hipMalloc); destroy them with the matching *_destroy call.  A factor
- *    refers to its plan: destroy the factor first.
+ *    refers to its plan: destroy the factor first.  A destroy call
+ *    synchronises the device once and keeps the handle's buffers in a
+ *    per-process cache (at most LSH_CACHE_BYTES bytes, default 32 GiB; 0
+ *    disables it) for the next plan or factor; lsh_cache_trim frees them.
  *  - The stream is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls that must read back small device values synchronise the stream
  *    and say so.
@@ -203,8 +206,15 @@ int lsh_correction_weights(int order, double kh, int* count, int* offsets, doubl
  * summed event time (ms) and the summed work.  lsh_profile_names writes the
  * recorded names, ';'-separated, into buf (host char[cap]). */
 int lsh_profile_enable(int on);
+/* Restrict recording to names that start with prefix (NULL or "" = all). */
+int lsh_profile_only(const char* prefix);
 int lsh_profile_query(const char* name, int* launches, double* ms, double* work);
 int lsh_profile_names(char* buf, int cap);
+
+/* Frees the device buffers that destroyed handles left in the cache
+ * (synchronises the device).  cached: host size_t, receives the bytes the
+ * cache held before the call (may be NULL). */
+int lsh_cache_trim(size_t* cached);
 
 const char* lsh_last_error(void);
 

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "mem.hpp"
+
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -82,24 +84,29 @@ struct Error : std::runtime_error {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  size_t cap = 0;  // capacity of the block behind p (>= bytes)
   DevBuf() = default;
   explicit DevBuf(size_t n) { alloc(n); }
   void alloc(size_t n) {
     release();
     bytes = n;
-    if (n) LSH_HIP(hipMalloc(&p, n));
+    if (n) LSH_HIP(mem::get(n, &p, &cap));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    mem::put(p, cap);
     p = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
   }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap) { o.p = nullptr; o.bytes = o.cap = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; cap = o.cap;
+      o.p = nullptr; o.bytes = o.cap = 0;
+    }
     return *this;
   }
   template <typename T>

@@ -30,6 +30,7 @@
 namespace lsh {
 namespace prof {
 void set(bool enable);
+void set_only(const char* prefix);
 int query(const char* name, int* launches, double* ms, double* work);
 std::string names();
 }  // namespace prof
@@ -967,9 +968,24 @@ int lsh_grad_b(lsh_plan_t P, const void* lambda, const void* u_inc, const void* 
   API_END
 }
 
+int lsh_cache_trim(size_t* cached) {
+  API_BEGIN
+  if (cached) *cached = mem::cached_bytes();
+  mem::trim();
+  return LSH_OK;
+  API_END
+}
+
 int lsh_profile_enable(int on) {
   API_BEGIN
   prof::set(on != 0);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_profile_only(const char* prefix) {
+  API_BEGIN
+  prof::set_only(prefix);
   return LSH_OK;
   API_END
 }
@@ -1022,6 +1038,7 @@ int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan) {
 
 int lsh_plan_destroy(lsh_plan_t plan) {
   API_BEGIN
+  mem::Recycle r;
   delete plan;
   return LSH_OK;
   API_END
@@ -1446,6 +1463,7 @@ int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b,
 
 int lsh_factor_destroy(lsh_factor_t F) {
   API_BEGIN
+  mem::Recycle r;
   delete F;
   return LSH_OK;
   API_END

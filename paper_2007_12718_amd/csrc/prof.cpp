@@ -1,6 +1,7 @@
 // Per-kernel hipEvent timing store (see prof.hpp).
 #include "prof.hpp"
 
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -16,6 +17,7 @@ struct Rec {
 };
 std::mutex mu;
 bool on = false;
+std::string only;  // record only names starting with this (empty: all)
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
 hipEvent_t get_event() {
@@ -34,6 +36,7 @@ bool enabled() { return on; }
 
 void record(const char* name, hipStream_t s, double work, bool start) {
   std::lock_guard<std::mutex> g(mu);
+  if (!only.empty() && std::strncmp(name, only.c_str(), only.size()) != 0) return;
   if (start) {
     Rec r;
     r.name = name;
@@ -59,6 +62,17 @@ void set(bool enable) {
   }
   recs.clear();
   on = enable;
+  // events are created ahead so that recording costs one hipEventRecord
+  while (enable && pool.size() < 8192) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    pool.push_back(e);
+  }
+}
+
+void set_only(const char* prefix) {
+  std::lock_guard<std::mutex> g(mu);
+  only = prefix ? prefix : "";
 }
 
 // totals per kernel name: launches, ms, work

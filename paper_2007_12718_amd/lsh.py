@@ -26,7 +26,8 @@ EXPORTED = [
     "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
     "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
-    "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor",
+    "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor", "lsh_profile_only",
+    "lsh_cache_trim",
 ]
 
 
@@ -94,6 +95,8 @@ def lib():
         L.lsh_profile_enable.argtypes = [c_int]
         L.lsh_profile_query.argtypes = [ctypes.c_char_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]
         L.lsh_profile_names.argtypes = [ctypes.c_char_p, c_int]
+        L.lsh_profile_only.argtypes = [ctypes.c_char_p]
+        L.lsh_cache_trim.argtypes = [POINTER(ctypes.c_size_t)]
         _lib = L
     return _lib
 
@@ -353,6 +356,18 @@ def dev_inverse(A):
 
 def lsh_profile_enable(on=True):
     _check(lib().lsh_profile_enable(int(on)))
+
+
+def lsh_profile_only(prefix=None):
+    """Record only the kernels whose name starts with prefix (None: all)."""
+    _check(lib().lsh_profile_only(prefix.encode() if prefix else None))
+
+
+def cache_trim():
+    """Free the device buffers cached by destroyed plans/factors; returns the bytes freed."""
+    n = ctypes.c_size_t(0)
+    _check(lib().lsh_cache_trim(ctypes.byref(n)))
+    return n.value
 
 
 def lsh_profile_query(name):

@@ -217,3 +217,30 @@ def test_pipelined_build_equals_separate_calls(prec):
     s1 = F1.solve(cuda(synth.plane_wave(n, kappa)[None]), tol=1e-12)[0].cpu().numpy()
     s2 = F2.solve(cuda(synth.plane_wave(n, kappa)[None]), tol=1e-12)[0].cpu().numpy()
     assert np.array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cached_buffers_give_identical_factor(prec):
+    """Destroyed handles leave their buffers, with their old contents, in the
+    library's cache; a rebuild from those buffers must compute exactly what
+    a build on freshly allocated memory computed."""
+    from paper_2007_12718_amd import lsh
+    n, kappa = 64, 2 * np.pi * 6
+    b1 = synth.bumps(n, np.random.default_rng(21))
+    b2 = synth.bumps(n, np.random.default_rng(22))
+    x = np.random.default_rng(2).standard_normal((1, n, n)) + 0j
+    lsh.cache_trim()
+
+    def run(b):
+        P, F = lsh.build(n, kappa, cuda(b), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
+        y = F.apply_precond(cuda(x)).cpu().numpy()
+        yt = F.apply_precond(cuda(x), transpose=True).cpu().numpy()
+        F.close()
+        P.close()
+        return y, yt
+
+    y1, yt1 = run(b1)
+    run(b2)
+    y3, yt3 = run(b1)
+    assert np.array_equal(y1, y3) and np.array_equal(yt1, yt3)
+    assert lsh.cache_trim() > 0
