@@ -101,8 +101,12 @@ typedef struct {
  * (parentid); translation invariance), the sibling blocks (eq. (sibint)) and
  * the spectrum of the order-p operator for the FFT matvec.
  * Synchronises the stream (ranks are read back level by level).
- * Errors: LSH_ERR_INVALID_ARG for a bad descriptor; LSH_ERR_UNSUPPORTED for
- * sizes beyond the kernels' limits. */
+ * Row-ID method (for tol >= 1e-7; below, column-pivoted QR): environment
+ * LSH_ROWID=block (default) pivots several rows per step, accepting a pivot
+ * whose Schur diagonal is at least LSH_BP_ALPHA (default 0.75; 1 = greedy)
+ * times the largest; LSH_ROWID=panel pivots greedily one row at a time.
+ * Errors: LSH_ERR_INVALID_ARG for a bad descriptor or LSH_BP_ALPHA outside
+ * (0, 1]; LSH_ERR_UNSUPPORTED for sizes beyond the kernels' limits. */
 int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan);
 int lsh_plan_destroy(lsh_plan_t plan);
 /* host: number of levels L and the ranks k_l (l = 0..L; k_0 = 0) */

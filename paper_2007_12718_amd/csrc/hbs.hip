@@ -443,10 +443,13 @@ __global__ void k_scatter_U(z64* U, int k, const int* piv, const int* rest, int 
 //     and its inverse;
 //  4. the new columns L[:, P] = (M[:, P] - L L[P,:]^H) L_PP^{-H} and
 //     d_i -= |L[i, P]|^2.
-// Step 3 stops before a pivot whose Schur diagonal falls below dout:
-// diagonals only decrease, so every pivot taken is the greedy pivot over all
-// rows, and the pivot sequence, the stopping point and the rank are those of
-// one-at-a-time greedy pivoting (up to ties).  All step state (rank so far,
+// Step 3 stops before a pivot whose Schur diagonal falls below alpha * dout.
+// Diagonals only decrease, so every pivot taken has a Schur diagonal of at
+// least alpha times the largest over all rows.  With alpha = 1 each pivot is
+// the greedy pivot, and the pivot sequence, the stopping point and the rank
+// are those of one-at-a-time greedy pivoting (up to ties); alpha < 1 takes
+// more pivots per step (alpha-greedy pivoting: the same stopping rule, so the
+// same error bound, with a rank that can differ by a few).  All step state (rank so far,
 // pivot count, done flag) lives on the device: the host queues steps in
 // batches and reads the done flag once per batch; a step queued after the
 // end returns at entry.
@@ -649,12 +652,12 @@ __global__ void k_bp_sc_reduce(const z64* M, int m, const z64* part, const int* 
 }
 
 // Greedy pivoted Cholesky of the candidate block S (first nc rows valid)
-// while the pivot exceeds thr2 and, after the first, is not below dout; at
+// while the pivot exceeds thr2 and, after the first, is not below alpha * dout; at
 // most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
 // pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
 // pivot qualifies.
-__global__ __launch_bounds__(1024) void k_bp_chol(const z64* Sg, int m, double thr2, int* J, int* st, z64* Lpp,
-                                                  z64* Linv) {
+__global__ __launch_bounds__(1024) void k_bp_chol(const z64* Sg, int m, double thr2, double alpha, int* J, int* st,
+                                                  z64* Lpp, z64* Linv) {
   __shared__ z64 S[BP_B][BP_B + 1];
   __shared__ z64 Lb[BP_B][BP_NP];  // Cholesky columns for every candidate row
   __shared__ int piv[BP_NP];
@@ -664,7 +667,7 @@ __global__ __launch_bounds__(1024) void k_bp_chol(const z64* Sg, int m, double t
   if (st[BPS_DONE]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nc = st[BPS_NC], j = st[BPS_J];
-  const double dout = reinterpret_cast<const double*>(st + BPS_DOUT)[0];
+  const double dout = alpha * reinterpret_cast<const double*>(st + BPS_DOUT)[0];
   const int* cand = st + BPS_CAND;
   for (int e = tid; e < BP_B * BP_B; e += 1024) S[e / BP_B][e % BP_B] = Sg[e];
   for (int a = tid; a < BP_B; a += 1024) picked[a] = 0;
@@ -680,8 +683,8 @@ __global__ __launch_bounds__(1024) void k_bp_chol(const z64* Sg, int m, double t
       if (lane == 0) {
         s_p = bi;
         s_d = best;
-        // rows outside the block have Schur diagonal <= dout (diagonals only
-        // decrease), so while best >= dout this is the greedy pivot of all rows
+        // rows outside the block have Schur diagonal <= dout / alpha
+        // (diagonals only decrease): this pivot is alpha-greedy over all rows
         if (best > thr2 && bi < nc && (t == 0 || best >= dout)) {
           picked[bi] = 1;
           piv[t] = bi;
@@ -923,7 +926,8 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
   LSH_LAUNCH_CHECK();
 }
 
-int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws) {
+int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws) {
+  LSH_REQUIRE(alpha > 0.0 && alpha <= 1.0, -1, "row ID: alpha must lie in (0, 1]");
   LSH_REQUIRE(m <= BP_SEL, -6, "row ID: more than 4096 candidate rows in one level");
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t bytes) { char* r = p; p += ((bytes + 255) / 256) * 256; return (void*)r; };
@@ -976,7 +980,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64
       LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
-        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(1024), 0, s, Sc, m, thr2, J, st, Lpp, Linv);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(1024), 0, s, Sc, m, thr2, alpha, J, st, Lpp, Linv);
       }
       LSH_LAUNCH_CHECK();
       {

@@ -31,7 +31,7 @@ size_t rowid_gram_ws(int m);
 // chosen among the 48 largest Schur diagonals only while they remain the
 // greedy choice over all rows): the greedy pivots and stopping rule.
 // Returns the rank (synchronises on the stream once per step).
-int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws);
+int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws);
 size_t rowid_bp_ws(int m);
 
 // Leaf factor helpers (R = working precision)

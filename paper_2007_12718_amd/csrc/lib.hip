@@ -191,16 +191,19 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     LSH_HIP(hipStreamSynchronize(s));
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
   } else {
-    // block-pivoted left-looking Cholesky by default; LSH_ROWID=panel selects
-    // the one-pivot-at-a-time panels (the same greedy pivots)
+    // block-pivoted left-looking Cholesky by default (alpha-greedy with
+    // alpha = LSH_BP_ALPHA, default 0.75; 1 = greedy); LSH_ROWID=panel selects
+    // the one-pivot-at-a-time panels (greedy)
     const char* e = std::getenv("LSH_ROWID");
     const bool block = !(e && std::string(e) == "panel");
+    const char* ea = std::getenv("LSH_BP_ALPHA");
+    const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
     if (!block) {
       AsyncBuf ws(rowid_gram_ws(m), s);
       k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
     } else {
       AsyncBuf ws(rowid_bp_ws(m), s);
-      k = rowid_bp(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
+      k = rowid_bp(s, A.as<z64>(), m, np, P.d.tol, alpha, J.as<int>(), Ufull.as<z64>(), ws.p);
     }
   }
   lv.k = k;

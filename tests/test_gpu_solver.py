@@ -72,18 +72,21 @@ def test_operator_matches_dense(n, order, use_b):
         assert np.abs(y[r].reshape(-1) - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("n,tol,width,method", [(32, 1e-10, 3, "panel"), (64, 1e-4, 2, "panel"),
-                                                (128, 1e-5, 2, "panel"), (64, 1e-4, 2, "block"),
-                                                (128, 1e-5, 2, "block")])
-def test_level_ids_valid_and_ranks_match_oracle(n, tol, width, method, monkeypatch):
+@pytest.mark.parametrize("n,tol,width,method,alpha", [(32, 1e-10, 3, "panel", 1), (64, 1e-4, 2, "panel", 1),
+                                                      (128, 1e-5, 2, "panel", 1), (64, 1e-4, 2, "block", 1),
+                                                      (128, 1e-5, 2, "block", 1), (64, 1e-4, 2, "block", 0.75),
+                                                      (128, 1e-5, 2, "block", 0.5), (128, 1e-4, 2, "block", 0.25)])
+def test_level_ids_valid_and_ranks_match_oracle(n, tol, width, method, alpha, monkeypatch):
     """The pivots are not unique (the boxes and proxy rings are symmetric, so
     column norms tie exactly).  Each level's ID must hold U[J] = I and
     approximate the proxy matrix to the tolerance, with the oracle's rank
-    (+-2 for ties).  tol 1e-10 runs the CPQR path, the others the Gram
-    path: one-pivot panels ("panel") or the block-pivoted left-looking
-    Cholesky ("block", the same greedy pivots, several per step)."""
+    (+-2 for ties and for alpha-greedy pivoting).  tol 1e-10 runs the CPQR
+    path, the others the Gram path: one-pivot panels ("panel") or the
+    block-pivoted left-looking Cholesky ("block": alpha = 1 takes the greedy
+    pivots, alpha < 1 alpha-greedy ones, several per step)."""
     from paper_2007_12718_amd import lsh
     monkeypatch.setenv("LSH_ROWID", method)
+    monkeypatch.setenv("LSH_BP_ALPHA", str(alpha))
     w = synth.small(n)
     P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=tol, proxy_width=width, prec="fp64")
     C = hbs.Compression(w.n, w.kappa, 8, tol, width)
