@@ -656,89 +656,162 @@ __global__ void k_bp_sc_reduce(const z64* M, int m, const z64* part, const int* 
 // most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
 // pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
 // pivot qualifies.
-__global__ __launch_bounds__(1024) void k_bp_chol(const z64* Sg, int m, double thr2, double alpha, int* J, int* st,
-                                                  z64* Lpp, z64* Linv) {
-  __shared__ z64 S[BP_B][BP_B + 1];
-  __shared__ z64 Lb[BP_B][BP_NP];  // Cholesky columns for every candidate row
+// Wave-wide maximum of a 32-bit key, the same in every lane.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_max_u32(unsigned k) {
+  const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, CTRL, 0xF, 0xF, false);
+  return o > k ? o : k;
+}
+__device__ __forceinline__ unsigned wave_max_u32_uniform(unsigned k) {
+  k = dpp_max_u32<0xB1>(k);   // quad_perm [1,0,3,2]
+  k = dpp_max_u32<0x4E>(k);   // quad_perm [2,3,0,1]
+  k = dpp_max_u32<0x141>(k);  // row_half_mirror
+  k = dpp_max_u32<0x140>(k);  // row_mirror
+  unsigned best = (unsigned)__builtin_amdgcn_readlane((int)k, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const unsigned v = (unsigned)__builtin_amdgcn_readlane((int)k, 16 * r);
+    best = v > best ? v : best;
+  }
+  return best;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  return __longlong_as_double(
+      (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), lane) << 32) |
+                  (unsigned)__builtin_amdgcn_readlane((int)bits, lane)));
+}
+
+// Four waves: lane b of wave w holds rows 12w..12w+11 of column b of S in
+// registers, and every wave keeps all the Schur diagonals d_b (lane b).  Per
+// pivot p: the pivot's lanes write column t of the factor (rl * S[:, p],
+// zero in picked rows) to LDS, one barrier, then every lane updates its rows,
+// S[:, b] -= L[:, t] conj(L[b, t]), and d_b -= |L[b, t]|^2.  The next
+// pivot's search (a DPP maximum of d) is independent of the row updates, so
+// the two run interleaved.  Pivot keys hold the top 26 bits of d (sign,
+// exponent, 14 mantissa bits): diagonals within a relative 2^-14 of the
+// largest count as ties, won by the lower candidate.  L_PP^{-1} follows by
+// forward substitution inside each wave.
+constexpr int BP_CW = 4, BP_CR = BP_B / BP_CW;  // waves, rows per wave
+__global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, double thr2, double alpha, int* J,
+                                                        int* st, z64* Lpp, z64* Linv) {
+  static_assert(BP_B <= 64 && BP_NP == 32 && BP_B % BP_CW == 0 && BP_CW * 8 == BP_NP,
+                "one lane per candidate; 8 columns of L_PP^{-1} per wave");
+  __shared__ z64 Lb[BP_B][BP_NP + 1];  // factor columns for every candidate row
+  __shared__ z64 xs[BP_NP][BP_NP + 1]; // L_PP^{-1}
+  __shared__ double rlv[BP_NP];        // 1 / L[t][t]
   __shared__ int piv[BP_NP];
-  __shared__ int picked[BP_B];
-  __shared__ int s_p, s_np, s_bad;
-  __shared__ double s_d;
   if (st[BPS_DONE]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, b = tid & 63, w = tid >> 6, r0 = w * BP_CR;
   const int nc = st[BPS_NC], j = st[BPS_J];
   const double dout = alpha * reinterpret_cast<const double*>(st + BPS_DOUT)[0];
   const int* cand = st + BPS_CAND;
-  for (int e = tid; e < BP_B * BP_B; e += 1024) S[e / BP_B][e % BP_B] = Sg[e];
-  for (int a = tid; a < BP_B; a += 1024) picked[a] = 0;
-  for (int e = tid; e < BP_B * BP_NP; e += 1024) Lb[e / BP_NP][e % BP_NP] = mk(0.0, 0.0);
-  if (tid == 0) { s_np = 0; s_bad = 0; }
-  __syncthreads();
-  for (int t = 0; t < BP_NP; ++t) {
-    if (wave == 0) {
-      double best = -1.0;
-      int bi = BP_B;
-      if (lane < nc && !picked[lane]) { best = S[lane][lane].x; bi = lane; }
-      wave_argmax_d(best, bi);
-      if (lane == 0) {
-        s_p = bi;
-        s_d = best;
-        // rows outside the block have Schur diagonal <= dout / alpha
-        // (diagonals only decrease): this pivot is alpha-greedy over all rows
-        if (best > thr2 && bi < nc && (t == 0 || best >= dout)) {
-          picked[bi] = 1;
-          piv[t] = bi;
-          s_np = t + 1;
-        }
+  z64 col[BP_CR];
+#pragma unroll
+  for (int i = 0; i < BP_CR; ++i)
+    col[i] = (r0 + i < nc && b < nc) ? Sg[(r0 + i) * BP_B + b] : mk(0.0, 0.0);
+  double d = b < nc ? Sg[b * BP_B + b].x : 0.0;
+  unsigned long long picked = 0;  // (the same in every lane)
+  auto pick = [&]() -> int {      // largest unpicked diagonal, or -1
+    unsigned key = 0;
+    if (b < nc && !((picked >> b) & 1ull) && d > 0.0)
+      key = ((unsigned)((unsigned long long)__double_as_longlong(d) >> 32) & ~63u) | (unsigned)(63 - b);
+    key = wave_max_u32_uniform(key);
+    return key ? 63 - (int)(key & 63u) : -1;
+  };
+  int p = pick();
+  double dp = (p >= 0 && p < nc) ? readlane_f64(d, p) : 0.0;
+  bool go = p >= 0 && p < nc && dp > thr2;
+  int np = 0;
+  for (int t = 0; t < BP_NP && go; ++t) {
+    // rl = 1 / sqrt(dp): hardware estimate and two Newton steps
+    double rl = __builtin_amdgcn_rsq(dp);
+    rl = rl * (1.5 - 0.5 * dp * rl * rl);
+    rl = rl * (1.5 - 0.5 * dp * rl * rl);
+    const double lpp = dp * rl;
+    if (b == p) {
+#pragma unroll
+      for (int i = 0; i < BP_CR; ++i) {
+        const int a = r0 + i;
+        const bool zero = (picked >> a) & 1ull;
+        z64 v = rl * col[i];
+        v.x = a == p ? lpp : (zero ? 0.0 : v.x);
+        v.y = (a == p || zero) ? 0.0 : v.y;
+        Lb[a][t] = v;
+      }
+      if (w == 0) {
+        rlv[t] = rl;
+        piv[t] = p;
       }
     }
     __syncthreads();
-    const int p = s_p;
-    const double dp = s_d;
-    if (!(dp > thr2) || p >= nc || (t > 0 && dp < dout)) break;
-    const double lpp = sqrt(dp), rl = 1.0 / lpp;
-    // column t and the Schur update read only row/column p, which neither writes
-    for (int a = tid; a < nc; a += 1024)
-      if (a == p || !picked[a]) Lb[a][t] = a == p ? mk(lpp, 0.0) : rl * S[a][p];
-    for (int e = tid; e < BP_B * BP_B; e += 1024) {
-      const int a = e / BP_B, b = e % BP_B;  // (constant divisor)
-      if (a < nc && b < nc && a != p && b != p) S[a][b] = S[a][b] - (rl * S[a][p]) * conjg(rl * S[b][p]);
-    }
-    __syncthreads();
+    const z64 clb = conjg(Lb[b < BP_B ? b : 0][t]);
+    d -= abs2(clb);
+    if (b == p) d = 0.0;
+    picked |= 1ull << p;
+    np = t + 1;
+    // the next pivot (rows outside the block have Schur diagonal <= dout /
+    // alpha, since diagonals only decrease: an accepted pivot is
+    // alpha-greedy over all rows) and this pivot's row updates
+    const int pn = pick();
+#pragma unroll
+    for (int i = 0; i < BP_CR; ++i) col[i] = col[i] - Lb[r0 + i][t] * clb;
+    dp = (pn >= 0 && pn < nc) ? readlane_f64(d, pn) : 0.0;
+    go = pn >= 0 && pn < nc && dp > thr2 && dp >= dout;
+    p = pn;
   }
-  const int np = s_np;
-  for (int e = tid; e < BP_NP * BP_NP; e += 1024) {
-    const int q = e / BP_NP, r = e % BP_NP;
-    Lpp[e] = (q < np && r <= q) ? Lb[piv[q]][r] : mk(0.0, 0.0);
-  }
-  // Linv = Lpp^{-1}, column c by the 32 lanes of group c (lane r holds
-  // X[r][c]); X[q][c] = -(sum_{c <= r < q} L[q][r] X[r][c]) / L[q][q]
+  __syncthreads();
+  // X = L_PP^{-1}: wave w takes columns c = 8w + lane / 8; lane k = lane % 8
+  // of a column holds rows r = k + 8i.  Step q: the owner of row q finishes
+  // X[q][c] and passes it to the column's lanes, which subtract
+  // L[r][q] X[q][c] from their later rows.
   {
-    const int c = tid >> 5, r = tid & 31;
-    z64 x = mk(0.0, 0.0);
-    if (c < np) {
-      if (r == c) x = crecip(Lb[piv[c]][c]);
-      for (int q = c + 1; q < np; ++q) {
-        z64 v = (r >= c && r < q) ? Lb[piv[q]][r] * x : mk(0.0, 0.0);
-        for (int off = 16; off > 0; off >>= 1) {
-          v.x += __shfl_xor(v.x, off);
-          v.y += __shfl_xor(v.y, off);
-        }
-        if (r == q) x = mk(0.0, 0.0) - v * crecip(Lb[piv[q]][q]);
+    const int c = 8 * w + (b >> 3), k = b & 7;
+    z64 acc[BP_NP / 8];
+    int pr[BP_NP / 8];
+#pragma unroll
+    for (int i = 0; i < BP_NP / 8; ++i) {
+      const int r = k + 8 * i;
+      acc[i] = mk(r == c ? 1.0 : 0.0, 0.0);
+      pr[i] = r < np ? piv[r] : 0;
+    }
+    for (int q = 0; q < np; ++q) {
+      z64 xq = mk(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < BP_NP / 8; ++i)
+        if (i == (q >> 3)) xq = rlv[q] * acc[i];
+      const int src = (b & ~7) | (q & 7);
+      xq.x = __shfl(xq.x, src);
+      xq.y = __shfl(xq.y, src);
+      if (k == (q & 7)) xs[q][c] = xq;
+#pragma unroll
+      for (int i = 0; i < BP_NP / 8; ++i) {
+        const int r = k + 8 * i;
+        if (r > q && r < np) acc[i] = acc[i] - Lb[pr[i]][q] * xq;
       }
     }
-    Linv[r * BP_NP + c] = (c < np && r < np) ? x : mk(0.0, 0.0);
-  }
-  if (tid < np) {
-    const int row = cand[piv[tid]];
-    if (row < 0 || row >= m) s_bad = 1;  // (cannot happen: candidates are rows)
-    J[j + tid] = row;
   }
   __syncthreads();
-  if (tid == 0) {
-    st[BPS_NP] = s_bad ? 0 : np;
-    if (np == 0 || s_bad) st[BPS_DONE] = 1;
-    if (s_bad) st[BPS_ERR] = 1;
+  for (int e = tid; e < BP_NP * BP_NP; e += 64 * BP_CW) {
+    const int q = e / BP_NP, r = e % BP_NP;
+    const bool in = q < np && r <= q;
+    Lpp[e] = in ? Lb[piv[q]][r] : mk(0.0, 0.0);
+    Linv[e] = in ? xs[q][r] : mk(0.0, 0.0);
+  }
+  if (w == 0) {
+    int bad = 0;
+    if (b < np) {
+      const int row = cand[piv[b]];
+      bad = row < 0 || row >= m;  // (cannot happen: candidates are rows)
+      J[j + b] = row;
+    }
+    bad = __any(bad);
+    if (b == 0) {
+      st[BPS_NP] = bad ? 0 : np;
+      if (np == 0 || bad) st[BPS_DONE] = 1;
+      if (bad) st[BPS_ERR] = 1;
+    }
   }
 }
 
@@ -980,7 +1053,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
       LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
-        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(1024), 0, s, Sc, m, thr2, alpha, J, st, Lpp, Linv);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(64 * BP_CW), 0, s, Sc, m, thr2, alpha, J, st, Lpp, Linv);
       }
       LSH_LAUNCH_CHECK();
       {
