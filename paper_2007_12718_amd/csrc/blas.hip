@@ -203,13 +203,13 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
 // matrix instructions; the imaginary part is a difference of products, which
 // stays within FP32 rounding of |A||B| sums): 2 x 2 wavefronts, each owning
 // WM x WN blocks of 32 x 32 outputs, so
-// the workgroup tile is (64 WM) x (64 WN), K advancing 16 per LDS tile.  The
+// the workgroup tile is (64 WM) x (64 WN), K advancing 32 per LDS tile.  The
 // sum over k inside one instruction does not care which k each lane group
-// supplies, so lane group g (lanes 32g .. 32g+31) takes k = 8g + s at step s:
+// supplies, so lane group g (lanes 32g .. 32g+31) takes k = 16g + s at step s:
 // each lane then reads its operands for four steps with one 16-byte LDS load
-// per plane.  Row stride 20 floats keeps those loads free of bank conflicts.
+// per plane.  Row stride 36 floats keeps those loads free of bank conflicts.
 // Accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-constexpr int X32_LDK = GBK + 4;
+constexpr int X32_BK = 32, X32_LDK = X32_BK + 4;
 
 // One (64 WM) x (64 WN) output tile of problem b of P, at (m0, n0).
 template <int WM, int WN>
@@ -217,7 +217,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
   typedef float f16v __attribute__((ext_vector_type(16)));
   typedef float f4v __attribute__((ext_vector_type(4)));
   constexpr int BM = 64 * WM, BN = 64 * WN;
-  constexpr int EA = BM * GBK / 256, EB = BN * GBK / 256;
+  constexpr int EA = BM * X32_BK / 256, EB = BN * X32_BK / 256;
   __shared__ __align__(16) float sAr[BM][X32_LDK], sAi[BM][X32_LDK];
   __shared__ __align__(16) float sBr[BN][X32_LDK], sBi[BN][X32_LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -242,7 +242,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * 256;
       int m, k;
-      if (aN) { m = idx / GBK; k = idx % GBK; }
+      if (aN) { m = idx / X32_BK; k = idx % X32_BK; }
       else { k = idx / BM; m = idx % BM; }
       const int gm = m0 + m, gk = k0 + k;
       cplx<float> v = mk<float>(0, 0);
@@ -255,7 +255,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       const int idx = tid + e * 256;
       int n, k;
       if (bN) { k = idx / BN; n = idx % BN; }
-      else { n = idx / GBK; k = idx % GBK; }
+      else { n = idx / X32_BK; k = idx % X32_BK; }
       const int gn = n0 + n, gk = k0 + k;
       cplx<float> v = mk<float>(0, 0);
       if (gn < P.N && gk < P.K) v = bN ? B[(long)gk * P.ldb + gn] : B[(long)gn * P.ldb + gk];
@@ -268,7 +268,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * 256;
       int m, k;
-      if (aN) { m = idx / GBK; k = idx % GBK; }
+      if (aN) { m = idx / X32_BK; k = idx % X32_BK; }
       else { k = idx / BM; m = idx % BM; }
       sAr[m][k] = ra[e].x;
       sAi[m][k] = ra[e].y;
@@ -278,7 +278,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       const int idx = tid + e * 256;
       int n, k;
       if (bN) { k = idx / BN; n = idx % BN; }
-      else { n = idx / GBK; k = idx % GBK; }
+      else { n = idx / X32_BK; k = idx % X32_BK; }
       sBr[n][k] = rb[e].x;
       sBi[n][k] = rb[e].y;
     }
@@ -286,13 +286,13 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
   load(0);
   store();
   __syncthreads();
-  for (int k0 = 0; k0 < P.K; k0 += GBK) {
-    const bool more = k0 + GBK < P.K;
-    if (more) load(k0 + GBK);
+  for (int k0 = 0; k0 < P.K; k0 += X32_BK) {
+    const bool more = k0 + X32_BK < P.K;
+    if (more) load(k0 + X32_BK);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {  // two halves of four k steps
+    for (int h = 0; h < X32_BK / 8; ++h) {  // groups of four k steps
       f4v ar[WM], ai[WM], as[WM], br[WN], bi[WN], bs[WN];
-      const int kq = 8 * g + 4 * h;
+      const int kq = (X32_BK / 2) * g + 4 * h;
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         const int row = wm * 32 * WM + i * 32 + l32;

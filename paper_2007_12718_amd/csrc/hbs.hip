@@ -410,15 +410,48 @@ __global__ void k_gather_rows(const z64* Lt, int m, const int* rest, int nr, int
 }
 
 // D[q] = diagonal block q of L11 (nb x nb), identity-padded past k
-__global__ void k_diag_blocks(const z64* L11, int k, int nb, z64* D, int nblk) {
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= (long)nblk * nb * nb) return;
-  const int q = (int)(e / ((long)nb * nb)), rr = (int)((e / nb) % nb), cc = (int)(e % nb);
-  const int gi = q * nb + rr, gj = q * nb + cc;
-  z64 v = mk(0.0, 0.0);
-  if (gi < k && gj < k) v = L11[(long)gi * k + gj];
-  else if (rr == cc) v = mk(1.0, 0.0);
-  D[e] = v;
+// Inverses of the 64 x 64 lower-triangular diagonal blocks of L11 (the last
+// block padded with the identity) by forward substitution, one workgroup per
+// block.  The four lanes of a quad share column c of the inverse, lane part
+// holding rows 16 part .. 16 part + 15; step q finishes X[q][c] and passes it
+// along the quad, whose later rows subtract L[r][q] X[q][c].
+constexpr int TRI_B = 64;
+__global__ __launch_bounds__(256) void k_trinv_blocks(const z64* L11, int k, z64* Dinv) {
+  __shared__ z64 Ls[TRI_B][TRI_B];
+  __shared__ z64 rd[TRI_B];  // 1 / L[q][q]
+  const int tid = threadIdx.x, base = blockIdx.x * TRI_B;
+  for (int e = tid; e < TRI_B * TRI_B; e += 256) {
+    const int r = e / TRI_B, c = e % TRI_B, gi = base + r, gj = base + c;
+    z64 v = mk(0.0, 0.0);
+    if (gi < k && gj < k) v = L11[(long)gi * k + gj];
+    else if (r == c) v = mk(1.0, 0.0);
+    Ls[r][c] = v;
+  }
+  __syncthreads();
+  if (tid < TRI_B) rd[tid] = crecip(Ls[tid][tid]);
+  __syncthreads();
+  const int c = tid >> 2, part = tid & 3, lane = tid & 63;
+  z64 x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) x[i] = mk(16 * part + i == c ? 1.0 : 0.0, 0.0);
+  for (int q = 0; q < TRI_B; ++q) {
+    z64 xq = mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (16 * part + i == q) xq = x[i] * rd[q];
+    const int src = (lane & ~3) | (q >> 4);
+    xq.x = __shfl(xq.x, src);
+    xq.y = __shfl(xq.y, src);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = 16 * part + i;
+      if (r == q) x[i] = xq;
+      else if (r > q) x[i] = x[i] - Ls[r][q] * xq;
+    }
+  }
+  z64* D = Dinv + (long)blockIdx.x * TRI_B * TRI_B;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) D[(16 * part + i) * TRI_B + c] = x[i];
 }
 
 // U[piv[a]] = e_a ; U[rest[r]] = X[r]
@@ -816,59 +849,89 @@ __global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, do
 }
 
 // Wt partial sums over depth chunk c (BP_KC deep): part[c][q][i] =
-// sum_{t in chunk, t < j} conj(L(P_q, t)) L(i, t) for q < np.  Thread per
-// unchosen row i (chosen rows get zeros later); the pivot rows' values in
-// LDS, 2 BP_SUB depths at a time; NQ accumulators (the pivot count rounded
-// up to a multiple of 8).
-template <int NQ>
-__device__ __forceinline__ void bp_wt_body(const z64* Lt, const int* Pq, int m, int j, int np, int c, bool live,
-                                           int i, z64 (*Lp)[BP_NP], z64* part) {
-  const int tid = threadIdx.x, t0 = c * BP_KC;
-  z64 acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = mk(0.0, 0.0);
-  const int tend = (j - t0) < BP_KC ? j : t0 + BP_KC;
-  for (int s0 = t0; s0 < tend; s0 += 2 * BP_SUB) {
-    __syncthreads();
-    for (int e = tid; e < 2 * BP_SUB * NQ; e += 256) {
-      const int t = e / NQ, q = e % NQ;
-      Lp[t][q] = (q < np && s0 + t < tend) ? conjg(Lt[(long)(s0 + t) * m + Pq[q]]) : mk(0.0, 0.0);
-    }
-    __syncthreads();
-    if (live) {
-      const int tn = (tend - s0) < 2 * BP_SUB ? (tend - s0) : 2 * BP_SUB;
-      for (int tb = 0; tb < tn; tb += 8) {  // eight independent loads in flight
-        z64 l[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) l[u] = tb + u < tn ? Lt[(long)(s0 + tb + u) * m + i] : mk(0.0, 0.0);
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + Lp[tb + u][q] * l[u];
-      }
-    }
-  }
-  if (!live) return;
-  z64* pc = part + (long)c * BP_NP * m;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-    if (q < np) pc[(long)q * m + i] = acc[q];
-}
-
-__global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, const int* chosen, int m, const int* st,
-                                               z64* part) {
-  __shared__ z64 Lp[BP_SUB * 2][BP_NP];
+// sum_{t in chunk, t < j} conj(L(P_q, t)) L(i, t) for q < np, as a product
+// on the 16x16x4 FP64 matrix instruction: (pivots x depth) times (depth x
+// rows).  The pivot rows' conjugated values for the chunk sit in LDS (real
+// and imaginary planes); each wave owns 64 rows i and streams their factor
+// entries from HBM (16 consecutive rows per instruction operand, the next
+// four depths in flight).  Four real products per complex step; the second
+// pivot tile is skipped when np <= 16.  Rows already chosen are computed too
+// (the new-columns kernel ignores them).
+constexpr int BP_WT_ROWS = 256;  // rows per workgroup: four waves of 64
+__global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int m, const int* st, z64* part) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  __shared__ double Apr[BP_NP][BP_KC + 1], Api[BP_NP][BP_KC + 1];
   if (st[BPS_DONE]) return;
   const int j = st[BPS_J], np = st[BPS_NP];
-  const int c = blockIdx.y;
-  if (c * BP_KC >= j) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const bool live = i < m && !chosen[i];
+  const int c = blockIdx.y, t0 = c * BP_KC;
+  if (t0 >= j) return;
+  const int tn = (j - t0) < BP_KC ? (j - t0) : BP_KC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int* Pq = J + j;
-  if (np <= 8) bp_wt_body<8>(Lt, Pq, m, j, np, c, live, i, Lp, part);
-  else if (np <= 16) bp_wt_body<16>(Lt, Pq, m, j, np, c, live, i, Lp, part);
-  else if (np <= 24) bp_wt_body<24>(Lt, Pq, m, j, np, c, live, i, Lp, part);
-  else bp_wt_body<32>(Lt, Pq, m, j, np, c, live, i, Lp, part);
+  for (int e = tid; e < BP_NP * BP_KC; e += 256) {
+    const int q = e / BP_KC, t = e % BP_KC;
+    const z64 v = (q < np && t < tn) ? Lt[(long)(t0 + t) * m + Pq[q]] : mk(0.0, 0.0);
+    Apr[q][t] = v.x;
+    Api[q][t] = -v.y;
+  }
+  __syncthreads();
+  const int i0 = blockIdx.x * BP_WT_ROWS + wave * 64, lr = lane & 15, lk = lane >> 4;
+  const bool two = np > 16;
+  d4 wr[2][4], wi[2][4];
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt)
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+      wr[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
+      wi[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  auto loadB = [&](int s0, double (&br)[4], double (&bi)[4]) {
+    const int t = s0 + lk;
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+      const int i = i0 + 16 * jt + lr;
+      const z64 v = (t < tn && i < m) ? Lt[(long)(t0 + t) * m + i] : mk(0.0, 0.0);
+      br[jt] = v.x;
+      bi[jt] = v.y;
+    }
+  };
+  double br[4], bi[4];
+  loadB(0, br, bi);
+  for (int s0 = 0; s0 < tn; s0 += 4) {
+    double nbr[4], nbi[4];
+    loadB(s0 + 4, nbr, nbi);  // the next four depths in flight meanwhile
+    const int t = s0 + lk;    // (< BP_KC: s0 < tn <= BP_KC and s0 % 4 == 0)
+#pragma unroll
+    for (int qt = 0; qt < 2; ++qt) {
+      if (qt == 1 && !two) break;
+      const double ar = Apr[16 * qt + lr][t], ai = Api[16 * qt + lr][t], nai = -ai;
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) {
+        wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br[jt], wr[qt][jt], 0, 0, 0);
+        wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi[jt], wr[qt][jt], 0, 0, 0);
+        wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi[jt], wi[qt][jt], 0, 0, 0);
+        wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br[jt], wi[qt][jt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+      br[jt] = nbr[jt];
+      bi[jt] = nbi[jt];
+    }
+  }
+  // accumulator register r of lane l holds the pivot row lk + 4 r of its tile
+  z64* pc = part + (long)c * BP_NP * m;
+#pragma unroll
+  for (int qt = 0; qt < 2; ++qt) {
+    if (qt == 1 && !two) break;
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * qt + lk + 4 * r, i = i0 + 16 * jt + lr;
+        if (q < np && i < m) pc[(long)q * m + i] = mk(wr[qt][jt][r], wi[qt][jt][r]);
+      }
+  }
 }
 
 // New factor rows Lt[j+q][i] = sum_q' conj(Linv[q][q']) W[q'][i] with
@@ -970,10 +1033,10 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
     hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div((long)nr * k, 256)), dim3(256), 0, s, Lt, m, rest, nr, k, Lr);
     LSH_LAUNCH_CHECK();
     const int nblk = ceil_div(k, DB);
-    hipLaunchKernelGGL(k_diag_blocks, dim3(ceil_div((long)nblk * DB * DB, 256)), dim3(256), 0, s, L11, k, DB, Dinv,
-                       nblk);
+    static_assert(DB == TRI_B, "diagonal block size");
+    hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk), dim3(256), 0, s, L11, k, Dinv);
     LSH_LAUNCH_CHECK();
-    inverse<double>(s, Dinv, DB, DB, (long)DB * DB, nblk, invws, nullptr);
+    (void)invws;
     z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
     // X L11 = Lr, recursively on column halves (L11 lower triangular):
     // X(:, right) first, then Lr(:, left) -= X(:, right) L11(right, left),
@@ -1058,7 +1121,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
       LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_wt", s, 16.0 * m * m);
-        hipLaunchKernelGGL(k_bp_wt, dim3(gm, nch), dim3(256), 0, s, Lt, J, chosen, m, st, partW);
+        hipLaunchKernelGGL(k_bp_wt, dim3(ceil_div(m, BP_WT_ROWS), nch), dim3(256), 0, s, Lt, J, m, st, partW);
       }
       LSH_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_bp_newcols, dim3(ceil_div(m, BP_NCR)), dim3(1024), 0, s, Lt, M, m, J, partW, Lpp, Linv,
@@ -1175,52 +1238,7 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
     rank = st[0];
   }
   const int k = rank < 1 ? 1 : rank;
-  // U(piv, :) = I and U(rest, :) = L(rest, 0:k) L11^{-1}: X L11 = Lr solved by
-  // column blocks from the right (L11 lower triangular).
-  std::vector<int> ph(k), rh;
-  LSH_HIP(hipMemcpyAsync(ph.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-  LSH_HIP(hipStreamSynchronize(s));
-  {
-    std::vector<char> used(m, 0);
-    for (int v : ph) used[v] = 1;
-    for (int i = 0; i < m; ++i)
-      if (!used[i]) rh.push_back(i);
-  }
-  const int nr = (int)rh.size();
-  if (nr) LSH_HIP(hipMemcpyAsync(rest, rh.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_gather_L11, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, Lt, m, J, k, L11);
-  LSH_LAUNCH_CHECK();
-  if (nr) {
-    hipLaunchKernelGGL(k_gather_rows, dim3(ceil_div((long)nr * k, 256)), dim3(256), 0, s, Lt, m, rest, nr, k, Lr);
-    LSH_LAUNCH_CHECK();
-    const int nblk = ceil_div(k, DB);
-    hipLaunchKernelGGL(k_diag_blocks, dim3(ceil_div((long)nblk * DB * DB, 256)), dim3(256), 0, s, L11, k, DB, Dinv,
-                       nblk);
-    LSH_LAUNCH_CHECK();
-    inverse<double>(s, Dinv, DB, DB, (long)DB * DB, nblk, invws, nullptr);
-    z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
-    // X L11 = Lr, recursively on column halves (L11 lower triangular):
-    // X(:, right) first, then Lr(:, left) -= X(:, right) L11(right, left),
-    // then X(:, left); diagonal blocks of DB columns use their inverses
-    std::function<void(int, int)> solve = [&](int q0, int q1) {  // diagonal blocks q0 .. q1-1
-      const int c0 = q0 * DB, c1 = (q1 * DB < k) ? q1 * DB : k;
-      if (q1 - q0 == 1) {  // X(:, B) = Lr(:, B) L11(B, B)^{-1}
-        cgemm<double>(s, nr, c1 - c0, c1 - c0, mk(1.0, 0.0), Lr + c0, k, 0, OP_N, Dinv + (long)q0 * DB * DB, DB, 0,
-                      OP_N, mk(0.0, 0.0), nullptr, 0, 0, X + c0, k, 0, 1);
-        return;
-      }
-      const int qm = (q0 + q1) / 2, cm = qm * DB;
-      solve(qm, q1);
-      cgemm<double>(s, nr, cm - c0, c1 - cm, mk(-1.0, 0.0), X + cm, k, 0, OP_N, L11 + (long)cm * k + c0, k, 0, OP_N,
-                    mk(1.0, 0.0), Lr + c0, k, 0, Lr + c0, k, 0, 1);
-      solve(q0, qm);
-    };
-    solve(0, nblk);
-    hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)(k + nr) * k, 256)), dim3(256), 0, s, U, k, J, rest, nr, X);
-  } else {
-    hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J, rest, 0, L11);
-  }
-  LSH_LAUNCH_CHECK();
+  gram_interp(s, Lt, m, k, J, U, rest, L11, Lr, Dinv, invws);
   return k;
 }
 
