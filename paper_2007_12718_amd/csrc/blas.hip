@@ -835,10 +835,15 @@ __device__ __forceinline__ void lds_sync() {
 template <typename R>
 constexpr int gj_kr() { return GJ_STAGE_BYTES / (GJ_NT * (int)sizeof(cplx<R>)); }
 
+// After its columns, the panel writes Tb[q][t] = A[p_{j0+q}][s0 + t] for the
+// other columns of its slab (zero in its own), the pivot rows the slab
+// update needs before any of them changes (Tb null or w2 <= nb: no update).
 template <typename R, int RPT, int NB>
-__device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int j0, int* pb, int* ub, int* infob) {
+__device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int j0, int* pb, int* ub, int* infob,
+                                              int s0, int w2, cplx<R>* Tb) {
   constexpr int KR = gj_kr<R>();
   __shared__ cplx<R> stg[KR * GJ_NT];
+  __shared__ int pvs[NB];
   __shared__ cplx<R> cand[2][GJ_NT / 64][NB];  // each wave's best candidate row (double-buffered)
   __shared__ unsigned long long ckey[2][GJ_NT / 64];
   const int nt = blockDim.x, nw = nt >> 6;
@@ -922,6 +927,7 @@ __device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int 
     if (tid == 0) {
       pb[j] = p;
       ub[p] = 1;
+      pvs[jj] = p;
       if (!(abs2(pr[jj]) > R(0)) && infob && *infob == 0) *infob = j + 1;
     }
     const cplx<R> rp = crecip(pr[jj]);
@@ -960,13 +966,60 @@ __device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int 
       if (e < ne && q < nb) Ab[(long)(e / NB) * lda + j0 + q] = stg[tid + k * nt];
     }
   }
+  if (Tb && w2 > nb) {
+    lds_sync();  // (pvs)
+    for (int e = tid; e < nb * w2; e += nt) {
+      const int q = e / w2, col = s0 + e % w2;
+      Tb[e] = (col >= j0 && col < j0 + nb) ? mk<R>(0, 0) : Ab[(long)pvs[q] * lda + col];
+    }
+  }
+}
+
+// The rest of slab [s0, s0 + w2) after the panel [j0, j0 + nb): row i gets
+// A[i][col] += sum_q F[i][q] T[q][col] with F[i][q] = A[i][j0 + q] -
+// [i == p_{j0+q}] (the panel's finished columns) and T from the panel.  The
+// 64 lanes of a wave take one row, a column each.
+template <typename R>
+__device__ __forceinline__ void gj_slab_update_body(cplx<R>* Ab, int c, long lda, int j0, int nb, int s0, int w2,
+                                                    const int* pb, const cplx<R>* Tb, int i, int lane) {
+  if (i >= c) return;
+  cplx<R> f[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    f[q] = q < nb ? Ab[(long)i * lda + j0 + q] : mk<R>(0, 0);
+    if (q < nb && i == pb[q]) f[q].x -= R(1);
+  }
+  for (int t = lane; t < w2; t += 64) {
+    const int col = s0 + t;
+    if (col >= j0 && col < j0 + nb) continue;
+    cplx<R> acc = Ab[(long)i * lda + col];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nb) {
+        const cplx<R> tv = Tb[q * w2 + t];
+        acc.x = fmaR(f[q].x, tv.x, acc.x);
+        acc.x = fmaR(-f[q].y, tv.y, acc.x);
+        acc.y = fmaR(f[q].x, tv.y, acc.y);
+        acc.y = fmaR(f[q].y, tv.x, acc.y);
+      }
+    Ab[(long)i * lda + col] = acc;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gj_slab_update(cplx<R>* A, int c, long lda, long sA, int j0, int nb, int s0,
+                                                        int w2, const int* perm, const cplx<R>* T, int nb2) {
+  const long b = blockIdx.y;
+  gj_slab_update_body<R>(A + b * sA, c, lda, j0, nb, s0, w2, perm + b * c + j0, T + b * (long)nb2 * c,
+                         blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 template <typename R, int RPT, int NB>
 __global__ __launch_bounds__(GJ_NT) void k_gj_panel(cplx<R>* A, int c, long lda, long sA, int j0, int* perm,
-                                                    int* used, int* info) {
+                                                    int* used, int* info, int s0, int w2, cplx<R>* T, int nb2) {
   const long b = blockIdx.x;
-  gj_panel_body<R, RPT, NB>(A + b * sA, c, lda, j0, perm + b * c, used + b * c, info ? info + b : nullptr);
+  gj_panel_body<R, RPT, NB>(A + b * sA, c, lda, j0, perm + b * c, used + b * c, info ? info + b : nullptr, s0, w2,
+                            T + b * (long)nb2 * c);
 }
 
 // Block K = columns [kb, kb+nbk) with pivot rows perm[kb ..]:
@@ -1054,13 +1107,13 @@ size_t inverse_ws_bytes(int c, int batch) {
 
 template <typename R, int NB>
 static void gj_panel_launch(hipStream_t s, int rpt, int nt, cplx<R>* A, int c, long lda, long sA, int j0,
-                            int* perm, int* used, int batch, int* info) {
+                            int* perm, int* used, int batch, int* info, int s0, int w2, cplx<R>* T, int nb2) {
   const size_t lds = 0;
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_gj_panel<R, 1, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
-    case 2: hipLaunchKernelGGL((k_gj_panel<R, 2, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
-    case 3: hipLaunchKernelGGL((k_gj_panel<R, 3, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
-    default: hipLaunchKernelGGL((k_gj_panel<R, 4, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info); break;
+    case 1: hipLaunchKernelGGL((k_gj_panel<R, 1, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info, s0, w2, T, nb2); break;
+    case 2: hipLaunchKernelGGL((k_gj_panel<R, 2, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info, s0, w2, T, nb2); break;
+    case 3: hipLaunchKernelGGL((k_gj_panel<R, 3, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info, s0, w2, T, nb2); break;
+    default: hipLaunchKernelGGL((k_gj_panel<R, 4, NB>), dim3(batch), dim3(nt), lds, s, A, c, lda, sA, j0, perm, used, info, s0, w2, T, nb2); break;
   }
   LSH_LAUNCH_CHECK();
 }
@@ -1108,14 +1161,12 @@ void inverse(hipStream_t s, cplx<R>* A, int c, long lda, long sA, int batch, voi
     const int w2 = (c - s0) < NB2 ? (c - s0) : NB2;
     for (int j0 = s0; j0 < s0 + w2; j0 += NB) {
       const int nb = (s0 + w2 - j0) < NB ? (s0 + w2 - j0) : NB;
-      if (NB == 8) gj_panel_launch<R, 8>(s, rpt, nt, A, c, lda, sA, j0, perm, used, batch, info);
-      else gj_panel_launch<R, 4>(s, rpt, nt, A, c, lda, sA, j0, perm, used, batch, info);
+      if (NB == 8) gj_panel_launch<R, 8>(s, rpt, nt, A, c, lda, sA, j0, perm, used, batch, info, s0, w2, T, NB2);
+      else gj_panel_launch<R, 4>(s, rpt, nt, A, c, lda, sA, j0, perm, used, batch, info, s0, w2, T, NB2);
       if (w2 > nb) {  // the rest of the slab
-        hipLaunchKernelGGL(k_gj_gather<R>, dim3(grid_for((long)(nb + c) * w2), batch), dim3(256), 0, s, A, c, lda,
-                           sA, j0, nb, s0, w2, perm, T, F);
+        hipLaunchKernelGGL(k_gj_slab_update<R>, dim3(ceil_div(c, 4), batch), dim3(256), 0, s, A, c, lda, sA, j0, nb,
+                           s0, w2, perm, T, NB2);
         LSH_LAUNCH_CHECK();
-        cgemm<R>(s, c, w2, nb, one, F, nb, (long)c * nb, OP_N, T, w2, (long)nb * w2, OP_N, one, A + s0, lda, sA,
-                 A + s0, lda, sA, batch);
       }
     }
     if (c > w2) {  // every column outside the slab, depth w2
@@ -1189,7 +1240,22 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_panel_grouped(const InvDev* G, int
   if (j0 >= se) return;
   const long b = gm - it.mat0;
   gj_panel_body<float, 1, 8>(it.A + b * it.sA, c, it.lda, j0, it.perm + b * c, it.used + b * c,
-                             it.info ? it.info + b : nullptr);
+                             it.info ? it.info + b : nullptr, s0, se - s0, it.T + b * (long)nb2 * c);
+}
+
+// the rest of slab s0 after panel j0 (items with such a rest)
+__global__ __launch_bounds__(256) void k_gj_slab_update_grouped(const InvDev* G, int ng, int s0, int nb2, int j0) {
+  const long gm = blockIdx.y;
+  const InvDev& it = G[inv_item_of(G, ng, gm)];
+  const int c = it.c;
+  if (s0 >= c) return;
+  const int w2 = (c - s0) < nb2 ? c - s0 : nb2;
+  if (j0 >= s0 + w2) return;
+  const int nb = (s0 + w2 - j0) < 8 ? s0 + w2 - j0 : 8;
+  if (w2 <= nb) return;
+  const long b = gm - it.mat0;
+  gj_slab_update_body<float>(it.A + b * it.sA, c, it.lda, j0, nb, s0, w2, it.perm + b * c + j0,
+                             it.T + b * (long)nb2 * c, blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // mode 0: the rest of slab s0 after panel j0 (block [j0, j0+nb), columns of
@@ -1319,19 +1385,9 @@ void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws,
       for (int j0 = s0; j0 < s0 + NB2 && j0 < cmax_blocked; j0 += 8) {
         hipLaunchKernelGGL(k_gj_panel_grouped, dim3((unsigned)mblocked), dim3(nt), 0, s, Tb, ng, s0, NB2, j0);
         LSH_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_gj_gather_grouped, dim3(64, (unsigned)mblocked), dim3(256), 0, s, Tb, ng, 0, s0, NB2,
-                           j0);
+        hipLaunchKernelGGL(k_gj_slab_update_grouped, dim3(ceil_div(cmax_blocked, 4), (unsigned)mblocked), dim3(256),
+                           0, s, Tb, ng, s0, NB2, j0);
         LSH_LAUNCH_CHECK();
-        for (const InvDev& d : blocked) {
-          if (s0 >= d.c) continue;
-          const int w2 = (d.c - s0) < NB2 ? d.c - s0 : NB2;
-          if (j0 >= s0 + w2) continue;
-          const int nb = (s0 + w2 - j0) < 8 ? s0 + w2 - j0 : 8;
-          if (w2 <= nb) continue;
-          gi.push_back({d.c, w2, nb, one, one, d.F, nb, (long)d.c * nb, OP_N, d.T, w2, (long)nb * w2, OP_N,
-                        d.A + s0, d.lda, d.sA, d.A + s0, d.lda, d.sA, d.batch, false});
-        }
-        gemms(gi);
       }
       hipLaunchKernelGGL(k_gj_gather_grouped, dim3(64, (unsigned)mblocked), dim3(256), 0, s, Tb, ng, 1, s0, NB2, 0);
       LSH_LAUNCH_CHECK();
