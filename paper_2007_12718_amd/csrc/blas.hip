@@ -539,48 +539,97 @@ template void mirror_lower<float>(hipStream_t, cplx<float>*, int, long);
 
 // ---------------------------------------------------------------- GEMV
 // One wavefront per row, lanes stride the row (coalesced); x_b staged in LDS.
-constexpr int GV_ROWS = 16;
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_cgemv(int M, int N, cplx<R> alpha,
-                                               const cplx<R>* __restrict__ A, long lda, long sA, int amod,
-                                               const cplx<R>* __restrict__ x, long sx, cplx<R> beta,
-                                               const cplx<R>* z, long sz, cplx<R>* y, long sy) {
-  extern __shared__ unsigned char smem_raw[];
-  cplx<R>* xs = reinterpret_cast<cplx<R>*>(smem_raw);
-  const long b = blockIdx.x;  // problem index (unbounded grid dimension)
-  const cplx<R>* Ab = A + (b % amod) * sA;
-  const cplx<R>* xb = x + b * sx;
-  for (int j = threadIdx.x; j < N; j += blockDim.x) xs[j] = xb[j];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
-    const int i = blockIdx.y * GV_ROWS + wave * (GV_ROWS / 4) + rr;
-    if (i >= M) break;
-    const cplx<R>* row = Ab + (long)i * lda;
-    // eight independent loads in flight per lane, four partial sums
-    cplx<R> a4[4] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
-    int j = lane;
-    for (; j + 7 * 64 < N; j += 8 * 64) {
-      cplx<R> v[8];
+// Per-problem GEMV over the rows of all problems: global row g = b M + i
+// (problem b, row i of its matrix, matrix b mod amod).  L lanes share a row
+// (a power of two, the row length rounded up, at most 64); a wave takes
+// 64 / L rows per pass, and P passes whose loads are issued together, so that
+// short rows (small boxes) still keep many loads in flight.  x is read
+// through the caches (the rows of one problem share it).
+template <typename R, int L, int P>
+__global__ __launch_bounds__(256) void k_cgemv(int M, int N, cplx<R> alpha, const cplx<R>* __restrict__ A, long lda,
+                                               long sA, int amod, const cplx<R>* __restrict__ x, long sx,
+                                               cplx<R> beta, const cplx<R>* z, long sz, cplx<R>* y, long sy,
+                                               long rows) {
+  constexpr int RW = 64 / L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sub = lane & (L - 1);
+  // rows < 2^31 (checked by the launcher): 32-bit problem / row split, once
+  const unsigned g0 = ((blockIdx.x * 4u + wave) * P) * RW + lane / L;
+  unsigned bp[P], ip[P];
+  {
+    unsigned b = g0 / (unsigned)M, i = g0 - b * (unsigned)M;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = row[j + u * 64];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) fma_acc(a4[u & 3], v[u], xs[j + u * 64]);
-    }
-    for (; j < N; j += 64) fma_acc(a4[0], row[j], xs[j]);
-    cplx<R> acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off);
-      acc.y += __shfl_xor(acc.y, off);
-    }
-    if (lane == 0) {
-      cplx<R> v = alpha * acc;
-      if (z && (beta.x != R(0) || beta.y != R(0))) v = v + beta * z[b * sz + i];
-      y[b * sy + i] = v;
+    for (int p = 0; p < P; ++p) {
+      bp[p] = b;
+      ip[p] = i;
+      i += RW;
+      while (i >= (unsigned)M) { i -= M; ++b; }
     }
   }
+  cplx<R> acc[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) acc[p] = mk<R>(0, 0);
+  if (N <= L) {  // one element per lane and row: all P loads in flight together
+    cplx<R> av[P], xv[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const long g = (long)g0 + (long)p * RW;
+      av[p] = xv[p] = mk<R>(0, 0);
+      if (g < rows && sub < N) {
+        av[p] = A[(long)(bp[p] % (unsigned)amod) * sA + (long)ip[p] * lda + sub];
+        xv[p] = x[(long)bp[p] * sx + sub];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) fma_acc(acc[p], av[p], xv[p]);
+  } else {  // long rows (L == 64): eight independent loads per lane per row
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const long g = (long)g0 + (long)p * RW;
+      if (g >= rows) break;
+      const cplx<R>* row = A + (long)(bp[p] % (unsigned)amod) * sA + (long)ip[p] * lda;
+      const cplx<R>* xb = x + (long)bp[p] * sx;
+      cplx<R> a4[4] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
+      for (int j = sub; j < N; j += 8 * L) {
+        cplx<R> v[8], xw[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int jj = j + u * L;
+          v[u] = jj < N ? row[jj] : mk<R>(0, 0);
+          xw[u] = jj < N ? xb[jj] : mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) fma_acc(a4[u & 3], v[u], xw[u]);
+      }
+      acc[p] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    cplx<R> v = acc[p];
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {  // (stays inside the row's L lanes)
+      v.x += __shfl_xor(v.x, off);
+      v.y += __shfl_xor(v.y, off);
+    }
+    const long g = (long)g0 + (long)p * RW;
+    if (sub == 0 && g < rows) {
+      const long b = bp[p], i = ip[p];
+      cplx<R> o = alpha * v;
+      if (z && (beta.x != R(0) || beta.y != R(0))) o = o + beta * z[b * sz + i];
+      y[b * sy + i] = o;
+    }
+  }
+}
+
+template <typename R, int L, int P>
+static void cgemv_launch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<R>* A, long lda, long sA, int amod,
+                         const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz, cplx<R>* y, long sy,
+                         long rows) {
+  const long per_wg = 4L * P * (64 / L);
+  const long g = (rows + per_wg - 1) / per_wg;
+  LSH_REQUIRE(rows + per_wg < 2147483647L, -6, "cgemv: too many rows");
+  hipLaunchKernelGGL((k_cgemv<R, L, P>), dim3((unsigned)g), dim3(256), 0, s, M, N, alpha, A, lda, sA, amod, x, sx,
+                     beta, z, sz, y, sy, rows);
 }
 
 template <typename R>
@@ -589,67 +638,69 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
            const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz,
            cplx<R>* y, long sy, int batch) {
   if (M <= 0 || batch <= 0) return;
-  LSH_REQUIRE((size_t)N * sizeof(cplx<R>) <= 65536, -6, "cgemv: row length too large for LDS staging");
   // algorithmic bytes: every distinct matrix once, x, z and y once per problem
   const int nmat = amod < batch ? amod : batch;
   ProfScope ps(sizeof(R) == 4 ? "cgemv_f32" : "cgemv_f64", s,
                (double)sizeof(cplx<R>) * ((double)nmat * M * N + (double)batch * (N + (z ? 2.0 : 1.0) * M)));
-  LSH_REQUIRE(ceil_div(M, GV_ROWS) <= 65535, -6, "cgemv: too many rows");
-  dim3 grid(batch, ceil_div(M, GV_ROWS));
-  hipLaunchKernelGGL(k_cgemv<R>, grid, dim3(256), N * sizeof(cplx<R>), s, M, N, alpha, A, lda, sA,
-                     amod > 0 ? amod : 1, x, sx, beta, z, sz, y, sy);
+  const long rows = (long)batch * M;
+  const int am = amod > 0 ? amod : 1;
+  if (N <= 8) cgemv_launch<R, 8, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
+  else if (N <= 16) cgemv_launch<R, 16, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
+  else if (N <= 32) cgemv_launch<R, 32, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
+  else if (N <= 64) cgemv_launch<R, 64, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
+  else if (N <= 512) cgemv_launch<R, 64, 2>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
+  else cgemv_launch<R, 64, 1>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
   LSH_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------ shared-matrix multi-GEMV
-// One wavefront per row of Mat (lanes stride the row), up to MG_VEC vectors
-// accumulated in registers; X is read through the caches by every wave.
+// One workgroup per row of Mat: the four waves interleave over the row (a
+// wave reads 64 consecutive entries, the workgroup 256), four loads in flight
+// per lane; up to MG_VEC vectors accumulated in registers, X read through the
+// caches; the waves' partial sums meet in LDS.
 constexpr int MG_VEC = 8;
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int C, cplx<R> alpha, const cplx<R>* __restrict__ Mat,
                                                 long ldm, const cplx<R>* __restrict__ X, long ldx, cplx<R> beta,
                                                 const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+  __shared__ cplx<R> red[4][MG_VEC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = blockIdx.x * 4 + wave;
-  if (i >= Rr) return;
+  const int i = blockIdx.x;
   const cplx<R>* row = Mat + (long)i * ldm;
   for (int b0 = 0; b0 < nvec; b0 += MG_VEC) {
     const int nb = nvec - b0 < MG_VEC ? nvec - b0 : MG_VEC;
     cplx<R> acc[MG_VEC];
 #pragma unroll
     for (int v = 0; v < MG_VEC; ++v) acc[v] = mk<R>(0, 0);
-    int j = lane;
-    for (; j + 3 * 64 < C; j += 4 * 64) {  // four matrix loads in flight per lane
+    for (int j = threadIdx.x; j < C; j += 4 * 256) {
       cplx<R> a[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = row[j + u * 64];
+      for (int u = 0; u < 4; ++u) a[u] = j + u * 256 < C ? row[j + u * 256] : mk<R>(0, 0);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < MG_VEC; ++v)
-          if (v < nb) fma_acc(acc[v], a[u], X[(long)(b0 + v) * ldx + j + u * 64]);
-    }
-    for (; j < C; j += 64) {
-      const cplx<R> a = row[j];
-#pragma unroll
-      for (int v = 0; v < MG_VEC; ++v)
-        if (v < nb) fma_acc(acc[v], a, X[(long)(b0 + v) * ldx + j]);
+          if (v < nb && j + u * 256 < C) fma_acc(acc[v], a[u], X[(long)(b0 + v) * ldx + j + u * 256]);
     }
 #pragma unroll
     for (int v = 0; v < MG_VEC; ++v) {
-      if (v >= nb) break;
-      cplx<R> a = acc[v];
+      cplx<R> t = acc[v];
       for (int off = 32; off > 0; off >>= 1) {
-        a.x += __shfl_xor(a.x, off);
-        a.y += __shfl_xor(a.y, off);
+        t.x += __shfl_xor(t.x, off);
+        t.y += __shfl_xor(t.y, off);
       }
-      if (lane == 0) {
-        cplx<R> r = alpha * a;
-        if (Z && (beta.x != R(0) || beta.y != R(0))) r = r + beta * Z[(long)(b0 + v) * ldz + i];
-        Y[(long)(b0 + v) * ldy + i] = r;
-      }
+      if (lane == 0) red[wave][v] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < nb) {
+      const int v = threadIdx.x;
+      const cplx<R> t = (red[0][v] + red[1][v]) + (red[2][v] + red[3][v]);
+      cplx<R> r = alpha * t;
+      if (Z && (beta.x != R(0) || beta.y != R(0))) r = r + beta * Z[(long)(b0 + v) * ldz + i];
+      Y[(long)(b0 + v) * ldy + i] = r;
+    }
+    __syncthreads();
   }
 }
 
@@ -659,8 +710,8 @@ void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, lon
   if (Rr <= 0 || nvec <= 0) return;
   ProfScope ps(sizeof(R) == 4 ? "cmgemv_f32" : "cmgemv_f64", s,
                (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * (C + (Z ? 2.0 : 1.0) * Rr)));
-  hipLaunchKernelGGL(k_cmgemv<R>, dim3(ceil_div(Rr, 4)), dim3(256), 0, s, Rr, C, alpha, Mat, ldm, X, ldx, beta, Z,
-                     ldz, Y, ldy, nvec);
+  hipLaunchKernelGGL(k_cmgemv<R>, dim3(Rr), dim3(256), 0, s, Rr, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy,
+                     nvec);
   LSH_LAUNCH_CHECK();
 }
 
