@@ -133,7 +133,12 @@ int lsh_factor_create(lsh_plan_t plan, const double* b, void* stream, lsh_factor
  * exist (Sec. 3.2 builds them leaves-up, like Algorithm 1), so the
  * latency-bound pivot loops of the compression overlap the factor's matrix
  * products.  Same results as lsh_plan_create + lsh_factor_create; destroy
- * the factor, then the plan.  Synchronises the stream before returning. */
+ * the factor, then the plan.  Synchronises the stream before returning.
+ * The plan runs on a library stream; the factor runs on a library stream
+ * kept off LSH_PLAN_CUS compute units (default: an eighth of them for FP32
+ * factors, none for FP64; 0 = the caller's stream, unmasked), so that the
+ * plan's latency-bound kernels find free units while the factor's products
+ * fill the rest. */
 int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* plan, lsh_factor_t* factor);
 int lsh_factor_destroy(lsh_factor_t factor);
 

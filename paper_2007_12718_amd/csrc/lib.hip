@@ -1159,14 +1159,41 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
     hipStream_t st;
     ~StreamGuard() { if (st) (void)hipStreamDestroy(st); }
   } sg{ps};
+  // The factor runs on a stream kept off LSH_PLAN_CUS compute units, so that
+  // the plan's small latency-bound kernels (the critical path) find free
+  // units while the factor's products fill the rest.  Default: an eighth of
+  // the units for the FP32 factor, none for the FP64 factor (whose products
+  // are the longer path).  Without CU masking the factor uses the caller's
+  // stream.
+  hipStream_t fsm = nullptr;
+  {
+    const char* e = std::getenv("LSH_PLAN_CUS");
+    int ncu = 0;
+    LSH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int reserve = (e && *e) ? std::atoi(e) : (desc->hbs_prec == LSH_FP32 ? ncu / 8 : 0);
+    if (reserve > 0 && reserve < ncu / 2) {
+      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+      for (int c = 0; c < ncu - reserve; ++c) mask[c / 32] |= 1u << (c % 32);
+      if (hipExtStreamCreateWithCUMask(&fsm, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        fsm = nullptr;
+      }
+    }
+  }
+  StreamGuard fg{fsm};
+  hipStream_t fs = fsm ? fsm : s;
   plan_init(*P, ps);
   const int L = P->L;
-  std::vector<hipEvent_t> ev(2 * L + 3, nullptr);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
+  std::vector<hipEvent_t> ev(2 * L + 5, nullptr);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
   struct EventGuard {
     std::vector<hipEvent_t>& v;
     ~EventGuard() { for (auto e : v) if (e) (void)hipEventDestroy(e); }
   } eg{ev};
   for (auto& e : ev) LSH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (fsm) {  // the factor stream follows the copy of b on the caller's stream
+    LSH_HIP(hipEventRecord(ev[2 * L + 3], s));
+    LSH_HIP(hipStreamWaitEvent(fsm, ev[2 * L + 3], 0));
+  }
   std::mutex mu;
   std::condition_variable cv;
   int doneU = L + 1, doneG = L + 1;  // lowest level with U_l / G_l ready; -2 = failed
@@ -1210,19 +1237,23 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
     auto run = [&](auto& FD) {
       factor_init(*P, FD);
       if (!wait_for(L, 0)) return;
-      LSH_HIP(hipStreamWaitEvent(s, ev[L], 0));
-      factor_leaves(*P, F->b.template as<double>(), FD, s);
+      LSH_HIP(hipStreamWaitEvent(fs, ev[L], 0));
+      factor_leaves(*P, F->b.template as<double>(), FD, fs);
       for (int l = L - 1; l >= 0; --l) {
         if (!wait_for(l, 1)) return;  // G_l: the merge overlaps the row ID of level l
-        LSH_HIP(hipStreamWaitEvent(s, ev[L + 1 + l], 0));
-        factor_merge(*P, FD, l, s);
+        LSH_HIP(hipStreamWaitEvent(fs, ev[L + 1 + l], 0));
+        factor_merge(*P, FD, l, fs);
         if (l >= 1) {
           if (!wait_for(l, 0)) return;
-          LSH_HIP(hipStreamWaitEvent(s, ev[l], 0));
-          factor_scatter(*P, FD, l, s);
+          LSH_HIP(hipStreamWaitEvent(fs, ev[l], 0));
+          factor_scatter(*P, FD, l, fs);
         }
       }
-      factor_check(FD, s);
+      factor_check(FD, fs);
+      if (fsm) {
+        LSH_HIP(hipEventRecord(ev[2 * L + 4], fsm));
+        LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 4], 0));
+      }
     };
     if (desc->hbs_prec == LSH_FP32) run(F->f32);
     else run(F->f64);
