@@ -464,13 +464,18 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
   P.B = B; P.ldb = ldb; P.sB = sB; P.opB = opB;
   P.D = D; P.ldd = ldd; P.sD = sD;
   P.C = C; P.ldc = ldc; P.sC = sC; P.addI = add_identity ? 1 : 0;
-  // large tiles when they still leave a few waves of workgroups in flight
-  const double big_tiles = (double)ceil_div(M, 128) * ceil_div(N, sizeof(R) == 4 ? 128 : 64) * batch;
   if constexpr (sizeof(R) == 4) {
     if (f32_tile(M, N, batch) == 0) launch_gemm_x32<2, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm_x32<1, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   } else {
-    if (M >= 128 && N >= 64 && K >= 32 && big_tiles >= 128) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    // FP64: the 64 x 64 tile (two workgroups per CU) beats 128 x 64 (one) on
+    // every measured shape (44-46 against 34-39 TF/s); LSH_GEMM64_TILE=0
+    // forces 128 x 64
+    static const int f64_forced = [] {
+      const char* e = getenv("LSH_GEMM64_TILE");
+      return e ? atoi(e) : -1;
+    }();
+    if (f64_forced == 0) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
 }

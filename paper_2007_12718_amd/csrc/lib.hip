@@ -365,7 +365,7 @@ struct FactorData {
   std::vector<DevBuf> vb;         // transpose pass: per parent level [nrhs][2^l][2c]
   int vb_nrhs = 0;
   // singularity flags of the local inverses, read back once when the factor ends
-  std::vector<DevBuf> info;
+  std::vector<AsyncBuf> info;  // stream-ordered: freeing them never waits for the device
   std::vector<int> info_n;
   std::vector<std::string> info_what;
 };
@@ -417,7 +417,7 @@ void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipSt
   leaf_build<R>(s, X, P.Gleaf<R>(), mL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
   {
     AsyncBuf ws(inverse_ws_bytes<R>(mL, nleaf), s);
-    F.info.emplace_back(sizeof(int) * nleaf);
+    F.info.emplace_back(sizeof(int) * nleaf, s);
     F.info_n.push_back(nleaf);
     F.info_what.push_back("singular leaf matrix I + B G");
     inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws.p, F.info.back().template as<int>());
@@ -451,7 +451,7 @@ void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
   {
     AsyncBuf ws(inverse_ws_bytes<R>(c, nb), s);
-    F.info.emplace_back(sizeof(int) * nb);
+    F.info.emplace_back(sizeof(int) * nb, s);
     F.info_n.push_back(nb);
     F.info_what.push_back("singular merge matrix I - Pb Pa at level " + std::to_string(l));
     inverse<R>(s, Ci, c, c, cc, nb, ws.p, F.info.back().template as<int>());
@@ -1111,7 +1111,7 @@ int lsh_factor_create(lsh_plan_t P, const double* b, void* stream, lsh_factor_t*
   F->b.alloc(sizeof(double) * N);
   LSH_HIP(hipMemcpyAsync(F->b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   {
-    DevBuf bad(sizeof(int));
+    AsyncBuf bad(sizeof(int), s);
     fill_zero(s, bad.p, sizeof(int));
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
     int hb = 0;
@@ -1143,7 +1143,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   F->b.alloc(sizeof(double) * N);
   LSH_HIP(hipMemcpyAsync(F->b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   {
-    DevBuf bad(sizeof(int));
+    AsyncBuf bad(sizeof(int), s);
     fill_zero(s, bad.p, sizeof(int));
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
     int hb = 0;
@@ -1478,7 +1478,7 @@ int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b,
     F->plan = P;
     F->b.alloc(sizeof(double) * N);
     LSH_HIP(hipMemcpyAsync(F->b.p, b[i], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    DevBuf bad(sizeof(int));
+    AsyncBuf bad(sizeof(int), s);
     fill_zero(s, bad.p, sizeof(int));
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
     int hb = 0;

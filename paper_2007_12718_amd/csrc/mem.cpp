@@ -10,6 +10,7 @@
 // off); a failed hipMalloc empties it and retries once.
 #include "mem.hpp"
 
+#include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -22,6 +23,14 @@ std::mutex mu;
 std::multimap<std::pair<int, size_t>, void*> blocks;  // (device, capacity) -> pointer
 size_t held = 0;
 thread_local int recycle_depth = 0;
+
+bool trace() {
+  static const bool t = [] {
+    const char* e = std::getenv("LSH_MEM_TRACE");
+    return e && *e == '1';
+  }();
+  return t;
+}
 
 size_t cap_bytes() {
   static const size_t c = [] {
@@ -70,6 +79,7 @@ hipError_t get(size_t n, void** p, size_t* cap) {
       return hipSuccess;
     }
   }
+  if (trace()) std::fprintf(stderr, "lsh mem: hipMalloc %zu bytes (cache miss)\n", *cap);
   e = hipMalloc(p, *cap);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
@@ -97,6 +107,7 @@ void put(void* p, size_t cap) {
       }
     }
   }
+  if (trace()) std::fprintf(stderr, "lsh mem: hipFree %zu bytes (outside a destroy)\n", cap);
   (void)hipFree(p);
 }
 

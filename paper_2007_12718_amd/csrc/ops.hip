@@ -190,7 +190,7 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
     dxy.push_back(e.dy);
     wv.push_back(mk(h * h * e.re, h * h * e.im));
   }
-  DevBuf ddxy(sizeof(int) * dxy.size()), dw(sizeof(z64) * wv.size());
+  AsyncBuf ddxy(sizeof(int) * dxy.size(), s), dw(sizeof(z64) * wv.size(), s);
   LSH_HIP(hipMemcpyAsync(ddxy.p, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
   LSH_HIP(hipMemcpyAsync(dw.p, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_add_stencil, dim3(1), dim3(64), 0, s, C, M, ddxy.as<int>(), dw.as<z64>(), (int)wv.size());
