@@ -7,6 +7,7 @@
 #include <cstdlib>
 
 #include "blas.hpp"
+#include "wave.hpp"
 #include "prof.hpp"
 
 namespace lsh {
@@ -858,38 +859,31 @@ static int gj_nb2() {
   return v;
 }
 
-// Pivot search keys: a 64-bit integer whose maximum is the largest |a|^2
-// and, among equal values, the smallest row.  Non-negative IEEE values order
-// like their bit patterns.  FP32: value bits above the complemented row.
-// FP64: the value's top 51 bits above 8191 - row (rows < 4096; values equal in
-// those bits count as ties).  A NaN value counts as 0.  Every key of a
-// candidate row is nonzero; 0 = no candidate.
+// Pivot search keys: a 32-bit integer whose maximum is, up to the low bits
+// of the value, the largest |a|^2, and among values equal in the kept bits the
+// smallest row.  Non-negative IEEE values order like their bit patterns: the
+// key keeps the value's top 19 bits (FP32: exponent and 10 mantissa bits;
+// FP64, from its top word: exponent and 7 mantissa bits) above 8191 - row
+// (rows < 4096).  So a pivot is chosen among the values within 2^-10 (FP32)
+// or 2^-7 (FP64) of the largest, a threshold partial pivoting.  A NaN value
+// counts as 0.  Every key of a candidate row is nonzero; 0 = no candidate.
 template <typename R>
 struct PivKey;
 template <>
 struct PivKey<float> {
-  static __device__ __forceinline__ unsigned long long make(float a, int i) {
-    return ((unsigned long long)(a >= 0.f ? __float_as_uint(a) : 0u) << 32) | (unsigned)(~i);
+  static __device__ __forceinline__ unsigned make(float a, int i) {
+    return ((a >= 0.f ? __float_as_uint(a) : 0u) & ~0x1FFFu) | (unsigned)(0x1FFF - i);
   }
-  static __device__ __forceinline__ int row(unsigned long long k) { return (int)(~(unsigned)k); }
+  static __device__ __forceinline__ int row(unsigned k) { return 0x1FFF - (int)(k & 0x1FFF); }
 };
 template <>
 struct PivKey<double> {
-  static __device__ __forceinline__ unsigned long long make(double a, int i) {
-    const unsigned long long v = a >= 0.0 ? (unsigned long long)__double_as_longlong(a) : 0ull;
-    return (v & ~0x1FFFull) | (unsigned)(0x1FFF - i);
+  static __device__ __forceinline__ unsigned make(double a, int i) {
+    const unsigned v = a >= 0.0 ? (unsigned)((unsigned long long)__double_as_longlong(a) >> 32) : 0u;
+    return (v & ~0x1FFFu) | (unsigned)(0x1FFF - i);
   }
-  static __device__ __forceinline__ int row(unsigned long long k) { return 0x1FFF - (int)(k & 0x1FFF); }
+  static __device__ __forceinline__ int row(unsigned k) { return 0x1FFF - (int)(k & 0x1FFF); }
 };
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(k, off);
-    k = o > k ? o : k;
-  }
-  return k;
-}
 
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -923,7 +917,7 @@ __device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int 
   __shared__ cplx<R> stg[KR * GJ_NT];
   __shared__ int pvs[NB];
   __shared__ cplx<R> cand[2][GJ_NT / 64][NB];  // each wave's best candidate row (double-buffered)
-  __shared__ unsigned long long ckey[2][GJ_NT / 64];
+  __shared__ unsigned ckey[2][GJ_NT / 64];
   const int nt = blockDim.x, nw = nt >> 6;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = (c - j0) < NB ? (c - j0) : NB;
@@ -972,14 +966,14 @@ __device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int 
   for (int jj = 0; jj < NB; ++jj) {
     if (jj >= nb) break;
     const int j = j0 + jj, buf = jj & 1;
-    unsigned long long key = 0;
+    unsigned key = 0;
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
       if (avail[r]) {
-        const unsigned long long k = PivKey<R>::make(abs2(P[r][jj]), tid + r * nt);
+        const unsigned k = PivKey<R>::make(abs2(P[r][jj]), tid + r * nt);
         key = k > key ? k : key;
       }
-    key = wave_max_u64(key);
+    key = wave_max_u32_uniform(key);
     const int bi = key ? PivKey<R>::row(key) : -1;
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
@@ -988,13 +982,11 @@ __device__ __forceinline__ void gj_panel_body(cplx<R>* Ab, int c, long lda, int 
         for (int q = 0; q < NB; ++q) cand[buf][wave][q] = P[r][q];
     if (lane == 0) ckey[buf][wave] = key;
     lds_sync();
-    // block maximum: lane l reads wave (l mod 16)'s post, four exchange steps
-    unsigned long long kb = (lane & 15) < nw ? ckey[buf][lane & 15] : 0ull;
+    // block maximum: every lane reads the waves' posts (the same words)
+    unsigned kb = 0;
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(kb, off);
-      kb = o > kb ? o : kb;
-    }
+    for (int w = 0; w < GJ_NT / 64; ++w)
+      if (w < nw) kb = ckey[buf][w] > kb ? ckey[buf][w] : kb;
     // fewer than c pivots are in use, so some row is a candidate (kb != 0);
     // row p is held by thread p mod nt, so its post is that thread's wave's
     const int p = PivKey<R>::row(kb);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hbs.hpp"
+#include "wave.hpp"
 #include "ops.hpp"
 #include "prof.hpp"
 
@@ -684,31 +685,6 @@ __global__ void k_bp_sc_reduce(const z64* M, int m, const z64* part, const int* 
   S[e] = v;
 }
 
-// Greedy pivoted Cholesky of the candidate block S (first nc rows valid)
-// while the pivot exceeds thr2 and, after the first, is not below alpha * dout; at
-// most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
-// pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
-// pivot qualifies.
-// Wave-wide maximum of a 32-bit key, the same in every lane.
-template <int CTRL>
-__device__ __forceinline__ unsigned dpp_max_u32(unsigned k) {
-  const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, CTRL, 0xF, 0xF, false);
-  return o > k ? o : k;
-}
-__device__ __forceinline__ unsigned wave_max_u32_uniform(unsigned k) {
-  k = dpp_max_u32<0xB1>(k);   // quad_perm [1,0,3,2]
-  k = dpp_max_u32<0x4E>(k);   // quad_perm [2,3,0,1]
-  k = dpp_max_u32<0x141>(k);  // row_half_mirror
-  k = dpp_max_u32<0x140>(k);  // row_mirror
-  unsigned best = (unsigned)__builtin_amdgcn_readlane((int)k, 0);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) {
-    const unsigned v = (unsigned)__builtin_amdgcn_readlane((int)k, 16 * r);
-    best = v > best ? v : best;
-  }
-  return best;
-}
-
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   return __longlong_as_double(
@@ -716,6 +692,12 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
                   (unsigned)__builtin_amdgcn_readlane((int)bits, lane)));
 }
 
+// Greedy pivoted Cholesky of the candidate block S (first nc rows valid)
+// while the pivot exceeds thr2 and, after the first, is not below alpha * dout; at
+// most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
+// pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
+// pivot qualifies.
+//
 // Four waves: lane b of wave w holds rows 12w..12w+11 of column b of S in
 // registers, and every wave keeps all the Schur diagonals d_b (lane b).  Per
 // pivot p: the pivot's lanes write column t of the factor (rl * S[:, p],
