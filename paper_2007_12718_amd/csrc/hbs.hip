@@ -489,10 +489,26 @@ __global__ void k_scatter_U(z64* U, int k, const int* piv, const int* rest, int 
 // end returns at entry.
 constexpr int BP_B = 48, BP_NP = 32, BP_KC = 128, BP_KCS = 64, BP_SUB = 32, BP_SEL = 4096;
 // state words (int): 0 rank j, 1 done, 2 pivots of this step, 3 candidates,
-// 4..5 dout (double), 6 error flag, 8..8+BP_B candidate rows
+// 4..5 dout (double), 6 error flag, 8..8+BP_B candidate rows, 120..121 the
+// stopping threshold thr2 (double)
 constexpr int BPS_J = 0, BPS_DONE = 1, BPS_NP = 2, BPS_NC = 3, BPS_DOUT = 4, BPS_ERR = 6, BPS_CAND = 8,
-              BPS_WORDS = 128;
-static_assert(BPS_CAND + BP_B <= BPS_WORDS - 4, "candidate rows overflow the step state");
+              BPS_THR = 120, BPS_WORDS = 128;
+static_assert(BPS_CAND + BP_B <= BPS_THR && BPS_THR + 2 <= BPS_WORDS - 4, "step state layout");
+
+// thr2 = tol^2 sum_i d_i (the squared Frobenius norm of the candidate
+// matrix), in one workgroup with a fixed summation order
+__global__ __launch_bounds__(1024) void k_bp_thr2(const double* d, int m, double tol2, int* st) {
+  __shared__ double part[1024];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) v += d[i];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) reinterpret_cast<double*>(st + BPS_THR)[0] = tol2 * part[0];
+}
 
 __device__ __forceinline__ unsigned long long bp_key(double d, int i) {
   return d > 0.0 ? (((unsigned long long)__double_as_longlong(d) & ~0xFFFull) | (unsigned)(0xFFF - i)) : 0ull;
@@ -501,14 +517,14 @@ __device__ __forceinline__ unsigned long long bp_key(double d, int i) {
 // Candidates: the BP_B largest keys (unchosen rows, d > 0) by an 8-pass
 // most-significant-digit radix selection of the BP_B-th largest key, then
 // the <= BP_B keys at or above it, sorted descending.
-__global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* chosen, int m, double thr2,
-                                                    int* st) {
+__global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* chosen, int m, int* st) {
   __shared__ unsigned int hist[256];
   __shared__ unsigned long long s_prefix, s_mask;
   __shared__ int s_rank, s_cnt;
   __shared__ unsigned long long ck[64];
   __shared__ unsigned long long s_below;
   if (st[BPS_DONE]) return;
+  const double thr2 = reinterpret_cast<const double*>(st + BPS_THR)[0];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // the previous step's pivots join the rank here (every later kernel of
   // this step reads the rank after this kernel has ended)
@@ -709,8 +725,8 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // largest count as ties, won by the lower candidate.  L_PP^{-1} follows by
 // forward substitution inside each wave.
 constexpr int BP_CW = 4, BP_CR = BP_B / BP_CW;  // waves, rows per wave
-__global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, double thr2, double alpha, int* J,
-                                                        int* st, z64* Lpp, z64* Linv) {
+__global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, double alpha, int* J, int* st,
+                                                        z64* Lpp, z64* Linv) {
   static_assert(BP_B <= 64 && BP_NP == 32 && BP_B % BP_CW == 0 && BP_CW * 8 == BP_NP,
                 "one lane per candidate; 8 columns of L_PP^{-1} per wave");
   __shared__ z64 Lb[BP_B][BP_NP + 1];  // factor columns for every candidate row
@@ -721,6 +737,7 @@ __global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, do
   const int tid = threadIdx.x, b = tid & 63, w = tid >> 6, r0 = w * BP_CR;
   const int nc = st[BPS_NC], j = st[BPS_J];
   const double dout = alpha * reinterpret_cast<const double*>(st + BPS_DOUT)[0];
+  const double thr2 = reinterpret_cast<const double*>(st + BPS_THR)[0];
   const int* cand = st + BPS_CAND;
   z64 col[BP_CR];
 #pragma unroll
@@ -1075,12 +1092,8 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
   fill_zero(s, st, sizeof(int) * BPS_WORDS);
   hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, st + BPS_WORDS - 4);
   LSH_LAUNCH_CHECK();
-  std::vector<double> dh(m);
-  LSH_HIP(hipMemcpyAsync(dh.data(), d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-  LSH_HIP(hipStreamSynchronize(s));
-  double fro2 = 0;
-  for (double v : dh) fro2 += v;
-  const double thr2 = tol * tol * fro2;
+  hipLaunchKernelGGL(k_bp_thr2, dim3(1), dim3(1024), 0, s, d, m, tol * tol, st);
+  LSH_LAUNCH_CHECK();
   const int gm = ceil_div(m, 256);
   // steps in batches; the first batches are short (the first step alone
   // can take every pivot of a small block)
@@ -1089,7 +1102,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
     for (int b = 0; b < batch; ++b) {
       {
         ProfScope ps("bp_select", s, 16.0 * m);
-        hipLaunchKernelGGL(k_bp_select, dim3(1), dim3(1024), 0, s, d, chosen, m, thr2, st);
+        hipLaunchKernelGGL(k_bp_select, dim3(1), dim3(1024), 0, s, d, chosen, m, st);
       }
       LSH_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_bp_sc, dim3(nchS, 4), dim3(256), 0, s, Lt, m, st, partS);
@@ -1098,7 +1111,7 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
       LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
-        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(64 * BP_CW), 0, s, Sc, m, thr2, alpha, J, st, Lpp, Linv);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(64 * BP_CW), 0, s, Sc, m, alpha, J, st, Lpp, Linv);
       }
       LSH_LAUNCH_CHECK();
       {

@@ -47,6 +47,7 @@ struct Level {
   int m = 0, k = 0;    // candidate rows and rank (levels 1..L)
   std::vector<I2> cand;
   std::vector<int> J;
+  std::vector<I2> ra, rb;  // skeleton points of the two children (sibling-block rows / columns)
   DevBuf U64, U32;       // m x k
   DevBuf Ut64, Ut32;     // k x m (transpose, for row-streamed products)
   DevBuf Gab64, Gab32;   // sibling block of this parent level (c x c, c = k of level+1)
@@ -306,12 +307,16 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
     int ax, ay, bx, by, sx, sy;
     box_of(d.n, l + 1, 0, ax, ay, sx, sy);
     box_of(d.n, l + 1, 1, bx, by, sx, sy);
-    std::vector<I2> ra, rb;
+    Level& lv = P.lev[l];
+    // (kept in the level: the host source of the uploads below outlives them)
+    std::vector<I2>& ra = lv.ra;
+    std::vector<I2>& rb = lv.rb;
+    ra.clear();
+    rb.clear();
     for (int j : ch.J) {
       ra.push_back(I2{ch.cand[j].x + ax, ch.cand[j].y + ay});
       rb.push_back(I2{ch.cand[j].x + bx, ch.cand[j].y + by});
     }
-    Level& lv = P.lev[l];
     lv.c = ch.k;
     AsyncBuf da = upload_async(ra, s), db = upload_async(rb, s);
     const long cc = (long)lv.c * lv.c;
@@ -325,7 +330,7 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
       lv.Gabt32.alloc(sizeof(c32) * cc);
       ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
     }
-    LSH_HIP(hipStreamSynchronize(s));  // the staging buffers die here
+    // (the device staging buffers are freed in stream order)
   }
 }
 
