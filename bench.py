@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--batched", type=int, default=0,
                     help="instead of the headline run: time the factor of this many uneven instances "
                          "(sides 64..256, 5-20 wavelengths), batched (lsh_batch_factor) against one by one")
+    ap.add_argument("--multi-rhs", type=int, default=0,
+                    help="instead of the headline run: time the FP64 FGMRES solve of this many plane waves "
+                         "(512 x 512 grid, kappa = 80 pi) in lockstep (one lsh_solve call) against one call "
+                         "per right-hand side, with one FP32 HBS factor")
     return ap.parse_args()
 
 
@@ -209,9 +213,59 @@ def batched_run(a):
            "separate_s": res["separate"], "speedup": res["separate"] / res["batched"],
            "dtype": "c64 HBS", "data": "synthetic",
            "config": {"workload": f"batched-{a.batched}: sides {sizes}, kappa = 2 pi U[5,20], 10 bumps clipped at "
-                                  f"0.95, HBS 4th order tol 1e-4, FP32", "iterations": its,
+                                  f"0.95, 6th-order operator, FP32 HBS at tol 1e-4", "iterations": its,
                       "max_true_residual": worst}}
     print(json.dumps(out))
+    return 0
+
+
+def multi_rhs_run(a):
+    """Solve time of several right-hand sides with one factor: the lockstep
+    FGMRES (one preconditioner and one operator application per iteration
+    for the whole group) against one lsh_solve call per right-hand side."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2007_12718_amd import lsh
+    w = synth.differentiation(nwaves=a.multi_rhs)
+    b_d = torch.from_numpy(w.b).cuda()
+    u_d = torch.from_numpy(w.u_inc).cuda()
+    P, F = lsh.build(w.n, w.kappa, b_d, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width,
+                     prec="fp32")
+    nr = u_d.shape[0]
+    res, its = {}, {}
+    for mode in ("one_by_one", "lockstep"):
+        times = []
+        for k in range(a.warmup + a.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "lockstep":
+                s, _, info, rc = F.solve(u_d, tol=1e-10, maxit=100, want_u=False)
+                it = [info.iterations]
+            else:
+                it = []
+                for r in range(nr):
+                    s, _, info, rc = F.solve(u_d[r:r + 1], tol=1e-10, maxit=100, want_u=False)
+                    it.append(info.iterations)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            assert rc == 0 and info.true_residual < 1e-10, (mode, rc, info.true_residual)
+            if k >= a.warmup:
+                times.append(dt)
+        res[mode] = sorted(times)[len(times) // 2]
+        its[mode] = it
+        print(f"# {mode}: {times} iterations {it}", file=sys.stderr, flush=True)
+    out = {"metric": "FGMRES solve time to 1e-10, several right-hand sides, one FP32 HBS factor",
+           "value": res["lockstep"], "unit": "s", "higher_is_better": False, "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "one_by_one_s": res["one_by_one"],
+           "speedup": res["one_by_one"] / res["lockstep"], "dtype": "f64 FGMRES, c64 HBS", "data": "synthetic",
+           "config": {"workload": f"{w.name}: {nr} plane waves at equispaced angles, kappa = 80 pi, 30 smooth "
+                                  f"bumps, 10th-order operator, FP32 HBS at tol 1e-4",
+                      "iterations_one_by_one": its["one_by_one"],
+                      "iterations_last_lockstep": its["lockstep"]}}
+    print(json.dumps(out))
+    F.close()
+    P.close()
     return 0
 
 
@@ -228,6 +282,8 @@ def main():
     torch.cuda.set_device(0)
     if a.batched:
         return batched_run(a)
+    if a.multi_rhs:
+        return multi_rhs_run(a)
     if a.calib_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

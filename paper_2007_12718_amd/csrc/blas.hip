@@ -660,6 +660,114 @@ static void cgemv_launch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<
                      beta, z, sz, y, sy, rows);
 }
 
+// Several vectors per matrix: problem p = v * amod + b uses matrix b, so the
+// nv = batch / amod vectors of one matrix are read with one pass over it.
+// Rows g range over the matrices (g = b M + i); each of the NV vectors of a
+// group gets exactly the arithmetic of k_cgemv (the same lanes, loads in the
+// same order, the same sums), so a column comes out bitwise as from a
+// one-vector call.
+template <typename R, int L, int P, int NV>
+__global__ __launch_bounds__(256) void k_cgemv_mv(int M, int N, cplx<R> alpha, const cplx<R>* __restrict__ A,
+                                                  long lda, long sA, int amod, int nv,
+                                                  const cplx<R>* __restrict__ x, long sx, cplx<R> beta,
+                                                  const cplx<R>* z, long sz, cplx<R>* y, long sy, long rows) {
+  constexpr int RW = 64 / L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sub = lane & (L - 1);
+  const unsigned g0 = ((blockIdx.x * 4u + wave) * P) * RW + lane / L;
+  unsigned bp[P], ip[P];
+  {
+    unsigned b = g0 / (unsigned)M, i = g0 - b * (unsigned)M;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      bp[p] = b;
+      ip[p] = i;
+      i += RW;
+      while (i >= (unsigned)M) { i -= M; ++b; }
+    }
+  }
+  cplx<R> acc[P][NV];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[p][v] = mk<R>(0, 0);
+  if (N <= L) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const long g = (long)g0 + (long)p * RW;
+      cplx<R> av = mk<R>(0, 0);
+      if (g < rows && sub < N) av = A[(long)bp[p] * sA + (long)ip[p] * lda + sub];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        cplx<R> xv = mk<R>(0, 0);
+        if (v < nv && g < rows && sub < N) xv = x[((long)v * amod + bp[p]) * sx + sub];
+        fma_acc(acc[p][v], av, xv);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const long g = (long)g0 + (long)p * RW;
+      if (g >= rows) break;
+      const cplx<R>* row = A + (long)bp[p] * sA + (long)ip[p] * lda;
+      cplx<R> a4[NV][4];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a4[v][u] = mk<R>(0, 0);
+      for (int j = sub; j < N; j += 8 * L) {
+        cplx<R> w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int jj = j + u * L;
+          w[u] = jj < N ? row[jj] : mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (v >= nv) break;
+          const cplx<R>* xb = x + ((long)v * amod + bp[p]) * sx;
+          cplx<R> xw[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int jj = j + u * L;
+            xw[u] = jj < N ? xb[jj] : mk<R>(0, 0);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) fma_acc(a4[v][u & 3], w[u], xw[u]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[p][v] = (a4[v][0] + a4[v][1]) + (a4[v][2] + a4[v][3]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      cplx<R> t = acc[p][v];
+      t.x = group_sum<L>(t.x);
+      t.y = group_sum<L>(t.y);
+      const long g = (long)g0 + (long)p * RW;
+      if (v < nv && sub == 0 && g < rows) {
+        const long pb = (long)v * amod + bp[p], i = ip[p];
+        cplx<R> o = alpha * t;
+        if (z && (beta.x != R(0) || beta.y != R(0))) o = o + beta * z[pb * sz + i];
+        y[pb * sy + i] = o;
+      }
+    }
+}
+
+template <typename R, int L, int P, int NV>
+static void cgemv_mv_launch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<R>* A, long lda, long sA,
+                            int amod, int nv, const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz,
+                            cplx<R>* y, long sy) {
+  const long rows = (long)amod * M;
+  const long per_wg = 4L * P * (64 / L);
+  const long g = (rows + per_wg - 1) / per_wg;
+  LSH_REQUIRE(rows + per_wg < 2147483647L, -6, "cgemv: too many rows");
+  hipLaunchKernelGGL((k_cgemv_mv<R, L, P, NV>), dim3((unsigned)g), dim3(256), 0, s, M, N, alpha, A, lda, sA, amod,
+                     nv, x, sx, beta, z, sz, y, sy, rows);
+}
+
 template <typename R>
 void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
            const cplx<R>* A, long lda, long sA, int amod,
@@ -670,8 +778,24 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
   const int nmat = amod < batch ? amod : batch;
   ProfScope ps(sizeof(R) == 4 ? "cgemv_f32" : "cgemv_f64", s,
                (double)sizeof(cplx<R>) * ((double)nmat * M * N + (double)batch * (N + (z ? 2.0 : 1.0) * M)));
-  const long rows = (long)batch * M;
   const int am = amod > 0 ? amod : 1;
+  if (batch > am && batch % am == 0) {
+    // several vectors per matrix: groups of four read each matrix once
+    const int nvec = batch / am;
+    for (int v0 = 0; v0 < nvec; v0 += 4) {
+      const int nv = nvec - v0 < 4 ? nvec - v0 : 4;
+      const long o = (long)v0 * am;
+      const cplx<R>* zv = z ? z + o * sz : nullptr;
+      constexpr int P = sizeof(R) == 8 ? 1 : 2;  // FP64: keep the register file under 128
+      if (N <= 8) cgemv_mv_launch<R, 8, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
+      else if (N <= 16) cgemv_mv_launch<R, 16, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
+      else if (N <= 32) cgemv_mv_launch<R, 32, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
+      else cgemv_mv_launch<R, 64, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
+      LSH_LAUNCH_CHECK();
+    }
+    return;
+  }
+  const long rows = (long)batch * M;
   if (N <= 8) cgemv_launch<R, 8, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
   else if (N <= 16) cgemv_launch<R, 16, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
   else if (N <= 32) cgemv_launch<R, 32, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);

@@ -1289,54 +1289,88 @@ void leaf_scale_U(hipStream_t s, cplx<R>* Y, const cplx<R>* U, int mL, int k, co
 }
 
 // -------------------------------------------------------------- leaf apply
-// Up: r = X_tau f_tau ; rt = U_L^T r      (one workgroup per leaf and rhs)
+// One workgroup per leaf and group of up to NV right-hand sides: the leaf's
+// X_tau and U_L are read once for the group. Each right-hand side gets the
+// same arithmetic, in the same order, as in a one-vector launch.
 constexpr int LEAF_MAX = 144;
+constexpr int LEAF_NV = 4;
 
-template <typename R>
+// rows i of the mL x mL leaf matrix Xt times NV vectors in LDS (ins[v][*]);
+// one wave per row, the row sum by butterfly shuffles; fn(i, v, sum) on lane 0
+template <typename R, int NV, typename Fn>
+__device__ __forceinline__ void leaf_rows(const cplx<R>* __restrict__ Xt, int mL, const cplx<R> (*ins)[LEAF_MAX],
+                                          int nv, Fn fn) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < mL; i += 4) {
+    cplx<R> acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
+    for (int j = lane; j < mL; j += 64) {
+      const cplx<R> xv = Xt[(long)i * mL + j];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fma_acc(acc[v], xv, ins[v][j]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (v >= nv) break;
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[v].x += __shfl_xor(acc[v].x, off);
+        acc[v].y += __shfl_xor(acc[v].y, off);
+      }
+      if (lane == 0) fn(i, v, acc[v]);
+    }
+  }
+}
+
+// Up: r = X_tau f_tau ; rt = U_L^T r
+template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ UL,
                                                  int mL, int k, const z64* __restrict__ f, cplx<R>* r, cplx<R>* rt,
                                                  const I2* __restrict__ org, const I2* __restrict__ pts, int n,
-                                                 int nleaf, const double* __restrict__ b, double sb) {
-  __shared__ cplx<R> fs[LEAF_MAX];
-  __shared__ cplx<R> rs[LEAF_MAX];
-  const long t = blockIdx.x, rhs = blockIdx.y;
+                                                 int nleaf, int nrhs, const double* __restrict__ b, double sb) {
+  __shared__ cplx<R> fs[NV][LEAF_MAX];
+  __shared__ cplx<R> rs[NV][LEAF_MAX];
+  const long t = blockIdx.x, r0 = (long)blockIdx.y * NV;
+  const int nv = nrhs - r0 < NV ? (int)(nrhs - r0) : NV;
   const I2 o = org[t];
-  const z64* fr = f + rhs * (long)n * n;
   for (int i = threadIdx.x; i < mL; i += blockDim.x) {
     const I2 pi = pts[i];
-    const z64 v = fr[(long)(o.y + pi.y) * n + (o.x + pi.x)];
-    fs[i] = mk<R>((R)v.x, (R)v.y);
+    const long at = (long)(o.y + pi.y) * n + (o.x + pi.x);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      z64 val = mk(0.0, 0.0);
+      if (v < nv) val = f[(r0 + v) * (long)n * n + at];
+      fs[v][i] = mk<R>((R)val.x, (R)val.y);
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const cplx<R>* Xt = X + t * (long)mL * mL;
-  for (int i = wave; i < mL; i += 4) {
-    cplx<R> acc = mk<R>(0, 0);
-    for (int j = lane; j < mL; j += 64) fma_acc(acc, Xt[(long)i * mL + j], fs[j]);
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off);
-      acc.y += __shfl_xor(acc.y, off);
-    }
-    if (lane == 0) rs[i] = acc;
-  }
+  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, fs, nv, [&](int i, int v, cplx<R> acc) { rs[v][i] = acc; });
   __syncthreads();
-  if (r) {
-    cplx<R>* rr = r + (rhs * nleaf + t) * (long)mL;
-    for (int i = threadIdx.x; i < mL; i += blockDim.x) rr[i] = rs[i];
-  }
-  if (b) {  // transpose pass: rs <- sb * b .* rs before U_L^T
-    __syncthreads();
-    for (int i = threadIdx.x; i < mL; i += blockDim.x) {
-      const I2 pi = pts[i];
-      rs[i] = (R)(sb * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]) * rs[i];
+  for (int v = 0; v < nv; ++v) {
+    if (r) {
+      cplx<R>* rr = r + ((r0 + v) * nleaf + t) * (long)mL;
+      for (int i = threadIdx.x; i < mL; i += blockDim.x) rr[i] = rs[v][i];
     }
-    __syncthreads();
+    if (b) {  // transpose pass: rs <- sb * b .* rs before U_L^T
+      for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+        const I2 pi = pts[i];
+        rs[v][i] = (R)(sb * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]) * rs[v][i];
+      }
+    }
   }
-  cplx<R>* rtt = rt + (rhs * nleaf + t) * (long)k;
+  if (b) __syncthreads();
   for (int a = threadIdx.x; a < k; a += blockDim.x) {
-    cplx<R> acc = mk<R>(0, 0);
-    for (int i = 0; i < mL; ++i) fma_acc(acc, UL[(long)i * k + a], rs[i]);
-    rtt[a] = acc;
+    cplx<R> acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
+    for (int i = 0; i < mL; ++i) {
+      const cplx<R> u = UL[(long)i * k + a];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, rs[v][i]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (v < nv) rt[((r0 + v) * nleaf + t) * (long)k + a] = acc[v];
   }
 }
 
@@ -1345,53 +1379,55 @@ void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, 
              cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs, const double* b,
              double sb) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
-  ProfScope ps("leaf_up", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (2.0 * mL + k)) +
+  const int ng = nrhs == 1 ? 1 : ceil_div(nrhs, LEAF_NV);
+  ProfScope ps("leaf_up", s, (double)sizeof(cplx<R>) * nleaf * ((double)ng * mL * mL + (double)nrhs * (2.0 * mL + k)) +
                                  16.0 * nrhs * (double)nleaf * mL);
-  hipLaunchKernelGGL(k_leaf_up<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, f, r, rt, leaf_origin,
-                     leaf_pts, n, nleaf, b, sb);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_leaf_up<R, 1>), dim3(nleaf, 1), dim3(256), 0, s, X, UL, mL, k, f, r, rt, leaf_origin,
+                       leaf_pts, n, nleaf, nrhs, b, sb);
+  else
+    hipLaunchKernelGGL((k_leaf_up<R, LEAF_NV>), dim3(nleaf, ng), dim3(256), 0, s, X, UL, mL, k, f, r, rt,
+                       leaf_origin, leaf_pts, n, nleaf, nrhs, b, sb);
   LSH_LAUNCH_CHECK();
 }
 
 // Down: q_tau = r_tau - X_tau B_tau U_L wt_tau, written to the grid (FP64)
-template <typename R>
+template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_leaf_down(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ UL,
                                                    int mL, int k, const cplx<R>* __restrict__ wt,
                                                    const cplx<R>* __restrict__ r, z64* q,
                                                    const double* __restrict__ b, double kappa2,
                                                    const I2* __restrict__ org, const I2* __restrict__ pts, int n,
-                                                   int nleaf) {
-  __shared__ cplx<R> us[LEAF_MAX];
-  __shared__ cplx<R> ws[LEAF_MAX];
-  const long t = blockIdx.x, rhs = blockIdx.y;
+                                                   int nleaf, int nrhs) {
+  __shared__ cplx<R> us[NV][LEAF_MAX];
+  __shared__ cplx<R> ws[NV][LEAF_MAX];
+  const long t = blockIdx.x, r0 = (long)blockIdx.y * NV;
+  const int nv = nrhs - r0 < NV ? (int)(nrhs - r0) : NV;
   const I2 o = org[t];
-  const cplx<R>* wtt = wt + (rhs * nleaf + t) * (long)k;
-  for (int a = threadIdx.x; a < k; a += blockDim.x) ws[a] = wtt[a];
+  for (int a = threadIdx.x; a < k; a += blockDim.x)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ws[v][a] = v < nv ? wt[((r0 + v) * nleaf + t) * (long)k + a] : mk<R>(0, 0);
   __syncthreads();
   for (int i = threadIdx.x; i < mL; i += blockDim.x) {
-    cplx<R> acc = mk<R>(0, 0);
-    for (int a = 0; a < k; ++a) fma_acc(acc, UL[(long)i * k + a], ws[a]);
+    cplx<R> acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
+    for (int a = 0; a < k; ++a) {
+      const cplx<R> u = UL[(long)i * k + a];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, ws[v][a]);
+    }
     const I2 pi = pts[i];
     const R bi = (R)(kappa2 * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]);
-    us[i] = bi * acc;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) us[v][i] = bi * acc[v];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const cplx<R>* Xt = X + t * (long)mL * mL;
-  const cplx<R>* rr = r + (rhs * nleaf + t) * (long)mL;
-  z64* qr = q + rhs * (long)n * n;
-  for (int i = wave; i < mL; i += 4) {
-    cplx<R> acc = mk<R>(0, 0);
-    for (int j = lane; j < mL; j += 64) fma_acc(acc, Xt[(long)i * mL + j], us[j]);
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off);
-      acc.y += __shfl_xor(acc.y, off);
-    }
-    if (lane == 0) {
-      const cplx<R> v = rr[i] - acc;
-      const I2 pi = pts[i];
-      qr[(long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)v.x, (double)v.y);
-    }
-  }
+  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) {
+    const cplx<R> val = r[((r0 + v) * nleaf + t) * (long)mL + i] - acc;
+    const I2 pi = pts[i];
+    q[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)val.x, (double)val.y);
+  });
 }
 
 template <typename R>
@@ -1399,60 +1435,71 @@ void leaf_down(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k
                const cplx<R>* r, z64* q, const double* b, double kappa2, const I2* leaf_origin, const I2* leaf_pts,
                int nleaf, int n, int nrhs) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
-  ProfScope ps("leaf_down", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (mL + k)) +
+  const int ng = nrhs == 1 ? 1 : ceil_div(nrhs, LEAF_NV);
+  ProfScope ps("leaf_down", s, (double)sizeof(cplx<R>) * nleaf * ((double)ng * mL * mL + (double)nrhs * (mL + k)) +
                                    (16.0 + 8.0) * nrhs * (double)nleaf * mL);
-  hipLaunchKernelGGL(k_leaf_down<R>, dim3(nleaf, nrhs), dim3(256), 0, s, X, UL, mL, k, wt, r, q, b, kappa2,
-                     leaf_origin, leaf_pts, n, nleaf);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_leaf_down<R, 1>), dim3(nleaf, 1), dim3(256), 0, s, X, UL, mL, k, wt, r, q, b, kappa2,
+                       leaf_origin, leaf_pts, n, nleaf, nrhs);
+  else
+    hipLaunchKernelGGL((k_leaf_down<R, LEAF_NV>), dim3(nleaf, ng), dim3(256), 0, s, X, UL, mL, k, wt, r, q, b,
+                       kappa2, leaf_origin, leaf_pts, n, nleaf, nrhs);
   LSH_LAUNCH_CHECK();
 }
 
 // Transpose pass, leaves: q_tau = X_tau^T (g_tau + U_L rb_tau) (X given transposed)
-template <typename R>
+template <typename R, int NV>
 __global__ __launch_bounds__(256) void k_leaf_tdown(const cplx<R>* __restrict__ XT, const cplx<R>* __restrict__ UL,
                                                     int mL, int k, const cplx<R>* __restrict__ w,
                                                     const z64* __restrict__ g, z64* q, const I2* __restrict__ org,
-                                                    const I2* __restrict__ pts, int n, int nleaf) {
-  __shared__ cplx<R> us[LEAF_MAX];
-  __shared__ cplx<R> ws[LEAF_MAX];
-  const long t = blockIdx.x, rhs = blockIdx.y;
+                                                    const I2* __restrict__ pts, int n, int nleaf, int nrhs) {
+  __shared__ cplx<R> us[NV][LEAF_MAX];
+  __shared__ cplx<R> ws[NV][LEAF_MAX];
+  const long t = blockIdx.x, r0 = (long)blockIdx.y * NV;
+  const int nv = nrhs - r0 < NV ? (int)(nrhs - r0) : NV;
   const I2 o = org[t];
-  const cplx<R>* wt = w + (rhs * nleaf + t) * (long)k;
-  for (int a = threadIdx.x; a < k; a += blockDim.x) ws[a] = wt[a];
+  for (int a = threadIdx.x; a < k; a += blockDim.x)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ws[v][a] = v < nv ? w[((r0 + v) * nleaf + t) * (long)k + a] : mk<R>(0, 0);
   __syncthreads();
-  const z64* gr = g + rhs * (long)n * n;
   for (int i = threadIdx.x; i < mL; i += blockDim.x) {
-    cplx<R> acc = mk<R>(0, 0);
-    for (int a = 0; a < k; ++a) fma_acc(acc, UL[(long)i * k + a], ws[a]);
+    cplx<R> acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
+    for (int a = 0; a < k; ++a) {
+      const cplx<R> u = UL[(long)i * k + a];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, ws[v][a]);
+    }
     const I2 pi = pts[i];
-    const z64 gv = gr[(long)(o.y + pi.y) * n + (o.x + pi.x)];
-    us[i] = acc + mk<R>((R)gv.x, (R)gv.y);
+    const long at = (long)(o.y + pi.y) * n + (o.x + pi.x);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      z64 gv = mk(0.0, 0.0);
+      if (v < nv) gv = g[(r0 + v) * (long)n * n + at];
+      us[v][i] = acc[v] + mk<R>((R)gv.x, (R)gv.y);
+    }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const cplx<R>* Xt = XT + t * (long)mL * mL;
-  z64* qr = q + rhs * (long)n * n;
-  for (int i = wave; i < mL; i += 4) {
-    cplx<R> acc = mk<R>(0, 0);
-    for (int j = lane; j < mL; j += 64) fma_acc(acc, Xt[(long)i * mL + j], us[j]);
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off);
-      acc.y += __shfl_xor(acc.y, off);
-    }
-    if (lane == 0) {
-      const I2 pi = pts[i];
-      qr[(long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)acc.x, (double)acc.y);
-    }
-  }
+  leaf_rows<R, NV>(XT + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) {
+    const I2 pi = pts[i];
+    q[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)acc.x, (double)acc.y);
+  });
 }
 
 template <typename R>
 void leaf_tdown(hipStream_t s, const cplx<R>* XT, const cplx<R>* UL, int mL, int k, const cplx<R>* w, const z64* g,
                 z64* q, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
-  ProfScope ps("leaf_tdown", s, (double)sizeof(cplx<R>) * nleaf * ((double)mL * mL + (double)nrhs * (mL + k)) +
+  const int ng = nrhs == 1 ? 1 : ceil_div(nrhs, LEAF_NV);
+  ProfScope ps("leaf_tdown", s, (double)sizeof(cplx<R>) * nleaf * ((double)ng * mL * mL + (double)nrhs * (mL + k)) +
                                     32.0 * nrhs * (double)nleaf * mL);
-  hipLaunchKernelGGL(k_leaf_tdown<R>, dim3(nleaf, nrhs), dim3(256), 0, s, XT, UL, mL, k, w, g, q, leaf_origin,
-                     leaf_pts, n, nleaf);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_leaf_tdown<R, 1>), dim3(nleaf, 1), dim3(256), 0, s, XT, UL, mL, k, w, g, q, leaf_origin,
+                       leaf_pts, n, nleaf, nrhs);
+  else
+    hipLaunchKernelGGL((k_leaf_tdown<R, LEAF_NV>), dim3(nleaf, ng), dim3(256), 0, s, XT, UL, mL, k, w, g, q,
+                       leaf_origin, leaf_pts, n, nleaf, nrhs);
   LSH_LAUNCH_CHECK();
 }
 

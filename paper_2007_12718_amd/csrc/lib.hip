@@ -723,7 +723,7 @@ struct lsh_factor_s {
   FactorData<float> f32;
   FactorData<double> f64;
   // FGMRES workspace
-  int gm_maxit = 0;
+  int gm_maxit = 0, gm_nr = 0;
   DevBuf V, Z, w, h1, h2, part, fvec, res;
   void apply(const z64* x, z64* y, int nrhs, hipStream_t s, bool transpose = false) {
     if (plan->d.hbs_prec == LSH_FP32) {
@@ -757,14 +757,16 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
   const long N = (long)P.n * P.n;
   const int maxit = o.maxit;
   if (F.gm_maxit < maxit) {
-    F.V.alloc(sizeof(z64) * (size_t)(maxit + 1) * N);
-    F.Z.alloc(sizeof(z64) * (size_t)maxit * N);
+    const int mr = std::max(1, F.gm_nr);
+    F.V.alloc(sizeof(z64) * (size_t)(maxit + 1) * mr * N);
+    F.Z.alloc(sizeof(z64) * (size_t)maxit * mr * N);
     F.w.alloc(sizeof(z64) * N);
-    F.h1.alloc(sizeof(z64) * (maxit + 2));
-    F.h2.alloc(sizeof(z64) * (maxit + 2));
+    F.h1.alloc(sizeof(z64) * (size_t)mr * (maxit + 2));
+    F.h2.alloc(sizeof(z64) * (size_t)mr * (maxit + 2));
     F.part.alloc(multidot_partial_bytes(maxit + 2));
-    F.res.alloc(sizeof(z64) * N);
+    F.res.alloc(sizeof(z64) * (size_t)mr * N);
     F.gm_maxit = maxit;
+    F.gm_nr = mr;
   }
   z64* V = F.V.as<z64>();
   z64* Z = F.Z.as<z64>();
@@ -850,6 +852,166 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
   true_res = std::sqrt(rn.x) / beta;
   if (info) { info->iterations = its; info->residual = est; }
   conv = true_res < o.tol ? 1 : 0;
+}
+
+// right-hand sides solved together by the lockstep solver (memory: the
+// Krylov basis holds (maxit + 1) * SOLVE_GROUP grid vectors)
+constexpr int SOLVE_GROUP = 8;
+
+// Flexible GMRES for nr right-hand sides in lockstep: every iteration applies
+// the preconditioner and the operator once to all nr current basis vectors
+// (so each box matrix and each FFT plan pass serves the whole group), while
+// the Krylov bases, Hessenberg matrices, rotations and stopping tests stay
+// per right-hand side, as in nr separate runs. Layout: V[j][r][N],
+// Z[j][r][N]; f, x: [nr][N]. A right-hand side that has stopped gets a zero
+// basis vector, which the (linear, per-vector) applies keep at zero.
+// info: iterations, estimate and history of the last right-hand side.
+void fgmres_multi(lsh_factor_s& F, const z64* f, z64* x, int nr, const lsh_solve_opts& o, lsh_info* info,
+                  double& worst, int& allconv, hipStream_t s, bool transposed = false) {
+  lsh_plan_s& P = *F.plan;
+  const long N = (long)P.n * P.n, S = (long)nr * N;
+  const int maxit = o.maxit, hs = maxit + 2;
+  if (F.gm_maxit < maxit || F.gm_nr < nr) {
+    const int mi = std::max(maxit, F.gm_maxit), mr = std::max(nr, F.gm_nr);
+    F.V.alloc(sizeof(z64) * (size_t)(mi + 1) * mr * N);
+    F.Z.alloc(sizeof(z64) * (size_t)mi * mr * N);
+    F.w.alloc(sizeof(z64) * N);
+    F.h1.alloc(sizeof(z64) * (size_t)mr * (mi + 2));
+    F.h2.alloc(sizeof(z64) * (size_t)mr * (mi + 2));
+    F.part.alloc(multidot_partial_bytes(mi + 2));
+    F.res.alloc(sizeof(z64) * (size_t)mr * N);
+    F.gm_maxit = mi;
+    F.gm_nr = mr;
+  }
+  z64* V = F.V.as<z64>();
+  z64* Z = F.Z.as<z64>();
+  z64* h1 = F.h1.as<z64>();
+  z64* h2 = F.h2.as<z64>();
+  z64* part = F.part.as<z64>();
+  for (int r = 0; r < nr; ++r) multidot(s, f + r * N, 0, 1, f + r * N, N, h1 + r * hs, part);
+  std::vector<z64> hv((size_t)nr * hs), hv2((size_t)nr * hs);
+  LSH_HIP(hipMemcpyAsync(hv.data(), h1, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  using cd = std::complex<double>;
+  struct Run {
+    double beta = 0, est = 1.0;
+    int its = 0;
+    bool active = false;
+    std::vector<cd> H, cs, sn, g;
+    std::vector<double> hist;
+  };
+  std::vector<Run> run(nr);
+  int nact = 0;
+  for (int r = 0; r < nr; ++r) {
+    Run& R = run[r];
+    R.beta = std::sqrt(hv[(size_t)r * hs].x);
+    R.hist.assign(1, 1.0);
+    if (R.beta == 0) {
+      fill_zero(s, V + r * N, sizeof(z64) * N);
+      continue;
+    }
+    scale_by_invnorm(s, V + r * N, f + r * N, h1 + r * hs, N);
+    R.H.assign((size_t)(maxit + 1) * maxit, 0.0);
+    R.cs.assign(maxit, 0.0);
+    R.sn.assign(maxit, 0.0);
+    R.g.assign(maxit + 1, 0.0);
+    R.g[0] = R.beta;
+    R.active = true;
+    ++nact;
+  }
+  for (int j = 0; j < maxit && nact > 0; ++j) {
+    z64* vj = V + (long)j * S;
+    z64* zj = Z + (long)j * S;
+    z64* wj = V + (long)(j + 1) * S;
+    if (o.precondition) F.apply(vj, zj, nr, s, transposed);
+    else LSH_HIP(hipMemcpyAsync(zj, vj, sizeof(z64) * S, hipMemcpyDeviceToDevice, s));
+    P.op.apply(s, F.b.as<double>(), zj, wj, nr, transposed);
+    for (int r = 0; r < nr; ++r) {
+      if (!run[r].active) continue;
+      z64* w = wj + r * N;
+      z64 *a1 = h1 + r * hs, *a2 = h2 + r * hs;
+      multidot(s, V + r * N, S, j + 1, w, N, a1, part);
+      multiaxpy(s, w, V + r * N, S, j + 1, a1, N);
+      multidot(s, V + r * N, S, j + 1, w, N, a2, part);
+      multiaxpy(s, w, V + r * N, S, j + 1, a2, N);
+      multidot(s, w, 0, 1, w, N, a2 + (j + 1), part);
+    }
+    LSH_HIP(hipMemcpyAsync(hv.data(), h1, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipMemcpyAsync(hv2.data(), h2, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nr; ++r) {
+      Run& R = run[r];
+      if (!R.active) continue;
+      const z64* e1 = hv.data() + (size_t)r * hs;
+      const z64* e2 = hv2.data() + (size_t)r * hs;
+      z64* w = wj + r * N;
+      const double hn = std::sqrt(e2[j + 1].x);
+      if (hn > 0) scale_by_invnorm(s, w, w, h2 + r * hs + (j + 1), N);
+      auto Hc = [&](int i, int c) -> cd& { return R.H[(size_t)i * maxit + c]; };
+      for (int i = 0; i <= j; ++i) Hc(i, j) = {e1[i].x + e2[i].x, e1[i].y + e2[i].y};
+      Hc(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {
+        cd a = Hc(i, j), c2 = Hc(i + 1, j);
+        Hc(i, j) = std::conj(R.cs[i]) * a + std::conj(R.sn[i]) * c2;
+        Hc(i + 1, j) = -R.sn[i] * a + R.cs[i] * c2;
+      }
+      cd a = Hc(j, j), c2 = Hc(j + 1, j);
+      const double rho = std::hypot(std::abs(a), std::abs(c2));
+      R.cs[j] = rho > 0 ? a / rho : 1.0;
+      R.sn[j] = rho > 0 ? c2 / rho : 0.0;
+      Hc(j, j) = rho;
+      Hc(j + 1, j) = 0.0;
+      R.g[j + 1] = -R.sn[j] * R.g[j];
+      R.g[j] = std::conj(R.cs[j]) * R.g[j];
+      R.est = std::abs(R.g[j + 1]) / R.beta;
+      R.its = j + 1;
+      R.hist.push_back(R.est);
+      if (R.est < o.tol || hn == 0) {
+        R.active = false;
+        --nact;
+        fill_zero(s, w, sizeof(z64) * N);  // keeps this vector's later applies at zero
+      }
+    }
+  }
+  // per right-hand side: y = H^{-1} g (upper triangular), x = Z y
+  std::vector<z64> yz((size_t)nr * hs, mk(0.0, 0.0));
+  for (int r = 0; r < nr; ++r) {
+    Run& R = run[r];
+    const int k = R.its;
+    std::vector<cd> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      cd t = R.g[i];
+      for (int c2 = i + 1; c2 < k; ++c2) t -= R.H[(size_t)i * maxit + c2] * y[c2];
+      y[i] = t / R.H[(size_t)i * maxit + i];
+    }
+    for (int i = 0; i < k; ++i) yz[(size_t)r * hs + i] = mk(y[i].real(), y[i].imag());
+  }
+  LSH_HIP(hipMemcpyAsync(h1, yz.data(), sizeof(z64) * nr * hs, hipMemcpyHostToDevice, s));
+  for (int r = 0; r < nr; ++r) {
+    if (run[r].its > 0) lincomb(s, x + r * N, Z + r * N, S, run[r].its, h1 + r * hs, N);
+    else fill_zero(s, x + r * N, sizeof(z64) * N);
+  }
+  // true residuals, one operator pass for the group
+  z64* res = F.res.as<z64>();
+  P.op.apply(s, F.b.as<double>(), x, res, nr, transposed);
+  for (int r = 0; r < nr; ++r) {
+    sub_from(s, res + r * N, f + r * N, N);
+    multidot(s, res + r * N, 0, 1, res + r * N, N, h2 + r * hs, part);
+  }
+  LSH_HIP(hipMemcpyAsync(hv2.data(), h2, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r < nr; ++r) {
+    const Run& R = run[r];
+    const double tr = R.beta > 0 ? std::sqrt(hv2[(size_t)r * hs].x) / R.beta : 0.0;
+    if (!(tr < o.tol) && R.beta > 0) allconv = 0;
+    if (tr > worst) worst = tr;
+  }
+  if (info) {
+    const Run& R = run[nr - 1];
+    info->iterations = R.its;
+    info->residual = R.beta > 0 ? R.est : 0.0;
+    for (size_t i = 0; i < R.hist.size() && i <= LSH_MAX_ITERS; ++i) info->history[i] = R.hist[i];
+  }
 }
 
 // receivers: u(x_r) = h^2 sum_j (i/4) H0(kappa |x_r - x_j|) sigma_j
@@ -1534,21 +1696,29 @@ int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u,
   hipStream_t s = (hipStream_t)stream;
   lsh_plan_s& P = *F->plan;
   const long N = (long)P.n * P.n;
-  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * N) F->fvec.alloc(sizeof(z64) * N);
+  const int G = std::min(nrhs, SOLVE_GROUP);
+  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * G * N) F->fvec.alloc(sizeof(z64) * G * N);
   z64* f = F->fvec.as<z64>();
   int allconv = 1;
   double worst = 0;
   if (info) std::memset(info, 0, sizeof(lsh_info));
-  for (int r = 0; r < nrhs; ++r) {
-    const z64* ui = static_cast<const z64*>(u_inc) + r * N;
-    z64* sg = static_cast<z64*>(sigma) + r * N;
-    hipLaunchKernelGGL(k_rhs, dim3(2048), dim3(256), 0, s, f, ui, F->b.as<double>(), P.kappa * P.kappa, N);
+  if (nrhs == 1) {
+    hipLaunchKernelGGL(k_rhs, dim3(2048), dim3(256), 0, s, f, static_cast<const z64*>(u_inc), F->b.as<double>(),
+                       P.kappa * P.kappa, N);
     LSH_LAUNCH_CHECK();
-    double tr = 0;
     int conv = 0;
-    fgmres_one(*F, f, sg, o, info, tr, conv, s);
-    if (!conv) allconv = 0;
-    if (tr > worst) worst = tr;
+    fgmres_one(*F, f, static_cast<z64*>(sigma), o, info, worst, conv, s);
+    allconv = conv;
+  } else {
+    for (int r0 = 0; r0 < nrhs; r0 += G) {
+      const int nr = std::min(G, nrhs - r0);
+      for (int r = 0; r < nr; ++r) {
+        hipLaunchKernelGGL(k_rhs, dim3(2048), dim3(256), 0, s, f + r * N,
+                           static_cast<const z64*>(u_inc) + (r0 + r) * N, F->b.as<double>(), P.kappa * P.kappa, N);
+        LSH_LAUNCH_CHECK();
+      }
+      fgmres_multi(*F, f, static_cast<z64*>(sigma) + r0 * N, nr, o, info, worst, allconv, s);
+    }
   }
   if (info) info->true_residual = worst;
   if (u) P.op.apply(s, nullptr, static_cast<const z64*>(sigma), static_cast<z64*>(u), nrhs);
@@ -1566,21 +1736,28 @@ int lsh_solve_adjoint(lsh_factor_t F, const void* g, int nrhs, void* lambda, con
   hipStream_t s = (hipStream_t)stream;
   lsh_plan_s& P = *F->plan;
   const long N = (long)P.n * P.n;
-  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * N) F->fvec.alloc(sizeof(z64) * N);
+  const int G = std::min(nrhs, SOLVE_GROUP);
+  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * G * N) F->fvec.alloc(sizeof(z64) * G * N);
   z64* f = F->fvec.as<z64>();
   int allconv = 1;
   double worst = 0;
   if (info) std::memset(info, 0, sizeof(lsh_info));
   // A^H lambda = g  <=>  A^T conj(lambda) = conj(g),  A^T = I + K B (K symmetric)
-  for (int r = 0; r < nrhs; ++r) {
-    z64* lr = static_cast<z64*>(lambda) + r * N;
-    conj_copy(s, f, static_cast<const z64*>(g) + r * N, N);
-    double tr = 0;
+  z64* lam = static_cast<z64*>(lambda);
+  const z64* gg = static_cast<const z64*>(g);
+  if (nrhs == 1) {
+    conj_copy(s, f, gg, N);
     int conv = 0;
-    fgmres_one(*F, f, lr, o, info, tr, conv, s, true);
-    conj_copy(s, lr, lr, N);
-    if (!conv) allconv = 0;
-    if (tr > worst) worst = tr;
+    fgmres_one(*F, f, lam, o, info, worst, conv, s, true);
+    conj_copy(s, lam, lam, N);
+    allconv = conv;
+  } else {
+    for (int r0 = 0; r0 < nrhs; r0 += G) {
+      const int nr = std::min(G, nrhs - r0);
+      conj_copy(s, f, gg + r0 * N, (long)nr * N);
+      fgmres_multi(*F, f, lam + r0 * N, nr, o, info, worst, allconv, s, true);
+      conj_copy(s, lam + r0 * N, lam + r0 * N, (long)nr * N);
+    }
   }
   if (info) info->true_residual = worst;
   return allconv ? LSH_OK : LSH_NOT_CONVERGED;
