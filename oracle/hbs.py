@@ -19,6 +19,12 @@ TEST INFRASTRUCTURE.  Plain numpy/scipy transcription of the paper's method:
   with |R_kk| <= eps ||A||_F.  tol = 0 selects the exact full-rank form
   (U = I, J = all candidates), in which the HBS matrix equals G.
 * Build: Algorithm 1 (eqs. (localsol_leaf), (smat_leaf), (localsol), (smat)).
+  Optionally (the remark after Algorithm 2's description, eq. (blockinv))
+  the merge inverse X_tau by the Woodbury formula on a low-rank sibling
+  block G_ab ~= L R^T (a row ID of G_ab at its own tolerance).  As printed,
+  eq. (blockinv) leaves out the scattering matrices: with
+  P = diag(S_a L_ab, S_b L_ba) and Q = [[0, R_ab^T], [R_ba^T, 0]] the
+  merge matrix is I + P Q, so X_tau = I - P (I + Q P)^{-1} Q.
 * Apply: Algorithm 2, loops read as: up l = L-1..1, top solve at the root,
   down l = 1..L-1, then the leaves.  Also its exact transpose and the HBS
   forward matvec of G^eps.
@@ -174,11 +180,30 @@ class Compression:
         return y
 
 
-class Inverse:
-    """Algorithm 1 (build) and Algorithm 2 (apply) for (I + B G^eps)^{-1}."""
+def woodbury_merge(Sa, Sb, L, Rt):
+    """X_tau = [[I, S_a G_ab], [S_b G_ab^T, I]]^{-1} for G_ab = L Rt (eq.
+    (blockinv) with the S factors): G_ba = G_ab^T = Rt^T L^T, so L_ab = L,
+    R_ab^T = Rt, L_ba = Rt^T, R_ba^T = L^T."""
+    ca, cb, r = Sa.shape[0], Sb.shape[0], L.shape[1]
+    P = sla.block_diag(Sa @ L, Sb @ Rt.T)
+    Q = np.block([[np.zeros((r, ca)), Rt], [L.T, np.zeros((r, cb))]])
+    return np.eye(ca + cb) - P @ np.linalg.solve(np.eye(2 * r) + Q @ P, Q)
 
-    def __init__(self, comp: Compression, b):
+
+class Inverse:
+    """Algorithm 1 (build) and Algorithm 2 (apply) for (I + B G^eps)^{-1}.
+
+    lowrank_tol: None forms X_tau by inverting the merge matrix; a number
+    uses woodbury_merge with G_ab ~= L Rt, the row ID of G_ab at that
+    tolerance (L = U, Rt = G_ab[J, :])."""
+
+    def __init__(self, comp: Compression, b, lowrank_tol=None):
         self.comp = comp
+        self.lowrank = {}
+        if lowrank_tol is not None:
+            for lev, G in comp.Gab.items():
+                J, Ug = row_id(G, lowrank_tol)
+                self.lowrank[lev] = (Ug, G[J, :])
         T, L = comp.tree, comp.tree.L
         self.B = comp.kappa ** 2 * np.asarray(b, dtype=float).reshape(-1)
         self.X, self.S = {}, {}
@@ -192,8 +217,11 @@ class Inverse:
             for t in range(2 ** lev):
                 Sa, Sb = self.S[(lev + 1, 2 * t)], self.S[(lev + 1, 2 * t + 1)]
                 ca, cb = Sa.shape[0], Sb.shape[0]
-                M = np.block([[np.eye(ca), Sa @ Gab], [Sb @ Gab.T, np.eye(cb)]])
-                X = np.linalg.inv(M)
+                if lowrank_tol is None:
+                    M = np.block([[np.eye(ca), Sa @ Gab], [Sb @ Gab.T, np.eye(cb)]])
+                    X = np.linalg.inv(M)
+                else:
+                    X = woodbury_merge(Sa, Sb, *self.lowrank[lev])
                 self.X[(lev, t)] = X
                 if lev > 0:
                     D = sla.block_diag(Sa, Sb)

@@ -161,3 +161,38 @@ def test_table1_proxy_errors():
                 assert ref / 2 < err < ref * 2, (lam_box, wdt, err, ref)
             else:
                 assert err < 1e-13
+
+
+def test_woodbury_merge_inverts_merge_matrix():
+    """eq. (blockinv) with the scattering matrices restored: X (I + P Q) = I
+    for an exactly low-rank sibling block; dropping S (the printed form)
+    does not invert it."""
+    rng = np.random.default_rng(11)
+    c, r = 40, 9
+    cplx = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    Sa, Sb = 0.3 * cplx(c, c), 0.3 * cplx(c, c)
+    L, Rt = cplx(c, r) / np.sqrt(c), cplx(r, c) / np.sqrt(c)
+    G = L @ Rt
+    M = np.block([[np.eye(c), Sa @ G], [Sb @ G.T, np.eye(c)]])
+    X = hbs.woodbury_merge(Sa, Sb, L, Rt)
+    assert np.abs(X @ M - np.eye(2 * c)).max() <= 1e-12
+    I = np.eye(c)
+    assert np.abs(hbs.woodbury_merge(I, I, L, Rt) @ M - np.eye(2 * c)).max() > 1e-2
+
+
+def test_woodbury_inverse_full_rank_and_truncated(case32):
+    """With an exact (tol 0) ID of G_ab the Woodbury build equals the direct
+    merge inverses; truncating G_ab at eps perturbs M by O(eps)."""
+    w, D = case32
+    C = hbs.Compression(w.n, w.kappa, 8, 1e-8, 3)
+    M0 = hbs.Inverse(C, w.b)
+    f = dense.rhs(w.b, w.u_inc, w.kappa)
+    q0 = M0.apply(f)
+    qe = hbs.Inverse(C, w.b, lowrank_tol=0.0).apply(f)
+    assert np.linalg.norm(qe - q0) <= 1e-11 * np.linalg.norm(q0)
+    for eps in (1e-4, 1e-7):
+        Mw = hbs.Inverse(C, w.b, lowrank_tol=eps)
+        ranks = {l: Mw.lowrank[l][0].shape[1] for l in Mw.lowrank}
+        assert all(ranks[l] < C.Gab[l].shape[0] for l in ranks)
+        err = np.linalg.norm(Mw.apply(f) - q0) / np.linalg.norm(q0)
+        assert 1e-3 * eps < err <= 3 * eps, (eps, err)
