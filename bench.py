@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--batched", type=int, default=0,
                     help="instead of the headline run: time the factor of this many uneven instances "
                          "(sides 64..256, 5-20 wavelengths), batched (lsh_batch_factor) against one by one")
+    ap.add_argument("--merge", default="auto", choices=["auto", "schur", "lowrank"],
+                    help="form of the merge inverses (lsh_desc.merge)")
     ap.add_argument("--multi-rhs", type=int, default=0,
                     help="instead of the headline run: time the FP64 FGMRES solve of this many plane waves "
                          "(512 x 512 grid, kappa = 80 pi) in lockstep (one lsh_solve call) against one call "
@@ -63,18 +65,18 @@ def workload(n):
     return synth.largest(n=n, kappa=200 * np.pi * n / 1024)
 
 
-def run_step(lsh, w, b_d, u_d, prec, torch, separate=False):
+def run_step(lsh, w, b_d, u_d, prec, torch, separate=False, merge="auto"):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if separate:  # lsh_plan_create then lsh_factor_create
         P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width,
-                     prec=prec)
+                     prec=prec, merge=merge)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         F = lsh.Factor(P, b_d)
     else:  # lsh_build: the same plan and factor, pipelined by level
         P, F = lsh.build(w.n, w.kappa, b_d, op_order=w.op_order, leaf=w.leaf, tol=w.tol,
-                         proxy_width=w.proxy_width, prec=prec)
+                         proxy_width=w.proxy_width, prec=prec, merge=merge)
         t1 = None
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -84,7 +86,7 @@ def run_step(lsh, w, b_d, u_d, prec, torch, separate=False):
     out = {"build_s": t2 - t0, "plan_s": (t1 - t0) if t1 else None, "factor_s": (t2 - t1) if t1 else None,
            "solve_s": t3 - t2, "total_s": t3 - t0,
            "iterations": info.iterations, "true_residual": info.true_residual, "rc": rc,
-           "ranks": P.ranks()[1]}
+           "ranks": P.ranks()[1], "lowrank_ranks": P.lowrank_ranks()}
     F.close()
     P.close()
     del sig
@@ -304,7 +306,7 @@ def main():
             if full:
                 lsh.lsh_profile_only(None)
                 lsh.lsh_profile_enable(True)
-            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate)
+            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate, a.merge)
             if full:
                 kernels_warm = kernel_table(lsh)
                 rl = roofline(lsh)
@@ -321,7 +323,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(a.steps):
-            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate)
+            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate, a.merge)
             steps.append(r)
             print(f"# step {k} {prec}: {json.dumps(r)}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -351,7 +353,7 @@ def main():
                                f"b random Fourier field |k|<=20 cycles in [-1,0.9], plane wave, "
                                f"HBS 4th order tol={w.tol} leaf={w.leaf} proxy_width={w.proxy_width}, "
                                f"operator order {w.op_order}, GMRES tol {w.gmres_tol}",
-                   "hbs_prec": "fp32", "phases_s": {k: head["median"][k] for k in
+                   "hbs_prec": "fp32", "merge": a.merge, "phases_s": {k: head["median"][k] for k in
                                                     ("build_s", "plan_s", "factor_s", "solve_s", "total_s")},
                    "iterations": head["median"]["iterations"],
                    "true_residual": head["median"]["true_residual"],

@@ -79,7 +79,20 @@ typedef struct {
   double tol;       /* compression tolerance eps (>= 0; 0 = exact full-rank HBS) */
   int proxy_width;  /* layers of proxy points around each box (1..3) */
   int hbs_prec;     /* LSH_FP64 or LSH_FP32: precision of factor and apply */
+  int merge;        /* LSH_MERGE_*: form of the merge inverses X_tau (below) */
 } lsh_desc;
+
+/* Merge inverses X_tau of Algorithm 1 (eq. (localsol)).  SCHUR inverts the
+ * c x c Schur complement I - S_b G_ab^T S_a G_ab of every parent.  LOWRANK
+ * takes a row ID G_ab ~= L R^T of the level's sibling block at the
+ * compression tolerance (once per level, in the plan) and uses the Woodbury
+ * form of the remark after Algorithm 2 (eq. (blockinv), with the scattering
+ * matrices the printed formula leaves out): X_tau = I - P (I + Q P)^{-1} Q,
+ * P = diag(S_a L, S_b R), Q = [[0, R^T], [L^T, 0]], whose inverse is of
+ * order r (by the same Schur step).  AUTO (0, the default) uses LOWRANK on
+ * the levels where r <= 0.6 c and SCHUR elsewhere (and everywhere at
+ * tol = 0). */
+enum { LSH_MERGE_AUTO = 0, LSH_MERGE_SCHUR = 1, LSH_MERGE_LOWRANK = 2 };
 
 typedef struct {
   double tol;       /* stop when ||f - A x|| / ||f|| < tol (true residual re-checked) */
@@ -122,6 +135,12 @@ int lsh_plan_block(lsh_plan_t plan, int level, int* rows, void* out, void* strea
 /* device out[(D+1)^2]: offset table T[dy][dx] = h^2 (i/4) H0(kappa h |d|),
  * T[0][0] = h^2 tau_0 (4th order); D via *D. */
 int lsh_plan_table(lsh_plan_t plan, int* D, void* out, void* stream);
+/* host: low-rank form G_ab ~= L R^T of parent level l's sibling block:
+ * *c its order, *r the rank (0: this level's merges use the Schur form);
+ * copies (if non-NULL and r > 0) L (device double2[c*r], row-major, FP64;
+ * L[J, :] = I) and R^T = G_ab[J, :] (device double2[r*c]).  Synchronises
+ * the stream. */
+int lsh_plan_lowrank(lsh_plan_t plan, int level, int* c, int* r, void* L, void* Rt, void* stream);
 
 /* ---- factor: Algorithm 1 (leaf inverses, scattering matrices, merges) ----
  * b: device double[n*n].  Errors: LSH_ERR_INPUT_NONFINITE (non-finite b),

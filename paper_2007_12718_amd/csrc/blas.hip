@@ -815,11 +815,13 @@ constexpr int MG_VEC = 8;
 template <typename R>
 __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int C, cplx<R> alpha, const cplx<R>* __restrict__ Mat,
                                                 long ldm, const cplx<R>* __restrict__ X, long ldx, cplx<R> beta,
-                                                const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+                                                const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec, int R1,
+                                                long xoff2) {
   __shared__ cplx<R> red[4][MG_VEC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blockIdx.x;
   const cplx<R>* row = Mat + (long)i * ldm;
+  if (i >= R1) X += xoff2;  // rows of the second block read their own part of each vector
   for (int b0 = 0; b0 < nvec; b0 += MG_VEC) {
     const int nb = nvec - b0 < MG_VEC ? nvec - b0 : MG_VEC;
     cplx<R> acc[MG_VEC];
@@ -857,14 +859,21 @@ __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int C, cplx<R> alpha, co
 }
 
 template <typename R>
-void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
-            cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm,
+             const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
   if (Rr <= 0 || nvec <= 0) return;
   ProfScope ps(sizeof(R) == 4 ? "cmgemv_f32" : "cmgemv_f64", s,
-               (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * (C + (Z ? 2.0 : 1.0) * Rr)));
+               (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * ((R1 < Rr ? 2.0 : 1.0) * C +
+                                                                          (Z ? 2.0 : 1.0) * Rr)));
   hipLaunchKernelGGL(k_cmgemv<R>, dim3(Rr), dim3(256), 0, s, Rr, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy,
-                     nvec);
+                     nvec, R1, xoff2);
   LSH_LAUNCH_CHECK();
+}
+
+template <typename R>
+void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
+            cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+  cmgemv2<R>(s, Rr, Rr, 0, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
 }
 
 // ------------------------------------------------- Gauss-Jordan inverse
@@ -1612,6 +1621,28 @@ void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws,
   }
 }
 
+// dst[b][i][j] = src[b][i][j] for rows x cols blocks with their own leading
+// dimensions and batch strides
+template <typename R>
+__global__ void k_ccopy2d(int rows, int cols, const cplx<R>* __restrict__ src, long lds, long ss, cplx<R>* dst,
+                          long ldd, long sd, long total) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long b = e / ((long)rows * cols), q = e - b * rows * cols;
+    const long i = q / cols, j = q - i * cols;
+    dst[b * sd + i * ldd + j] = src[b * ss + i * lds + j];
+  }
+}
+
+template <typename R>
+void ccopy2d(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, long ss, cplx<R>* dst, long ldd,
+             long sd, long batch) {
+  const long total = (long)rows * cols * batch;
+  if (total <= 0) return;
+  const long g = std::min<long>(ceil_div(total, 256L), 65536L);
+  hipLaunchKernelGGL(k_ccopy2d<R>, dim3((unsigned)g), dim3(256), 0, s, rows, cols, src, lds, ss, dst, ldd, sd, total);
+  LSH_LAUNCH_CHECK();
+}
+
 template <typename R>
 __global__ void k_ctranspose(const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -1654,6 +1685,9 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
   template void cmgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, const cplx<R>*, long, cplx<R>, \
                           const cplx<R>*, long, cplx<R>*, long, int);                                        \
   template void ctranspose<R>(hipStream_t, const cplx<R>*, int, int, cplx<R>*, long);                       \
+  template void cmgemv2<R>(hipStream_t, int, int, long, int, cplx<R>, const cplx<R>*, long, const cplx<R>*,   \
+                           long, cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                        \
+  template void ccopy2d<R>(hipStream_t, int, int, const cplx<R>*, long, long, cplx<R>*, long, long, long);   \
   template size_t inverse_ws_bytes<R>(int, int);                                                           \
   template void inverse<R>(hipStream_t, cplx<R>*, int, long, long, int, void*, int*);
 LSH_INST(float)

@@ -63,6 +63,11 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
 template <typename R>
 void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
             cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec);
+// The same with the rows split in two blocks: rows i >= R1 read X + xoff2
+// (each vector's second part), rows i < R1 read X.
+template <typename R>
+void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm,
+             const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec);
 
 // In-place inverse of each c x c matrix by Gauss-Jordan elimination with
 // partial (row) pivoting.  ws must hold inverse_ws_bytes(c, batch) bytes.
@@ -90,6 +95,11 @@ void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws,
 // out_b (cols x rows) = in_b^T (rows x cols), row-major, batch of contiguous matrices
 template <typename R>
 void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch = 1);
+
+// dst_b = src_b for rows x cols blocks (leading dimensions lds, ldd; batch strides ss, sd)
+template <typename R>
+void ccopy2d(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, long ss, cplx<R>* dst, long ldd,
+             long sd, long batch = 1);
 
 // dst (R2) = src (R1), elementwise, n complex entries
 template <typename R1, typename R2>

@@ -53,6 +53,11 @@ struct Level {
   DevBuf Gab64, Gab32;   // sibling block of this parent level (c x c, c = k of level+1)
   DevBuf Gabt64, Gabt32; // its transpose
   int c = 0;
+  // low-rank form G_ab ~= L R^T (merge by the Woodbury form); wr = 0: Schur form
+  int wr = 0;
+  std::vector<I2> wrows;  // skeleton points J of G_ab's row ID (upload source)
+  DevBuf Pm64, Pm32;      // [L; R] (2c x wr): L = U of the row ID, R = G_ab[J, :]^T
+  DevBuf Qm64, Qm32;      // [L^T; R^T] (2 wr x c)
 };
 
 }  // namespace
@@ -79,6 +84,14 @@ struct lsh_plan_s {
   const cplx<R>* Ut(int l) const;
   template <typename R>
   const cplx<R>* Gabt(int l) const;
+  // low-rank sibling factors of parent level l: 0 L, 1 L^T, 2 R, 3 R^T
+  // (L and R stacked in [L; R], L^T and R^T in [L^T; R^T])
+  template <typename R>
+  const cplx<R>* W(int l, int which) const {
+    const Level& v = lev[l];
+    const DevBuf& b = (which & 1) ? (sizeof(R) == 8 ? v.Qm64 : v.Qm32) : (sizeof(R) == 8 ? v.Pm64 : v.Pm32);
+    return static_cast<const cplx<R>*>(b.p) + (which >= 2 ? (long)v.c * v.wr : 0L);
+  }
 };
 
 template <>
@@ -158,23 +171,22 @@ void validate(const lsh_desc& d) {
   LSH_REQUIRE(d.tol >= 0 && d.tol < 1, LSH_ERR_INVALID_ARG, "tol must be in [0, 1)");
   LSH_REQUIRE(d.proxy_width >= 1 && d.proxy_width <= 3, LSH_ERR_INVALID_ARG, "proxy_width must be 1..3");
   LSH_REQUIRE(d.hbs_prec == LSH_FP64 || d.hbs_prec == LSH_FP32, LSH_ERR_INVALID_ARG, "hbs_prec");
+  LSH_REQUIRE(d.merge >= LSH_MERGE_AUTO && d.merge <= LSH_MERGE_LOWRANK, LSH_ERR_INVALID_ARG, "merge");
 }
 
-// Row ID of the level's proxy matrix (FP64); fills lv.J (host) and lv.U64.
-void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
-  const int m = lv.m, np = (int)prox.size();
-  if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all candidates
-    lv.k = m;
-    lv.J.resize(m);
-    for (int i = 0; i < m; ++i) lv.J[i] = i;
+// Row ID A ~= U A[J, :] of a device matrix A (m x np, FP64; overwritten) at
+// the plan's tolerance: J to the host, U (m x k) to a new device buffer;
+// returns k.
+int row_id_matrix(const lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64,
+                  hipStream_t s) {
+  if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all rows
+    Jh.resize(m);
+    for (int i = 0; i < m; ++i) Jh[i] = i;
     std::vector<z64> I((size_t)m * m, mk(0.0, 0.0));
     for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = mk(1.0, 0.0);
-    lv.U64 = upload(I, s);
-    return;
+    U64 = upload(I, s);
+    return m;
   }
-  AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
-  AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
-  gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
   AsyncBuf J(sizeof(int) * m, s), Ufull(sizeof(z64) * (size_t)m * m, s);
   int k = 0;
   // Gram + pivoted Cholesky squares the conditioning: FP64 resolves the
@@ -182,12 +194,12 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
   if (P.d.tol < 1e-7) {
     // ||A||_F for the stopping rule |R_kk| <= tol ||A||_F (computed on device)
     AsyncBuf ws(rowid_cpqr_ws(m), s), kd(sizeof(int), s), fro(sizeof(z64), s), part(multidot_partial_bytes(1), s);
-    multidot(s, A.as<z64>(), 0, 1, A.as<z64>(), (long)m * np, fro.as<z64>(), part.as<z64>());
+    multidot(s, A, 0, 1, A, (long)m * np, fro.as<z64>(), part.as<z64>());
     z64 f2;
     LSH_HIP(hipMemcpyAsync(&f2, fro.p, sizeof(z64), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     const double thr = P.d.tol * std::sqrt(f2.x);
-    rowid_cpqr(s, A.as<z64>(), m, np, thr, J.as<int>(), Ufull.as<z64>(), kd.as<int>(), ws.p);
+    rowid_cpqr(s, A, m, np, thr, J.as<int>(), Ufull.as<z64>(), kd.as<int>(), ws.p);
     LSH_HIP(hipMemcpyAsync(&k, kd.p, sizeof(int), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
@@ -201,18 +213,31 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
     if (!block) {
       AsyncBuf ws(rowid_gram_ws(m), s);
-      k = rowid_gram(s, A.as<z64>(), m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
+      k = rowid_gram(s, A, m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
     } else {
       AsyncBuf ws(rowid_bp_ws(m), s);
-      k = rowid_bp(s, A.as<z64>(), m, np, P.d.tol, alpha, J.as<int>(), Ufull.as<z64>(), ws.p);
+      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J.as<int>(), Ufull.as<z64>(), ws.p);
     }
   }
-  lv.k = k;
-  lv.J.resize(k);
-  LSH_HIP(hipMemcpyAsync(lv.J.data(), J.p, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-  lv.U64.alloc(sizeof(z64) * (size_t)m * k);
-  LSH_HIP(hipMemcpyAsync(lv.U64.p, Ufull.p, sizeof(z64) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
+  Jh.resize(k);
+  LSH_HIP(hipMemcpyAsync(Jh.data(), J.p, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  U64.alloc(sizeof(z64) * (size_t)m * k);
+  LSH_HIP(hipMemcpyAsync(U64.p, Ufull.p, sizeof(z64) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
   LSH_HIP(hipStreamSynchronize(s));
+  return k;
+}
+
+// Row ID of the level's proxy matrix (FP64); fills lv.J (host) and lv.U64.
+void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
+  const int m = lv.m, np = (int)prox.size();
+  if (P.d.tol == 0) {
+    lv.k = row_id_matrix(P, nullptr, m, np, lv.J, lv.U64, s);
+    return;
+  }
+  AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
+  AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
+  gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
+  lv.k = row_id_matrix(P, A.as<z64>(), m, np, lv.J, lv.U64, s);
 }
 
 // Plan in three phases so that the factor can follow it level by level:
@@ -298,6 +323,51 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
   }
 }
 
+// Low-rank form of parent level l's sibling block for the Woodbury merge:
+// G_ab ~= L R^T with L = U and R^T = G_ab[J, :] from the row ID of G_ab at
+// the compression tolerance (the remark after Algorithm 2; rank about a
+// quarter to two fifths of c at tol 1e-4).  AUTO keeps the Schur form where
+// r > 0.6 c, where the Woodbury products stop saving work.
+void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
+  const lsh_desc& d = P.d;
+  Level& lv = P.lev[l];
+  lv.wr = 0;
+  const int c = lv.c;
+  if (d.merge == LSH_MERGE_SCHUR || (d.merge == LSH_MERGE_AUTO && d.tol == 0)) return;
+  const long cc = (long)c * c;
+  std::vector<int> J;
+  DevBuf U;
+  int r = 0;
+  {
+    AsyncBuf A(sizeof(z64) * cc, s);
+    LSH_HIP(hipMemcpyAsync(A.p, lv.Gab64.p, sizeof(z64) * cc, hipMemcpyDeviceToDevice, s));
+    r = row_id_matrix(P, A.as<z64>(), c, c, J, U, s);
+  }
+  if (d.merge == LSH_MERGE_AUTO && 10 * r > 6 * c) return;
+  const bool f32 = d.hbs_prec == LSH_FP32;
+  const long cr = (long)c * r;
+  lv.wr = r;
+  std::vector<I2>& rows = lv.wrows;
+  rows.resize(r);
+  for (int i = 0; i < r; ++i) rows[i] = lv.ra[J[i]];
+  AsyncBuf dr = upload_async(rows, s), db = upload_async(lv.rb, s);
+  lv.Pm64.alloc(sizeof(z64) * 2 * cr);
+  lv.Qm64.alloc(sizeof(z64) * 2 * cr);
+  z64* Pm = lv.Pm64.as<z64>();
+  z64* Qm = lv.Qm64.as<z64>();
+  LSH_HIP(hipMemcpyAsync(Pm, U.p, sizeof(z64) * cr, hipMemcpyDeviceToDevice, s));       // L
+  gather_table(s, P.table.as<z64>(), P.D, dr.as<I2>(), r, db.as<I2>(), c, Qm + cr, c);  // R^T = G_ab[J, :]
+  ctranspose<double>(s, Pm, c, r, Qm);                                                 // L^T
+  ctranspose<double>(s, Qm + cr, r, c, Pm + cr);                                       // R
+  if (f32) {
+    lv.Pm32.alloc(sizeof(c32) * 2 * cr);
+    lv.Qm32.alloc(sizeof(c32) * 2 * cr);
+    ccast<double, float>(s, Pm, lv.Pm32.as<c32>(), 2 * cr);
+    ccast<double, float>(s, Qm, lv.Qm32.as<c32>(), 2 * cr);
+  }
+  LSH_HIP(hipStreamSynchronize(s));  // (U is freed on return)
+}
+
 // sibling block of parent level l (needs the skeletons of level l + 1)
 void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
   const lsh_desc& d = P.d;
@@ -331,6 +401,7 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
       ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
     }
     // (the device staging buffers are freed in stream order)
+    plan_lowrank(P, l, s);
   }
 }
 
@@ -358,11 +429,15 @@ struct FactorData {
   DevBuf X;                       // leaf inverses [nleaf][mL][mL]
   std::vector<DevBuf> S;          // S[l], l = 1..L : [2^l][k_l][k_l]
   std::vector<DevBuf> Pa, Pb, Ci; // parent level l = 0..L-1 : [2^l][c][c]
+  // Woodbury levels (wr[l] = r > 0): Pa = [S_a L; S_b R] per box
+  // ([2^l][2][c][r]) and Ci = W', the inverse of I + Q P with its two column
+  // blocks swapped ([2^l][2r][2r]); Pb unused
+  std::vector<int> wr;
   // apply workspace
   int ws_nrhs = 0;
   DevBuf r;                       // [nrhs][nleaf][mL]
   std::vector<DevBuf> rt, wt;     // [nrhs][2^l][k_l]
-  DevBuf t1, t2, t3, ty;          // scratch
+  DevBuf t1, t2, t3, ty, tw;      // scratch
   // transposed per-box matrices for M^T (built on first use)
   bool has_T = false;
   DevBuf XT;
@@ -409,6 +484,7 @@ void factor_init(const lsh_plan_s& P, FactorData<R>& F) {
   F.S.resize(P.L + 1);
   F.Pa.clear(); F.Pb.clear(); F.Ci.clear();
   F.Pa.resize(P.L); F.Pb.resize(P.L); F.Ci.resize(P.L);
+  F.wr.assign(P.L, 0);
 }
 
 template <typename R>
@@ -437,13 +513,61 @@ void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipSt
            nullptr, 0, 0, F.S[L].template as<cplx<R>>(), kL, (long)kL * kL, nleaf);
 }
 
+// Woodbury merge of parent level l (G_ab ~= L R^T, rank r): with
+// P = diag(S_a L, S_b R) and Q = [[0, R^T], [L^T, 0]] the merge matrix is
+// I + P Q, so X = I - P (I + Q P)^{-1} Q.  I + Q P = [[I, Aw], [Bw, I]]
+// (Aw = R^T S_b R, Bw = L^T S_a L) is inverted by its own Schur step,
+// C = (I - Bw Aw)^{-1}:  (I + Q P)^{-1} = [[I + Aw C Bw, -Aw C], [-C Bw, C]].
+// Stored: W' = that inverse with its column blocks swapped,
+// [[-Aw C, I + Aw C Bw], [C, -C Bw]], which takes Q v in the order
+// [L^T v_a; R^T v_b] (so that both halves of Q v, and of Q^T z, are one
+// strided product).
+template <typename R>
+void factor_merge_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  const int c = P.lev[l].c, r = P.lev[l].wr, nb = 1 << l;
+  const long cc = (long)c * c, cr = (long)c * r, rr = (long)r * r, r2 = 2L * r, w4 = 4L * rr;
+  const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
+  F.wr[l] = r;
+  F.Pa[l].alloc(sizeof(cplx<R>) * nb * 2 * cr);
+  F.Ci[l].alloc(sizeof(cplx<R>) * nb * w4);
+  cplx<R>* Pst = F.Pa[l].template as<cplx<R>>();
+  cplx<R>* W = F.Ci[l].template as<cplx<R>>();
+  AsyncBuf T(sizeof(cplx<R>) * nb * 3 * rr, s);
+  cplx<R>* Aw = T.template as<cplx<R>>();
+  cplx<R>* Bw = Aw + nb * rr;
+  cplx<R>* C = Bw + nb * rr;
+  // S_a L, S_b R
+  cgemm<R>(s, c, r, c, one, Sch, c, 2 * cc, OP_N, P.W<R>(l, 0), r, 0, OP_N, zero, nullptr, 0, 0, Pst, r, 2 * cr, nb);
+  cgemm<R>(s, c, r, c, one, Sch + cc, c, 2 * cc, OP_N, P.W<R>(l, 2), r, 0, OP_N, zero, nullptr, 0, 0, Pst + cr, r,
+           2 * cr, nb);
+  // Aw = R^T (S_b R), Bw = L^T (S_a L), C = (I - Bw Aw)^{-1}
+  cgemm<R>(s, r, r, c, one, P.W<R>(l, 3), c, 0, OP_N, Pst + cr, r, 2 * cr, OP_N, zero, nullptr, 0, 0, Aw, r, rr, nb);
+  cgemm<R>(s, r, r, c, one, P.W<R>(l, 1), c, 0, OP_N, Pst, r, 2 * cr, OP_N, zero, nullptr, 0, 0, Bw, r, rr, nb);
+  cgemm<R>(s, r, r, r, mone, Bw, r, rr, OP_N, Aw, r, rr, OP_N, zero, nullptr, 0, 0, C, r, rr, nb, true);
+  {
+    AsyncBuf ws(inverse_ws_bytes<R>(r, nb), s);
+    F.info.emplace_back(sizeof(int) * nb, s);
+    F.info_n.push_back(nb);
+    F.info_what.push_back("singular merge matrix I - Bw Aw at level " + std::to_string(l));
+    inverse<R>(s, C, r, r, rr, nb, ws.p, F.info.back().template as<int>());
+  }
+  // W' = [[-Aw C, I + Aw C Bw], [C, -C Bw]]  (row blocks of 2r entries)
+  ccopy2d<R>(s, r, r, C, r, rr, W + r * r2, r2, w4, nb);
+  cgemm<R>(s, r, r, r, mone, Aw, r, rr, OP_N, C, r, rr, OP_N, zero, nullptr, 0, 0, W, r2, w4, nb);
+  cgemm<R>(s, r, r, r, mone, W, r2, w4, OP_N, Bw, r, rr, OP_N, zero, nullptr, 0, 0, W + r, r2, w4, nb, true);
+  cgemm<R>(s, r, r, r, mone, C, r, rr, OP_N, Bw, r, rr, OP_N, zero, nullptr, 0, 0, W + r * r2 + r, r2, w4, nb);
+}
+
 // merge of parent level l: P_a, P_b, C^{-1} (needs G_ab of level l)
 template <typename R>
 void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  if (P.lev[l].wr > 0) return factor_merge_lowrank(P, F, l, s);
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
   const int c = P.lev[l].c, nb = 1 << l;
   const long cc = (long)c * c;
   const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
+  F.wr[l] = 0;
   const cplx<R>* G = P.Gab<R>(l);
   F.Pa[l].alloc(sizeof(cplx<R>) * nb * cc);
   F.Pb[l].alloc(sizeof(cplx<R>) * nb * cc);
@@ -478,16 +602,41 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
   const long ck = (long)c * k;
   const cplx<R>* U1 = P.U<R>(l);
   const cplx<R>* U2 = U1 + ck;
+  if (F.wr[l] > 0) {
+    // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] (a1, a2 interleaved per box in A12)
+    const int r = F.wr[l];
+    const long rk = (long)r * k, cr = (long)c * r, w4 = 4L * r * r;
+    AsyncBuf A12(sizeof(cplx<R>) * nb * 2 * ck, s), Qb(sizeof(cplx<R>) * nb * 4 * rk, s);
+    cplx<R>* a = A12.template as<cplx<R>>();
+    cplx<R>* q = Qb.template as<cplx<R>>();
+    cplx<R>* yv = q + nb * 2 * rk;
+    cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a, k, 2 * ck, nb);
+    cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a + ck, k, 2 * ck, nb);
+    cgemm<R>(s, r, k, c, one, P.W<R>(l, 1), c, 0, OP_N, a, k, 2 * ck, OP_N, zero, nullptr, 0, 0, q, k, 2 * rk, nb);
+    cgemm<R>(s, r, k, c, one, P.W<R>(l, 3), c, 0, OP_N, a + ck, k, 2 * ck, OP_N, zero, nullptr, 0, 0, q + rk, k,
+             2 * rk, nb);
+    cgemm<R>(s, 2 * r, k, 2 * r, one, Ci, 2 * r, w4, OP_N, q, k, 2 * rk, OP_N, zero, nullptr, 0, 0, yv, k, 2 * rk,
+             nb);
+    cgemm<R>(s, c, k, r, mone, Pa, r, cr, OP_N, yv, k, rk, OP_N, one, a, k, ck, a, k, ck, 2 * nb);
+    F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
+    cplx<R>* S = F.S[l].template as<cplx<R>>();
+    cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a, k, 2 * ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
+    cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, a + ck, k, 2 * ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k,
+             nb);
+    return;
+  }
   AsyncBuf A1(sizeof(cplx<R>) * nb * ck, s), A2(sizeof(cplx<R>) * nb * ck, s), Yb(sizeof(cplx<R>) * nb * ck, s);
   cplx<R>* a1 = A1.template as<cplx<R>>();
   cplx<R>* a2 = A2.template as<cplx<R>>();
   cplx<R>* y = Yb.template as<cplx<R>>();
   cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a1, k, ck, nb);
   cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a2, k, ck, nb);
-  // a2 <- A2 - Pb A1 ; y = C^{-1} a2 ; a1 <- A1 - Pa y
-  cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, a1, k, ck, OP_N, one, a2, k, ck, a2, k, ck, nb);
-  cgemm<R>(s, c, k, c, one, Ci, c, cc, OP_N, a2, k, ck, OP_N, zero, nullptr, 0, 0, y, k, ck, nb);
-  cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, y, k, ck, OP_N, one, a1, k, ck, a1, k, ck, nb);
+  {
+    // a2 <- A2 - Pb A1 ; y = C^{-1} a2 ; a1 <- A1 - Pa y
+    cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, a1, k, ck, OP_N, one, a2, k, ck, a2, k, ck, nb);
+    cgemm<R>(s, c, k, c, one, Ci, c, cc, OP_N, a2, k, ck, OP_N, zero, nullptr, 0, 0, y, k, ck, nb);
+    cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, y, k, ck, OP_N, one, a1, k, ck, a1, k, ck, nb);
+  }
   F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
   cplx<R>* S = F.S[l].template as<cplx<R>>();
   cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a1, k, ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
@@ -528,13 +677,55 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
   F.t2.alloc(sizeof(cplx<R>) * big);
   F.t3.alloc(sizeof(cplx<R>) * big);
   F.ty.alloc(sizeof(cplx<R>) * big);
+  F.tw.alloc(sizeof(cplx<R>) * big);
   F.ws_nrhs = nrhs;
+}
+
+// below this many box vectors the shared products stream the matrix rows
+// (multi-vector GEMV); above it they are MFMA GEMMs
+constexpr int SKINNY = 32;
+
+// out = X_tau in on a Woodbury level, three launches:
+//   q = [L^T a; R^T b]  (shared [L^T; R^T], one two-block product),
+//   y = W' q            (per box, 2r x 2r),
+//   out = in - [S_a L y1; S_b R y2]  (per box, as 2B problems of c x r).
+// Transposed: X^T = I - Q^T (I + Q P)^{-T} P^T with Q^T = [[0, L], [R, 0]]:
+//   p = [(S_a L)^T a; (S_b R)^T b], z = W'^T p = [z2; z1],
+//   out = in - [L z2; R z1]  (shared [L; R], one two-block product).
+template <typename R>
+void apply_X_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, const cplx<R>* in, cplx<R>* out,
+                     hipStream_t s, bool transposed) {
+  const int c = P.lev[l].c, r = F.wr[l], nb = 1 << l, B = nrhs * nb;
+  const long cr = (long)c * r, w4 = 4L * r * r;
+  const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
+  cplx<R>* q = F.tw.template as<cplx<R>>();  // [B][2r]
+  cplx<R>* y = F.ty.template as<cplx<R>>();  // [B][2r]
+  const cplx<R>* Pm = P.W<R>(l, 0);  // [L; R]
+  const cplx<R>* Qm = P.W<R>(l, 1);  // [L^T; R^T]
+  if (!transposed) {
+    if (B <= SKINNY)
+      cmgemv2<R>(s, 2 * r, r, c, c, one, Qm, c, in, 2 * c, zero, nullptr, 0, q, 2 * r, B);
+    else  // two strided products: (a, L) and (b, R)
+      cgemm<R>(s, B, r, c, one, in, 2 * c, c, OP_N, Pm, r, cr, OP_N, zero, nullptr, 0, 0, q, 2 * r, r, 2);
+    cgemv<R>(s, 2 * r, 2 * r, one, F.Ci[l].template as<cplx<R>>(), 2 * r, w4, nb, q, 2 * r, zero, nullptr, 0, y,
+             2 * r, B);
+    cgemv<R>(s, c, r, mone, F.Pa[l].template as<cplx<R>>(), r, cr, 2 * nb, y, r, one, in, c, out, c, 2 * B);
+  } else {
+    cgemv<R>(s, r, c, one, F.PaT[l].template as<cplx<R>>(), c, cr, 2 * nb, in, c, zero, nullptr, 0, q, r, 2 * B);
+    cgemv<R>(s, 2 * r, 2 * r, one, F.CiT[l].template as<cplx<R>>(), 2 * r, w4, nb, q, 2 * r, zero, nullptr, 0, y,
+             2 * r, B);
+    if (B <= SKINNY)
+      cmgemv2<R>(s, 2 * c, c, r, r, mone, Pm, r, y, 2 * r, one, in, 2 * c, out, 2 * c, B);
+    else  // (z2, L^T) -> a, (z1, R^T) -> b
+      cgemm<R>(s, B, c, r, mone, y, 2 * r, r, OP_N, Qm, c, cr, OP_N, one, in, 2 * c, c, out, 2 * c, c, 2);
+  }
 }
 
 // out = X_tau in for every box of parent level l (B = nrhs * 2^l problems, [B][2c])
 template <typename R>
 void apply_X(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, const cplx<R>* in, cplx<R>* out,
              hipStream_t s, bool transposed = false) {
+  if (F.wr[l] > 0) return apply_X_lowrank(P, F, l, nrhs, in, out, s, transposed);
   const int c = P.lev[l].c, nb = 1 << l, B = nrhs * nb;
   const long cc = (long)c * c;
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
@@ -566,6 +757,14 @@ void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
   }
   for (int l = 0; l < L; ++l) {
     const int c = P.lev[l].c;
+    if (F.wr[l] > 0) {  // Woodbury level: [S_a L; S_b R] blocks (c x r) and W' (2r x 2r)
+      const int r = F.wr[l];
+      F.PaT[l].alloc(F.Pa[l].bytes);
+      F.CiT[l].alloc(F.Ci[l].bytes);
+      ctranspose<R>(s, F.Pa[l].template as<cplx<R>>(), c, r, F.PaT[l].template as<cplx<R>>(), 2L << l);
+      ctranspose<R>(s, F.Ci[l].template as<cplx<R>>(), 2 * r, 2 * r, F.CiT[l].template as<cplx<R>>(), 1L << l);
+      continue;
+    }
     F.PaT[l].alloc(F.Pa[l].bytes);
     F.PbT[l].alloc(F.Pb[l].bytes);
     F.CiT[l].alloc(F.Ci[l].bytes);
@@ -576,10 +775,6 @@ void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
   LSH_HIP(hipStreamSynchronize(s));
   F.has_T = true;
 }
-
-// below this many box vectors the shared products stream the matrix rows
-// (multi-vector GEMV); above it they are MFMA GEMMs
-constexpr int SKINNY = 32;
 
 template <typename R>
 void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* f, z64* q, int nrhs,
@@ -1242,6 +1437,23 @@ int lsh_plan_level(lsh_plan_t P, int level, int* m, int* k, int* J, int* cand, v
   API_END
 }
 
+int lsh_plan_lowrank(lsh_plan_t P, int level, int* c, int* r, void* L, void* Rt, void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(P && level >= 0 && level < P->L, LSH_ERR_INVALID_ARG, "bad level");
+  const Level& lv = P->lev[level];
+  if (c) *c = lv.c;
+  if (r) *r = lv.wr;
+  const size_t bytes = sizeof(z64) * (size_t)lv.c * lv.wr;
+  if (L && lv.wr > 0)
+    LSH_HIP(hipMemcpyAsync(L, lv.Pm64.p, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  if (Rt && lv.wr > 0)
+    LSH_HIP(hipMemcpyAsync(Rt, lv.Qm64.as<z64>() + (size_t)lv.c * lv.wr, bytes, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  LSH_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return LSH_OK;
+  API_END
+}
+
 int lsh_plan_block(lsh_plan_t P, int level, int* rows, void* out, void* stream) {
   API_BEGIN
   LSH_REQUIRE(P && level >= -1 && level < P->L, LSH_ERR_INVALID_ARG, "bad level");
@@ -1320,12 +1532,14 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   }
   int dev = 0;
   LSH_HIP(hipGetDevice(&dev));
-  hipStream_t ps = nullptr;
+  hipStream_t ps = nullptr, ps2 = nullptr;
   LSH_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
   struct StreamGuard {
     hipStream_t st;
     ~StreamGuard() { if (st) (void)hipStreamDestroy(st); }
   } sg{ps};
+  LSH_HIP(hipStreamCreateWithFlags(&ps2, hipStreamNonBlocking));
+  StreamGuard sg2{ps2};
   // The factor runs on a stream kept off LSH_PLAN_CUS compute units, so that
   // the plan's small latency-bound kernels (the critical path) find free
   // units while the factor's products fill the rest.  Default: an eighth of
@@ -1363,35 +1577,58 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   }
   std::mutex mu;
   std::condition_variable cv;
-  int doneU = L + 1, doneG = L + 1;  // lowest level with U_l / G_l ready; -2 = failed
+  int doneU = L + 1, doneG = L + 1;  // lowest level with U_l / G_l ready
+  int running = 2;                   // plan threads still running
   bool finished = false, failed = false;
   std::exception_ptr err;
+  auto fail = [&] {
+    std::lock_guard<std::mutex> g(mu);
+    if (!err) err = std::current_exception();
+    failed = true;
+  };
+  auto leave = [&] {
+    { std::lock_guard<std::mutex> g(mu); finished = --running == 0; }
+    cv.notify_all();
+  };
+  // two plan threads: the row IDs of levels L..1 (the critical path), and
+  // behind them the sibling blocks of parent levels L-1..0 with their
+  // low-rank forms (sibling block l needs the skeletons of level l + 1)
   std::thread th([&] {
     try {
       LSH_HIP(hipSetDevice(dev));
-      for (int l = L; l >= 0; --l) {
-        if (l < L) {
-          plan_sibling(*P, l, ps);
-          LSH_HIP(hipEventRecord(ev[L + 1 + l], ps));
-          { std::lock_guard<std::mutex> g(mu); doneG = l; }
-          cv.notify_all();
-        }
-        if (l >= 1) {
-          plan_id(*P, l, ps);
-          LSH_HIP(hipEventRecord(ev[l], ps));
-          { std::lock_guard<std::mutex> g(mu); doneU = l; }
-          cv.notify_all();
-        }
+      for (int l = L; l >= 1; --l) {
+        plan_id(*P, l, ps);
+        LSH_HIP(hipEventRecord(ev[l], ps));
+        { std::lock_guard<std::mutex> g(mu); doneU = l; }
+        cv.notify_all();
       }
-      plan_finish(*P, ps);
-      LSH_HIP(hipEventRecord(ev[2 * L + 2], ps));
-      { std::lock_guard<std::mutex> g(mu); finished = true; }
     } catch (...) {
-      std::lock_guard<std::mutex> g(mu);
-      err = std::current_exception();
-      failed = true;
+      fail();
     }
-    cv.notify_all();
+    leave();
+  });
+  std::thread th2([&] {
+    try {
+      LSH_HIP(hipSetDevice(dev));
+      for (int l = L - 1; l >= 0; --l) {
+        {
+          std::unique_lock<std::mutex> g(mu);
+          cv.wait(g, [&] { return failed || doneU <= l + 1; });
+          if (failed) break;
+        }
+        plan_sibling(*P, l, ps2);
+        LSH_HIP(hipEventRecord(ev[L + 1 + l], ps2));
+        { std::lock_guard<std::mutex> g(mu); doneG = l; }
+        cv.notify_all();
+      }
+      if (!failed) {
+        plan_finish(*P, ps2);
+        LSH_HIP(hipEventRecord(ev[2 * L + 2], ps2));
+      }
+    } catch (...) {
+      fail();
+    }
+    leave();
   });
   // wait until U_l (kind 0) or G_l (kind 1) exists; false if the plan failed
   auto wait_for = [&](int l, int kind) -> bool {
@@ -1427,7 +1664,12 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   } catch (...) {
     ferr = std::current_exception();
   }
+  if (ferr) {  // let the plan threads stop early
+    { std::lock_guard<std::mutex> g(mu); failed = true; }
+    cv.notify_all();
+  }
   th.join();
+  th2.join();
   if (err) std::rethrow_exception(err);
   if (ferr) std::rethrow_exception(ferr);
   LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 2], 0));
@@ -1507,9 +1749,18 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
   Yb.clear(); Zb.clear();
   // levels, aligned from the leaves
   for (int dpt = 1; dpt <= Lmax; ++dpt) {
-    std::vector<int> act;
+    std::vector<int> act, wact;  // Schur-form levels (grouped) and Woodbury levels (per instance)
     for (int i = 0; i < n_inst; ++i)
-      if (Fs[i]->plan->L - dpt >= 0) act.push_back(i);
+      if (Fs[i]->plan->L - dpt >= 0) (Fs[i]->plan->lev[Fs[i]->plan->L - dpt].wr > 0 ? wact : act).push_back(i);
+    for (int i : wact) {
+      const int l = Fs[i]->plan->L - dpt;
+      factor_merge<float>(*Fs[i]->plan, Fs[i]->f32, l, s);
+      factor_scatter<float>(*Fs[i]->plan, Fs[i]->f32, l, s);
+    }
+    if (act.empty()) {
+      LSH_HIP(hipStreamSynchronize(s));
+      continue;
+    }
     std::vector<DevBuf> tabs(9);
     auto lev = [&](int i) { return Fs[i]->plan->L - dpt; };
     for (int i : act) {  // allocations of this level
@@ -1623,6 +1874,13 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
       run_gemms(tabs[7]);
     }
     LSH_HIP(hipStreamSynchronize(s));  // scratch and tables of this level die here
+  }
+  for (int i = 0; i < n_inst; ++i) {  // singularity flags of the Woodbury levels
+    try {
+      factor_check(Fs[i]->f32, s);
+    } catch (const Error& e) {
+      throw Error(e.code, std::string(e.what()) + " (instance " + std::to_string(i) + ")");
+    }
   }
 }
 

@@ -13,6 +13,7 @@ namespace {
 struct Rec {
   std::string name;
   hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s = nullptr;
   double work = 0;
 };
 std::mutex mu;
@@ -41,12 +42,13 @@ void record(const char* name, hipStream_t s, double work, bool start) {
     Rec r;
     r.name = name;
     r.work = work;
+    r.s = s;
     r.a = get_event();
     if (r.a) (void)hipEventRecord(r.a, s);
     recs.push_back(r);
   } else {
     for (auto it = recs.rbegin(); it != recs.rend(); ++it)
-      if (it->b == nullptr && it->name == name) {
+      if (it->b == nullptr && it->s == s && it->name == name) {
         it->b = get_event();
         if (it->b) (void)hipEventRecord(it->b, s);
         break;

@@ -27,14 +27,17 @@ EXPORTED = [
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
     "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
     "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor", "lsh_profile_only",
-    "lsh_cache_trim",
+    "lsh_cache_trim", "lsh_plan_lowrank",
 ]
 
 
 class LshDesc(ctypes.Structure):
     _fields_ = [("n", c_int), ("h", c_double), ("x0", c_double), ("y0", c_double), ("kappa", c_double),
                 ("op_order", c_int), ("leaf", c_int), ("tol", c_double), ("proxy_width", c_int),
-                ("hbs_prec", c_int)]
+                ("hbs_prec", c_int), ("merge", c_int)]
+
+
+MERGE = {"auto": 0, "schur": 1, "lowrank": 2}
 
 
 class LshSolveOpts(ctypes.Structure):
@@ -141,10 +144,10 @@ class Plan:
     """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
 
     def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
-                 h=None, x0=-0.5, y0=-0.5, _create=True):
+                 h=None, x0=-0.5, y0=-0.5, merge="auto", _create=True):
         self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
                             op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
-                            hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64)
+                            hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64, merge=MERGE[merge])
         self.n = n
         self.h = self.desc.h
         self.kappa = kappa
@@ -188,6 +191,28 @@ class Plan:
         out = torch.empty((c.value, c.value), dtype=torch.complex128, device="cuda")
         _check(lib().lsh_plan_block(self.handle, level, None, _ptr(out), _stream()))
         return out
+
+    def lowrank_ranks(self):
+        """Rank r of each parent level's low-rank sibling block (0: Schur-form merges there)."""
+        out = []
+        for l in range(self.ranks()[0]):
+            c, r = c_int(0), c_int(0)
+            _check(lib().lsh_plan_lowrank(self.handle, l, ctypes.byref(c), ctypes.byref(r), None, None, _stream()))
+            out.append(r.value)
+        return out
+
+    def lowrank(self, level):
+        """(L, Rt) of parent level `level` (G_ab ~= L Rt, complex128 on device), or None
+        where that level's merges use the Schur form."""
+        import torch
+        c, r = c_int(0), c_int(0)
+        _check(lib().lsh_plan_lowrank(self.handle, level, ctypes.byref(c), ctypes.byref(r), None, None, _stream()))
+        if r.value == 0:
+            return None
+        L = torch.empty((c.value, r.value), dtype=torch.complex128, device="cuda")
+        Rt = torch.empty((r.value, c.value), dtype=torch.complex128, device="cuda")
+        _check(lib().lsh_plan_lowrank(self.handle, level, None, None, _ptr(L), _ptr(Rt), _stream()))
+        return L, Rt
 
     def table(self):
         import torch
@@ -300,10 +325,11 @@ class Factor:
         return lam, info, rc
 
 
-def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5):
+def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5,
+          merge="auto"):
     """lsh_build: plan and factor pipelined by level; returns (Plan, Factor)."""
     import torch
-    P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, _create=False)
+    P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge=merge, _create=False)
     fh = c_void_p()
     b = b.reshape(n, n).contiguous()
     _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), _stream(), ctypes.byref(P.handle),

@@ -1,0 +1,132 @@
+"""The Woodbury merge (low-rank sibling blocks, lsh_desc.merge): the plan's
+low-rank factors of G_ab, and the factor and apply built on them, against
+the oracle's Woodbury build, the dense LU and the Schur-form factor.
+
+Tolerances: G_ab - L R^T is a row-ID error, bounded like the compression's
+(a small multiple of tol ||G_ab||_F); full-rank factors (tol = 0) are exact,
+so M equals the dense LU solution to 1e-11 (FP64) / 2e-5 (FP32); against
+the oracle at tol 1e-8 both sides are O(tol) approximations with different
+(tied) pivots, as for the Schur form.
+"""
+import numpy as np
+import pytest
+
+from oracle import dense, hbs
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8])
+def test_sibling_block_lowrank_factors(tol):
+    from paper_2007_12718_amd import lsh
+    n, kappa = 64, 2 * np.pi * 6
+    P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=tol, proxy_width=2 if tol > 1e-6 else 3, prec="fp64",
+                 merge="lowrank")
+    L = P.ranks()[0]
+    for l in range(L):
+        G = P.block(l).cpu().numpy()
+        LR = P.lowrank(l)
+        assert LR is not None, l
+        Lm, Rt = (t.cpu().numpy() for t in LR)
+        c, r = Lm.shape
+        assert Rt.shape == (r, c) and 1 <= r < c
+        assert np.linalg.norm(G - Lm @ Rt) <= 10 * tol * np.linalg.norm(G), l
+        # R^T holds r rows of G_ab (the skeleton), and L is the identity on them
+        rows = [int(np.argmin(np.abs(G - Rt[i]).sum(axis=1))) for i in range(r)]
+        assert np.array_equal(G[rows], Rt)
+        assert np.abs(Lm[rows] - np.eye(r)).max() <= 1e-12
+        # rank within a few pivots of the oracle's CPQR row ID at the same tolerance
+        r_or = hbs.row_id(G, tol)[0].size
+        assert abs(r - r_or) <= max(2, r_or // 10), (l, r, r_or)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_lowrank_full_rank_equals_dense(prec, tol):
+    from paper_2007_12718_amd import lsh
+    w = synth.small(32)
+    sig, _ = dense.DenseSolver(w.n, w.kappa, 4, w.b).solve(w.u_inc)
+    P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=0.0, proxy_width=2, prec=prec, merge="lowrank")
+    assert all(P.lowrank(l) is not None for l in range(P.ranks()[0]))
+    F = lsh.Factor(P, cuda(w.b))
+    f = dense.rhs(w.b, w.u_inc, w.kappa).reshape(1, w.n, w.n)
+    assert rel(F.apply_precond(cuda(f)).cpu().numpy(), sig[0]) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lowrank_inverse_matches_oracle(prec):
+    from paper_2007_12718_amd import lsh
+    w = synth.small(32)
+    tol = 1e-8
+    P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=tol, proxy_width=3, prec=prec, merge="lowrank")
+    M = hbs.Inverse(hbs.Compression(w.n, w.kappa, 8, tol, 3), w.b, lowrank_tol=tol)
+    F = lsh.Factor(P, cuda(w.b))
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, w.n, w.n)) + 1j * rng.standard_normal((2, w.n, w.n))
+    q = F.apply_precond(cuda(x)).cpu().numpy()
+    qt = F.apply_precond(cuda(x), transpose=True).cpu().numpy()
+    for r in range(2):
+        assert rel(q[r], M.apply(x[r])) <= (1e-6 if prec == "fp64" else 2e-5)
+        assert rel(qt[r], M.apply_transpose(x[r])) <= (1e-6 if prec == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_lowrank_transpose_dot_product(prec, tol):
+    from paper_2007_12718_amd import lsh
+    n, kappa = 64, 2 * np.pi * 6
+    b = synth.bumps(n, np.random.default_rng(5))
+    P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, merge="lowrank")
+    F = lsh.Factor(P, cuda(b))
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))
+    y = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))
+    My = F.apply_precond(cuda(y)).cpu().numpy()
+    MTx = F.apply_precond(cuda(x), transpose=True).cpu().numpy()
+    for r in range(3):
+        a, c = np.sum(x[r] * My[r]), np.sum(MTx[r] * y[r])
+        assert abs(a - c) <= tol * abs(a)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lowrank_and_schur_solves_match_dense(prec):
+    """Both merge forms precondition FGMRES to the same dense LU answer; the
+    two preconditioners differ by O(tol)."""
+    from paper_2007_12718_amd import lsh
+    n, kappa = 64, 2 * np.pi * 6
+    b = synth.bumps(n, np.random.default_rng(64))
+    uinc = np.stack([synth.plane_wave(n, kappa, t) for t in (0.0, 1.0)])
+    sig, _ = dense.DenseSolver(n, kappa, 6, b).solve(uinc)
+    x = np.random.default_rng(1).standard_normal((1, n, n)) + 0j
+    out, its = {}, {}
+    for merge in ("schur", "lowrank"):
+        P, F = lsh.build(n, kappa, cuda(b), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, merge=merge)
+        s, _, info, rc = F.solve(cuda(uinc), tol=1e-13, maxit=60)
+        assert rc == 0 and info.true_residual < 1e-13
+        for r in range(2):
+            assert rel(s.cpu().numpy()[r], sig[r]) <= 1e-9
+        out[merge] = F.apply_precond(cuda(x)).cpu().numpy()
+        its[merge] = info.iterations
+    assert rel(out["lowrank"], out["schur"]) <= 1e-2
+    assert its["lowrank"] <= its["schur"] + 2
+
+
+def test_batch_factor_with_lowrank_levels_equals_separate():
+    from paper_2007_12718_amd import lsh
+    ws = synth.batched(3, seed0=77)
+    plans = [lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=2, prec="fp32",
+                      merge="lowrank") for w in ws]
+    bs = [cuda(w.b) for w in ws]
+    fb = lsh.batch_factor(plans, bs)
+    for P, b, F, w in zip(plans, bs, fb, ws):
+        F1 = lsh.Factor(P, b)
+        x = np.random.default_rng(w.n).standard_normal((1, w.n, w.n)) + 0j
+        assert np.array_equal(F.apply_precond(cuda(x)).cpu().numpy(), F1.apply_precond(cuda(x)).cpu().numpy())
