@@ -6,8 +6,12 @@ TEST INFRASTRUCTURE.  Plain numpy/scipy transcription of the paper's method:
   whole grid; cuts alternate vertical (split x1) at even levels and horizontal
   (split x2) at odd levels; children of box t on level l are boxes 2t (the
   half with the smaller coordinates, alpha) and 2t+1 (beta) on level l+1.
-* Compression (Sec. 3.2): only the b-independent 4th-order matrix G of
-  eq. (Gmat) is compressed.  Leaf row ID of G(I_tau, proxy ring) (eqs.
+* Compression (Sec. 3.2): only the b-independent matrix G of eq. (Gmat) is
+  compressed: 4th order for the preconditioner; the direct-solver
+  experiments (Sec. 6) compress higher orders, whose correction stencils
+  reach up to 3 lattice steps, so every block (leaf, proxy, sibling) takes
+  the corrected entries, and the proxy ring must be at least as wide as the
+  stencil.  Leaf row ID of G(I_tau, proxy ring) (eqs.
   (leafid), (proxy)); parent row ID of G([J_alpha, J_beta], proxy ring)
   (eq. (parentid)); sibling blocks G_ab = G(J_alpha, J_beta) (eq. (sibint)).
   Translation invariance: one ID per level, done on box 0 in box-local
@@ -105,11 +109,14 @@ class Compression:
     """Per-level shared factors {J_l, U_l, G_ab,l} and the leaf block of G."""
 
     def __init__(self, n: int, kappa: float, leaf: int, tol: float, w: int,
-                 levels: int | None = None):
+                 levels: int | None = None, order: int = 4):
         self.tree = T = Tree(n, leaf, levels)
-        self.n, self.kappa, self.tol, self.w = n, kappa, tol, w
+        self.n, self.kappa, self.tol, self.w, self.order = n, kappa, tol, w, order
         self.h = 1.0 / n
-        self.tau0 = quad.correction_weights(4, kappa * self.h)[(0, 0)]
+        self.tau = quad.correction_weights(order, kappa * self.h)
+        reach = max(max(abs(a), abs(b)) for a, b in self.tau)
+        if reach > w:
+            raise ValueError(f"order-{order} stencil reaches {reach} > proxy width {w}")
         L = T.L
         self.cand = {}   # level -> candidate rows (box-local lattice coords)
         self.skel = {}   # level -> skeleton coords (box-local)
@@ -140,14 +147,17 @@ class Compression:
         self.Gleaf = self.gblock(self.cand[L], self.cand[L])
 
     def gblock(self, rows, cols):
-        """4th-order G entries between lattice points (eq. (Gmat))."""
+        """Order-p entries h^2 (G(h|d|) [d != 0] + tau_d), d = col - row (eq. (Gmat))."""
         rows = np.asarray(rows).reshape(-1, 2)
         cols = np.asarray(cols).reshape(-1, 2)
-        d = np.hypot(rows[:, None, 0] - cols[None, :, 0], rows[:, None, 1] - cols[None, :, 1])
-        G = np.empty(d.shape, dtype=complex)
+        dx = cols[None, :, 0] - rows[:, None, 0]
+        dy = cols[None, :, 1] - rows[:, None, 1]
+        d = np.hypot(dx, dy)
+        G = np.zeros(d.shape, dtype=complex)
         nz = d > 0
         G[nz] = quad.green(self.kappa, self.h * d[nz])
-        G[~nz] = self.tau0
+        for (ox, oy), t in self.tau.items():
+            G[(dx == ox) & (dy == oy)] += t
         return self.h * self.h * G
 
     def ranks(self):

@@ -147,7 +147,7 @@ def test_table1_proxy_errors():
             kappa, h = 2 * np.pi, lam_box / box
             C = hbs.Compression.__new__(hbs.Compression)
             C.kappa, C.h = kappa, h
-            C.tau0 = quad.correction_weights(4, kappa * h)[(0, 0)]
+            C.tau = quad.correction_weights(4, kappa * h)
             iy, ix = np.meshgrid(np.arange(box), np.arange(box), indexing="ij")
             I = np.stack([ix.ravel() + o, iy.ravel() + o], 1)
             jy, jx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
@@ -196,3 +196,35 @@ def test_woodbury_inverse_full_rank_and_truncated(case32):
         assert all(ranks[l] < C.Gab[l].shape[0] for l in ranks)
         err = np.linalg.norm(Mw.apply(f) - q0) / np.linalg.norm(q0)
         assert 1e-3 * eps < err <= 3 * eps, (eps, err)
+
+
+@pytest.mark.parametrize("order", [6, 10])
+def test_order_p_full_rank_inverse_equals_dense_lu(case32, order):
+    """Direct-solver mode: the HBS of the order-p matrix (corrected entries in
+    the leaf, sibling and proxy blocks) in full-rank form is exact block
+    elimination of the order-p dense matrix."""
+    w, _ = case32
+    D = dense.DenseSolver(w.n, w.kappa, order, w.b)
+    C = hbs.Compression(w.n, w.kappa, 8, 0.0, 3, order=order)
+    sig, _ = D.solve(w.u_inc)
+    q = hbs.Inverse(C, w.b).apply(dense.rhs(w.b, w.u_inc, w.kappa))
+    assert np.linalg.norm(q - sig[0]) <= 1e-12 * np.linalg.norm(sig[0])
+
+
+def test_order10_compressed_matvec_and_direct_solve(case32):
+    """At tol 1e-10 with a 3-layer proxy ring (the 10th-order stencil's
+    reach) the compressed order-10 matrix is accurate to the tolerance and
+    its HBS inverse solves the order-10 system directly; a ring narrower
+    than the stencil is refused."""
+    w, _ = case32
+    tol = 1e-10
+    D = dense.DenseSolver(w.n, w.kappa, 10, w.b)
+    C = hbs.Compression(w.n, w.kappa, 8, tol, 3, order=10)
+    x = np.random.default_rng(3).standard_normal(w.n ** 2) + 0j
+    ref = D.K @ x
+    assert np.linalg.norm(C.matvec(x) - ref) <= 10 * tol * np.linalg.norm(ref)
+    sig, _ = D.solve(w.u_inc)
+    q = hbs.Inverse(C, w.b).apply(dense.rhs(w.b, w.u_inc, w.kappa))
+    assert np.linalg.norm(q - sig[0]) <= 1e-8 * np.linalg.norm(sig[0])
+    with pytest.raises(ValueError):
+        hbs.Compression(w.n, w.kappa, 8, tol, 2, order=10)
