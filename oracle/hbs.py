@@ -133,7 +133,7 @@ class Compression:
                     cx, cy, _, _ = T.box(lev + 1, c)
                     parts.append(self.skel[lev + 1] + np.array([cx - ox, cy - oy]))
                 cand = np.concatenate(parts)
-            A = self.gblock(cand, proxy_ring(sx, sy, w))
+            A = self.proxy_block(cand, proxy_ring(sx, sy, w))
             J, U = row_id(A, tol)
             self.cand[lev], self.J[lev], self.U[lev] = cand, J, U
             self.skel[lev] = cand[J]
@@ -159,6 +159,23 @@ class Compression:
         for (ox, oy), t in self.tau.items():
             G[(dx == ox) & (dy == oy)] += t
         return self.h * self.h * G
+
+    def proxy_block(self, rows, ring):
+        """Columns whose span must hold every row of the box's off-diagonal
+        block: plain G on the ring (Green's representation of all sources
+        beyond the stencil's reach) and, for orders above 4, the corrected
+        entries against the ring points themselves, which are the actual
+        near neighbours (the ring is at least as wide as the stencil)."""
+        A = self.gblock(rows, ring)
+        if self.order == 4:
+            return A
+        tau = self.tau
+        self.tau = {(0, 0): tau[(0, 0)]}
+        try:
+            G = self.gblock(rows, ring)
+        finally:
+            self.tau = tau
+        return np.hstack([G, A])
 
     def ranks(self):
         return {lev: self.U[lev].shape[1] for lev in self.U}
