@@ -80,6 +80,11 @@ typedef struct {
   int proxy_width;  /* layers of proxy points around each box (1..3) */
   int hbs_prec;     /* LSH_FP64 or LSH_FP32: precision of factor and apply */
   int merge;        /* LSH_MERGE_*: form of the merge inverses X_tau (below) */
+  int hbs_order;    /* correction order of the compressed matrix: 0 or 4 (the 4th-order
+                       preconditioner, Sec. 5), or 6, 8, 10 (direct-solver mode, Sec. 6:
+                       the HBS of that order's matrix, used with or without GMRES; its
+                       correction stencil reaches 1, 2, 3 lattice steps and proxy_width
+                       must be at least that) */
 } lsh_desc;
 
 /* Merge inverses X_tau of Algorithm 1 (eq. (localsol)).  SCHUR inverts the

@@ -487,7 +487,7 @@ __global__ void k_scatter_U(z64* U, int k, const int* piv, const int* rest, int 
 // pivot count, done flag) lives on the device: the host queues steps in
 // batches and reads the done flag once per batch; a step queued after the
 // end returns at entry.
-constexpr int BP_B = 48, BP_NP = 32, BP_KC = 128, BP_KCS = 64, BP_SUB = 32, BP_SEL = 4096;
+constexpr int BP_B = 48, BP_NP = 32, BP_KC = 128, BP_KCS = 64, BP_SUB = 32, BP_SEL = 16384;
 // state words (int): 0 rank j, 1 done, 2 pivots of this step, 3 candidates,
 // 4..5 dout (double), 6 error flag, 8..8+BP_B candidate rows, 120..121 the
 // stopping threshold thr2 (double)
@@ -510,13 +510,20 @@ __global__ __launch_bounds__(1024) void k_bp_thr2(const double* d, int m, double
   if (threadIdx.x == 0) reinterpret_cast<double*>(st + BPS_THR)[0] = tol2 * part[0];
 }
 
+// selection key of candidate row i: the Schur diagonal's bits above the
+// index field, then the complemented index (ties go to the lower row)
+constexpr unsigned BP_IDX = 0x3FFF;  // index field: rows < BP_SEL
+static_assert(BP_SEL <= BP_IDX + 1, "key index field");
 __device__ __forceinline__ unsigned long long bp_key(double d, int i) {
-  return d > 0.0 ? (((unsigned long long)__double_as_longlong(d) & ~0xFFFull) | (unsigned)(0xFFF - i)) : 0ull;
+  return d > 0.0 ? (((unsigned long long)__double_as_longlong(d) & ~(unsigned long long)BP_IDX) | (BP_IDX - i))
+                 : 0ull;
 }
 
 // Candidates: the BP_B largest keys (unchosen rows, d > 0) by an 8-pass
 // most-significant-digit radix selection of the BP_B-th largest key, then
 // the <= BP_B keys at or above it, sorted descending.
+// KPT keys per thread: m <= 1024 KPT
+template <int KPT>
 __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* chosen, int m, int* st) {
   __shared__ unsigned int hist[256];
   __shared__ unsigned long long s_prefix, s_mask;
@@ -538,10 +545,10 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
     }
     if (jn >= m) return;
   }
-  unsigned long long key[BP_SEL / 1024];
+  unsigned long long key[KPT];
   int nz = 0;
 #pragma unroll
-  for (int r = 0; r < BP_SEL / 1024; ++r) {
+  for (int r = 0; r < KPT; ++r) {
     const int i = tid + r * 1024;
     key[r] = (i < m && !chosen[i]) ? bp_key(d[i], i) : 0ull;
     nz += key[r] != 0;
@@ -562,7 +569,7 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
       __syncthreads();
       const unsigned long long pre = s_prefix, msk = s_mask;
 #pragma unroll
-      for (int r = 0; r < BP_SEL / 1024; ++r)
+      for (int r = 0; r < KPT; ++r)
         if (key[r] && (key[r] & msk) == pre) atomicAdd(&hist[(key[r] >> sh) & 255], 1u);
       __syncthreads();
       if (wave == 0) {
@@ -597,7 +604,7 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
   // gather the candidates and the largest key below them
   unsigned long long below = 0;
 #pragma unroll
-  for (int r = 0; r < BP_SEL / 1024; ++r) {
+  for (int r = 0; r < KPT; ++r) {
     if (key[r] >= thr && key[r]) {
       const int slot = atomicAdd(&s_cnt, 1);
       if (slot < 64) ck[slot] = key[r];
@@ -623,14 +630,14 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
         const bool takeMax = (up == lower);
         k = takeMax ? (o > k ? o : k) : (o < k ? o : k);
       }
-    const int row = k ? 0xFFF - (int)(k & 0xFFF) : -1;
+    const int row = k ? (int)(BP_IDX - (unsigned)(k & BP_IDX)) : -1;
     if (lane < BP_B) st[BPS_CAND + lane] = row;
     int valid = (lane < BP_B && row >= 0 && d[row] > thr2) ? 1 : 0;
     for (int off = 32; off > 0; off >>= 1) valid += __shfl_xor(valid, off);
     if (lane == 0) {
       st[BPS_NC] = valid;
       const unsigned long long kb = s_below;
-      reinterpret_cast<double*>(st + BPS_DOUT)[0] = kb ? d[0xFFF - (int)(kb & 0xFFF)] : 0.0;
+      reinterpret_cast<double*>(st + BPS_DOUT)[0] = kb ? d[BP_IDX - (unsigned)(kb & BP_IDX)] : 0.0;
       if (valid == 0) st[BPS_DONE] = 1;
     }
   }
@@ -1063,7 +1070,7 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
 
 int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws) {
   LSH_REQUIRE(alpha > 0.0 && alpha <= 1.0, -1, "row ID: alpha must lie in (0, 1]");
-  LSH_REQUIRE(m <= BP_SEL, -6, "row ID: more than 4096 candidate rows in one level");
+  LSH_REQUIRE(m <= BP_SEL, -6, "row ID: more than 16384 candidate rows in one level");
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t bytes) { char* r = p; p += ((bytes + 255) / 256) * 256; return (void*)r; };
   const size_t mp = (size_t)m + BP_KC;
@@ -1102,7 +1109,9 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
     for (int b = 0; b < batch; ++b) {
       {
         ProfScope ps("bp_select", s, 16.0 * m);
-        hipLaunchKernelGGL(k_bp_select, dim3(1), dim3(1024), 0, s, d, chosen, m, st);
+        if (m <= 4096) hipLaunchKernelGGL(k_bp_select<4>, dim3(1), dim3(1024), 0, s, d, chosen, m, st);
+        else if (m <= 8192) hipLaunchKernelGGL(k_bp_select<8>, dim3(1), dim3(1024), 0, s, d, chosen, m, st);
+        else hipLaunchKernelGGL(k_bp_select<BP_SEL / 1024>, dim3(1), dim3(1024), 0, s, d, chosen, m, st);
       }
       LSH_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_bp_sc, dim3(nchS, 4), dim3(256), 0, s, Lt, m, st, partS);

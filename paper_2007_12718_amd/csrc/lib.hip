@@ -69,8 +69,11 @@ struct lsh_plan_s {
   std::vector<Level> lev;
   std::vector<I2> leaf_origin_h, leaf_pts_h;
   DevBuf leaf_origin, leaf_pts;
-  DevBuf table;
+  DevBuf table;   // 4th-order offset table (operator circulant, inspection)
+  DevBuf htable;  // offset table of the compressed matrix when hbs_order > 4
   DevBuf Gleaf64, Gleaf32;
+  int hbs_order = 4;
+  const z64* hbs_table() const { return htable.p ? htable.as<z64>() : table.as<z64>(); }
   ConvOperator op;
   std::vector<StencilEntry> st4;
   double tau0_re = 0, tau0_im = 0;
@@ -172,6 +175,11 @@ void validate(const lsh_desc& d) {
   LSH_REQUIRE(d.proxy_width >= 1 && d.proxy_width <= 3, LSH_ERR_INVALID_ARG, "proxy_width must be 1..3");
   LSH_REQUIRE(d.hbs_prec == LSH_FP64 || d.hbs_prec == LSH_FP32, LSH_ERR_INVALID_ARG, "hbs_prec");
   LSH_REQUIRE(d.merge >= LSH_MERGE_AUTO && d.merge <= LSH_MERGE_LOWRANK, LSH_ERR_INVALID_ARG, "merge");
+  LSH_REQUIRE(d.hbs_order == 0 || d.hbs_order == 4 || d.hbs_order == 6 || d.hbs_order == 8 || d.hbs_order == 10,
+              LSH_ERR_INVALID_ARG, "hbs_order must be 0, 4, 6, 8 or 10");
+  const int reach = d.hbs_order > 4 ? d.hbs_order / 2 - 2 : 0;  // stencil reach of order 6/8/10: 1/2/3
+  LSH_REQUIRE(d.proxy_width >= reach, LSH_ERR_INVALID_ARG,
+              "proxy_width must reach the correction stencil of hbs_order (6: 1, 8: 2, 10: 3)");
 }
 
 // Row ID A ~= U A[J, :] of a device matrix A (m x np, FP64; overwritten) at
@@ -235,9 +243,19 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     return;
   }
   AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
-  AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
-  gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
-  lv.k = row_id_matrix(P, A.as<z64>(), m, np, lv.J, lv.U64, s);
+  if (P.hbs_order == 4) {
+    AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
+    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
+    lv.k = row_id_matrix(P, A.as<z64>(), m, np, lv.J, lv.U64, s);
+    return;
+  }
+  // order > 4: the rows must also span the corrected entries against the
+  // ring's points (the actual near neighbours, within the stencil's reach),
+  // beside plain G on the ring (the representation of everything farther)
+  AsyncBuf A(sizeof(z64) * (size_t)m * 2 * np, s);
+  gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), 2 * np);
+  gather_table(s, P.hbs_table(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>() + np, 2 * np);
+  lv.k = row_id_matrix(P, A.as<z64>(), m, 2 * np, lv.J, lv.U64, s);
 }
 
 // Plan in three phases so that the factor can follow it level by level:
@@ -263,6 +281,14 @@ void plan_init(lsh_plan_s& P, hipStream_t s) {
   P.tau0_im = P.st4[0].im;
   P.table.alloc(sizeof(z64) * (size_t)(P.D + 1) * (P.D + 1));
   build_offset_table(s, P.table.as<z64>(), P.D, d.h, d.kappa, P.tau0_re, P.tau0_im);
+  P.hbs_order = d.hbs_order > 4 ? d.hbs_order : 4;
+  P.htable.release();
+  if (P.hbs_order > 4) {  // direct-solver mode: the compressed matrix carries the order-p corrections
+    const std::vector<StencilEntry> st = correction_stencil(P.hbs_order, d.kappa * d.h);
+    P.htable.alloc(sizeof(z64) * (size_t)(P.D + 1) * (P.D + 1));
+    build_offset_table(s, P.htable.as<z64>(), P.D, d.h, d.kappa, st[0].re, st[0].im);
+    add_table_stencil(s, P.htable.as<z64>(), P.D, d.h, st);
+  }
   // leaves
   P.leaf_origin_h.resize(P.nleaf);
   for (int t = 0; t < P.nleaf; ++t) {
@@ -282,7 +308,7 @@ void plan_init(lsh_plan_s& P, hipStream_t s) {
     box_of(d.n, l, 0, ox, oy, P.lev[l].sx, P.lev[l].sy);
   }
   P.Gleaf64.alloc(sizeof(z64) * (size_t)P.mL * P.mL);
-  gather_table(s, P.table.as<z64>(), P.D, P.leaf_pts.as<I2>(), P.mL, P.leaf_pts.as<I2>(), P.mL, P.Gleaf64.as<z64>(),
+  gather_table(s, P.hbs_table(), P.D, P.leaf_pts.as<I2>(), P.mL, P.leaf_pts.as<I2>(), P.mL, P.Gleaf64.as<z64>(),
                P.mL);
   if (d.hbs_prec == LSH_FP32) {
     P.Gleaf32.alloc(sizeof(c32) * (size_t)P.mL * P.mL);
@@ -356,7 +382,7 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
   z64* Pm = lv.Pm64.as<z64>();
   z64* Qm = lv.Qm64.as<z64>();
   LSH_HIP(hipMemcpyAsync(Pm, U.p, sizeof(z64) * cr, hipMemcpyDeviceToDevice, s));       // L
-  gather_table(s, P.table.as<z64>(), P.D, dr.as<I2>(), r, db.as<I2>(), c, Qm + cr, c);  // R^T = G_ab[J, :]
+  gather_table(s, P.hbs_table(), P.D, dr.as<I2>(), r, db.as<I2>(), c, Qm + cr, c);  // R^T = G_ab[J, :]
   ctranspose<double>(s, Pm, c, r, Qm);                                                 // L^T
   ctranspose<double>(s, Qm + cr, r, c, Pm + cr);                                       // R
   if (f32) {
@@ -391,7 +417,7 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
     AsyncBuf da = upload_async(ra, s), db = upload_async(rb, s);
     const long cc = (long)lv.c * lv.c;
     lv.Gab64.alloc(sizeof(z64) * cc);
-    gather_table(s, P.table.as<z64>(), P.D, da.as<I2>(), lv.c, db.as<I2>(), lv.c, lv.Gab64.as<z64>(), lv.c);
+    gather_table(s, P.hbs_table(), P.D, da.as<I2>(), lv.c, db.as<I2>(), lv.c, lv.Gab64.as<z64>(), lv.c);
     lv.Gabt64.alloc(sizeof(z64) * cc);
     ctranspose<double>(s, lv.Gab64.as<z64>(), lv.c, lv.c, lv.Gabt64.as<z64>());
     if (f32) {

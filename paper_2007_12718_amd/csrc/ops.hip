@@ -32,6 +32,32 @@ void build_offset_table(hipStream_t s, z64* T, int D, double h, double kappa, do
   LSH_LAUNCH_CHECK();
 }
 
+__global__ void k_table_add(z64* T, int D, const int* dxy, const z64* w, int cnt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cnt) return;
+  const int dx = dxy[2 * k], dy = dxy[2 * k + 1];
+  T[(long)dy * (D + 1) + dx] = T[(long)dy * (D + 1) + dx] + w[k];
+}
+
+void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector<StencilEntry>& stencil) {
+  std::vector<int> dxy;
+  std::vector<z64> wv;
+  for (auto& e : stencil) {  // one representative per offset (|dx|, |dy|): the stencil is symmetric
+    if (e.dx < 0 || e.dy < 0 || (e.dx == 0 && e.dy == 0) || e.dx > D || e.dy > D) continue;
+    dxy.push_back(e.dx);
+    dxy.push_back(e.dy);
+    wv.push_back(mk(h * h * e.re, h * h * e.im));
+  }
+  if (wv.empty()) return;
+  AsyncBuf ddxy(sizeof(int) * dxy.size(), s), dw(sizeof(z64) * wv.size(), s);
+  LSH_HIP(hipMemcpyAsync(ddxy.p, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
+  LSH_HIP(hipMemcpyAsync(dw.p, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_table_add, dim3(ceil_div((int)wv.size(), 64)), dim3(64), 0, s, T, D, ddxy.as<int>(),
+                     dw.as<z64>(), (int)wv.size());
+  LSH_LAUNCH_CHECK();
+  LSH_HIP(hipStreamSynchronize(s));  // the host staging vectors die here
+}
+
 // ------------------------------------------------------------------- FFT
 void FFTPlan::init(int M_) {
   M = M_;

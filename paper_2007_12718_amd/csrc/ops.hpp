@@ -38,6 +38,9 @@ struct ConvOperator {
 // with T[0][0] = h^2 tau0 (the 4th-order centre correction).
 void build_offset_table(hipStream_t s, z64* T, int D, double h, double kappa, double tau0_re,
                         double tau0_im);
+// T[|dy|][|dx|] += h^2 tau for the stencil entries off the origin (the
+// order-p table; the origin value is set by build_offset_table)
+void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector<StencilEntry>& stencil);
 
 // ---- FGMRES vector kernels (deterministic fixed-order reductions)
 // out[v] = sum_i conj(V[v][i]) w[i], v < nv (V rows at stride ldv)

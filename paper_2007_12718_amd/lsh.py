@@ -34,7 +34,7 @@ EXPORTED = [
 class LshDesc(ctypes.Structure):
     _fields_ = [("n", c_int), ("h", c_double), ("x0", c_double), ("y0", c_double), ("kappa", c_double),
                 ("op_order", c_int), ("leaf", c_int), ("tol", c_double), ("proxy_width", c_int),
-                ("hbs_prec", c_int), ("merge", c_int)]
+                ("hbs_prec", c_int), ("merge", c_int), ("hbs_order", c_int)]
 
 
 MERGE = {"auto": 0, "schur": 1, "lowrank": 2}
@@ -144,10 +144,11 @@ class Plan:
     """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
 
     def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
-                 h=None, x0=-0.5, y0=-0.5, merge="auto", _create=True):
+                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, _create=True):
         self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
                             op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
-                            hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64, merge=MERGE[merge])
+                            hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64, merge=MERGE[merge],
+                            hbs_order=hbs_order)
         self.n = n
         self.h = self.desc.h
         self.kappa = kappa
@@ -326,10 +327,11 @@ class Factor:
 
 
 def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5,
-          merge="auto"):
+          merge="auto", hbs_order=4):
     """lsh_build: plan and factor pipelined by level; returns (Plan, Factor)."""
     import torch
-    P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge=merge, _create=False)
+    P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge=merge, hbs_order=hbs_order,
+             _create=False)
     fh = c_void_p()
     b = b.reshape(n, n).contiguous()
     _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), _stream(), ctypes.byref(P.handle),
