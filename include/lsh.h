@@ -85,6 +85,8 @@ typedef struct {
                        the HBS of that order's matrix, used with or without GMRES; its
                        correction stencil reaches 1, 2, 3 lattice steps and proxy_width
                        must be at least that) */
+  int plan_cache;   /* 1: take each level's row IDs from the process-wide plan cache
+                       when present and add the ones computed (lsh_plan_cache_*); 0: off */
 } lsh_desc;
 
 /* Merge inverses X_tau of Algorithm 1 (eq. (localsol)).  SCHUR inverts the
@@ -146,6 +148,24 @@ int lsh_plan_table(lsh_plan_t plan, int* D, void* out, void* stream);
  * L[J, :] = I) and R^T = G_ab[J, :] (device double2[r*c]).  Synchronises
  * the stream. */
 int lsh_plan_lowrank(lsh_plan_t plan, int level, int* c, int* r, void* L, void* Rt, void* stream);
+
+/* ---- plan cache: universal compression (Sec. 3.2 remark: the compression
+ * of G depends only on box size and kappa h, so it can be stored and reused)
+ * Plans created with desc.plan_cache = 1 look up every row ID (of a level's
+ * proxy matrix and of a sibling block) by box size, kappa h, tol,
+ * proxy_width, hbs_order and pivoting rule (LSH_ROWID, LSH_BP_ALPHA), and
+ * store the ones they compute; a hit copies the pivots and U instead of
+ * computing them, so later plans on other b, or on other grids with the same
+ * kappa h, skip the row IDs.  Entries live on the device they were made on.
+ * Not safe against a concurrent lsh_plan_cache_clear or _load. */
+int lsh_plan_cache_info(int* entries, size_t* device_bytes);
+int lsh_plan_cache_clear(void);
+/* host: writes every entry to a file (binary: pivots, candidates, U) /
+ * reads a file written by lsh_plan_cache_save into the cache of the current
+ * device (replacing equal keys).  Errors: LSH_ERR_INVALID_ARG for a file
+ * that cannot be opened or is not such a file. */
+int lsh_plan_cache_save(const char* path);
+int lsh_plan_cache_load(const char* path);
 
 /* ---- factor: Algorithm 1 (leaf inverses, scattering matrices, merges) ----
  * b: device double[n*n].  Errors: LSH_ERR_INPUT_NONFINITE (non-finite b),

@@ -24,6 +24,7 @@
 #include "blas.hpp"
 #include "hbs.hpp"
 #include "ops.hpp"
+#include "plancache.hpp"
 #include "prof.hpp"
 #include "weights.hpp"
 
@@ -235,6 +236,27 @@ int row_id_matrix(const lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& 
   return k;
 }
 
+// Cache key of a row ID (kind 0: a level's proxy matrix, 1: a sibling
+// block) of the box sx x sy: everything the pivots and U depend on.
+pcache::Key cache_key(const lsh_plan_s& P, int kind, int sx, int sy) {
+  pcache::Key k;
+  LSH_HIP(hipGetDevice(&k.dev));
+  k.kind = kind;
+  k.sx = sx;
+  k.sy = sy;
+  k.w = P.d.proxy_width;
+  k.order = P.hbs_order;
+  const double kh = P.d.kappa * P.d.h, tol = P.d.tol;
+  std::memcpy(&k.kh, &kh, sizeof(double));
+  std::memcpy(&k.tol, &tol, sizeof(double));
+  const char* e = std::getenv("LSH_ROWID");
+  const char* ea = std::getenv("LSH_BP_ALPHA");
+  const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
+  k.method = tol == 0 ? 0 : tol < 1e-7 ? 1 : (e && std::string(e) == "panel") ? 2 : 3;
+  if (k.method == 3) std::memcpy(&k.alpha, &alpha, sizeof(double));
+  return k;
+}
+
 // Row ID of the level's proxy matrix (FP64); fills lv.J (host) and lv.U64.
 void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
   const int m = lv.m, np = (int)prox.size();
@@ -242,20 +264,26 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     lv.k = row_id_matrix(P, nullptr, m, np, lv.J, lv.U64, s);
     return;
   }
+  pcache::Key key;
+  if (P.d.plan_cache) {
+    key = cache_key(P, 0, lv.sx, lv.sy);
+    if (pcache::find(key, lv.cand, lv.J, lv.k, lv.U64, s)) return;
+  }
   AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
   if (P.hbs_order == 4) {
     AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
     gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
     lv.k = row_id_matrix(P, A.as<z64>(), m, np, lv.J, lv.U64, s);
-    return;
+  } else {
+    // order > 4: the rows must also span the corrected entries against the
+    // ring's points (the actual near neighbours, within the stencil's reach),
+    // beside plain G on the ring (the representation of everything farther)
+    AsyncBuf A(sizeof(z64) * (size_t)m * 2 * np, s);
+    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), 2 * np);
+    gather_table(s, P.hbs_table(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>() + np, 2 * np);
+    lv.k = row_id_matrix(P, A.as<z64>(), m, 2 * np, lv.J, lv.U64, s);
   }
-  // order > 4: the rows must also span the corrected entries against the
-  // ring's points (the actual near neighbours, within the stencil's reach),
-  // beside plain G on the ring (the representation of everything farther)
-  AsyncBuf A(sizeof(z64) * (size_t)m * 2 * np, s);
-  gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), 2 * np);
-  gather_table(s, P.hbs_table(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>() + np, 2 * np);
-  lv.k = row_id_matrix(P, A.as<z64>(), m, 2 * np, lv.J, lv.U64, s);
+  if (P.d.plan_cache) pcache::insert(key, lv.cand, lv.J, m, lv.k, lv.U64, s);
 }
 
 // Plan in three phases so that the factor can follow it level by level:
@@ -364,10 +392,22 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
   std::vector<int> J;
   DevBuf U;
   int r = 0;
-  {
+  std::vector<I2> sk;  // the sibling skeletons: the cache entry's identity
+  pcache::Key key;
+  bool hit = false;
+  if (P.d.plan_cache && d.tol > 0) {
+    sk = lv.ra;
+    sk.insert(sk.end(), lv.rb.begin(), lv.rb.end());
+    int psx, psy, ox, oy;
+    box_of(d.n, l, 0, ox, oy, psx, psy);
+    key = cache_key(P, 1, psx, psy);
+    hit = pcache::find(key, sk, J, r, U, s);
+  }
+  if (!hit) {
     AsyncBuf A(sizeof(z64) * cc, s);
     LSH_HIP(hipMemcpyAsync(A.p, lv.Gab64.p, sizeof(z64) * cc, hipMemcpyDeviceToDevice, s));
     r = row_id_matrix(P, A.as<z64>(), c, c, J, U, s);
+    if (P.d.plan_cache && d.tol > 0) pcache::insert(key, sk, J, c, r, U, s);  // U = L: c x r
   }
   if (d.merge == LSH_MERGE_AUTO && 10 * r > 6 * c) return;
   const bool f32 = d.hbs_prec == LSH_FP32;
@@ -1459,6 +1499,36 @@ int lsh_plan_level(lsh_plan_t P, int level, int* m, int* k, int* J, int* cand, v
                            (hipStream_t)stream));
     LSH_HIP(hipStreamSynchronize((hipStream_t)stream));
   }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_cache_info(int* entries, size_t* device_bytes) {
+  API_BEGIN
+  pcache::info(entries, device_bytes);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_cache_clear(void) {
+  API_BEGIN
+  pcache::clear();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_cache_save(const char* path) {
+  API_BEGIN
+  LSH_REQUIRE(path, LSH_ERR_INVALID_ARG, "null path");
+  pcache::save(path);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_cache_load(const char* path) {
+  API_BEGIN
+  LSH_REQUIRE(path, LSH_ERR_INVALID_ARG, "null path");
+  pcache::load(path);
   return LSH_OK;
   API_END
 }

@@ -27,14 +27,15 @@ EXPORTED = [
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
     "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
     "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor", "lsh_profile_only",
-    "lsh_cache_trim", "lsh_plan_lowrank",
+    "lsh_cache_trim", "lsh_plan_lowrank", "lsh_plan_cache_info", "lsh_plan_cache_clear", "lsh_plan_cache_save",
+    "lsh_plan_cache_load",
 ]
 
 
 class LshDesc(ctypes.Structure):
     _fields_ = [("n", c_int), ("h", c_double), ("x0", c_double), ("y0", c_double), ("kappa", c_double),
                 ("op_order", c_int), ("leaf", c_int), ("tol", c_double), ("proxy_width", c_int),
-                ("hbs_prec", c_int), ("merge", c_int), ("hbs_order", c_int)]
+                ("hbs_prec", c_int), ("merge", c_int), ("hbs_order", c_int), ("plan_cache", c_int)]
 
 
 MERGE = {"auto": 0, "schur": 1, "lowrank": 2}
@@ -100,6 +101,12 @@ def lib():
         L.lsh_profile_names.argtypes = [ctypes.c_char_p, c_int]
         L.lsh_profile_only.argtypes = [ctypes.c_char_p]
         L.lsh_cache_trim.argtypes = [POINTER(ctypes.c_size_t)]
+        L.lsh_plan_lowrank.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_int), c_void_p, c_void_p,
+                                       c_void_p]
+        L.lsh_plan_cache_info.argtypes = [POINTER(c_int), POINTER(ctypes.c_size_t)]
+        L.lsh_plan_cache_clear.argtypes = []
+        L.lsh_plan_cache_save.argtypes = [ctypes.c_char_p]
+        L.lsh_plan_cache_load.argtypes = [ctypes.c_char_p]
         _lib = L
     return _lib
 
@@ -144,11 +151,11 @@ class Plan:
     """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
 
     def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
-                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, _create=True):
+                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, _create=True):
         self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
                             op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
                             hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64, merge=MERGE[merge],
-                            hbs_order=hbs_order)
+                            hbs_order=hbs_order, plan_cache=int(bool(plan_cache)))
         self.n = n
         self.h = self.desc.h
         self.kappa = kappa
@@ -327,11 +334,11 @@ class Factor:
 
 
 def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5,
-          merge="auto", hbs_order=4):
+          merge="auto", hbs_order=4, plan_cache=False):
     """lsh_build: plan and factor pipelined by level; returns (Plan, Factor)."""
     import torch
     P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge=merge, hbs_order=hbs_order,
-             _create=False)
+             plan_cache=plan_cache, _create=False)
     fh = c_void_p()
     b = b.reshape(n, n).contiguous()
     _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), _stream(), ctypes.byref(P.handle),
@@ -389,6 +396,25 @@ def lsh_profile_enable(on=True):
 def lsh_profile_only(prefix=None):
     """Record only the kernels whose name starts with prefix (None: all)."""
     _check(lib().lsh_profile_only(prefix.encode() if prefix else None))
+
+
+def plan_cache_info():
+    """(entries, device bytes) of the process-wide plan cache."""
+    n, b = c_int(0), ctypes.c_size_t(0)
+    _check(lib().lsh_plan_cache_info(ctypes.byref(n), ctypes.byref(b)))
+    return n.value, b.value
+
+
+def plan_cache_clear():
+    _check(lib().lsh_plan_cache_clear())
+
+
+def plan_cache_save(path):
+    _check(lib().lsh_plan_cache_save(str(path).encode()))
+
+
+def plan_cache_load(path):
+    _check(lib().lsh_plan_cache_load(str(path).encode()))
 
 
 def cache_trim():
