@@ -1780,6 +1780,167 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
 
 namespace {
 
+// Woodbury merge and scattering matrices of one aligned level step for the
+// instances in wact: the products of factor_merge_lowrank and of the
+// Woodbury branch of factor_scatter, each step one grouped launch over the
+// instances (same operands, shapes and order, so the same bits).
+void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>& wact, int dpt, hipStream_t s) {
+  const c32 one = mk<float>(1, 0), zero = mk<float>(0, 0), mone = mk<float>(-1, 0);
+  const int n_inst = (int)Fs.size();
+  std::vector<GemmItem> gi;
+  DevBuf gtab, itab;
+  auto run = [&] {
+    cgemm_grouped(s, gi, gtab);
+    gi.clear();
+  };
+  struct Lv {
+    int l, c, r, nb, k;
+    long cc, cr, rr, r2, w4;
+    const lsh_plan_s* P;
+    FactorData<float>* F;
+  };
+  std::vector<Lv> L;
+  std::vector<DevBuf> T(n_inst), info(n_inst);
+  for (int i : wact) {
+    const lsh_plan_s& P = *Fs[i]->plan;
+    const int l = P.L - dpt, c = P.lev[l].c, r = P.lev[l].wr;
+    Lv v{l, c, r, 1 << l, P.lev[l].k, (long)c * c, (long)c * r, (long)r * r, 2L * r, 4L * r * r, &P, &Fs[i]->f32};
+    FactorData<float>& F = *v.F;
+    F.wr[l] = r;
+    F.Pa[l].alloc(sizeof(c32) * v.nb * 2 * v.cr);
+    F.Ci[l].alloc(sizeof(c32) * v.nb * v.w4);
+    T[i].alloc(sizeof(c32) * v.nb * 3 * v.rr);
+    info[i].alloc(sizeof(int) * v.nb);
+    L.push_back(v);
+  }
+  auto each = [&](auto&& fn) {
+    for (size_t q = 0; q < wact.size(); ++q) fn(wact[q], L[q]);
+  };
+  auto ptrs = [&](int i, const Lv& v, c32*& Pst, c32*& W, c32*& Aw, c32*& Bw, c32*& C) {
+    Pst = v.F->Pa[v.l].as<c32>();
+    W = v.F->Ci[v.l].as<c32>();
+    Aw = T[i].as<c32>();
+    Bw = Aw + v.nb * v.rr;
+    C = Bw + v.nb * v.rr;
+  };
+  c32 *Pst, *W, *Aw, *Bw, *C;
+  each([&](int i, const Lv& v) {  // S_a L, S_b R
+    ptrs(i, v, Pst, W, Aw, Bw, C);
+    const c32* Sch = v.F->S[v.l + 1].as<c32>();
+    gi.push_back({v.c, v.r, v.c, one, zero, Sch, v.c, 2 * v.cc, OP_N, v.P->W<float>(v.l, 0), v.r, 0, OP_N, nullptr,
+                  0, 0, Pst, v.r, 2 * v.cr, v.nb, false});
+    gi.push_back({v.c, v.r, v.c, one, zero, Sch + v.cc, v.c, 2 * v.cc, OP_N, v.P->W<float>(v.l, 2), v.r, 0, OP_N,
+                  nullptr, 0, 0, Pst + v.cr, v.r, 2 * v.cr, v.nb, false});
+  });
+  run();
+  each([&](int i, const Lv& v) {  // Aw = R^T (S_b R), Bw = L^T (S_a L)
+    ptrs(i, v, Pst, W, Aw, Bw, C);
+    gi.push_back({v.r, v.r, v.c, one, zero, v.P->W<float>(v.l, 3), v.c, 0, OP_N, Pst + v.cr, v.r, 2 * v.cr, OP_N,
+                  nullptr, 0, 0, Aw, v.r, v.rr, v.nb, false});
+    gi.push_back({v.r, v.r, v.c, one, zero, v.P->W<float>(v.l, 1), v.c, 0, OP_N, Pst, v.r, 2 * v.cr, OP_N, nullptr,
+                  0, 0, Bw, v.r, v.rr, v.nb, false});
+  });
+  run();
+  each([&](int i, const Lv& v) {  // C = I - Bw Aw
+    ptrs(i, v, Pst, W, Aw, Bw, C);
+    gi.push_back({v.r, v.r, v.r, mone, zero, Bw, v.r, v.rr, OP_N, Aw, v.r, v.rr, OP_N, nullptr, 0, 0, C, v.r, v.rr,
+                  v.nb, true});
+  });
+  run();
+  {
+    std::vector<InvItem> inv;
+    each([&](int i, const Lv& v) {
+      ptrs(i, v, Pst, W, Aw, Bw, C);
+      inv.push_back({C, v.r, (long)v.r, v.rr, v.nb, info[i].as<int>()});
+    });
+    DevBuf ws(inverse_grouped_ws_bytes(inv));
+    inverse_grouped(s, inv, ws.p, itab);
+    LSH_HIP(hipStreamSynchronize(s));  // (ws dies here)
+  }
+  for (size_t q = 0; q < wact.size(); ++q)
+    LSH_REQUIRE(!check_info(info[wact[q]], L[q].nb, s), LSH_ERR_SINGULAR,
+                "singular merge matrix I - Bw Aw at level " + std::to_string(L[q].l) + " (instance " +
+                    std::to_string(wact[q]) + ")");
+  each([&](int i, const Lv& v) {  // W' = [[-Aw C, I + Aw C Bw], [C, -C Bw]]
+    ptrs(i, v, Pst, W, Aw, Bw, C);
+    ccopy2d<float>(s, v.r, v.r, C, v.r, v.rr, W + v.r * v.r2, v.r2, v.w4, v.nb);
+    gi.push_back({v.r, v.r, v.r, mone, zero, Aw, v.r, v.rr, OP_N, C, v.r, v.rr, OP_N, nullptr, 0, 0, W, v.r2, v.w4,
+                  v.nb, false});
+    gi.push_back({v.r, v.r, v.r, mone, zero, C, v.r, v.rr, OP_N, Bw, v.r, v.rr, OP_N, nullptr, 0, 0,
+                  W + v.r * v.r2 + v.r, v.r2, v.w4, v.nb, false});
+  });
+  run();
+  each([&](int i, const Lv& v) {
+    ptrs(i, v, Pst, W, Aw, Bw, C);
+    gi.push_back({v.r, v.r, v.r, mone, zero, W, v.r2, v.w4, OP_N, Bw, v.r, v.rr, OP_N, nullptr, 0, 0, W + v.r, v.r2,
+                  v.w4, v.nb, true});
+  });
+  run();
+  // scattering matrices (not at the root): X D U through W'
+  std::vector<DevBuf> A12(n_inst), Qb(n_inst);
+  std::vector<int> sc;
+  std::vector<Lv> SL;
+  for (size_t q = 0; q < wact.size(); ++q) {
+    const Lv& v = L[q];
+    if (v.l == 0) continue;
+    const int i = wact[q];
+    A12[i].alloc(sizeof(c32) * v.nb * 2 * (long)v.c * v.k);
+    Qb[i].alloc(sizeof(c32) * v.nb * 4 * (long)v.r * v.k);
+    v.F->S[v.l].alloc(sizeof(c32) * v.nb * (long)v.k * v.k);
+    sc.push_back(i);
+    SL.push_back(v);
+  }
+  if (sc.empty()) return;
+  auto each_s = [&](auto&& fn) {
+    for (size_t q = 0; q < sc.size(); ++q) {
+      const Lv& v = SL[q];
+      const int i = sc[q];
+      const long ck = (long)v.c * v.k, rk = (long)v.r * v.k;
+      c32* a = A12[i].as<c32>();
+      c32* qv = Qb[i].as<c32>();
+      fn(v, ck, rk, a, qv, qv + v.nb * 2 * rk);
+    }
+  };
+  each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
+    const c32* Sch = v.F->S[v.l + 1].as<c32>();
+    const c32* U1 = v.P->U<float>(v.l);
+    gi.push_back({v.c, v.k, v.c, one, zero, Sch, v.c, 2 * v.cc, OP_N, U1, v.k, 0, OP_N, nullptr, 0, 0, a, v.k,
+                  2 * ck, v.nb, false});
+    gi.push_back({v.c, v.k, v.c, one, zero, Sch + v.cc, v.c, 2 * v.cc, OP_N, U1 + ck, v.k, 0, OP_N, nullptr, 0, 0,
+                  a + ck, v.k, 2 * ck, v.nb, false});
+  });
+  run();
+  each_s([&](const Lv& v, long ck, long rk, c32* a, c32* qv, c32*) {
+    gi.push_back({v.r, v.k, v.c, one, zero, v.P->W<float>(v.l, 1), v.c, 0, OP_N, a, v.k, 2 * ck, OP_N, nullptr, 0,
+                  0, qv, v.k, 2 * rk, v.nb, false});
+    gi.push_back({v.r, v.k, v.c, one, zero, v.P->W<float>(v.l, 3), v.c, 0, OP_N, a + ck, v.k, 2 * ck, OP_N, nullptr,
+                  0, 0, qv + rk, v.k, 2 * rk, v.nb, false});
+  });
+  run();
+  each_s([&](const Lv& v, long, long rk, c32*, c32* qv, c32* yv) {
+    gi.push_back({2 * v.r, v.k, 2 * v.r, one, zero, v.F->Ci[v.l].as<c32>(), v.r2, v.w4, OP_N, qv, v.k, 2 * rk, OP_N,
+                  nullptr, 0, 0, yv, v.k, 2 * rk, v.nb, false});
+  });
+  run();
+  each_s([&](const Lv& v, long ck, long rk, c32* a, c32*, c32* yv) {
+    gi.push_back({v.c, v.k, v.r, mone, one, v.F->Pa[v.l].as<c32>(), v.r, v.cr, OP_N, yv, v.k, rk, OP_N, a, v.k, ck,
+                  a, v.k, ck, 2 * v.nb, false});
+  });
+  run();
+  each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
+    gi.push_back({v.k, v.k, v.c, one, zero, v.P->U<float>(v.l), v.k, 0, OP_T, a, v.k, 2 * ck, OP_N, nullptr, 0, 0,
+                  v.F->S[v.l].as<c32>(), v.k, (long)v.k * v.k, v.nb, false});
+  });
+  run();
+  each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
+    c32* S = v.F->S[v.l].as<c32>();
+    gi.push_back({v.k, v.k, v.c, one, one, v.P->U<float>(v.l) + ck, v.k, 0, OP_T, a + ck, v.k, 2 * ck, OP_N, S, v.k,
+                  (long)v.k * v.k, S, v.k, (long)v.k * v.k, v.nb, false});
+  });
+  run();
+  LSH_HIP(hipStreamSynchronize(s));  // scratch and tables die here
+}
+
 // Algorithm 1 for many instances at once (FP32 factors): the levels are
 // aligned from the leaves, and every step of a level (each product, the
 // inverses) is one grouped launch over the instances that have that level.
@@ -1845,14 +2006,10 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
   Yb.clear(); Zb.clear();
   // levels, aligned from the leaves
   for (int dpt = 1; dpt <= Lmax; ++dpt) {
-    std::vector<int> act, wact;  // Schur-form levels (grouped) and Woodbury levels (per instance)
+    std::vector<int> act, wact;  // Schur-form and Woodbury levels, each grouped
     for (int i = 0; i < n_inst; ++i)
       if (Fs[i]->plan->L - dpt >= 0) (Fs[i]->plan->lev[Fs[i]->plan->L - dpt].wr > 0 ? wact : act).push_back(i);
-    for (int i : wact) {
-      const int l = Fs[i]->plan->L - dpt;
-      factor_merge<float>(*Fs[i]->plan, Fs[i]->f32, l, s);
-      factor_scatter<float>(*Fs[i]->plan, Fs[i]->f32, l, s);
-    }
+    if (!wact.empty()) batch_lowrank_level(Fs, wact, dpt, s);
     if (act.empty()) {
       LSH_HIP(hipStreamSynchronize(s));
       continue;
