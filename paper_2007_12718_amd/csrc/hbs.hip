@@ -863,7 +863,11 @@ __global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, do
 // four depths in flight).  Four real products per complex step; the second
 // pivot tile is skipped when np <= 16.  Rows already chosen are computed too
 // (the new-columns kernel ignores them).
-constexpr int BP_WT_ROWS = 256;  // rows per workgroup: four waves of 64
+// rows per workgroup: four waves of 16 JT rows.  The MFMA work of a
+// workgroup, not the memory, bounds a launch here (FP64 16x16x4 at 64 cycles
+// a wave), and early steps have few depth chunks: small row blocks (JT = 1)
+// keep every unit busy then.
+constexpr int BP_WT_JT = 1, BP_WT_ROWS = 64 * BP_WT_JT;
 __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int m, const int* st, z64* part) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   __shared__ double Apr[BP_NP][BP_KC + 1], Api[BP_NP][BP_KC + 1];
@@ -881,49 +885,63 @@ __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int 
     Api[q][t] = -v.y;
   }
   __syncthreads();
-  const int i0 = blockIdx.x * BP_WT_ROWS + wave * 64, lr = lane & 15, lk = lane >> 4;
+  constexpr int JT = BP_WT_JT;
+  const int i0 = blockIdx.x * BP_WT_ROWS + wave * 16 * JT, lr = lane & 15, lk = lane >> 4;
   const bool two = np > 16;
-  d4 wr[2][4], wi[2][4];
+  d4 wr[2][JT], wi[2][JT];
 #pragma unroll
   for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
+    for (int jt = 0; jt < JT; ++jt) {
       wr[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
       wi[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
     }
-  auto loadB = [&](int s0, double (&br)[4], double (&bi)[4]) {
-    const int t = s0 + lk;
+  // B (the rows' factor entries) streams in stages of WT_DS depths: the next
+  // stage's loads are issued before the current stage's MFMAs, so that a
+  // stage of matrix work (WT_DS / 4 depth steps) covers the memory latency
+  constexpr int WT_DS = 16, WT_SUB = WT_DS / 4;
+  static_assert(BP_KC % WT_DS == 0, "stages tile the depth chunk");
+  auto loadB = [&](int s0, double (&br)[WT_SUB][JT], double (&bi)[WT_SUB][JT]) {
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
-      const int i = i0 + 16 * jt + lr;
-      const z64 v = (t < tn && i < m) ? Lt[(long)(t0 + t) * m + i] : mk(0.0, 0.0);
-      br[jt] = v.x;
-      bi[jt] = v.y;
+    for (int u = 0; u < WT_SUB; ++u) {
+      const int t = s0 + 4 * u + lk;
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const int i = i0 + 16 * jt + lr;
+        const z64 v = (t < tn && i < m) ? Lt[(long)(t0 + t) * m + i] : mk(0.0, 0.0);
+        br[u][jt] = v.x;
+        bi[u][jt] = v.y;
+      }
     }
   };
-  double br[4], bi[4];
+  double br[WT_SUB][JT], bi[WT_SUB][JT];
   loadB(0, br, bi);
-  for (int s0 = 0; s0 < tn; s0 += 4) {
-    double nbr[4], nbi[4];
-    loadB(s0 + 4, nbr, nbi);  // the next four depths in flight meanwhile
-    const int t = s0 + lk;    // (< BP_KC: s0 < tn <= BP_KC and s0 % 4 == 0)
+  for (int s0 = 0; s0 < tn; s0 += WT_DS) {
+    double nbr[WT_SUB][JT], nbi[WT_SUB][JT];
+    loadB(s0 + WT_DS, nbr, nbi);  // the next stage in flight meanwhile
 #pragma unroll
-    for (int qt = 0; qt < 2; ++qt) {
-      if (qt == 1 && !two) break;
-      const double ar = Apr[16 * qt + lr][t], ai = Api[16 * qt + lr][t], nai = -ai;
+    for (int u = 0; u < WT_SUB; ++u) {
+      const int t = s0 + 4 * u + lk;  // (< BP_KC: s0 <= BP_KC - WT_DS, BP_KC % WT_DS == 0)
 #pragma unroll
-      for (int jt = 0; jt < 4; ++jt) {
-        wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br[jt], wr[qt][jt], 0, 0, 0);
-        wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi[jt], wr[qt][jt], 0, 0, 0);
-        wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi[jt], wi[qt][jt], 0, 0, 0);
-        wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br[jt], wi[qt][jt], 0, 0, 0);
+      for (int qt = 0; qt < 2; ++qt) {
+        if (qt == 1 && !two) break;
+        const double ar = Apr[16 * qt + lr][t], ai = Api[16 * qt + lr][t], nai = -ai;
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br[u][jt], wr[qt][jt], 0, 0, 0);
+          wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi[u][jt], wr[qt][jt], 0, 0, 0);
+          wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi[u][jt], wi[qt][jt], 0, 0, 0);
+          wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br[u][jt], wi[qt][jt], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
-      br[jt] = nbr[jt];
-      bi[jt] = nbi[jt];
-    }
+    for (int u = 0; u < WT_SUB; ++u)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        br[u][jt] = nbr[u][jt];
+        bi[u][jt] = nbi[u][jt];
+      }
   }
   // accumulator register r of lane l holds the pivot row lk + 4 r of its tile
   z64* pc = part + (long)c * BP_NP * m;
@@ -931,7 +949,7 @@ __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int 
   for (int qt = 0; qt < 2; ++qt) {
     if (qt == 1 && !two) break;
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
+    for (int jt = 0; jt < JT; ++jt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int q = 16 * qt + lk + 4 * r, i = i0 + 16 * jt + lr;
