@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <condition_variable>
+#include <deque>
 #include <exception>
 #include <memory>
 #include <mutex>
@@ -76,6 +77,23 @@ struct lsh_plan_s {
   DevBuf Gleaf64, Gleaf32;
   int hbs_order = 4;
   const z64* hbs_table() const { return htable.p ? htable.as<z64>() : table.as<z64>(); }
+  // Scratch of the row IDs.  Stream-ordered frees of these large blocks
+  // (and hipFree, which synchronises the device) cost milliseconds per level
+  // in the middle of the build, so they stay allocated until the plan is
+  // built and then go back to the device cache (release_scratch, after the
+  // final synchronisation).
+  std::mutex scratch_mu;
+  std::deque<DevBuf> scratch;
+  void* scratch_buf(size_t bytes) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    scratch.emplace_back(bytes ? bytes : 1);
+    return scratch.back().p;
+  }
+  void release_scratch() {
+    mem::Recycle r;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    scratch.clear();
+  }
   ConvOperator op;
   std::vector<StencilEntry> st4;
   double tau0_re = 0, tau0_im = 0;
@@ -187,8 +205,7 @@ void validate(const lsh_desc& d) {
 // Row ID A ~= U A[J, :] of a device matrix A (m x np, FP64; overwritten) at
 // the plan's tolerance: J to the host, U (m x k) to a new device buffer;
 // returns k.
-int row_id_matrix(const lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64,
-                  hipStream_t s) {
+int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64, hipStream_t s) {
   if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all rows
     Jh.resize(m);
     for (int i = 0; i < m; ++i) Jh[i] = i;
@@ -197,19 +214,21 @@ int row_id_matrix(const lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& 
     U64 = upload(I, s);
     return m;
   }
-  AsyncBuf J(sizeof(int) * m, s), Ufull(sizeof(z64) * (size_t)m * m, s);
+  int* J = static_cast<int*>(P.scratch_buf(sizeof(int) * m));
+  z64* Ufull = static_cast<z64*>(P.scratch_buf(sizeof(z64) * (size_t)m * m));
   int k = 0;
   // Gram + pivoted Cholesky squares the conditioning: FP64 resolves the
   // stopping rule only while tol stays above ~1e-7; below that, CPQR.
   if (P.d.tol < 1e-7) {
     // ||A||_F for the stopping rule |R_kk| <= tol ||A||_F (computed on device)
-    AsyncBuf ws(rowid_cpqr_ws(m), s), kd(sizeof(int), s), fro(sizeof(z64), s), part(multidot_partial_bytes(1), s);
+    void* ws = P.scratch_buf(rowid_cpqr_ws(m));
+    AsyncBuf kd(sizeof(int), s), fro(sizeof(z64), s), part(multidot_partial_bytes(1), s);
     multidot(s, A, 0, 1, A, (long)m * np, fro.as<z64>(), part.as<z64>());
     z64 f2;
     LSH_HIP(hipMemcpyAsync(&f2, fro.p, sizeof(z64), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     const double thr = P.d.tol * std::sqrt(f2.x);
-    rowid_cpqr(s, A, m, np, thr, J.as<int>(), Ufull.as<z64>(), kd.as<int>(), ws.p);
+    rowid_cpqr(s, A, m, np, thr, J, Ufull, kd.as<int>(), ws);
     LSH_HIP(hipMemcpyAsync(&k, kd.p, sizeof(int), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
@@ -221,18 +240,15 @@ int row_id_matrix(const lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& 
     const bool block = !(e && std::string(e) == "panel");
     const char* ea = std::getenv("LSH_BP_ALPHA");
     const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
-    if (!block) {
-      AsyncBuf ws(rowid_gram_ws(m), s);
-      k = rowid_gram(s, A, m, np, P.d.tol, J.as<int>(), Ufull.as<z64>(), ws.p);
-    } else {
-      AsyncBuf ws(rowid_bp_ws(m), s);
-      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J.as<int>(), Ufull.as<z64>(), ws.p);
-    }
+    if (!block)
+      k = rowid_gram(s, A, m, np, P.d.tol, J, Ufull, P.scratch_buf(rowid_gram_ws(m)));
+    else
+      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, P.scratch_buf(rowid_bp_ws(m)));
   }
   Jh.resize(k);
-  LSH_HIP(hipMemcpyAsync(Jh.data(), J.p, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipMemcpyAsync(Jh.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
   U64.alloc(sizeof(z64) * (size_t)m * k);
-  LSH_HIP(hipMemcpyAsync(U64.p, Ufull.p, sizeof(z64) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
+  LSH_HIP(hipMemcpyAsync(U64.p, Ufull, sizeof(z64) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
   LSH_HIP(hipStreamSynchronize(s));
   return k;
 }
@@ -272,17 +288,17 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
   }
   AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
   if (P.hbs_order == 4) {
-    AsyncBuf A(sizeof(z64) * (size_t)m * np, s);
-    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), np);
-    lv.k = row_id_matrix(P, A.as<z64>(), m, np, lv.J, lv.U64, s);
+    z64* A = static_cast<z64*>(P.scratch_buf(sizeof(z64) * (size_t)m * np));
+    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A, np);
+    lv.k = row_id_matrix(P, A, m, np, lv.J, lv.U64, s);
   } else {
     // order > 4: the rows must also span the corrected entries against the
     // ring's points (the actual near neighbours, within the stencil's reach),
     // beside plain G on the ring (the representation of everything farther)
-    AsyncBuf A(sizeof(z64) * (size_t)m * 2 * np, s);
-    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>(), 2 * np);
-    gather_table(s, P.hbs_table(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A.as<z64>() + np, 2 * np);
-    lv.k = row_id_matrix(P, A.as<z64>(), m, 2 * np, lv.J, lv.U64, s);
+    z64* A = static_cast<z64*>(P.scratch_buf(sizeof(z64) * (size_t)m * 2 * np));
+    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A, 2 * np);
+    gather_table(s, P.hbs_table(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A + np, 2 * np);
+    lv.k = row_id_matrix(P, A, m, 2 * np, lv.J, lv.U64, s);
   }
   if (P.d.plan_cache) pcache::insert(key, lv.cand, lv.J, m, lv.k, lv.U64, s);
 }
@@ -405,9 +421,9 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
     hit = pcache::find(key, sk, J, r, U, s);
   }
   if (!hit) {
-    AsyncBuf A(sizeof(z64) * cc, s);
-    LSH_HIP(hipMemcpyAsync(A.p, lv.Gab64.p, sizeof(z64) * cc, hipMemcpyDeviceToDevice, s));
-    r = row_id_matrix(P, A.as<z64>(), c, c, J, U, s);
+    z64* A = static_cast<z64*>(P.scratch_buf(sizeof(z64) * cc));
+    LSH_HIP(hipMemcpyAsync(A, lv.Gab64.p, sizeof(z64) * cc, hipMemcpyDeviceToDevice, s));
+    r = row_id_matrix(P, A, c, c, J, U, s);
     if (P.d.plan_cache && d.tol > 0) pcache::insert(key, sk, J, c, r, U, s);  // U = L: c x r
   }
   if (d.merge == LSH_MERGE_AUTO && 10 * r > 6 * c) return;
@@ -488,6 +504,7 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
   plan_init(P, s);
   for (int l = P.L; l >= 0; --l) plan_level(P, l, s);
   plan_finish(P, s);
+  P.release_scratch();
 }
 
 // ------------------------------------------------------------ factor
@@ -1778,6 +1795,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   if (ferr) std::rethrow_exception(ferr);
   LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 2], 0));
   LSH_HIP(hipStreamSynchronize(s));
+  P->release_scratch();
   *plan = P.release();
   *factor = F.release();
   return LSH_OK;
