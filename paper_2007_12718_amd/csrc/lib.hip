@@ -530,6 +530,20 @@ struct FactorData {
   int vb_nrhs = 0;
   // singularity flags of the local inverses, read back once when the factor ends
   std::vector<AsyncBuf> info;  // stream-ordered: freeing them never waits for the device
+  // Temporaries of the build (products, inverse workspaces): held until the
+  // factor is built, then returned to the device cache (release_scratch,
+  // after the final synchronisation), since freeing large blocks mid-build
+  // stalls the enqueueing thread for milliseconds.
+  std::deque<DevBuf> scratch;
+  template <typename T = void>
+  T* scratch_buf(size_t bytes) {
+    scratch.emplace_back(bytes ? bytes : 1);
+    return static_cast<T*>(scratch.back().p);
+  }
+  void release_scratch() {
+    mem::Recycle r;
+    scratch.clear();
+  }
   std::vector<int> info_n;
   std::vector<std::string> info_what;
 };
@@ -581,19 +595,19 @@ void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipSt
   cplx<R>* X = F.X.template as<cplx<R>>();
   leaf_build<R>(s, X, P.Gleaf<R>(), mL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
   {
-    AsyncBuf ws(inverse_ws_bytes<R>(mL, nleaf), s);
+    void* ws = F.scratch_buf(inverse_ws_bytes<R>(mL, nleaf));
     F.info.emplace_back(sizeof(int) * nleaf, s);
     F.info_n.push_back(nleaf);
     F.info_what.push_back("singular leaf matrix I + B G");
-    inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws.p, F.info.back().template as<int>());
+    inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws, F.info.back().template as<int>());
   }
-  AsyncBuf Y(sizeof(cplx<R>) * (size_t)nleaf * mL * kL, s), Z(sizeof(cplx<R>) * (size_t)nleaf * mL * kL, s);
-  leaf_scale_U<R>(s, Y.template as<cplx<R>>(), P.U<R>(L), mL, kL, b, k2, P.leaf_origin.as<I2>(),
-                  P.leaf_pts.as<I2>(), nleaf, P.n);
-  cgemm<R>(s, mL, kL, mL, one, X, mL, (long)mL * mL, OP_N, Y.template as<cplx<R>>(), kL, (long)mL * kL, OP_N,
-           zero, nullptr, 0, 0, Z.template as<cplx<R>>(), kL, (long)mL * kL, nleaf);
+  cplx<R>* Y = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * (size_t)nleaf * mL * kL);
+  cplx<R>* Z = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * (size_t)nleaf * mL * kL);
+  leaf_scale_U<R>(s, Y, P.U<R>(L), mL, kL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
+  cgemm<R>(s, mL, kL, mL, one, X, mL, (long)mL * mL, OP_N, Y, kL, (long)mL * kL, OP_N, zero, nullptr, 0, 0, Z, kL,
+           (long)mL * kL, nleaf);
   F.S[L].alloc(sizeof(cplx<R>) * (size_t)nleaf * kL * kL);
-  cgemm<R>(s, kL, kL, mL, one, P.U<R>(L), kL, 0, OP_T, Z.template as<cplx<R>>(), kL, (long)mL * kL, OP_N, zero,
+  cgemm<R>(s, kL, kL, mL, one, P.U<R>(L), kL, 0, OP_T, Z, kL, (long)mL * kL, OP_N, zero,
            nullptr, 0, 0, F.S[L].template as<cplx<R>>(), kL, (long)kL * kL, nleaf);
 }
 
@@ -617,8 +631,7 @@ void factor_merge_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, hipStrea
   F.Ci[l].alloc(sizeof(cplx<R>) * nb * w4);
   cplx<R>* Pst = F.Pa[l].template as<cplx<R>>();
   cplx<R>* W = F.Ci[l].template as<cplx<R>>();
-  AsyncBuf T(sizeof(cplx<R>) * nb * 3 * rr, s);
-  cplx<R>* Aw = T.template as<cplx<R>>();
+  cplx<R>* Aw = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 3 * rr);
   cplx<R>* Bw = Aw + nb * rr;
   cplx<R>* C = Bw + nb * rr;
   // S_a L, S_b R
@@ -630,11 +643,11 @@ void factor_merge_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, hipStrea
   cgemm<R>(s, r, r, c, one, P.W<R>(l, 1), c, 0, OP_N, Pst, r, 2 * cr, OP_N, zero, nullptr, 0, 0, Bw, r, rr, nb);
   cgemm<R>(s, r, r, r, mone, Bw, r, rr, OP_N, Aw, r, rr, OP_N, zero, nullptr, 0, 0, C, r, rr, nb, true);
   {
-    AsyncBuf ws(inverse_ws_bytes<R>(r, nb), s);
+    void* ws = F.scratch_buf(inverse_ws_bytes<R>(r, nb));
     F.info.emplace_back(sizeof(int) * nb, s);
     F.info_n.push_back(nb);
     F.info_what.push_back("singular merge matrix I - Bw Aw at level " + std::to_string(l));
-    inverse<R>(s, C, r, r, rr, nb, ws.p, F.info.back().template as<int>());
+    inverse<R>(s, C, r, r, rr, nb, ws, F.info.back().template as<int>());
   }
   // W' = [[-Aw C, I + Aw C Bw], [C, -C Bw]]  (row blocks of 2r entries)
   ccopy2d<R>(s, r, r, C, r, rr, W + r * r2, r2, w4, nb);
@@ -663,11 +676,11 @@ void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   cgemm<R>(s, c, c, c, one, Sch + cc, c, 2 * cc, OP_N, G, c, 0, OP_T, zero, nullptr, 0, 0, Pb, c, cc, nb);
   cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
   {
-    AsyncBuf ws(inverse_ws_bytes<R>(c, nb), s);
+    void* ws = F.scratch_buf(inverse_ws_bytes<R>(c, nb));
     F.info.emplace_back(sizeof(int) * nb, s);
     F.info_n.push_back(nb);
     F.info_what.push_back("singular merge matrix I - Pb Pa at level " + std::to_string(l));
-    inverse<R>(s, Ci, c, c, cc, nb, ws.p, F.info.back().template as<int>());
+    inverse<R>(s, Ci, c, c, cc, nb, ws, F.info.back().template as<int>());
   }
 }
 
@@ -690,9 +703,8 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
     // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] (a1, a2 interleaved per box in A12)
     const int r = F.wr[l];
     const long rk = (long)r * k, cr = (long)c * r, w4 = 4L * r * r;
-    AsyncBuf A12(sizeof(cplx<R>) * nb * 2 * ck, s), Qb(sizeof(cplx<R>) * nb * 4 * rk, s);
-    cplx<R>* a = A12.template as<cplx<R>>();
-    cplx<R>* q = Qb.template as<cplx<R>>();
+    cplx<R>* a = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 2 * ck);
+    cplx<R>* q = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 4 * rk);
     cplx<R>* yv = q + nb * 2 * rk;
     cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a, k, 2 * ck, nb);
     cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a + ck, k, 2 * ck, nb);
@@ -709,10 +721,9 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
              nb);
     return;
   }
-  AsyncBuf A1(sizeof(cplx<R>) * nb * ck, s), A2(sizeof(cplx<R>) * nb * ck, s), Yb(sizeof(cplx<R>) * nb * ck, s);
-  cplx<R>* a1 = A1.template as<cplx<R>>();
-  cplx<R>* a2 = A2.template as<cplx<R>>();
-  cplx<R>* y = Yb.template as<cplx<R>>();
+  cplx<R>* a1 = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
+  cplx<R>* a2 = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
+  cplx<R>* y = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
   cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a1, k, ck, nb);
   cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a2, k, ck, nb);
   {
@@ -739,6 +750,7 @@ void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStr
   factor_leaves(P, b, F, s);
   for (int l = P.L - 1; l >= 0; --l) factor_level(P, F, l, s);
   factor_check(F, s);
+  F.release_scratch();
 }
 
 template <typename R>
@@ -1796,6 +1808,8 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 2], 0));
   LSH_HIP(hipStreamSynchronize(s));
   P->release_scratch();
+  F->f32.release_scratch();
+  F->f64.release_scratch();
   *plan = P.release();
   *factor = F.release();
   return LSH_OK;
