@@ -779,7 +779,7 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
   ProfScope ps(sizeof(R) == 4 ? "cgemv_f32" : "cgemv_f64", s,
                (double)sizeof(cplx<R>) * ((double)nmat * M * N + (double)batch * (N + (z ? 2.0 : 1.0) * M)));
   const int am = amod > 0 ? amod : 1;
-  if (batch > am && batch % am == 0) {
+  if (batch > am && batch % am == 0 && batch / am <= 64) {
     // several vectors per matrix: groups of four read each matrix once
     const int nvec = batch / am;
     for (int v0 = 0; v0 < nvec; v0 += 4) {

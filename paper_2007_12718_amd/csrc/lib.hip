@@ -778,8 +778,22 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
 }
 
 // below this many box vectors the shared products stream the matrix rows
-// (multi-vector GEMV); above it they are MFMA GEMMs
+// (multi-vector GEMV); above it they are MFMA GEMMs (a GEMV per vector and
+// row was slower at every level size measured, fourier-1024)
 constexpr int SKINNY = 32;
+
+// Y[v] = alpha M X[v] + beta Z[v] for B vectors (strides ldx, ldz, ldy) and
+// one shared matrix M (rows x cols, row-major); (MtB, ldb, opB) give M^T as
+// the B operand of the GEMM used for many vectors.
+template <typename R>
+void shared_mv(hipStream_t s, int rows, int cols, cplx<R> alpha, const cplx<R>* M, const cplx<R>* MtB, long ldb,
+               Op opB, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy,
+               int B) {
+  if (B <= SKINNY)
+    cmgemv<R>(s, rows, cols, alpha, M, cols, X, ldx, beta, Z, ldz, Y, ldy, B);
+  else
+    cgemm<R>(s, B, rows, cols, alpha, X, ldx, 0, OP_N, MtB, ldb, 0, opB, beta, Z, ldz, 0, Y, ldy, 0, 1);
+}
 
 // out = X_tau in on a Woodbury level, three launches:
 //   q = [L^T a; R^T b]  (shared [L^T; R^T], one two-block product),
@@ -890,12 +904,8 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     const int c = P.lev[l].c, k = P.lev[l].k, B = nrhs << l;
     apply_X<R>(P, F, l, nrhs, F.rt[l + 1].template as<cplx<R>>(), t1, s);
     // rt_l = U_l^T xv
-    if (B <= SKINNY)
-      cmgemv<R>(s, k, 2 * c, one, P.Ut<R>(l), 2 * c, t1, 2 * c, zero, nullptr, 0, F.rt[l].template as<cplx<R>>(), k,
-                B);
-    else
-      cgemm<R>(s, B, k, 2 * c, one, t1, 2 * c, 0, OP_N, P.U<R>(l), k, 0, OP_N, zero, nullptr, 0, 0,
-               F.rt[l].template as<cplx<R>>(), k, 0, 1);
+    shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t1, 2 * c, zero, nullptr, 0,
+                 F.rt[l].template as<cplx<R>>(), k, B);
   }
   // root: w_children = Ghat X_root [rt_a; rt_b]
   {
@@ -910,11 +920,8 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
     const long cc = (long)c * c;
     // u = U_l wt_l  ([B][2c])
-    if (B <= SKINNY)
-      cmgemv<R>(s, 2 * c, k, one, P.U<R>(l), k, F.wt[l].template as<cplx<R>>(), k, zero, nullptr, 0, t1, 2 * c, B);
-    else
-      cgemm<R>(s, B, 2 * c, k, one, F.wt[l].template as<cplx<R>>(), k, 0, OP_N, P.U<R>(l), k, 0, OP_T, zero,
-               nullptr, 0, 0, t1, 2 * c, 0, 1);
+    shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.wt[l].template as<cplx<R>>(), k, zero, nullptr,
+                 0, t1, 2 * c, B);
     // d = rt_children - diag(S_a, S_b) u  ([2B][c])
     cgemv<R>(s, c, c, mone, F.S[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t1, c, one,
              F.rt[l + 1].template as<cplx<R>>(), c, t2, c, 2 * B);
@@ -922,14 +929,8 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     apply_X<R>(P, F, l, nrhs, t2, t3, s);
     // wt_children = Ghat qt + u
     cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
-    if (B <= SKINNY) {
-      cmgemv<R>(s, c, c, one, P.Gab<R>(l), c, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B);
-      cmgemv<R>(s, c, c, one, P.Gabt<R>(l), c, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c, B);
-    } else {
-      cgemm<R>(s, B, c, c, one, t3 + c, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_T, one, t1, 2 * c, 0, wc, 2 * c, 0, 1);
-      cgemm<R>(s, B, c, c, one, t3, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_N, one, t1 + c, 2 * c, 0, wc + c, 2 * c, 0,
-               1);
-    }
+    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B);
+    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c, B);
   }
   leaf_down<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, F.wt[L].template as<cplx<R>>(), r, q,
                b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
@@ -963,24 +964,14 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
     const cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
     cplx<R>* vb = F.vb[l].template as<cplx<R>>();
     // vb = Ghat wc
-    if (B <= SKINNY) {
-      cmgemv<R>(s, c, c, one, P.Gab<R>(l), c, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B);
-      cmgemv<R>(s, c, c, one, P.Gabt<R>(l), c, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B);
-    } else {
-      cgemm<R>(s, B, c, c, one, wc + c, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_T, zero, nullptr, 0, 0, vb, 2 * c, 0, 1);
-      cgemm<R>(s, B, c, c, one, wc, 2 * c, 0, OP_N, P.Gab<R>(l), c, 0, OP_N, zero, nullptr, 0, 0, vb + c, 2 * c, 0,
-               1);
-    }
+    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B);
+    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B);
     // t3 = X^T vb ; t2 = wc - diag(S_a^T, S_b^T) t3
     apply_X<R>(P, F, l, nrhs, vb, t3, s, true);
     cgemv<R>(s, c, c, mone, F.ST[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t3, c, one, wc, c, t2, c, 2 * B);
     // wb_l = U_l^T t2
-    if (B <= SKINNY)
-      cmgemv<R>(s, k, 2 * c, one, P.Ut<R>(l), 2 * c, t2, 2 * c, zero, nullptr, 0, F.wt[l].template as<cplx<R>>(), k,
-                B);
-    else
-      cgemm<R>(s, B, k, 2 * c, one, t2, 2 * c, 0, OP_N, P.U<R>(l), k, 0, OP_N, zero, nullptr, 0, 0,
-               F.wt[l].template as<cplx<R>>(), k, 0, 1);
+    shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t2, 2 * c, zero, nullptr, 0,
+                 F.wt[l].template as<cplx<R>>(), k, B);
   }
   // root: rb_1 = X_root^T Ghat wb_1
   {
@@ -994,11 +985,8 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
   for (int l = 1; l <= L - 1; ++l) {
     const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
     const cplx<R>* vb = F.vb[l].template as<cplx<R>>();
-    if (B <= SKINNY)
-      cmgemv<R>(s, 2 * c, k, one, P.U<R>(l), k, F.rt[l].template as<cplx<R>>(), k, one, vb, 2 * c, t1, 2 * c, B);
-    else
-      cgemm<R>(s, B, 2 * c, k, one, F.rt[l].template as<cplx<R>>(), k, 0, OP_N, P.U<R>(l), k, 0, OP_T, one, vb,
-               2 * c, 0, t1, 2 * c, 0, 1);
+    shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.rt[l].template as<cplx<R>>(), k, one, vb, 2 * c,
+                 t1, 2 * c, B);
     apply_X<R>(P, F, l, nrhs, t1, F.rt[l + 1].template as<cplx<R>>(), s, true);
   }
   // leaves: q = X^T (g + U_L rb_L)
