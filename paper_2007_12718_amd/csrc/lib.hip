@@ -2174,6 +2174,10 @@ int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b,
   API_BEGIN
   LSH_REQUIRE(ninst >= 1 && plans && b && factors, LSH_ERR_INVALID_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
+  // Every step below runs on this one stream, so temporaries released here
+  // can go back to the device cache (stream order protects their reuse)
+  // instead of hipFree, which would synchronise the device each time.
+  mem::Recycle recycle;
   std::vector<std::unique_ptr<lsh_factor_s>> own;
   std::vector<lsh_factor_s*> f32;
   for (int i = 0; i < ninst; ++i) {
