@@ -1619,6 +1619,67 @@ int lsh_factor_create(lsh_plan_t P, const double* b, void* stream, lsh_factor_t*
   API_END
 }
 
+}  // extern "C"
+
+namespace {
+// Streams and events of lsh_build, kept for the process (per device and CU
+// reserve) and handed to one build at a time.
+struct BuildStreams {
+  int dev = 0, reserve = 0;
+  hipStream_t ps = nullptr, ps2 = nullptr, fsm = nullptr;
+  std::vector<hipEvent_t> ev;
+  void events(size_t n) {
+    while (ev.size() < n) {
+      hipEvent_t e = nullptr;
+      LSH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ev.push_back(e);
+    }
+  }
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::vector<BuildStreams*>& pool() {
+    static std::vector<BuildStreams*> p;
+    return p;
+  }
+  static BuildStreams* acquire(int dev, int reserve) {
+    {
+      std::lock_guard<std::mutex> g(mu());
+      auto& p = pool();
+      for (size_t i = 0; i < p.size(); ++i)
+        if (p[i]->dev == dev && p[i]->reserve == reserve) {
+          BuildStreams* b = p[i];
+          p.erase(p.begin() + i);
+          return b;
+        }
+    }
+    std::unique_ptr<BuildStreams> b(new BuildStreams());
+    b->dev = dev;
+    b->reserve = reserve;
+    LSH_HIP(hipStreamCreateWithFlags(&b->ps, hipStreamNonBlocking));
+    LSH_HIP(hipStreamCreateWithFlags(&b->ps2, hipStreamNonBlocking));
+    if (reserve > 0) {
+      int ncu = 0;
+      LSH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+      for (int c = 0; c < ncu - reserve; ++c) mask[c / 32] |= 1u << (c % 32);
+      if (hipExtStreamCreateWithCUMask(&b->fsm, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        b->fsm = nullptr;
+      }
+    }
+    return b.release();
+  }
+  static void release(BuildStreams* b) {
+    std::lock_guard<std::mutex> g(mu());
+    pool().push_back(b);
+  }
+};
+}  // namespace
+
+extern "C" {
+
 // Plan and factor pipelined by level: the plan runs level by level in a host
 // thread on its own stream (its row IDs are latency-bound pivot loops), and
 // the factor of level l starts on the caller's stream as soon as plan level l
@@ -1646,45 +1707,32 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   }
   int dev = 0;
   LSH_HIP(hipGetDevice(&dev));
-  hipStream_t ps = nullptr, ps2 = nullptr;
-  LSH_HIP(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
-  struct StreamGuard {
-    hipStream_t st;
-    ~StreamGuard() { if (st) (void)hipStreamDestroy(st); }
-  } sg{ps};
   // The factor runs on a stream kept off LSH_PLAN_CUS compute units, so that
   // the plan's small latency-bound kernels (the critical path) find free
   // units while the factor's products fill the rest.  Default: an eighth of
   // the units for the FP32 factor, none for the FP64 factor (whose products
   // are the longer path).  Without CU masking the factor uses the caller's
-  // stream.
-  hipStream_t fsm = nullptr;
+  // stream.  Streams and events come from a per-process pool (creating them
+  // costs milliseconds per build).
+  int reserve = 0;
   {
     const char* e = std::getenv("LSH_PLAN_CUS");
     int ncu = 0;
     LSH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int reserve = (e && *e) ? std::atoi(e) : (desc->hbs_prec == LSH_FP32 ? ncu / 8 : 0);
-    if (reserve > 0 && reserve < ncu / 2) {
-      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-      for (int c = 0; c < ncu - reserve; ++c) mask[c / 32] |= 1u << (c % 32);
-      if (hipExtStreamCreateWithCUMask(&fsm, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
-        (void)hipGetLastError();
-        fsm = nullptr;
-      }
-    }
+    reserve = (e && *e) ? std::atoi(e) : (desc->hbs_prec == LSH_FP32 ? ncu / 8 : 0);
+    if (!(reserve > 0 && reserve < ncu / 2)) reserve = 0;
   }
-  StreamGuard fg{fsm};
-  LSH_HIP(hipStreamCreateWithFlags(&ps2, hipStreamNonBlocking));
-  StreamGuard sg2{ps2};
+  BuildStreams* bs = BuildStreams::acquire(dev, reserve);
+  struct BsGuard {
+    BuildStreams* b;
+    ~BsGuard() { BuildStreams::release(b); }
+  } bsg{bs};
+  hipStream_t ps = bs->ps, ps2 = bs->ps2, fsm = bs->fsm;
   hipStream_t fs = fsm ? fsm : s;
   plan_init(*P, ps);
   const int L = P->L;
-  std::vector<hipEvent_t> ev(2 * L + 5, nullptr);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
-  struct EventGuard {
-    std::vector<hipEvent_t>& v;
-    ~EventGuard() { for (auto e : v) if (e) (void)hipEventDestroy(e); }
-  } eg{ev};
-  for (auto& e : ev) LSH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  bs->events(2 * L + 5);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
+  std::vector<hipEvent_t>& ev = bs->ev;
   if (fsm) {  // the factor stream follows the copy of b on the caller's stream
     LSH_HIP(hipEventRecord(ev[2 * L + 3], s));
     LSH_HIP(hipStreamWaitEvent(fsm, ev[2 * L + 3], 0));
