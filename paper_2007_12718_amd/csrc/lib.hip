@@ -1764,6 +1764,9 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
         { std::lock_guard<std::mutex> g(mu); doneU = l; }
         cv.notify_all();
       }
+      // the operator spectrum, while the other thread does the root's sibling block
+      plan_finish(*P, ps);
+      LSH_HIP(hipEventRecord(ev[2 * L + 2], ps));
     } catch (...) {
       fail();
     }
@@ -1789,10 +1792,6 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
         LSH_HIP(hipEventRecord(ev[L + 1 + l], ps2));
         { std::lock_guard<std::mutex> g(mu); doneG = l; }
         cv.notify_all();
-      }
-      if (!failed) {
-        plan_finish(*P, ps2);
-        LSH_HIP(hipEventRecord(ev[2 * L + 2], ps2));
       }
     } catch (...) {
       fail();
