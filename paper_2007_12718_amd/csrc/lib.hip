@@ -777,10 +777,11 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
   F.ws_nrhs = nrhs;
 }
 
-// below this many box vectors the shared products stream the matrix rows
+// up to this many box vectors the shared products stream the matrix rows
 // (multi-vector GEMV); above it they are MFMA GEMMs (a GEMV per vector and
-// row was slower at every level size measured, fourier-1024)
-constexpr int SKINNY = 32;
+// row was slower at every level size measured, fourier-1024; 64 measured
+// best against 32, 128 and 256)
+constexpr int SKINNY = 64;
 
 // Y[v] = alpha M X[v] + beta Z[v] for B vectors (strides ldx, ldz, ldy) and
 // one shared matrix M (rows x cols, row-major); (MtB, ldb, opB) give M^T as
