@@ -112,7 +112,7 @@ typedef struct {
   double residual;                      /* Givens estimate at exit (last rhs) */
   double true_residual;                 /* max over rhs of ||f - A sigma|| / ||f|| */
   double history[LSH_MAX_ITERS + 1];    /* residual estimates of the last rhs */
-  double ms_precond, ms_operator, ms_ortho;  /* time per phase (last solve) */
+  double ms_precond, ms_operator, ms_ortho;  /* reserved (set to 0) */
 } lsh_info;
 
 /* ---- plan: paper Sec. 3 (tree, proxy-source IDs; independent of b) ----
@@ -210,8 +210,13 @@ int lsh_apply_operator(lsh_plan_t plan, const double* b, const void* x, void* y,
 
 /* sigma (and u = K sigma if u != NULL) for each incident field:
  * right-preconditioned flexible GMRES (x0 = 0, CGS2, no restart).
- * Synchronises once per iteration (residual read-back).  Returns
- * LSH_NOT_CONVERGED if some rhs did not reach opts->tol. */
+ * nrhs >= 2: groups of up to 8 right-hand sides run in lockstep (one
+ * preconditioner and one operator application per iteration for the whole
+ * group; each right-hand side keeps its own Krylov basis and stopping
+ * test, so it takes the iterations of its own one-column solve); the
+ * factor keeps (2 maxit + 1) min(nrhs, 8) n^2 complex FP64 values of
+ * Krylov workspace.  Synchronises once per iteration (residual read-back).
+ * Returns LSH_NOT_CONVERGED if some rhs did not reach opts->tol. */
 int lsh_solve(lsh_factor_t factor, const void* u_inc, int nrhs, void* sigma, void* u, const lsh_solve_opts* opts,
               lsh_info* info, void* stream);
 
