@@ -1636,15 +1636,30 @@ struct BuildStreams {
       ev.push_back(e);
     }
   }
+  // (never destroyed: the exit handler below still uses them)
   static std::mutex& mu() {
-    static std::mutex m;
-    return m;
+    static std::mutex* m = new std::mutex;
+    return *m;
   }
   static std::vector<BuildStreams*>& pool() {
-    static std::vector<BuildStreams*> p;
-    return p;
+    static std::vector<BuildStreams*>* p = new std::vector<BuildStreams*>;
+    return *p;
+  }
+  // destroys the pooled streams and events at process exit, before the
+  // runtime's own teardown (a handler registered after the runtime started)
+  static void destroy_all() {
+    std::lock_guard<std::mutex> g(mu());
+    for (BuildStreams* b : pool()) {
+      for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+      for (hipStream_t st : {b->ps, b->ps2, b->fsm})
+        if (st) (void)hipStreamDestroy(st);
+      delete b;
+    }
+    pool().clear();
   }
   static BuildStreams* acquire(int dev, int reserve) {
+    static const bool registered = [] { return std::atexit(destroy_all) == 0; }();
+    (void)registered;
     {
       std::lock_guard<std::mutex> g(mu());
       auto& p = pool();
