@@ -59,7 +59,7 @@ void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector
 }
 
 // ------------------------------------------------------------------- FFT
-void FFTPlan::init(int M_) {
+void FFTPlan::init(int M_, hipStream_t s) {
   M = M_;
   logM = 0;
   while ((1 << logM) < M) ++logM;
@@ -70,7 +70,10 @@ void FFTPlan::init(int M_) {
     h[k] = mk((double)std::cos(a), (double)std::sin(a));
   }
   tw.alloc(sizeof(z64) * h.size());
-  LSH_HIP(hipMemcpy(tw.p, h.data(), sizeof(z64) * h.size(), hipMemcpyHostToDevice));
+  // on the caller's stream: a plain hipMemcpy would also wait for every
+  // blocking stream of the device (a factorisation running beside the plan)
+  LSH_HIP(hipMemcpyAsync(tw.p, h.data(), sizeof(z64) * h.size(), hipMemcpyHostToDevice, s));
+  LSH_HIP(hipStreamSynchronize(s));  // h dies here
 }
 
 // In-place radix-2 decimation-in-time transform of x (bit-reversed input).
@@ -201,7 +204,7 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
   kappa = kappa_;
   M = 1;
   while (M < 2 * n) M <<= 1;
-  fft.init(M);
+  fft.init(M, s);
   khatT.alloc(sizeof(z64) * (size_t)M * M);
   w1.alloc(sizeof(z64) * (size_t)n * M);
   w2.alloc(sizeof(z64) * (size_t)M * M);

@@ -9,7 +9,7 @@ namespace lsh {
 struct FFTPlan {
   int M = 0, logM = 0;
   DevBuf tw;  // exp(-2 pi i k / M), k < M/2
-  void init(int M_);
+  void init(int M_, hipStream_t s);
 };
 
 // Batched row transforms: out[r][k] (k < nout) = DFT_M(in[r][0 .. nin)) (zero padded).
