@@ -57,6 +57,26 @@ def dense_A(b, K, kappa: float):
     return np.eye(K.shape[0], dtype=complex) + (kappa ** 2 * b)[:, None] * K
 
 
+def apply_rows(Koff, b, x, kappa: float, rows):
+    """(A x)_i for the flat target indices in ``rows``, each by the direct sum
+    over all n^2 sources (eqs. (linsys), (Gmat)).
+
+    ``Koff`` is ``kernel_offsets(n, kappa, order)``; target (t1, t2) meets
+    source (j1, j2) at offset (j1 - t1, j2 - t2), so its row of K is the n x n
+    window of the offset table that starts at (n - 1 - t2, n - 1 - t1).
+    O(n^2) work per row: spot checks at sizes where A cannot be formed.
+    """
+    n = Koff.shape[0] // 2 + 1
+    b = np.asarray(b, dtype=float).reshape(n, n)
+    x = np.asarray(x, dtype=complex).reshape(n, n)
+    out = np.empty(len(rows), dtype=complex)
+    for k, i in enumerate(rows):
+        t2, t1 = divmod(int(i), n)
+        win = Koff[n - 1 - t2:2 * n - 1 - t2, n - 1 - t1:2 * n - 1 - t1]
+        out[k] = x[t2, t1] + kappa ** 2 * b[t2, t1] * np.sum(win * x)
+    return out
+
+
 def rhs(b, u_inc, kappa: float):
     """f = -kappa^2 b u_inc (paper eq. (linsys))."""
     return -kappa ** 2 * np.asarray(b, dtype=float).reshape(-1) * np.asarray(u_inc).reshape(-1)
