@@ -25,6 +25,17 @@ int lsh_dev_gemm(int prec, int M, int N, int K, const double* alpha, const void*
                  const void* B, long ldb, long sB, int opB, const double* beta, const void* D, long ldd, long sD,
                  void* C, long ldc, long sC, int batch, void* stream);
 
+/* As lsh_dev_gemm, with ws (device, ws_bytes) as scratch for the partial
+ * products: an FP32 product with fewer than 128 output tiles of 64 x 64 and
+ * K >= 128 splits K over workgroups (as the preconditioner's shared box
+ * products do); otherwise, or without room in ws, it is lsh_dev_gemm.  ws
+ * must not be in use by other work on the device until the call's work on
+ * the stream has finished. */
+int lsh_dev_gemm_split(int prec, int M, int N, int K, const double* alpha, const void* A, long lda, long sA,
+                       int opA, const void* B, long ldb, long sB, int opB, const double* beta, const void* D,
+                       long ldd, long sD, void* C, long ldc, long sC, int batch, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* In place: A_b <- A_b^{-1} (c x c, leading dimension lda, stride sA) by
  * Gauss-Jordan elimination with partial pivoting.  info: device int[batch],
  * 0 or j+1 for a zero pivot at step j.  Allocates its own scratch. */

@@ -50,6 +50,10 @@ struct GemmP {
   int addI;
   const int* skip;  // optional device flag: the whole launch is a no-op when *skip != 0
   int lower;        // 1: only tiles that reach the diagonal or below it (M == N)
+  // split K (FP32 kernel only): grid z runs over (problem, K chunk); chunk ks
+  // of problem b writes alpha A[:, chunk] B[chunk, :] to part + (b nsplit + ks) M N
+  cplx<R>* part = nullptr;
+  int nsplit = 1, kchunk = 0;
 };
 
 // Tile: 2 x 2 wavefronts, each owning WM x WN blocks of 16 x 16 outputs, so the
@@ -359,7 +363,43 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {  // (WM,
   const int tm = (int)((L / gridDim.x) % gridDim.y);
   const long b = L / ((long)gridDim.x * gridDim.y);
   if (P.lower && tn * BN >= (tm + 1) * BM) return;  // strictly above the diagonal
+  if (P.part) {
+    const int ks = (int)(b % P.nsplit);
+    const long bb = b / P.nsplit;
+    const long k0 = (long)ks * P.kchunk;
+    const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
+    GemmP<float> Q = P;
+    Q.A = P.A + (aN ? k0 : k0 * P.lda);
+    Q.B = P.B + (bN ? k0 * P.ldb : k0);
+    Q.K = (int)(P.K - k0 < P.kchunk ? P.K - k0 : P.kchunk);
+    Q.C = P.part + b * (long)P.M * P.N;
+    Q.ldc = P.N;
+    Q.sC = 0;
+    Q.D = nullptr;
+    Q.beta = mk<float>(0, 0);
+    Q.addI = 0;
+    cgemm_x32_tile<WM, WN>(Q, bb, tm * BM, tn * BN);
+    return;
+  }
   cgemm_x32_tile<WM, WN>(P, b, tm * BM, tn * BN);
+}
+
+// C = sum of the nsplit partial products + beta D (+ I)
+template <typename R>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const cplx<R>* __restrict__ part, int nsplit, int M, int N,
+                                                       long total, cplx<R> beta, const cplx<R>* D, long ldd, long sD,
+                                                       cplx<R>* C, long ldc, long sC, int addI) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long mn = (long)M * N;
+  const long b = e / mn, r = e - b * mn;
+  const int m = (int)(r / N), n = (int)(r - (long)m * N);
+  const cplx<R>* p = part + b * nsplit * mn + r;
+  cplx<R> v = p[0];
+  for (int ks = 1; ks < nsplit; ++ks) v = v + p[ks * mn];
+  if (D && (beta.x != R(0) || beta.y != R(0))) v = v + beta * D[b * sD + (long)m * ldd + n];
+  if (addI && m == n) v.x += R(1);
+  C[b * sC + (long)m * ldc + n] = v;
 }
 
 // Grouped form: problem g of the table has tiles_m x tiles_n x batch tiles
@@ -479,6 +519,53 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
     if (f64_forced == 0) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
+}
+
+// Products with too few output tiles to fill the device (shared box
+// matrices at the upper levels: a few hundred boxes times a few hundred
+// rows) split K over workgroups into ws, then sum the partial tiles.
+constexpr long SPLIT_TILES = 128;  // split below this many 64 x 64 output tiles
+constexpr long SPLIT_WG = 512;     // aim for about this many workgroups
+constexpr int SPLIT_KMIN = 64;     // at least two K tiles per chunk
+
+template <typename R>
+void cgemm_ws(hipStream_t s, int M, int N, int K, cplx<R> alpha, const cplx<R>* A, long lda, long sA, Op opA,
+              const cplx<R>* B, long ldb, long sB, Op opB, cplx<R> beta, const cplx<R>* D, long ldd, long sD,
+              cplx<R>* C, long ldc, long sC, int batch, void* ws, size_t ws_bytes) {
+  if constexpr (sizeof(R) == 4) {
+    const long tiles = (long)ceil_div(M, 64) * ceil_div(N, 64) * batch;
+    if (ws && M > 0 && N > 0 && batch > 0 && tiles < SPLIT_TILES && K >= 2 * SPLIT_KMIN) {
+      long ns = (SPLIT_WG + tiles - 1) / tiles;
+      if (ns > K / SPLIT_KMIN) ns = K / SPLIT_KMIN;
+      const size_t per = sizeof(cplx<R>) * (size_t)M * N * batch;
+      if ((size_t)ns > ws_bytes / per) ns = (long)(ws_bytes / per);
+      if (ns >= 2) {
+        const int kchunk = ceil_div(ceil_div(K, (int)ns), X32_BK) * X32_BK;
+        const int nsplit = ceil_div(K, kchunk);
+        GemmP<R> P;
+        P.skip = nullptr;
+        P.lower = 0;
+        P.M = M; P.N = N; P.K = K; P.alpha = alpha; P.beta = mk<R>(0, 0);
+        P.A = A; P.lda = lda; P.sA = sA; P.opA = opA;
+        P.B = B; P.ldb = ldb; P.sB = sB; P.opB = opB;
+        P.D = nullptr; P.ldd = 0; P.sD = 0;
+        P.C = nullptr; P.ldc = N; P.sC = 0; P.addI = 0;
+        P.part = static_cast<cplx<R>*>(ws);
+        P.nsplit = nsplit;
+        P.kchunk = kchunk;
+        ProfScope ps("cgemm_f32_splitk", s, 8.0 * M * N * (double)K * batch);
+        hipLaunchKernelGGL((k_cgemm_x32<1, 1>), dim3(ceil_div(N, 64), ceil_div(M, 64), batch * nsplit), dim3(256), 0,
+                           s, P);
+        LSH_LAUNCH_CHECK();
+        const long total = (long)batch * M * N;
+        hipLaunchKernelGGL(k_splitk_reduce<R>, dim3((unsigned)ceil_div(total, 256L)), dim3(256), 0, s,
+                           P.part, nsplit, M, N, total, beta, D, ldd, sD, C, ldc, sC, 0);
+        LSH_LAUNCH_CHECK();
+        return;
+      }
+    }
+  }
+  cgemm<R>(s, M, N, K, alpha, A, lda, sA, opA, B, ldb, sB, opB, beta, D, ldd, sD, C, ldc, sC, batch);
 }
 
 void cgemm_grouped(hipStream_t s, const std::vector<GemmItem>& items, DevBuf& dev) {
@@ -1685,6 +1772,9 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
   template void cmgemv<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, const cplx<R>*, long, cplx<R>, \
                           const cplx<R>*, long, cplx<R>*, long, int);                                        \
   template void ctranspose<R>(hipStream_t, const cplx<R>*, int, int, cplx<R>*, long);                       \
+  template void cgemm_ws<R>(hipStream_t, int, int, int, cplx<R>, const cplx<R>*, long, long, Op,              \
+                            const cplx<R>*, long, long, Op, cplx<R>, const cplx<R>*, long, long, cplx<R>*,   \
+                            long, long, int, void*, size_t);                                                 \
   template void cmgemv2<R>(hipStream_t, int, int, long, int, cplx<R>, const cplx<R>*, long, const cplx<R>*,   \
                            long, cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                        \
   template void ccopy2d<R>(hipStream_t, int, int, const cplx<R>*, long, long, cplx<R>*, long, long, long);   \

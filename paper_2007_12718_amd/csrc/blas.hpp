@@ -28,6 +28,15 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
            cplx<R>* C, long ldc, long sC, int batch, bool add_identity = false, const int* skip = nullptr,
            bool lower = false);
 
+// As cgemm (no identity, skip flag or lower mode), but in FP32 a product
+// with few output tiles splits K over workgroups, with ws (ws_bytes of
+// device memory, stream-ordered scratch) holding the partial products;
+// without room in ws, or in FP64, it is cgemm.
+template <typename R>
+void cgemm_ws(hipStream_t s, int M, int N, int K, cplx<R> alpha, const cplx<R>* A, long lda, long sA, Op opA,
+              const cplx<R>* B, long ldb, long sB, Op opB, cplx<R> beta, const cplx<R>* D, long ldd, long sD,
+              cplx<R>* C, long ldc, long sC, int batch, void* ws, size_t ws_bytes);
+
 // C[i][j] = conj(C[j][i]) for j > i: completes a Hermitian matrix from its lower triangle
 template <typename R>
 void mirror_lower(hipStream_t s, cplx<R>* C, int n, long ldc);

@@ -1323,28 +1323,48 @@ constexpr int LEAF_MAX = 144;
 constexpr int LEAF_NV = 4;
 
 // rows i of the mL x mL leaf matrix Xt times NV vectors in LDS (ins[v][*]);
-// one wave per row, the row sum by butterfly shuffles; fn(i, v, sum) on lane 0
+// one wave per row, the row sum by butterfly shuffles; fn(i, v, sum) on lane 0.
+// A wave takes LEAF_RU rows at a time (i, i + 4, ...) with their loads issued
+// together, so that each lane keeps several HBM reads in flight (one row per
+// wave at a time left the leaf kernels at a third of HBM bandwidth); every
+// row gets the same arithmetic in the same order either way.
+constexpr int LEAF_RU = 4;
 template <typename R, int NV, typename Fn>
 __device__ __forceinline__ void leaf_rows(const cplx<R>* __restrict__ Xt, int mL, const cplx<R> (*ins)[LEAF_MAX],
                                           int nv, Fn fn) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < mL; i += 4) {
-    cplx<R> acc[NV];
+  for (int i0 = wave; i0 < mL; i0 += 4 * LEAF_RU) {
+    cplx<R> acc[LEAF_RU][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
+    for (int u = 0; u < LEAF_RU; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[u][v] = mk<R>(0, 0);
     for (int j = lane; j < mL; j += 64) {
-      const cplx<R> xv = Xt[(long)i * mL + j];
+      cplx<R> xv[LEAF_RU];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) fma_acc(acc[v], xv, ins[v][j]);
+      for (int u = 0; u < LEAF_RU; ++u) {
+        const int i = i0 + 4 * u;
+        xv[u] = i < mL ? Xt[(long)i * mL + j] : mk<R>(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < LEAF_RU; ++u)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fma_acc(acc[u][v], xv[u], ins[v][j]);
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (v >= nv) break;
-      for (int off = 32; off > 0; off >>= 1) {
-        acc[v].x += __shfl_xor(acc[v].x, off);
-        acc[v].y += __shfl_xor(acc[v].y, off);
+    for (int u = 0; u < LEAF_RU; ++u) {
+      const int i = i0 + 4 * u;
+      if (i >= mL) break;  // (uniform across the wave)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (v >= nv) break;
+        cplx<R> a = acc[u][v];
+        for (int off = 32; off > 0; off >>= 1) {
+          a.x += __shfl_xor(a.x, off);
+          a.y += __shfl_xor(a.y, off);
+        }
+        if (lane == 0) fn(i, v, a);
       }
-      if (lane == 0) fn(i, v, acc[v]);
     }
   }
 }

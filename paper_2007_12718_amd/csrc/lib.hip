@@ -522,6 +522,7 @@ struct FactorData {
   DevBuf r;                       // [nrhs][nleaf][mL]
   std::vector<DevBuf> rt, wt;     // [nrhs][2^l][k_l]
   DevBuf t1, t2, t3, ty, tw;      // scratch
+  DevBuf tk;                      // partial products of split-K shared products
   // transposed per-box matrices for M^T (built on first use)
   bool has_T = false;
   DevBuf XT;
@@ -774,6 +775,7 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
   F.t3.alloc(sizeof(cplx<R>) * big);
   F.ty.alloc(sizeof(cplx<R>) * big);
   F.tw.alloc(sizeof(cplx<R>) * big);
+  if (sizeof(R) == 4 && !F.tk.p) F.tk.alloc(size_t(24) << 20);  // (FP64 products do not split)
   F.ws_nrhs = nrhs;
 }
 
@@ -781,7 +783,10 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
 // (multi-vector GEMV); above it they are MFMA GEMMs (a GEMV per vector and
 // row was slower at every level size measured, fourier-1024; 64 measured
 // best against 32, 128 and 256)
-constexpr int SKINNY = 64;
+static const int SKINNY = [] {
+  const char* e = std::getenv("LSH_SKINNY");
+  return e ? std::atoi(e) : 8;
+}();
 
 // Y[v] = alpha M X[v] + beta Z[v] for B vectors (strides ldx, ldz, ldy) and
 // one shared matrix M (rows x cols, row-major); (MtB, ldb, opB) give M^T as
@@ -789,11 +794,12 @@ constexpr int SKINNY = 64;
 template <typename R>
 void shared_mv(hipStream_t s, int rows, int cols, cplx<R> alpha, const cplx<R>* M, const cplx<R>* MtB, long ldb,
                Op opB, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy,
-               int B) {
+               int B, DevBuf& ws) {
   if (B <= SKINNY)
     cmgemv<R>(s, rows, cols, alpha, M, cols, X, ldx, beta, Z, ldz, Y, ldy, B);
   else
-    cgemm<R>(s, B, rows, cols, alpha, X, ldx, 0, OP_N, MtB, ldb, 0, opB, beta, Z, ldz, 0, Y, ldy, 0, 1);
+    cgemm_ws<R>(s, B, rows, cols, alpha, X, ldx, 0, OP_N, MtB, ldb, 0, opB, beta, Z, ldz, 0, Y, ldy, 0, 1, ws.p,
+                ws.bytes);
 }
 
 // out = X_tau in on a Woodbury level, three launches:
@@ -817,7 +823,8 @@ void apply_X_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, con
     if (B <= SKINNY)
       cmgemv2<R>(s, 2 * r, r, c, c, one, Qm, c, in, 2 * c, zero, nullptr, 0, q, 2 * r, B);
     else  // two strided products: (a, L) and (b, R)
-      cgemm<R>(s, B, r, c, one, in, 2 * c, c, OP_N, Pm, r, cr, OP_N, zero, nullptr, 0, 0, q, 2 * r, r, 2);
+      cgemm_ws<R>(s, B, r, c, one, in, 2 * c, c, OP_N, Pm, r, cr, OP_N, zero, nullptr, 0, 0, q, 2 * r, r, 2, F.tk.p,
+                  F.tk.bytes);
     cgemv<R>(s, 2 * r, 2 * r, one, F.Ci[l].template as<cplx<R>>(), 2 * r, w4, nb, q, 2 * r, zero, nullptr, 0, y,
              2 * r, B);
     cgemv<R>(s, c, r, mone, F.Pa[l].template as<cplx<R>>(), r, cr, 2 * nb, y, r, one, in, c, out, c, 2 * B);
@@ -828,7 +835,8 @@ void apply_X_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, con
     if (B <= SKINNY)
       cmgemv2<R>(s, 2 * c, c, r, r, mone, Pm, r, y, 2 * r, one, in, 2 * c, out, 2 * c, B);
     else  // (z2, L^T) -> a, (z1, R^T) -> b
-      cgemm<R>(s, B, c, r, mone, y, 2 * r, r, OP_N, Qm, c, cr, OP_N, one, in, 2 * c, c, out, 2 * c, c, 2);
+      cgemm_ws<R>(s, B, c, r, mone, y, 2 * r, r, OP_N, Qm, c, cr, OP_N, one, in, 2 * c, c, out, 2 * c, c, 2,
+                  F.tk.p, F.tk.bytes);
   }
 }
 
@@ -906,7 +914,7 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     apply_X<R>(P, F, l, nrhs, F.rt[l + 1].template as<cplx<R>>(), t1, s);
     // rt_l = U_l^T xv
     shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t1, 2 * c, zero, nullptr, 0,
-                 F.rt[l].template as<cplx<R>>(), k, B);
+                 F.rt[l].template as<cplx<R>>(), k, B, F.tk);
   }
   // root: w_children = Ghat X_root [rt_a; rt_b]
   {
@@ -922,7 +930,7 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     const long cc = (long)c * c;
     // u = U_l wt_l  ([B][2c])
     shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.wt[l].template as<cplx<R>>(), k, zero, nullptr,
-                 0, t1, 2 * c, B);
+                 0, t1, 2 * c, B, F.tk);
     // d = rt_children - diag(S_a, S_b) u  ([2B][c])
     cgemv<R>(s, c, c, mone, F.S[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t1, c, one,
              F.rt[l + 1].template as<cplx<R>>(), c, t2, c, 2 * B);
@@ -930,8 +938,8 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     apply_X<R>(P, F, l, nrhs, t2, t3, s);
     // wt_children = Ghat qt + u
     cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
-    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B);
-    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c, B);
+    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B, F.tk);
+    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c, B, F.tk);
   }
   leaf_down<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, F.wt[L].template as<cplx<R>>(), r, q,
                b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
@@ -965,14 +973,14 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
     const cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
     cplx<R>* vb = F.vb[l].template as<cplx<R>>();
     // vb = Ghat wc
-    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B);
-    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B);
+    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B, F.tk);
+    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B, F.tk);
     // t3 = X^T vb ; t2 = wc - diag(S_a^T, S_b^T) t3
     apply_X<R>(P, F, l, nrhs, vb, t3, s, true);
     cgemv<R>(s, c, c, mone, F.ST[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t3, c, one, wc, c, t2, c, 2 * B);
     // wb_l = U_l^T t2
     shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t2, 2 * c, zero, nullptr, 0,
-                 F.wt[l].template as<cplx<R>>(), k, B);
+                 F.wt[l].template as<cplx<R>>(), k, B, F.tk);
   }
   // root: rb_1 = X_root^T Ghat wb_1
   {
@@ -987,7 +995,7 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
     const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
     const cplx<R>* vb = F.vb[l].template as<cplx<R>>();
     shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.rt[l].template as<cplx<R>>(), k, one, vb, 2 * c,
-                 t1, 2 * c, B);
+                 t1, 2 * c, B, F.tk);
     apply_X<R>(P, F, l, nrhs, t1, F.rt[l + 1].template as<cplx<R>>(), s, true);
   }
   // leaves: q = X^T (g + U_L rb_L)
@@ -2407,6 +2415,26 @@ int lsh_dev_gemm(int prec, int M, int N, int K, const double* alpha, const void*
     cgemm<float>(s, M, N, K, mk((float)alpha[0], (float)alpha[1]), (const c32*)A, lda, sA, (Op)opA, (const c32*)B,
                  ldb, sB, (Op)opB, mk((float)beta[0], (float)beta[1]), (const c32*)D, ldd, sD, (c32*)C, ldc, sC,
                  batch);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_dev_gemm_split(int prec, int M, int N, int K, const double* alpha, const void* A, long lda, long sA,
+                       int opA, const void* B, long ldb, long sB, int opB, const double* beta, const void* D,
+                       long ldd, long sD, void* C, long ldc, long sC, int batch, void* ws, size_t ws_bytes,
+                       void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(alpha && beta && A && B && C && M >= 0 && N >= 0 && K >= 0 && batch >= 0, LSH_ERR_INVALID_ARG,
+              "bad gemm argument");
+  LSH_REQUIRE(opA >= 0 && opA <= 3 && opB >= 0 && opB <= 3, LSH_ERR_INVALID_ARG, "bad op");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == LSH_FP64)
+    cgemm_ws<double>(s, M, N, K, mk(alpha[0], alpha[1]), (const z64*)A, lda, sA, (Op)opA, (const z64*)B, ldb, sB,
+                     (Op)opB, mk(beta[0], beta[1]), (const z64*)D, ldd, sD, (z64*)C, ldc, sC, batch, ws, ws_bytes);
+  else
+    cgemm_ws<float>(s, M, N, K, mk((float)alpha[0], (float)alpha[1]), (const c32*)A, lda, sA, (Op)opA,
+                    (const c32*)B, ldb, sB, (Op)opB, mk((float)beta[0], (float)beta[1]), (const c32*)D, ldd, sD,
+                    (c32*)C, ldc, sC, batch, ws, ws_bytes);
   return LSH_OK;
   API_END
 }

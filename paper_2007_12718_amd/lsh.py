@@ -25,7 +25,7 @@ EXPORTED = [
     "lsh_plan_create", "lsh_plan_destroy", "lsh_plan_ranks", "lsh_plan_level", "lsh_plan_block",
     "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
     "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
-    "lsh_dev_gemm", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
+    "lsh_dev_gemm", "lsh_dev_gemm_split", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
     "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor", "lsh_profile_only",
     "lsh_cache_trim", "lsh_plan_lowrank", "lsh_plan_cache_info", "lsh_plan_cache_clear", "lsh_plan_cache_save",
     "lsh_plan_cache_load",
@@ -93,6 +93,9 @@ def lib():
         L.lsh_dev_gemm.argtypes = [c_int, c_int, c_int, c_int, POINTER(c_double), c_void_p, c_long, c_long, c_int,
                                    c_void_p, c_long, c_long, c_int, POINTER(c_double), c_void_p, c_long, c_long,
                                    c_void_p, c_long, c_long, c_int, c_void_p]
+        L.lsh_dev_gemm_split.argtypes = [c_int, c_int, c_int, c_int, POINTER(c_double), c_void_p, c_long, c_long,
+                                         c_int, c_void_p, c_long, c_long, c_int, POINTER(c_double), c_void_p, c_long,
+                                         c_long, c_void_p, c_long, c_long, c_int, c_void_p, ctypes.c_size_t, c_void_p]
         L.lsh_dev_inverse.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p]
         L.lsh_eval_points_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p]
         L.lsh_grad_b.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]
@@ -360,8 +363,9 @@ def batch_factor(plans, bs):
     return [Factor(p, None, _handle=c_void_p(fh[i])) for i, p in enumerate(plans)]
 
 
-def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None):
-    """Batched complex GEMM through lsh_dev_gemm.  A, B: (batch, r, c) complex tensors."""
+def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None, ws=None):
+    """Batched complex GEMM through lsh_dev_gemm.  A, B: (batch, r, c) complex tensors.
+    ws: a device tensor of scratch bytes for lsh_dev_gemm_split (split K)."""
     import torch
     prec = LSH_FP64 if A.dtype == torch.complex128 else LSH_FP32
     bA, ra, ca = A.shape
@@ -373,9 +377,12 @@ def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None):
     al = (c_double * 2)(complex(alpha).real, complex(alpha).imag)
     be = (c_double * 2)(complex(beta).real, complex(beta).imag)
     Dp = _ptr(D) if D is not None else None
-    _check(lib().lsh_dev_gemm(prec, M, N, K, al, _ptr(A), ca, ra * ca if bA > 1 else 0, opA, _ptr(B), cb,
-                              rb * cb if bB > 1 else 0, opB, be, Dp, N, M * N if D is not None else 0,
-                              _ptr(C), N, M * N, batch, _stream()))
+    args = (prec, M, N, K, al, _ptr(A), ca, ra * ca if bA > 1 else 0, opA, _ptr(B), cb, rb * cb if bB > 1 else 0,
+            opB, be, Dp, N, M * N if D is not None else 0, _ptr(C), N, M * N, batch)
+    if ws is None:
+        _check(lib().lsh_dev_gemm(*args, _stream()))
+    else:
+        _check(lib().lsh_dev_gemm_split(*args, _ptr(ws), ws.numel() * ws.element_size(), _stream()))
     return C
 
 

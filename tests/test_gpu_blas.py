@@ -34,6 +34,31 @@ def test_gemm_matches_definition(prec, opA, opB):
     assert np.abs(C - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("opA,opB", [(0, 0), (0, 1), (2, 3)])
+@pytest.mark.parametrize("M,N,K,B", [(300, 379, 502, 1), (128, 70, 1990, 2), (70, 64, 130, 1), (65, 1, 4100, 3)])
+def test_split_k_gemm_matches_definition(opA, opB, M, N, K, B):
+    """Few output tiles: the FP32 product splits K over workgroups (chunks of
+    whole K tiles, a ragged last chunk, partial sums reduced with beta D).
+    With too little scratch it falls back to the unsplit kernel."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    rng = np.random.default_rng(M + N + K + opA)
+    dt = np.complex64
+    A = _rand((B, M, K) if opA in (0, 3) else (B, K, M), rng, dt)
+    Bm = _rand((B, K, N) if opB in (0, 3) else (B, N, K), rng, dt)
+    D = _rand((B, M, N), rng, dt)
+    al, be = 0.7 - 0.2j, -0.3 + 1.1j
+    tA, tB, tD = (torch.from_numpy(x).cuda() for x in (A, Bm, D))
+    ref = al * (_op(A.astype(np.complex128), opA) @ _op(Bm.astype(np.complex128), opB)) + be * D
+    scale = np.sqrt(K) * np.abs(_op(A, opA)).max() * np.abs(_op(Bm, opB)).max() + np.abs(ref).max()
+    for ws_bytes in (24 << 20, 16):
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        C = lsh.dev_gemm(tA, tB, opA, opB, al, be, D=tD, ws=ws).cpu().numpy()
+        assert np.abs(C - ref).max() <= 2e-6 * scale, ws_bytes
+        C0 = lsh.dev_gemm(tA, tB, opA, opB, al, be, D=tD).cpu().numpy()
+        assert np.abs(C - C0).max() <= 2e-6 * scale
+
+
 def test_gemm_shared_operand_and_large_batch():
     import torch
     from paper_2007_12718_amd import lsh
