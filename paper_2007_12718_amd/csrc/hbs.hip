@@ -1410,7 +1410,8 @@ __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, 
     cplx<R> acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
-    for (int i = 0; i < mL; ++i) {
+#pragma unroll 8
+    for (int i = 0; i < mL; ++i) {  // (unrolled: the U_L loads issued together)
       const cplx<R> u = UL[(long)i * k + a];
 #pragma unroll
       for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, rs[v][i]);
@@ -1448,18 +1449,22 @@ __global__ __launch_bounds__(256) void k_leaf_down(const cplx<R>* __restrict__ X
                                                    int nleaf, int nrhs) {
   __shared__ cplx<R> us[NV][LEAF_MAX];
   __shared__ cplx<R> ws[NV][LEAF_MAX];
+  __shared__ cplx<R> rl[NV][LEAF_MAX];  // r, then the result (stored to the grid together at the end)
   const long t = blockIdx.x, r0 = (long)blockIdx.y * NV;
   const int nv = nrhs - r0 < NV ? (int)(nrhs - r0) : NV;
   const I2 o = org[t];
   for (int a = threadIdx.x; a < k; a += blockDim.x)
 #pragma unroll
     for (int v = 0; v < NV; ++v) ws[v][a] = v < nv ? wt[((r0 + v) * nleaf + t) * (long)k + a] : mk<R>(0, 0);
+  for (int v = 0; v < nv; ++v)
+    for (int i = threadIdx.x; i < mL; i += blockDim.x) rl[v][i] = r[((r0 + v) * nleaf + t) * (long)mL + i];
   __syncthreads();
   for (int i = threadIdx.x; i < mL; i += blockDim.x) {
     cplx<R> acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
-    for (int a = 0; a < k; ++a) {
+#pragma unroll 8
+    for (int a = 0; a < k; ++a) {  // (unrolled: the U_L loads issued together)
       const cplx<R> u = UL[(long)i * k + a];
 #pragma unroll
       for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, ws[v][a]);
@@ -1470,11 +1475,14 @@ __global__ __launch_bounds__(256) void k_leaf_down(const cplx<R>* __restrict__ X
     for (int v = 0; v < NV; ++v) us[v][i] = bi * acc[v];
   }
   __syncthreads();
-  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) {
-    const cplx<R> val = r[((r0 + v) * nleaf + t) * (long)mL + i] - acc;
-    const I2 pi = pts[i];
-    q[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)val.x, (double)val.y);
-  });
+  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) { rl[v][i] = rl[v][i] - acc; });
+  __syncthreads();
+  for (int v = 0; v < nv; ++v)
+    for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+      const I2 pi = pts[i];
+      const cplx<R> val = rl[v][i];
+      q[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)val.x, (double)val.y);
+    }
 }
 
 template <typename R>
@@ -1513,7 +1521,8 @@ __global__ __launch_bounds__(256) void k_leaf_tdown(const cplx<R>* __restrict__ 
     cplx<R> acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
-    for (int a = 0; a < k; ++a) {
+#pragma unroll 8
+    for (int a = 0; a < k; ++a) {  // (unrolled: the U_L loads issued together)
       const cplx<R> u = UL[(long)i * k + a];
 #pragma unroll
       for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, ws[v][a]);
@@ -1528,10 +1537,15 @@ __global__ __launch_bounds__(256) void k_leaf_tdown(const cplx<R>* __restrict__ 
     }
   }
   __syncthreads();
-  leaf_rows<R, NV>(XT + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) {
-    const I2 pi = pts[i];
-    q[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)acc.x, (double)acc.y);
-  });
+  // (ws is free once us is built: it stages the results for one store pass)
+  leaf_rows<R, NV>(XT + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) { ws[v][i] = acc; });
+  __syncthreads();
+  for (int v = 0; v < nv; ++v)
+    for (int i = threadIdx.x; i < mL; i += blockDim.x) {
+      const I2 pi = pts[i];
+      const cplx<R> val = ws[v][i];
+      q[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)] = mk((double)val.x, (double)val.y);
+    }
 }
 
 template <typename R>
