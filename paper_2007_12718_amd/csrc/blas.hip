@@ -50,8 +50,8 @@ struct GemmP {
   int addI;
   const int* skip;  // optional device flag: the whole launch is a no-op when *skip != 0
   int lower;        // 1: only tiles that reach the diagonal or below it (M == N)
-  // split K (FP32 kernel only): grid z runs over (problem, K chunk); chunk ks
-  // of problem b writes alpha A[:, chunk] B[chunk, :] to part + (b nsplit + ks) M N
+  // split K (k_cgemm_x32_splitk): partial products [batch][nsplit][M][N],
+  // chunks of kchunk along K
   cplx<R>* part = nullptr;
   int nsplit = 1, kchunk = 0;
 };
@@ -363,25 +363,35 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {  // (WM,
   const int tm = (int)((L / gridDim.x) % gridDim.y);
   const long b = L / ((long)gridDim.x * gridDim.y);
   if (P.lower && tn * BN >= (tm + 1) * BM) return;  // strictly above the diagonal
-  if (P.part) {
-    const int ks = (int)(b % P.nsplit);
-    const long bb = b / P.nsplit;
-    const long k0 = (long)ks * P.kchunk;
-    const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
-    GemmP<float> Q = P;
-    Q.A = P.A + (aN ? k0 : k0 * P.lda);
-    Q.B = P.B + (bN ? k0 * P.ldb : k0);
-    Q.K = (int)(P.K - k0 < P.kchunk ? P.K - k0 : P.kchunk);
-    Q.C = P.part + b * (long)P.M * P.N;
-    Q.ldc = P.N;
-    Q.sC = 0;
-    Q.D = nullptr;
-    Q.beta = mk<float>(0, 0);
-    Q.addI = 0;
-    cgemm_x32_tile<WM, WN>(Q, bb, tm * BM, tn * BN);
-    return;
-  }
   cgemm_x32_tile<WM, WN>(P, b, tm * BM, tn * BN);
+}
+
+// Split K (64 x 64 tiles, XCD-aware order as above): grid z runs over
+// (problem, K chunk); chunk ks of problem b writes its partial product to
+// part + (b nsplit + ks) M N.
+__global__ __launch_bounds__(256, 2) void k_cgemm_x32_splitk(GemmP<float> P) {
+  const long T = (long)gridDim.x * gridDim.y * gridDim.z;
+  long L = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+  const long T8 = (T / 8) * 8;
+  if (L < T8) L = (L % 8) * (T / 8) + L / 8;
+  const int tn = (int)(L % gridDim.x);
+  const int tm = (int)((L / gridDim.x) % gridDim.y);
+  const long b = L / ((long)gridDim.x * gridDim.y);
+  const int ks = (int)(b % P.nsplit);
+  const long bb = b / P.nsplit;
+  const long k0 = (long)ks * P.kchunk;
+  const bool aN = (P.opA == OP_N || P.opA == OP_R), bN = (P.opB == OP_N || P.opB == OP_R);
+  GemmP<float> Q = P;
+  Q.A = P.A + (aN ? k0 : k0 * P.lda);
+  Q.B = P.B + (bN ? k0 * P.ldb : k0);
+  Q.K = (int)(P.K - k0 < P.kchunk ? P.K - k0 : P.kchunk);
+  Q.C = P.part + b * (long)P.M * P.N;
+  Q.ldc = P.N;
+  Q.sC = 0;
+  Q.D = nullptr;
+  Q.beta = mk<float>(0, 0);
+  Q.addI = 0;
+  cgemm_x32_tile<1, 1>(Q, bb, tm * 64, tn * 64);
 }
 
 // C = sum of the nsplit partial products + beta D (+ I)
@@ -554,7 +564,7 @@ void cgemm_ws(hipStream_t s, int M, int N, int K, cplx<R> alpha, const cplx<R>* 
         P.nsplit = nsplit;
         P.kchunk = kchunk;
         ProfScope ps("cgemm_f32_splitk", s, 8.0 * M * N * (double)K * batch);
-        hipLaunchKernelGGL((k_cgemm_x32<1, 1>), dim3(ceil_div(N, 64), ceil_div(M, 64), batch * nsplit), dim3(256), 0,
+        hipLaunchKernelGGL(k_cgemm_x32_splitk, dim3(ceil_div(N, 64), ceil_div(M, 64), batch * nsplit), dim3(256), 0,
                            s, P);
         LSH_LAUNCH_CHECK();
         const long total = (long)batch * M * N;

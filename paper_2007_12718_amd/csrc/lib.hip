@@ -780,13 +780,12 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
 }
 
 // up to this many box vectors the shared products stream the matrix rows
-// (multi-vector GEMV); above it they are MFMA GEMMs (a GEMV per vector and
-// row was slower at every level size measured, fourier-1024; 64 measured
-// best against 32, 128 and 256)
-static const int SKINNY = [] {
-  const char* e = std::getenv("LSH_SKINNY");
-  return e ? std::atoi(e) : 8;
-}();
+// (multi-vector GEMV); above it they are MFMA GEMMs, split along K when they
+// have few output tiles (FP32).  fourier-1024, one FP32 apply: 3.81 ms with
+// 64, 3.58 with 32, 3.50 with 16, 3.50 with 8, 3.48 with 4, 3.54 with 2.  The
+// FP64 products do not split, and stay on the GEMV up to 64 vectors.
+template <typename R>
+constexpr int skinny() { return sizeof(R) == 4 ? 8 : 64; }
 
 // Y[v] = alpha M X[v] + beta Z[v] for B vectors (strides ldx, ldz, ldy) and
 // one shared matrix M (rows x cols, row-major); (MtB, ldb, opB) give M^T as
@@ -795,7 +794,7 @@ template <typename R>
 void shared_mv(hipStream_t s, int rows, int cols, cplx<R> alpha, const cplx<R>* M, const cplx<R>* MtB, long ldb,
                Op opB, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy,
                int B, DevBuf& ws) {
-  if (B <= SKINNY)
+  if (B <= skinny<R>())
     cmgemv<R>(s, rows, cols, alpha, M, cols, X, ldx, beta, Z, ldz, Y, ldy, B);
   else
     cgemm_ws<R>(s, B, rows, cols, alpha, X, ldx, 0, OP_N, MtB, ldb, 0, opB, beta, Z, ldz, 0, Y, ldy, 0, 1, ws.p,
@@ -820,7 +819,7 @@ void apply_X_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, con
   const cplx<R>* Pm = P.W<R>(l, 0);  // [L; R]
   const cplx<R>* Qm = P.W<R>(l, 1);  // [L^T; R^T]
   if (!transposed) {
-    if (B <= SKINNY)
+    if (B <= skinny<R>())
       cmgemv2<R>(s, 2 * r, r, c, c, one, Qm, c, in, 2 * c, zero, nullptr, 0, q, 2 * r, B);
     else  // two strided products: (a, L) and (b, R)
       cgemm_ws<R>(s, B, r, c, one, in, 2 * c, c, OP_N, Pm, r, cr, OP_N, zero, nullptr, 0, 0, q, 2 * r, r, 2, F.tk.p,
@@ -832,7 +831,7 @@ void apply_X_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, con
     cgemv<R>(s, r, c, one, F.PaT[l].template as<cplx<R>>(), c, cr, 2 * nb, in, c, zero, nullptr, 0, q, r, 2 * B);
     cgemv<R>(s, 2 * r, 2 * r, one, F.CiT[l].template as<cplx<R>>(), 2 * r, w4, nb, q, 2 * r, zero, nullptr, 0, y,
              2 * r, B);
-    if (B <= SKINNY)
+    if (B <= skinny<R>())
       cmgemv2<R>(s, 2 * c, c, r, r, mone, Pm, r, y, 2 * r, one, in, 2 * c, out, 2 * c, B);
     else  // (z2, L^T) -> a, (z1, R^T) -> b
       cgemm_ws<R>(s, B, c, r, mone, y, 2 * r, r, OP_N, Qm, c, cr, OP_N, one, in, 2 * c, c, out, 2 * c, c, 2,
