@@ -26,8 +26,8 @@ int lsh_dev_gemm(int prec, int M, int N, int K, const double* alpha, const void*
                  void* C, long ldc, long sC, int batch, void* stream);
 
 /* As lsh_dev_gemm, with ws (device, ws_bytes) as scratch for the partial
- * products: an FP32 product with fewer than 128 output tiles of 64 x 64 and
- * K >= 128 splits K over workgroups (as the preconditioner's shared box
+ * products: an FP32 product with fewer than 256 output tiles of 64 x 64 and
+ * K >= 64 splits K over workgroups (as the preconditioner's shared box
  * products do); otherwise, or without room in ws, it is lsh_dev_gemm.  ws
  * must not be in use by other work on the device until the call's work on
  * the stream has finished. */

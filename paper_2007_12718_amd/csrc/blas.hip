@@ -532,11 +532,13 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
 }
 
 // Products with too few output tiles to fill the device (shared box
-// matrices at the upper levels: a few hundred boxes times a few hundred
-// rows) split K over workgroups into ws, then sum the partial tiles.
-constexpr long SPLIT_TILES = 128;  // split below this many 64 x 64 output tiles
+// matrices: a few hundred boxes times a few hundred rows at the upper
+// levels, thousands of boxes times a few dozen rows at the lower ones)
+// split K over workgroups into ws, then sum the partial tiles.
+// (fourier-1024, one FP32 apply: 3.38 ms without the 32 < K < 128 and 128..255-tile splits, 3.19 ms with them)
+constexpr long SPLIT_TILES = 256;  // split below this many 64 x 64 output tiles
 constexpr long SPLIT_WG = 512;     // aim for about this many workgroups
-constexpr int SPLIT_KMIN = 64;     // at least two K tiles per chunk
+constexpr int SPLIT_KMIN = 32;     // at least one K tile per chunk
 
 template <typename R>
 void cgemm_ws(hipStream_t s, int M, int N, int K, cplx<R> alpha, const cplx<R>* A, long lda, long sA, Op opA,

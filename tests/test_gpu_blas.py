@@ -35,11 +35,12 @@ def test_gemm_matches_definition(prec, opA, opB):
 
 
 @pytest.mark.parametrize("opA,opB", [(0, 0), (0, 1), (2, 3)])
-@pytest.mark.parametrize("M,N,K,B", [(300, 379, 502, 1), (128, 70, 1990, 2), (70, 64, 130, 1), (65, 1, 4100, 3)])
+@pytest.mark.parametrize("M,N,K,B", [(300, 379, 502, 1), (128, 70, 1990, 2), (70, 64, 130, 1), (65, 1, 4100, 3),
+                                     (300, 379, 100, 1), (4096, 58, 70, 2), (512, 45, 40, 1)])
 def test_split_k_gemm_matches_definition(opA, opB, M, N, K, B):
     """Few output tiles: the FP32 product splits K over workgroups (chunks of
     whole K tiles, a ragged last chunk, partial sums reduced with beta D).
-    With too little scratch it falls back to the unsplit kernel."""
+    With too little scratch, or K below two K tiles, it is the unsplit kernel."""
     import torch
     from paper_2007_12718_amd import lsh
     rng = np.random.default_rng(M + N + K + opA)
