@@ -127,3 +127,26 @@ def test_adjoint_gradient_matches_finite_differences():
         fd = (dense.misfit_loss_and_grad(n, kappa, order, bp, U, pts, tgt)[0]
               - dense.misfit_loss_and_grad(n, kappa, order, bm, U, pts, tgt)[0]) / (2 * eps)
         assert g[k] == pytest.approx(fd, rel=1e-6)
+
+
+def test_receiver_sum_matches_disk_series_off_grid():
+    """The off-grid receiver sum u(x) = h^2 sum_j (i/4) H0(kappa |x - x_j|) sigma_j
+    (eq. (ansatz), trapezoidal) against the transmission series of a constant-b
+    disk (Remark 1.1) at 16 points off the grid: 8 outside the domain (radius
+    0.7) and 8 inside it but outside the disk (radius 0.42), at angles with no
+    symmetry in x1 <-> x2 or x -> -x.  b is discontinuous, so the error falls
+    like O(h); a dropped h^2, a missing i/4, swapped coordinates or a flipped
+    offset would leave an O(1) error."""
+    kappa, b0, a = 4 * np.pi, 0.5, 0.3
+    th = np.linspace(0, 2 * np.pi, 8, endpoint=False) + 0.37
+    pts = np.concatenate([np.stack([0.7 * np.cos(th), 0.7 * np.sin(th)], 1),
+                          np.stack([0.42 * np.cos(th + 0.2), 0.42 * np.sin(th + 0.2)], 1)])
+    exact = disk.total_field(kappa, b0, a, pts[:, 0], pts[:, 1]) - np.exp(1j * kappa * pts[:, 0])
+    errs = []
+    for n in (24, 72):
+        X1, X2, h = dense.grid(n)
+        b = np.where(np.hypot(X1, X2) < a, b0, 0.0)
+        sig, _ = dense.DenseSolver(n, kappa, 4, b).solve(np.exp(1j * kappa * X1)[None])
+        up = dense.receiver_matrix(n, kappa, pts) @ sig[0]
+        errs.append(np.abs(up - exact).max() / np.abs(exact).max())
+    assert errs[1] < 5e-3 and errs[0] / errs[1] > 4, errs
