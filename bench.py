@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-HBS comparison form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=512, help="grid side of the oracle's timed sample")
+    ap.add_argument("--cpu-n", type=int, default=0,
+                    help="grid side of the oracle's timed run (default: the workload's own n)")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel hipEvent records")
     ap.add_argument("--separate", action="store_true",
                     help="lsh_plan_create + lsh_factor_create instead of the pipelined lsh_build")
@@ -151,31 +152,55 @@ def kernel_table(lsh):
     return rows
 
 
+def host_cpu():
+    """CPU model name (from /proc/cpuinfo, as lscpu reports it) and logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(n_full, n_sample):
-    """The oracle (numpy/scipy, as written) on a bounded sample: the same
-    workload family at n_sample (same kappa*h), plan + build + FGMRES to 1e-10;
-    scaled to n_full by the O(N^{3/2}) = O(n^3) cost of the method."""
+    """The oracle (numpy/scipy, as written) timed on the host: plan + build +
+    FGMRES to 1e-10 on the workload at n_sample (by default the headline size
+    itself, so the value is measured, not scaled; a smaller n_sample keeps
+    kappa*h and is scaled by the method's O(N^{3/2}) = O(n^3) cost)."""
     import numpy as np
     from oracle import dense, fftop, gmres, hbs
     w = workload(n_sample)
     hbs.Compression(16, w.kappa, 8, w.tol, w.proxy_width)  # warm the weight constants
     t0 = time.perf_counter()
     C = hbs.Compression(w.n, w.kappa, w.leaf, w.tol, w.proxy_width)
+    t1 = time.perf_counter()
+    print(f"# cpu_baseline n={w.n}: plan {t1 - t0:.1f} s", file=sys.stderr, flush=True)
     M = hbs.Inverse(C, w.b)
+    t2 = time.perf_counter()
+    print(f"# cpu_baseline n={w.n}: build {t2 - t1:.1f} s", file=sys.stderr, flush=True)
     F = fftop.FFTOperator(w.n, w.kappa, w.op_order)
     f = dense.rhs(w.b, w.u_inc, w.kappa)
     x, it, hist = gmres.fgmres(lambda v: F.apply(w.b, v).reshape(-1), M.apply, f, w.gmres_tol, 100)
     dt = time.perf_counter() - t0
+    res = float(np.linalg.norm(f - F.apply(w.b, x).reshape(-1)) / np.linalg.norm(f))
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count()
+        blas = os.cpu_count()
+    model, ncpu = host_cpu()
     scale = (n_full / n_sample) ** 3
-    return {"value": dt * scale, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle plan+build+FGMRES at n={n_sample} (N={n_sample ** 2}, same kappa*h), "
-                      f"{dt:.2f} s measured, {it} iterations, scaled by (n/{n_sample})^3 = {scale:.0f} "
-                      f"to n={n_full}; host cpu_count={os.cpu_count()}"}
+    how = "measured" if scale == 1 else f"{dt:.2f} s measured at n={n_sample}, scaled by (n/{n_sample})^3 = {scale:.0f}"
+    return {"value": dt * scale, "unit": "s", "cores": blas, "kind": "oracle",
+            "sample": f"oracle plan + build + FGMRES to 1e-10 on the full workload at n={n_sample} "
+                      f"(N={n_sample ** 2}): {how}; plan {t1 - t0:.1f} s, build {t2 - t1:.1f} s, "
+                      f"FGMRES {dt - (t2 - t0):.1f} s, {it} iterations, residual {res:.1e}; LAPACK/BLAS "
+                      f"threads {blas} (numpy FFT single-threaded); host '{model}', os.cpu_count()={ncpu}",
+            "host_cpu": model, "cpu_count": ncpu}
 
 
 def batched_run(a):
@@ -459,6 +484,7 @@ def main():
                                f"operator order {w.op_order}, GMRES tol {w.gmres_tol}",
                    "hbs_prec": "fp32", "merge": a.merge, "phases_s": {k: head["median"][k] for k in
                                                     ("build_s", "plan_s", "factor_s", "solve_s", "total_s")},
+                   "step_median_s": head["median"]["total_s"],
                    "iterations": head["median"]["iterations"],
                    "true_residual": head["median"]["true_residual"],
                    "ranks": head["median"]["ranks"]},
@@ -477,7 +503,7 @@ def main():
         out["kernels"] = prof["kernels"]
         out["kernels_from"] = prof["kernels_from"]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w.n, min(a.cpu_n, w.n))
+        out["cpu_baseline"] = cpu_baseline(w.n, min(a.cpu_n or w.n, w.n))
     print(json.dumps(out))
     return 0
 

@@ -1,6 +1,5 @@
 // HBS compression (paper Sec. 3.2), leaf factor (Alg. 1, leaf loop) and the
 // leaf steps of the apply (Alg. 2) on gfx950.
-#include <hip/hip_cooperative_groups.h>
 
 #include <cmath>
 #include <cstdlib>
@@ -290,110 +289,6 @@ __global__ __launch_bounds__(QR_NT) void k_pchol_panel(const z64* __restrict__ M
   if (!stop && tid == 0) state[0] = j0 + nb;
 }
 
-// Cooperative panel: G workgroups own contiguous row slices (<= PC_RPW rows,
-// their panel entries kept in LDS); one grid-wide sync per pivot.  Candidate
-// (d, index) slots are double buffered by step parity.
-constexpr int PC_NT = 256, PC_RPW = 112, PC_NB = 32;
-
-__global__ __launch_bounds__(PC_NT) void k_pchol_coop(const z64* __restrict__ M, int m, double* d, int* chosen,
-                                                      z64* Lt, int* piv, int j0, int nb, double thr2, int* state,
-                                                      double* cval, int* cidx) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
-  __shared__ z64 Lp[PC_RPW][PC_NB];
-  __shared__ double ds[PC_RPW];
-  __shared__ int cs[PC_RPW];
-  __shared__ z64 lpiv[PC_NB];
-  __shared__ double wv[PC_NT / 64];
-  __shared__ int wi[PC_NT / 64];
-  __shared__ int s_p;
-  __shared__ double s_d;
-  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (state[1]) return;  // uniform: written only by earlier launches
-  const int rpw = (m + G - 1) / G;
-  const int r0 = g * rpw, r1 = (r0 + rpw < m) ? r0 + rpw : m;
-  for (int i = r0 + tid; i < r1; i += PC_NT) {
-    ds[i - r0] = d[i];
-    cs[i - r0] = chosen[i];
-  }
-  __syncthreads();
-  auto local_argmax = [&](int slot) {
-    double best = -1;
-    int bi = m;
-    for (int i = r0 + tid; i < r1; i += PC_NT)
-      if (!cs[i - r0]) {
-        const double a = ds[i - r0];
-        if (a > best || (a == best && i < bi)) { best = a; bi = i; }
-      }
-    wave_argmax_d(best, bi);
-    if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double bb = wv[0];
-      int ii = wi[0];
-      for (int w = 1; w < PC_NT / 64; ++w)
-        if (wv[w] > bb || (wv[w] == bb && wi[w] < ii)) { bb = wv[w]; ii = wi[w]; }
-      cval[slot * G + g] = bb;
-      cidx[slot * G + g] = ii;
-    }
-  };
-  local_argmax(0);
-  grid.sync();
-  int jj = 0;
-  for (; jj < nb; ++jj) {
-    const int j = j0 + jj;
-    if (j >= m) break;
-    if (tid == 0) {
-      const int slot = jj & 1;
-      double bb = cval[slot * G];
-      int ii = cidx[slot * G];
-      for (int w = 1; w < G; ++w) {
-        const double v = cval[slot * G + w];
-        const int x = cidx[slot * G + w];
-        if (v > bb || (v == bb && x < ii)) { bb = v; ii = x; }
-      }
-      s_p = ii;
-      s_d = bb;
-    }
-    __syncthreads();
-    const int p = s_p;
-    const double dp = s_d;
-    if (!(dp > thr2)) {  // uniform: every workgroup read the same slots
-      if (g == 0 && tid == 0) { state[0] = j; state[1] = 1; }
-      break;
-    }
-    for (int t = tid; t < jj; t += PC_NT) lpiv[t] = Lt[(long)(j0 + t) * m + p];
-    __syncthreads();
-    const double sq = sqrt(dp), rs = 1.0 / sq;
-    for (int i = r0 + tid; i < r1; i += PC_NT) {
-      z64 l;
-      if (i == p) {
-        l = mk(sq, 0.0);
-        cs[i - r0] = 1;
-        ds[i - r0] = 0;
-        piv[j] = p;
-      } else if (cs[i - r0]) {
-        l = mk(0.0, 0.0);
-      } else {
-        l = conjg(M[(long)p * m + i]);
-        for (int t = 0; t < jj; ++t) l = l - Lp[i - r0][t] * conjg(lpiv[t]);
-        l = rs * l;
-        ds[i - r0] -= abs2(l);
-      }
-      Lp[i - r0][jj] = l;
-      Lt[(long)j * m + i] = l;
-    }
-    __syncthreads();
-    local_argmax((jj + 1) & 1);
-    grid.sync();
-  }
-  for (int i = r0 + tid; i < r1; i += PC_NT) {
-    d[i] = ds[i - r0];
-    chosen[i] = cs[i - r0];
-  }
-  if (jj == nb && g == 0 && tid == 0) state[0] = j0 + nb;
-  if (j0 + jj >= m && g == 0 && tid == 0) { state[0] = m; state[1] = 1; }
-}
 
 __global__ void k_gather_L11(const z64* Lt, int m, const int* piv, int k, z64* L11) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -1213,40 +1108,18 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
   static const int nb = [] {
     const char* e = std::getenv("LSH_PCHOL_NB");
     int v = e ? std::atoi(e) : 16;
-    return (v >= 4 && v <= PC_NB && v <= PCH_NB) ? v : 16;
+    return (v >= 4 && v <= PCH_NB) ? v : 16;
   }();
   int rank = 0;
-  // one-workgroup panels by default (per-pivot cost is one workgroup's L2
-  // stream of the panel, ~m * nb / 2 entries); LSH_COOP=1 selects the
-  // cooperative multi-workgroup panel (one grid sync per pivot), which
-  // profilers may fail to finalise after.
-  static const bool coop_env = [] {
-    const char* e = std::getenv("LSH_COOP");
-    return e && e[0] == '1';
-  }();
-  bool coop_ok = coop_env && ceil_div(m, PC_RPW) <= 240;
-  double* cval = static_cast<double*>(take(sizeof(double) * 2 * 256));
-  int* cidx = static_cast<int*>(take(sizeof(int) * 2 * 256));
-  // All panels and trailing updates are queued at once: each panel kernel
+  // One workgroup per panel: the per-pivot cost is one workgroup's L2
+  // stream of the panel, ~m * nb / 2 entries.  All panels and trailing updates are queued at once: each panel kernel
   // returns at entry once state[1] (done) is set, and each update is skipped
   // through the same flag, so the host reads the rank once per level.
   for (int j0 = 0; j0 < m; j0 += nb) {
     {
       ProfScope ps("pchol_panel", s, 16.0 * (double)m * nb);
-      bool done = false;
-      if (coop_ok) {
-        int G = ceil_div(m, PC_RPW);
-        const z64* Mc = M;
-        int mm = m, jj0 = j0, nbb = nb;
-        double t2 = thr2;
-        void* args[] = {(void*)&Mc, &mm, &d, &chosen, &Lt, &J, &jj0, &nbb, &t2, &state, &cval, &cidx};
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_pchol_coop, dim3(G), dim3(PC_NT), args, 0, s);
-        if (e == hipSuccess) done = true;
-        else { (void)hipGetLastError(); coop_ok = false; }
-      }
-      if (!done)
-        hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), (size_t)m * (sizeof(double) + 1), s, M, m, d, chosen,
-                           Lt, J, j0, nb, thr2, state);
+      hipLaunchKernelGGL(k_pchol_panel, dim3(1), dim3(QR_NT), (size_t)m * (sizeof(double) + 1), s, M, m, d, chosen,
+                         Lt, J, j0, nb, thr2, state);
     }
     LSH_LAUNCH_CHECK();
     if (j0 + nb < m)  // trailing update of the Schur complement: M -= Lp Lp^H

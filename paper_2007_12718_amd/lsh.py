@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblsh.so")
 
 LSH_OK, LSH_NOT_CONVERGED = 0, 1
+(LSH_ERR_INVALID_ARG, LSH_ERR_INPUT_NONFINITE, LSH_ERR_SINGULAR, LSH_ERR_HIP, LSH_ERR_NOMEM,
+ LSH_ERR_UNSUPPORTED) = -1, -2, -3, -4, -5, -6
 LSH_FP64, LSH_FP32 = 0, 1
 MAX_ITERS = 200
 MAX_LEVELS = 32

@@ -52,7 +52,7 @@ def test_offset_table(small):
     assert err.max() <= 1e-13, err.max()
 
 
-@pytest.mark.parametrize("n,order,use_b", [(20, 10, True), (32, 6, True), (32, 8, False), (33, 4, True)])
+@pytest.mark.parametrize("n,order,use_b", [(20, 10, True), (32, 6, True), (32, 8, False), (24, 4, True)])
 def test_operator_matches_dense(n, order, use_b):
     from paper_2007_12718_amd import lsh
     rng = np.random.default_rng(n + order)
@@ -62,8 +62,6 @@ def test_operator_matches_dense(n, order, use_b):
     leaf = 4 if n % 4 == 0 and (n // 4) & (n // 4 - 1) == 0 else (n if n < 12 else 3)
     if n == 20:
         leaf = 5
-    if n == 33:
-        pytest.skip("33 has no power-of-two leaf split")
     P = lsh.Plan(n, kappa, op_order=order, leaf=leaf, tol=1e-4, proxy_width=2, prec="fp64")
     y = P.apply_operator(cuda(b) if use_b else None, cuda(x)).cpu().numpy()
     K = dense.dense_K(n, kappa, order)
@@ -247,3 +245,47 @@ def test_cached_buffers_give_identical_factor(prec):
     y3, yt3 = run(b1)
     assert np.array_equal(y1, y3) and np.array_equal(yt1, yt3)
     assert lsh.cache_trim() > 0
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_not_converged_returns_best_iterate(nrhs):
+    """maxit below what the tolerance needs: LSH_NOT_CONVERGED, and sigma is
+    the FGMRES iterate after maxit steps, whose true residual is reported and
+    lies between the tolerance and the residual of x0 = 0."""
+    from paper_2007_12718_amd import lsh
+    n, kappa = 32, 2 * np.pi * 4
+    b = synth.bumps(n, np.random.default_rng(5))
+    U = np.stack([synth.plane_wave(n, kappa, t) for t in np.linspace(0, 2, nrhs)])
+    P = lsh.Plan(n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32")
+    F = lsh.Factor(P, cuda(b))
+    sig, _, info, rc = F.solve(cuda(U), tol=1e-13, maxit=2, want_u=False)
+    assert rc == lsh.LSH_NOT_CONVERGED
+    assert info.iterations == 2 and 1e-13 < info.true_residual < 1.0
+    A = dense.dense_A(b, dense.dense_K(n, kappa, 10), kappa)
+    for r in range(nrhs):
+        f = dense.rhs(b, U[r], kappa)
+        res = np.linalg.norm(f - A @ sig[r].cpu().numpy().reshape(-1)) / np.linalg.norm(f)
+        assert 1e-13 < res < 1.0 and res <= info.true_residual * (1 + 1e-6)
+    # the same factor then converges with enough iterations
+    sig2, _, info2, rc2 = F.solve(cuda(U), tol=1e-12, maxit=50, want_u=False)
+    assert rc2 == lsh.LSH_OK and info2.true_residual < 1e-12
+
+
+def test_nonfinite_b_rejected_by_factor_and_build():
+    from paper_2007_12718_amd import lsh
+    n, kappa = 32, 2 * np.pi * 4
+    b = synth.gaussian_b(n)
+    for bad in (np.nan, np.inf):
+        bb = b.copy()
+        bb[7, 3] = bad
+        P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec="fp32")
+        with pytest.raises(lsh.LshError) as e1:
+            lsh.Factor(P, cuda(bb))
+        assert e1.value.code == lsh.LSH_ERR_INPUT_NONFINITE
+        with pytest.raises(lsh.LshError) as e2:
+            lsh.build(n, kappa, cuda(bb), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec="fp64")
+        assert e2.value.code == lsh.LSH_ERR_INPUT_NONFINITE
+        # the plan is still usable after the failed factor
+        F = lsh.Factor(P, cuda(b))
+        sig, _, info, rc = F.solve(cuda(synth.plane_wave(n, kappa)[None]), tol=1e-10)
+        assert rc == lsh.LSH_OK
