@@ -75,26 +75,45 @@ def workload(n):
     return synth.largest(n=n, kappa=200 * np.pi * n / 1024)
 
 
+_WS = {}
+
+
+def workspaces(lsh, w, prec, merge):
+    """The device workspaces of one form (plan, factor, solve), allocated once
+    and reused by every step: the library itself allocates nothing."""
+    key = (w.n, prec, merge)
+    if key not in _WS:
+        pw, fw = lsh.build_workspaces(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol,
+                                      proxy_width=w.proxy_width, prec=prec, merge=merge)
+        _WS[key] = {"plan": pw, "factor": fw, "solve": None}
+    return _WS[key]
+
+
 def run_step(lsh, w, b_d, u_d, prec, torch, separate=False, merge="auto"):
+    ws = workspaces(lsh, w, prec, merge)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if separate:  # lsh_plan_create then lsh_factor_create
         P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width,
-                     prec=prec, merge=merge)
+                     prec=prec, merge=merge, ws=ws["plan"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        F = lsh.Factor(P, b_d)
+        F = lsh.Factor(P, b_d, ws=ws["factor"])
     else:  # lsh_build: the same plan and factor, pipelined by level
         P, F = lsh.build(w.n, w.kappa, b_d, op_order=w.op_order, leaf=w.leaf, tol=w.tol,
-                         proxy_width=w.proxy_width, prec=prec, merge=merge)
+                         proxy_width=w.proxy_width, prec=prec, merge=merge, workspaces=(ws["plan"], ws["factor"]))
         t1 = None
+    if ws["solve"] is None:  # (first, untimed warmup step)
+        ws["solve"] = lsh.workspace(F.solve_workspace_bytes(1, 100))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    sig, _, info, rc = F.solve(u_d, tol=w.gmres_tol, maxit=100, want_u=False)
+    sig, _, info, rc = F.solve(u_d, tol=w.gmres_tol, maxit=100, want_u=False, ws=ws["solve"])
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     out = {"build_s": t2 - t0, "plan_s": (t1 - t0) if t1 else None, "factor_s": (t2 - t1) if t1 else None,
            "solve_s": t3 - t2, "total_s": t3 - t0,
+           "solve_ms_precond": info.ms_precond, "solve_ms_operator": info.ms_operator,
+           "solve_ms_ortho": info.ms_ortho,
            "iterations": info.iterations, "true_residual": info.true_residual, "rc": rc,
            "ranks": P.ranks()[1], "lowrank_ranks": P.lowrank_ranks()}
     F.close()

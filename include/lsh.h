@@ -25,13 +25,21 @@
  *  - Array pointers are DEVICE pointers owned by the caller unless the
  *    argument says "host".  The library reads inputs and writes outputs only
  *    on the given stream; it keeps no reference to caller arrays after a call
- *    returns, except that a factor keeps a private copy of b.
- *  - Handles own their device memory (allocated by the library with
- *    hipMalloc); destroy them with the matching *_destroy call.  A factor
- *    refers to its plan: destroy the factor first.  A destroy call
- *    synchronises the device once and keeps the handle's buffers in a
- *    per-process cache (at most LSH_CACHE_BYTES bytes, default 32 GiB; 0
- *    disables it) for the next plan or factor; lsh_cache_trim frees them.
+ *    returns, except for the workspaces of handles (below).
+ *  - The library allocates no device memory.  Each plan, factor and solve
+ *    works in a device workspace that the caller owns: query its size with
+ *    the matching lsh_*_workspace call (host-only), allocate it (e.g. a
+ *    torch tensor; 256-byte aligned, any contents), and pass the pointer and
+ *    its size.  A plan or factor workspace belongs to its handle until the
+ *    handle is destroyed (a handle is invalid once its workspace is freed);
+ *    a solve workspace is in use until the call's work on the stream is
+ *    done.  A workspace smaller than the query gives
+ *    LSH_ERR_WORKSPACE_TOO_SMALL.  Plan sizes are upper bounds (the ranks
+ *    are found while the plan is built; lsh_plan_workspace_used reports what
+ *    was used); factor and solve sizes are exact for the given plan.
+ *  - Handles are small host objects; destroy them with the matching
+ *    *_destroy call (host only; the workspace stays the caller's).  A
+ *    factor refers to its plan: destroy the factor first.
  *  - The stream is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls that must read back small device values synchronise the stream
  *    and say so.
@@ -57,8 +65,15 @@ enum {
   LSH_ERR_SINGULAR = -3,
   LSH_ERR_HIP = -4,
   LSH_ERR_NOMEM = -5,
-  LSH_ERR_UNSUPPORTED = -6
+  LSH_ERR_UNSUPPORTED = -6,
+  LSH_ERR_WORKSPACE_TOO_SMALL = -7
 };
+
+/* factor flags: LSH_FACTOR_TRANSPOSE reserves room in the factor's workspace
+ * for the transposed copies that M^T needs (lsh_apply_precond with
+ * transpose = 1, lsh_solve_adjoint); without it those calls fail with
+ * LSH_ERR_INVALID_ARG. */
+#define LSH_FACTOR_TRANSPOSE 1
 
 enum { LSH_FP64 = 0, LSH_FP32 = 1 };
 
@@ -112,7 +127,10 @@ typedef struct {
   double residual;                      /* Givens estimate at exit (last rhs) */
   double true_residual;                 /* max over rhs of ||f - A sigma|| / ||f|| */
   double history[LSH_MAX_ITERS + 1];    /* residual estimates of the last rhs */
-  double ms_precond, ms_operator, ms_ortho;  /* reserved (set to 0) */
+  double ms_precond, ms_operator, ms_ortho;  /* time on the stream (hipEvents) in the
+                                               preconditioner applies, the FFT operator
+                                               applies and the Gram-Schmidt passes of the
+                                               call (all right-hand sides) */
 } lsh_info;
 
 /* ---- plan: paper Sec. 3 (tree, proxy-source IDs; independent of b) ----
@@ -126,9 +144,15 @@ typedef struct {
  * whose Schur diagonal is at least LSH_BP_ALPHA (default 0.75; 1 = greedy)
  * times the largest; LSH_ROWID=panel pivots greedily one row at a time.
  * Errors: LSH_ERR_INVALID_ARG for a bad descriptor or LSH_BP_ALPHA outside
- * (0, 1]; LSH_ERR_UNSUPPORTED for sizes beyond the kernels' limits. */
-int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan);
+ * (0, 1]; LSH_ERR_UNSUPPORTED for sizes beyond the kernels' limits;
+ * LSH_ERR_WORKSPACE_TOO_SMALL.
+ * ws: device workspace of at least lsh_plan_workspace bytes (ws_bytes its
+ * size), the plan's memory until lsh_plan_destroy. */
+int lsh_plan_workspace(const lsh_desc* desc, size_t* bytes /* host */);
+int lsh_plan_create(const lsh_desc* desc, void* ws, size_t ws_bytes, void* stream, lsh_plan_t* plan);
 int lsh_plan_destroy(lsh_plan_t plan);
+/* host: bytes of the plan's workspace used at most so far, and its size */
+int lsh_plan_workspace_used(lsh_plan_t plan, size_t* used, size_t* size);
 /* host: number of levels L and the ranks k_l (l = 0..L; k_0 = 0) */
 int lsh_plan_ranks(lsh_plan_t plan, int* L, int* ranks /* host, L+1 */);
 /* host: level-l compression data for inspection.  m = candidate rows,
@@ -156,9 +180,10 @@ int lsh_plan_lowrank(lsh_plan_t plan, int level, int* c, int* r, void* L, void* 
  * proxy_width, hbs_order and pivoting rule (LSH_ROWID, LSH_BP_ALPHA), and
  * store the ones they compute; a hit copies the pivots and U instead of
  * computing them, so later plans on other b, or on other grids with the same
- * kappa h, skip the row IDs.  Entries live on the device they were made on.
- * Not safe against a concurrent lsh_plan_cache_clear or _load. */
-int lsh_plan_cache_info(int* entries, size_t* device_bytes);
+ * kappa h, skip the row IDs.  Entries live in host memory (the only memory
+ * the library owns) and are keyed by device.  Not safe against a concurrent
+ * lsh_plan_cache_clear or _load. */
+int lsh_plan_cache_info(int* entries, size_t* host_bytes);
 int lsh_plan_cache_clear(void);
 /* host: writes every entry to a file (binary: pivots, candidates, U) /
  * reads a file written by lsh_plan_cache_save into the cache of the current
@@ -168,9 +193,16 @@ int lsh_plan_cache_save(const char* path);
 int lsh_plan_cache_load(const char* path);
 
 /* ---- factor: Algorithm 1 (leaf inverses, scattering matrices, merges) ----
- * b: device double[n*n].  Errors: LSH_ERR_INPUT_NONFINITE (non-finite b),
- * LSH_ERR_SINGULAR (zero pivot in a local inverse). */
-int lsh_factor_create(lsh_plan_t plan, const double* b, void* stream, lsh_factor_t* factor);
+ * b: device double[n*n].  flags: 0 or LSH_FACTOR_TRANSPOSE.  ws: device
+ * workspace of at least lsh_factor_workspace(plan, flags) bytes, the
+ * factor's memory until lsh_factor_destroy (it holds the factor, a copy of
+ * b and the apply vectors).  Errors: LSH_ERR_INPUT_NONFINITE (non-finite b),
+ * LSH_ERR_SINGULAR (zero pivot in a local inverse),
+ * LSH_ERR_WORKSPACE_TOO_SMALL. */
+int lsh_factor_workspace(lsh_plan_t plan, int flags, size_t* bytes /* host */);
+int lsh_factor_create(lsh_plan_t plan, const double* b, int flags, void* ws, size_t ws_bytes, void* stream,
+                      lsh_factor_t* factor);
+int lsh_factor_workspace_used(lsh_factor_t factor, size_t* used, size_t* size);
 
 /* Plan and factor in one call, pipelined by level: the factor of level l
  * (Algorithm 1) starts as soon as the row ID and sibling block of level l
@@ -182,8 +214,14 @@ int lsh_factor_create(lsh_plan_t plan, const double* b, void* stream, lsh_factor
  * kept off LSH_PLAN_CUS compute units (default: an eighth of them for FP32
  * factors, none for FP64; 0 = the caller's stream, unmasked), so that the
  * plan's latency-bound kernels find free units while the factor's products
- * fill the rest. */
-int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* plan, lsh_factor_t* factor);
+ * fill the rest.  The factor starts before the ranks are known, so both
+ * workspaces are sized by the plan's rank bounds (lsh_build_workspace:
+ * plan_bytes as lsh_plan_workspace, factor_bytes at least what
+ * lsh_factor_workspace would give once the plan exists).
+ * Errors: as lsh_plan_create and lsh_factor_create. */
+int lsh_build_workspace(const lsh_desc* desc, int flags, size_t* plan_bytes, size_t* factor_bytes);
+int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, size_t plan_ws_bytes,
+              void* factor_ws, size_t factor_ws_bytes, void* stream, lsh_plan_t* plan, lsh_factor_t* factor);
 int lsh_factor_destroy(lsh_factor_t factor);
 
 /* Algorithm 1 for ninst independent problems at once (many uneven instances:
@@ -195,13 +233,24 @@ int lsh_factor_destroy(lsh_factor_t factor);
  * instance at step d) and each product and inverse of a step is one grouped
  * launch over all instances' boxes; the results equal per-instance
  * lsh_factor_create bitwise.  FP64 plans are factored one by one.
+ * Workspaces: ws[i] (device, ws_bytes[i] bytes; host arrays of ninst) is
+ * instance i's factor workspace, as for lsh_factor_create; shared_ws
+ * (shared_bytes) holds the grouped launches' tables, flags and inverse
+ * workspace during the call.  lsh_batch_factor_workspace writes the
+ * sizes (factor_bytes: host size_t[ninst]).
  * Synchronises the stream.  Errors: as lsh_factor_create (the message names
  * the instance); on error no handle is returned. */
-int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b, void* stream,
+int lsh_batch_factor_workspace(int ninst, const lsh_plan_t* plans, int flags, size_t* factor_bytes,
+                               size_t* shared_bytes);
+int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b, int flags, void* const* ws,
+                     const size_t* ws_bytes, void* shared_ws, size_t shared_bytes, void* stream,
                      lsh_factor_t* factors);
 
-/* y = M x: Algorithm 2 (M ~ (I + B G)^{-1}); transpose = 1 applies M^T.
- * x, y: device double2[nrhs*n*n]; x and y must not overlap. */
+/* y = M x: Algorithm 2 (M ~ (I + B G)^{-1}); transpose = 1 applies M^T
+ * (needs LSH_FACTOR_TRANSPOSE; the first such call builds the transposed
+ * copies in the factor's workspace and synchronises the stream).
+ * x, y: device double2[nrhs*n*n]; x and y must not overlap.  Uses the
+ * factor's apply vectors: calls on one factor must not overlap. */
 int lsh_apply_precond(lsh_factor_t factor, int transpose, const void* x, void* y, int nrhs, void* stream);
 
 /* y = A x = x + kappa^2 b (K * x), K of order op_order, by FFT (Sec. 5);
@@ -213,21 +262,25 @@ int lsh_apply_operator(lsh_plan_t plan, const double* b, const void* x, void* y,
  * nrhs >= 2: groups of up to 8 right-hand sides run in lockstep (one
  * preconditioner and one operator application per iteration for the whole
  * group; each right-hand side keeps its own Krylov basis and stopping
- * test, so it takes the iterations of its own one-column solve); the
- * factor keeps (2 maxit + 1) min(nrhs, 8) n^2 complex FP64 values of
- * Krylov workspace.  Synchronises once per iteration (residual read-back).
- * Returns LSH_NOT_CONVERGED if some rhs did not reach opts->tol. */
+ * test, so it takes the iterations of its own one-column solve).
+ * ws: device workspace of lsh_solve_workspace(factor, nrhs, opts->maxit)
+ * bytes (the Krylov bases: about (2 maxit + 3) min(nrhs, 8) n^2 complex FP64
+ * values).  Synchronises once per iteration (residual read-back).
+ * Returns LSH_NOT_CONVERGED if some rhs did not reach opts->tol; sigma
+ * then holds the last iterate and info->true_residual its residual. */
+int lsh_solve_workspace(lsh_factor_t factor, int nrhs, int maxit, size_t* bytes /* host */);
 int lsh_solve(lsh_factor_t factor, const void* u_inc, int nrhs, void* sigma, void* u, const lsh_solve_opts* opts,
-              lsh_info* info, void* stream);
+              lsh_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* lambda = A^{-H} g (the adjoint solve of a misfit gradient; not in the
  * paper, derived from eq. (linsys)).  Since K is complex symmetric,
  * A^H lambda = g  <=>  A^T conj(lambda) = conj(g) with A^T = I + K B; this is
  * solved by the same flexible GMRES on the transposed FFT operator,
- * right-preconditioned by M^T (Algorithm 2 transposed).  Synchronises once
- * per iteration. */
+ * right-preconditioned by M^T (Algorithm 2 transposed; the factor needs
+ * LSH_FACTOR_TRANSPOSE).  ws as for lsh_solve (same size).  Synchronises
+ * once per iteration. */
 int lsh_solve_adjoint(lsh_factor_t factor, const void* g, int nrhs, void* lambda, const lsh_solve_opts* opts,
-                      lsh_info* info, void* stream);
+                      lsh_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* u(x_r) = h^2 sum_j (i/4) H0(kappa |x_r - x_j|) sigma_j at off-grid points
  * (eq. (ansatz), trapezoidal sum).  xy: device double[2*npts];
@@ -268,11 +321,6 @@ int lsh_profile_enable(int on);
 int lsh_profile_only(const char* prefix);
 int lsh_profile_query(const char* name, int* launches, double* ms, double* work);
 int lsh_profile_names(char* buf, int cap);
-
-/* Frees the device buffers that destroyed handles left in the cache
- * (synchronises the device).  cached: host size_t, receives the bytes the
- * cache held before the call (may be NULL). */
-int lsh_cache_trim(size_t* cached);
 
 const char* lsh_last_error(void);
 

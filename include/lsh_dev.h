@@ -36,10 +36,45 @@ int lsh_dev_gemm_split(int prec, int M, int N, int K, const double* alpha, const
                        long ldd, long sD, void* C, long ldc, long sC, int batch, void* ws, size_t ws_bytes,
                        void* stream);
 
-/* In place: A_b <- A_b^{-1} (c x c, leading dimension lda, stride sA) by
- * Gauss-Jordan elimination with partial pivoting.  info: device int[batch],
- * 0 or j+1 for a zero pivot at step j.  Allocates its own scratch. */
-int lsh_dev_inverse(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* stream);
+/* In place: A_b <- A_b^{-1} (c x c, leading dimension lda >= c, stride sA)
+ * by Gauss-Jordan elimination with partial pivoting.  info: device
+ * int[batch], 0 or j+1 for a zero pivot at step j.  ws: device workspace of
+ * at least lsh_dev_inverse_workspace(prec, c, batch) bytes (256-byte
+ * aligned), in use until the call's work on the stream has finished.
+ * Errors: LSH_ERR_WORKSPACE_TOO_SMALL. */
+int lsh_dev_inverse_workspace(int prec, int c, int batch, size_t* bytes /* host */);
+int lsh_dev_inverse(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* ---- GEMM autotuner (the level merges' products, Algorithm 1)
+ * The batched complex GEMM has several variants per precision (workgroup
+ * tile shape and LDS K depth); every variant of a precision adds the same
+ * products in the same order, so the choice changes only the time.  A call
+ * takes the variant recorded for its shape's bucket (half-octaves of M, N,
+ * K and the batch: round(2 log2 x)), else a wave-quantisation model.
+ * lsh_gemm_variants: count and ';'-separated names (host char[cap]).
+ * lsh_gemm_tune: times every variant on M x K times K x N products (A per
+ * problem, B shared, as in the level merges), reps launches each after one
+ * warm-up, in a workspace of lsh_gemm_tune_workspace bytes; writes each
+ * variant's mean ms (host double[count], may be NULL) and the fastest
+ * (*best), and records it for the shape's bucket.  Synchronises the stream.
+ * lsh_gemm_table_save / _load: the recorded choices as a text file (load
+ * adds the file's entries; *entries = their count).
+ * lsh_gemm_record(1) starts recording the (precision, M, N, K, batch) of
+ * every product (precision 1 = FP32, 0 = FP64); lsh_gemm_recorded returns
+ * them (host int[5 * cap]).
+ * lsh_gemm_force_variant(v): this host thread's products use variant v
+ * (-1: the table or model). */
+int lsh_gemm_variants(int prec, int* count, char* names, int cap);
+int lsh_gemm_tune_workspace(int prec, int M, int N, int K, int batch, size_t* bytes);
+int lsh_gemm_tune(int prec, int M, int N, int K, int batch, int reps, void* ws, size_t ws_bytes, void* stream,
+                  int* best, double* ms);
+int lsh_gemm_table_save(const char* path);
+int lsh_gemm_table_load(const char* path, int* entries);
+int lsh_gemm_table_clear(void);
+int lsh_gemm_record(int on);
+int lsh_gemm_recorded(int* count, int* shapes, int cap);
+int lsh_gemm_force_variant(int variant);
 
 #ifdef __cplusplus
 }

@@ -3,8 +3,14 @@
 // Complex products run on the real matrix cores: each complex k-step is four
 // real 16x16x4 MFMAs (Re += ArBr - AiBi, Im += ArBi + AiBr) on LDS-staged
 // 64x64 tiles; four 64-wide wavefronts each own a 32x32 quarter of the tile.
+#include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <set>
+#include <tuple>
 
 #include "blas.hpp"
 #include "wave.hpp"
@@ -208,23 +214,26 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
 // matrix instructions; the imaginary part is a difference of products, which
 // stays within FP32 rounding of |A||B| sums): 2 x 2 wavefronts, each owning
 // WM x WN blocks of 32 x 32 outputs, so
-// the workgroup tile is (64 WM) x (64 WN), K advancing 32 per LDS tile.  The
-// sum over k inside one instruction does not care which k each lane group
-// supplies, so lane group g (lanes 32g .. 32g+31) takes k = 16g + s at step s:
-// each lane then reads its operands for four steps with one 16-byte LDS load
-// per plane.  Row stride 36 floats keeps those loads free of bank conflicts.
+// the workgroup tile is (64 WM) x (64 WN), K advancing BK (a multiple of 32)
+// per LDS tile.  The sum over k inside one instruction does not care which k
+// each lane group supplies, so in each 32-deep chunk lane group g (lanes
+// 32g .. 32g+31) takes k = 16g + s at step s: each lane then reads its
+// operands for four steps with one 16-byte LDS load per plane.  Row stride
+// BK + 4 floats keeps those loads free of bank conflicts.  Every tile shape
+// and depth issues the same instructions per output in the same order.
 // Accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-constexpr int X32_BK = 32, X32_LDK = X32_BK + 4;
+constexpr int X32_BK = 32;  // K depth of the split-K chunks' tiles
 
-// One (64 WM) x (64 WN) output tile of problem b of P, at (m0, n0).
-template <int WM, int WN>
+// One (64 WM) x (64 WN) output tile of problem b of P, at (m0, n0), K
+// advancing BK per LDS tile.
+template <int WM, int WN, int BK = 32>
 __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, int m0, int n0) {
   typedef float f16v __attribute__((ext_vector_type(16)));
   typedef float f4v __attribute__((ext_vector_type(4)));
-  constexpr int BM = 64 * WM, BN = 64 * WN;
-  constexpr int EA = BM * X32_BK / 256, EB = BN * X32_BK / 256;
-  __shared__ __align__(16) float sAr[BM][X32_LDK], sAi[BM][X32_LDK];
-  __shared__ __align__(16) float sBr[BN][X32_LDK], sBi[BN][X32_LDK];
+  constexpr int BM = 64 * WM, BN = 64 * WN, LDK = BK + 4;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  __shared__ __align__(16) float sAr[BM][LDK], sAi[BM][LDK];
+  __shared__ __align__(16) float sBr[BN][LDK], sBi[BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int g = lane >> 5, l32 = lane & 31;
@@ -247,7 +256,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * 256;
       int m, k;
-      if (aN) { m = idx / X32_BK; k = idx % X32_BK; }
+      if (aN) { m = idx / BK; k = idx % BK; }
       else { k = idx / BM; m = idx % BM; }
       const int gm = m0 + m, gk = k0 + k;
       cplx<float> v = mk<float>(0, 0);
@@ -260,7 +269,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       const int idx = tid + e * 256;
       int n, k;
       if (bN) { k = idx / BN; n = idx % BN; }
-      else { n = idx / X32_BK; k = idx % X32_BK; }
+      else { n = idx / BK; k = idx % BK; }
       const int gn = n0 + n, gk = k0 + k;
       cplx<float> v = mk<float>(0, 0);
       if (gn < P.N && gk < P.K) v = bN ? B[(long)gk * P.ldb + gn] : B[(long)gn * P.ldb + gk];
@@ -273,7 +282,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + e * 256;
       int m, k;
-      if (aN) { m = idx / X32_BK; k = idx % X32_BK; }
+      if (aN) { m = idx / BK; k = idx % BK; }
       else { k = idx / BM; m = idx % BM; }
       sAr[m][k] = ra[e].x;
       sAi[m][k] = ra[e].y;
@@ -283,7 +292,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       const int idx = tid + e * 256;
       int n, k;
       if (bN) { k = idx / BN; n = idx % BN; }
-      else { n = idx / X32_BK; k = idx % X32_BK; }
+      else { n = idx / BK; k = idx % BK; }
       sBr[n][k] = rb[e].x;
       sBi[n][k] = rb[e].y;
     }
@@ -291,13 +300,15 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
   load(0);
   store();
   __syncthreads();
-  for (int k0 = 0; k0 < P.K; k0 += X32_BK) {
-    const bool more = k0 + X32_BK < P.K;
-    if (more) load(k0 + X32_BK);
+  for (int k0 = 0; k0 < P.K; k0 += BK) {
+    const bool more = k0 + BK < P.K;
+    if (more) load(k0 + BK);
 #pragma unroll
-    for (int h = 0; h < X32_BK / 8; ++h) {  // groups of four k steps
+    for (int h = 0; h < BK / 8; ++h) {  // groups of four k steps
       f4v ar[WM], ai[WM], as[WM], br[WN], bi[WN], bs[WN];
-      const int kq = (X32_BK / 2) * g + 4 * h;
+      // within each 32-deep chunk lane group g takes k = 16 g + 4 (h % 4) + step:
+      // every BK adds the same products in the same order (the same bits)
+      const int kq = 32 * (h >> 2) + 16 * g + 4 * (h & 3);
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         const int row = wm * 32 * WM + i * 32 + l32;
@@ -350,8 +361,8 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       }
 }
 
-template <int WM, int WN>
-__global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {  // (WM, WN) = (2, 1) or (1, 1)
+template <int WM, int WN, int BK>
+__global__ __launch_bounds__(256, (WM * WN >= 4 ? 1 : 2)) void k_cgemm_x32(GemmP<float> P) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
   if (P.skip && *P.skip) return;  // uniform across the launch
   // XCD-aware tile order (see k_cgemm)
@@ -363,7 +374,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_x32(GemmP<float> P) {  // (WM,
   const int tm = (int)((L / gridDim.x) % gridDim.y);
   const long b = L / ((long)gridDim.x * gridDim.y);
   if (P.lower && tn * BN >= (tm + 1) * BM) return;  // strictly above the diagonal
-  cgemm_x32_tile<WM, WN>(P, b, tm * BM, tn * BN);
+  cgemm_x32_tile<WM, WN, BK>(P, b, tm * BM, tn * BN);
 }
 
 // Split K (64 x 64 tiles, XCD-aware order as above): grid z runs over
@@ -437,11 +448,11 @@ __global__ __launch_bounds__(256, 4) void k_cgemm_x32_grouped(const GemmGroupDev
   cgemm_x32_tile<1, 1>(gd.p, b, tm * 64, tn * 64);
 }
 
-template <int WM, int WN>
+template <int WM, int WN, int BK>
 static void launch_gemm_x32(hipStream_t s, const GemmP<float>& P, const cplx<float>* A, const cplx<float>* B,
-                            const cplx<float>* D, cplx<float>* C, long sA, long sB, long sD, long sC, int batch) {
+                            const cplx<float>* D, cplx<float>* C, long sA, long sB, long sD, long sC, int batch,
+                            const char* name) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
-  const char* name = BM == 128 ? (BN == 128 ? "cgemm_f32_128x128" : "cgemm_f32_128x64") : "cgemm_f32_64x64";
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     int nb = batch - b0 < 65535 ? batch - b0 : 65535;
     ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb);
@@ -449,7 +460,7 @@ static void launch_gemm_x32(hipStream_t s, const GemmP<float>& P, const cplx<flo
     Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
     if (D) Q.D = D + b0 * sD;
     dim3 grid(ceil_div(P.N, BN), ceil_div(P.M, BM), nb);
-    hipLaunchKernelGGL((k_cgemm_x32<WM, WN>), grid, dim3(256), 0, s, Q);
+    hipLaunchKernelGGL((k_cgemm_x32<WM, WN, BK>), grid, dim3(256), 0, s, Q);
     LSH_LAUNCH_CHECK();
   }
 }
@@ -472,31 +483,136 @@ static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, cons
   }
 }
 
-// FP32 tile choice by a wave-quantisation model: a launch takes
+// ---- GEMM variants and their choice
+//
+// FP32: tile (64 WM) x (64 WN) with K depth BK.  FP64: 64 x 64 or 128 x 64.
+// All variants of one precision add the same products in the same order, so
+// the choice changes the time, never the bits.
+struct GemmVariant { int wm, wn, bk; const char* name; };
+static const GemmVariant kF32Variants[] = {
+    {1, 1, 32, "cgemm_f32_64x64"},   {2, 1, 32, "cgemm_f32_128x64"},    {2, 2, 32, "cgemm_f32_128x128"},
+    {1, 1, 64, "cgemm_f32_64x64k64"}, {2, 1, 64, "cgemm_f32_128x64k64"}, {1, 2, 32, "cgemm_f32_64x128"}};
+static const GemmVariant kF64Variants[] = {{2, 2, 16, "cgemm_f64_64x64"}, {4, 2, 16, "cgemm_f64_128x64"}};
+constexpr int kNumF32Variants = sizeof(kF32Variants) / sizeof(kF32Variants[0]);
+constexpr int kNumF64Variants = sizeof(kF64Variants) / sizeof(kF64Variants[0]);
+
+int gemm_variant_count(int prec) { return prec == 1 ? kNumF32Variants : kNumF64Variants; }
+const char* gemm_variant_name(int prec, int v) {
+  return prec == 1 ? kF32Variants[v].name : kF64Variants[v].name;
+}
+
+// Without a tuned entry: a wave-quantisation model for FP32 (a launch takes
 // ceil(tiles / (256 CUs x resident workgroups per CU)) rounds, and a full
 // round costs (resident workgroups x tile area) / (per-CU efficiency of that
-// tile).  Residency and efficiency per tile come from the register/LDS budget
-// and a sweep of square and batched shapes (128x64: 2 resident, 64x64: 4).
-// LSH_GEMM_TILE=0/1 forces a tile.
-struct TileModel { int bm, bn, resident; double eff; };
-static const TileModel kF32Tiles[2] = {{128, 64, 2, 0.60}, {64, 64, 4, 0.69}};
+// tile)), and the 64 x 64 tile for FP64 (44-46 against 34-39 TF/s on every
+// measured shape).
+struct TileModel { int variant, bm, bn, resident; double eff; };
+static const TileModel kF32Model[2] = {{1, 128, 64, 2, 0.60}, {0, 64, 64, 4, 0.69}};
 
-static int f32_tile(int M, int N, int batch) {
-  static const int forced = [] {
-    const char* e = getenv("LSH_GEMM_TILE");
-    return e ? atoi(e) : -1;
-  }();
-  if (forced >= 0 && forced <= 1) return forced;
-  int best = 1;
+static int model_variant(int prec, int M, int N, int batch) {
+  if (prec != 1) return 0;
+  int best = 0;
   double bt = 1e300;
-  for (int t = 0; t < 2; ++t) {
-    const TileModel& tm = kF32Tiles[t];
+  for (const TileModel& tm : kF32Model) {
     const double tiles = (double)ceil_div(M, tm.bm) * ceil_div(N, tm.bn) * batch;
     const double rounds = std::ceil(tiles / (256.0 * tm.resident));
     const double cost = rounds * tm.resident * tm.bm * tm.bn / tm.eff;
-    if (cost < bt * 0.999) { bt = cost; best = t; }
+    if (cost < bt * 0.999) { bt = cost; best = tm.variant; }
   }
   return best;
+}
+
+// Tuned choices, keyed by precision and the half-octave buckets of M, N, K
+// and the batch (lsh_gemm_tune fills it; lsh_gemm_table_load reads a file).
+namespace {
+struct TuneKey {
+  int prec, m, n, k, b;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, m, n, k, b) < std::tie(o.prec, o.m, o.n, o.k, o.b);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+thread_local int g_forced_variant = -1;  // (the tuner's timing runs)
+bool g_record = false;
+std::set<std::array<int, 5>> g_recorded;
+
+int half_octave(long x) { return x <= 1 ? 0 : (int)std::lround(2.0 * std::log2((double)x)); }
+TuneKey tune_key(int prec, int M, int N, int K, int batch) {
+  return {prec, half_octave(M), half_octave(N), half_octave(K), half_octave(batch)};
+}
+}  // namespace
+
+static int choose_variant(int prec, int M, int N, int K, int batch) {
+  if (g_forced_variant >= 0) return g_forced_variant;
+  static const int env = [] {
+    const char* e = getenv("LSH_GEMM_VARIANT");
+    return e ? atoi(e) : -1;
+  }();
+  const int nv = gemm_variant_count(prec);
+  if (env >= 0 && env < nv) return env;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_record) g_recorded.insert({prec, M, N, K, batch});
+    auto it = g_tune.find(tune_key(prec, M, N, K, batch));
+    if (it != g_tune.end() && it->second < nv) return it->second;
+  }
+  return model_variant(prec, M, N, batch);
+}
+
+void gemm_force_variant(int v) { g_forced_variant = v; }
+
+void gemm_tune_set(int prec, int M, int N, int K, int batch, int v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[tune_key(prec, M, N, K, batch)] = v;
+}
+
+void gemm_table_clear() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
+}
+
+// Text file, one entry per line: prec m n k batch (bucket indices) variant.
+void gemm_table_save(const char* path) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  LSH_REQUIRE(f, -1, std::string("gemm table: cannot open ") + path);
+  std::fprintf(f, "# prec(0 FP64, 1 FP32) M N K batch (half-octave buckets, round(2 log2 x)) variant name\n");
+  for (auto& kv : g_tune)
+    std::fprintf(f, "%d %d %d %d %d %d %s\n", kv.first.prec, kv.first.m, kv.first.n, kv.first.k, kv.first.b,
+                 kv.second, gemm_variant_name(kv.first.prec, kv.second));
+  std::fclose(f);
+}
+
+int gemm_table_load(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  LSH_REQUIRE(f, -1, std::string("gemm table: cannot open ") + path);
+  char line[256];
+  int n = 0;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    TuneKey k;
+    int v;
+    if (std::sscanf(line, "%d %d %d %d %d %d", &k.prec, &k.m, &k.n, &k.k, &k.b, &v) == 6 && (k.prec == 0 || k.prec == 1) &&
+        v >= 0 && v < gemm_variant_count(k.prec)) {
+      g_tune[k] = v;
+      ++n;
+    }
+  }
+  std::fclose(f);
+  return n;
+}
+
+void gemm_record(bool on) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_record = on;
+  if (on) g_recorded.clear();
+}
+
+std::vector<std::array<int, 5>> gemm_recorded() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return std::vector<std::array<int, 5>>(g_recorded.begin(), g_recorded.end());
 }
 
 template <typename R>
@@ -516,17 +632,19 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
   P.D = D; P.ldd = ldd; P.sD = sD;
   P.C = C; P.ldc = ldc; P.sC = sC; P.addI = add_identity ? 1 : 0;
   if constexpr (sizeof(R) == 4) {
-    if (f32_tile(M, N, batch) == 0) launch_gemm_x32<2, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
-    else launch_gemm_x32<1, 1>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    const int v = lower ? 0 : choose_variant(1, M, N, K, batch);
+    const char* nm = kF32Variants[v].name;
+    switch (v) {
+      case 1: launch_gemm_x32<2, 1, 32>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
+      case 2: launch_gemm_x32<2, 2, 32>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
+      case 3: launch_gemm_x32<1, 1, 64>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
+      case 4: launch_gemm_x32<2, 1, 64>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
+      case 5: launch_gemm_x32<1, 2, 32>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
+      default: launch_gemm_x32<1, 1, 32>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
+    }
   } else {
-    // FP64: the 64 x 64 tile (two workgroups per CU) beats 128 x 64 (one) on
-    // every measured shape (44-46 against 34-39 TF/s); LSH_GEMM64_TILE=0
-    // forces 128 x 64
-    static const int f64_forced = [] {
-      const char* e = getenv("LSH_GEMM64_TILE");
-      return e ? atoi(e) : -1;
-    }();
-    if (f64_forced == 0) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    const int v = lower ? 0 : choose_variant(0, M, N, K, batch);
+    if (v == 1) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
 }
@@ -1610,6 +1728,28 @@ size_t inverse_grouped_ws_bytes(const std::vector<InvItem>& items) {
               ((b * (2 * (size_t)gj_nb2() * c + c * c) * sizeof(c32) + 255) / 256) * 256 + 4 * 256;
   }
   return t + 256;
+}
+
+size_t cgemm_grouped_table_bytes(size_t items) { return mem::round_up(sizeof(GemmGroupDev) * (items ? items : 1)); }
+
+size_t inverse_grouped_arena_bytes(const std::vector<InvItem>& items) {
+  size_t t = mem::round_up(sizeof(InvDev) * (items.size() ? items.size() : 1));  // problem table
+  int cmax = 0;
+  size_t nblocked = 0;
+  for (const InvItem& it : items) {
+    if (it.c <= 0 || it.batch <= 0) continue;
+    if (small_inv_lds<float>(it.c) <= 65536) continue;
+    if (it.c <= GJ_NT) {
+      cmax = it.c > cmax ? it.c : cmax;
+      ++nblocked;
+    } else {
+      t += mem::round_up(inverse_ws_bytes<float>(it.c, it.batch));  // one-by-one fallback
+    }
+  }
+  // the blocked path's slab GEMM tables (two problems per matrix batch per slab)
+  const int NB2 = gj_nb2();
+  t += (size_t)((cmax + NB2 - 1) / NB2) * cgemm_grouped_table_bytes(2 * nblocked);
+  return t;
 }
 
 void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws, DevBuf& table) {

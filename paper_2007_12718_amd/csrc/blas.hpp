@@ -4,6 +4,7 @@
 // double.  A "batch" is a set of equally sized problems at a fixed stride
 // (stride 0 = one operand shared by every problem).
 #pragma once
+#include <array>
 #include <vector>
 
 #include "common.hpp"
@@ -56,6 +57,8 @@ struct GemmItem {
   bool addI;
 };
 void cgemm_grouped(hipStream_t s, const std::vector<GemmItem>& items, DevBuf& dev);
+// bytes of the problem table of a grouped launch of this many items
+size_t cgemm_grouped_table_bytes(size_t items);
 
 // y_b = alpha * A_{b mod amod} x_b + beta * z_b   (A_b is M x N, op N).
 // z may alias y; z may be null when beta == 0.
@@ -77,6 +80,20 @@ void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, lon
 template <typename R>
 void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm,
              const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec);
+
+// GEMM variants (tile shape and LDS depth; prec 1 = FP32, 0 = FP64) and
+// their choice per shape: a tuned table keyed by half-octave buckets of
+// (M, N, K, batch), else a model.  Every variant of a precision gives the
+// same bits.
+int gemm_variant_count(int prec);
+const char* gemm_variant_name(int prec, int v);
+void gemm_force_variant(int v);  // this thread's launches (-1: choose)
+void gemm_tune_set(int prec, int M, int N, int K, int batch, int v);
+void gemm_table_clear();
+void gemm_table_save(const char* path);
+int gemm_table_load(const char* path);
+void gemm_record(bool on);  // record the (prec, M, N, K, batch) of every product
+std::vector<std::array<int, 5>> gemm_recorded();
 
 // In-place inverse of each c x c matrix by Gauss-Jordan elimination with
 // partial (row) pivoting.  ws must hold inverse_ws_bytes(c, batch) bytes.
@@ -100,6 +117,9 @@ struct InvItem {
 };
 size_t inverse_grouped_ws_bytes(const std::vector<InvItem>& items);
 void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws, DevBuf& table);
+// device memory inverse_grouped takes from the bound arena besides ws (its
+// tables, and the workspace of orders beyond the grouped kernels), at most
+size_t inverse_grouped_arena_bytes(const std::vector<InvItem>& items);
 
 // out_b (cols x rows) = in_b^T (rows x cols), row-major, batch of contiguous matrices
 template <typename R>

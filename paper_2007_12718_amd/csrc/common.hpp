@@ -80,77 +80,37 @@ struct Error : std::runtime_error {
 
 #define LSH_LAUNCH_CHECK() LSH_HIP(hipGetLastError())
 
-// Device allocation owned by the library (plan / factor arenas).
+// Device memory carved from a caller-owned workspace: alloc() takes from the
+// arena bound to the calling thread (mem::Bind) or from a given arena;
+// release() only forgets the pointer (the arena rewinds as a whole).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  size_t cap = 0;  // capacity of the block behind p (>= bytes)
   DevBuf() = default;
   explicit DevBuf(size_t n) { alloc(n); }
   void alloc(size_t n) {
-    release();
+    mem::Arena* a = mem::current();
+    if (n && !a) throw Error(-1, "internal: device allocation outside a workspace");
+    alloc_in(*a, n);
+  }
+  void alloc_in(mem::Arena& a, size_t n) {
     bytes = n;
-    if (n) LSH_HIP(mem::get(n, &p, &cap));
+    p = n ? a.take(n) : nullptr;
   }
   void release() {
-    mem::put(p, cap);
-    p = nullptr;
-    bytes = cap = 0;
-  }
-  ~DevBuf() { release(); }
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap) { o.p = nullptr; o.bytes = o.cap = 0; }
-  DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) {
-      release();
-      p = o.p; bytes = o.bytes; cap = o.cap;
-      o.p = nullptr; o.bytes = o.cap = 0;
-    }
-    return *this;
-  }
-  template <typename T>
-  T* as() const { return static_cast<T*>(p); }
-};
-
-// Stream-ordered scratch (hipMallocAsync / hipFreeAsync on one stream): no
-// device-wide synchronisation on release, unlike hipFree.  The device's
-// default pool keeps freed memory for reuse (release threshold raised once).
-inline void retain_async_pool() {
-  static bool done = [] {
-    int dev = 0;
-    hipMemPool_t pool;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    return true;
-  }();
-  (void)done;
-}
-
-struct AsyncBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  hipStream_t s = nullptr;
-  AsyncBuf() = default;
-  AsyncBuf(size_t n, hipStream_t st) { alloc(n, st); }
-  void alloc(size_t n, hipStream_t st) {
-    release();
-    retain_async_pool();
-    s = st;
-    bytes = n;
-    if (n) LSH_HIP(hipMallocAsync(&p, n, st));
-  }
-  void release() {
-    if (p) (void)hipFreeAsync(p, s);
     p = nullptr;
     bytes = 0;
   }
-  ~AsyncBuf() { release(); }
-  AsyncBuf(const AsyncBuf&) = delete;
-  AsyncBuf& operator=(const AsyncBuf&) = delete;
-  AsyncBuf(AsyncBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      p = o.p; bytes = o.bytes;
+      o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
 };

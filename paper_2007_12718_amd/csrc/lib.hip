@@ -77,23 +77,11 @@ struct lsh_plan_s {
   DevBuf Gleaf64, Gleaf32;
   int hbs_order = 4;
   const z64* hbs_table() const { return htable.p ? htable.as<z64>() : table.as<z64>(); }
-  // Scratch of the row IDs.  Stream-ordered frees of these large blocks
-  // (and hipFree, which synchronises the device) cost milliseconds per level
-  // in the middle of the build, so they stay allocated until the plan is
-  // built and then go back to the device cache (release_scratch, after the
-  // final synchronisation).
-  std::mutex scratch_mu;
-  std::deque<DevBuf> scratch;
-  void* scratch_buf(size_t bytes) {
-    std::lock_guard<std::mutex> g(scratch_mu);
-    scratch.emplace_back(bytes ? bytes : 1);
-    return scratch.back().p;
-  }
-  void release_scratch() {
-    mem::Recycle r;
-    std::lock_guard<std::mutex> g(scratch_mu);
-    scratch.clear();
-  }
+  // Device memory, all from the caller's plan workspace: persist holds what
+  // the plan keeps; sid and ssib hold the temporaries of the level row IDs
+  // and of the sibling blocks (the two plan threads of lsh_build), each
+  // rewound at the start of its next level, after a stream synchronisation.
+  mem::Arena persist, sid, ssib;
   ConvOperator op;
   std::vector<StencilEntry> st4;
   double tau0_re = 0, tau0_im = 0;
@@ -174,12 +162,13 @@ DevBuf upload(const std::vector<T>& v, hipStream_t s) {
   return b;
 }
 
-// scratch copy of a host vector, freed in stream order
+// copy of a host vector in a temporary arena (the host vector must outlive
+// the copy: the callers synchronise the stream before it goes)
 template <typename T>
-AsyncBuf upload_async(const std::vector<T>& v, hipStream_t s) {
-  AsyncBuf b(sizeof(T) * (v.size() ? v.size() : 1), s);
-  if (!v.empty()) LSH_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
-  return b;
+T* upload_to(mem::Arena& a, const std::vector<T>& v, hipStream_t s) {
+  T* p = static_cast<T*>(a.take(sizeof(T) * (v.size() ? v.size() : 1)));
+  if (!v.empty()) LSH_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+  return p;
 }
 
 void validate(const lsh_desc& d) {
@@ -203,9 +192,10 @@ void validate(const lsh_desc& d) {
 }
 
 // Row ID A ~= U A[J, :] of a device matrix A (m x np, FP64; overwritten) at
-// the plan's tolerance: J to the host, U (m x k) to a new device buffer;
-// returns k.
-int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64, hipStream_t s) {
+// the plan's tolerance: J to the host, U (m x k) to a new buffer of the
+// bound arena, temporaries from scr; returns k.  Synchronises s.
+int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64, mem::Arena& scr,
+                  hipStream_t s) {
   if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all rows
     Jh.resize(m);
     for (int i = 0; i < m; ++i) Jh[i] = i;
@@ -214,22 +204,24 @@ int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, De
     U64 = upload(I, s);
     return m;
   }
-  int* J = static_cast<int*>(P.scratch_buf(sizeof(int) * m));
-  z64* Ufull = static_cast<z64*>(P.scratch_buf(sizeof(z64) * (size_t)m * m));
+  int* J = static_cast<int*>(scr.take(sizeof(int) * m));
+  z64* Ufull = static_cast<z64*>(scr.take(sizeof(z64) * (size_t)m * m));
   int k = 0;
   // Gram + pivoted Cholesky squares the conditioning: FP64 resolves the
   // stopping rule only while tol stays above ~1e-7; below that, CPQR.
   if (P.d.tol < 1e-7) {
     // ||A||_F for the stopping rule |R_kk| <= tol ||A||_F (computed on device)
-    void* ws = P.scratch_buf(rowid_cpqr_ws(m));
-    AsyncBuf kd(sizeof(int), s), fro(sizeof(z64), s), part(multidot_partial_bytes(1), s);
-    multidot(s, A, 0, 1, A, (long)m * np, fro.as<z64>(), part.as<z64>());
+    void* ws = scr.take(rowid_cpqr_ws(m));
+    int* kd = static_cast<int*>(scr.take(sizeof(int)));
+    z64* fro = static_cast<z64*>(scr.take(sizeof(z64)));
+    z64* part = static_cast<z64*>(scr.take(multidot_partial_bytes(1)));
+    multidot(s, A, 0, 1, A, (long)m * np, fro, part);
     z64 f2;
-    LSH_HIP(hipMemcpyAsync(&f2, fro.p, sizeof(z64), hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipMemcpyAsync(&f2, fro, sizeof(z64), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     const double thr = P.d.tol * std::sqrt(f2.x);
-    rowid_cpqr(s, A, m, np, thr, J, Ufull, kd.as<int>(), ws);
-    LSH_HIP(hipMemcpyAsync(&k, kd.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    rowid_cpqr(s, A, m, np, thr, J, Ufull, kd, ws);
+    LSH_HIP(hipMemcpyAsync(&k, kd, sizeof(int), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
   } else {
@@ -241,9 +233,9 @@ int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, De
     const char* ea = std::getenv("LSH_BP_ALPHA");
     const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
     if (!block)
-      k = rowid_gram(s, A, m, np, P.d.tol, J, Ufull, P.scratch_buf(rowid_gram_ws(m)));
+      k = rowid_gram(s, A, m, np, P.d.tol, J, Ufull, scr.take(rowid_gram_ws(m)));
     else
-      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, P.scratch_buf(rowid_bp_ws(m)));
+      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, scr.take(rowid_bp_ws(m)));
   }
   Jh.resize(k);
   LSH_HIP(hipMemcpyAsync(Jh.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
@@ -278,7 +270,7 @@ pcache::Key cache_key(const lsh_plan_s& P, int kind, int sx, int sy) {
 void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
   const int m = lv.m, np = (int)prox.size();
   if (P.d.tol == 0) {
-    lv.k = row_id_matrix(P, nullptr, m, np, lv.J, lv.U64, s);
+    lv.k = row_id_matrix(P, nullptr, m, np, lv.J, lv.U64, P.sid, s);
     return;
   }
   pcache::Key key;
@@ -286,19 +278,20 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     key = cache_key(P, 0, lv.sx, lv.sy);
     if (pcache::find(key, lv.cand, lv.J, lv.k, lv.U64, s)) return;
   }
-  AsyncBuf dc = upload_async(lv.cand, s), dp = upload_async(prox, s);
+  const I2* dc = upload_to(P.sid, lv.cand, s);
+  const I2* dp = upload_to(P.sid, prox, s);
   if (P.hbs_order == 4) {
-    z64* A = static_cast<z64*>(P.scratch_buf(sizeof(z64) * (size_t)m * np));
-    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A, np);
-    lv.k = row_id_matrix(P, A, m, np, lv.J, lv.U64, s);
+    z64* A = static_cast<z64*>(P.sid.take(sizeof(z64) * (size_t)m * np));
+    gather_table(s, P.table.as<z64>(), P.D, dc, m, dp, np, A, np);
+    lv.k = row_id_matrix(P, A, m, np, lv.J, lv.U64, P.sid, s);
   } else {
     // order > 4: the rows must also span the corrected entries against the
     // ring's points (the actual near neighbours, within the stencil's reach),
     // beside plain G on the ring (the representation of everything farther)
-    z64* A = static_cast<z64*>(P.scratch_buf(sizeof(z64) * (size_t)m * 2 * np));
-    gather_table(s, P.table.as<z64>(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A, 2 * np);
-    gather_table(s, P.hbs_table(), P.D, dc.as<I2>(), m, dp.as<I2>(), np, A + np, 2 * np);
-    lv.k = row_id_matrix(P, A, m, 2 * np, lv.J, lv.U64, s);
+    z64* A = static_cast<z64*>(P.sid.take(sizeof(z64) * (size_t)m * 2 * np));
+    gather_table(s, P.table.as<z64>(), P.D, dc, m, dp, np, A, 2 * np);
+    gather_table(s, P.hbs_table(), P.D, dc, m, dp, np, A + np, 2 * np);
+    lv.k = row_id_matrix(P, A, m, 2 * np, lv.J, lv.U64, P.sid, s);
   }
   if (P.d.plan_cache) pcache::insert(key, lv.cand, lv.J, m, lv.k, lv.U64, s);
 }
@@ -332,7 +325,7 @@ void plan_init(lsh_plan_s& P, hipStream_t s) {
     const std::vector<StencilEntry> st = correction_stencil(P.hbs_order, d.kappa * d.h);
     P.htable.alloc(sizeof(z64) * (size_t)(P.D + 1) * (P.D + 1));
     build_offset_table(s, P.htable.as<z64>(), P.D, d.h, d.kappa, st[0].re, st[0].im);
-    add_table_stencil(s, P.htable.as<z64>(), P.D, d.h, st);
+    add_table_stencil(s, P.htable.as<z64>(), P.D, d.h, st, P.sid);
   }
   // leaves
   P.leaf_origin_h.resize(P.nleaf);
@@ -367,6 +360,8 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
   const lsh_desc& d = P.d;
   const bool f32 = d.hbs_prec == LSH_FP32;
   if (l >= 1) {  // row ID of level l (Sec. 3.2)
+    LSH_HIP(hipStreamSynchronize(s));
+    P.sid.reset(0);  // (the previous level's temporaries are no longer in use)
     Level& lv = P.lev[l];
     if (l == P.L) {
       lv.cand = P.leaf_pts_h;
@@ -421,9 +416,9 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
     hit = pcache::find(key, sk, J, r, U, s);
   }
   if (!hit) {
-    z64* A = static_cast<z64*>(P.scratch_buf(sizeof(z64) * cc));
+    z64* A = static_cast<z64*>(P.ssib.take(sizeof(z64) * cc));
     LSH_HIP(hipMemcpyAsync(A, lv.Gab64.p, sizeof(z64) * cc, hipMemcpyDeviceToDevice, s));
-    r = row_id_matrix(P, A, c, c, J, U, s);
+    r = row_id_matrix(P, A, c, c, J, U, P.ssib, s);
     if (P.d.plan_cache && d.tol > 0) pcache::insert(key, sk, J, c, r, U, s);  // U = L: c x r
   }
   if (d.merge == LSH_MERGE_AUTO && 10 * r > 6 * c) return;
@@ -433,13 +428,14 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
   std::vector<I2>& rows = lv.wrows;
   rows.resize(r);
   for (int i = 0; i < r; ++i) rows[i] = lv.ra[J[i]];
-  AsyncBuf dr = upload_async(rows, s), db = upload_async(lv.rb, s);
+  const I2* dr = upload_to(P.ssib, rows, s);
+  const I2* db = upload_to(P.ssib, lv.rb, s);
   lv.Pm64.alloc(sizeof(z64) * 2 * cr);
   lv.Qm64.alloc(sizeof(z64) * 2 * cr);
   z64* Pm = lv.Pm64.as<z64>();
   z64* Qm = lv.Qm64.as<z64>();
   LSH_HIP(hipMemcpyAsync(Pm, U.p, sizeof(z64) * cr, hipMemcpyDeviceToDevice, s));       // L
-  gather_table(s, P.hbs_table(), P.D, dr.as<I2>(), r, db.as<I2>(), c, Qm + cr, c);  // R^T = G_ab[J, :]
+  gather_table(s, P.hbs_table(), P.D, dr, r, db, c, Qm + cr, c);  // R^T = G_ab[J, :]
   ctranspose<double>(s, Pm, c, r, Qm);                                                 // L^T
   ctranspose<double>(s, Qm + cr, r, c, Pm + cr);                                       // R
   if (f32) {
@@ -456,6 +452,8 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
   const lsh_desc& d = P.d;
   const bool f32 = d.hbs_prec == LSH_FP32;
   if (l < P.L) {  // sibling block G_ab of parent level l (eq. (sibint)): children 0 and 1 of box 0
+    LSH_HIP(hipStreamSynchronize(s));
+    P.ssib.reset(0);  // (the previous sibling block's temporaries are no longer in use)
     const Level& ch = P.lev[l + 1];
     int ax, ay, bx, by, sx, sy;
     box_of(d.n, l + 1, 0, ax, ay, sx, sy);
@@ -471,10 +469,11 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
       rb.push_back(I2{ch.cand[j].x + bx, ch.cand[j].y + by});
     }
     lv.c = ch.k;
-    AsyncBuf da = upload_async(ra, s), db = upload_async(rb, s);
+    const I2* da = upload_to(P.ssib, ra, s);
+    const I2* db = upload_to(P.ssib, rb, s);
     const long cc = (long)lv.c * lv.c;
     lv.Gab64.alloc(sizeof(z64) * cc);
-    gather_table(s, P.hbs_table(), P.D, da.as<I2>(), lv.c, db.as<I2>(), lv.c, lv.Gab64.as<z64>(), lv.c);
+    gather_table(s, P.hbs_table(), P.D, da, lv.c, db, lv.c, lv.Gab64.as<z64>(), lv.c);
     lv.Gabt64.alloc(sizeof(z64) * cc);
     ctranspose<double>(s, lv.Gab64.as<z64>(), lv.c, lv.c, lv.Gabt64.as<z64>());
     if (f32) {
@@ -483,7 +482,6 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
       lv.Gabt32.alloc(sizeof(c32) * cc);
       ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
     }
-    // (the device staging buffers are freed in stream order)
     plan_lowrank(P, l, s);
   }
 }
@@ -496,7 +494,9 @@ void plan_level(lsh_plan_s& P, int l, hipStream_t s) {
 void plan_finish(lsh_plan_s& P, hipStream_t s) {
   const lsh_desc& d = P.d;
   // operator spectrum (order op_order)
-  P.op.init(s, d.n, d.h, d.kappa, P.table.as<z64>(), P.D, correction_stencil(d.op_order, d.kappa * d.h));
+  LSH_HIP(hipStreamSynchronize(s));
+  P.sid.reset(0);
+  P.op.init(s, d.n, d.h, d.kappa, P.table.as<z64>(), P.D, correction_stencil(d.op_order, d.kappa * d.h), P.sid);
   LSH_HIP(hipStreamSynchronize(s));
 }
 
@@ -504,7 +504,223 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
   plan_init(P, s);
   for (int l = P.L; l >= 0; --l) plan_level(P, l, s);
   plan_finish(P, s);
-  P.release_scratch();
+}
+
+// ------------------------------------------------------------ workspace sizes
+// The ranks are known only once the row IDs have run, so the plan's
+// workspace is sized by bounds: a level's rank is at most its number of
+// candidate rows (twice the children's rank; the leaf's nodes) and at most
+// its number of proxy columns (the ring, twice that for an order-p
+// compression); a sibling block's rank is at most its order.  Given a plan,
+// the factor's size is exact; so is the solve's.
+
+struct PlanBytes {
+  size_t persist = 0, sid = 0, ssib = 0;
+  size_t total() const { return persist + sid + ssib; }
+};
+
+// Per-level sizes that the factor's memory depends on: ranks k, merge
+// orders c, Woodbury ranks r and which merge forms may occur (bit 0: Schur,
+// bit 1: Woodbury).
+struct Profile {
+  long N = 0;
+  int L = 0, nleaf = 0, mL = 0;
+  bool f32 = false;
+  std::vector<long> k, c, r;
+  std::vector<int> form;
+};
+
+size_t rowid_scratch_bytes(long m, double tol) {
+  if (tol == 0) return 0;  // (U = I goes to the plan's own memory)
+  mem::Sizer z, q;
+  z.add_n<int>(m);
+  z.add_n<z64>((size_t)m * m);
+  q.add(rowid_cpqr_ws((int)m));
+  q.add(sizeof(int));
+  q.add(sizeof(z64));
+  q.add(multidot_partial_bytes(1));
+  return z.total + std::max({q.total, mem::round_up(rowid_gram_ws((int)m)), mem::round_up(rowid_bp_ws((int)m))});
+}
+
+// Plan sizes (bounds) and the factor's rank profile under the same bounds.
+PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
+  int p = d.n / d.leaf, lg = 0;
+  while ((1 << lg) < p) ++lg;
+  const int L = 2 * lg, nleaf = 1 << L, mL = d.leaf * d.leaf, D = d.n + d.proxy_width + 1, w = d.proxy_width;
+  const bool f32 = d.hbs_prec == LSH_FP32;
+  const int horder = d.hbs_order > 4 ? d.hbs_order : 4;
+  const bool lowrank = !(d.merge == LSH_MERGE_SCHUR || (d.merge == LSH_MERGE_AUTO && d.tol == 0));
+  const size_t e = f32 ? sizeof(c32) : 0;  // extra FP32 copies
+  std::vector<long> m(L + 2, 0), k(L + 2, 0), np(L + 1, 0);
+  for (int l = L; l >= 1; --l) {
+    int ox, oy, sx, sy;
+    box_of(d.n, l, 0, ox, oy, sx, sy);
+    np[l] = (long)(sx + 2 * w) * (sy + 2 * w) - (long)sx * sy;
+    const long ncols = (horder > 4 ? 2 : 1) * np[l];
+    m[l] = l == L ? mL : 2 * k[l + 1];
+    k[l] = d.tol == 0 ? m[l] : std::max(1L, std::min(m[l], ncols));
+  }
+  PlanBytes b;
+  mem::Sizer z;
+  z.add_n<z64>((size_t)(D + 1) * (D + 1));                      // table
+  if (horder > 4) z.add_n<z64>((size_t)(D + 1) * (D + 1));      // htable
+  z.add_n<I2>(nleaf);                                           // leaf_origin
+  z.add_n<I2>(mL);                                              // leaf_pts
+  z.add_n<z64>((size_t)mL * mL);                                // Gleaf64
+  if (f32) z.add(e * mL * mL);                                  // Gleaf32
+  size_t sid = mem::round_up(4096) + ConvOperator::scratch_bytes(), ssib = 0;
+  for (int l = 1; l <= L; ++l) {
+    const size_t mk = (size_t)m[l] * k[l];
+    z.add_n<z64>(mk);  // U64
+    z.add_n<z64>(mk);  // Ut64
+    if (f32) { z.add(e * mk); z.add(e * mk); }
+    const long ncols = (horder > 4 ? 2 : 1) * np[l];
+    mem::Sizer t;
+    t.add_n<I2>(m[l]);
+    t.add_n<I2>(np[l]);
+    if (d.tol > 0) t.add_n<z64>((size_t)m[l] * ncols);
+    sid = std::max(sid, t.total + rowid_scratch_bytes(m[l], d.tol));
+  }
+  for (int l = 0; l < L; ++l) {
+    // r <= c; AUTO keeps the low-rank factors only where 10 r <= 6 c
+    const size_t c = k[l + 1], cc = c * c, cr = c * (d.merge == LSH_MERGE_AUTO ? c * 6 / 10 : c);
+    z.add_n<z64>(cc);
+    z.add_n<z64>(cc);
+    if (f32) { z.add(e * cc); z.add(e * cc); }
+    mem::Sizer t;
+    t.add_n<I2>(c);
+    t.add_n<I2>(c);
+    if (lowrank) {
+      z.add_n<z64>(cc);                     // U of the sibling block's row ID
+      z.add_n<z64>(2 * cr);                 // [L; R]
+      z.add_n<z64>(2 * cr);                 // [L^T; R^T]
+      if (f32) { z.add(e * 2 * cr); z.add(e * 2 * cr); }
+      t.add_n<z64>(cc);                     // copy of G_ab (overwritten by the row ID)
+      t.add_n<I2>(c);
+      t.add_n<I2>(c);
+      ssib = std::max(ssib, t.total + rowid_scratch_bytes((long)c, d.tol));
+    } else {
+      ssib = std::max(ssib, t.total);
+    }
+  }
+  z.add(ConvOperator::bytes(d.n));
+  b.persist = z.total;
+  b.sid = sid;
+  b.ssib = ssib;
+  if (prof) {
+    Profile& P = *prof;
+    P.N = (long)d.n * d.n;
+    P.L = L;
+    P.nleaf = nleaf;
+    P.mL = mL;
+    P.f32 = f32;
+    P.k.assign(k.begin(), k.begin() + L + 1);
+    P.c.resize(L);
+    P.r.resize(L);
+    P.form.resize(L);
+    for (int l = 0; l < L; ++l) {
+      P.c[l] = k[l + 1];
+      if (!lowrank) { P.form[l] = 1; P.r[l] = 0; }
+      else if (d.merge == LSH_MERGE_LOWRANK) { P.form[l] = 2; P.r[l] = P.c[l]; }
+      else { P.form[l] = 3; P.r[l] = P.c[l] * 6 / 10; }  // AUTO: Woodbury only where 10 r <= 6 c
+    }
+  }
+  return b;
+}
+
+Profile plan_profile(const lsh_plan_s& P) {
+  Profile f;
+  f.N = (long)P.n * P.n;
+  f.L = P.L;
+  f.nleaf = P.nleaf;
+  f.mL = P.mL;
+  f.f32 = P.d.hbs_prec == LSH_FP32;
+  f.k.resize(P.L + 1);
+  f.c.resize(P.L);
+  f.r.resize(P.L);
+  f.form.resize(P.L);
+  for (int l = 0; l <= P.L; ++l) f.k[l] = P.lev[l].k;
+  for (int l = 0; l < P.L; ++l) {
+    f.c[l] = P.lev[l].c;
+    f.r[l] = P.lev[l].wr;
+    f.form[l] = P.lev[l].wr > 0 ? 2 : 1;
+  }
+  return f;
+}
+
+struct FactorBytes {
+  size_t keep = 0, scr = 0;
+  size_t total() const { return keep + scr; }
+};
+
+// Right-hand sides per apply of the preconditioner (larger calls are split).
+constexpr int APPLY_GROUP = 8;
+// FP32 partial products of the apply's split-K shared products.
+constexpr size_t kSplitKBytes = size_t(24) << 20;
+
+template <typename R>
+FactorBytes factor_bytes_t(const Profile& f, bool want_T) {
+  const size_t e = sizeof(cplx<R>);
+  const long L = f.L, nleaf = f.nleaf, mL = f.mL, kL = f.k[L];
+  mem::Sizer z;
+  z.add_n<double>(f.N);                                 // b
+  z.add(sizeof(int));                                   // input check flag
+  z.add(e * nleaf * mL * mL);                           // X
+  z.add_n<int>(nleaf);                                  // leaf flags
+  z.add(e * nleaf * kL * kL);                           // S_L
+  size_t scr = mem::round_up(inverse_ws_bytes<R>((int)mL, (int)nleaf)) + 2 * mem::round_up(e * nleaf * mL * kL);
+  for (long l = L - 1; l >= 0; --l) {
+    const long nb = 1L << l, c = f.c[l], r = f.r[l], k = f.k[l];
+    size_t keep_l = 0, scr_l = 0;
+    if (f.form[l] & 2) {  // Woodbury
+      mem::Sizer a, t;
+      a.add(e * nb * 2 * c * r);
+      a.add(e * nb * 4 * r * r);
+      if (want_T) { a.add(e * nb * 2 * c * r); a.add(e * nb * 4 * r * r); }
+      t.add(e * nb * 3 * r * r);
+      t.add(inverse_ws_bytes<R>((int)std::max(1L, r), (int)nb));
+      if (l >= 1) { t.add(e * nb * 2 * c * k); t.add(e * nb * 4 * r * k); }
+      keep_l = std::max(keep_l, a.total);
+      scr_l = std::max(scr_l, t.total);
+    }
+    if (f.form[l] & 1) {  // Schur
+      mem::Sizer a, t;
+      for (int q = 0; q < (want_T ? 6 : 3); ++q) a.add(e * nb * c * c);
+      t.add(inverse_ws_bytes<R>((int)c, (int)nb));
+      if (l >= 1) for (int q = 0; q < 3; ++q) t.add(e * nb * c * k);
+      keep_l = std::max(keep_l, a.total);
+      scr_l = std::max(scr_l, t.total);
+    }
+    z.add(keep_l);
+    z.add_n<int>(nb);                                   // merge flags
+    if (l >= 1) z.add(e * nb * k * k);                  // S_l
+    scr = std::max(scr, scr_l);
+  }
+  // apply vectors for APPLY_GROUP right-hand sides
+  const long G = APPLY_GROUP;
+  z.add(e * G * nleaf * mL);
+  size_t big = 0;
+  for (long l = 1; l <= L; ++l) {
+    const size_t v = (size_t)G * ((size_t)1 << l) * f.k[l];
+    z.add(e * v);
+    z.add(e * v);
+    big = std::max(big, v);
+  }
+  for (int q = 0; q < 5; ++q) z.add(e * big);
+  if (sizeof(R) == 4) z.add(kSplitKBytes);
+  if (want_T) {  // transposed leaf and scattering matrices, transpose-pass vectors
+    z.add(e * nleaf * mL * mL);
+    for (long l = 1; l <= L; ++l) z.add(e * ((size_t)1 << l) * f.k[l] * f.k[l]);
+    for (long l = 1; l < L; ++l) z.add(e * G * ((size_t)1 << l) * 2 * f.c[l]);
+  }
+  FactorBytes b;
+  b.keep = z.total;
+  b.scr = scr;
+  return b;
+}
+
+FactorBytes factor_bytes(const Profile& f, bool want_T) {
+  return f.f32 ? factor_bytes_t<float>(f, want_T) : factor_bytes_t<double>(f, want_T);
 }
 
 // ------------------------------------------------------------ factor
@@ -528,23 +744,21 @@ struct FactorData {
   DevBuf XT;
   std::vector<DevBuf> ST, PaT, PbT, CiT;
   std::vector<DevBuf> vb;         // transpose pass: per parent level [nrhs][2^l][2c]
-  int vb_nrhs = 0;
   // singularity flags of the local inverses, read back once when the factor ends
-  std::vector<AsyncBuf> info;  // stream-ordered: freeing them never waits for the device
-  // Temporaries of the build (products, inverse workspaces): held until the
-  // factor is built, then returned to the device cache (release_scratch,
-  // after the final synchronisation), since freeing large blocks mid-build
-  // stalls the enqueueing thread for milliseconds.
-  std::deque<DevBuf> scratch;
+  std::vector<DevBuf> info;
+  // The factor's arenas (its workspace): keep holds the factor, the apply
+  // vectors and the transposed copies; scr the temporaries of the build,
+  // rewound at the start of every level (all of the build runs on one
+  // stream, so a level's temporaries are reused only after the previous
+  // level's kernels).
+  mem::Arena* keep = nullptr;
+  mem::Arena* scr = nullptr;
+  bool want_T = false;  // room for the transposed copies was reserved
   template <typename T = void>
   T* scratch_buf(size_t bytes) {
-    scratch.emplace_back(bytes ? bytes : 1);
-    return static_cast<T*>(scratch.back().p);
+    return static_cast<T*>(scr->take(bytes));
   }
-  void release_scratch() {
-    mem::Recycle r;
-    scratch.clear();
-  }
+  void scratch_reset() { scr->reset(0); }
   std::vector<int> info_n;
   std::vector<std::string> info_what;
 };
@@ -591,13 +805,15 @@ void factor_leaves(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipSt
   const int L = P.L, nleaf = P.nleaf, mL = P.mL, kL = P.lev[L].k;
   const double k2 = P.kappa * P.kappa;
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0);
+  mem::Bind bind(F.keep);
+  F.scratch_reset();
   // leaves: X = (I + B G_leaf)^{-1}, S = U^T X B U
   F.X.alloc(sizeof(cplx<R>) * (size_t)nleaf * mL * mL);
   cplx<R>* X = F.X.template as<cplx<R>>();
   leaf_build<R>(s, X, P.Gleaf<R>(), mL, b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
   {
     void* ws = F.scratch_buf(inverse_ws_bytes<R>(mL, nleaf));
-    F.info.emplace_back(sizeof(int) * nleaf, s);
+    F.info.emplace_back(sizeof(int) * nleaf);
     F.info_n.push_back(nleaf);
     F.info_what.push_back("singular leaf matrix I + B G");
     inverse<R>(s, X, mL, mL, (long)mL * mL, nleaf, ws, F.info.back().template as<int>());
@@ -627,6 +843,7 @@ void factor_merge_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, hipStrea
   const int c = P.lev[l].c, r = P.lev[l].wr, nb = 1 << l;
   const long cc = (long)c * c, cr = (long)c * r, rr = (long)r * r, r2 = 2L * r, w4 = 4L * rr;
   const cplx<R>* Sch = F.S[l + 1].template as<cplx<R>>();
+  mem::Bind bind(F.keep);
   F.wr[l] = r;
   F.Pa[l].alloc(sizeof(cplx<R>) * nb * 2 * cr);
   F.Ci[l].alloc(sizeof(cplx<R>) * nb * w4);
@@ -645,7 +862,7 @@ void factor_merge_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, hipStrea
   cgemm<R>(s, r, r, r, mone, Bw, r, rr, OP_N, Aw, r, rr, OP_N, zero, nullptr, 0, 0, C, r, rr, nb, true);
   {
     void* ws = F.scratch_buf(inverse_ws_bytes<R>(r, nb));
-    F.info.emplace_back(sizeof(int) * nb, s);
+    F.info.emplace_back(sizeof(int) * nb);
     F.info_n.push_back(nb);
     F.info_what.push_back("singular merge matrix I - Bw Aw at level " + std::to_string(l));
     inverse<R>(s, C, r, r, rr, nb, ws, F.info.back().template as<int>());
@@ -660,7 +877,9 @@ void factor_merge_lowrank(const lsh_plan_s& P, FactorData<R>& F, int l, hipStrea
 // merge of parent level l: P_a, P_b, C^{-1} (needs G_ab of level l)
 template <typename R>
 void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  F.scratch_reset();  // (a new level: the previous level's temporaries are done in stream order)
   if (P.lev[l].wr > 0) return factor_merge_lowrank(P, F, l, s);
+  mem::Bind bind(F.keep);
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
   const int c = P.lev[l].c, nb = 1 << l;
   const long cc = (long)c * c;
@@ -678,7 +897,7 @@ void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   cgemm<R>(s, c, c, c, mone, Pb, c, cc, OP_N, Pa, c, cc, OP_N, zero, nullptr, 0, 0, Ci, c, cc, nb, true);
   {
     void* ws = F.scratch_buf(inverse_ws_bytes<R>(c, nb));
-    F.info.emplace_back(sizeof(int) * nb, s);
+    F.info.emplace_back(sizeof(int) * nb);
     F.info_n.push_back(nb);
     F.info_what.push_back("singular merge matrix I - Pb Pa at level " + std::to_string(l));
     inverse<R>(s, Ci, c, c, cc, nb, ws, F.info.back().template as<int>());
@@ -689,6 +908,7 @@ void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
 template <typename R>
 void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   if (l == 0) return;
+  mem::Bind bind(F.keep);
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
   const int c = P.lev[l].c, nb = 1 << l;
   const long cc = (long)c * c;
@@ -745,19 +965,12 @@ void factor_level(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   factor_scatter(P, F, l, s);
 }
 
+// The apply vectors (for APPLY_GROUP right-hand sides), from the factor's keep arena.
 template <typename R>
-void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStream_t s) {
-  factor_init(P, F);
-  factor_leaves(P, b, F, s);
-  for (int l = P.L - 1; l >= 0; --l) factor_level(P, F, l, s);
-  factor_check(F, s);
-  F.release_scratch();
-}
-
-template <typename R>
-void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
-  if (F.ws_nrhs >= nrhs) return;
-  const int L = P.L;
+void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F) {
+  if (F.ws_nrhs) return;
+  mem::Bind bind(F.keep);
+  const int L = P.L, nrhs = APPLY_GROUP;
   F.r.alloc(sizeof(cplx<R>) * (size_t)nrhs * P.nleaf * P.mL);
   F.rt.clear();
   F.wt.clear();
@@ -775,8 +988,17 @@ void ensure_apply_ws(const lsh_plan_s& P, FactorData<R>& F, int nrhs) {
   F.t3.alloc(sizeof(cplx<R>) * big);
   F.ty.alloc(sizeof(cplx<R>) * big);
   F.tw.alloc(sizeof(cplx<R>) * big);
-  if (sizeof(R) == 4 && !F.tk.p) F.tk.alloc(size_t(24) << 20);  // (FP64 products do not split)
+  if (sizeof(R) == 4) F.tk.alloc(kSplitKBytes);  // (FP64 products do not split)
   F.ws_nrhs = nrhs;
+}
+
+template <typename R>
+void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStream_t s) {
+  factor_init(P, F);
+  factor_leaves(P, b, F, s);
+  for (int l = P.L - 1; l >= 0; --l) factor_level(P, F, l, s);
+  factor_check(F, s);
+  ensure_apply_ws(P, F);
 }
 
 // up to this many box vectors the shared products stream the matrix rows
@@ -863,6 +1085,9 @@ void apply_X(const lsh_plan_s& P, FactorData<R>& F, int l, int nrhs, const cplx<
 template <typename R>
 void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
   if (F.has_T) return;
+  LSH_REQUIRE(F.want_T, LSH_ERR_INVALID_ARG,
+              "M^T needs a factor created with LSH_FACTOR_TRANSPOSE (room for the transposed copies)");
+  mem::Bind bind(F.keep);
   const int L = P.L;
   F.XT.alloc(F.X.bytes);
   ctranspose<R>(s, F.X.template as<cplx<R>>(), P.mL, P.mL, F.XT.template as<cplx<R>>(), P.nleaf);
@@ -890,6 +1115,10 @@ void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
     ctranspose<R>(s, F.Pb[l].template as<cplx<R>>(), c, c, F.PbT[l].template as<cplx<R>>(), 1L << l);
     ctranspose<R>(s, F.Ci[l].template as<cplx<R>>(), c, c, F.CiT[l].template as<cplx<R>>(), 1L << l);
   }
+  F.vb.clear();
+  F.vb.resize(L);
+  for (int l = 1; l < L; ++l)
+    F.vb[l].alloc(sizeof(cplx<R>) * (size_t)APPLY_GROUP * ((size_t)1 << l) * 2 * P.lev[l].c);
   LSH_HIP(hipStreamSynchronize(s));
   F.has_T = true;
 }
@@ -897,7 +1126,7 @@ void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
 template <typename R>
 void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* f, z64* q, int nrhs,
              hipStream_t s) {
-  ensure_apply_ws(P, F, nrhs);
+  LSH_REQUIRE(F.ws_nrhs >= nrhs, LSH_ERR_INVALID_ARG, "internal: apply workspace");
   const int L = P.L;
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
   const double k2 = P.kappa * P.kappa;
@@ -948,17 +1177,11 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
 template <typename R>
 void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* g, z64* q, int nrhs,
               hipStream_t s) {
-  ensure_apply_ws(P, F, nrhs);
+  LSH_REQUIRE(F.ws_nrhs >= nrhs, LSH_ERR_INVALID_ARG, "internal: apply workspace");
   ensure_transposed(P, F, s);
   const int L = P.L;
   const cplx<R> one = mk<R>(1, 0), zero = mk<R>(0, 0), mone = mk<R>(-1, 0);
   const double k2 = P.kappa * P.kappa;
-  if (F.vb_nrhs < nrhs) {
-    F.vb.clear();
-    F.vb.resize(L);
-    for (int l = 1; l < L; ++l) F.vb[l].alloc(sizeof(cplx<R>) * (size_t)nrhs * ((size_t)1 << l) * 2 * P.lev[l].c);
-    F.vb_nrhs = nrhs;
-  }
   cplx<R>* t1 = F.t1.template as<cplx<R>>();
   cplx<R>* t2 = F.t2.template as<cplx<R>>();
   cplx<R>* t3 = F.t3.template as<cplx<R>>();
@@ -1006,19 +1229,26 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
 
 struct lsh_factor_s {
   lsh_plan_s* plan = nullptr;
+  // the caller's factor workspace: keep (b, the factor, apply vectors) and scr
+  mem::Arena keep, scr;
   DevBuf b;  // private copy of b (device, FP64)
+  DevBuf bad;  // non-finite flag of the input check
   FactorData<float> f32;
   FactorData<double> f64;
-  // FGMRES workspace
-  int gm_maxit = 0, gm_nr = 0;
-  DevBuf V, Z, w, h1, h2, part, fvec, res;
+  // y = M x (or M^T x) in groups of APPLY_GROUP right-hand sides
   void apply(const z64* x, z64* y, int nrhs, hipStream_t s, bool transpose = false) {
-    if (plan->d.hbs_prec == LSH_FP32) {
-      if (transpose) apply_MT<float>(*plan, b.as<double>(), f32, x, y, nrhs, s);
-      else apply_M<float>(*plan, b.as<double>(), f32, x, y, nrhs, s);
-    } else {
-      if (transpose) apply_MT<double>(*plan, b.as<double>(), f64, x, y, nrhs, s);
-      else apply_M<double>(*plan, b.as<double>(), f64, x, y, nrhs, s);
+    const long N = (long)plan->n * plan->n;
+    for (int r0 = 0; r0 < nrhs; r0 += APPLY_GROUP) {
+      const int nr = std::min(APPLY_GROUP, nrhs - r0);
+      const z64* xi = x + r0 * N;
+      z64* yi = y + r0 * N;
+      if (plan->d.hbs_prec == LSH_FP32) {
+        if (transpose) apply_MT<float>(*plan, b.as<double>(), f32, xi, yi, nr, s);
+        else apply_M<float>(*plan, b.as<double>(), f32, xi, yi, nr, s);
+      } else {
+        if (transpose) apply_MT<double>(*plan, b.as<double>(), f64, xi, yi, nr, s);
+        else apply_M<double>(*plan, b.as<double>(), f64, xi, yi, nr, s);
+      }
     }
   }
 };
@@ -1036,30 +1266,87 @@ __global__ void k_rhs(z64* f, const z64* u, const double* b, double k2, long N) 
     f[i] = (-k2 * b[i]) * u[i];
 }
 
+// right-hand sides solved together by the lockstep solver (memory: the
+// Krylov basis holds (maxit + 1) * SOLVE_GROUP grid vectors)
+constexpr int SOLVE_GROUP = 8;
+
+// FGMRES arrays for G right-hand sides in lockstep and maxit iterations,
+// carved from the caller's solve workspace: f [G][N] (right-hand sides),
+// V [maxit + 1][G][N], Z [maxit][G][N], the Hessenberg columns h1, h2
+// [G][maxit + 2], the reduction partials, res [G][N].
+struct SolveWs {
+  int G = 0, maxit = 0;
+  z64 *f = nullptr, *V = nullptr, *Z = nullptr, *h1 = nullptr, *h2 = nullptr, *part = nullptr, *res = nullptr;
+  template <typename Take>
+  static SolveWs carve(Take&& take, long N, int G, int maxit) {
+    SolveWs w;
+    w.G = G;
+    w.maxit = maxit;
+    w.f = static_cast<z64*>(take(sizeof(z64) * (size_t)G * N));
+    w.V = static_cast<z64*>(take(sizeof(z64) * (size_t)(maxit + 1) * G * N));
+    w.Z = static_cast<z64*>(take(sizeof(z64) * (size_t)maxit * G * N));
+    w.h1 = static_cast<z64*>(take(sizeof(z64) * (size_t)G * (maxit + 2)));
+    w.h2 = static_cast<z64*>(take(sizeof(z64) * (size_t)G * (maxit + 2)));
+    w.part = static_cast<z64*>(take(multidot_partial_bytes(maxit + 2)));
+    w.res = static_cast<z64*>(take(sizeof(z64) * (size_t)G * N));
+    return w;
+  }
+  static size_t bytes(long N, int G, int maxit) {
+    mem::Sizer z;
+    carve([&](size_t b) { z.add(b); return (void*)nullptr; }, N, G, maxit);
+    return z.total;
+  }
+};
+
+// Stream time of the three phases of an FGMRES iteration (preconditioner,
+// operator, Gram-Schmidt), from event pairs read after the iteration's
+// synchronisation; added to the info's ms fields.
+struct PhaseClock {
+  bool on = false;
+  hipEvent_t e[4] = {};
+  double ms[3] = {0, 0, 0};
+  explicit PhaseClock(bool enable) : on(enable) {
+    if (on)
+      for (auto& x : e) LSH_HIP(hipEventCreate(&x));
+  }
+  ~PhaseClock() {
+    if (on)
+      for (auto x : e) (void)hipEventDestroy(x);
+  }
+  PhaseClock(const PhaseClock&) = delete;
+  PhaseClock& operator=(const PhaseClock&) = delete;
+  void mark(int i, hipStream_t s) {
+    if (on) LSH_HIP(hipEventRecord(e[i], s));
+  }
+  void add() {  // (after the stream has been synchronised)
+    if (!on) return;
+    for (int q = 0; q < 3; ++q) {
+      float t = 0;
+      LSH_HIP(hipEventElapsedTime(&t, e[q], e[q + 1]));
+      ms[q] += t;
+    }
+  }
+  void store(lsh_info* info) const {
+    if (!on || !info) return;
+    info->ms_precond += ms[0];
+    info->ms_operator += ms[1];
+    info->ms_ortho += ms[2];
+  }
+};
+
 // Right-preconditioned flexible GMRES on A (or on A^T = I + K B with M^T
 // when transposed), x0 = 0, CGS2, Givens rotations on the host.
-void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, lsh_info* info, double& true_res,
-                int& conv, hipStream_t s, bool transposed = false) {
+void fgmres_one(lsh_factor_s& F, SolveWs& W, const z64* f, z64* x, const lsh_solve_opts& o, lsh_info* info,
+                double& true_res, int& conv, hipStream_t s, bool transposed = false) {
   lsh_plan_s& P = *F.plan;
   const long N = (long)P.n * P.n;
   const int maxit = o.maxit;
-  if (F.gm_maxit < maxit) {
-    const int mr = std::max(1, F.gm_nr);
-    F.V.alloc(sizeof(z64) * (size_t)(maxit + 1) * mr * N);
-    F.Z.alloc(sizeof(z64) * (size_t)maxit * mr * N);
-    F.w.alloc(sizeof(z64) * N);
-    F.h1.alloc(sizeof(z64) * (size_t)mr * (maxit + 2));
-    F.h2.alloc(sizeof(z64) * (size_t)mr * (maxit + 2));
-    F.part.alloc(multidot_partial_bytes(maxit + 2));
-    F.res.alloc(sizeof(z64) * (size_t)mr * N);
-    F.gm_maxit = maxit;
-    F.gm_nr = mr;
-  }
-  z64* V = F.V.as<z64>();
-  z64* Z = F.Z.as<z64>();
-  z64* h1 = F.h1.as<z64>();
-  z64* h2 = F.h2.as<z64>();
-  z64* part = F.part.as<z64>();
+  LSH_REQUIRE(W.maxit >= maxit && W.G >= 1, LSH_ERR_INVALID_ARG, "internal: solve workspace");
+  z64* V = W.V;
+  z64* Z = W.Z;
+  z64* h1 = W.h1;
+  z64* h2 = W.h2;
+  z64* part = W.part;
   multidot(s, f, 0, 1, f, N, h1, part);
   z64 fn;
   LSH_HIP(hipMemcpyAsync(&fn, h1, sizeof(z64), hipMemcpyDeviceToHost, s));
@@ -1077,22 +1364,28 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
   std::vector<z64> hv(maxit + 2), hv2(maxit + 2);
   int j = 0, its = 0;
   double est = 1.0;
+  PhaseClock clk(info != nullptr);
   for (j = 0; j < maxit; ++j) {
     z64* vj = V + (long)j * N;
     z64* zj = Z + (long)j * N;
     z64* w = V + (long)(j + 1) * N;
+    clk.mark(0, s);
     if (o.precondition) F.apply(vj, zj, 1, s, transposed);
     else LSH_HIP(hipMemcpyAsync(zj, vj, sizeof(z64) * N, hipMemcpyDeviceToDevice, s));
+    clk.mark(1, s);
     P.op.apply(s, F.b.as<double>(), zj, w, 1, transposed);
+    clk.mark(2, s);
     // classical Gram-Schmidt, twice
     multidot(s, V, N, j + 1, w, N, h1, part);
     multiaxpy(s, w, V, N, j + 1, h1, N);
     multidot(s, V, N, j + 1, w, N, h2, part);
     multiaxpy(s, w, V, N, j + 1, h2, N);
     multidot(s, w, 0, 1, w, N, h2 + (j + 1), part);
+    clk.mark(3, s);
     LSH_HIP(hipMemcpyAsync(hv.data(), h1, sizeof(z64) * (j + 1), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipMemcpyAsync(hv2.data(), h2, sizeof(z64) * (j + 2), hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
+    clk.add();
     const double hn = std::sqrt(hv2[j + 1].x);
     if (hn > 0) scale_by_invnorm(s, w, w, h2 + (j + 1), N);
     auto Hc = [&](int r, int c) -> std::complex<double>& { return H[(size_t)r * maxit + c]; };
@@ -1129,7 +1422,7 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
   LSH_HIP(hipMemcpyAsync(h1, yz.data(), sizeof(z64) * k, hipMemcpyHostToDevice, s));
   lincomb(s, x, Z, N, k, h1, N);
   // true residual
-  z64* r = F.res.as<z64>();
+  z64* r = W.res;
   P.op.apply(s, F.b.as<double>(), x, r, 1, transposed);
   sub_from(s, r, f, N);
   multidot(s, r, 0, 1, r, N, h2, part);
@@ -1138,12 +1431,9 @@ void fgmres_one(lsh_factor_s& F, const z64* f, z64* x, const lsh_solve_opts& o, 
   LSH_HIP(hipStreamSynchronize(s));
   true_res = std::sqrt(rn.x) / beta;
   if (info) { info->iterations = its; info->residual = est; }
+  clk.store(info);
   conv = true_res < o.tol ? 1 : 0;
 }
-
-// right-hand sides solved together by the lockstep solver (memory: the
-// Krylov basis holds (maxit + 1) * SOLVE_GROUP grid vectors)
-constexpr int SOLVE_GROUP = 8;
 
 // Flexible GMRES for nr right-hand sides in lockstep: every iteration applies
 // the preconditioner and the operator once to all nr current basis vectors
@@ -1153,28 +1443,17 @@ constexpr int SOLVE_GROUP = 8;
 // Z[j][r][N]; f, x: [nr][N]. A right-hand side that has stopped gets a zero
 // basis vector, which the (linear, per-vector) applies keep at zero.
 // info: iterations, estimate and history of the last right-hand side.
-void fgmres_multi(lsh_factor_s& F, const z64* f, z64* x, int nr, const lsh_solve_opts& o, lsh_info* info,
-                  double& worst, int& allconv, hipStream_t s, bool transposed = false) {
+void fgmres_multi(lsh_factor_s& F, SolveWs& W, const z64* f, z64* x, int nr, const lsh_solve_opts& o,
+                  lsh_info* info, double& worst, int& allconv, hipStream_t s, bool transposed = false) {
   lsh_plan_s& P = *F.plan;
   const long N = (long)P.n * P.n, S = (long)nr * N;
   const int maxit = o.maxit, hs = maxit + 2;
-  if (F.gm_maxit < maxit || F.gm_nr < nr) {
-    const int mi = std::max(maxit, F.gm_maxit), mr = std::max(nr, F.gm_nr);
-    F.V.alloc(sizeof(z64) * (size_t)(mi + 1) * mr * N);
-    F.Z.alloc(sizeof(z64) * (size_t)mi * mr * N);
-    F.w.alloc(sizeof(z64) * N);
-    F.h1.alloc(sizeof(z64) * (size_t)mr * (mi + 2));
-    F.h2.alloc(sizeof(z64) * (size_t)mr * (mi + 2));
-    F.part.alloc(multidot_partial_bytes(mi + 2));
-    F.res.alloc(sizeof(z64) * (size_t)mr * N);
-    F.gm_maxit = mi;
-    F.gm_nr = mr;
-  }
-  z64* V = F.V.as<z64>();
-  z64* Z = F.Z.as<z64>();
-  z64* h1 = F.h1.as<z64>();
-  z64* h2 = F.h2.as<z64>();
-  z64* part = F.part.as<z64>();
+  LSH_REQUIRE(W.maxit >= maxit && W.G >= nr, LSH_ERR_INVALID_ARG, "internal: solve workspace");
+  z64* V = W.V;
+  z64* Z = W.Z;
+  z64* h1 = W.h1;
+  z64* h2 = W.h2;
+  z64* part = W.part;
   for (int r = 0; r < nr; ++r) multidot(s, f + r * N, 0, 1, f + r * N, N, h1 + r * hs, part);
   std::vector<z64> hv((size_t)nr * hs), hv2((size_t)nr * hs);
   LSH_HIP(hipMemcpyAsync(hv.data(), h1, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
@@ -1206,13 +1485,17 @@ void fgmres_multi(lsh_factor_s& F, const z64* f, z64* x, int nr, const lsh_solve
     R.active = true;
     ++nact;
   }
+  PhaseClock clk(info != nullptr);
   for (int j = 0; j < maxit && nact > 0; ++j) {
     z64* vj = V + (long)j * S;
     z64* zj = Z + (long)j * S;
     z64* wj = V + (long)(j + 1) * S;
+    clk.mark(0, s);
     if (o.precondition) F.apply(vj, zj, nr, s, transposed);
     else LSH_HIP(hipMemcpyAsync(zj, vj, sizeof(z64) * S, hipMemcpyDeviceToDevice, s));
+    clk.mark(1, s);
     P.op.apply(s, F.b.as<double>(), zj, wj, nr, transposed);
+    clk.mark(2, s);
     for (int r = 0; r < nr; ++r) {
       if (!run[r].active) continue;
       z64* w = wj + r * N;
@@ -1223,9 +1506,11 @@ void fgmres_multi(lsh_factor_s& F, const z64* f, z64* x, int nr, const lsh_solve
       multiaxpy(s, w, V + r * N, S, j + 1, a2, N);
       multidot(s, w, 0, 1, w, N, a2 + (j + 1), part);
     }
+    clk.mark(3, s);
     LSH_HIP(hipMemcpyAsync(hv.data(), h1, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
     LSH_HIP(hipMemcpyAsync(hv2.data(), h2, sizeof(z64) * nr * hs, hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
+    clk.add();
     for (int r = 0; r < nr; ++r) {
       Run& R = run[r];
       if (!R.active) continue;
@@ -1279,7 +1564,7 @@ void fgmres_multi(lsh_factor_s& F, const z64* f, z64* x, int nr, const lsh_solve
     else fill_zero(s, x + r * N, sizeof(z64) * N);
   }
   // true residuals, one operator pass for the group
-  z64* res = F.res.as<z64>();
+  z64* res = W.res;
   P.op.apply(s, F.b.as<double>(), x, res, nr, transposed);
   for (int r = 0; r < nr; ++r) {
     sub_from(s, res + r * N, f + r * N, N);
@@ -1293,6 +1578,7 @@ void fgmres_multi(lsh_factor_s& F, const z64* f, z64* x, int nr, const lsh_solve
     if (!(tr < o.tol) && R.beta > 0) allconv = 0;
     if (tr > worst) worst = tr;
   }
+  clk.store(info);
   if (info) {
     const Run& R = run[nr - 1];
     info->iterations = R.its;
@@ -1372,6 +1658,56 @@ __global__ void k_grad_b(const z64* __restrict__ lam, const z64* __restrict__ ui
   }
 }
 
+void check_ws(void* ws, size_t bytes, size_t need, const char* what) {
+  LSH_REQUIRE(need == 0 || ws, LSH_ERR_INVALID_ARG, std::string("null ") + what + " workspace");
+  LSH_REQUIRE(((uintptr_t)ws & (mem::kGranule - 1)) == 0, LSH_ERR_INVALID_ARG,
+              std::string(what) + " workspace must be 256-byte aligned");
+  LSH_REQUIRE(bytes >= need, LSH_ERR_WORKSPACE_TOO_SMALL,
+              std::string(what) + " workspace: " + std::to_string(bytes) + " bytes given, " + std::to_string(need) +
+                  " needed");
+}
+
+// Splits a caller's plan workspace into the plan's arenas (the part beyond
+// the bound goes to the kept memory).
+void attach_plan(lsh_plan_s& P, void* ws, size_t bytes) {
+  const PlanBytes b = plan_bytes(P.d, nullptr);
+  check_ws(ws, bytes, b.total(), "plan");
+  char* p = static_cast<char*>(ws);
+  const size_t keep = bytes - b.sid - b.ssib;
+  P.persist.attach(p, keep, "plan");
+  P.sid.attach(p + keep, b.sid, "plan row-ID temporaries");
+  P.ssib.attach(p + keep + b.sid, b.ssib, "plan sibling-block temporaries");
+}
+
+// The same for a factor, sized by the rank profile f.
+void attach_factor(lsh_factor_s& F, const Profile& f, int flags, void* ws, size_t bytes) {
+  const bool want_T = (flags & LSH_FACTOR_TRANSPOSE) != 0;
+  const FactorBytes b = factor_bytes(f, want_T);
+  check_ws(ws, bytes, b.total(), "factor");
+  char* p = static_cast<char*>(ws);
+  const size_t keep = bytes - b.scr;
+  F.keep.attach(p, keep, "factor");
+  F.scr.attach(p + keep, b.scr, "factor temporaries");
+  for (auto* d : {&F.f32.keep, &F.f64.keep}) *d = &F.keep;
+  F.f32.scr = F.f64.scr = &F.scr;
+  F.f32.want_T = F.f64.want_T = want_T;
+}
+
+// The factor's private copy of b, checked for non-finite entries.
+void copy_check_b(lsh_factor_s& F, const double* b, long N, hipStream_t s, const std::string& what) {
+  mem::Bind bind(&F.keep);
+  F.b.alloc(sizeof(double) * N);
+  F.bad.alloc(sizeof(int));
+  LSH_HIP(hipMemcpyAsync(F.b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  fill_zero(s, F.bad.p, sizeof(int));
+  hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F.b.as<double>(), N, F.bad.as<int>());
+  LSH_LAUNCH_CHECK();
+  int hb = 0;
+  LSH_HIP(hipMemcpyAsync(&hb, F.bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  LSH_HIP(hipStreamSynchronize(s));
+  LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries" + what);
+}
+
 int fail(const lsh::Error& e) {
   g_last_error = e.what();
   return e.code;
@@ -1425,14 +1761,6 @@ int lsh_grad_b(lsh_plan_t P, const void* lambda, const void* u_inc, const void* 
   API_END
 }
 
-int lsh_cache_trim(size_t* cached) {
-  API_BEGIN
-  if (cached) *cached = mem::cached_bytes();
-  mem::trim();
-  return LSH_OK;
-  API_END
-}
-
 int lsh_profile_enable(int on) {
   API_BEGIN
   prof::set(on != 0);
@@ -1481,12 +1809,23 @@ int lsh_correction_weights(int order, double kh, int* count, int* offsets, doubl
   API_END
 }
 
-int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan) {
+int lsh_plan_workspace(const lsh_desc* desc, size_t* bytes) {
+  API_BEGIN
+  LSH_REQUIRE(desc && bytes, LSH_ERR_INVALID_ARG, "null argument");
+  validate(*desc);
+  *bytes = plan_bytes(*desc, nullptr).total();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_create(const lsh_desc* desc, void* ws, size_t ws_bytes, void* stream, lsh_plan_t* plan) {
   API_BEGIN
   LSH_REQUIRE(desc && plan, LSH_ERR_INVALID_ARG, "null argument");
   validate(*desc);
   std::unique_ptr<lsh_plan_s> P(new lsh_plan_s());
   P->d = *desc;
+  attach_plan(*P, ws, ws_bytes);
+  mem::Bind bind(&P->persist);
   plan_build(*P, (hipStream_t)stream);
   *plan = P.release();
   return LSH_OK;
@@ -1495,8 +1834,16 @@ int lsh_plan_create(const lsh_desc* desc, void* stream, lsh_plan_t* plan) {
 
 int lsh_plan_destroy(lsh_plan_t plan) {
   API_BEGIN
-  mem::Recycle r;
   delete plan;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_plan_workspace_used(lsh_plan_t P, size_t* used, size_t* size) {
+  API_BEGIN
+  LSH_REQUIRE(P, LSH_ERR_INVALID_ARG, "null plan");
+  if (used) *used = P->persist.high() + P->sid.high() + P->ssib.high();
+  if (size) *size = P->persist.cap() + P->sid.cap() + P->ssib.cap();
   return LSH_OK;
   API_END
 }
@@ -1529,9 +1876,9 @@ int lsh_plan_level(lsh_plan_t P, int level, int* m, int* k, int* J, int* cand, v
   API_END
 }
 
-int lsh_plan_cache_info(int* entries, size_t* device_bytes) {
+int lsh_plan_cache_info(int* entries, size_t* host_bytes) {
   API_BEGIN
-  pcache::info(entries, device_bytes);
+  pcache::info(entries, host_bytes);
   return LSH_OK;
   API_END
 }
@@ -1602,24 +1949,33 @@ int lsh_plan_table(lsh_plan_t P, int* D, void* out, void* stream) {
   API_END
 }
 
-int lsh_factor_create(lsh_plan_t P, const double* b, void* stream, lsh_factor_t* factor) {
+int lsh_factor_workspace(lsh_plan_t P, int flags, size_t* bytes) {
+  API_BEGIN
+  LSH_REQUIRE(P && bytes, LSH_ERR_INVALID_ARG, "null argument");
+  *bytes = factor_bytes(plan_profile(*P), (flags & LSH_FACTOR_TRANSPOSE) != 0).total();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_factor_workspace_used(lsh_factor_t F, size_t* used, size_t* size) {
+  API_BEGIN
+  LSH_REQUIRE(F, LSH_ERR_INVALID_ARG, "null factor");
+  if (used) *used = F->keep.high() + F->scr.high();
+  if (size) *size = F->keep.cap() + F->scr.cap();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_factor_create(lsh_plan_t P, const double* b, int flags, void* ws, size_t ws_bytes, void* stream,
+                      lsh_factor_t* factor) {
   API_BEGIN
   LSH_REQUIRE(P && b && factor, LSH_ERR_INVALID_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
   const long N = (long)P->n * P->n;
   std::unique_ptr<lsh_factor_s> F(new lsh_factor_s());
   F->plan = P;
-  F->b.alloc(sizeof(double) * N);
-  LSH_HIP(hipMemcpyAsync(F->b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-  {
-    AsyncBuf bad(sizeof(int), s);
-    fill_zero(s, bad.p, sizeof(int));
-    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
-    int hb = 0;
-    LSH_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    LSH_HIP(hipStreamSynchronize(s));
-    LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries");
-  }
+  attach_factor(*F, plan_profile(*P), flags, ws, ws_bytes);
+  copy_check_b(*F, b, N, s, "");
   if (P->d.hbs_prec == LSH_FP32) factor_build<float>(*P, F->b.as<double>(), F->f32, s);
   else factor_build<double>(*P, F->b.as<double>(), F->f64, s);
   *factor = F.release();
@@ -1707,27 +2063,35 @@ extern "C" {
 // thread on its own stream (its row IDs are latency-bound pivot loops), and
 // the factor of level l starts on the caller's stream as soon as plan level l
 // is recorded.
-int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* plan, lsh_factor_t* factor) {
+int lsh_build_workspace(const lsh_desc* desc, int flags, size_t* plan_bytes_out, size_t* factor_bytes_out) {
+  API_BEGIN
+  LSH_REQUIRE(desc && plan_bytes_out && factor_bytes_out, LSH_ERR_INVALID_ARG, "null argument");
+  validate(*desc);
+  Profile f;
+  *plan_bytes_out = plan_bytes(*desc, &f).total();
+  *factor_bytes_out = factor_bytes(f, (flags & LSH_FACTOR_TRANSPOSE) != 0).total();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, size_t plan_ws_bytes,
+              void* factor_ws, size_t factor_ws_bytes, void* stream, lsh_plan_t* plan, lsh_factor_t* factor) {
   API_BEGIN
   LSH_REQUIRE(desc && b && plan && factor, LSH_ERR_INVALID_ARG, "null argument");
   validate(*desc);
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<lsh_plan_s> P(new lsh_plan_s());
   P->d = *desc;
+  attach_plan(*P, plan_ws, plan_ws_bytes);
   std::unique_ptr<lsh_factor_s> F(new lsh_factor_s());
   F->plan = P.get();
-  const long N = (long)desc->n * desc->n;
-  F->b.alloc(sizeof(double) * N);
-  LSH_HIP(hipMemcpyAsync(F->b.p, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   {
-    AsyncBuf bad(sizeof(int), s);
-    fill_zero(s, bad.p, sizeof(int));
-    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
-    int hb = 0;
-    LSH_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    LSH_HIP(hipStreamSynchronize(s));
-    LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries");
+    Profile f;
+    plan_bytes(*desc, &f);  // the factor's size under the plan's rank bounds
+    attach_factor(*F, f, flags, factor_ws, factor_ws_bytes);
   }
+  const long N = (long)desc->n * desc->n;
+  copy_check_b(*F, b, N, s, "");
   int dev = 0;
   LSH_HIP(hipGetDevice(&dev));
   // The factor runs on a stream kept off LSH_PLAN_CUS compute units, so that
@@ -1752,6 +2116,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   } bsg{bs};
   hipStream_t ps = bs->ps, ps2 = bs->ps2, fsm = bs->fsm;
   hipStream_t fs = fsm ? fsm : s;
+  mem::Bind bind(&P->persist);  // (plan_init; each plan thread binds its own)
   plan_init(*P, ps);
   const int L = P->L;
   bs->events(2 * L + 5);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
@@ -1781,6 +2146,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   std::thread th([&] {
     try {
       LSH_HIP(hipSetDevice(dev));
+      mem::Bind tbind(&P->persist);
       for (int l = L; l >= 1; --l) {
         plan_id(*P, l, ps);
         LSH_HIP(hipEventRecord(ev[l], ps));
@@ -1800,6 +2166,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   std::thread th2([&] {
     try {
       LSH_HIP(hipSetDevice(dev));
+      mem::Bind tbind(&P->persist);
       for (int l = L - 1; l >= 0; --l) {
         {
           std::unique_lock<std::mutex> g(mu);
@@ -1845,6 +2212,7 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
         }
       }
       factor_check(FD, fs);
+      ensure_apply_ws(*P, FD);
       if (fsm) {
         LSH_HIP(hipEventRecord(ev[2 * L + 4], fsm));
         LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 4], 0));
@@ -1865,9 +2233,6 @@ int lsh_build(const lsh_desc* desc, const double* b, void* stream, lsh_plan_t* p
   if (ferr) std::rethrow_exception(ferr);
   LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 2], 0));
   LSH_HIP(hipStreamSynchronize(s));
-  P->release_scratch();
-  F->f32.release_scratch();
-  F->f64.release_scratch();
   *plan = P.release();
   *factor = F.release();
   return LSH_OK;
@@ -1882,12 +2247,17 @@ namespace {
 // instances in wact: the products of factor_merge_lowrank and of the
 // Woodbury branch of factor_scatter, each step one grouped launch over the
 // instances (same operands, shapes and order, so the same bits).
+// Memory: the factors' own parts from each instance's keep arena, each
+// instance's temporaries from its scr arena, the grouped launches' tables,
+// flags and inverse workspace from the arena bound to the thread (the batch's
+// shared workspace); all rewound per level step by the caller.
 void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>& wact, int dpt, hipStream_t s) {
   const c32 one = mk<float>(1, 0), zero = mk<float>(0, 0), mone = mk<float>(-1, 0);
   const int n_inst = (int)Fs.size();
   std::vector<GemmItem> gi;
-  DevBuf gtab, itab;
+  DevBuf itab;
   auto run = [&] {
+    DevBuf gtab;  // (one table per launch)
     cgemm_grouped(s, gi, gtab);
     gi.clear();
   };
@@ -1905,9 +2275,9 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
     Lv v{l, c, r, 1 << l, P.lev[l].k, (long)c * c, (long)c * r, (long)r * r, 2L * r, 4L * r * r, &P, &Fs[i]->f32};
     FactorData<float>& F = *v.F;
     F.wr[l] = r;
-    F.Pa[l].alloc(sizeof(c32) * v.nb * 2 * v.cr);
-    F.Ci[l].alloc(sizeof(c32) * v.nb * v.w4);
-    T[i].alloc(sizeof(c32) * v.nb * 3 * v.rr);
+    F.Pa[l].alloc_in(*F.keep, sizeof(c32) * v.nb * 2 * v.cr);
+    F.Ci[l].alloc_in(*F.keep, sizeof(c32) * v.nb * v.w4);
+    T[i].alloc_in(*F.scr, sizeof(c32) * v.nb * 3 * v.rr);
     info[i].alloc(sizeof(int) * v.nb);
     L.push_back(v);
   }
@@ -1982,9 +2352,9 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
     const Lv& v = L[q];
     if (v.l == 0) continue;
     const int i = wact[q];
-    A12[i].alloc(sizeof(c32) * v.nb * 2 * (long)v.c * v.k);
-    Qb[i].alloc(sizeof(c32) * v.nb * 4 * (long)v.r * v.k);
-    v.F->S[v.l].alloc(sizeof(c32) * v.nb * (long)v.k * v.k);
+    A12[i].alloc_in(*v.F->scr, sizeof(c32) * v.nb * 2 * (long)v.c * v.k);
+    Qb[i].alloc_in(*v.F->scr, sizeof(c32) * v.nb * 4 * (long)v.r * v.k);
+    v.F->S[v.l].alloc_in(*v.F->keep, sizeof(c32) * v.nb * (long)v.k * v.k);
     sc.push_back(i);
     SL.push_back(v);
   }
@@ -2042,15 +2412,21 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
 // Algorithm 1 for many instances at once (FP32 factors): the levels are
 // aligned from the leaves, and every step of a level (each product, the
 // inverses) is one grouped launch over the instances that have that level.
-void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
+void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStream_t s) {
   const int n_inst = (int)Fs.size();
   const c32 one = mk<float>(1, 0), zero = mk<float>(0, 0), mone = mk<float>(-1, 0);
-  DevBuf gtab, itab;
+  mem::Bind bind(&shared);
   std::vector<GemmItem> gi;
   auto run_gemms = [&](DevBuf& tab) {
     cgemm_grouped(s, gi, tab);
     gi.clear();
   };
+  // a new level step: the previous step has been synchronised
+  auto new_step = [&] {
+    shared.reset(0);
+    for (auto* F : Fs) F->scr.reset(0);
+  };
+  new_step();
   int Lmax = 0;
   for (auto* F : Fs) {
     factor_init<float>(*F->plan, F->f32);
@@ -2059,11 +2435,12 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
   // leaves: X = (I + B G_leaf)^{-1}, S = U^T X B U
   std::vector<DevBuf> Yb(n_inst), Zb(n_inst), infos(n_inst);
   std::vector<InvItem> inv;
+  DevBuf itab0;
   for (int i = 0; i < n_inst; ++i) {
     const lsh_plan_s& P = *Fs[i]->plan;
     FactorData<float>& F = Fs[i]->f32;
     const int nleaf = P.nleaf, mL = P.mL;
-    F.X.alloc(sizeof(c32) * (size_t)nleaf * mL * mL);
+    F.X.alloc_in(*F.keep, sizeof(c32) * (size_t)nleaf * mL * mL);
     leaf_build<float>(s, F.X.as<c32>(), P.Gleaf<float>(), mL, Fs[i]->b.as<double>(), P.kappa * P.kappa,
                       P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
     infos[i].alloc(sizeof(int) * nleaf);
@@ -2071,7 +2448,7 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
   }
   {
     DevBuf ws(inverse_grouped_ws_bytes(inv));
-    inverse_grouped(s, inv, ws.p, itab);
+    inverse_grouped(s, inv, ws.p, itab0);
   }
   for (int i = 0; i < n_inst; ++i) {
     LSH_REQUIRE(!check_info(infos[i], Fs[i]->plan->nleaf, s), LSH_ERR_SINGULAR,
@@ -2082,19 +2459,20 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
     const lsh_plan_s& P = *Fs[i]->plan;
     FactorData<float>& F = Fs[i]->f32;
     const int nleaf = P.nleaf, mL = P.mL, kL = P.lev[P.L].k;
-    Yb[i].alloc(sizeof(c32) * (size_t)nleaf * mL * kL);
-    Zb[i].alloc(sizeof(c32) * (size_t)nleaf * mL * kL);
+    Yb[i].alloc_in(*F.scr, sizeof(c32) * (size_t)nleaf * mL * kL);
+    Zb[i].alloc_in(*F.scr, sizeof(c32) * (size_t)nleaf * mL * kL);
     leaf_scale_U<float>(s, Yb[i].as<c32>(), P.U<float>(P.L), mL, kL, Fs[i]->b.as<double>(), P.kappa * P.kappa,
                         P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), nleaf, P.n);
     gi.push_back({mL, kL, mL, one, zero, F.X.as<c32>(), mL, (long)mL * mL, OP_N, Yb[i].as<c32>(), kL,
                   (long)mL * kL, OP_N, nullptr, 0, 0, Zb[i].as<c32>(), kL, (long)mL * kL, nleaf, false});
   }
-  run_gemms(gtab);
+  DevBuf gtab1;
+  run_gemms(gtab1);
   for (int i = 0; i < n_inst; ++i) {
     const lsh_plan_s& P = *Fs[i]->plan;
     FactorData<float>& F = Fs[i]->f32;
     const int nleaf = P.nleaf, mL = P.mL, kL = P.lev[P.L].k;
-    F.S[P.L].alloc(sizeof(c32) * (size_t)nleaf * kL * kL);
+    F.S[P.L].alloc_in(*F.keep, sizeof(c32) * (size_t)nleaf * kL * kL);
     gi.push_back({kL, kL, mL, one, zero, P.U<float>(P.L), kL, 0, OP_T, Zb[i].as<c32>(), kL, (long)mL * kL, OP_N,
                   nullptr, 0, 0, F.S[P.L].as<c32>(), kL, (long)kL * kL, nleaf, false});
   }
@@ -2104,6 +2482,8 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
   Yb.clear(); Zb.clear();
   // levels, aligned from the leaves
   for (int dpt = 1; dpt <= Lmax; ++dpt) {
+    new_step();
+    DevBuf itab;
     std::vector<int> act, wact;  // Schur-form and Woodbury levels, each grouped
     for (int i = 0; i < n_inst; ++i)
       if (Fs[i]->plan->L - dpt >= 0) (Fs[i]->plan->lev[Fs[i]->plan->L - dpt].wr > 0 ? wact : act).push_back(i);
@@ -2119,9 +2499,9 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
       FactorData<float>& F = Fs[i]->f32;
       const int l = lev(i), c = P.lev[l].c, nb = 1 << l;
       const long cc = (long)c * c;
-      F.Pa[l].alloc(sizeof(c32) * nb * cc);
-      F.Pb[l].alloc(sizeof(c32) * nb * cc);
-      F.Ci[l].alloc(sizeof(c32) * nb * cc);
+      F.Pa[l].alloc_in(*F.keep, sizeof(c32) * nb * cc);
+      F.Pb[l].alloc_in(*F.keep, sizeof(c32) * nb * cc);
+      F.Ci[l].alloc_in(*F.keep, sizeof(c32) * nb * cc);
     }
     // P_a = S_a G_ab ; P_b = S_b G_ab^T
     for (int i : act) {
@@ -2174,10 +2554,11 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
       any = true;
       const int c = P.lev[l].c, nb = 1 << l, k = P.lev[l].k;
       const long ck = (long)c * k;
-      A1[i].alloc(sizeof(c32) * nb * ck);
-      A2[i].alloc(sizeof(c32) * nb * ck);
-      Yl[i].alloc(sizeof(c32) * nb * ck);
-      Fs[i]->f32.S[l].alloc(sizeof(c32) * nb * (long)k * k);
+      mem::Arena& scr = Fs[i]->scr;
+      A1[i].alloc_in(scr, sizeof(c32) * nb * ck);
+      A2[i].alloc_in(scr, sizeof(c32) * nb * ck);
+      Yl[i].alloc_in(scr, sizeof(c32) * nb * ck);
+      Fs[i]->f32.S[l].alloc_in(Fs[i]->keep, sizeof(c32) * nb * (long)k * k);
     }
     if (any) {
       auto each = [&](auto&& fn) {
@@ -2233,43 +2614,102 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, hipStream_t s) {
       throw Error(e.code, std::string(e.what()) + " (instance " + std::to_string(i) + ")");
     }
   }
+  for (auto* F : Fs) ensure_apply_ws(*F->plan, F->f32);
+}
+
+// The batch's shared workspace: per level step (rewound between steps) the
+// flags of the step's inverses, their grouped workspace and tables, and the
+// problem tables of the step's grouped products (at most 12 launches of up
+// to two problems per instance).
+size_t batch_shared_bytes(const std::vector<const lsh_plan_s*>& Ps) {
+  std::vector<const lsh_plan_s*> f;
+  int Lmax = 0;
+  for (auto* P : Ps)
+    if (P->d.hbs_prec == LSH_FP32) {
+      f.push_back(P);
+      Lmax = std::max(Lmax, P->L);
+    }
+  if (f.empty()) return mem::kGranule;
+  auto inv_bytes = [](const std::vector<InvItem>& it) {
+    return mem::round_up(inverse_grouped_ws_bytes(it)) + inverse_grouped_arena_bytes(it);
+  };
+  size_t best = 0;
+  {
+    std::vector<InvItem> it;
+    mem::Sizer z;
+    for (auto* P : f) {
+      it.push_back({nullptr, P->mL, (long)P->mL, (long)P->mL * P->mL, P->nleaf, nullptr});
+      z.add_n<int>(P->nleaf);
+    }
+    best = z.total + inv_bytes(it) + 2 * cgemm_grouped_table_bytes(f.size());
+  }
+  for (int dpt = 1; dpt <= Lmax; ++dpt) {
+    std::vector<InvItem> iw, is;
+    mem::Sizer z;
+    for (auto* P : f) {
+      const int l = P->L - dpt;
+      if (l < 0) continue;
+      const Level& v = P->lev[l];
+      const int nb = 1 << l;
+      const int c = v.wr > 0 ? v.wr : v.c;
+      (v.wr > 0 ? iw : is).push_back({nullptr, c, (long)c, (long)c * c, nb, nullptr});
+      z.add_n<int>(nb);
+    }
+    const size_t t = z.total + inv_bytes(iw) + inv_bytes(is) +
+                     (iw.empty() ? 0 : 12 * cgemm_grouped_table_bytes(2 * iw.size())) +
+                     (is.empty() ? 0 : 12 * cgemm_grouped_table_bytes(2 * is.size()));
+    best = std::max(best, t);
+  }
+  return best;
 }
 
 }  // namespace
 
 extern "C" {
 
-int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b, void* stream,
+int lsh_batch_factor_workspace(int ninst, const lsh_plan_t* plans, int flags, size_t* factor_bytes_out,
+                               size_t* shared_bytes) {
+  API_BEGIN
+  LSH_REQUIRE(ninst >= 1 && plans && factor_bytes_out && shared_bytes, LSH_ERR_INVALID_ARG, "null argument");
+  std::vector<const lsh_plan_s*> Ps;
+  for (int i = 0; i < ninst; ++i) {
+    LSH_REQUIRE(plans[i], LSH_ERR_INVALID_ARG, "null plan");
+    Ps.push_back(plans[i]);
+    factor_bytes_out[i] = factor_bytes(plan_profile(*plans[i]), (flags & LSH_FACTOR_TRANSPOSE) != 0).total();
+  }
+  *shared_bytes = batch_shared_bytes(Ps);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b, int flags, void* const* ws,
+                     const size_t* ws_bytes, void* shared_ws, size_t shared_bytes, void* stream,
                      lsh_factor_t* factors) {
   API_BEGIN
-  LSH_REQUIRE(ninst >= 1 && plans && b && factors, LSH_ERR_INVALID_ARG, "null argument");
+  LSH_REQUIRE(ninst >= 1 && plans && b && ws && ws_bytes && factors, LSH_ERR_INVALID_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
-  // Every step below runs on this one stream, so temporaries released here
-  // can go back to the device cache (stream order protects their reuse)
-  // instead of hipFree, which would synchronise the device each time.
-  mem::Recycle recycle;
   std::vector<std::unique_ptr<lsh_factor_s>> own;
   std::vector<lsh_factor_s*> f32;
+  std::vector<const lsh_plan_s*> Ps;
+  for (int i = 0; i < ninst; ++i) {
+    LSH_REQUIRE(plans[i] && b[i], LSH_ERR_INVALID_ARG, "null plan or b");
+    Ps.push_back(plans[i]);
+  }
+  mem::Arena shared;
+  check_ws(shared_ws, shared_bytes, batch_shared_bytes(Ps), "batch shared");
+  shared.attach(shared_ws, shared_bytes, "batch shared");
   for (int i = 0; i < ninst; ++i) {
     lsh_plan_s* P = plans[i];
-    LSH_REQUIRE(P && b[i], LSH_ERR_INVALID_ARG, "null plan or b");
     const long N = (long)P->n * P->n;
     std::unique_ptr<lsh_factor_s> F(new lsh_factor_s());
     F->plan = P;
-    F->b.alloc(sizeof(double) * N);
-    LSH_HIP(hipMemcpyAsync(F->b.p, b[i], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    AsyncBuf bad(sizeof(int), s);
-    fill_zero(s, bad.p, sizeof(int));
-    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, F->b.as<double>(), N, bad.as<int>());
-    int hb = 0;
-    LSH_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    LSH_HIP(hipStreamSynchronize(s));
-    LSH_REQUIRE(!hb, LSH_ERR_INPUT_NONFINITE, "b has non-finite entries (instance " + std::to_string(i) + ")");
+    attach_factor(*F, plan_profile(*P), flags, ws[i], ws_bytes[i]);
+    copy_check_b(*F, b[i], N, s, " (instance " + std::to_string(i) + ")");
     if (P->d.hbs_prec == LSH_FP32) f32.push_back(F.get());
     else factor_build<double>(*P, F->b.as<double>(), F->f64, s);  // FP64 instances: one at a time
     own.push_back(std::move(F));
   }
-  if (!f32.empty()) batch_factor_f32(f32, s);
+  if (!f32.empty()) batch_factor_f32(f32, shared, s);
   for (int i = 0; i < ninst; ++i) factors[i] = own[i].release();
   return LSH_OK;
   API_END
@@ -2277,7 +2717,6 @@ int lsh_batch_factor(int ninst, const lsh_plan_t* plans, const double* const* b,
 
 int lsh_factor_destroy(lsh_factor_t F) {
   API_BEGIN
-  mem::Recycle r;
   delete F;
   return LSH_OK;
   API_END
@@ -2299,8 +2738,31 @@ int lsh_apply_operator(lsh_plan_t P, const double* b, const void* x, void* y, in
   API_END
 }
 
+int lsh_solve_workspace(lsh_factor_t F, int nrhs, int maxit, size_t* bytes) {
+  API_BEGIN
+  LSH_REQUIRE(F && bytes && nrhs >= 1 && maxit >= 1 && maxit <= LSH_MAX_ITERS, LSH_ERR_INVALID_ARG, "bad argument");
+  *bytes = SolveWs::bytes((long)F->plan->n * F->plan->n, std::min(nrhs, SOLVE_GROUP), maxit);
+  return LSH_OK;
+  API_END
+}
+
+}  // extern "C"
+
+namespace {
+// FGMRES arrays in the caller's solve workspace.
+SolveWs solve_ws(lsh_factor_s& F, int nrhs, int maxit, void* ws, size_t bytes, mem::Arena& a) {
+  const long N = (long)F.plan->n * F.plan->n;
+  const int G = std::min(nrhs, SOLVE_GROUP);
+  check_ws(ws, bytes, SolveWs::bytes(N, G, maxit), "solve");
+  a.attach(ws, bytes, "solve");
+  return SolveWs::carve([&](size_t b) { return a.take(b); }, N, G, maxit);
+}
+}  // namespace
+
+extern "C" {
+
 int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u, const lsh_solve_opts* opts,
-              lsh_info* info, void* stream) {
+              lsh_info* info, void* ws, size_t ws_bytes, void* stream) {
   API_BEGIN
   LSH_REQUIRE(F && u_inc && sigma && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
   lsh_solve_opts o{1e-10, 100, 1};
@@ -2310,8 +2772,9 @@ int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u,
   lsh_plan_s& P = *F->plan;
   const long N = (long)P.n * P.n;
   const int G = std::min(nrhs, SOLVE_GROUP);
-  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * G * N) F->fvec.alloc(sizeof(z64) * G * N);
-  z64* f = F->fvec.as<z64>();
+  mem::Arena arena;
+  SolveWs W = solve_ws(*F, nrhs, o.maxit, ws, ws_bytes, arena);
+  z64* f = W.f;
   int allconv = 1;
   double worst = 0;
   if (info) std::memset(info, 0, sizeof(lsh_info));
@@ -2320,7 +2783,7 @@ int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u,
                        P.kappa * P.kappa, N);
     LSH_LAUNCH_CHECK();
     int conv = 0;
-    fgmres_one(*F, f, static_cast<z64*>(sigma), o, info, worst, conv, s);
+    fgmres_one(*F, W, f, static_cast<z64*>(sigma), o, info, worst, conv, s);
     allconv = conv;
   } else {
     for (int r0 = 0; r0 < nrhs; r0 += G) {
@@ -2330,7 +2793,7 @@ int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u,
                            static_cast<const z64*>(u_inc) + (r0 + r) * N, F->b.as<double>(), P.kappa * P.kappa, N);
         LSH_LAUNCH_CHECK();
       }
-      fgmres_multi(*F, f, static_cast<z64*>(sigma) + r0 * N, nr, o, info, worst, allconv, s);
+      fgmres_multi(*F, W, f, static_cast<z64*>(sigma) + r0 * N, nr, o, info, worst, allconv, s);
     }
   }
   if (info) info->true_residual = worst;
@@ -2340,7 +2803,7 @@ int lsh_solve(lsh_factor_t F, const void* u_inc, int nrhs, void* sigma, void* u,
 }
 
 int lsh_solve_adjoint(lsh_factor_t F, const void* g, int nrhs, void* lambda, const lsh_solve_opts* opts,
-                      lsh_info* info, void* stream) {
+                      lsh_info* info, void* ws, size_t ws_bytes, void* stream) {
   API_BEGIN
   LSH_REQUIRE(F && g && lambda && nrhs >= 1, LSH_ERR_INVALID_ARG, "bad argument");
   lsh_solve_opts o{1e-10, 100, 1};
@@ -2350,8 +2813,9 @@ int lsh_solve_adjoint(lsh_factor_t F, const void* g, int nrhs, void* lambda, con
   lsh_plan_s& P = *F->plan;
   const long N = (long)P.n * P.n;
   const int G = std::min(nrhs, SOLVE_GROUP);
-  if (!F->fvec.p || F->fvec.bytes < sizeof(z64) * G * N) F->fvec.alloc(sizeof(z64) * G * N);
-  z64* f = F->fvec.as<z64>();
+  mem::Arena arena;
+  SolveWs W = solve_ws(*F, nrhs, o.maxit, ws, ws_bytes, arena);
+  z64* f = W.f;
   int allconv = 1;
   double worst = 0;
   if (info) std::memset(info, 0, sizeof(lsh_info));
@@ -2361,14 +2825,14 @@ int lsh_solve_adjoint(lsh_factor_t F, const void* g, int nrhs, void* lambda, con
   if (nrhs == 1) {
     conj_copy(s, f, gg, N);
     int conv = 0;
-    fgmres_one(*F, f, lam, o, info, worst, conv, s, true);
+    fgmres_one(*F, W, f, lam, o, info, worst, conv, s, true);
     conj_copy(s, lam, lam, N);
     allconv = conv;
   } else {
     for (int r0 = 0; r0 < nrhs; r0 += G) {
       const int nr = std::min(G, nrhs - r0);
       conj_copy(s, f, gg + r0 * N, (long)nr * N);
-      fgmres_multi(*F, f, lam + r0 * N, nr, o, info, worst, allconv, s, true);
+      fgmres_multi(*F, W, f, lam + r0 * N, nr, o, info, worst, allconv, s, true);
       conj_copy(s, lam + r0 * N, lam + r0 * N, (long)nr * N);
     }
   }
@@ -2438,19 +2902,160 @@ int lsh_dev_gemm_split(int prec, int M, int N, int K, const double* alpha, const
   API_END
 }
 
-int lsh_dev_inverse(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* stream) {
+// ---- GEMM autotuner
+int lsh_gemm_variants(int prec, int* count, char* names, int cap) {
   API_BEGIN
-  LSH_REQUIRE(A && c >= 1 && batch >= 1, LSH_ERR_INVALID_ARG, "bad inverse argument");
-  hipStream_t s = (hipStream_t)stream;
-  if (prec == LSH_FP64) {
-    DevBuf ws(inverse_ws_bytes<double>(c, batch));
-    inverse<double>(s, (z64*)A, c, lda, sA, batch, ws.p, info);
-    LSH_HIP(hipStreamSynchronize(s));
-  } else {
-    DevBuf ws(inverse_ws_bytes<float>(c, batch));
-    inverse<float>(s, (c32*)A, c, lda, sA, batch, ws.p, info);
-    LSH_HIP(hipStreamSynchronize(s));
+  LSH_REQUIRE(count && (prec == LSH_FP32 || prec == LSH_FP64), LSH_ERR_INVALID_ARG, "bad argument");
+  const int p = prec == LSH_FP32 ? 1 : 0;
+  *count = gemm_variant_count(p);
+  if (names && cap > 0) {
+    std::string t;
+    for (int v = 0; v < *count; ++v) t += (v ? ";" : "") + std::string(gemm_variant_name(p, v));
+    std::strncpy(names, t.c_str(), cap - 1);
+    names[cap - 1] = 0;
   }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_force_variant(int variant) {
+  API_BEGIN
+  gemm_force_variant(variant);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_tune_workspace(int prec, int M, int N, int K, int batch, size_t* bytes) {
+  API_BEGIN
+  LSH_REQUIRE(bytes && M >= 1 && N >= 1 && K >= 1 && batch >= 1, LSH_ERR_INVALID_ARG, "bad argument");
+  const size_t e = prec == LSH_FP32 ? sizeof(c32) : sizeof(z64);
+  mem::Sizer z;
+  z.add(e * (size_t)batch * M * K);
+  z.add(e * (size_t)K * N);
+  z.add(e * (size_t)batch * M * N);
+  *bytes = z.total;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_tune(int prec, int M, int N, int K, int batch, int reps, void* ws, size_t ws_bytes, void* stream,
+                  int* best, double* ms) {
+  API_BEGIN
+  LSH_REQUIRE(M >= 1 && N >= 1 && K >= 1 && batch >= 1 && reps >= 1 && (prec == LSH_FP32 || prec == LSH_FP64),
+              LSH_ERR_INVALID_ARG, "bad argument");
+  size_t need = 0;
+  LSH_REQUIRE(lsh_gemm_tune_workspace(prec, M, N, K, batch, &need) == LSH_OK, LSH_ERR_INVALID_ARG, "bad shape");
+  check_ws(ws, ws_bytes, need, "tune");
+  hipStream_t s = (hipStream_t)stream;
+  mem::Arena a;
+  a.attach(ws, ws_bytes, "tune");
+  const size_t e = prec == LSH_FP32 ? sizeof(c32) : sizeof(z64);
+  void* A = a.take(e * (size_t)batch * M * K);
+  void* B = a.take(e * (size_t)K * N);
+  void* C = a.take(e * (size_t)batch * M * N);
+  fill_zero(s, A, e * (size_t)batch * M * K);
+  fill_zero(s, B, e * (size_t)K * N);
+  const int p = prec == LSH_FP32 ? 1 : 0, nv = gemm_variant_count(p);
+  hipEvent_t e0, e1;
+  LSH_HIP(hipEventCreate(&e0));
+  LSH_HIP(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } evs{e0, e1};
+  auto run = [&] {
+    if (p == 1)
+      cgemm<float>(s, M, N, K, mk(1.0f, 0.0f), (const c32*)A, K, (long)M * K, OP_N, (const c32*)B, N, 0, OP_N,
+                   mk(0.0f, 0.0f), nullptr, 0, 0, (c32*)C, N, (long)M * N, batch);
+    else
+      cgemm<double>(s, M, N, K, mk(1.0, 0.0), (const z64*)A, K, (long)M * K, OP_N, (const z64*)B, N, 0, OP_N,
+                    mk(0.0, 0.0), nullptr, 0, 0, (z64*)C, N, (long)M * N, batch);
+  };
+  int bv = 0;
+  double bt = 1e300;
+  struct Unforce {
+    ~Unforce() { gemm_force_variant(-1); }
+  } unforce;
+  for (int v = 0; v < nv; ++v) {
+    gemm_force_variant(v);
+    run();  // warm
+    LSH_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) run();
+    LSH_HIP(hipEventRecord(e1, s));
+    LSH_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    LSH_HIP(hipEventElapsedTime(&t, e0, e1));
+    const double tv = (double)t / reps;
+    if (ms) ms[v] = tv;
+    if (tv < bt) { bt = tv; bv = v; }
+  }
+  gemm_force_variant(-1);
+  gemm_tune_set(p, M, N, K, batch, bv);
+  if (best) *best = bv;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_table_save(const char* path) {
+  API_BEGIN
+  LSH_REQUIRE(path, LSH_ERR_INVALID_ARG, "null path");
+  gemm_table_save(path);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_table_load(const char* path, int* entries) {
+  API_BEGIN
+  LSH_REQUIRE(path, LSH_ERR_INVALID_ARG, "null path");
+  const int n = gemm_table_load(path);
+  if (entries) *entries = n;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_table_clear(void) {
+  API_BEGIN
+  gemm_table_clear();
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_record(int on) {
+  API_BEGIN
+  gemm_record(on != 0);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_gemm_recorded(int* count, int* shapes, int cap) {
+  API_BEGIN
+  LSH_REQUIRE(count, LSH_ERR_INVALID_ARG, "null count");
+  const auto v = gemm_recorded();
+  *count = (int)v.size();
+  if (shapes)
+    for (int i = 0; i < (int)v.size() && i < cap; ++i)
+      for (int q = 0; q < 5; ++q) shapes[5 * i + q] = v[i][q];
+  return LSH_OK;
+  API_END
+}
+
+int lsh_dev_inverse_workspace(int prec, int c, int batch, size_t* bytes) {
+  API_BEGIN
+  LSH_REQUIRE(bytes && c >= 1 && batch >= 1, LSH_ERR_INVALID_ARG, "bad inverse argument");
+  *bytes = prec == LSH_FP64 ? inverse_ws_bytes<double>(c, batch) : inverse_ws_bytes<float>(c, batch);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_dev_inverse(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* ws, size_t ws_bytes,
+                    void* stream) {
+  API_BEGIN
+  LSH_REQUIRE(A && c >= 1 && batch >= 1 && lda >= c, LSH_ERR_INVALID_ARG, "bad inverse argument");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = prec == LSH_FP64 ? inverse_ws_bytes<double>(c, batch) : inverse_ws_bytes<float>(c, batch);
+  check_ws(ws, ws_bytes, need, "inverse");
+  if (prec == LSH_FP64) inverse<double>(s, (z64*)A, c, lda, sA, batch, ws, info);
+  else inverse<float>(s, (c32*)A, c, lda, sA, batch, ws, info);
   return LSH_OK;
   API_END
 }

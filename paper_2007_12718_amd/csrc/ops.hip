@@ -39,7 +39,8 @@ __global__ void k_table_add(z64* T, int D, const int* dxy, const z64* w, int cnt
   T[(long)dy * (D + 1) + dx] = T[(long)dy * (D + 1) + dx] + w[k];
 }
 
-void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector<StencilEntry>& stencil) {
+void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector<StencilEntry>& stencil,
+                       mem::Arena& scr) {
   std::vector<int> dxy;
   std::vector<z64> wv;
   for (auto& e : stencil) {  // one representative per offset (|dx|, |dy|): the stencil is symmetric
@@ -49,11 +50,12 @@ void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector
     wv.push_back(mk(h * h * e.re, h * h * e.im));
   }
   if (wv.empty()) return;
-  AsyncBuf ddxy(sizeof(int) * dxy.size(), s), dw(sizeof(z64) * wv.size(), s);
-  LSH_HIP(hipMemcpyAsync(ddxy.p, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
-  LSH_HIP(hipMemcpyAsync(dw.p, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_table_add, dim3(ceil_div((int)wv.size(), 64)), dim3(64), 0, s, T, D, ddxy.as<int>(),
-                     dw.as<z64>(), (int)wv.size());
+  int* ddxy = static_cast<int*>(scr.take(sizeof(int) * dxy.size()));
+  z64* dw = static_cast<z64*>(scr.take(sizeof(z64) * wv.size()));
+  LSH_HIP(hipMemcpyAsync(ddxy, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
+  LSH_HIP(hipMemcpyAsync(dw, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_table_add, dim3(ceil_div((int)wv.size(), 64)), dim3(64), 0, s, T, D, ddxy, dw,
+                     (int)wv.size());
   LSH_LAUNCH_CHECK();
   LSH_HIP(hipStreamSynchronize(s));  // the host staging vectors die here
 }
@@ -198,8 +200,21 @@ __global__ void k_scale_c(z64* a, long n, double s) {
   if (i < n) a[i] = s * a[i];
 }
 
+size_t ConvOperator::bytes(int n) {
+  int M = 1;
+  while (M < 2 * n) M <<= 1;
+  mem::Sizer z;
+  z.add_n<z64>(M / 2);             // twiddles
+  z.add_n<z64>((size_t)M * M);     // khatT
+  z.add_n<z64>((size_t)n * M);     // w1
+  z.add_n<z64>((size_t)M * M);     // w2
+  return z.total;
+}
+
+size_t ConvOperator::scratch_bytes() { return 2 * mem::round_up(sizeof(z64) * 64); }
+
 void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z64* table, int D,
-                        const std::vector<StencilEntry>& stencil) {
+                        const std::vector<StencilEntry>& stencil, mem::Arena& scr) {
   n = n_;
   kappa = kappa_;
   M = 1;
@@ -219,10 +234,11 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
     dxy.push_back(e.dy);
     wv.push_back(mk(h * h * e.re, h * h * e.im));
   }
-  AsyncBuf ddxy(sizeof(int) * dxy.size(), s), dw(sizeof(z64) * wv.size(), s);
-  LSH_HIP(hipMemcpyAsync(ddxy.p, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
-  LSH_HIP(hipMemcpyAsync(dw.p, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_add_stencil, dim3(1), dim3(64), 0, s, C, M, ddxy.as<int>(), dw.as<z64>(), (int)wv.size());
+  int* ddxy = static_cast<int*>(scr.take(sizeof(int) * dxy.size()));
+  z64* dw = static_cast<z64*>(scr.take(sizeof(z64) * wv.size()));
+  LSH_HIP(hipMemcpyAsync(ddxy, dxy.data(), sizeof(int) * dxy.size(), hipMemcpyHostToDevice, s));
+  LSH_HIP(hipMemcpyAsync(dw, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_add_stencil, dim3(1), dim3(64), 0, s, C, M, ddxy, dw, (int)wv.size());
   LSH_LAUNCH_CHECK();
   // full 2-D transform, kept transposed: khatT[k1][k2]
   z64* Kt = khatT.as<z64>();

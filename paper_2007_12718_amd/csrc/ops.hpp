@@ -27,8 +27,12 @@ struct ConvOperator {
   FFTPlan fft;
   DevBuf khatT;     // transposed spectrum of the kernel, scaled by 1/M^2
   DevBuf w1, w2;    // n x M and M x n work arrays
+  // (device memory from the bound arena; scr: staging of the stencil)
   void init(hipStream_t s, int n_, double h, double kappa_, const z64* table, int D,
-            const std::vector<StencilEntry>& stencil);
+            const std::vector<StencilEntry>& stencil, mem::Arena& scr);
+  // bytes that init takes from the bound arena, and from scr
+  static size_t bytes(int n);
+  static size_t scratch_bytes();
   // b == nullptr: y = K * x ; otherwise y = x + kappa^2 b (K * x), or with
   // transpose the transposed operator y = x + K * (kappa^2 b x)
   void apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs, bool transpose = false);
@@ -40,7 +44,8 @@ void build_offset_table(hipStream_t s, z64* T, int D, double h, double kappa, do
                         double tau0_im);
 // T[|dy|][|dx|] += h^2 tau for the stencil entries off the origin (the
 // order-p table; the origin value is set by build_offset_table)
-void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector<StencilEntry>& stencil);
+void add_table_stencil(hipStream_t s, z64* T, int D, double h, const std::vector<StencilEntry>& stencil,
+                       mem::Arena& scr);
 
 // ---- FGMRES vector kernels (deterministic fixed-order reductions)
 // out[v] = sum_i conj(V[v][i]) w[i], v < nv (V rows at stride ldv)

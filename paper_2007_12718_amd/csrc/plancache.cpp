@@ -2,8 +2,9 @@
 // universal (b-independent) compression, Sec. 3.2, depend only on the box
 // size, kappa h, the tolerance, the ring width, the matrix order and the
 // pivoting rule, so one plan's levels serve later plans, on other b and on
-// other grids with the same kappa h.  Entries hold host copies of the
-// candidates and pivots and a device copy of U.
+// other grids with the same kappa h.  Entries live in host memory (the
+// library owns no device memory): candidates, pivots and U; a hit copies U
+// into the plan's workspace.
 #include "plancache.hpp"
 
 #include <cstdio>
@@ -26,7 +27,7 @@ struct Entry {
   std::vector<I2> rows;
   std::vector<int> J;
   int m = 0, k = 0;
-  DevBuf U;
+  std::vector<z64> U;  // m x k, row-major
 };
 std::mutex mu;
 std::map<Key, std::shared_ptr<Entry>> entries;
@@ -52,8 +53,8 @@ bool find(const Key& key, const std::vector<I2>& rows, std::vector<int>& J, int&
   k = e->k;
   const size_t bytes = sizeof(z64) * (size_t)e->m * e->k;
   U.alloc(bytes);
-  LSH_HIP(hipMemcpyAsync(U.p, e->U.p, bytes, hipMemcpyDeviceToDevice, s));
-  LSH_HIP(hipStreamSynchronize(s));  // (the entry may be replaced once the lock is gone)
+  LSH_HIP(hipMemcpyAsync(U.p, e->U.data(), bytes, hipMemcpyHostToDevice, s));
+  LSH_HIP(hipStreamSynchronize(s));  // (the entry is held by e until here)
   return true;
 }
 
@@ -66,8 +67,8 @@ void insert(const Key& key, const std::vector<I2>& rows, const std::vector<int>&
   e->k = k;
   const size_t bytes = sizeof(z64) * (size_t)m * k;
   LSH_REQUIRE((int)J.size() == k && U.bytes >= bytes, -1, "plan cache: inconsistent entry");
-  e->U.alloc(bytes);
-  LSH_HIP(hipMemcpyAsync(e->U.p, U.p, bytes, hipMemcpyDeviceToDevice, s));
+  e->U.resize((size_t)m * k);
+  LSH_HIP(hipMemcpyAsync(e->U.data(), U.p, bytes, hipMemcpyDeviceToHost, s));
   LSH_HIP(hipStreamSynchronize(s));
   std::lock_guard<std::mutex> g(mu);
   entries[key] = e;
@@ -84,7 +85,7 @@ void clear() {
 void info(int* n, size_t* bytes) {
   std::lock_guard<std::mutex> g(mu);
   size_t b = 0;
-  for (auto& kv : entries) b += kv.second->U.bytes;
+  for (auto& kv : entries) b += sizeof(z64) * kv.second->U.size();
   if (n) *n = (int)entries.size();
   if (bytes) *bytes = b;
 }
@@ -117,7 +118,6 @@ void save(const char* path) {
   put(fc.f, kMagic, sizeof(kMagic));
   const int64_t n = (int64_t)all.size();
   put(fc.f, &n, sizeof(n));
-  std::vector<z64> h;
   for (auto& kv : all) {
     const Entry& e = *kv.second;
     put(fc.f, &kv.first, sizeof(Key));
@@ -127,9 +127,7 @@ void save(const char* path) {
     put(fc.f, &nr, sizeof(int));
     put(fc.f, e.rows.data(), sizeof(I2) * e.rows.size());
     put(fc.f, e.J.data(), sizeof(int) * e.J.size());
-    h.resize((size_t)e.m * e.k);
-    LSH_HIP(hipMemcpy(h.data(), e.U.p, sizeof(z64) * h.size(), hipMemcpyDeviceToHost));
-    put(fc.f, h.data(), sizeof(z64) * h.size());
+    put(fc.f, e.U.data(), sizeof(z64) * e.U.size());
   }
 }
 
@@ -144,7 +142,6 @@ void load(const char* path) {
   LSH_REQUIRE(n >= 0 && n < (1 << 20), -1, "plan cache: bad entry count");
   int dev = 0;
   LSH_HIP(hipGetDevice(&dev));
-  std::vector<z64> h;
   for (int64_t q = 0; q < n; ++q) {
     Key key;
     get(fc.f, &key, sizeof(Key));
@@ -160,10 +157,8 @@ void load(const char* path) {
     get(fc.f, e->rows.data(), sizeof(I2) * nr);
     get(fc.f, e->J.data(), sizeof(int) * e->k);
     for (int j : e->J) LSH_REQUIRE(j >= 0 && j < e->m, -1, "plan cache: bad pivot index");
-    h.resize((size_t)e->m * e->k);
-    get(fc.f, h.data(), sizeof(z64) * h.size());
-    e->U.alloc(sizeof(z64) * h.size());
-    LSH_HIP(hipMemcpy(e->U.p, h.data(), sizeof(z64) * h.size(), hipMemcpyHostToDevice));
+    e->U.resize((size_t)e->m * e->k);
+    get(fc.f, e->U.data(), sizeof(z64) * e->U.size());
     key.dev = dev;
     std::lock_guard<std::mutex> g(mu);
     entries[key] = e;

@@ -22,9 +22,10 @@ struct Key {
 
 // Looks up key; rows (the points the ID was taken over, identifying the
 // entry) must equal the cached ones.  On a hit, J and k are set and U
-// (m x k, FP64, m as stored) is copied into a new buffer on stream s.
+// (m x k, FP64, m as stored) is copied into a new buffer from the bound
+// arena on stream s (the call synchronises s).
 bool find(const Key& key, const std::vector<I2>& rows, std::vector<int>& J, int& k, DevBuf& U, hipStream_t s);
-// Stores a copy of the m x k matrix U (copied on stream s; the call
+// Stores a host copy of the m x k matrix U (copied on stream s; the call
 // synchronises s).
 void insert(const Key& key, const std::vector<I2>& rows, const std::vector<int>& J, int m, int k, const DevBuf& U,
             hipStream_t s);

@@ -18,20 +18,29 @@ LIB_PATH = os.path.join(HERE, "liblsh.so")
 
 LSH_OK, LSH_NOT_CONVERGED = 0, 1
 (LSH_ERR_INVALID_ARG, LSH_ERR_INPUT_NONFINITE, LSH_ERR_SINGULAR, LSH_ERR_HIP, LSH_ERR_NOMEM,
- LSH_ERR_UNSUPPORTED) = -1, -2, -3, -4, -5, -6
+ LSH_ERR_UNSUPPORTED, LSH_ERR_WORKSPACE_TOO_SMALL) = -1, -2, -3, -4, -5, -6, -7
+LSH_FACTOR_TRANSPOSE = 1
 LSH_FP64, LSH_FP32 = 0, 1
 MAX_ITERS = 200
 MAX_LEVELS = 32
 
 EXPORTED = [
-    "lsh_plan_create", "lsh_plan_destroy", "lsh_plan_ranks", "lsh_plan_level", "lsh_plan_block",
-    "lsh_plan_table", "lsh_factor_create", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
-    "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights", "lsh_last_error",
-    "lsh_dev_gemm", "lsh_dev_gemm_split", "lsh_dev_inverse", "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names",
-    "lsh_eval_points_adjoint", "lsh_grad_b", "lsh_build", "lsh_batch_factor", "lsh_profile_only",
-    "lsh_cache_trim", "lsh_plan_lowrank", "lsh_plan_cache_info", "lsh_plan_cache_clear", "lsh_plan_cache_save",
-    "lsh_plan_cache_load",
+    "lsh_plan_workspace", "lsh_plan_create", "lsh_plan_destroy", "lsh_plan_workspace_used", "lsh_plan_ranks",
+    "lsh_plan_level", "lsh_plan_block", "lsh_plan_table", "lsh_factor_workspace", "lsh_factor_create",
+    "lsh_factor_workspace_used", "lsh_factor_destroy", "lsh_apply_precond", "lsh_apply_operator",
+    "lsh_solve_workspace", "lsh_solve", "lsh_solve_adjoint", "lsh_eval_points", "lsh_correction_weights",
+    "lsh_last_error", "lsh_dev_gemm", "lsh_dev_gemm_split", "lsh_dev_inverse_workspace", "lsh_dev_inverse",
+    "lsh_profile_enable", "lsh_profile_query", "lsh_profile_names", "lsh_eval_points_adjoint", "lsh_grad_b",
+    "lsh_build_workspace", "lsh_build", "lsh_batch_factor_workspace", "lsh_batch_factor", "lsh_profile_only",
+    "lsh_plan_lowrank", "lsh_plan_cache_info", "lsh_plan_cache_clear", "lsh_plan_cache_save",
+    "lsh_plan_cache_load", "lsh_gemm_variants", "lsh_gemm_tune_workspace", "lsh_gemm_tune", "lsh_gemm_table_save",
+    "lsh_gemm_table_load", "lsh_gemm_table_clear", "lsh_gemm_record", "lsh_gemm_recorded",
+    "lsh_gemm_force_variant",
 ]
+
+# tuned GEMM variant choices (written by tune_gemm.py on an MI355X); LSH_GEMM_TABLE overrides the path,
+# LSH_GEMM_TABLE=none loads nothing (the library's model then chooses)
+GEMM_TABLE = os.path.join(HERE, "tune", "gemm_table.txt")
 
 
 class LshDesc(ctypes.Structure):
@@ -73,23 +82,36 @@ def lib():
         import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.lsh_last_error.restype = ctypes.c_char_p
-        L.lsh_plan_create.argtypes = [POINTER(LshDesc), c_void_p, POINTER(c_void_p)]
+        L.lsh_plan_workspace.argtypes = [POINTER(LshDesc), POINTER(ctypes.c_size_t)]
+        L.lsh_plan_create.argtypes = [POINTER(LshDesc), c_void_p, ctypes.c_size_t, c_void_p, POINTER(c_void_p)]
+        L.lsh_plan_workspace_used.argtypes = [c_void_p, POINTER(ctypes.c_size_t), POINTER(ctypes.c_size_t)]
         L.lsh_plan_destroy.argtypes = [c_void_p]
         L.lsh_plan_ranks.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int)]
         L.lsh_plan_level.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int),
                                      POINTER(c_int), c_void_p, c_void_p]
         L.lsh_plan_block.argtypes = [c_void_p, c_int, POINTER(c_int), c_void_p, c_void_p]
         L.lsh_plan_table.argtypes = [c_void_p, POINTER(c_int), c_void_p, c_void_p]
-        L.lsh_factor_create.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]
+        L.lsh_factor_workspace.argtypes = [c_void_p, c_int, POINTER(ctypes.c_size_t)]
+        L.lsh_factor_create.argtypes = [c_void_p, c_void_p, c_int, c_void_p, ctypes.c_size_t, c_void_p,
+                                        POINTER(c_void_p)]
+        L.lsh_factor_workspace_used.argtypes = [c_void_p, POINTER(ctypes.c_size_t), POINTER(ctypes.c_size_t)]
         L.lsh_factor_destroy.argtypes = [c_void_p]
-        L.lsh_build.argtypes = [POINTER(LshDesc), c_void_p, c_void_p, POINTER(c_void_p), POINTER(c_void_p)]
-        L.lsh_batch_factor.argtypes = [c_int, POINTER(c_void_p), POINTER(c_void_p), c_void_p, POINTER(c_void_p)]
+        L.lsh_build_workspace.argtypes = [POINTER(LshDesc), c_int, POINTER(ctypes.c_size_t),
+                                          POINTER(ctypes.c_size_t)]
+        L.lsh_build.argtypes = [POINTER(LshDesc), c_void_p, c_int, c_void_p, ctypes.c_size_t, c_void_p,
+                                ctypes.c_size_t, c_void_p, POINTER(c_void_p), POINTER(c_void_p)]
+        L.lsh_batch_factor_workspace.argtypes = [c_int, POINTER(c_void_p), c_int, POINTER(ctypes.c_size_t),
+                                                 POINTER(ctypes.c_size_t)]
+        L.lsh_batch_factor.argtypes = [c_int, POINTER(c_void_p), POINTER(c_void_p), c_int, POINTER(c_void_p),
+                                       POINTER(ctypes.c_size_t), c_void_p, ctypes.c_size_t, c_void_p,
+                                       POINTER(c_void_p)]
         L.lsh_apply_precond.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p]
         L.lsh_apply_operator.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+        L.lsh_solve_workspace.argtypes = [c_void_p, c_int, c_int, POINTER(ctypes.c_size_t)]
         L.lsh_solve.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p, POINTER(LshSolveOpts),
-                                POINTER(LshInfo), c_void_p]
+                                POINTER(LshInfo), c_void_p, ctypes.c_size_t, c_void_p]
         L.lsh_solve_adjoint.argtypes = [c_void_p, c_void_p, c_int, c_void_p, POINTER(LshSolveOpts),
-                                        POINTER(LshInfo), c_void_p]
+                                        POINTER(LshInfo), c_void_p, ctypes.c_size_t, c_void_p]
         L.lsh_eval_points.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p]
         L.lsh_correction_weights.argtypes = [c_int, c_double, POINTER(c_int), POINTER(c_int), POINTER(c_double)]
         L.lsh_dev_gemm.argtypes = [c_int, c_int, c_int, c_int, POINTER(c_double), c_void_p, c_long, c_long, c_int,
@@ -98,20 +120,36 @@ def lib():
         L.lsh_dev_gemm_split.argtypes = [c_int, c_int, c_int, c_int, POINTER(c_double), c_void_p, c_long, c_long,
                                          c_int, c_void_p, c_long, c_long, c_int, POINTER(c_double), c_void_p, c_long,
                                          c_long, c_void_p, c_long, c_long, c_int, c_void_p, ctypes.c_size_t, c_void_p]
-        L.lsh_dev_inverse.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p]
+        L.lsh_dev_inverse_workspace.argtypes = [c_int, c_int, c_int, POINTER(ctypes.c_size_t)]
+        L.lsh_dev_inverse.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p,
+                                      ctypes.c_size_t, c_void_p]
         L.lsh_eval_points_adjoint.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p]
         L.lsh_grad_b.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]
         L.lsh_profile_enable.argtypes = [c_int]
         L.lsh_profile_query.argtypes = [ctypes.c_char_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]
         L.lsh_profile_names.argtypes = [ctypes.c_char_p, c_int]
         L.lsh_profile_only.argtypes = [ctypes.c_char_p]
-        L.lsh_cache_trim.argtypes = [POINTER(ctypes.c_size_t)]
         L.lsh_plan_lowrank.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_int), c_void_p, c_void_p,
                                        c_void_p]
         L.lsh_plan_cache_info.argtypes = [POINTER(c_int), POINTER(ctypes.c_size_t)]
         L.lsh_plan_cache_clear.argtypes = []
         L.lsh_plan_cache_save.argtypes = [ctypes.c_char_p]
         L.lsh_plan_cache_load.argtypes = [ctypes.c_char_p]
+        L.lsh_gemm_variants.argtypes = [c_int, POINTER(c_int), ctypes.c_char_p, c_int]
+        L.lsh_gemm_tune_workspace.argtypes = [c_int, c_int, c_int, c_int, c_int, POINTER(ctypes.c_size_t)]
+        L.lsh_gemm_tune.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, ctypes.c_size_t, c_void_p,
+                                    POINTER(c_int), POINTER(c_double)]
+        L.lsh_gemm_table_save.argtypes = [ctypes.c_char_p]
+        L.lsh_gemm_table_load.argtypes = [ctypes.c_char_p, POINTER(c_int)]
+        L.lsh_gemm_table_clear.argtypes = []
+        L.lsh_gemm_record.argtypes = [c_int]
+        L.lsh_gemm_recorded.argtypes = [POINTER(c_int), POINTER(c_int), c_int]
+        L.lsh_gemm_force_variant.argtypes = [c_int]
+        table = os.environ.get("LSH_GEMM_TABLE", GEMM_TABLE)
+        if table != "none" and os.path.exists(table):
+            n = c_int(0)
+            if L.lsh_gemm_table_load(table.encode(), ctypes.byref(n)) != LSH_OK:
+                raise RuntimeError(f"cannot load the GEMM table {table}: {L.lsh_last_error().decode()}")
         _lib = L
     return _lib
 
@@ -140,6 +178,16 @@ def _ptr(t, dtype=None, numel=None):
     return c_void_p(t.data_ptr())
 
 
+def workspace(nbytes):
+    """A caller-owned device workspace of nbytes (torch's allocator aligns it to 512 bytes)."""
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+def _size():
+    return ctypes.c_size_t(0)
+
+
 def lsh_correction_weights(order: int, kh: float):
     """Host call: stencil offsets (count, 2) and tau (count,) complex."""
     cnt = c_int(0)
@@ -156,7 +204,7 @@ class Plan:
     """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
 
     def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
-                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, _create=True):
+                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, ws=None, _create=True):
         self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
                             op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
                             hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64, merge=MERGE[merge],
@@ -165,13 +213,25 @@ class Plan:
         self.h = self.desc.h
         self.kappa = kappa
         self.handle = c_void_p()
+        self.ws = None  # the plan's device workspace (caller-owned; lives as long as the plan)
         if _create:
-            _check(lib().lsh_plan_create(ctypes.byref(self.desc), _stream(), ctypes.byref(self.handle)))
+            nb = _size()
+            _check(lib().lsh_plan_workspace(ctypes.byref(self.desc), ctypes.byref(nb)))
+            self.ws = workspace(nb.value) if ws is None else ws
+            _check(lib().lsh_plan_create(ctypes.byref(self.desc), _ptr(self.ws), self.ws.numel(), _stream(),
+                                         ctypes.byref(self.handle)))
+
+    def workspace_used(self):
+        """(bytes of the workspace used at most, workspace size)."""
+        u, z = _size(), _size()
+        _check(lib().lsh_plan_workspace_used(self.handle, ctypes.byref(u), ctypes.byref(z)))
+        return u.value, z.value
 
     def close(self):
         if self.handle:
             lib().lsh_plan_destroy(self.handle)
             self.handle = c_void_p()
+        self.ws = None
 
     def __del__(self):
         try:
@@ -279,22 +339,45 @@ class Plan:
 
 
 class Factor:
-    """lsh_factor_create: Algorithm 1 for the potential b (float64, (n, n), device)."""
+    """lsh_factor_create: Algorithm 1 for the potential b (float64, (n, n), device).
+    transpose=True reserves room for M^T (apply_precond(transpose=True), solve_adjoint)."""
 
-    def __init__(self, plan: Plan, b, _handle=None):
+    def __init__(self, plan: Plan, b, transpose=False, ws=None, _handle=None, _ws=None):
         import torch
         self.plan = plan
         self.handle = c_void_p()
+        self.ws = _ws  # the factor's device workspace (caller-owned)
         if _handle is not None:
             self.handle = _handle
             return
         b = b.reshape(plan.n, plan.n).contiguous()
-        _check(lib().lsh_factor_create(plan.handle, _ptr(b, torch.float64), _stream(), ctypes.byref(self.handle)))
+        flags = LSH_FACTOR_TRANSPOSE if transpose else 0
+        nb = _size()
+        _check(lib().lsh_factor_workspace(plan.handle, flags, ctypes.byref(nb)))
+        self.ws = workspace(nb.value) if ws is None else ws
+        _check(lib().lsh_factor_create(plan.handle, _ptr(b, torch.float64), flags, _ptr(self.ws), self.ws.numel(),
+                                       _stream(), ctypes.byref(self.handle)))
+
+    def workspace_used(self):
+        u, z = _size(), _size()
+        _check(lib().lsh_factor_workspace_used(self.handle, ctypes.byref(u), ctypes.byref(z)))
+        return u.value, z.value
+
+    def solve_workspace_bytes(self, nrhs, maxit):
+        nb = _size()
+        _check(lib().lsh_solve_workspace(self.handle, nrhs, maxit, ctypes.byref(nb)))
+        return nb.value
+
+    def _solve_ws(self, nrhs, maxit, ws=None):
+        if ws is None:
+            ws = workspace(self.solve_workspace_bytes(nrhs, maxit))
+        return ws, ws.numel()
 
     def close(self):
         if self.handle:
             lib().lsh_factor_destroy(self.handle)
             self.handle = c_void_p()
+        self.ws = None
 
     def __del__(self):
         try:
@@ -311,8 +394,9 @@ class Factor:
                                        _ptr(y, torch.complex128), x.shape[0], _stream()))
         return y
 
-    def solve(self, u_inc, tol=1e-10, maxit=100, precondition=True, want_u=True):
-        """sigma, u, info for incident fields u_inc (nrhs, n, n) complex128."""
+    def solve(self, u_inc, tol=1e-10, maxit=100, precondition=True, want_u=True, ws=None):
+        """sigma, u, info for incident fields u_inc (nrhs, n, n) complex128.
+        ws: a solve workspace (uint8 device tensor) to reuse, else a new one."""
         import torch
         n = self.plan.n
         u_inc = u_inc.reshape(-1, n, n).contiguous()
@@ -320,49 +404,77 @@ class Factor:
         u = torch.empty_like(u_inc) if want_u else None
         opts = LshSolveOpts(tol=tol, maxit=maxit, precondition=int(precondition))
         info = LshInfo()
+        ws, nb = self._solve_ws(u_inc.shape[0], maxit, ws)
         rc = _check(lib().lsh_solve(self.handle, _ptr(u_inc, torch.complex128), u_inc.shape[0], _ptr(sig),
                                     _ptr(u) if u is not None else None, ctypes.byref(opts), ctypes.byref(info),
-                                    _stream()), allow_not_converged=True)
+                                    _ptr(ws), nb, _stream()), allow_not_converged=True)
         return sig, u, info, rc
 
-    def solve_adjoint(self, g, tol=1e-10, maxit=100):
+    def solve_adjoint(self, g, tol=1e-10, maxit=100, ws=None):
         import torch
         n = self.plan.n
         g = g.reshape(-1, n, n).contiguous()
         lam = torch.empty_like(g)
         opts = LshSolveOpts(tol=tol, maxit=maxit, precondition=1)
         info = LshInfo()
+        ws, nb = self._solve_ws(g.shape[0], maxit, ws)
         rc = _check(lib().lsh_solve_adjoint(self.handle, _ptr(g, torch.complex128), g.shape[0], _ptr(lam),
-                                            ctypes.byref(opts), ctypes.byref(info), _stream()),
+                                            ctypes.byref(opts), ctypes.byref(info), _ptr(ws), nb, _stream()),
                     allow_not_converged=True)
         return lam, info, rc
 
 
+def build_workspaces(n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5,
+                     y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, transpose=False):
+    """(plan_ws, factor_ws): device workspaces sized for lsh_build (allocate once, reuse across builds)."""
+    d = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa, op_order=op_order, leaf=leaf,
+                tol=tol, proxy_width=proxy_width, hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64,
+                merge=MERGE[merge], hbs_order=hbs_order, plan_cache=int(bool(plan_cache)))
+    pb, fb = _size(), _size()
+    _check(lib().lsh_build_workspace(ctypes.byref(d), LSH_FACTOR_TRANSPOSE if transpose else 0, ctypes.byref(pb),
+                                     ctypes.byref(fb)))
+    return workspace(pb.value), workspace(fb.value)
+
+
 def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5,
-          merge="auto", hbs_order=4, plan_cache=False):
-    """lsh_build: plan and factor pipelined by level; returns (Plan, Factor)."""
+          merge="auto", hbs_order=4, plan_cache=False, transpose=False, workspaces=None):
+    """lsh_build: plan and factor pipelined by level; returns (Plan, Factor).
+    workspaces: (plan_ws, factor_ws) from build_workspaces, reused (else new ones)."""
     import torch
     P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge=merge, hbs_order=hbs_order,
              plan_cache=plan_cache, _create=False)
+    if workspaces is None:
+        workspaces = build_workspaces(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge,
+                                      hbs_order, plan_cache, transpose)
+    pw, fw = workspaces
     fh = c_void_p()
     b = b.reshape(n, n).contiguous()
-    _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), _stream(), ctypes.byref(P.handle),
+    _check(lib().lsh_build(ctypes.byref(P.desc), _ptr(b, torch.float64), LSH_FACTOR_TRANSPOSE if transpose else 0,
+                           _ptr(pw), pw.numel(), _ptr(fw), fw.numel(), _stream(), ctypes.byref(P.handle),
                            ctypes.byref(fh)))
-    return P, Factor(P, None, _handle=fh)
+    P.ws = pw
+    return P, Factor(P, None, _handle=fh, _ws=fw)
 
 
-def batch_factor(plans, bs):
+def batch_factor(plans, bs, transpose=False):
     """lsh_batch_factor: Algorithm 1 for many instances at once (each level's
     products and inverses grouped over all instances); returns one Factor per
     plan."""
     import torch
     n = len(plans)
+    flags = LSH_FACTOR_TRANSPOSE if transpose else 0
     bs = [b.reshape(p.n, p.n).contiguous() for p, b in zip(plans, bs)]
     ph = (c_void_p * n)(*[p.handle.value for p in plans])
     bp = (c_void_p * n)(*[_ptr(b, torch.float64).value for b in bs])
+    fb = (ctypes.c_size_t * n)()
+    sb = _size()
+    _check(lib().lsh_batch_factor_workspace(n, ph, flags, fb, ctypes.byref(sb)))
+    wss = [workspace(fb[i]) for i in range(n)]
+    shared = workspace(sb.value)
+    wp = (c_void_p * n)(*[w.data_ptr() for w in wss])
     fh = (c_void_p * n)()
-    _check(lib().lsh_batch_factor(n, ph, bp, _stream(), fh))
-    return [Factor(p, None, _handle=c_void_p(fh[i])) for i, p in enumerate(plans)]
+    _check(lib().lsh_batch_factor(n, ph, bp, flags, wp, fb, _ptr(shared), sb.value, _stream(), fh))
+    return [Factor(p, None, _handle=c_void_p(fh[i]), _ws=wss[i]) for i, p in enumerate(plans)]
 
 
 def dev_gemm(A, B, opA=0, opB=0, alpha=1.0, beta=0.0, D=None, out=None, ws=None):
@@ -394,8 +506,62 @@ def dev_inverse(A):
     prec = LSH_FP64 if A.dtype == torch.complex128 else LSH_FP32
     b, c, _ = A.shape
     info = torch.zeros(b, dtype=torch.int32, device=A.device)
-    _check(lib().lsh_dev_inverse(prec, _ptr(A), c, c, c * c, b, _ptr(info), _stream()))
+    nb = ctypes.c_size_t(0)
+    _check(lib().lsh_dev_inverse_workspace(prec, c, b, ctypes.byref(nb)))
+    ws = workspace(nb.value)
+    _check(lib().lsh_dev_inverse(prec, _ptr(A), c, c, c * c, b, _ptr(info), _ptr(ws), nb.value, _stream()))
     return A, info
+
+
+def gemm_variants(prec="fp32"):
+    n = c_int(0)
+    buf = ctypes.create_string_buffer(1024)
+    _check(lib().lsh_gemm_variants(LSH_FP32 if prec == "fp32" else LSH_FP64, ctypes.byref(n), buf, 1024))
+    return buf.value.decode().split(";")
+
+
+def gemm_tune(prec, M, N, K, batch, reps=5):
+    """Time every GEMM variant on one shape (lsh_gemm_tune); returns (best, ms per variant)."""
+    p = LSH_FP32 if prec == "fp32" else LSH_FP64
+    nb = _size()
+    _check(lib().lsh_gemm_tune_workspace(p, M, N, K, batch, ctypes.byref(nb)))
+    ws = workspace(nb.value)
+    count = len(gemm_variants(prec))
+    ms = (c_double * count)()
+    best = c_int(0)
+    _check(lib().lsh_gemm_tune(p, M, N, K, batch, reps, _ptr(ws), nb.value, _stream(), ctypes.byref(best), ms))
+    return best.value, list(ms)
+
+
+def gemm_force_variant(v=-1):
+    _check(lib().lsh_gemm_force_variant(int(v)))
+
+
+def gemm_record(on=True):
+    _check(lib().lsh_gemm_record(int(on)))
+
+
+def gemm_recorded():
+    """[(prec, M, N, K, batch)] of the products since gemm_record(True) (prec 1 = FP32, 0 = FP64)."""
+    n = c_int(0)
+    _check(lib().lsh_gemm_recorded(ctypes.byref(n), None, 0))
+    buf = (c_int * (5 * max(n.value, 1)))()
+    _check(lib().lsh_gemm_recorded(ctypes.byref(n), buf, n.value))
+    return [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
+
+
+def gemm_table_save(path):
+    _check(lib().lsh_gemm_table_save(str(path).encode()))
+
+
+def gemm_table_load(path):
+    n = c_int(0)
+    _check(lib().lsh_gemm_table_load(str(path).encode(), ctypes.byref(n)))
+    return n.value
+
+
+def gemm_table_clear():
+    _check(lib().lsh_gemm_table_clear())
 
 
 def lsh_profile_enable(on=True):
@@ -408,7 +574,7 @@ def lsh_profile_only(prefix=None):
 
 
 def plan_cache_info():
-    """(entries, device bytes) of the process-wide plan cache."""
+    """(entries, host bytes) of the process-wide plan cache."""
     n, b = c_int(0), ctypes.c_size_t(0)
     _check(lib().lsh_plan_cache_info(ctypes.byref(n), ctypes.byref(b)))
     return n.value, b.value
@@ -424,13 +590,6 @@ def plan_cache_save(path):
 
 def plan_cache_load(path):
     _check(lib().lsh_plan_cache_load(str(path).encode()))
-
-
-def cache_trim():
-    """Free the device buffers cached by destroyed plans/factors; returns the bytes freed."""
-    n = ctypes.c_size_t(0)
-    _check(lib().lsh_cache_trim(ctypes.byref(n)))
-    return n.value
 
 
 def lsh_profile_query(name):
@@ -464,7 +623,7 @@ def _autograd_function():
     class ReceiverField(torch.autograd.Function):
         @staticmethod
         def forward(ctx, b, u_inc, xy, plan, tol, maxit):
-            F = Factor(plan, b.detach())
+            F = Factor(plan, b.detach(), transpose=True)
             sig, u, info, rc = F.solve(u_inc.detach(), tol=tol, maxit=maxit)
             if rc != LSH_OK:
                 raise LshError(rc, "forward solve did not converge")

@@ -45,3 +45,44 @@ def test_bad_arguments_are_reported_not_raised():
     with pytest.raises(lsh.LshError) as e:
         lsh.lsh_correction_weights(5, 0.3)
     assert e.value.code == -1
+
+
+def test_library_sources_allocate_no_device_memory():
+    """Every device buffer comes from a caller's workspace: no allocation or
+    free call of the HIP runtime appears in the library's sources."""
+    csrc = os.path.join(ROOT, "paper_2007_12718_amd", "csrc")
+    pat = re.compile(r"\bhip(Malloc\w*|Free\w*|ExtMalloc\w*|MallocAsync|HostMalloc)\s*\(")
+    hits = []
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            for i, line in enumerate(open(os.path.join(csrc, f)), 1):
+                if pat.search(line):
+                    hits.append(f"{f}:{i}: {line.strip()}")
+    assert not hits, hits
+
+
+def _desc(lsh, n, prec="fp32", merge="auto", tol=1e-4):
+    return lsh.LshDesc(n=n, h=1.0 / n, x0=-0.5, y0=-0.5, kappa=2 * np.pi * n / 10.24, op_order=10, leaf=8,
+                       tol=tol, proxy_width=2, hbs_prec=lsh.LSH_FP32 if prec == "fp32" else lsh.LSH_FP64,
+                       merge=lsh.MERGE[merge], hbs_order=4, plan_cache=0)
+
+
+def test_workspace_queries_are_host_only_and_consistent():
+    import ctypes
+    from paper_2007_12718_amd import lsh
+    L = lsh.lib()
+    prev = 0
+    for n in (32, 64, 256, 1024):
+        for prec in ("fp32", "fp64"):
+            d = _desc(lsh, n, prec)
+            p, pb, fb, fbt = (ctypes.c_size_t(0) for _ in range(4))
+            assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p)) == 0
+            assert L.lsh_build_workspace(ctypes.byref(d), 0, ctypes.byref(pb), ctypes.byref(fb)) == 0
+            assert L.lsh_build_workspace(ctypes.byref(d), lsh.LSH_FACTOR_TRANSPOSE, ctypes.byref(pb),
+                                         ctypes.byref(fbt)) == 0
+            assert p.value == pb.value and 0 < fb.value < fbt.value
+            assert p.value % 256 == 0 and fb.value % 256 == 0
+        assert p.value > prev
+        prev = p.value
+    d = _desc(lsh, 30)  # n / leaf not a power of two
+    assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p)) == lsh.LSH_ERR_INVALID_ARG

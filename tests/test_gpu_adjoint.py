@@ -24,7 +24,7 @@ def test_transpose_apply_dot_product(prec, tol):
     from paper_2007_12718_amd import lsh
     w = synth.small(32)
     P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
-    F = lsh.Factor(P, cuda(w.b))
+    F = lsh.Factor(P, cuda(w.b), transpose=True)
     rng = np.random.default_rng(1)
     x = rng.standard_normal((1, 32, 32)) + 1j * rng.standard_normal((1, 32, 32))
     y = rng.standard_normal((1, 32, 32)) + 1j * rng.standard_normal((1, 32, 32))
@@ -39,7 +39,7 @@ def test_transpose_apply_full_rank_equals_dense():
     w = synth.small(32)
     A = dense.dense_A(w.b, dense.dense_K(32, w.kappa, 4), w.kappa)
     P = lsh.Plan(32, w.kappa, op_order=4, leaf=8, tol=0.0, proxy_width=2, prec="fp64")
-    F = lsh.Factor(P, cuda(w.b))
+    F = lsh.Factor(P, cuda(w.b), transpose=True)
     rng = np.random.default_rng(2)
     x = rng.standard_normal((2, 32, 32)) + 1j * rng.standard_normal((2, 32, 32))
     q = F.apply_precond(cuda(x), transpose=True).cpu().numpy()
@@ -57,7 +57,7 @@ def test_adjoint_solve_matches_dense(prec):
     g = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
     ref = D.solve_adjoint(g.reshape(2, -1))
     P = lsh.Plan(n, kappa, op_order=10, leaf=6, tol=1e-4, proxy_width=2, prec=prec)
-    F = lsh.Factor(P, cuda(b))
+    F = lsh.Factor(P, cuda(b), transpose=True)
     lam, info, rc = F.solve_adjoint(cuda(g), tol=1e-13, maxit=60)
     assert rc == 0 and info.true_residual < 1e-13 and info.iterations <= 15
     assert rel(lam.cpu().numpy().reshape(2, -1), ref) <= 1e-9

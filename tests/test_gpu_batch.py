@@ -33,10 +33,10 @@ def test_batch_factor_equals_separate_factors():
     plans = [lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=2, prec="fp32")
              for w in ws]
     bs = [cuda(w.b) for w in ws]
-    fb = lsh.batch_factor(plans, bs)
+    fb = lsh.batch_factor(plans, bs, transpose=True)
     rng = np.random.default_rng(7)
     for w, P, F, b in zip(ws, plans, fb, bs):
-        Fs = lsh.Factor(P, b)
+        Fs = lsh.Factor(P, b, transpose=True)
         x = cuda(rng.standard_normal((2, w.n, w.n)) + 1j * rng.standard_normal((2, w.n, w.n)))
         for tr in (False, True):
             y1 = F.apply_precond(x, transpose=tr)

@@ -119,3 +119,42 @@ def test_inverse_reports_singular_blocked(prec):
     ref = np.linalg.inv(A[1])
     tol = 1e-12 if prec == "fp64" else 5e-5
     assert np.abs(Ai[1].cpu().numpy() - ref).max() <= tol * np.abs(ref).max() * 4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("M,N,K,B,opA,opB", [(70, 45, 37, 3, 0, 0), (300, 379, 502, 2, 0, 1), (129, 200, 97, 1, 2, 3),
+                                             (64, 64, 64, 5, 1, 0)])
+def test_gemm_variants_give_identical_bits(prec, M, N, K, B, opA, opB):
+    """Every tile shape and LDS depth adds the same products in the same
+    order: the autotuner's choice changes the time, never the result."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    rng = np.random.default_rng(M + N + K)
+    dt = np.complex128 if prec == "fp64" else np.complex64
+    A = _rand((B, M, K) if opA in (0, 3) else (B, K, M), rng, dt)
+    Bm = _rand((B, K, N) if opB in (0, 3) else (B, N, K), rng, dt)
+    D = _rand((B, M, N), rng, dt)
+    tA, tB, tD = (torch.from_numpy(x).cuda() for x in (A, Bm, D))
+    outs = []
+    try:
+        for v in range(len(lsh.gemm_variants(prec))):
+            lsh.gemm_force_variant(v)
+            outs.append(lsh.dev_gemm(tA, tB, opA, opB, 0.7 - 0.2j, -0.3 + 1.1j, D=tD).cpu())
+    finally:
+        lsh.gemm_force_variant(-1)
+    for v, C in enumerate(outs):
+        assert torch.equal(C, outs[0]), v
+    exact = (0.7 - 0.2j) * (_op(A.astype(np.complex128), opA) @ _op(Bm.astype(np.complex128), opB)) + \
+        (-0.3 + 1.1j) * D
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    assert np.abs(outs[0].numpy() - exact).max() <= tol * np.abs(exact).max()
+
+
+def test_gemm_tuner_records_fastest_variant(tmp_path):
+    from paper_2007_12718_amd import lsh
+    best, ms = lsh.gemm_tune("fp32", 512, 512, 512, 4, reps=2)
+    assert len(ms) == len(lsh.gemm_variants("fp32")) and all(t > 0 for t in ms)
+    assert ms[best] == min(ms)
+    p = tmp_path / "t.txt"
+    lsh.gemm_table_save(p)
+    assert lsh.gemm_table_load(p) >= 1

@@ -69,7 +69,7 @@ def test_lowrank_inverse_matches_oracle(prec):
     tol = 1e-8
     P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=tol, proxy_width=3, prec=prec, merge="lowrank")
     M = hbs.Inverse(hbs.Compression(w.n, w.kappa, 8, tol, 3), w.b, lowrank_tol=tol)
-    F = lsh.Factor(P, cuda(w.b))
+    F = lsh.Factor(P, cuda(w.b), transpose=True)
     rng = np.random.default_rng(0)
     x = rng.standard_normal((2, w.n, w.n)) + 1j * rng.standard_normal((2, w.n, w.n))
     q = F.apply_precond(cuda(x)).cpu().numpy()
@@ -85,7 +85,7 @@ def test_lowrank_transpose_dot_product(prec, tol):
     n, kappa = 64, 2 * np.pi * 6
     b = synth.bumps(n, np.random.default_rng(5))
     P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, merge="lowrank")
-    F = lsh.Factor(P, cuda(b))
+    F = lsh.Factor(P, cuda(b), transpose=True)
     rng = np.random.default_rng(6)
     x = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))
     y = rng.standard_normal((3, n, n)) + 1j * rng.standard_normal((3, n, n))

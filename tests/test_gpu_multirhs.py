@@ -73,7 +73,7 @@ def test_multi_rhs_adjoint_matches_dense(prec):
     g = rng.standard_normal((nr, n, n)) + 1j * rng.standard_normal((nr, n, n))
     ref = dense.DenseSolver(n, kappa, 6, b).solve_adjoint(g.reshape(nr, -1))
     P = lsh.Plan(n, kappa, op_order=6, leaf=6, tol=1e-4, proxy_width=2, prec=prec)
-    F = lsh.Factor(P, cuda(b))
+    F = lsh.Factor(P, cuda(b), transpose=True)
     lam, info, rc = F.solve_adjoint(cuda(g), tol=1e-13, maxit=60)
     assert rc == 0 and info.true_residual < 1e-13
     lam = lam.cpu().numpy().reshape(nr, -1)
@@ -89,7 +89,7 @@ def test_multi_column_apply_equals_columns(prec, tol, transpose):
     kappa = 2 * np.pi * 6
     b = synth.bumps(n, np.random.default_rng(3))
     P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
-    F = lsh.Factor(P, cuda(b))
+    F = lsh.Factor(P, cuda(b), transpose=transpose)
     rng = np.random.default_rng(4)
     x = rng.standard_normal((nr, n, n)) + 1j * rng.standard_normal((nr, n, n))
     y = F.apply_precond(cuda(x), transpose=transpose).cpu().numpy()

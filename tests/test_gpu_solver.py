@@ -221,30 +221,73 @@ def test_pipelined_build_equals_separate_calls(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_cached_buffers_give_identical_factor(prec):
-    """Destroyed handles leave their buffers, with their old contents, in the
-    library's cache; a rebuild from those buffers must compute exactly what
-    a build on freshly allocated memory computed."""
+def test_reused_workspaces_give_identical_factor(prec):
+    """Plans and factors live in caller-owned workspaces with arbitrary
+    contents: builds into workspaces full of 0xff bytes (NaN patterns), or
+    reused after a build for another b, compute bit for bit what a build into
+    zeroed memory computes."""
+    import torch
     from paper_2007_12718_amd import lsh
     n, kappa = 64, 2 * np.pi * 6
+    kw = dict(op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, transpose=True)
     b1 = synth.bumps(n, np.random.default_rng(21))
     b2 = synth.bumps(n, np.random.default_rng(22))
     x = np.random.default_rng(2).standard_normal((1, n, n)) + 0j
-    lsh.cache_trim()
 
-    def run(b):
-        P, F = lsh.build(n, kappa, cuda(b), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
+    def run(b, ws):
+        P, F = lsh.build(n, kappa, cuda(b), workspaces=ws, **kw)
         y = F.apply_precond(cuda(x)).cpu().numpy()
         yt = F.apply_precond(cuda(x), transpose=True).cpu().numpy()
+        s, _, info, rc = F.solve(cuda(synth.plane_wave(n, kappa)[None]), tol=1e-12)
         F.close()
         P.close()
-        return y, yt
+        return y, yt, s.cpu().numpy()
 
-    y1, yt1 = run(b1)
-    run(b2)
-    y3, yt3 = run(b1)
-    assert np.array_equal(y1, y3) and np.array_equal(yt1, yt3)
-    assert lsh.cache_trim() > 0
+    pw, fw = lsh.build_workspaces(n, kappa, **kw)
+    r1 = run(b1, (torch.zeros_like(pw), torch.zeros_like(fw)))
+    pw.fill_(255)
+    fw.fill_(255)
+    run(b2, (pw, fw))
+    r3 = run(b1, (pw, fw))
+    for a, c in zip(r1, r3):
+        assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("prec,merge", [("fp32", "auto"), ("fp64", "auto"), ("fp32", "lowrank"), ("fp64", "schur")])
+def test_workspace_bounds_hold(prec, merge):
+    """The plan and factor use at most the workspace the queries ask for
+    (the factor's exact size given the plan is within lsh_build's bound), and
+    a workspace one granule short is refused with
+    LSH_ERR_WORKSPACE_TOO_SMALL before any device work."""
+    import ctypes
+    from paper_2007_12718_amd import lsh
+    n, kappa = 64, 2 * np.pi * 6
+    b = synth.bumps(n, np.random.default_rng(4))
+    P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, merge=merge)
+    used, size = P.workspace_used()
+    assert 0 < used <= size
+    for tr in (False, True):
+        pb, fb = lsh.build_workspaces(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec,
+                                      merge=merge, transpose=tr)
+        assert size == pb.numel()
+        F = lsh.Factor(P, cuda(b), transpose=tr)
+        u, z = F.workspace_used()
+        assert 0 < u <= z <= fb.numel()
+        if tr:
+            F.apply_precond(cuda(np.ones((1, n, n), complex)), transpose=True)
+            u, z = F.workspace_used()
+            assert u <= z
+        F.close()
+    nb = ctypes.c_size_t(0)
+    rc = lsh.lib().lsh_plan_workspace(ctypes.byref(P.desc), ctypes.byref(nb))
+    assert rc == 0 and nb.value == size
+    small = lsh.workspace(nb.value - 256)
+    h = ctypes.c_void_p()
+    rc = lsh.lib().lsh_plan_create(ctypes.byref(P.desc), ctypes.c_void_p(small.data_ptr()), nb.value - 256,
+                                   lsh._stream(), ctypes.byref(h))
+    assert rc == lsh.LSH_ERR_WORKSPACE_TOO_SMALL and not h.value
+    assert b"workspace" in lsh.lib().lsh_last_error()
+    P.close()
 
 
 @pytest.mark.parametrize("nrhs", [1, 3])
