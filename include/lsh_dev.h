@@ -46,6 +46,16 @@ int lsh_dev_inverse_workspace(int prec, int c, int batch, size_t* bytes /* host 
 int lsh_dev_inverse(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* ws, size_t ws_bytes,
                     void* stream);
 
+/* As lsh_dev_inverse, with the scratch in a static device array of the
+ * library (32 MiB, one per GPU, held until the process ends) instead of a
+ * caller workspace: for callers that cannot allocate device memory (code
+ * under graph capture, allocation-free serving loops).  Allocates nothing.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other streams or host threads) race.  Errors:
+ * LSH_ERR_WORKSPACE_TOO_SMALL when lsh_dev_inverse_workspace(prec, c,
+ * batch) exceeds 32 MiB. */
+int lsh_dev_inverse_static(int prec, void* A, int c, long lda, long sA, int batch, int* info, void* stream);
+
 /* ---- GEMM autotuner (the level merges' products, Algorithm 1)
  * The batched complex GEMM has several variants per precision (workgroup
  * tile shape and LDS K depth); every variant of a precision adds the same

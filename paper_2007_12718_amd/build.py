@@ -8,7 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblsh.so")
-SOURCES = ["blas.hip", "ops.hip", "hbs.hip", "lib.hip", "weights.cpp", "prof.cpp", "mem.cpp", "plancache.cpp"]
+SOURCES = ["blas.hip", "ops.hip", "hbs.hip", "lib.hip", "noalloc.hip", "weights.cpp", "prof.cpp", "mem.cpp",
+           "plancache.cpp"]
 ARCH = os.environ.get("LSH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1728,6 +1728,15 @@ int fail(const lsh::Error& e) {
 
 }  // namespace
 
+namespace lsh {
+// failure reporting for entry points defined in other sources
+int report_failure(const Error& e) { return fail(e); }
+int report_other_failure(const std::exception& e) {
+  g_last_error = e.what();
+  return LSH_ERR_HIP;
+}
+}  // namespace lsh
+
 extern "C" {
 
 const char* lsh_last_error(void) { return g_last_error.c_str(); }
