@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-HBS comparison form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the bumps-256 and batched-64 records that follow the headline")
     ap.add_argument("--cpu-n", type=int, default=0,
                     help="grid side of the oracle's timed run (default: the workload's own n)")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel hipEvent records")
@@ -222,22 +224,23 @@ def cpu_baseline(n_full, n_sample):
             "host_cpu": model, "cpu_count": ncpu}
 
 
-def batched_run(a):
-    """Factor time of many uneven instances: one grouped launch per level step
-    (lsh_batch_factor) against lsh_factor_create per instance; plans are
-    built beforehand (b-independent), solves are per instance either way."""
-    import numpy as np
+def batched_record(count, steps, warmup):
+    """Factor time of many uneven instances: the levels aligned from the
+    leaves, each level step's products and inverses over all instances
+    (lsh_batch_factor; the lower levels as one persistent launch per level),
+    against lsh_factor_create per instance; plans are built beforehand
+    (b-independent), solves are per instance either way."""
     import torch
     import synth
     from paper_2007_12718_amd import lsh
-    ws = synth.batched(a.batched)
+    ws = synth.batched(count)
     plans = [lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=2, prec="fp32")
              for w in ws]
     bs = [torch.from_numpy(w.b).cuda() for w in ws]
     res = {}
     for mode in ("separate", "batched"):
         times = []
-        for k in range(a.warmup + a.steps):
+        for k in range(warmup + steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if mode == "batched":
@@ -246,12 +249,12 @@ def batched_run(a):
                 fs = [lsh.Factor(P, b) for P, b in zip(plans, bs)]
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            if k >= a.warmup:
+            if k >= warmup:
                 times.append(dt)
             for F in fs:
                 F.close()
         res[mode] = sorted(times)[len(times) // 2]
-        print(f"# {mode}: {times}", file=sys.stderr, flush=True)
+        print(f"# batched-{count} {mode}: {times}", file=sys.stderr, flush=True)
     # one solve per instance with the batched factors (FP64 FGMRES to 1e-10)
     fs = lsh.batch_factor(plans, bs)
     its, worst = [], 0.0
@@ -260,18 +263,51 @@ def batched_run(a):
         its.append(info.iterations)
         worst = max(worst, info.true_residual)
         F.close()
+    for P in plans:
+        P.close()
     sizes = {}
     for w in ws:
         sizes[w.n] = sizes.get(w.n, 0) + 1
-    out = {"metric": "batched HBS factor time, uneven instances", "value": res["batched"], "unit": "s",
+    return {"value": res["batched"], "unit": "s", "separate_s": res["separate"],
+            "speedup": res["separate"] / res["batched"],
+            "workload": f"batched-{count}: sides {sizes}, kappa = 2 pi U[5,20], 10 bumps clipped at 0.95, "
+                        f"6th-order operator, FP32 HBS at tol 1e-4; factor time of all instances",
+            "iterations": its, "max_true_residual": worst}
+
+
+def batched_run(a):
+    r = batched_record(a.batched, a.steps, a.warmup)
+    out = {"metric": "batched HBS factor time, uneven instances", "value": r["value"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-           "separate_s": res["separate"], "speedup": res["separate"] / res["batched"],
-           "dtype": "c64 HBS", "data": "synthetic",
-           "config": {"workload": f"batched-{a.batched}: sides {sizes}, kappa = 2 pi U[5,20], 10 bumps clipped at "
-                                  f"0.95, 6th-order operator, FP32 HBS at tol 1e-4", "iterations": its,
-                      "max_true_residual": worst}}
+           "separate_s": r["separate_s"], "speedup": r["speedup"], "dtype": "c64 HBS", "data": "synthetic",
+           "config": {"workload": r["workload"], "iterations": r["iterations"],
+                      "max_true_residual": r["max_true_residual"]}}
     print(json.dumps(out))
     return 0
+
+
+def bumps_record(steps, warmup):
+    """The 256 x 256 ten-bump workload (kappa = 40 pi, 6th-order operator):
+    time to a 1e-10 residual with FP32 and FP64 HBS factors."""
+    import torch
+    import synth
+    from paper_2007_12718_amd import lsh
+    w = synth.bumps20()
+    b_d = torch.from_numpy(w.b).cuda()
+    u_d = torch.from_numpy(w.u_inc).cuda()
+    out = {"workload": f"bumps-256: n=256 (N=65536), kappa=40 pi, 10 bumps clipped at 0.95, HBS 4th order tol 1e-4, "
+                       f"operator order 6, GMRES tol 1e-10"}
+    for prec in ("fp32", "fp64"):
+        rs = []
+        for k in range(warmup + steps):
+            r = run_step(lsh, w, b_d, u_d, prec, torch)
+            if k >= warmup:
+                rs.append(r)
+        med = sorted(rs, key=lambda r: r["total_s"])[len(rs) // 2]
+        out[prec] = {"value": med["total_s"], "unit": "s", "build_s": med["build_s"], "solve_s": med["solve_s"],
+                     "iterations": med["iterations"], "true_residual": med["true_residual"]}
+    out["speedup_fp32_over_fp64"] = out["fp64"]["value"] / out["fp32"]["value"]
+    return out
 
 
 def direct_run(a):
@@ -521,6 +557,9 @@ def main():
         out["roofline"] = prof["roofline"]
         out["kernels"] = prof["kernels"]
         out["kernels_from"] = prof["kernels_from"]
+    if not a.no_extra:  # the other workloads' figures, beside the headline
+        out["bumps256"] = bumps_record(3, 1)
+        out["batched64"] = batched_record(64, 3, 1)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.n, min(a.cpu_n or w.n, w.n))
     print(json.dumps(out))

@@ -86,6 +86,17 @@ int lsh_gemm_record(int on);
 int lsh_gemm_recorded(int* count, int* shapes, int cap);
 int lsh_gemm_force_variant(int variant);
 
+/* Levels of an FP32 factor whose merges use the Woodbury form with a merge
+ * inverse of order r <= 90 (it fits in LDS) and that have at least
+ * min_boxes boxes run as one persistent launch per level (the merge chain
+ * and the scattering matrices of every box, in lsh_factor_create, lsh_build
+ * and, over all instances, lsh_batch_factor); the other levels use separate
+ * launches (the same bits either way).  lsh_fused_levels sets min_boxes
+ * for later factors: 0 never fuses (the default: on MI355X the separate
+ * launches are faster), 1 fuses every such level, -1 restores the
+ * default. */
+int lsh_fused_levels(int min_boxes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1860,6 +1860,137 @@ void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws,
   }
 }
 
+// ---- One persistent launch per level: the Woodbury merge (Algorithm 1 with
+// eq. (blockinv) restored) and the scattering matrices of every box of every
+// instance in the launch.  A fixed grid of workgroups takes boxes from a work
+// counter; a workgroup runs the whole chain of its box (each product as a
+// loop over 64 x 64 output tiles of the FP32 tile routine, the order-r
+// inverse in LDS), so the box's intermediates are made and used on one
+// compute unit, and a level is one launch instead of about a dozen.  Every
+// product and the inverse are the same instructions as in the separate
+// launches, so the factor has the same bits.
+namespace {
+__device__ __forceinline__ void gemm_all_tiles(const GemmP<float>& P, long b) {
+  for (int m0 = 0; m0 < P.M; m0 += 64)
+    for (int n0 = 0; n0 < P.N; n0 += 64) cgemm_x32_tile<1, 1, 32>(P, b, m0, n0);
+  __syncthreads();  // (the outputs are read by other threads of the workgroup next)
+}
+
+__device__ __forceinline__ GemmP<float> gp(int M, int N, int K, float alpha, const c32* A, long lda, long sA, int opA,
+                                           const c32* B, long ldb, long sB, int opB, float beta, const c32* D,
+                                           long ldd, long sD, c32* C, long ldc, long sC, int addI) {
+  GemmP<float> P;
+  P.M = M; P.N = N; P.K = K;
+  P.alpha = mk<float>(alpha, 0); P.beta = mk<float>(beta, 0);
+  P.A = A; P.lda = lda; P.sA = sA; P.opA = opA;
+  P.B = B; P.ldb = ldb; P.sB = sB; P.opB = opB;
+  P.D = D; P.ldd = ldd; P.sD = sD;
+  P.C = C; P.ldc = ldc; P.sC = sC;
+  P.addI = addI; P.skip = nullptr; P.lower = 0;
+  return P;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_merge_level(const MergeLevelDev* G, int ng, long total, int* counter) {
+  __shared__ long s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const long item = s_item;
+    __syncthreads();
+    if (item >= total) break;  // (uniform: every wave of the workgroup leaves)
+    int lo = 0, hi = ng - 1;   // last level entry with item0 <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (G[mid].item0 <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const MergeLevelDev& g = G[lo];
+    const long t = item - g.item0;
+    const int c = g.c, r = g.r, k = g.k;
+    const long cc = (long)c * c, cr = (long)c * r, rr = (long)r * r, r2 = 2L * r, w4 = 4L * rr;
+    const long ck = (long)c * k, rk = (long)r * k;
+    const c32* Lm = g.Pm;           // L (c x r)
+    const c32* Rm = g.Pm + cr;      // R (c x r)
+    const c32* Lt = g.Qm;           // L^T (r x c)
+    const c32* Rt = g.Qm + cr;      // R^T (r x c)
+    c32* Pst = g.Pst + t * 2 * cr;  // [S_a L; S_b R]
+    c32* W = g.W + t * w4;
+    c32* Aw = g.T + t * 3 * rr;
+    c32* Bw = Aw + rr;
+    c32* Cm = Bw + rr;
+    const c32* Sa = g.Sch + 2 * t * cc;
+    // S_a L, S_b R
+    gemm_all_tiles(gp(c, r, c, 1, Sa, c, 0, OP_N, Lm, r, 0, OP_N, 0, nullptr, 0, 0, Pst, r, 0, 0), 0);
+    gemm_all_tiles(gp(c, r, c, 1, Sa + cc, c, 0, OP_N, Rm, r, 0, OP_N, 0, nullptr, 0, 0, Pst + cr, r, 0, 0), 0);
+    // Aw = R^T (S_b R), Bw = L^T (S_a L), C = I - Bw Aw
+    gemm_all_tiles(gp(r, r, c, 1, Rt, c, 0, OP_N, Pst + cr, r, 0, OP_N, 0, nullptr, 0, 0, Aw, r, 0, 0), 0);
+    gemm_all_tiles(gp(r, r, c, 1, Lt, c, 0, OP_N, Pst, r, 0, OP_N, 0, nullptr, 0, 0, Bw, r, 0, 0), 0);
+    gemm_all_tiles(gp(r, r, r, -1, Bw, r, 0, OP_N, Aw, r, 0, OP_N, 0, nullptr, 0, 0, Cm, r, 0, 1), 0);
+    // C^{-1} in LDS
+    inv_small_body<float>(Cm, r, r, g.info + t, g.perm + t * r);
+    __syncthreads();
+    // W' = [[-Aw C, I + Aw C Bw], [C, -C Bw]]
+    for (long e = threadIdx.x; e < rr; e += blockDim.x) W[r * r2 + (e / r) * r2 + (e % r)] = Cm[e];
+    __syncthreads();
+    gemm_all_tiles(gp(r, r, r, -1, Aw, r, 0, OP_N, Cm, r, 0, OP_N, 0, nullptr, 0, 0, W, r2, 0, 0), 0);
+    gemm_all_tiles(gp(r, r, r, -1, W, r2, 0, OP_N, Bw, r, 0, OP_N, 0, nullptr, 0, 0, W + r, r2, 0, 1), 0);
+    gemm_all_tiles(gp(r, r, r, -1, Cm, r, 0, OP_N, Bw, r, 0, OP_N, 0, nullptr, 0, 0, W + r * r2 + r, r2, 0, 0), 0);
+    if (!g.U) continue;  // (the root has no scattering matrix)
+    // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] with a = [S_a U1; S_b U2], then S = U^T X D U
+    c32* a = g.A12 + t * 2 * ck;
+    c32* q = g.Qb + t * 4 * rk;
+    c32* y = q + 2 * rk;
+    const c32* U1 = g.U;
+    const c32* U2 = g.U + ck;
+    gemm_all_tiles(gp(c, k, c, 1, Sa, c, 0, OP_N, U1, k, 0, OP_N, 0, nullptr, 0, 0, a, k, 0, 0), 0);
+    gemm_all_tiles(gp(c, k, c, 1, Sa + cc, c, 0, OP_N, U2, k, 0, OP_N, 0, nullptr, 0, 0, a + ck, k, 0, 0), 0);
+    gemm_all_tiles(gp(r, k, c, 1, Lt, c, 0, OP_N, a, k, 0, OP_N, 0, nullptr, 0, 0, q, k, 0, 0), 0);
+    gemm_all_tiles(gp(r, k, c, 1, Rt, c, 0, OP_N, a + ck, k, 0, OP_N, 0, nullptr, 0, 0, q + rk, k, 0, 0), 0);
+    gemm_all_tiles(gp(2 * r, k, 2 * r, 1, W, r2, 0, OP_N, q, k, 0, OP_N, 0, nullptr, 0, 0, y, k, 0, 0), 0);
+    gemm_all_tiles(gp(c, k, r, -1, Pst, r, 0, OP_N, y, k, 0, OP_N, 1, a, k, 0, a, k, 0, 0), 0);
+    gemm_all_tiles(gp(c, k, r, -1, Pst + cr, r, 0, OP_N, y + rk, k, 0, OP_N, 1, a + ck, k, 0, a + ck, k, 0, 0), 0);
+    c32* S = g.S + t * (long)k * k;
+    gemm_all_tiles(gp(k, k, c, 1, U1, k, 0, OP_T, a, k, 0, OP_N, 0, nullptr, 0, 0, S, k, 0, 0), 0);
+    gemm_all_tiles(gp(k, k, c, 1, U2, k, 0, OP_T, a + ck, k, 0, OP_N, 1, S, k, 0, S, k, 0, 0), 0);
+  }
+}
+
+bool merge_level_fits(int r) { return r >= 1 && small_inv_lds<float>(r) <= 65536; }
+
+size_t merge_level_table_bytes(size_t levels) { return mem::round_up(sizeof(MergeLevelDev) * (levels ? levels : 1)); }
+
+void merge_levels(hipStream_t s, const std::vector<MergeLevelDev>& levels, DevBuf& table, int* counter) {
+  std::vector<MergeLevelDev> h;
+  long total = 0;
+  int rmax = 1;
+  double flops = 0;
+  for (MergeLevelDev g : levels) {
+    LSH_REQUIRE(merge_level_fits(g.r), -6, "merge_levels: inverse order beyond the in-LDS form");
+    g.item0 = total;
+    total += g.nb;
+    rmax = g.r > rmax ? g.r : rmax;
+    const double c = g.c, r = g.r, k = g.k;
+    flops += 8.0 * g.nb * (2 * c * r * c + 2 * r * r * c + 4 * r * r * r +
+                           (g.U ? 2 * c * k * c + 2 * r * k * c + 4 * r * r * k + 2 * c * k * r + 2 * k * k * c : 0));
+    h.push_back(g);
+  }
+  if (h.empty()) return;
+  if (table.bytes < sizeof(MergeLevelDev) * h.size()) table.alloc(sizeof(MergeLevelDev) * h.size());
+  LSH_HIP(hipMemcpyAsync(table.p, h.data(), sizeof(MergeLevelDev) * h.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, counter, 1L);
+  LSH_LAUNCH_CHECK();
+  int dev = 0, ncu = 0;
+  LSH_HIP(hipGetDevice(&dev));
+  LSH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const size_t lds = small_inv_lds<float>(rmax);
+  const long grid = std::min<long>(total, (long)ncu * (lds <= 16384 ? 3 : lds <= 40960 ? 2 : 1));
+  ProfScope ps("merge_level_f32", s, flops);
+  hipLaunchKernelGGL(k_merge_level, dim3((unsigned)grid), dim3(256), lds, s, table.as<MergeLevelDev>(),
+                     (int)h.size(), total, counter);
+  LSH_LAUNCH_CHECK();
+}
+
 // dst[b][i][j] = src[b][i][j] for rows x cols blocks with their own leading
 // dimensions and batch strides
 template <typename R>

@@ -121,6 +121,26 @@ void inverse_grouped(hipStream_t s, const std::vector<InvItem>& items, void* ws,
 // tables, and the workspace of orders beyond the grouped kernels), at most
 size_t inverse_grouped_arena_bytes(const std::vector<InvItem>& items);
 
+// One persistent launch per level step (FP32): for every box of every
+// entry, the Woodbury merge of Algorithm 1 (S_a L, S_b R; Aw, Bw;
+// C = (I - Bw Aw)^{-1}; W') and, with U set, the box's scattering matrix, in
+// the layouts of the separate launches (Pst [nb][2][c][r], W [nb][2r][2r],
+// S [nb][k][k]); the same bits.  T [nb][3][r][r], A12 [nb][2][c][k],
+// Qb [nb][4][r][k], perm [nb][r] are temporaries; info [nb] the inverses'
+// flags.  Only for r with merge_level_fits(r) (the inverse in LDS).
+// counter: one device int (zeroed by the call); table: at least
+// merge_level_table_bytes(levels.size()) bytes, else taken from the bound arena.
+struct MergeLevelDev {
+  const c32 *Sch, *Pm, *Qm, *U;
+  c32 *Pst, *W, *S, *T, *A12, *Qb;
+  int *info, *perm;
+  int c, r, k, nb;
+  long item0;
+};
+bool merge_level_fits(int r);
+size_t merge_level_table_bytes(size_t levels);
+void merge_levels(hipStream_t s, const std::vector<MergeLevelDev>& levels, DevBuf& table, int* counter);
+
 // out_b (cols x rows) = in_b^T (rows x cols), row-major, batch of contiguous matrices
 template <typename R>
 void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch = 1);

@@ -679,6 +679,8 @@ FactorBytes factor_bytes_t(const Profile& f, bool want_T) {
       if (want_T) { a.add(e * nb * 2 * c * r); a.add(e * nb * 4 * r * r); }
       t.add(e * nb * 3 * r * r);
       t.add(inverse_ws_bytes<R>((int)std::max(1L, r), (int)nb));
+      t.add(merge_level_table_bytes(1));  // (a level in one persistent launch: its table and counter)
+      t.add(sizeof(int));
       if (l >= 1) { t.add(e * nb * 2 * c * k); t.add(e * nb * 4 * r * k); }
       keep_l = std::max(keep_l, a.total);
       scr_l = std::max(scr_l, t.total);
@@ -726,6 +728,7 @@ FactorBytes factor_bytes(const Profile& f, bool want_T) {
 // ------------------------------------------------------------ factor
 template <typename R>
 struct FactorData {
+  using real_t = R;
   DevBuf X;                       // leaf inverses [nleaf][mL][mL]
   std::vector<DevBuf> S;          // S[l], l = 1..L : [2^l][k_l][k_l]
   std::vector<DevBuf> Pa, Pb, Ci; // parent level l = 0..L-1 : [2^l][c][c]
@@ -959,8 +962,70 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
   cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, y, k, ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k, nb);
 }  // (scratch freed in stream order)
 
+// Woodbury levels whose inverse order fits the in-LDS Gauss-Jordan run as one
+// persistent launch (merge and scattering matrices of every box;
+// merge_levels) when they have at least lsh_fused_levels(min_boxes) boxes;
+// 0 switches this off (the separate launches; the same bits).
+constexpr int kFusedMinBoxes = 0;  // (measured slower than the separate launches on MI355X)
+int g_fused_min_boxes = kFusedMinBoxes;  // fuse levels with at least this many boxes (0: never)
+
+template <typename R>
+bool level_fused(const lsh_plan_s& P, int l) {
+  return sizeof(R) == 4 && g_fused_min_boxes > 0 && (1 << l) >= g_fused_min_boxes && P.lev[l].wr > 0 &&
+         merge_level_fits(P.lev[l].wr);
+}
+
+// The level-l entry of a persistent merge launch for one FP32 factor:
+// the factor's own parts from keep, the temporaries from tmp.
+MergeLevelDev merge_entry(const lsh_plan_s& P, FactorData<float>& F, int l, mem::Arena& keep, mem::Arena& tmp,
+                          int* info) {
+  const int c = P.lev[l].c, r = P.lev[l].wr, nb = 1 << l, k = l >= 1 ? P.lev[l].k : 0;
+  const long cr = (long)c * r, rr = (long)r * r, ck = (long)c * k, rk = (long)r * k;
+  F.wr[l] = r;
+  F.Pa[l].alloc_in(keep, sizeof(c32) * nb * 2 * cr);
+  F.Ci[l].alloc_in(keep, sizeof(c32) * nb * 4 * rr);
+  if (l >= 1) F.S[l].alloc_in(keep, sizeof(c32) * nb * (long)k * k);
+  MergeLevelDev g{};
+  g.Sch = F.S[l + 1].as<c32>();
+  g.Pm = P.W<float>(l, 0);
+  g.Qm = P.W<float>(l, 1);
+  g.U = l >= 1 ? P.U<float>(l) : nullptr;
+  g.Pst = F.Pa[l].as<c32>();
+  g.W = F.Ci[l].as<c32>();
+  g.S = l >= 1 ? F.S[l].as<c32>() : nullptr;
+  g.T = static_cast<c32*>(tmp.take(sizeof(c32) * nb * 3 * rr));
+  g.A12 = l >= 1 ? static_cast<c32*>(tmp.take(sizeof(c32) * nb * 2 * ck)) : nullptr;
+  g.Qb = l >= 1 ? static_cast<c32*>(tmp.take(sizeof(c32) * nb * 4 * rk)) : nullptr;
+  g.perm = static_cast<int*>(tmp.take(sizeof(int) * nb * r));
+  g.info = info;
+  g.c = c;
+  g.r = r;
+  g.k = k;
+  g.nb = nb;
+  return g;
+}
+
+// merge and scattering matrices of level l in one launch (needs G_l and U_l)
+template <typename R>
+void factor_level_fused(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  if constexpr (sizeof(R) == 4) {
+    F.scratch_reset();
+    mem::Bind bind(F.keep);
+    const int nb = 1 << l;
+    F.info.emplace_back(sizeof(int) * nb);
+    F.info_n.push_back(nb);
+    F.info_what.push_back("singular merge matrix I - Bw Aw at level " + std::to_string(l));
+    std::vector<MergeLevelDev> e{merge_entry(P, F, l, *F.keep, *F.scr, F.info.back().template as<int>())};
+    DevBuf table;
+    table.alloc_in(*F.scr, merge_level_table_bytes(1));
+    int* counter = F.template scratch_buf<int>(sizeof(int));
+    merge_levels(s, e, table, counter);
+  }
+}
+
 template <typename R>
 void factor_level(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
+  if (level_fused<R>(P, l)) return factor_level_fused(P, F, l, s);
   factor_merge(P, F, l, s);
   factor_scatter(P, F, l, s);
 }
@@ -2213,6 +2278,15 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
       for (int l = L - 1; l >= 0; --l) {
         if (!wait_for(l, 1)) return;  // G_l: the merge overlaps the row ID of level l
         LSH_HIP(hipStreamWaitEvent(fs, ev[L + 1 + l], 0));
+        using RT = typename std::decay_t<decltype(FD)>::real_t;
+        if (level_fused<RT>(*P, l)) {  // one launch for merge and scattering matrices
+          if (l >= 1) {
+            if (!wait_for(l, 0)) return;
+            LSH_HIP(hipStreamWaitEvent(fs, ev[l], 0));
+          }
+          factor_level_fused(*P, FD, l, fs);
+          continue;
+        }
         factor_merge(*P, FD, l, fs);
         if (l >= 1) {
           if (!wait_for(l, 0)) return;
@@ -2260,9 +2334,36 @@ namespace {
 // instance's temporaries from its scr arena, the grouped launches' tables,
 // flags and inverse workspace from the arena bound to the thread (the batch's
 // shared workspace); all rewound per level step by the caller.
-void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>& wact, int dpt, hipStream_t s) {
+void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>& wact_all, int dpt, hipStream_t s) {
   const c32 one = mk<float>(1, 0), zero = mk<float>(0, 0), mone = mk<float>(-1, 0);
   const int n_inst = (int)Fs.size();
+  // levels whose inverse fits in LDS: every instance's boxes in one persistent launch
+  std::vector<int> wact, fused;
+  for (int i : wact_all) {
+    const lsh_plan_s& P = *Fs[i]->plan;
+    (level_fused<float>(P, P.L - dpt) ? fused : wact).push_back(i);
+  }
+  if (!fused.empty()) {
+    std::vector<MergeLevelDev> e;
+    std::vector<DevBuf> inf(fused.size());
+    for (size_t q = 0; q < fused.size(); ++q) {
+      lsh_factor_s& F = *Fs[fused[q]];
+      const int l = F.plan->L - dpt;
+      inf[q].alloc(sizeof(int) << l);
+      e.push_back(merge_entry(*F.plan, F.f32, l, F.keep, F.scr, inf[q].as<int>()));
+    }
+    DevBuf table;
+    table.alloc(merge_level_table_bytes(e.size()));
+    DevBuf counter(sizeof(int));
+    merge_levels(s, e, table, counter.as<int>());
+    for (size_t q = 0; q < fused.size(); ++q) {
+      const int l = Fs[fused[q]]->plan->L - dpt;
+      LSH_REQUIRE(!check_info(inf[q], 1 << l, s), LSH_ERR_SINGULAR,
+                  "singular merge matrix I - Bw Aw at level " + std::to_string(l) + " (instance " +
+                      std::to_string(fused[q]) + ")");
+    }
+  }
+  if (wact.empty()) return;
   std::vector<GemmItem> gi;
   DevBuf itab;
   auto run = [&] {
@@ -2664,7 +2765,8 @@ size_t batch_shared_bytes(const std::vector<const lsh_plan_s*>& Ps) {
       (v.wr > 0 ? iw : is).push_back({nullptr, c, (long)c, (long)c * c, nb, nullptr});
       z.add_n<int>(nb);
     }
-    const size_t t = z.total + inv_bytes(iw) + inv_bytes(is) +
+    const size_t t = z.total + inv_bytes(iw) + inv_bytes(is) + merge_level_table_bytes(iw.size()) +
+                     mem::round_up(sizeof(int)) +
                      (iw.empty() ? 0 : 12 * cgemm_grouped_table_bytes(2 * iw.size())) +
                      (is.empty() ? 0 : 12 * cgemm_grouped_table_bytes(2 * is.size()));
     best = std::max(best, t);
@@ -2923,6 +3025,14 @@ int lsh_gemm_variants(int prec, int* count, char* names, int cap) {
     std::strncpy(names, t.c_str(), cap - 1);
     names[cap - 1] = 0;
   }
+  return LSH_OK;
+  API_END
+}
+
+int lsh_fused_levels(int min_boxes) {
+  API_BEGIN
+  LSH_REQUIRE(min_boxes >= -1, LSH_ERR_INVALID_ARG, "min_boxes must be >= -1");
+  g_fused_min_boxes = min_boxes < 0 ? kFusedMinBoxes : min_boxes;
   return LSH_OK;
   API_END
 }

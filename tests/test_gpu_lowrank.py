@@ -130,3 +130,40 @@ def test_batch_factor_with_lowrank_levels_equals_separate():
         F1 = lsh.Factor(P, b)
         x = np.random.default_rng(w.n).standard_normal((1, w.n, w.n)) + 0j
         assert np.array_equal(F.apply_precond(cuda(x)).cpu().numpy(), F1.apply_precond(cuda(x)).cpu().numpy())
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_fused_levels_equal_separate_launches(batched):
+    """Woodbury levels with a merge inverse of order <= 90 run as one
+    persistent launch per level (every box's merge chain and scattering
+    matrix; over all instances when batched): the factors equal those of the
+    separate launches bit for bit, through M and M^T."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    ws = [w for w in synth.batched(24) if w.n in (128, 256)][:3] if batched else [synth.bumps20()]
+    plans = [lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=2, prec="fp32")
+             for w in ws]
+    assert any(0 < r <= 90 for P in plans for r in P.lowrank_ranks())
+    bs = [cuda(w.b) for w in ws]
+
+    def factors():
+        if batched:
+            return lsh.batch_factor(plans, bs, transpose=True)
+        return [lsh.Factor(P, b, transpose=True) for P, b in zip(plans, bs)]
+
+    try:
+        lsh.fused_levels(False)
+        f0 = factors()
+        lsh.fused_levels(True)
+        lsh.lsh_profile_only(None)
+        lsh.lsh_profile_enable(True)
+        f1 = factors()
+        names = lsh.lsh_profile_names()
+    finally:
+        lsh.lsh_profile_enable(False)
+        lsh.fused_levels(-1)
+    assert "merge_level_f32" in names
+    for w, F0, F1 in zip(ws, f0, f1):
+        x = cuda(np.random.default_rng(w.n).standard_normal((2, w.n, w.n)) + 1j)
+        for tr in (False, True):
+            assert torch.equal(F0.apply_precond(x, transpose=tr), F1.apply_precond(x, transpose=tr)), (w.name, tr)
