@@ -930,10 +930,25 @@ static int grid_of(long n) {
   return (int)(g < 2048 ? (g > 0 ? g : 1) : 2048);
 }
 
+// Linv[q] (diagonal block q of the k x k array, row-major, leading dimension
+// k) = D[q] for the nb inverted 64 x 64 blocks (the last one cut at k)
+__global__ void k_place_diag(const z64* D, int k, z64* Linv) {
+  const int q = blockIdx.y, base = q * TRI_B;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < TRI_B * TRI_B; e += gridDim.x * blockDim.x) {
+    const int r = e / TRI_B, c = e % TRI_B;
+    if (base + r < k && base + c < k) Linv[(long)(base + r) * k + base + c] = D[(long)q * TRI_B * TRI_B + e];
+  }
+}
+
 // U = L(rest, 0:k) L11^{-1} with U(J) = I, from the column-major factor Lt
-// (shared by both Gram paths)
+// (shared by both Gram paths).  L11^{-1} is formed explicitly from the
+// inverted 64 x 64 diagonal blocks by doubling (inv [[A, 0], [B, C]] =
+// [[A^-1, 0], [-C^-1 B A^-1, C^-1]], all pairs of one size in two batched
+// products), then U(rest) = L(rest) L11^{-1} is one product: a dozen wide
+// launches instead of a block-by-block substitution chain.  Linv (k x k) and
+// the pairs' temporaries T (at most k^2 / 4 entries) are scratch.
 static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64* U, int* rest, z64* L11, z64* Lr,
-                        z64* Dinv, void* invws) {
+                        z64* Dinv, z64* Linv, z64* T) {
   const int DB = 64;
   std::vector<int> ph(k), rh;
   LSH_HIP(hipMemcpyAsync(ph.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
@@ -955,25 +970,31 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
     static_assert(DB == TRI_B, "diagonal block size");
     hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk), dim3(256), 0, s, L11, k, Dinv);
     LSH_LAUNCH_CHECK();
-    (void)invws;
-    z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
-    // X L11 = Lr, recursively on column halves (L11 lower triangular):
-    // X(:, right) first, then Lr(:, left) -= X(:, right) L11(right, left),
-    // then X(:, left); diagonal blocks of DB columns use their inverses
-    std::function<void(int, int)> solve = [&](int q0, int q1) {  // diagonal blocks q0 .. q1-1
-      const int c0 = q0 * DB, c1 = (q1 * DB < k) ? q1 * DB : k;
-      if (q1 - q0 == 1) {  // X(:, B) = Lr(:, B) L11(B, B)^{-1}
-        cgemm<double>(s, nr, c1 - c0, c1 - c0, mk(1.0, 0.0), Lr + c0, k, 0, OP_N, Dinv + (long)q0 * DB * DB, DB, 0,
-                      OP_N, mk(0.0, 0.0), nullptr, 0, 0, X + c0, k, 0, 1);
-        return;
+    fill_zero(s, Linv, sizeof(z64) * (size_t)k * k);
+    hipLaunchKernelGGL(k_place_diag, dim3(16, nblk), dim3(256), 0, s, Dinv, k, Linv);
+    LSH_LAUNCH_CHECK();
+    const z64 one = mk(1.0, 0.0), mone = mk(-1.0, 0.0), zero = mk(0.0, 0.0);
+    for (int b = DB; b < k; b *= 2) {
+      // pairs (A at rows i0 .. i0+b, C at i0+b .. min(i0+2b, k)), i0 = p 2b
+      const int full = k / (2 * b);                  // pairs with a whole C block
+      const long st = 2L * b * (k + 1);              // stride between pairs' diagonal positions
+      if (full > 0) {
+        // T_p = B_p A_p^{-1}, then Linv(C rows, A cols) = -C_p^{-1} T_p
+        cgemm<double>(s, b, b, b, one, L11 + (long)b * k, k, st, OP_N, Linv, k, st, OP_N, zero, nullptr, 0, 0, T,
+                      b, (long)b * b, full);
+        cgemm<double>(s, b, b, b, mone, Linv + (long)b * (k + 1), k, st, OP_N, T, b, (long)b * b, OP_N, zero,
+                      nullptr, 0, 0, Linv + (long)b * k, k, st, full);
       }
-      const int qm = (q0 + q1) / 2, cm = qm * DB;
-      solve(qm, q1);
-      cgemm<double>(s, nr, cm - c0, c1 - cm, mk(-1.0, 0.0), X + cm, k, 0, OP_N, L11 + (long)cm * k + c0, k, 0, OP_N,
-                    mk(1.0, 0.0), Lr + c0, k, 0, Lr + c0, k, 0, 1);
-      solve(q0, qm);
-    };
-    solve(0, nblk);
+      const int i0 = full * 2 * b, c2 = k - i0 - b;  // a last pair with a partial C block
+      if (c2 > 0) {
+        cgemm<double>(s, c2, b, b, one, L11 + (long)(i0 + b) * k + i0, k, 0, OP_N, Linv + (long)i0 * (k + 1), k, 0,
+                      OP_N, zero, nullptr, 0, 0, T, b, 0, 1);
+        cgemm<double>(s, c2, b, c2, mone, Linv + (long)(i0 + b) * (k + 1), k, 0, OP_N, T, b, 0, OP_N, zero,
+                      nullptr, 0, 0, Linv + (long)(i0 + b) * k + i0, k, 0, 1);
+      }
+    }
+    z64* X = L11 + (size_t)k * k;  // (nr x k) after L11 in the same buffer
+    cgemm<double>(s, nr, k, k, one, Lr, k, 0, OP_N, Linv, k, 0, OP_N, zero, nullptr, 0, 0, X, k, 0, 1);
     hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)(k + nr) * k, 256)), dim3(256), 0, s, U, k, J, rest, nr, X);
   } else {
     hipLaunchKernelGGL(k_scatter_U, dim3(ceil_div((long)k * k, 256)), dim3(256), 0, s, U, k, J, rest, 0, L11);
@@ -1067,7 +1088,10 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
     LSH_HIP(hipStreamSynchronize(s));
     return 1;
   }
-  gram_interp(s, Lt, m, j, J, U, rest, L11, Lr, Dinv, invws);
+  // (the Gram is no longer needed: it holds L11^{-1}; the pairs' temporaries
+  // follow the rest rows in Lr)
+  gram_interp(s, Lt, m, j, J, U, rest, L11, Lr, Dinv, M, Lr + (size_t)(m - j) * j);
+  (void)invws;
   return j;
 }
 
@@ -1133,7 +1157,8 @@ int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z
     rank = st[0];
   }
   const int k = rank < 1 ? 1 : rank;
-  gram_interp(s, Lt, m, k, J, U, rest, L11, Lr, Dinv, invws);
+  gram_interp(s, Lt, m, k, J, U, rest, L11, Lr, Dinv, M, Lr + (size_t)(m - k) * k);
+  (void)invws;
   return k;
 }
 

@@ -2193,7 +2193,7 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   mem::Bind bind(&P->persist);  // (plan_init; each plan thread binds its own)
   plan_init(*P, ps);
   const int L = P->L;
-  bs->events(2 * L + 5);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
+  bs->events(2 * L + 6);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
   std::vector<hipEvent_t>& ev = bs->ev;
   if (fsm) {  // the factor stream follows the copy of b on the caller's stream
     LSH_HIP(hipEventRecord(ev[2 * L + 3], s));
@@ -2273,30 +2273,47 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
     auto run = [&](auto& FD) {
       factor_init(*P, FD);
       if (!wait_for(L, 0)) return;
-      LSH_HIP(hipStreamWaitEvent(fs, ev[L], 0));
-      factor_leaves(*P, F->b.template as<double>(), FD, fs);
+      hipStream_t cur = fs;
+      // Once the last row ID exists the plan's latency-bound kernels are done:
+      // the rest of the factor (the top levels, most of its flops) moves from
+      // the CU-masked stream to the caller's stream and every compute unit
+      // (LSH_WIDEN=0 keeps it on the masked stream).
+      static const bool widen_on = [] {
+        const char* e = std::getenv("LSH_WIDEN");
+        return !(e && *e == '0');
+      }();
+      auto widen = [&] {
+        if (!fsm || cur != fsm || !widen_on) return;
+        LSH_HIP(hipEventRecord(ev[2 * L + 5], fsm));
+        LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 5], 0));
+        cur = s;
+      };
+      LSH_HIP(hipStreamWaitEvent(cur, ev[L], 0));
+      factor_leaves(*P, F->b.template as<double>(), FD, cur);
       for (int l = L - 1; l >= 0; --l) {
         if (!wait_for(l, 1)) return;  // G_l: the merge overlaps the row ID of level l
-        LSH_HIP(hipStreamWaitEvent(fs, ev[L + 1 + l], 0));
+        LSH_HIP(hipStreamWaitEvent(cur, ev[L + 1 + l], 0));
         using RT = typename std::decay_t<decltype(FD)>::real_t;
         if (level_fused<RT>(*P, l)) {  // one launch for merge and scattering matrices
           if (l >= 1) {
             if (!wait_for(l, 0)) return;
-            LSH_HIP(hipStreamWaitEvent(fs, ev[l], 0));
+            LSH_HIP(hipStreamWaitEvent(cur, ev[l], 0));
+            if (l == 1) widen();
           }
-          factor_level_fused(*P, FD, l, fs);
+          factor_level_fused(*P, FD, l, cur);
           continue;
         }
-        factor_merge(*P, FD, l, fs);
+        factor_merge(*P, FD, l, cur);
         if (l >= 1) {
           if (!wait_for(l, 0)) return;
-          LSH_HIP(hipStreamWaitEvent(fs, ev[l], 0));
-          factor_scatter(*P, FD, l, fs);
+          LSH_HIP(hipStreamWaitEvent(cur, ev[l], 0));
+          if (l == 1) widen();
+          factor_scatter(*P, FD, l, cur);
         }
       }
-      factor_check(FD, fs);
+      factor_check(FD, cur);
       ensure_apply_ws(*P, FD);
-      if (fsm) {
+      if (fsm && cur == fsm) {
         LSH_HIP(hipEventRecord(ev[2 * L + 4], fsm));
         LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 4], 0));
       }
