@@ -124,6 +124,32 @@ def run_step(lsh, w, b_d, u_d, prec, torch, separate=False, merge="auto"):
     return out
 
 
+def apply_bytes(n, leaf, ranks, lowrank, esize):
+    """Algorithmic bytes of one preconditioner apply (Algorithm 2, one right
+    hand side): each stored matrix of the factor read as often as the passes
+    use it -- the leaf inverses X_tau in the leaf up and down steps, the merge
+    factors of level l >= 1 in the up and the down pass (the root's once), the
+    children's scattering matrices in the down pass, and the shared per-level
+    matrices (U_l, the sibling block G_ab, the low-rank factors) once per
+    launch that reads them.  Vectors (O(N) complex) are left out: they are a
+    few percent of the total at these sizes."""
+    L = len(ranks) - 1
+    nleaf, mL = 2 ** L, leaf * leaf
+    tot = 2.0 * nleaf * mL * mL + 2.0 * mL * ranks[L]
+    for l in range(L):
+        nb, c, r, k = 2 ** l, ranks[l + 1], lowrank[l], ranks[l]
+        uses = 1 if l == 0 else 2
+        if r > 0:  # [S_a L; S_b R] (2 nb blocks c x r), W' (nb of 2r x 2r), the shared [L; R] and its transpose
+            tot += uses * (2.0 * nb * c * r + 4.0 * nb * r * r + 2.0 * c * r)
+        else:      # P_a, P_b, C^{-1}
+            tot += uses * 3.0 * nb * c * c
+        tot += 2.0 * c * c                 # G_ab and its transpose
+        if l >= 1:
+            tot += 2.0 * nb * c * c        # S of the two children of every box (down pass)
+            tot += 2 * 2.0 * c * k         # U_l (up and down pass)
+    return esize * tot
+
+
 def roofline(lsh):
     """Dominant instrumented kernel over the timed region, against its peak."""
     best = None
@@ -141,7 +167,8 @@ def roofline(lsh):
         achieved = work / (ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None, "launches": n, "ms_total": ms,
-                "work_per_launch": work / n}
+                "work_per_launch": work / n,
+                "algorithmic_bytes_per_launch": lsh.lsh_profile_bytes(name) / n}
     achieved = work / (ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": None, "launches": n, "ms_total": ms,
@@ -544,6 +571,21 @@ def main():
                    "true_residual": head["median"]["true_residual"],
                    "ranks": head["median"]["ranks"]},
     }
+    # the solve's streams (K6 apply, K7 FFT operator, K8 Gram-Schmidt) from the
+    # median step's FGMRES phase clocks (hipEvents around each phase)
+    med = head["median"]
+    its = max(med["iterations"], 1)
+    ab = apply_bytes(w.n, w.leaf, med["ranks"], med["lowrank"], 8)
+    Mfft = 1
+    while Mfft < 2 * w.n:
+        Mfft *= 2
+    ob = 16.0 * 2 * w.n ** 2 + 8.0 * w.n ** 2 + 16.0 * Mfft ** 2   # x, y, b once and the spectrum once
+    t_ap, t_op = med["solve_ms_precond"] / its, med["solve_ms_operator"] / its
+    out["solve_streams"] = {
+        "apply_ms": t_ap, "apply_algorithmic_GB": ab / 1e9, "apply_GBs": ab / (t_ap * 1e-3) / 1e9,
+        "fft_operator_ms": t_op, "fft_operator_algorithmic_GB": ob / 1e9, "fft_operator_GBs": ob / (t_op * 1e-3) / 1e9,
+        "gram_schmidt_ms_per_iteration": med["solve_ms_ortho"] / its,
+        "note": "per FGMRES iteration of the median timed FP32 step; GB/s of algorithmic bytes against 8000"}
     if "fp64" in results:
         r64 = results["fp64"]
         out["fp64_hbs"] = {"value": r64["ms_per_step"] / 1e3, "unit": "s",
@@ -553,7 +595,10 @@ def main():
                            "speedup_fp32_over_fp64": r64["ms_per_step"] / head["ms_per_step"]}
     if prof:
         if prof["roofline"]:
-            prof["roofline"]["traffic"] = committed_traffic(prof["roofline"]["kernel"])
+            rl = prof["roofline"]
+            rl["traffic"] = committed_traffic(rl["kernel"])
+            if rl["traffic"] and rl.get("algorithmic_bytes_per_launch"):
+                rl["traffic_over_algorithmic"] = rl["traffic"] / rl["algorithmic_bytes_per_launch"]
         out["roofline"] = prof["roofline"]
         out["kernels"] = prof["kernels"]
         out["kernels_from"] = prof["kernels_from"]

@@ -320,6 +320,9 @@ int lsh_profile_enable(int on);
 /* Restrict recording to names that start with prefix (NULL or "" = all). */
 int lsh_profile_only(const char* prefix);
 int lsh_profile_query(const char* name, int* launches, double* ms, double* work);
+/* summed algorithmic bytes of one kernel name's records (for the GEMMs,
+ * whose work is flops: each distinct operand once, the result once) */
+int lsh_profile_bytes(const char* name, double* bytes);
 int lsh_profile_names(char* buf, int cap);
 
 const char* lsh_last_error(void);

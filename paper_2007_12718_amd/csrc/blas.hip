@@ -455,7 +455,10 @@ static void launch_gemm_x32(hipStream_t s, const GemmP<float>& P, const cplx<flo
   constexpr int BM = 64 * WM, BN = 64 * WN;
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     int nb = batch - b0 < 65535 ? batch - b0 : 65535;
-    ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb);
+    // algorithmic bytes: each distinct operand once, the result (and D) once per problem
+    const double bytes = 8.0 * ((double)P.M * P.K * (sA ? nb : 1) + (double)P.K * P.N * (sB ? nb : 1) +
+                                (double)P.M * P.N * nb * (D ? 2 : 1));
+    ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb, bytes);
     GemmP<float> Q = P;
     Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
     if (D) Q.D = D + b0 * sD;

@@ -33,7 +33,7 @@ namespace lsh {
 namespace prof {
 void set(bool enable);
 void set_only(const char* prefix);
-int query(const char* name, int* launches, double* ms, double* work);
+int query(const char* name, int* launches, double* ms, double* work, double* bytes);
 std::string names();
 }  // namespace prof
 }  // namespace lsh
@@ -1852,7 +1852,15 @@ int lsh_profile_only(const char* prefix) {
 int lsh_profile_query(const char* name, int* launches, double* ms, double* work) {
   API_BEGIN
   LSH_REQUIRE(name, LSH_ERR_INVALID_ARG, "null name");
-  prof::query(name, launches, ms, work);
+  prof::query(name, launches, ms, work, nullptr);
+  return LSH_OK;
+  API_END
+}
+
+int lsh_profile_bytes(const char* name, double* bytes) {
+  API_BEGIN
+  LSH_REQUIRE(name && bytes, LSH_ERR_INVALID_ARG, "null argument");
+  prof::query(name, nullptr, nullptr, nullptr, bytes);
   return LSH_OK;
   API_END
 }
@@ -2193,7 +2201,7 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   mem::Bind bind(&P->persist);  // (plan_init; each plan thread binds its own)
   plan_init(*P, ps);
   const int L = P->L;
-  bs->events(2 * L + 6);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
+  bs->events(2 * L + 5);  // [l]: U_l ready, [L+1+l]: G_l ready, [2L+2]: done
   std::vector<hipEvent_t>& ev = bs->ev;
   if (fsm) {  // the factor stream follows the copy of b on the caller's stream
     LSH_HIP(hipEventRecord(ev[2 * L + 3], s));
@@ -2274,20 +2282,6 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
       factor_init(*P, FD);
       if (!wait_for(L, 0)) return;
       hipStream_t cur = fs;
-      // Once the last row ID exists the plan's latency-bound kernels are done:
-      // the rest of the factor (the top levels, most of its flops) moves from
-      // the CU-masked stream to the caller's stream and every compute unit
-      // (LSH_WIDEN=0 keeps it on the masked stream).
-      static const bool widen_on = [] {
-        const char* e = std::getenv("LSH_WIDEN");
-        return !(e && *e == '0');
-      }();
-      auto widen = [&] {
-        if (!fsm || cur != fsm || !widen_on) return;
-        LSH_HIP(hipEventRecord(ev[2 * L + 5], fsm));
-        LSH_HIP(hipStreamWaitEvent(s, ev[2 * L + 5], 0));
-        cur = s;
-      };
       LSH_HIP(hipStreamWaitEvent(cur, ev[L], 0));
       factor_leaves(*P, F->b.template as<double>(), FD, cur);
       for (int l = L - 1; l >= 0; --l) {
@@ -2298,7 +2292,6 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
           if (l >= 1) {
             if (!wait_for(l, 0)) return;
             LSH_HIP(hipStreamWaitEvent(cur, ev[l], 0));
-            if (l == 1) widen();
           }
           factor_level_fused(*P, FD, l, cur);
           continue;
@@ -2307,7 +2300,6 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
         if (l >= 1) {
           if (!wait_for(l, 0)) return;
           LSH_HIP(hipStreamWaitEvent(cur, ev[l], 0));
-          if (l == 1) widen();
           factor_scatter(*P, FD, l, cur);
         }
       }

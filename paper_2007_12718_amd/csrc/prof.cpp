@@ -14,7 +14,7 @@ struct Rec {
   std::string name;
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s = nullptr;
-  double work = 0;
+  double work = 0, bytes = 0;
 };
 std::mutex mu;
 bool on = false;
@@ -35,13 +35,14 @@ hipEvent_t get_event() {
 
 bool enabled() { return on; }
 
-void record(const char* name, hipStream_t s, double work, bool start) {
+void record(const char* name, hipStream_t s, double work, double bytes, bool start) {
   std::lock_guard<std::mutex> g(mu);
   if (!only.empty() && std::strncmp(name, only.c_str(), only.size()) != 0) return;
   if (start) {
     Rec r;
     r.name = name;
     r.work = work;
+    r.bytes = bytes;
     r.s = s;
     r.a = get_event();
     if (r.a) (void)hipEventRecord(r.a, s);
@@ -77,22 +78,24 @@ void set_only(const char* prefix) {
   only = prefix ? prefix : "";
 }
 
-// totals per kernel name: launches, ms, work
-int query(const char* name, int* launches, double* ms, double* work) {
+// totals per kernel name: launches, ms, work, algorithmic bytes
+int query(const char* name, int* launches, double* ms, double* work, double* bytes) {
   std::lock_guard<std::mutex> g(mu);
   (void)hipDeviceSynchronize();
   int n = 0;
-  double t = 0, w = 0;
+  double t = 0, w = 0, by = 0;
   for (auto& r : recs) {
     if (r.name != name || !r.a || !r.b) continue;
     float e = 0;
     if (hipEventElapsedTime(&e, r.a, r.b) == hipSuccess) t += e;
     w += r.work;
+    by += r.bytes;
     ++n;
   }
   if (launches) *launches = n;
   if (ms) *ms = t;
   if (work) *work = w;
+  if (bytes) *bytes = by;
   return 0;
 }
 

@@ -8,19 +8,21 @@
 namespace lsh {
 namespace prof {
 bool enabled();
-void record(const char* name, hipStream_t s, double work, bool start);
+void record(const char* name, hipStream_t s, double work, double bytes, bool start);
 }  // namespace prof
 
+// bytes (optional): the launch's algorithmic memory traffic where work counts flops
 struct ProfScope {
   const char* name;
   hipStream_t s;
-  double work;
+  double work, bytes;
   bool on;
-  ProfScope(const char* n, hipStream_t st, double w) : name(n), s(st), work(w), on(prof::enabled()) {
-    if (on) prof::record(name, s, work, true);
+  ProfScope(const char* n, hipStream_t st, double w, double by = 0)
+      : name(n), s(st), work(w), bytes(by), on(prof::enabled()) {
+    if (on) prof::record(name, s, work, bytes, true);
   }
   ~ProfScope() {
-    if (on) prof::record(name, s, work, false);
+    if (on) prof::record(name, s, work, bytes, false);
   }
 };
 }  // namespace lsh

@@ -35,7 +35,7 @@ EXPORTED = [
     "lsh_plan_lowrank", "lsh_plan_cache_info", "lsh_plan_cache_clear", "lsh_plan_cache_save",
     "lsh_plan_cache_load", "lsh_gemm_variants", "lsh_gemm_tune_workspace", "lsh_gemm_tune", "lsh_gemm_table_save",
     "lsh_gemm_table_load", "lsh_gemm_table_clear", "lsh_gemm_record", "lsh_gemm_recorded",
-    "lsh_gemm_force_variant", "lsh_dev_inverse_static", "lsh_fused_levels",
+    "lsh_gemm_force_variant", "lsh_dev_inverse_static", "lsh_fused_levels", "lsh_profile_bytes",
 ]
 
 # tuned GEMM variant choices (written by tune_gemm.py on an MI355X); LSH_GEMM_TABLE overrides the path,
@@ -129,6 +129,7 @@ def lib():
         L.lsh_profile_query.argtypes = [ctypes.c_char_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]
         L.lsh_profile_names.argtypes = [ctypes.c_char_p, c_int]
         L.lsh_profile_only.argtypes = [ctypes.c_char_p]
+        L.lsh_profile_bytes.argtypes = [ctypes.c_char_p, POINTER(c_double)]
         L.lsh_plan_lowrank.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_int), c_void_p, c_void_p,
                                        c_void_p]
         L.lsh_plan_cache_info.argtypes = [POINTER(c_int), POINTER(ctypes.c_size_t)]
@@ -605,6 +606,13 @@ def lsh_profile_query(name):
     n, ms, w = c_int(0), c_double(0), c_double(0)
     _check(lib().lsh_profile_query(name.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
     return n.value, ms.value, w.value
+
+
+def lsh_profile_bytes(name):
+    """Summed algorithmic bytes recorded for one kernel name (GEMMs: operands and result once)."""
+    b = c_double(0)
+    _check(lib().lsh_profile_bytes(name.encode(), ctypes.byref(b)))
+    return b.value
 
 
 def lsh_profile_names():
