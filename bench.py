@@ -575,7 +575,7 @@ def main():
     # median step's FGMRES phase clocks (hipEvents around each phase)
     med = head["median"]
     its = max(med["iterations"], 1)
-    ab = apply_bytes(w.n, w.leaf, med["ranks"], med["lowrank"], 8)
+    ab = apply_bytes(w.n, w.leaf, med["ranks"], med["lowrank_ranks"], 8)
     Mfft = 1
     while Mfft < 2 * w.n:
         Mfft *= 2
