@@ -765,40 +765,25 @@ template void mirror_lower<float>(hipStream_t, cplx<float>*, int, long);
 
 // ---------------------------------------------------------------- GEMV
 // One wavefront per row, lanes stride the row (coalesced); x_b staged in LDS.
-// DPP lane exchange of a float or double (CTRL: a DPP control inside a
-// 16-lane row), and the sum over groups of L lanes, the same in every lane of
-// a group: DPP butterflies inside rows of 16, then exchanges across rows.
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-template <int L, typename R>
-__device__ __forceinline__ R group_sum(R v) {
-  if (L >= 2) v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (L >= 4) v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (L >= 8) v += dpp_mov<0x141>(v);  // row_half_mirror
-  if (L >= 16) v += dpp_mov<0x140>(v); // row_mirror
-  if (L >= 32) v += __shfl_xor(v, 16);
-  if (L >= 64) v += __shfl_xor(v, 32);
-  return v;
-}
 
-// Per-problem GEMV over the rows of all problems: global row g = b M + i
-// (problem b, row i of its matrix, matrix b mod amod).  L lanes share a row
-// (a power of two, the row length rounded up, at most 64); a wave takes
-// 64 / L rows per pass, and P passes whose loads are issued together, so that
-// short rows (small boxes) still keep many loads in flight.  x is read
-// through the caches (the rows of one problem share it).
-template <typename R, int L, int P>
+// Per-problem GEMV over the rows of all problems: y[v amod + b] = alpha A_b
+// x[v amod + b] + beta z[...] for rows i of problem b < nb (matrix b mod
+// amod) and v < nv vectors per matrix (nv = 1: one vector per problem, any
+// batch; nv > 1: the vectors of one matrix share its row loads).  Global row
+// g = b M + i.  L lanes share a row (a power of two chosen from the row
+// length, at most 64); a wave takes 64 / L rows per pass and P passes.  Short
+// and medium rows (NCH = the row's chunks of L, at most 8): every load of the
+// P rows is issued before the products, so small boxes still keep
+// 2 P NCH loads in flight per lane; long rows (NCH = 0) loop over chunks of
+// 8 L.  A lane adds its products in chunk order into four partial sums
+// (chunk u into sum u mod 4), then (s0 + s1) + (s2 + s3), then a butterfly
+// over the row's L lanes: every vector of a matrix gets the arithmetic of a
+// one-vector call (same lanes, same order), so columns come out bitwise the
+// same either way.  x is read through the caches (the rows of one problem
+// share it).
+template <typename R, int L, int NCH, int P, int NV>
 __global__ __launch_bounds__(256) void k_cgemv(int M, int N, cplx<R> alpha, const cplx<R>* __restrict__ A, long lda,
-                                               long sA, int amod, const cplx<R>* __restrict__ x, long sx,
+                                               long sA, int amod, int nv, const cplx<R>* __restrict__ x, long sx,
                                                cplx<R> beta, const cplx<R>* z, long sz, cplx<R>* y, long sy,
                                                long rows) {
   constexpr int RW = 64 / L;
@@ -816,119 +801,48 @@ __global__ __launch_bounds__(256) void k_cgemv(int M, int N, cplx<R> alpha, cons
       while (i >= (unsigned)M) { i -= M; ++b; }
     }
   }
-  cplx<R> acc[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) acc[p] = mk<R>(0, 0);
-  if (N <= L) {  // one element per lane and row: all P loads in flight together
-    cplx<R> av[P], xv[P];
+  cplx<R> out[P][NV];
+  if constexpr (NCH > 0) {
+    cplx<R> a[P][NCH];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const long g = (long)g0 + (long)p * RW;
-      av[p] = xv[p] = mk<R>(0, 0);
-      if (g < rows && sub < N) {
-        av[p] = A[(long)(bp[p] % (unsigned)amod) * sA + (long)ip[p] * lda + sub];
-        xv[p] = x[(long)bp[p] * sx + sub];
+      const bool live = (long)g0 + (long)p * RW < rows;
+      const cplx<R>* row = A + (long)(bp[p] % (unsigned)amod) * sA + (long)ip[p] * lda;
+#pragma unroll
+      for (int u = 0; u < NCH; ++u) {
+        const int col = sub + u * L;
+        a[p][u] = (live && col < N) ? row[col] : mk<R>(0, 0);
       }
     }
 #pragma unroll
-    for (int p = 0; p < P; ++p) fma_acc(acc[p], av[p], xv[p]);
-  } else {  // long rows (L == 64): eight independent loads per lane per row
+    for (int v = 0; v < NV; ++v) {
+      cplx<R> xv[P][NCH];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const bool live = v < nv && (long)g0 + (long)p * RW < rows;
+        const cplx<R>* xb = x + ((long)v * amod + bp[p]) * sx;
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int col = sub + u * L;
+          xv[p][u] = (live && col < N) ? xb[col] : mk<R>(0, 0);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        cplx<R> a4[4] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) fma_acc(a4[u & 3], a[p][u], xv[p][u]);
+        out[p][v] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+      }
+    }
+  } else {  // long rows (L == 64): eight independent loads per lane per chunk
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[p][v] = mk<R>(0, 0);
       const long g = (long)g0 + (long)p * RW;
       if (g >= rows) break;
       const cplx<R>* row = A + (long)(bp[p] % (unsigned)amod) * sA + (long)ip[p] * lda;
-      const cplx<R>* xb = x + (long)bp[p] * sx;
-      cplx<R> a4[4] = {mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0), mk<R>(0, 0)};
-      for (int j = sub; j < N; j += 8 * L) {
-        cplx<R> v[8], xw[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int jj = j + u * L;
-          v[u] = jj < N ? row[jj] : mk<R>(0, 0);
-          xw[u] = jj < N ? xb[jj] : mk<R>(0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) fma_acc(a4[u & 3], v[u], xw[u]);
-      }
-      acc[p] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    cplx<R> v = acc[p];
-    v.x = group_sum<L>(v.x);  // (stays inside the row's L lanes)
-    v.y = group_sum<L>(v.y);
-    const long g = (long)g0 + (long)p * RW;
-    if (sub == 0 && g < rows) {
-      const long b = bp[p], i = ip[p];
-      cplx<R> o = alpha * v;
-      if (z && (beta.x != R(0) || beta.y != R(0))) o = o + beta * z[b * sz + i];
-      y[b * sy + i] = o;
-    }
-  }
-}
-
-template <typename R, int L, int P>
-static void cgemv_launch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<R>* A, long lda, long sA, int amod,
-                         const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz, cplx<R>* y, long sy,
-                         long rows) {
-  const long per_wg = 4L * P * (64 / L);
-  const long g = (rows + per_wg - 1) / per_wg;
-  LSH_REQUIRE(rows + per_wg < 2147483647L, -6, "cgemv: too many rows");
-  hipLaunchKernelGGL((k_cgemv<R, L, P>), dim3((unsigned)g), dim3(256), 0, s, M, N, alpha, A, lda, sA, amod, x, sx,
-                     beta, z, sz, y, sy, rows);
-}
-
-// Several vectors per matrix: problem p = v * amod + b uses matrix b, so the
-// nv = batch / amod vectors of one matrix are read with one pass over it.
-// Rows g range over the matrices (g = b M + i); each of the NV vectors of a
-// group gets exactly the arithmetic of k_cgemv (the same lanes, loads in the
-// same order, the same sums), so a column comes out bitwise as from a
-// one-vector call.
-template <typename R, int L, int P, int NV>
-__global__ __launch_bounds__(256) void k_cgemv_mv(int M, int N, cplx<R> alpha, const cplx<R>* __restrict__ A,
-                                                  long lda, long sA, int amod, int nv,
-                                                  const cplx<R>* __restrict__ x, long sx, cplx<R> beta,
-                                                  const cplx<R>* z, long sz, cplx<R>* y, long sy, long rows) {
-  constexpr int RW = 64 / L;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, sub = lane & (L - 1);
-  const unsigned g0 = ((blockIdx.x * 4u + wave) * P) * RW + lane / L;
-  unsigned bp[P], ip[P];
-  {
-    unsigned b = g0 / (unsigned)M, i = g0 - b * (unsigned)M;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      bp[p] = b;
-      ip[p] = i;
-      i += RW;
-      while (i >= (unsigned)M) { i -= M; ++b; }
-    }
-  }
-  cplx<R> acc[P][NV];
-#pragma unroll
-  for (int p = 0; p < P; ++p)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[p][v] = mk<R>(0, 0);
-  if (N <= L) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const long g = (long)g0 + (long)p * RW;
-      cplx<R> av = mk<R>(0, 0);
-      if (g < rows && sub < N) av = A[(long)bp[p] * sA + (long)ip[p] * lda + sub];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        cplx<R> xv = mk<R>(0, 0);
-        if (v < nv && g < rows && sub < N) xv = x[((long)v * amod + bp[p]) * sx + sub];
-        fma_acc(acc[p][v], av, xv);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const long g = (long)g0 + (long)p * RW;
-      if (g >= rows) break;
-      const cplx<R>* row = A + (long)bp[p] * sA + (long)ip[p] * lda;
       cplx<R> a4[NV][4];
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -956,15 +870,15 @@ __global__ __launch_bounds__(256) void k_cgemv_mv(int M, int N, cplx<R> alpha, c
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[p][v] = (a4[v][0] + a4[v][1]) + (a4[v][2] + a4[v][3]);
+      for (int v = 0; v < NV; ++v) out[p][v] = (a4[v][0] + a4[v][1]) + (a4[v][2] + a4[v][3]);
     }
   }
 #pragma unroll
   for (int p = 0; p < P; ++p)
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      cplx<R> t = acc[p][v];
-      t.x = group_sum<L>(t.x);
+      cplx<R> t = out[p][v];
+      t.x = group_sum<L>(t.x);  // (stays inside the row's L lanes)
       t.y = group_sum<L>(t.y);
       const long g = (long)g0 + (long)p * RW;
       if (v < nv && sub == 0 && g < rows) {
@@ -976,16 +890,48 @@ __global__ __launch_bounds__(256) void k_cgemv_mv(int M, int N, cplx<R> alpha, c
     }
 }
 
-template <typename R, int L, int P, int NV>
-static void cgemv_mv_launch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<R>* A, long lda, long sA,
-                            int amod, int nv, const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz,
-                            cplx<R>* y, long sy) {
-  const long rows = (long)amod * M;
+template <typename R, int L, int NCH, int P, int NV>
+static void cgemv_launch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<R>* A, long lda, long sA, int amod,
+                         int nv, const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz, cplx<R>* y,
+                         long sy, long rows) {
   const long per_wg = 4L * P * (64 / L);
   const long g = (rows + per_wg - 1) / per_wg;
   LSH_REQUIRE(rows + per_wg < 2147483647L, -6, "cgemv: too many rows");
-  hipLaunchKernelGGL((k_cgemv_mv<R, L, P, NV>), dim3((unsigned)g), dim3(256), 0, s, M, N, alpha, A, lda, sA, amod,
+  hipLaunchKernelGGL((k_cgemv<R, L, NCH, P, NV>), dim3((unsigned)g), dim3(256), 0, s, M, N, alpha, A, lda, sA, amod,
                      nv, x, sx, beta, z, sz, y, sy, rows);
+}
+
+// Lanes per row and chunk count from the row length N: L = the power of two
+// >= N / 4 (8..64), NCH = the power of two >= N / L; rows past 8 x 64 loop.
+// P keeps P NCH near 16 for one FP32 vector; halved for several vectors and
+// again for FP64, so the loads and sums stay near 80 registers.
+template <typename R, int NV>
+static void cgemv_dispatch(hipStream_t s, int M, int N, cplx<R> alpha, const cplx<R>* A, long lda, long sA, int amod,
+                           int nv, const cplx<R>* x, long sx, cplx<R> beta, const cplx<R>* z, long sz, cplx<R>* y,
+                           long sy, long rows) {
+  constexpr int DIV = (NV > 1 ? 2 : 1) * (sizeof(R) == 8 ? 2 : 1);
+#define LSH_GV(LL, NC, PP) \
+  cgemv_launch<R, LL, NC, ((PP) / DIV > 0 ? (PP) / DIV : 1), NV>(s, M, N, alpha, A, lda, sA, amod, nv, x, sx, beta, \
+                                                                 z, sz, y, sy, rows)
+  if (N > 512) { LSH_GV(64, 0, 1); return; }
+  int L = 8;
+  while (L < 64 && 4 * L < N) L *= 2;
+  const int nch = (N + L - 1) / L;  // 1 .. 8
+  switch (L) {
+    case 8:
+      if (nch <= 1) LSH_GV(8, 1, 8); else if (nch <= 2) LSH_GV(8, 2, 8); else LSH_GV(8, 4, 4);
+      break;
+    case 16:
+      if (nch <= 2) LSH_GV(16, 2, 8); else LSH_GV(16, 4, 4);
+      break;
+    case 32:
+      if (nch <= 2) LSH_GV(32, 2, 8); else LSH_GV(32, 4, 4);
+      break;
+    default:
+      if (nch <= 2) LSH_GV(64, 2, 8); else if (nch <= 4) LSH_GV(64, 4, 4); else LSH_GV(64, 8, 2);
+      break;
+  }
+#undef LSH_GV
 }
 
 template <typename R>
@@ -1006,87 +952,119 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
       const int nv = nvec - v0 < 4 ? nvec - v0 : 4;
       const long o = (long)v0 * am;
       const cplx<R>* zv = z ? z + o * sz : nullptr;
-      constexpr int P = sizeof(R) == 8 ? 1 : 2;  // FP64: keep the register file under 128
-      if (N <= 8) cgemv_mv_launch<R, 8, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
-      else if (N <= 16) cgemv_mv_launch<R, 16, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
-      else if (N <= 32) cgemv_mv_launch<R, 32, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
-      else cgemv_mv_launch<R, 64, P, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy);
+      cgemv_dispatch<R, 4>(s, M, N, alpha, A, lda, sA, am, nv, x + o * sx, sx, beta, zv, sz, y + o * sy, sy,
+                           (long)am * M);
       LSH_LAUNCH_CHECK();
     }
     return;
   }
-  const long rows = (long)batch * M;
-  if (N <= 8) cgemv_launch<R, 8, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
-  else if (N <= 16) cgemv_launch<R, 16, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
-  else if (N <= 32) cgemv_launch<R, 32, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
-  else if (N <= 64) cgemv_launch<R, 64, 8>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
-  else if (N <= 512) cgemv_launch<R, 64, 2>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
-  else cgemv_launch<R, 64, 1>(s, M, N, alpha, A, lda, sA, am, x, sx, beta, z, sz, y, sy, rows);
+  cgemv_dispatch<R, 1>(s, M, N, alpha, A, lda, sA, am, 1, x, sx, beta, z, sz, y, sy, (long)batch * M);
   LSH_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------ shared-matrix multi-GEMV
-// One workgroup per row of Mat: the four waves interleave over the row (a
-// wave reads 64 consecutive entries, the workgroup 256), four loads in flight
-// per lane; up to MG_VEC vectors accumulated in registers, X read through the
-// caches; the waves' partial sums meet in LDS.
-constexpr int MG_VEC = 8;
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_cmgemv(int Rr, int C, cplx<R> alpha, const cplx<R>* __restrict__ Mat,
-                                                long ldm, const cplx<R>* __restrict__ X, long ldx, cplx<R> beta,
-                                                const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec, int R1,
-                                                long xoff2) {
-  __shared__ cplx<R> red[4][MG_VEC];
+// Y[v] = alpha Mat X[v] + beta Z[v] for v < nvec and one shared matrix
+// (rows x C, row-major): the few-vector products of the preconditioner's top
+// levels (U_l, G_ab, [L^T; R^T], [L; R]), where the matrix is large and read
+// once.  A workgroup takes RR consecutive rows of one block (the rows from R1
+// on read X + xoff2: the two halves of Q v in one launch); its four waves
+// split the columns (wave w takes columns 64(w + 4q) + lane, two chunks per
+// step), so each loaded piece of x serves RR rows and a lane keeps
+// 2 (RR + NV) loads in flight.  Sums in a fixed order: per lane over its
+// chunks, a butterfly over the wave's lanes, then the four waves in order.
+template <typename R, int RR, int NV>
+__global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, cplx<R> alpha,
+                                                const cplx<R>* __restrict__ Mat, long ldm,
+                                                const cplx<R>* __restrict__ X, long ldx, long xoff2, cplx<R> beta,
+                                                const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+  __shared__ cplx<R> red[4][RR * NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = blockIdx.x;
-  const cplx<R>* row = Mat + (long)i * ldm;
-  if (i >= R1) X += xoff2;  // rows of the second block read their own part of each vector
-  for (int b0 = 0; b0 < nvec; b0 += MG_VEC) {
-    const int nb = nvec - b0 < MG_VEC ? nvec - b0 : MG_VEC;
-    cplx<R> acc[MG_VEC];
+  int i0, iend;
+  const cplx<R>* Xb = X;
+  if ((int)blockIdx.x < wg1) {
+    i0 = blockIdx.x * RR;
+    iend = R1;
+  } else {
+    i0 = R1 + (blockIdx.x - wg1) * RR;
+    iend = Rr;
+    Xb = X + xoff2;
+  }
+  const int nr = iend - i0 < RR ? iend - i0 : RR;
+  const cplx<R>* row0 = Mat + (long)i0 * ldm;
+  for (int v0 = 0; v0 < nvec; v0 += NV) {
+    const int nv = nvec - v0 < NV ? nvec - v0 : NV;
+    const cplx<R>* xv = Xb + (long)v0 * ldx;
+    cplx<R> acc[RR][NV];
 #pragma unroll
-    for (int v = 0; v < MG_VEC; ++v) acc[v] = mk<R>(0, 0);
-    for (int j = threadIdx.x; j < C; j += 4 * 256) {
-      cplx<R> a[4];
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = j + u * 256 < C ? row[j + u * 256] : mk<R>(0, 0);
+      for (int v = 0; v < NV; ++v) acc[r][v] = mk<R>(0, 0);
+    for (int j = wave * 64 + lane; j < C; j += 512) {
+      const int j2 = j + 256;
+      cplx<R> a[2][RR], x[2][NV];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < MG_VEC; ++v)
-          if (v < nb && j + u * 256 < C) fma_acc(acc[v], a[u], X[(long)(b0 + v) * ldx + j + u * 256]);
-    }
-#pragma unroll
-    for (int v = 0; v < MG_VEC; ++v) {
-      cplx<R> t = acc[v];
-      for (int off = 32; off > 0; off >>= 1) {
-        t.x += __shfl_xor(t.x, off);
-        t.y += __shfl_xor(t.y, off);
+      for (int r = 0; r < RR; ++r) {
+        a[0][r] = r < nr ? row0[(long)r * ldm + j] : mk<R>(0, 0);
+        a[1][r] = (r < nr && j2 < C) ? row0[(long)r * ldm + j2] : mk<R>(0, 0);
       }
-      if (lane == 0) red[wave][v] = t;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        x[0][v] = v < nv ? xv[(long)v * ldx + j] : mk<R>(0, 0);
+        x[1][v] = (v < nv && j2 < C) ? xv[(long)v * ldx + j2] : mk<R>(0, 0);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) fma_acc(acc[r][v], a[h][r], x[h][v]);
     }
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        cplx<R> t = acc[r][v];
+        t.x = group_sum<64>(t.x);
+        t.y = group_sum<64>(t.y);
+        if (lane == 0) red[wave][r * NV + v] = t;
+      }
     __syncthreads();
-    if (threadIdx.x < nb) {
-      const int v = threadIdx.x;
-      const cplx<R> t = (red[0][v] + red[1][v]) + (red[2][v] + red[3][v]);
-      cplx<R> r = alpha * t;
-      if (Z && (beta.x != R(0) || beta.y != R(0))) r = r + beta * Z[(long)(b0 + v) * ldz + i];
-      Y[(long)(b0 + v) * ldy + i] = r;
+    if (threadIdx.x < RR * NV) {
+      const int r = threadIdx.x / NV, v = threadIdx.x % NV;
+      if (r < nr && v < nv) {
+        const cplx<R> t = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        const long yi = (long)(v0 + v);
+        cplx<R> o = alpha * t;
+        if (Z && (beta.x != R(0) || beta.y != R(0))) o = o + beta * Z[yi * ldz + i0 + r];
+        Y[yi * ldy + i0 + r] = o;
+      }
     }
     __syncthreads();
   }
+}
+
+template <typename R, int RR, int NV>
+static void cmgemv_launch(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat,
+                          long ldm, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y,
+                          long ldy, int nvec) {
+  const int wg1 = ceil_div(R1, RR), wg2 = ceil_div(Rr - R1, RR);
+  hipLaunchKernelGGL((k_cmgemv<R, RR, NV>), dim3(wg1 + wg2), dim3(256), 0, s, Rr, R1, wg1, C, alpha, Mat, ldm, X,
+                     ldx, xoff2, beta, Z, ldz, Y, ldy, nvec);
 }
 
 template <typename R>
 void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm,
              const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
   if (Rr <= 0 || nvec <= 0) return;
+  if (R1 > Rr) R1 = Rr;
   ProfScope ps(sizeof(R) == 4 ? "cmgemv_f32" : "cmgemv_f64", s,
                (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * ((R1 < Rr ? 2.0 : 1.0) * C +
                                                                           (Z ? 2.0 : 1.0) * Rr)));
-  hipLaunchKernelGGL(k_cmgemv<R>, dim3(Rr), dim3(256), 0, s, Rr, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy,
-                     nvec, R1, xoff2);
+  constexpr int RR = sizeof(R) == 4 ? 4 : 2;  // (FP64: the accumulators in half the rows)
+  if (nvec == 1) cmgemv_launch<R, RR, 1>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
+  else if (nvec == 2) cmgemv_launch<R, RR, 2>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
+  else if (nvec <= 4) cmgemv_launch<R, RR, 4>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
+  else cmgemv_launch<R, RR, 8>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
   LSH_LAUNCH_CHECK();
 }
 

@@ -1220,29 +1220,73 @@ void leaf_scale_U(hipStream_t s, cplx<R>* Y, const cplx<R>* U, int mL, int k, co
 constexpr int LEAF_MAX = 144;
 constexpr int LEAF_NV = 4;
 
-// rows i of the mL x mL leaf matrix Xt times NV vectors in LDS (ins[v][*]);
-// one wave per row, the row sum by butterfly shuffles; fn(i, v, sum) on lane 0.
-// A wave takes LEAF_RU rows at a time (i, i + 4, ...) with their loads issued
-// together, so that each lane keeps several HBM reads in flight (one row per
-// wave at a time left the leaf kernels at a third of HBM bandwidth); every
-// row gets the same arithmetic in the same order either way.
+// Rows i < nrows of the row-major matrix A (nrows x ncols) times NV vectors
+// in LDS (ins[v][0 .. ncols)); fn(i, v, sum) once per row and vector v < nv.
+// Rows of at most 64 (the leaf matrices and U_L of leaves up to 8 x 8): 16
+// lanes per row in four 16-wide chunks, four rows per wave at a time and
+// four such row groups per wave with every load issued before the products
+// (16 loads in flight per lane); a lane adds its chunks as (s0 + s1) +
+// (s2 + s3), then a DPP butterfly over the row's 16 lanes.  Longer rows: one
+// wave per row, LEAF_RU rows at a time, butterfly over the wave.  Each vector
+// gets the same arithmetic in the same order for any NV.
 constexpr int LEAF_RU = 4;
 template <typename R, int NV, typename Fn>
-__device__ __forceinline__ void leaf_rows(const cplx<R>* __restrict__ Xt, int mL, const cplx<R> (*ins)[LEAF_MAX],
-                                          int nv, Fn fn) {
+__device__ __forceinline__ void leaf_rows(const cplx<R>* __restrict__ A, int nrows, int ncols,
+                                          const cplx<R> (*ins)[LEAF_MAX], int nv, Fn fn) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i0 = wave; i0 < mL; i0 += 4 * LEAF_RU) {
+  if (ncols <= 64) {
+    constexpr int L = 16, NCH = 4, RW = 64 / L, P = 4;
+    const int sub = lane & (L - 1), rs = lane / L;
+    for (int base = wave * RW; base < nrows; base += 4 * RW * P) {
+      cplx<R> a[P][NCH];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int i = base + p * 4 * RW + rs;
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int c = sub + u * L;
+          a[p][u] = (i < nrows && c < ncols) ? A[(long)i * ncols + c] : mk<R>(0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (v >= nv) break;  // (uniform)
+        cplx<R> xin[NCH];
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int c = sub + u * L;
+          xin[u] = c < ncols ? ins[v][c] : mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          cplx<R> a4[NCH];
+#pragma unroll
+          for (int u = 0; u < NCH; ++u) {
+            a4[u] = mk<R>(0, 0);
+            fma_acc(a4[u], a[p][u], xin[u]);
+          }
+          cplx<R> t = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          t.x = group_sum<L>(t.x);
+          t.y = group_sum<L>(t.y);
+          const int i = base + p * 4 * RW + rs;
+          if (sub == 0 && i < nrows) fn(i, v, t);
+        }
+      }
+    }
+    return;
+  }
+  for (int i0 = wave; i0 < nrows; i0 += 4 * LEAF_RU) {
     cplx<R> acc[LEAF_RU][NV];
 #pragma unroll
     for (int u = 0; u < LEAF_RU; ++u)
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[u][v] = mk<R>(0, 0);
-    for (int j = lane; j < mL; j += 64) {
+    for (int j = lane; j < ncols; j += 64) {
       cplx<R> xv[LEAF_RU];
 #pragma unroll
       for (int u = 0; u < LEAF_RU; ++u) {
         const int i = i0 + 4 * u;
-        xv[u] = i < mL ? Xt[(long)i * mL + j] : mk<R>(0, 0);
+        xv[u] = i < nrows ? A[(long)i * ncols + j] : mk<R>(0, 0);
       }
 #pragma unroll
       for (int u = 0; u < LEAF_RU; ++u)
@@ -1252,24 +1296,22 @@ __device__ __forceinline__ void leaf_rows(const cplx<R>* __restrict__ Xt, int mL
 #pragma unroll
     for (int u = 0; u < LEAF_RU; ++u) {
       const int i = i0 + 4 * u;
-      if (i >= mL) break;  // (uniform across the wave)
+      if (i >= nrows) break;  // (uniform across the wave)
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (v >= nv) break;
         cplx<R> a = acc[u][v];
-        for (int off = 32; off > 0; off >>= 1) {
-          a.x += __shfl_xor(a.x, off);
-          a.y += __shfl_xor(a.y, off);
-        }
+        a.x = group_sum<64>(a.x);
+        a.y = group_sum<64>(a.y);
         if (lane == 0) fn(i, v, a);
       }
     }
   }
 }
 
-// Up: r = X_tau f_tau ; rt = U_L^T r
+// Up: r = X_tau f_tau ; rt = U_L^T r  (ULt: U_L transposed, k x mL)
 template <typename R, int NV>
-__global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ UL,
+__global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, const cplx<R>* __restrict__ ULt,
                                                  int mL, int k, const z64* __restrict__ f, cplx<R>* r, cplx<R>* rt,
                                                  const I2* __restrict__ org, const I2* __restrict__ pts, int n,
                                                  int nleaf, int nrhs, const double* __restrict__ b, double sb) {
@@ -1289,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, 
     }
   }
   __syncthreads();
-  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, fs, nv, [&](int i, int v, cplx<R> acc) { rs[v][i] = acc; });
+  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, mL, fs, nv, [&](int i, int v, cplx<R> acc) { rs[v][i] = acc; });
   __syncthreads();
   for (int v = 0; v < nv; ++v) {
     if (r) {
@@ -1304,24 +1346,12 @@ __global__ __launch_bounds__(256) void k_leaf_up(const cplx<R>* __restrict__ X, 
     }
   }
   if (b) __syncthreads();
-  for (int a = threadIdx.x; a < k; a += blockDim.x) {
-    cplx<R> acc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
-#pragma unroll 8
-    for (int i = 0; i < mL; ++i) {  // (unrolled: the U_L loads issued together)
-      const cplx<R> u = UL[(long)i * k + a];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, rs[v][i]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (v < nv) rt[((r0 + v) * nleaf + t) * (long)k + a] = acc[v];
-  }
+  leaf_rows<R, NV>(ULt, k, mL, rs, nv,
+                   [&](int a, int v, cplx<R> acc) { rt[((r0 + v) * nleaf + t) * (long)k + a] = acc; });
 }
 
 template <typename R>
-void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const z64* f, cplx<R>* r,
+void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* ULt, int mL, int k, const z64* f, cplx<R>* r,
              cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs, const double* b,
              double sb) {
   LSH_REQUIRE(mL <= LEAF_MAX, -6, "leaf too large");
@@ -1329,10 +1359,10 @@ void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, 
   ProfScope ps("leaf_up", s, (double)sizeof(cplx<R>) * nleaf * ((double)ng * mL * mL + (double)nrhs * (2.0 * mL + k)) +
                                  16.0 * nrhs * (double)nleaf * mL);
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_leaf_up<R, 1>), dim3(nleaf, 1), dim3(256), 0, s, X, UL, mL, k, f, r, rt, leaf_origin,
+    hipLaunchKernelGGL((k_leaf_up<R, 1>), dim3(nleaf, 1), dim3(256), 0, s, X, ULt, mL, k, f, r, rt, leaf_origin,
                        leaf_pts, n, nleaf, nrhs, b, sb);
   else
-    hipLaunchKernelGGL((k_leaf_up<R, LEAF_NV>), dim3(nleaf, ng), dim3(256), 0, s, X, UL, mL, k, f, r, rt,
+    hipLaunchKernelGGL((k_leaf_up<R, LEAF_NV>), dim3(nleaf, ng), dim3(256), 0, s, X, ULt, mL, k, f, r, rt,
                        leaf_origin, leaf_pts, n, nleaf, nrhs, b, sb);
   LSH_LAUNCH_CHECK();
 }
@@ -1357,23 +1387,13 @@ __global__ __launch_bounds__(256) void k_leaf_down(const cplx<R>* __restrict__ X
   for (int v = 0; v < nv; ++v)
     for (int i = threadIdx.x; i < mL; i += blockDim.x) rl[v][i] = r[((r0 + v) * nleaf + t) * (long)mL + i];
   __syncthreads();
-  for (int i = threadIdx.x; i < mL; i += blockDim.x) {
-    cplx<R> acc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
-#pragma unroll 8
-    for (int a = 0; a < k; ++a) {  // (unrolled: the U_L loads issued together)
-      const cplx<R> u = UL[(long)i * k + a];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, ws[v][a]);
-    }
+  leaf_rows<R, NV>(UL, mL, k, ws, nv, [&](int i, int v, cplx<R> acc) {
     const I2 pi = pts[i];
-    const R bi = (R)(kappa2 * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) us[v][i] = bi * acc[v];
-  }
+    us[v][i] = (R)(kappa2 * b[(long)(o.y + pi.y) * n + (o.x + pi.x)]) * acc;
+  });
   __syncthreads();
-  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) { rl[v][i] = rl[v][i] - acc; });
+  leaf_rows<R, NV>(X + t * (long)mL * mL, mL, mL, us, nv,
+                   [&](int i, int v, cplx<R> acc) { rl[v][i] = rl[v][i] - acc; });
   __syncthreads();
   for (int v = 0; v < nv; ++v)
     for (int i = threadIdx.x; i < mL; i += blockDim.x) {
@@ -1415,28 +1435,14 @@ __global__ __launch_bounds__(256) void k_leaf_tdown(const cplx<R>* __restrict__ 
 #pragma unroll
     for (int v = 0; v < NV; ++v) ws[v][a] = v < nv ? w[((r0 + v) * nleaf + t) * (long)k + a] : mk<R>(0, 0);
   __syncthreads();
-  for (int i = threadIdx.x; i < mL; i += blockDim.x) {
-    cplx<R> acc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = mk<R>(0, 0);
-#pragma unroll 8
-    for (int a = 0; a < k; ++a) {  // (unrolled: the U_L loads issued together)
-      const cplx<R> u = UL[(long)i * k + a];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) fma_acc(acc[v], u, ws[v][a]);
-    }
+  leaf_rows<R, NV>(UL, mL, k, ws, nv, [&](int i, int v, cplx<R> acc) {
     const I2 pi = pts[i];
-    const long at = (long)(o.y + pi.y) * n + (o.x + pi.x);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      z64 gv = mk(0.0, 0.0);
-      if (v < nv) gv = g[(r0 + v) * (long)n * n + at];
-      us[v][i] = acc[v] + mk<R>((R)gv.x, (R)gv.y);
-    }
-  }
+    const z64 gv = g[(r0 + v) * (long)n * n + (long)(o.y + pi.y) * n + (o.x + pi.x)];
+    us[v][i] = acc + mk<R>((R)gv.x, (R)gv.y);
+  });
   __syncthreads();
   // (ws is free once us is built: it stages the results for one store pass)
-  leaf_rows<R, NV>(XT + t * (long)mL * mL, mL, us, nv, [&](int i, int v, cplx<R> acc) { ws[v][i] = acc; });
+  leaf_rows<R, NV>(XT + t * (long)mL * mL, mL, mL, us, nv, [&](int i, int v, cplx<R> acc) { ws[v][i] = acc; });
   __syncthreads();
   for (int v = 0; v < nv; ++v)
     for (int i = threadIdx.x; i < mL; i += blockDim.x) {

@@ -42,9 +42,10 @@ template <typename R>
 void leaf_scale_U(hipStream_t s, cplx<R>* Y, const cplx<R>* U, int mL, int k, const double* b, double kappa2,
                   const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n);
 
-// Apply, leaf level.  f, q: FP64 grid vectors [nrhs][n][n].
+// Apply, leaf level.  f, q: FP64 grid vectors [nrhs][n][n].  leaf_up takes
+// U_L transposed (ULt, k x mL); the others U_L (mL x k).
 template <typename R>
-void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k, const z64* f, cplx<R>* r,
+void leaf_up(hipStream_t s, const cplx<R>* X, const cplx<R>* ULt, int mL, int k, const z64* f, cplx<R>* r,
              cplx<R>* rt, const I2* leaf_origin, const I2* leaf_pts, int nleaf, int n, int nrhs,
              const double* b = nullptr, double sb = 0);
 // transpose pass, leaves: q = X^T (g + U_L w), XT = X transposed per leaf

@@ -1199,7 +1199,7 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
   cplx<R>* t1 = F.t1.template as<cplx<R>>();
   cplx<R>* t2 = F.t2.template as<cplx<R>>();
   cplx<R>* t3 = F.t3.template as<cplx<R>>();
-  leaf_up<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, f, r, F.rt[L].template as<cplx<R>>(),
+  leaf_up<R>(s, F.X.template as<cplx<R>>(), P.Ut<R>(L), P.mL, P.lev[L].k, f, r, F.rt[L].template as<cplx<R>>(),
              P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
   // upward pass
   for (int l = L - 1; l >= 1; --l) {
@@ -1251,7 +1251,7 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
   cplx<R>* t2 = F.t2.template as<cplx<R>>();
   cplx<R>* t3 = F.t3.template as<cplx<R>>();
   // leaves: wb_L = -U_L^T B X^T g
-  leaf_up<R>(s, F.XT.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, g, nullptr,
+  leaf_up<R>(s, F.XT.template as<cplx<R>>(), P.Ut<R>(L), P.mL, P.lev[L].k, g, nullptr,
              F.wt[L].template as<cplx<R>>(), P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs, b, -k2);
   // transposed downward pass, leaves upward
   for (int l = L - 1; l >= 1; --l) {
