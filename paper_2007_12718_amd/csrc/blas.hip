@@ -964,61 +964,74 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
 
 // ------------------------------------------------ shared-matrix multi-GEMV
 // Y[v] = alpha Mat X[v] + beta Z[v] for v < nvec and one shared matrix
-// (rows x C, row-major): the few-vector products of the preconditioner's top
-// levels (U_l, G_ab, [L^T; R^T], [L; R]), where the matrix is large and read
-// once.  A workgroup takes RR consecutive rows of one block (the rows from R1
-// on read X + xoff2: the two halves of Q v in one launch); its four waves
-// split the columns (wave w takes columns 64(w + 4q) + lane, two chunks per
-// step), so each loaded piece of x serves RR rows and a lane keeps
-// 2 (RR + NV) loads in flight.  Sums in a fixed order: per lane over its
-// chunks, a butterfly over the wave's lanes, then the four waves in order.
-template <typename R, int RR, int NV>
+// (rows x C, row-major): the preconditioner's shared box products (U_l,
+// G_ab, [L^T; R^T], [L; R]) for up to a thousand box vectors.  A workgroup
+// takes a block of rows of one block of Mat (the rows from R1 on read
+// X + xoff2: the two halves of Q v in one launch) and NV vectors (grid y
+// runs over the groups of NV).  WS = 4 (long rows): the four waves split the
+// columns of RR rows (wave w takes columns 64(w + 4q) + lane, two chunks per
+// step) and meet in LDS; WS = 1 (rows under 1024): each wave takes RR rows of
+// its own over all columns.  Each loaded piece of x serves RR rows, and a
+// lane keeps 2 (RR + NV) loads in flight.  Sums in a fixed order: per lane
+// over its chunks, a butterfly over the wave's lanes, then (WS = 4) the
+// waves in order.
+template <typename R, int RR, int NV, int WS>
 __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, cplx<R> alpha,
                                                 const cplx<R>* __restrict__ Mat, long ldm,
                                                 const cplx<R>* __restrict__ X, long ldx, long xoff2, cplx<R> beta,
                                                 const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
-  __shared__ cplx<R> red[4][RR * NV];
+  constexpr int ROWS = WS == 4 ? RR : 4 * RR;  // rows per workgroup
+  __shared__ cplx<R> red[WS == 4 ? 4 : 1][RR * NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int i0, iend;
   const cplx<R>* Xb = X;
   if ((int)blockIdx.x < wg1) {
-    i0 = blockIdx.x * RR;
+    i0 = blockIdx.x * ROWS;
     iend = R1;
   } else {
-    i0 = R1 + (blockIdx.x - wg1) * RR;
+    i0 = R1 + (blockIdx.x - wg1) * ROWS;
     iend = Rr;
     Xb = X + xoff2;
   }
-  const int nr = iend - i0 < RR ? iend - i0 : RR;
+  if (WS == 1) i0 += wave * RR;
+  const int nr = iend - i0 < RR ? iend - i0 : RR;  // (<= 0: this wave has no rows)
+  const int v0 = blockIdx.y * NV;
+  const int nv = nvec - v0 < NV ? nvec - v0 : NV;
   const cplx<R>* row0 = Mat + (long)i0 * ldm;
-  for (int v0 = 0; v0 < nvec; v0 += NV) {
-    const int nv = nvec - v0 < NV ? nvec - v0 : NV;
-    const cplx<R>* xv = Xb + (long)v0 * ldx;
-    cplx<R> acc[RR][NV];
+  const cplx<R>* xv = Xb + (long)v0 * ldx;
+  cplx<R> acc[RR][NV];
 #pragma unroll
-    for (int r = 0; r < RR; ++r)
+  for (int r = 0; r < RR; ++r)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[r][v] = mk<R>(0, 0);
-    for (int j = wave * 64 + lane; j < C; j += 512) {
-      const int j2 = j + 256;
-      cplx<R> a[2][RR], x[2][NV];
+    for (int v = 0; v < NV; ++v) acc[r][v] = mk<R>(0, 0);
+  constexpr int STEP = 64 * WS;  // columns per chunk
+  for (int j = (WS == 4 ? wave * 64 : 0) + lane; j < C && nr > 0; j += 2 * STEP) {
+    const int j2 = j + STEP;
+    cplx<R> a[2][RR], x[2][NV];
 #pragma unroll
-      for (int r = 0; r < RR; ++r) {
-        a[0][r] = r < nr ? row0[(long)r * ldm + j] : mk<R>(0, 0);
-        a[1][r] = (r < nr && j2 < C) ? row0[(long)r * ldm + j2] : mk<R>(0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        x[0][v] = v < nv ? xv[(long)v * ldx + j] : mk<R>(0, 0);
-        x[1][v] = (v < nv && j2 < C) ? xv[(long)v * ldx + j2] : mk<R>(0, 0);
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int r = 0; r < RR; ++r)
-#pragma unroll
-          for (int v = 0; v < NV; ++v) fma_acc(acc[r][v], a[h][r], x[h][v]);
+    for (int r = 0; r < RR; ++r) {
+      a[0][r] = r < nr ? row0[(long)r * ldm + j] : mk<R>(0, 0);
+      a[1][r] = (r < nr && j2 < C) ? row0[(long)r * ldm + j2] : mk<R>(0, 0);
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      x[0][v] = v < nv ? xv[(long)v * ldx + j] : mk<R>(0, 0);
+      x[1][v] = (v < nv && j2 < C) ? xv[(long)v * ldx + j2] : mk<R>(0, 0);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fma_acc(acc[r][v], a[h][r], x[h][v]);
+  }
+  auto store = [&](int r, int v, cplx<R> t) {
+    const long yi = (long)(v0 + v);
+    cplx<R> o = alpha * t;
+    if (Z && (beta.x != R(0) || beta.y != R(0))) o = o + beta * Z[yi * ldz + i0 + r];
+    Y[yi * ldy + i0 + r] = o;
+  };
+  if (WS == 1) {
 #pragma unroll
     for (int r = 0; r < RR; ++r)
 #pragma unroll
@@ -1026,30 +1039,38 @@ __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, 
         cplx<R> t = acc[r][v];
         t.x = group_sum<64>(t.x);
         t.y = group_sum<64>(t.y);
-        if (lane == 0) red[wave][r * NV + v] = t;
+        if (lane == 0 && r < nr && v < nv) store(r, v, t);
       }
-    __syncthreads();
-    if (threadIdx.x < RR * NV) {
-      const int r = threadIdx.x / NV, v = threadIdx.x % NV;
-      if (r < nr && v < nv) {
-        const cplx<R> t = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
-        const long yi = (long)(v0 + v);
-        cplx<R> o = alpha * t;
-        if (Z && (beta.x != R(0) || beta.y != R(0))) o = o + beta * Z[yi * ldz + i0 + r];
-        Y[yi * ldy + i0 + r] = o;
-      }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < RR; ++r)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      cplx<R> t = acc[r][v];
+      t.x = group_sum<64>(t.x);
+      t.y = group_sum<64>(t.y);
+      if (lane == 0) red[WS == 4 ? wave : 0][r * NV + v] = t;
     }
-    __syncthreads();
+  __syncthreads();
+  if (threadIdx.x < RR * NV) {
+    const int r = threadIdx.x / NV, v = threadIdx.x % NV;
+    if (r < nr && v < nv) {
+      const int e = threadIdx.x, w3 = WS == 4 ? 3 : 0, w2 = WS == 4 ? 2 : 0, w1 = WS == 4 ? 1 : 0;
+      store(r, v, (red[0][e] + red[w1][e]) + (red[w2][e] + red[w3][e]));
+    }
   }
 }
 
-template <typename R, int RR, int NV>
+template <typename R, int RR, int NV, int WS>
 static void cmgemv_launch(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat,
                           long ldm, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y,
                           long ldy, int nvec) {
-  const int wg1 = ceil_div(R1, RR), wg2 = ceil_div(Rr - R1, RR);
-  hipLaunchKernelGGL((k_cmgemv<R, RR, NV>), dim3(wg1 + wg2), dim3(256), 0, s, Rr, R1, wg1, C, alpha, Mat, ldm, X,
-                     ldx, xoff2, beta, Z, ldz, Y, ldy, nvec);
+  constexpr int ROWS = WS == 4 ? RR : 4 * RR;
+  const int wg1 = ceil_div(R1, ROWS), wg2 = ceil_div(Rr - R1, ROWS);
+  LSH_REQUIRE(ceil_div(nvec, NV) <= 65535, -6, "cmgemv: too many vectors");
+  hipLaunchKernelGGL((k_cmgemv<R, RR, NV, WS>), dim3(wg1 + wg2, ceil_div(nvec, NV)), dim3(256), 0, s, Rr, R1, wg1,
+                     C, alpha, Mat, ldm, X, ldx, xoff2, beta, Z, ldz, Y, ldy, nvec);
 }
 
 template <typename R>
@@ -1061,10 +1082,20 @@ void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, co
                (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * ((R1 < Rr ? 2.0 : 1.0) * C +
                                                                           (Z ? 2.0 : 1.0) * Rr)));
   constexpr int RR = sizeof(R) == 4 ? 4 : 2;  // (FP64: the accumulators in half the rows)
-  if (nvec == 1) cmgemv_launch<R, RR, 1>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
-  else if (nvec == 2) cmgemv_launch<R, RR, 2>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
-  else if (nvec <= 4) cmgemv_launch<R, RR, 4>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
-  else cmgemv_launch<R, RR, 8>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
+#define LSH_MG(NVV, WSS) \
+  cmgemv_launch<R, RR, NVV, WSS>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec)
+  if (C >= 1024) {
+    if (nvec == 1) LSH_MG(1, 4);
+    else if (nvec == 2) LSH_MG(2, 4);
+    else if (nvec <= 4) LSH_MG(4, 4);
+    else LSH_MG(8, 4);
+  } else {
+    if (nvec == 1) LSH_MG(1, 1);
+    else if (nvec == 2) LSH_MG(2, 1);
+    else if (nvec <= 4) LSH_MG(4, 1);
+    else LSH_MG(8, 1);
+  }
+#undef LSH_MG
   LSH_LAUNCH_CHECK();
 }
 

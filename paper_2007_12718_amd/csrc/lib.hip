@@ -1067,12 +1067,12 @@ void factor_build(const lsh_plan_s& P, const double* b, FactorData<R>& F, hipStr
 }
 
 // up to this many box vectors the shared products stream the matrix rows
-// (multi-vector GEMV); above it they are MFMA GEMMs, split along K when they
-// have few output tiles (FP32).  fourier-1024, one FP32 apply: 3.81 ms with
-// 64, 3.58 with 32, 3.50 with 16, 3.50 with 8, 3.48 with 4, 3.54 with 2.  The
-// FP64 products do not split, and stay on the GEMV up to 64 vectors.
+// (multi-vector GEMV over vector groups); above it they are MFMA GEMMs,
+// split along K when they have few output tiles (FP32).  fourier-1024, one
+// apply, with 8 / 64 / 256 / 1024 / 8192: FP32 2.62 / 2.64 / 2.61 / 2.61 /
+// 2.86 ms, FP64 7.14 / 4.40 / 3.69 / 3.45 / 3.76 ms.
 template <typename R>
-constexpr int skinny() { return sizeof(R) == 4 ? 8 : 64; }
+constexpr int skinny() { return 1024; }
 
 // Y[v] = alpha M X[v] + beta Z[v] for B vectors (strides ldx, ldz, ldy) and
 // one shared matrix M (rows x cols, row-major); (MtB, ldb, opB) give M^T as
