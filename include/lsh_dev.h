@@ -72,7 +72,8 @@ int lsh_dev_inverse_static(int prec, void* A, int c, long lda, long sA, int batc
  * adds the file's entries; *entries = their count).
  * lsh_gemm_record(1) starts recording the (precision, M, N, K, batch) of
  * every product (precision 1 = FP32, 0 = FP64); lsh_gemm_recorded returns
- * them (host int[5 * cap]).
+ * the distinct shapes with the number of products of each (host int[6 * cap]:
+ * precision, M, N, K, batch, count).
  * lsh_gemm_force_variant(v): this host thread's products use variant v
  * (-1: the table or model). */
 int lsh_gemm_variants(int prec, int* count, char* names, int cap);

@@ -538,7 +538,7 @@ std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
 thread_local int g_forced_variant = -1;  // (the tuner's timing runs)
 bool g_record = false;
-std::set<std::array<int, 5>> g_recorded;
+std::map<std::array<int, 5>, int> g_recorded;  // shape -> number of products
 
 int half_octave(long x) { return x <= 1 ? 0 : (int)std::lround(2.0 * std::log2((double)x)); }
 TuneKey tune_key(int prec, int M, int N, int K, int batch) {
@@ -556,7 +556,7 @@ static int choose_variant(int prec, int M, int N, int K, int batch) {
   if (env >= 0 && env < nv) return env;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    if (g_record) g_recorded.insert({prec, M, N, K, batch});
+    if (g_record) ++g_recorded[{prec, M, N, K, batch}];
     auto it = g_tune.find(tune_key(prec, M, N, K, batch));
     if (it != g_tune.end() && it->second < nv) return it->second;
   }
@@ -613,9 +613,11 @@ void gemm_record(bool on) {
   if (on) g_recorded.clear();
 }
 
-std::vector<std::array<int, 5>> gemm_recorded() {
+std::vector<std::array<int, 6>> gemm_recorded() {
   std::lock_guard<std::mutex> g(g_tune_mu);
-  return std::vector<std::array<int, 5>>(g_recorded.begin(), g_recorded.end());
+  std::vector<std::array<int, 6>> v;
+  for (auto& kv : g_recorded) v.push_back({kv.first[0], kv.first[1], kv.first[2], kv.first[3], kv.first[4], kv.second});
+  return v;
 }
 
 template <typename R>

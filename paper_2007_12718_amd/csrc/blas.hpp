@@ -93,7 +93,7 @@ void gemm_table_clear();
 void gemm_table_save(const char* path);
 int gemm_table_load(const char* path);
 void gemm_record(bool on);  // record the (prec, M, N, K, batch) of every product
-std::vector<std::array<int, 5>> gemm_recorded();
+std::vector<std::array<int, 6>> gemm_recorded();
 
 // In-place inverse of each c x c matrix by Gauss-Jordan elimination with
 // partial (row) pivoting.  ws must hold inverse_ws_bytes(c, batch) bytes.

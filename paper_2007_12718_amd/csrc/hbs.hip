@@ -38,6 +38,58 @@ void gather_table(hipStream_t s, const z64* T, int D, const I2* rows, int m, con
   }
 }
 
+// rows r in [r0, r1) of the parent's proxy matrix, interleaved (r = 2q + c:
+// pivot q of this level in child c): out[r][j] = T(point - prox[j]) (and
+// T2 at column np + j), point = cand[J[q]] + off[c]
+__global__ void k_next_gram_rows(const z64* __restrict__ T, const z64* __restrict__ T2, int D,
+                                 const I2* __restrict__ cand, const int* __restrict__ J, I2 off0, I2 off1,
+                                 const I2* __restrict__ prox, int np, int r0, z64* out, long ld) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = r0 + blockIdx.y;
+  if (j >= np) return;
+  const I2 c = cand[J[r >> 1]], o = (r & 1) ? off1 : off0;
+  int dx = c.x + o.x - prox[j].x, dy = c.y + o.y - prox[j].y;
+  dx = dx < 0 ? -dx : dx;
+  dy = dy < 0 ? -dy : dy;
+  const long t = (long)dy * (D + 1) + dx;
+  out[(long)r * ld + j] = T[t];
+  if (T2) out[(long)r * ld + np + j] = T2[t];
+}
+
+// M[c k + q][c' k + q'] from the interleaved rows r = 2q + c, r' = 2q' + c'
+// (entry (r, r') stored when r >= r'; else the conjugate of (r', r))
+__global__ void k_next_gram_pack(const z64* __restrict__ G, long ldg, int k, z64* M) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long m = 2L * k;
+  if (e >= m * m) return;
+  const int i = (int)(e / m), jj = (int)(e - (long)i * m);
+  const int ci = i >= k, qi = i - ci * k, cj = jj >= k, qj = jj - cj * k;
+  const long r = 2L * qi + ci, rr = 2L * qj + cj;
+  M[e] = r >= rr ? G[r * ldg + rr] : conjg(G[rr * ldg + r]);
+}
+
+void next_gram_rows(NextGram& g, const int* J, int j) {
+  if (j > g.cap) j = g.cap;
+  if (j <= g.done) return;
+  const int r0 = 2 * g.done, nr = 2 * (j - g.done);
+  for (int a = 0; a < nr; a += 65535) {
+    const int rows = nr - a < 65535 ? nr - a : 65535;
+    hipLaunchKernelGGL(k_next_gram_rows, dim3(ceil_div(g.np, 256), rows), dim3(256), 0, g.gs, g.T, g.T2, g.D,
+                       g.cand, J, g.off[0], g.off[1], g.prox, g.np, r0 + a, g.A, (long)g.ncols);
+    LSH_LAUNCH_CHECK();
+  }
+  // G rows [r0, 2 j), columns [0, 2 j): the new rows against every row so far
+  cgemm<double>(g.gs, nr, 2 * j, g.ncols, mk(1.0, 0.0), g.A + (long)r0 * g.ncols, g.ncols, 0, OP_N, g.A, g.ncols, 0,
+                OP_C, mk(0.0, 0.0), nullptr, 0, 0, g.G + (long)r0 * 2 * g.cap, 2L * g.cap, 0, 1);
+  g.done = j;
+}
+
+void next_gram_pack(hipStream_t s, const NextGram& g, int k, z64* M) {
+  const long mm = 4L * k * k;
+  hipLaunchKernelGGL(k_next_gram_pack, dim3(ceil_div(mm, 256L)), dim3(256), 0, s, g.G, 2L * g.cap, k, M);
+  LSH_LAUNCH_CHECK();
+}
+
 __device__ __forceinline__ void wave_argmax_d(double& v, int& idx) {
   for (int off = 32; off > 0; off >>= 1) {
     double ov = __shfl_xor(v, off);
@@ -1002,7 +1054,8 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
   LSH_LAUNCH_CHECK();
 }
 
-int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws) {
+int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws,
+             bool gram_ready, NextGram* next) {
   LSH_REQUIRE(alpha > 0.0 && alpha <= 1.0, -1, "row ID: alpha must lie in (0, 1]");
   LSH_REQUIRE(m <= BP_SEL, -6, "row ID: more than 16384 candidate rows in one level");
   char* p = static_cast<char*>(ws);
@@ -1026,9 +1079,11 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
   z64* Dinv = static_cast<z64*>(take(sizeof(z64) * (size_t)(m / DB + 1) * DB * DB));
   void* invws = take(inverse_ws_bytes<double>(DB, m / DB + 1));
   // Gram matrix and its diagonal; the factor starts at zero
-  cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0, 1,
-                false, nullptr, true);  // Hermitian: lower tiles, then the mirror
-  mirror_lower<double>(s, M, m, m);
+  if (!gram_ready) {
+    cgemm<double>(s, m, m, np, mk(1.0, 0.0), A, np, 0, OP_N, A, np, 0, OP_C, mk(0.0, 0.0), nullptr, 0, 0, M, m, 0,
+                  1, false, nullptr, true);  // Hermitian: lower tiles, then the mirror
+    mirror_lower<double>(s, M, m, m);
+  }
   fill_zero(s, Lt, sizeof(z64) * mp * m);
   fill_zero(s, st, sizeof(int) * BPS_WORDS);
   hipLaunchKernelGGL(k_gram_init, dim3(ceil_div(m, 256)), dim3(256), 0, s, M, m, d, chosen, st + BPS_WORDS - 4);
@@ -1037,8 +1092,11 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
   LSH_LAUNCH_CHECK();
   const int gm = ceil_div(m, 256);
   // steps in batches; the first batches are short (the first step alone
-  // can take every pivot of a small block)
-  int batch = 4, host_st[2] = {0, 0};
+  // can take every pivot of a small block).  With a parent Gram to feed, at
+  // most 16 steps a batch, so that its last rows (after the final step) are
+  // few.
+  int batch = 4, host_st[4] = {0, 0, 0, 0};
+  const int max_batch = next ? 16 : 32;
   while (true) {
     for (int b = 0; b < batch; ++b) {
       {
@@ -1066,10 +1124,11 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
                          chosen, d, st);
       LSH_LAUNCH_CHECK();
     }
-    LSH_HIP(hipMemcpyAsync(host_st, st, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipMemcpyAsync(host_st, st, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
     LSH_HIP(hipStreamSynchronize(s));
     if (host_st[BPS_DONE]) break;
-    batch = batch < 32 ? batch * 2 : 32;
+    if (next) next_gram_rows(*next, J, host_st[BPS_J] + host_st[BPS_NP]);
+    batch = batch < max_batch ? batch * 2 : max_batch;
   }
   int j = 0;
   {
@@ -1086,8 +1145,10 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
     fill_zero(s, U, sizeof(z64) * (size_t)m);
     LSH_HIP(hipMemcpyAsync(U, &one, sizeof(z64), hipMemcpyHostToDevice, s));
     LSH_HIP(hipStreamSynchronize(s));
+    if (next) next_gram_rows(*next, J, 1);
     return 1;
   }
+  if (next) next_gram_rows(*next, J, j);  // (J is final: the stream was synchronised)
   // (the Gram is no longer needed: it holds L11^{-1}; the pairs' temporaries
   // follow the rest rows in Lr)
   gram_interp(s, Lt, m, j, J, U, rest, L11, Lr, Dinv, M, Lr + (size_t)(m - j) * j);

@@ -27,11 +27,45 @@ size_t rowid_cpqr_ws(int m);
 int rowid_gram(hipStream_t s, const z64* A, int m, int np, double tol, int* J, z64* U, void* ws);
 size_t rowid_gram_ws(int m);
 
+// The parent level's Gram matrix, built while this level's row ID finds its
+// pivots.  The parent's candidate rows are this level's skeleton points in
+// its two children (child c, pivot q); its proxy matrix rows hold the table
+// entries between such a point and the parent's proxy points (order 4:
+// T; order p > 4: T | T2).  Rows are stored interleaved (2q + c) as the
+// pivots appear, and after each batch of pivot steps the new rows' products
+// with every row so far fill the Gram rows 2q + c (columns up to the pivots
+// so far), on the side stream gs: the same products as the whole Gram, done
+// while the pivot steps run instead of after them.
+struct NextGram {
+  int cap = 0;                      // capacity in pivots (this level's candidate count)
+  int np = 0, ncols = 0, D = 0;     // proxy points; columns (np, or 2 np with T2)
+  const z64* T = nullptr;
+  const z64* T2 = nullptr;
+  const I2* cand = nullptr;         // this level's candidates (device, box-local)
+  const I2* prox = nullptr;         // the parent's proxy points (device)
+  I2 off[2] = {{0, 0}, {0, 0}};     // the children's origins in the parent box
+  z64* A = nullptr;                 // [2 cap][ncols]
+  z64* G = nullptr;                 // [2 cap][2 cap]
+  hipStream_t gs = nullptr;
+  int done = 0;                     // pivots whose rows are in
+};
+// rows and Gram rows of pivots [g.done, j) (J: this level's pivots, device;
+// final on the device when called); launches on g.gs
+void next_gram_rows(NextGram& g, const int* J, int j);
+// M (2k x 2k, order c k + q) from the interleaved Gram rows of k pivots on s:
+// entry (r, r') of the interleaved order read from row max(r, r'), so M is
+// exactly Hermitian
+void next_gram_pack(hipStream_t s, const NextGram& g, int k, z64* M);
+
 // Gram path with block pivoting (left-looking, up to 32 pivots per step,
 // chosen among the 48 largest Schur diagonals only while they remain the
 // greedy choice over all rows): the greedy pivots and stopping rule.
-// Returns the rank (synchronises on the stream once per step).
-int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws);
+// gram_ready: the Gram matrix is already in the workspace (its first m x m
+// entries, from next_gram_pack; A unused).  next (or null): the parent
+// level's Gram rows, fed after each batch of steps and at the end.
+// Returns the rank (synchronises on the stream once per batch of steps).
+int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws,
+             bool gram_ready = false, NextGram* next = nullptr);
 size_t rowid_bp_ws(int m);
 
 // Leaf factor helpers (R = working precision)

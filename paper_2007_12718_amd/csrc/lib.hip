@@ -15,6 +15,7 @@
 #include <condition_variable>
 #include <deque>
 #include <exception>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -80,8 +81,16 @@ struct lsh_plan_s {
   // Device memory, all from the caller's plan workspace: persist holds what
   // the plan keeps; sid and ssib hold the temporaries of the level row IDs
   // and of the sibling blocks (the two plan threads of lsh_build), each
-  // rewound at the start of its next level, after a stream synchronisation.
-  mem::Arena persist, sid, ssib;
+  // rewound at the start of its next level, after a stream synchronisation;
+  // sgram holds the parent level's Gram rows built during a level's row ID
+  // (rewound once they are packed into the parent's row-ID workspace).
+  mem::Arena persist, sid, ssib, sgram;
+  // side stream for the parent Gram rows while a plan is built (null: the
+  // Gram of each level is formed after its candidates are known)
+  hipStream_t gs = nullptr;
+  NextGram ng;          // the parent Gram in progress or done
+  int ng_level = -1;    // the level whose Gram ng holds (-1: none)
+  std::vector<I2> ng_prox;  // (host source of its proxy upload)
   ConvOperator op;
   std::vector<StencilEntry> st4;
   double tau0_re = 0, tau0_im = 0;
@@ -194,8 +203,12 @@ void validate(const lsh_desc& d) {
 // Row ID A ~= U A[J, :] of a device matrix A (m x np, FP64; overwritten) at
 // the plan's tolerance: J to the host, U (m x k) to a new buffer of the
 // bound arena, temporaries from scr; returns k.  Synchronises s.
+//
+// gram (block-pivoted path only): called with the row-ID workspace's Gram
+// block before the pivot steps; it may fill that block (ready = true: A is
+// then unused) and return the parent level's Gram rows to feed (or null).
 int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64, mem::Arena& scr,
-                  hipStream_t s) {
+                  hipStream_t s, const std::function<NextGram*(z64*, bool&)>& gram = {}) {
   if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all rows
     Jh.resize(m);
     for (int i = 0; i < m; ++i) Jh[i] = i;
@@ -234,8 +247,13 @@ int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, De
     const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
     if (!block)
       k = rowid_gram(s, A, m, np, P.d.tol, J, Ufull, scr.take(rowid_gram_ws(m)));
-    else
-      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, scr.take(rowid_bp_ws(m)));
+    else {
+      // (the Gram matrix is the first m x m block of the workspace)
+      void* ws = scr.take(rowid_bp_ws(m));
+      bool ready = false;
+      NextGram* next = gram ? gram(static_cast<z64*>(ws), ready) : nullptr;
+      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, ws, ready, next);
+    }
   }
   Jh.resize(k);
   LSH_HIP(hipMemcpyAsync(Jh.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
@@ -267,7 +285,22 @@ pcache::Key cache_key(const lsh_plan_s& P, int kind, int sx, int sy) {
 }
 
 // Row ID of the level's proxy matrix (FP64); fills lv.J (host) and lv.U64.
-void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
+// Levels with at least this many candidates build their parent's Gram rows
+// during their row ID (below it the parent's Gram is cheap).
+constexpr int kNextGramMin = 256;
+
+// The block-pivoted Gram row ID is in use (not CPQR, not the one-pivot panels).
+bool block_pivots(const lsh_plan_s& P) {
+  if (P.d.tol == 0 || P.d.tol < 1e-7) return false;
+  const char* e = std::getenv("LSH_ROWID");
+  return !(e && std::string(e) == "panel");
+}
+
+// Row ID of level l (candidates lv.cand, proxy ring prox).  With a side
+// stream, the Gram of level l (built during the row ID of level l + 1) is
+// packed instead of formed here, and the rows of level l - 1's Gram are
+// built while this row ID runs.
+void level_id(lsh_plan_s& P, int l, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
   const int m = lv.m, np = (int)prox.size();
   if (P.d.tol == 0) {
     lv.k = row_id_matrix(P, nullptr, m, np, lv.J, lv.U64, P.sid, s);
@@ -278,21 +311,54 @@ void level_id(lsh_plan_s& P, Level& lv, const std::vector<I2>& prox, hipStream_t
     key = cache_key(P, 0, lv.sx, lv.sy);
     if (pcache::find(key, lv.cand, lv.J, lv.k, lv.U64, s)) return;
   }
+  const bool block = block_pivots(P);
+  const bool pre = block && P.gs && P.ng_level == l && P.ng.done * 2 == m;
   const I2* dc = upload_to(P.sid, lv.cand, s);
-  const I2* dp = upload_to(P.sid, prox, s);
-  if (P.hbs_order == 4) {
-    z64* A = static_cast<z64*>(P.sid.take(sizeof(z64) * (size_t)m * np));
-    gather_table(s, P.table.as<z64>(), P.D, dc, m, dp, np, A, np);
-    lv.k = row_id_matrix(P, A, m, np, lv.J, lv.U64, P.sid, s);
-  } else {
+  const int ncols = P.hbs_order == 4 ? np : 2 * np;
+  z64* A = nullptr;
+  if (!pre) {
+    const I2* dp = upload_to(P.sid, prox, s);
+    A = static_cast<z64*>(P.sid.take(sizeof(z64) * (size_t)m * ncols));
+    gather_table(s, P.table.as<z64>(), P.D, dc, m, dp, np, A, ncols);
     // order > 4: the rows must also span the corrected entries against the
-    // ring's points (the actual near neighbours, within the stencil's reach),
-    // beside plain G on the ring (the representation of everything farther)
-    z64* A = static_cast<z64*>(P.sid.take(sizeof(z64) * (size_t)m * 2 * np));
-    gather_table(s, P.table.as<z64>(), P.D, dc, m, dp, np, A, 2 * np);
-    gather_table(s, P.hbs_table(), P.D, dc, m, dp, np, A + np, 2 * np);
-    lv.k = row_id_matrix(P, A, m, 2 * np, lv.J, lv.U64, P.sid, s);
+    // ring's points (the actual near neighbours, within the stencil's
+    // reach), beside plain G on the ring (the representation of everything
+    // farther)
+    if (P.hbs_order > 4) gather_table(s, P.hbs_table(), P.D, dc, m, dp, np, A + np, ncols);
   }
+  auto gram = [&](z64* M, bool& ready) -> NextGram* {
+    if (pre) {  // (the side stream was synchronised at the start of this level)
+      next_gram_pack(s, P.ng, m / 2, M);
+      ready = true;
+    }
+    P.ng_level = -1;
+    if (!(block && P.gs && l >= 2 && m >= kNextGramMin && !P.d.plan_cache)) return nullptr;
+    // the parent level l - 1: its box, the children's origins in it, its ring
+    P.sgram.reset(0);  // (after the pack above, on s; the new rows start after a sync of s)
+    int ox, oy, psx, psy, cx, cy, csx, csy;
+    box_of(P.d.n, l - 1, 0, ox, oy, psx, psy);
+    NextGram& g = P.ng;
+    g = NextGram();
+    for (int c = 0; c < 2; ++c) {
+      box_of(P.d.n, l, c, cx, cy, csx, csy);
+      g.off[c] = I2{cx - ox, cy - oy};
+    }
+    P.ng_prox = proxy_ring(psx, psy, P.d.proxy_width);
+    g.cap = m;
+    g.np = (int)P.ng_prox.size();
+    g.ncols = P.hbs_order == 4 ? g.np : 2 * g.np;
+    g.D = P.D;
+    g.T = P.table.as<z64>();
+    g.T2 = P.hbs_order > 4 ? P.hbs_table() : nullptr;
+    g.cand = dc;
+    g.prox = upload_to(P.sgram, P.ng_prox, s);
+    g.A = static_cast<z64*>(P.sgram.take(sizeof(z64) * 2 * (size_t)m * g.ncols));
+    g.G = static_cast<z64*>(P.sgram.take(sizeof(z64) * 4 * (size_t)m * m));
+    g.gs = P.gs;
+    P.ng_level = l - 1;
+    return &g;
+  };
+  lv.k = row_id_matrix(P, A, m, ncols, lv.J, lv.U64, P.sid, s, block ? gram : std::function<NextGram*(z64*, bool&)>());
   if (P.d.plan_cache) pcache::insert(key, lv.cand, lv.J, m, lv.k, lv.U64, s);
 }
 
@@ -361,6 +427,7 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
   const bool f32 = d.hbs_prec == LSH_FP32;
   if (l >= 1) {  // row ID of level l (Sec. 3.2)
     LSH_HIP(hipStreamSynchronize(s));
+    if (P.gs) LSH_HIP(hipStreamSynchronize(P.gs));  // (this level's Gram rows, read from the previous sid)
     P.sid.reset(0);  // (the previous level's temporaries are no longer in use)
     Level& lv = P.lev[l];
     if (l == P.L) {
@@ -377,7 +444,7 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
       }
     }
     lv.m = (int)lv.cand.size();
-    level_id(P, lv, proxy_ring(lv.sx, lv.sy, d.proxy_width), s);
+    level_id(P, l, lv, proxy_ring(lv.sx, lv.sy, d.proxy_width), s);
     lv.Ut64.alloc(sizeof(z64) * (size_t)lv.m * lv.k);
     ctranspose<double>(s, lv.U64.as<z64>(), lv.m, lv.k, lv.Ut64.as<z64>());
     if (f32) {
@@ -515,8 +582,8 @@ void plan_build(lsh_plan_s& P, hipStream_t s) {
 // the factor's size is exact; so is the solve's.
 
 struct PlanBytes {
-  size_t persist = 0, sid = 0, ssib = 0;
-  size_t total() const { return persist + sid + ssib; }
+  size_t persist = 0, sid = 0, ssib = 0, sgram = 0;
+  size_t total() const { return persist + sid + ssib + sgram; }
 };
 
 // Per-level sizes that the factor's memory depends on: ranks k, merge
@@ -568,7 +635,7 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
   z.add_n<I2>(mL);                                              // leaf_pts
   z.add_n<z64>((size_t)mL * mL);                                // Gleaf64
   if (f32) z.add(e * mL * mL);                                  // Gleaf32
-  size_t sid = mem::round_up(4096) + ConvOperator::scratch_bytes(), ssib = 0;
+  size_t sid = mem::round_up(4096) + ConvOperator::scratch_bytes(), ssib = 0, sgram = 0;
   for (int l = 1; l <= L; ++l) {
     const size_t mk = (size_t)m[l] * k[l];
     z.add_n<z64>(mk);  // U64
@@ -580,6 +647,15 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
     t.add_n<I2>(np[l]);
     if (d.tol > 0) t.add_n<z64>((size_t)m[l] * ncols);
     sid = std::max(sid, t.total + rowid_scratch_bytes(m[l], d.tol));
+    // the parent's Gram rows, built during this row ID (level_id)
+    if (d.tol >= 1e-7 && !d.plan_cache && l >= 2 && m[l] >= kNextGramMin) {
+      const long pcols = (horder > 4 ? 2 : 1) * np[l - 1];
+      mem::Sizer g;
+      g.add_n<I2>(np[l - 1]);
+      g.add_n<z64>(2 * (size_t)m[l] * pcols);
+      g.add_n<z64>(4 * (size_t)m[l] * m[l]);
+      sgram = std::max(sgram, g.total);
+    }
   }
   for (int l = 0; l < L; ++l) {
     // r <= c; AUTO keeps the low-rank factors only where 10 r <= 6 c
@@ -607,6 +683,7 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
   b.persist = z.total;
   b.sid = sid;
   b.ssib = ssib;
+  b.sgram = sgram;
   if (prof) {
     Profile& P = *prof;
     P.N = (long)d.n * d.n;
@@ -1738,10 +1815,11 @@ void attach_plan(lsh_plan_s& P, void* ws, size_t bytes) {
   const PlanBytes b = plan_bytes(P.d, nullptr);
   check_ws(ws, bytes, b.total(), "plan");
   char* p = static_cast<char*>(ws);
-  const size_t keep = bytes - b.sid - b.ssib;
+  const size_t keep = bytes - b.sid - b.ssib - b.sgram;
   P.persist.attach(p, keep, "plan");
   P.sid.attach(p + keep, b.sid, "plan row-ID temporaries");
   P.ssib.attach(p + keep + b.sid, b.ssib, "plan sibling-block temporaries");
+  P.sgram.attach(p + keep + b.sid + b.ssib, b.sgram, "plan parent Gram rows");
 }
 
 // The same for a factor, sized by the rank profile f.
@@ -1801,6 +1879,79 @@ int report_other_failure(const std::exception& e) {
   return LSH_ERR_HIP;
 }
 }  // namespace lsh
+
+namespace {
+// Streams and events of lsh_build, kept for the process (per device and CU
+// reserve) and handed to one build at a time.
+struct BuildStreams {
+  int dev = 0, reserve = 0;
+  hipStream_t ps = nullptr, ps2 = nullptr, fsm = nullptr, pg = nullptr;  // pg: the parent Gram rows
+  std::vector<hipEvent_t> ev;
+  void events(size_t n) {
+    while (ev.size() < n) {
+      hipEvent_t e = nullptr;
+      LSH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ev.push_back(e);
+    }
+  }
+  // (never destroyed: the exit handler below still uses them)
+  static std::mutex& mu() {
+    static std::mutex* m = new std::mutex;
+    return *m;
+  }
+  static std::vector<BuildStreams*>& pool() {
+    static std::vector<BuildStreams*>* p = new std::vector<BuildStreams*>;
+    return *p;
+  }
+  // destroys the pooled streams and events at process exit, before the
+  // runtime's own teardown (a handler registered after the runtime started)
+  static void destroy_all() {
+    std::lock_guard<std::mutex> g(mu());
+    for (BuildStreams* b : pool()) {
+      for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+      for (hipStream_t st : {b->ps, b->ps2, b->fsm, b->pg})
+        if (st) (void)hipStreamDestroy(st);
+      delete b;
+    }
+    pool().clear();
+  }
+  static BuildStreams* acquire(int dev, int reserve) {
+    static const bool registered = [] { return std::atexit(destroy_all) == 0; }();
+    (void)registered;
+    {
+      std::lock_guard<std::mutex> g(mu());
+      auto& p = pool();
+      for (size_t i = 0; i < p.size(); ++i)
+        if (p[i]->dev == dev && p[i]->reserve == reserve) {
+          BuildStreams* b = p[i];
+          p.erase(p.begin() + i);
+          return b;
+        }
+    }
+    std::unique_ptr<BuildStreams> b(new BuildStreams());
+    b->dev = dev;
+    b->reserve = reserve;
+    LSH_HIP(hipStreamCreateWithFlags(&b->ps, hipStreamNonBlocking));
+    LSH_HIP(hipStreamCreateWithFlags(&b->ps2, hipStreamNonBlocking));
+    LSH_HIP(hipStreamCreateWithFlags(&b->pg, hipStreamNonBlocking));
+    if (reserve > 0) {
+      int ncu = 0;
+      LSH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+      for (int c = 0; c < ncu - reserve; ++c) mask[c / 32] |= 1u << (c % 32);
+      if (hipExtStreamCreateWithCUMask(&b->fsm, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        b->fsm = nullptr;
+      }
+    }
+    return b.release();
+  }
+  static void release(BuildStreams* b) {
+    std::lock_guard<std::mutex> g(mu());
+    pool().push_back(b);
+  }
+};
+}  // namespace
 
 extern "C" {
 
@@ -1908,7 +2059,22 @@ int lsh_plan_create(const lsh_desc* desc, void* ws, size_t ws_bytes, void* strea
   P->d = *desc;
   attach_plan(*P, ws, ws_bytes);
   mem::Bind bind(&P->persist);
-  plan_build(*P, (hipStream_t)stream);
+  {  // (the parent Gram rows on a pooled side stream, as in lsh_build)
+    int dev = 0;
+    LSH_HIP(hipGetDevice(&dev));
+    BuildStreams* bs = BuildStreams::acquire(dev, 0);
+    struct Guard {
+      BuildStreams* b;
+      lsh_plan_s* P;
+      ~Guard() {
+        if (b->pg) (void)hipStreamSynchronize(b->pg);
+        P->gs = nullptr;
+        BuildStreams::release(b);
+      }
+    } guard{bs, P.get()};
+    P->gs = bs->pg;
+    plan_build(*P, (hipStream_t)stream);
+  }
   *plan = P.release();
   return LSH_OK;
   API_END
@@ -1924,8 +2090,8 @@ int lsh_plan_destroy(lsh_plan_t plan) {
 int lsh_plan_workspace_used(lsh_plan_t P, size_t* used, size_t* size) {
   API_BEGIN
   LSH_REQUIRE(P, LSH_ERR_INVALID_ARG, "null plan");
-  if (used) *used = P->persist.high() + P->sid.high() + P->ssib.high();
-  if (size) *size = P->persist.cap() + P->sid.cap() + P->ssib.cap();
+  if (used) *used = P->persist.high() + P->sid.high() + P->ssib.high() + P->sgram.high();
+  if (size) *size = P->persist.cap() + P->sid.cap() + P->ssib.cap() + P->sgram.cap();
   return LSH_OK;
   API_END
 }
@@ -2067,77 +2233,6 @@ int lsh_factor_create(lsh_plan_t P, const double* b, int flags, void* ws, size_t
 
 }  // extern "C"
 
-namespace {
-// Streams and events of lsh_build, kept for the process (per device and CU
-// reserve) and handed to one build at a time.
-struct BuildStreams {
-  int dev = 0, reserve = 0;
-  hipStream_t ps = nullptr, ps2 = nullptr, fsm = nullptr;
-  std::vector<hipEvent_t> ev;
-  void events(size_t n) {
-    while (ev.size() < n) {
-      hipEvent_t e = nullptr;
-      LSH_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      ev.push_back(e);
-    }
-  }
-  // (never destroyed: the exit handler below still uses them)
-  static std::mutex& mu() {
-    static std::mutex* m = new std::mutex;
-    return *m;
-  }
-  static std::vector<BuildStreams*>& pool() {
-    static std::vector<BuildStreams*>* p = new std::vector<BuildStreams*>;
-    return *p;
-  }
-  // destroys the pooled streams and events at process exit, before the
-  // runtime's own teardown (a handler registered after the runtime started)
-  static void destroy_all() {
-    std::lock_guard<std::mutex> g(mu());
-    for (BuildStreams* b : pool()) {
-      for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
-      for (hipStream_t st : {b->ps, b->ps2, b->fsm})
-        if (st) (void)hipStreamDestroy(st);
-      delete b;
-    }
-    pool().clear();
-  }
-  static BuildStreams* acquire(int dev, int reserve) {
-    static const bool registered = [] { return std::atexit(destroy_all) == 0; }();
-    (void)registered;
-    {
-      std::lock_guard<std::mutex> g(mu());
-      auto& p = pool();
-      for (size_t i = 0; i < p.size(); ++i)
-        if (p[i]->dev == dev && p[i]->reserve == reserve) {
-          BuildStreams* b = p[i];
-          p.erase(p.begin() + i);
-          return b;
-        }
-    }
-    std::unique_ptr<BuildStreams> b(new BuildStreams());
-    b->dev = dev;
-    b->reserve = reserve;
-    LSH_HIP(hipStreamCreateWithFlags(&b->ps, hipStreamNonBlocking));
-    LSH_HIP(hipStreamCreateWithFlags(&b->ps2, hipStreamNonBlocking));
-    if (reserve > 0) {
-      int ncu = 0;
-      LSH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-      for (int c = 0; c < ncu - reserve; ++c) mask[c / 32] |= 1u << (c % 32);
-      if (hipExtStreamCreateWithCUMask(&b->fsm, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
-        (void)hipGetLastError();
-        b->fsm = nullptr;
-      }
-    }
-    return b.release();
-  }
-  static void release(BuildStreams* b) {
-    std::lock_guard<std::mutex> g(mu());
-    pool().push_back(b);
-  }
-};
-}  // namespace
 
 extern "C" {
 
@@ -2194,9 +2289,15 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   BuildStreams* bs = BuildStreams::acquire(dev, reserve);
   struct BsGuard {
     BuildStreams* b;
-    ~BsGuard() { BuildStreams::release(b); }
-  } bsg{bs};
+    lsh_plan_s* P;
+    ~BsGuard() {  // (the side stream's rows read plan memory: drained before the streams go back)
+      if (b->pg) (void)hipStreamSynchronize(b->pg);
+      P->gs = nullptr;
+      BuildStreams::release(b);
+    }
+  } bsg{bs, P.get()};
   hipStream_t ps = bs->ps, ps2 = bs->ps2, fsm = bs->fsm;
+  P->gs = bs->pg;
   hipStream_t fs = fsm ? fsm : s;
   mem::Bind bind(&P->persist);  // (plan_init; each plan thread binds its own)
   plan_init(*P, ps);
@@ -3162,7 +3263,7 @@ int lsh_gemm_recorded(int* count, int* shapes, int cap) {
   *count = (int)v.size();
   if (shapes)
     for (int i = 0; i < (int)v.size() && i < cap; ++i)
-      for (int q = 0; q < 5; ++q) shapes[5 * i + q] = v[i][q];
+      for (int q = 0; q < 6; ++q) shapes[6 * i + q] = v[i][q];
   return LSH_OK;
   API_END
 }

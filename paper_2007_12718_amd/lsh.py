@@ -551,12 +551,12 @@ def gemm_record(on=True):
 
 
 def gemm_recorded():
-    """[(prec, M, N, K, batch)] of the products since gemm_record(True) (prec 1 = FP32, 0 = FP64)."""
+    """{(prec, M, N, K, batch): number of products} since gemm_record(True) (prec 1 = FP32, 0 = FP64)."""
     n = c_int(0)
     _check(lib().lsh_gemm_recorded(ctypes.byref(n), None, 0))
-    buf = (c_int * (5 * max(n.value, 1)))()
+    buf = (c_int * (6 * max(n.value, 1)))()
     _check(lib().lsh_gemm_recorded(ctypes.byref(n), buf, n.value))
-    return [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
+    return {tuple(buf[6 * i:6 * i + 5]): buf[6 * i + 5] for i in range(n.value)}
 
 
 def gemm_table_save(path):
