@@ -28,6 +28,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# lsh_build keeps four streams of its own busy beside the caller's; with
+# fewer hardware queues per process than streams, two of them share a queue
+# and run one after the other (set before the HIP runtime starts)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6

@@ -210,11 +210,15 @@ int lsh_factor_workspace_used(lsh_factor_t factor, size_t* used, size_t* size);
  * latency-bound pivot loops of the compression overlap the factor's matrix
  * products.  Same results as lsh_plan_create + lsh_factor_create; destroy
  * the factor, then the plan.  Synchronises the stream before returning.
- * The plan runs on a library stream; the factor runs on a library stream
- * kept off LSH_PLAN_CUS compute units (default: an eighth of them for FP32
- * factors, none for FP64; 0 = the caller's stream, unmasked), so that the
- * plan's latency-bound kernels find free units while the factor's products
- * fill the rest.  The factor starts before the ranks are known, so both
+ * The plan runs on library streams (the level row IDs, the sibling blocks,
+ * and the parent-level Gram rows built during each row ID); the factor runs
+ * on a library stream kept off LSH_PLAN_CUS compute units (default: an
+ * eighth of them for FP32 factors, none for FP64; 0 = the caller's stream,
+ * unmasked), so that the plan's latency-bound kernels find free units while
+ * the factor's products fill the rest.  Up to five streams are busy at once:
+ * give the process at least that many hardware queues (GPU_MAX_HW_QUEUES,
+ * read when the HIP runtime starts), or two of them share a queue and
+ * serialise.  The factor starts before the ranks are known, so both
  * workspaces are sized by the plan's rank bounds (lsh_build_workspace:
  * plan_bytes as lsh_plan_workspace, factor_bytes at least what
  * lsh_factor_workspace would give once the plan exists).
