@@ -60,6 +60,8 @@ def parse():
                          "(sides 64..256, 5-20 wavelengths), batched (lsh_batch_factor) against one by one")
     ap.add_argument("--merge", default="auto", choices=["auto", "schur", "lowrank"],
                     help="form of the merge inverses (lsh_desc.merge)")
+    ap.add_argument("--full-levels", type=int, default=0,
+                    help="levels 1..N keep all their candidates (lsh_desc.full_levels; 0 = every level compressed)")
     ap.add_argument("--direct", type=int, default=0,
                     help="instead of the headline run: direct-solver mode on this grid side (the largest "
                          "workload family at the same kappa h): 10th-order HBS, FP64, applied once")
@@ -85,30 +87,31 @@ def workload(n):
 _WS = {}
 
 
-def workspaces(lsh, w, prec, merge):
+def workspaces(lsh, w, prec, merge, full_levels=0):
     """The device workspaces of one form (plan, factor, solve), allocated once
     and reused by every step: the library itself allocates nothing."""
-    key = (w.n, prec, merge)
+    key = (w.n, prec, merge, full_levels)
     if key not in _WS:
         pw, fw = lsh.build_workspaces(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol,
-                                      proxy_width=w.proxy_width, prec=prec, merge=merge)
+                                      proxy_width=w.proxy_width, prec=prec, merge=merge, full_levels=full_levels)
         _WS[key] = {"plan": pw, "factor": fw, "solve": None}
     return _WS[key]
 
 
-def run_step(lsh, w, b_d, u_d, prec, torch, separate=False, merge="auto"):
-    ws = workspaces(lsh, w, prec, merge)
+def run_step(lsh, w, b_d, u_d, prec, torch, separate=False, merge="auto", full_levels=0):
+    ws = workspaces(lsh, w, prec, merge, full_levels)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if separate:  # lsh_plan_create then lsh_factor_create
         P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width,
-                     prec=prec, merge=merge, ws=ws["plan"])
+                     prec=prec, merge=merge, ws=ws["plan"], full_levels=full_levels)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         F = lsh.Factor(P, b_d, ws=ws["factor"])
     else:  # lsh_build: the same plan and factor, pipelined by level
         P, F = lsh.build(w.n, w.kappa, b_d, op_order=w.op_order, leaf=w.leaf, tol=w.tol,
-                         proxy_width=w.proxy_width, prec=prec, merge=merge, workspaces=(ws["plan"], ws["factor"]))
+                         proxy_width=w.proxy_width, prec=prec, merge=merge, workspaces=(ws["plan"], ws["factor"]),
+                         full_levels=full_levels)
         t1 = None
     if ws["solve"] is None:  # (first, untimed warmup step)
         ws["solve"] = lsh.workspace(F.solve_workspace_bytes(1, 100))
@@ -539,7 +542,7 @@ def main():
             if full:
                 lsh.lsh_profile_only(None)
                 lsh.lsh_profile_enable(True)
-            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate, a.merge)
+            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate, a.merge, a.full_levels)
             if full:
                 kernels_warm = kernel_table(lsh)
                 rl = roofline(lsh)
@@ -556,7 +559,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(a.steps):
-            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate, a.merge)
+            r = run_step(lsh, w, b_d, u_d, prec, torch, a.separate, a.merge, a.full_levels)
             steps.append(r)
             print(f"# step {k} {prec}: {json.dumps(r)}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -586,7 +589,8 @@ def main():
                                f"b random Fourier field |k|<=20 cycles in [-1,0.9], plane wave, "
                                f"HBS 4th order tol={w.tol} leaf={w.leaf} proxy_width={w.proxy_width}, "
                                f"operator order {w.op_order}, GMRES tol {w.gmres_tol}",
-                   "hbs_prec": "fp32", "merge": a.merge, "phases_s": {k: head["median"][k] for k in
+                   "hbs_prec": "fp32", "merge": a.merge, "full_levels": a.full_levels,
+                   "phases_s": {k: head["median"][k] for k in
                                                     ("build_s", "plan_s", "factor_s", "solve_s", "total_s")},
                    "step_median_s": head["median"]["total_s"],
                    "iterations": head["median"]["iterations"],

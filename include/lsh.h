@@ -102,6 +102,11 @@ typedef struct {
                        must be at least that) */
   int plan_cache;   /* 1: take each level's row IDs from the process-wide plan cache
                        when present and add the ones computed (lsh_plan_cache_*); 0: off */
+  int full_levels;  /* boxes of levels 1 .. full_levels keep all their candidate nodes
+                       (U_l = I, no row ID; their merges take the children's skeletons
+                       whole): 0 compresses every box below the root (Sec. 3); 1 leaves
+                       the root's two children uncompressed, where the row ID keeps most
+                       candidates anyway and is the longest step of the plan */
 } lsh_desc;
 
 /* Merge inverses X_tau of Algorithm 1 (eq. (localsol)).  SCHUR inverts the

@@ -2027,6 +2027,29 @@ void ccopy2d(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, lo
   LSH_LAUNCH_CHECK();
 }
 
+// Y[v][i] = alpha X[v][i] + beta Z[v][i] for i < n, v < nv (Z may be null)
+template <typename R>
+__global__ void k_caxpby(int n, int nv, cplx<R> alpha, const cplx<R>* __restrict__ X, long ldx, cplx<R> beta,
+                         const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * nv) return;
+  const long v = e / n, i = e - v * n;
+  cplx<R> o = alpha * X[v * ldx + i];
+  if (Z) o = o + beta * Z[v * ldz + i];
+  Y[v * ldy + i] = o;
+}
+
+template <typename R>
+void caxpby(hipStream_t s, int n, int nv, cplx<R> alpha, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z,
+            long ldz, cplx<R>* Y, long ldy) {
+  const long total = (long)n * nv;
+  if (total <= 0) return;
+  if (beta.x == R(0) && beta.y == R(0)) Z = nullptr;
+  hipLaunchKernelGGL(k_caxpby<R>, dim3((unsigned)ceil_div(total, 256L)), dim3(256), 0, s, n, nv, alpha, X, ldx, beta,
+                     Z, ldz, Y, ldy);
+  LSH_LAUNCH_CHECK();
+}
+
 template <typename R>
 __global__ void k_ctranspose(const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -2075,6 +2098,8 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
   template void cmgemv2<R>(hipStream_t, int, int, long, int, cplx<R>, const cplx<R>*, long, const cplx<R>*,   \
                            long, cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                        \
   template void ccopy2d<R>(hipStream_t, int, int, const cplx<R>*, long, long, cplx<R>*, long, long, long);   \
+  template void caxpby<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, cplx<R>, const cplx<R>*, long,  \
+                          cplx<R>*, long);                                                                  \
   template size_t inverse_ws_bytes<R>(int, int);                                                           \
   template void inverse<R>(hipStream_t, cplx<R>*, int, long, long, int, void*, int*);
 LSH_INST(float)

@@ -146,6 +146,10 @@ template <typename R>
 void ctranspose(hipStream_t s, const cplx<R>* in, int rows, int cols, cplx<R>* out, long batch = 1);
 
 // dst_b = src_b for rows x cols blocks (leading dimensions lds, ldd; batch strides ss, sd)
+// Y[v] = alpha X[v] + beta Z[v] (n entries each, nv vectors; Z may be null)
+template <typename R>
+void caxpby(hipStream_t s, int n, int nv, cplx<R> alpha, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z,
+            long ldz, cplx<R>* Y, long ldy);
 template <typename R>
 void ccopy2d(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, long ss, cplx<R>* dst, long ldd,
              long sd, long batch = 1);

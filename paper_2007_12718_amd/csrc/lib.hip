@@ -53,6 +53,7 @@ struct Level {
   std::vector<I2> ra, rb;  // skeleton points of the two children (sibling-block rows / columns)
   DevBuf U64, U32;       // m x k
   DevBuf Ut64, Ut32;     // k x m (transpose, for row-streamed products)
+  bool ident = false;    // U = I (k = m): the level keeps all its candidates
   DevBuf Gab64, Gab32;   // sibling block of this parent level (c x c, c = k of level+1)
   DevBuf Gabt64, Gabt32; // its transpose
   int c = 0;
@@ -198,6 +199,25 @@ void validate(const lsh_desc& d) {
   const int reach = d.hbs_order > 4 ? d.hbs_order / 2 - 2 : 0;  // stencil reach of order 6/8/10: 1/2/3
   LSH_REQUIRE(d.proxy_width >= reach, LSH_ERR_INVALID_ARG,
               "proxy_width must reach the correction stencil of hbs_order (6: 1, 8: 2, 10: 3)");
+  int lg = 0;
+  while ((1 << lg) < p) ++lg;
+  LSH_REQUIRE(d.full_levels >= 0 && d.full_levels < 2 * lg, LSH_ERR_INVALID_ARG,
+              "full_levels must be in [0, L) (L = 2 log2(n / leaf) levels below the root)");
+}
+
+__global__ void k_identity(z64* U, int m) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (long)m * m) U[e] = mk(e / m == e % m ? 1.0 : 0.0, 0.0);
+}
+
+// The exact "row ID" of m rows: J = all rows, U = I (on the device).
+int identity_id(int m, std::vector<int>& Jh, DevBuf& U64, hipStream_t s) {
+  Jh.resize(m);
+  for (int i = 0; i < m; ++i) Jh[i] = i;
+  U64.alloc(sizeof(z64) * (size_t)m * m);
+  hipLaunchKernelGGL(k_identity, dim3(ceil_div((long)m * m, 256L)), dim3(256), 0, s, U64.as<z64>(), m);
+  LSH_LAUNCH_CHECK();
+  return m;
 }
 
 // Row ID A ~= U A[J, :] of a device matrix A (m x np, FP64; overwritten) at
@@ -209,14 +229,7 @@ void validate(const lsh_desc& d) {
 // then unused) and return the parent level's Gram rows to feed (or null).
 int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64, mem::Arena& scr,
                   hipStream_t s, const std::function<NextGram*(z64*, bool&)>& gram = {}) {
-  if (P.d.tol == 0) {  // exact full-rank form: U = I, J = all rows
-    Jh.resize(m);
-    for (int i = 0; i < m; ++i) Jh[i] = i;
-    std::vector<z64> I((size_t)m * m, mk(0.0, 0.0));
-    for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = mk(1.0, 0.0);
-    U64 = upload(I, s);
-    return m;
-  }
+  if (P.d.tol == 0) return identity_id(m, Jh, U64, s);  // exact full-rank form
   int* J = static_cast<int*>(scr.take(sizeof(int) * m));
   z64* Ufull = static_cast<z64*>(scr.take(sizeof(z64) * (size_t)m * m));
   int k = 0;
@@ -302,8 +315,9 @@ bool block_pivots(const lsh_plan_s& P) {
 // built while this row ID runs.
 void level_id(lsh_plan_s& P, int l, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
   const int m = lv.m, np = (int)prox.size();
-  if (P.d.tol == 0) {
-    lv.k = row_id_matrix(P, nullptr, m, np, lv.J, lv.U64, P.sid, s);
+  lv.ident = P.d.tol == 0 || l <= P.d.full_levels;
+  if (lv.ident) {  // every candidate kept (exact form, or an uncompressed top level)
+    lv.k = identity_id(m, lv.J, lv.U64, s);
     return;
   }
   pcache::Key key;
@@ -332,7 +346,7 @@ void level_id(lsh_plan_s& P, int l, Level& lv, const std::vector<I2>& prox, hipS
       ready = true;
     }
     P.ng_level = -1;
-    if (!(block && P.gs && l >= 2 && m >= kNextGramMin && !P.d.plan_cache)) return nullptr;
+    if (!(block && P.gs && l - 1 > P.d.full_levels && l >= 2 && m >= kNextGramMin && !P.d.plan_cache)) return nullptr;
     // the parent level l - 1: its box, the children's origins in it, its ring
     P.sgram.reset(0);  // (after the pack above, on s; the new rows start after a sync of s)
     int ox, oy, psx, psy, cx, cy, csx, csy;
@@ -625,7 +639,7 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
     np[l] = (long)(sx + 2 * w) * (sy + 2 * w) - (long)sx * sy;
     const long ncols = (horder > 4 ? 2 : 1) * np[l];
     m[l] = l == L ? mL : 2 * k[l + 1];
-    k[l] = d.tol == 0 ? m[l] : std::max(1L, std::min(m[l], ncols));
+    k[l] = (d.tol == 0 || l <= d.full_levels) ? m[l] : std::max(1L, std::min(m[l], ncols));
   }
   PlanBytes b;
   mem::Sizer z;
@@ -648,7 +662,7 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
     if (d.tol > 0) t.add_n<z64>((size_t)m[l] * ncols);
     sid = std::max(sid, t.total + rowid_scratch_bytes(m[l], d.tol));
     // the parent's Gram rows, built during this row ID (level_id)
-    if (d.tol >= 1e-7 && !d.plan_cache && l >= 2 && m[l] >= kNextGramMin) {
+    if (d.tol >= 1e-7 && !d.plan_cache && l >= 2 && l - 1 > d.full_levels && m[l] >= kNextGramMin) {
       const long pcols = (horder > 4 ? 2 : 1) * np[l - 1];
       mem::Sizer g;
       g.add_n<I2>(np[l - 1]);
@@ -1000,6 +1014,35 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
   const long ck = (long)c * k;
   const cplx<R>* U1 = P.U<R>(l);
   const cplx<R>* U2 = U1 + ck;
+  if (P.lev[l].ident) {  // U_l = I (k = 2c): the products with U are placements
+    F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
+    cplx<R>* S = F.S[l].template as<cplx<R>>();
+    const long kk = (long)k * k;
+    // S = [[S_a, 0], [0, S_b]] per box: the rows U_1^T a1 and U_2^T a2 start from
+    fill_zero(s, S, sizeof(cplx<R>) * nb * kk);
+    ccopy2d<R>(s, c, c, Sch, c, 2 * cc, S, k, kk, nb);
+    ccopy2d<R>(s, c, c, Sch + cc, c, 2 * cc, S + ck + c, k, kk, nb);
+    if (F.wr[l] > 0) {  // S <- S - P W' [L^T a1; R^T a2], in place (as below with U = I)
+      const int r = F.wr[l];
+      const long rk = (long)r * k, cr = (long)c * r, w4 = 4L * r * r;
+      cplx<R>* q = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 4 * rk);
+      cplx<R>* yv = q + nb * 2 * rk;
+      cgemm<R>(s, r, k, c, one, P.W<R>(l, 1), c, 0, OP_N, S, k, kk, OP_N, zero, nullptr, 0, 0, q, k, 2 * rk, nb);
+      cgemm<R>(s, r, k, c, one, P.W<R>(l, 3), c, 0, OP_N, S + ck, k, kk, OP_N, zero, nullptr, 0, 0, q + rk, k,
+               2 * rk, nb);
+      cgemm<R>(s, 2 * r, k, 2 * r, one, Ci, 2 * r, w4, OP_N, q, k, 2 * rk, OP_N, zero, nullptr, 0, 0, yv, k, 2 * rk,
+               nb);
+      cgemm<R>(s, c, k, r, mone, Pa, r, cr, OP_N, yv, k, rk, OP_N, one, S, k, ck, S, k, ck, 2 * nb);
+      return;
+    }
+    // Schur form: a2 = [0, S_b] - Pb a1, y = C^{-1} a2 (the lower rows of S), then a1 - Pa y (the upper rows)
+    cplx<R>* a2 = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
+    ccopy2d<R>(s, c, k, S + ck, k, kk, a2, k, ck, nb);
+    cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, S, k, kk, OP_N, one, a2, k, ck, a2, k, ck, nb);
+    cgemm<R>(s, c, k, c, one, Ci, c, cc, OP_N, a2, k, ck, OP_N, zero, nullptr, 0, 0, S + ck, k, kk, nb);
+    cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, S + ck, k, kk, OP_N, one, S, k, kk, S, k, kk, nb);
+    return;
+  }
   if (F.wr[l] > 0) {
     // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] (a1, a2 interleaved per box in A12)
     const int r = F.wr[l];
@@ -1157,7 +1200,11 @@ constexpr int skinny() { return 1024; }
 template <typename R>
 void shared_mv(hipStream_t s, int rows, int cols, cplx<R> alpha, const cplx<R>* M, const cplx<R>* MtB, long ldb,
                Op opB, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy,
-               int B, DevBuf& ws) {
+               int B, DevBuf& ws, bool ident = false) {
+  if (ident) {  // M = I (a level that keeps all its candidates)
+    caxpby<R>(s, rows, B, alpha, X, ldx, beta, Z, ldz, Y, ldy);
+    return;
+  }
   if (B <= skinny<R>())
     cmgemv<R>(s, rows, cols, alpha, M, cols, X, ldx, beta, Z, ldz, Y, ldy, B);
   else
@@ -1284,7 +1331,7 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     apply_X<R>(P, F, l, nrhs, F.rt[l + 1].template as<cplx<R>>(), t1, s);
     // rt_l = U_l^T xv
     shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t1, 2 * c, zero, nullptr, 0,
-                 F.rt[l].template as<cplx<R>>(), k, B, F.tk);
+                 F.rt[l].template as<cplx<R>>(), k, B, F.tk, P.lev[l].ident);
   }
   // root: w_children = Ghat X_root [rt_a; rt_b]
   {
@@ -1300,7 +1347,7 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     const long cc = (long)c * c;
     // u = U_l wt_l  ([B][2c])
     shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.wt[l].template as<cplx<R>>(), k, zero, nullptr,
-                 0, t1, 2 * c, B, F.tk);
+                 0, t1, 2 * c, B, F.tk, P.lev[l].ident);
     // d = rt_children - diag(S_a, S_b) u  ([2B][c])
     cgemv<R>(s, c, c, mone, F.S[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t1, c, one,
              F.rt[l + 1].template as<cplx<R>>(), c, t2, c, 2 * B);
@@ -1344,7 +1391,7 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
     cgemv<R>(s, c, c, mone, F.ST[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t3, c, one, wc, c, t2, c, 2 * B);
     // wb_l = U_l^T t2
     shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t2, 2 * c, zero, nullptr, 0,
-                 F.wt[l].template as<cplx<R>>(), k, B, F.tk);
+                 F.wt[l].template as<cplx<R>>(), k, B, F.tk, P.lev[l].ident);
   }
   // root: rb_1 = X_root^T Ghat wb_1
   {
@@ -1359,7 +1406,7 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
     const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
     const cplx<R>* vb = F.vb[l].template as<cplx<R>>();
     shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.rt[l].template as<cplx<R>>(), k, one, vb, 2 * c,
-                 t1, 2 * c, B, F.tk);
+                 t1, 2 * c, B, F.tk, P.lev[l].ident);
     apply_X<R>(P, F, l, nrhs, t1, F.rt[l + 1].template as<cplx<R>>(), s, true);
   }
   // leaves: q = X^T (g + U_L rb_L)

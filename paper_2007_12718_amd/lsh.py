@@ -46,7 +46,8 @@ GEMM_TABLE = os.path.join(HERE, "tune", "gemm_table.txt")
 class LshDesc(ctypes.Structure):
     _fields_ = [("n", c_int), ("h", c_double), ("x0", c_double), ("y0", c_double), ("kappa", c_double),
                 ("op_order", c_int), ("leaf", c_int), ("tol", c_double), ("proxy_width", c_int),
-                ("hbs_prec", c_int), ("merge", c_int), ("hbs_order", c_int), ("plan_cache", c_int)]
+                ("hbs_prec", c_int), ("merge", c_int), ("hbs_order", c_int), ("plan_cache", c_int),
+                ("full_levels", c_int)]
 
 
 MERGE = {"auto": 0, "schur": 1, "lowrank": 2}
@@ -207,11 +208,12 @@ class Plan:
     """lsh_plan_create: tree, weights, kernel table, per-level row IDs, FFT spectrum."""
 
     def __init__(self, n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32",
-                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, ws=None, _create=True):
+                 h=None, x0=-0.5, y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, ws=None, _create=True,
+                 full_levels=0):
         self.desc = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa,
                             op_order=op_order, leaf=leaf, tol=tol, proxy_width=proxy_width,
                             hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64, merge=MERGE[merge],
-                            hbs_order=hbs_order, plan_cache=int(bool(plan_cache)))
+                            hbs_order=hbs_order, plan_cache=int(bool(plan_cache)), full_levels=full_levels)
         self.n = n
         self.h = self.desc.h
         self.kappa = kappa
@@ -428,11 +430,12 @@ class Factor:
 
 
 def build_workspaces(n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5,
-                     y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, transpose=False):
+                     y0=-0.5, merge="auto", hbs_order=4, plan_cache=False, transpose=False, full_levels=0):
     """(plan_ws, factor_ws): device workspaces sized for lsh_build (allocate once, reuse across builds)."""
     d = LshDesc(n=n, h=(1.0 / n if h is None else h), x0=x0, y0=y0, kappa=kappa, op_order=op_order, leaf=leaf,
                 tol=tol, proxy_width=proxy_width, hbs_prec=LSH_FP32 if prec == "fp32" else LSH_FP64,
-                merge=MERGE[merge], hbs_order=hbs_order, plan_cache=int(bool(plan_cache)))
+                merge=MERGE[merge], hbs_order=hbs_order, plan_cache=int(bool(plan_cache)),
+                full_levels=full_levels)
     pb, fb = _size(), _size()
     _check(lib().lsh_build_workspace(ctypes.byref(d), LSH_FACTOR_TRANSPOSE if transpose else 0, ctypes.byref(pb),
                                      ctypes.byref(fb)))
@@ -440,15 +443,15 @@ def build_workspaces(n, kappa, op_order=10, leaf=8, tol=1e-4, proxy_width=2, pre
 
 
 def build(n, kappa, b, op_order=10, leaf=8, tol=1e-4, proxy_width=2, prec="fp32", h=None, x0=-0.5, y0=-0.5,
-          merge="auto", hbs_order=4, plan_cache=False, transpose=False, workspaces=None):
+          merge="auto", hbs_order=4, plan_cache=False, transpose=False, workspaces=None, full_levels=0):
     """lsh_build: plan and factor pipelined by level; returns (Plan, Factor).
     workspaces: (plan_ws, factor_ws) from build_workspaces, reused (else new ones)."""
     import torch
     P = Plan(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge=merge, hbs_order=hbs_order,
-             plan_cache=plan_cache, _create=False)
+             plan_cache=plan_cache, _create=False, full_levels=full_levels)
     if workspaces is None:
         workspaces = build_workspaces(n, kappa, op_order, leaf, tol, proxy_width, prec, h, x0, y0, merge,
-                                      hbs_order, plan_cache, transpose)
+                                      hbs_order, plan_cache, transpose, full_levels)
     pw, fw = workspaces
     fh = c_void_p()
     b = b.reshape(n, n).contiguous()

@@ -86,3 +86,22 @@ def test_workspace_queries_are_host_only_and_consistent():
         prev = p.value
     d = _desc(lsh, 30)  # n / leaf not a power of two
     assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p)) == lsh.LSH_ERR_INVALID_ARG
+
+
+def test_full_levels_validated_and_bounded():
+    """full_levels lies in [0, L); keeping the top levels whole can only
+    raise the plan's bound (their ranks become their candidate counts)."""
+    import ctypes
+    from paper_2007_12718_amd import lsh
+    L = lsh.lib()
+    p0, p1 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    d = _desc(lsh, 256)  # 256 / 8 = 32 leaves a side: L = 10 levels below the root
+    assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p0)) == 0
+    d.full_levels = 1
+    assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p1)) == 0
+    assert p1.value >= p0.value
+    for bad in (-1, 10, 11):
+        d.full_levels = bad
+        assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p1)) == lsh.LSH_ERR_INVALID_ARG
+    d.full_levels = 9
+    assert L.lsh_plan_workspace(ctypes.byref(d), ctypes.byref(p1)) == 0

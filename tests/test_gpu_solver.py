@@ -202,16 +202,41 @@ def test_eval_points_matches_oracle():
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_pipelined_build_equals_separate_calls(prec):
+@pytest.mark.parametrize("merge", ["auto", "lowrank"])
+@pytest.mark.parametrize("prec,fl", [("fp64", 1), ("fp64", 2), ("fp32", 1)])
+def test_full_top_levels_keep_candidates(small, prec, fl, merge):
+    """Levels 1..full_levels keep every candidate (U = I, no row ID): their
+    ranks are their candidate counts, the HBS below is compressed as usual,
+    and the inverse and its transpose still match the dense ones to the
+    compression tolerance (FP64 at 1e-10: to 1e-8; FP32: to 2e-5)."""
+    from paper_2007_12718_amd import lsh
+    w, D, sig, _ = small
+    P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=1e-10, proxy_width=3, prec=prec, merge=merge,
+                 full_levels=fl)
+    L, r = P.ranks()
+    for l in range(1, fl + 1):
+        assert r[l] == 2 * r[l + 1]
+    F = lsh.Factor(P, cuda(w.b), transpose=True)
+    f = dense.rhs(w.b, w.u_inc, w.kappa).reshape(1, w.n, w.n)
+    q = F.apply_precond(cuda(f)).cpu().numpy()
+    bound = 1e-8 if prec == "fp64" else 2e-5
+    assert rel(q, sig[0]) <= bound
+    A = dense.dense_A(w.b, dense.dense_K(w.n, w.kappa, 4), w.kappa)
+    x = np.random.default_rng(3).standard_normal((1, w.n, w.n)) + 0j
+    qt = F.apply_precond(cuda(x), transpose=True).cpu().numpy()
+    assert rel(qt[0], np.linalg.solve(A.T, x[0].reshape(-1)).reshape(w.n, w.n)) <= bound
+
+
+@pytest.mark.parametrize("prec,fl", [("fp64", 0), ("fp32", 0), ("fp32", 1)])
+def test_pipelined_build_equals_separate_calls(prec, fl):
     """lsh_build (plan and factor overlapped by level) computes exactly what
     lsh_plan_create + lsh_factor_create compute."""
     from paper_2007_12718_amd import lsh
     n, kappa = 64, 2 * np.pi * 6
     b = synth.bumps(n, np.random.default_rng(9))
-    P1 = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
+    P1 = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, full_levels=fl)
     F1 = lsh.Factor(P1, cuda(b))
-    P2, F2 = lsh.build(n, kappa, cuda(b), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec)
+    P2, F2 = lsh.build(n, kappa, cuda(b), op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, full_levels=fl)
     assert P1.ranks() == P2.ranks()
     x = np.random.default_rng(1).standard_normal((1, n, n)) + 0j
     assert np.array_equal(F1.apply_precond(cuda(x)).cpu().numpy(), F2.apply_precond(cuda(x)).cpu().numpy())
@@ -253,8 +278,9 @@ def test_reused_workspaces_give_identical_factor(prec):
         assert np.array_equal(a, c)
 
 
-@pytest.mark.parametrize("prec,merge", [("fp32", "auto"), ("fp64", "auto"), ("fp32", "lowrank"), ("fp64", "schur")])
-def test_workspace_bounds_hold(prec, merge):
+@pytest.mark.parametrize("prec,merge,fl", [("fp32", "auto", 0), ("fp64", "auto", 0), ("fp32", "lowrank", 0),
+                                           ("fp64", "schur", 0), ("fp32", "auto", 1)])
+def test_workspace_bounds_hold(prec, merge, fl):
     """The plan and factor use at most the workspace the queries ask for
     (the factor's exact size given the plan is within lsh_build's bound), and
     a workspace one granule short is refused with
@@ -263,12 +289,12 @@ def test_workspace_bounds_hold(prec, merge):
     from paper_2007_12718_amd import lsh
     n, kappa = 64, 2 * np.pi * 6
     b = synth.bumps(n, np.random.default_rng(4))
-    P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, merge=merge)
+    P = lsh.Plan(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec, merge=merge, full_levels=fl)
     used, size = P.workspace_used()
     assert 0 < used <= size
     for tr in (False, True):
         pb, fb = lsh.build_workspaces(n, kappa, op_order=6, leaf=8, tol=1e-4, proxy_width=2, prec=prec,
-                                      merge=merge, transpose=tr)
+                                      merge=merge, transpose=tr, full_levels=fl)
         assert size == pb.numel()
         F = lsh.Factor(P, cuda(b), transpose=tr)
         u, z = F.workspace_used()
