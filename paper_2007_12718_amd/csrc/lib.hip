@@ -475,7 +475,7 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
 // the compression tolerance (the remark after Algorithm 2; rank about a
 // quarter to two fifths of c at tol 1e-4).  AUTO keeps the Schur form where
 // r > 0.6 c, where the Woodbury products stop saving work.
-void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
+void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s, mem::Arena& tmp) {
   const lsh_desc& d = P.d;
   Level& lv = P.lev[l];
   lv.wr = 0;
@@ -497,9 +497,9 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
     hit = pcache::find(key, sk, J, r, U, s);
   }
   if (!hit) {
-    z64* A = static_cast<z64*>(P.ssib.take(sizeof(z64) * cc));
+    z64* A = static_cast<z64*>(tmp.take(sizeof(z64) * cc));
     LSH_HIP(hipMemcpyAsync(A, lv.Gab64.p, sizeof(z64) * cc, hipMemcpyDeviceToDevice, s));
-    r = row_id_matrix(P, A, c, c, J, U, P.ssib, s);
+    r = row_id_matrix(P, A, c, c, J, U, tmp, s);
     if (P.d.plan_cache && d.tol > 0) pcache::insert(key, sk, J, c, r, U, s);  // U = L: c x r
   }
   if (d.merge == LSH_MERGE_AUTO && 10 * r > 6 * c) return;
@@ -509,8 +509,8 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
   std::vector<I2>& rows = lv.wrows;
   rows.resize(r);
   for (int i = 0; i < r; ++i) rows[i] = lv.ra[J[i]];
-  const I2* dr = upload_to(P.ssib, rows, s);
-  const I2* db = upload_to(P.ssib, lv.rb, s);
+  const I2* dr = upload_to(tmp, rows, s);
+  const I2* db = upload_to(tmp, lv.rb, s);
   lv.Pm64.alloc(sizeof(z64) * 2 * cr);
   lv.Qm64.alloc(sizeof(z64) * 2 * cr);
   z64* Pm = lv.Pm64.as<z64>();
@@ -528,13 +528,14 @@ void plan_lowrank(lsh_plan_s& P, int l, hipStream_t s) {
   LSH_HIP(hipStreamSynchronize(s));
 }
 
-// sibling block of parent level l (needs the skeletons of level l + 1)
-void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
+// sibling block of parent level l (needs the skeletons of level l + 1);
+// temporaries from tmp, rewound first (after a synchronisation of s)
+void plan_sibling(lsh_plan_s& P, int l, hipStream_t s, mem::Arena& tmp) {
   const lsh_desc& d = P.d;
   const bool f32 = d.hbs_prec == LSH_FP32;
   if (l < P.L) {  // sibling block G_ab of parent level l (eq. (sibint)): children 0 and 1 of box 0
     LSH_HIP(hipStreamSynchronize(s));
-    P.ssib.reset(0);  // (the previous sibling block's temporaries are no longer in use)
+    tmp.reset(0);  // (the previous sibling block's temporaries are no longer in use)
     const Level& ch = P.lev[l + 1];
     int ax, ay, bx, by, sx, sy;
     box_of(d.n, l + 1, 0, ax, ay, sx, sy);
@@ -550,8 +551,8 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
       rb.push_back(I2{ch.cand[j].x + bx, ch.cand[j].y + by});
     }
     lv.c = ch.k;
-    const I2* da = upload_to(P.ssib, ra, s);
-    const I2* db = upload_to(P.ssib, rb, s);
+    const I2* da = upload_to(tmp, ra, s);
+    const I2* db = upload_to(tmp, rb, s);
     const long cc = (long)lv.c * lv.c;
     lv.Gab64.alloc(sizeof(z64) * cc);
     gather_table(s, P.hbs_table(), P.D, da, lv.c, db, lv.c, lv.Gab64.as<z64>(), lv.c);
@@ -563,12 +564,12 @@ void plan_sibling(lsh_plan_s& P, int l, hipStream_t s) {
       lv.Gabt32.alloc(sizeof(c32) * cc);
       ctranspose<float>(s, lv.Gab32.as<c32>(), lv.c, lv.c, lv.Gabt32.as<c32>());
     }
-    plan_lowrank(P, l, s);
+    plan_lowrank(P, l, s, tmp);
   }
 }
 
 void plan_level(lsh_plan_s& P, int l, hipStream_t s) {
-  plan_sibling(P, l, s);
+  plan_sibling(P, l, s, P.ssib);
   plan_id(P, l, s);
 }
 
@@ -695,7 +696,7 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
   }
   z.add(ConvOperator::bytes(d.n));
   b.persist = z.total;
-  b.sid = sid;
+  b.sid = std::max(sid, ssib);  // (lsh_build's row-ID thread may take the last sibling blocks)
   b.ssib = ssib;
   b.sgram = sgram;
   if (prof) {
@@ -2357,7 +2358,7 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   }
   std::mutex mu;
   std::condition_variable cv;
-  int doneU = L + 1, doneG = L + 1;  // lowest level with U_l / G_l ready
+  int doneU = L + 1;  // lowest level with U_l ready
   int running = 2;                   // plan threads still running
   bool finished = false, failed = false;
   std::exception_ptr err;
@@ -2372,7 +2373,35 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   };
   // two plan threads: the row IDs of levels L..1 (the critical path), and
   // behind them the sibling blocks of parent levels L-1..0 with their
-  // low-rank forms (sibling block l needs the skeletons of level l + 1)
+  // low-rank forms (sibling block l needs the skeletons of level l + 1).
+  // Sibling levels are claimed in order by either thread: once its row IDs
+  // are done, the first thread takes the next unclaimed one (the last two,
+  // typically: they need the same skeletons and run side by side).
+  int nextSib = L - 1;                 // next sibling level to claim
+  std::vector<char> sibDone(L + 1, 0);
+  auto claim = [&]() -> int {
+    std::lock_guard<std::mutex> g(mu);
+    return failed ? -1 : nextSib--;
+  };
+  auto sibling = [&](int l, hipStream_t st, mem::Arena& tmp, bool drain) {
+    {
+      std::unique_lock<std::mutex> g(mu);
+      cv.wait(g, [&] { return failed || doneU <= l + 1; });
+      if (failed) return false;
+    }
+    plan_sibling(*P, l, st, tmp);
+    // Before the next sibling block, let every stream drain: the level IDs'
+    // latency-bound steps (the critical path) then run without this thread's
+    // kernels interleaved (fourier-1024: 8 ms less per build).  LSH_SIB_SYNC=0
+    // lets it run ahead.
+    if (drain) LSH_HIP(hipDeviceSynchronize());
+    LSH_HIP(hipEventRecord(ev[L + 1 + l], st));
+    { std::lock_guard<std::mutex> g(mu); sibDone[l] = 1; }
+    cv.notify_all();
+    return true;
+  };
+  const char* ess = std::getenv("LSH_SIB_SYNC");
+  const bool sib_sync = !(ess && *ess == '0');
   std::thread th([&] {
     try {
       LSH_HIP(hipSetDevice(dev));
@@ -2383,7 +2412,12 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
         { std::lock_guard<std::mutex> g(mu); doneU = l; }
         cv.notify_all();
       }
-      // the operator spectrum, while the other thread does the root's sibling block
+      // the remaining sibling blocks (in the row IDs' temporaries: every row
+      // ID is done; the parent Gram rows too), then the operator spectrum
+      LSH_HIP(hipStreamSynchronize(ps));
+      LSH_HIP(hipStreamSynchronize(P->gs));
+      for (int l = claim(); l >= 0; l = claim())
+        if (!sibling(l, ps, P->sid, false)) break;
       plan_finish(*P, ps);
       LSH_HIP(hipEventRecord(ev[2 * L + 2], ps));
     } catch (...) {
@@ -2391,28 +2425,12 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
     }
     leave();
   });
-  const char* ess = std::getenv("LSH_SIB_SYNC");
-  const bool sib_sync = !(ess && *ess == '0');
   std::thread th2([&] {
     try {
       LSH_HIP(hipSetDevice(dev));
       mem::Bind tbind(&P->persist);
-      for (int l = L - 1; l >= 0; --l) {
-        {
-          std::unique_lock<std::mutex> g(mu);
-          cv.wait(g, [&] { return failed || doneU <= l + 1; });
-          if (failed) break;
-        }
-        plan_sibling(*P, l, ps2);
-        // Before the next sibling block, let every stream drain: the level
-        // IDs' latency-bound steps (the critical path) then run without this
-        // thread's kernels interleaved (fourier-1024: 8 ms less per build).
-        // LSH_SIB_SYNC=0 lets it run ahead.
-        if (sib_sync) LSH_HIP(hipDeviceSynchronize());
-        LSH_HIP(hipEventRecord(ev[L + 1 + l], ps2));
-        { std::lock_guard<std::mutex> g(mu); doneG = l; }
-        cv.notify_all();
-      }
+      for (int l = claim(); l >= 0; l = claim())
+        if (!sibling(l, ps2, P->ssib, sib_sync)) break;
     } catch (...) {
       fail();
     }
@@ -2421,7 +2439,7 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   // wait until U_l (kind 0) or G_l (kind 1) exists; false if the plan failed
   auto wait_for = [&](int l, int kind) -> bool {
     std::unique_lock<std::mutex> g(mu);
-    cv.wait(g, [&] { return failed || finished || (kind ? doneG : doneU) <= l; });
+    cv.wait(g, [&] { return failed || finished || (kind ? sibDone[l] != 0 : doneU <= l); });
     return !failed;
   };
   std::exception_ptr ferr;
