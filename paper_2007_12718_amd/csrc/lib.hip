@@ -116,9 +116,13 @@ struct lsh_plan_s {
 };
 
 template <>
-const cplx<double>* lsh_plan_s::Ut<double>(int l) const { return lev[l].Ut64.as<z64>(); }
+const cplx<double>* lsh_plan_s::Ut<double>(int l) const {
+  return lev[l].ident ? lev[l].U64.as<z64>() : lev[l].Ut64.as<z64>();
+}
 template <>
-const cplx<float>* lsh_plan_s::Ut<float>(int l) const { return lev[l].Ut32.as<c32>(); }
+const cplx<float>* lsh_plan_s::Ut<float>(int l) const {
+  return lev[l].ident ? lev[l].U32.as<c32>() : lev[l].Ut32.as<c32>();
+}
 template <>
 const cplx<double>* lsh_plan_s::Gabt<double>(int l) const { return lev[l].Gabt64.as<z64>(); }
 template <>
@@ -459,13 +463,17 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
     }
     lv.m = (int)lv.cand.size();
     level_id(P, l, lv, proxy_ring(lv.sx, lv.sy, d.proxy_width), s);
-    lv.Ut64.alloc(sizeof(z64) * (size_t)lv.m * lv.k);
-    ctranspose<double>(s, lv.U64.as<z64>(), lv.m, lv.k, lv.Ut64.as<z64>());
     if (f32) {
       lv.U32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
       ccast<double, float>(s, lv.U64.as<z64>(), lv.U32.as<c32>(), (long)lv.m * lv.k);
-      lv.Ut32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
-      ctranspose<float>(s, lv.U32.as<c32>(), lv.m, lv.k, lv.Ut32.as<c32>());
+    }
+    if (!lv.ident) {  // (U = I is its own transpose: Ut(l) then reads U)
+      lv.Ut64.alloc(sizeof(z64) * (size_t)lv.m * lv.k);
+      ctranspose<double>(s, lv.U64.as<z64>(), lv.m, lv.k, lv.Ut64.as<z64>());
+      if (f32) {
+        lv.Ut32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
+        ctranspose<float>(s, lv.U32.as<c32>(), lv.m, lv.k, lv.Ut32.as<c32>());
+      }
     }
   }
 }

@@ -32,17 +32,19 @@ def record_shapes(lsh, quick):
     import numpy as np
     import torch
     import synth
-    runs = [(synth.largest(), "fp32"), (synth.largest(), "fp64"), (synth.differentiation(), "fp32"),
-            (synth.bumps20(), "fp32"), (synth.bumps20(), "fp64")]
+    # (workload, precision, full_levels): the bench's headline keeps level 1 whole
+    runs = [(synth.largest(), "fp32", 1), (synth.largest(), "fp64", 1), (synth.largest(), "fp32", 0),
+            (synth.largest(), "fp64", 0), (synth.differentiation(), "fp32", 0), (synth.bumps20(), "fp32", 1),
+            (synth.bumps20(), "fp64", 1)]
     if quick:
-        runs = [(synth.largest(n=256, kappa=50 * np.pi), "fp32"), (synth.bumps20(), "fp64")]
-    runs += [(w, "fp32") for w in synth.batched(12)]
+        runs = [(synth.largest(n=256, kappa=50 * np.pi), "fp32", 1), (synth.bumps20(), "fp64", 0)]
+    runs += [(w, "fp32", 0) for w in synth.batched(12)]
     shapes = set()
-    for w, prec in runs:
+    for w, prec, fl in runs:
         lsh.gemm_record(True)
         b = torch.from_numpy(w.b).cuda()
         P, F = lsh.build(w.n, w.kappa, b, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=w.proxy_width,
-                         prec=prec)
+                         prec=prec, full_levels=fl)
         F.solve(torch.from_numpy(w.u_inc[:1]).cuda(), tol=w.gmres_tol, maxit=100, want_u=False)
         torch.cuda.synchronize()
         got = lsh.gemm_recorded()
@@ -50,7 +52,7 @@ def record_shapes(lsh, quick):
         F.close()
         P.close()
         shapes.update(got)
-        print(f"# {w.name} {prec}: {len(got)} product shapes", flush=True)
+        print(f"# {w.name} {prec} full_levels={fl}: {len(got)} product shapes", flush=True)
     return shapes
 
 
