@@ -474,7 +474,7 @@ template <int KPT>
 __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* chosen, int m, int* st) {
   __shared__ unsigned int hist[256];
   __shared__ unsigned long long s_prefix, s_mask;
-  __shared__ int s_rank, s_cnt;
+  __shared__ int s_rank, s_cnt, s_stop;
   __shared__ unsigned long long ck[64];
   __shared__ unsigned long long s_below;
   if (st[BPS_DONE]) return;
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
     key[r] = (i < m && !chosen[i]) ? bp_key(d[i], i) : 0ull;
     nz += key[r] != 0;
   }
-  if (tid == 0) { s_prefix = 0; s_mask = 0; s_rank = BP_B; s_cnt = 0; s_below = 0; }
+  if (tid == 0) { s_prefix = 0; s_mask = 0; s_rank = BP_B; s_cnt = 0; s_below = 0; s_stop = 0; }
   // total nonzero keys: when at most BP_B, every one is a candidate
   for (int off = 32; off > 0; off >>= 1) nz += __shfl_xor(nz, off);
   __shared__ int wz[16];
@@ -538,6 +538,9 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
               s_prefix = pre | (digit << sh);
               s_mask = msk | (255ull << sh);
               s_rank = rank - (int)run;
+              // the whole bin is among the BP_B largest: keys >= the prefix
+              // (lower digits zero) are exactly the candidates
+              if (rank - (int)run == (int)c[q]) s_stop = 1;
               break;
             }
             run += c[q];
@@ -545,6 +548,7 @@ __global__ __launch_bounds__(1024) void k_bp_select(const double* d, const int* 
         }
       }
       __syncthreads();
+      if (s_stop) break;  // (uniform)
     }
     thr = s_prefix;
   }
