@@ -658,7 +658,7 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
   z.add_n<I2>(mL);                                              // leaf_pts
   z.add_n<z64>((size_t)mL * mL);                                // Gleaf64
   if (f32) z.add(e * mL * mL);                                  // Gleaf32
-  size_t sid = mem::round_up(4096) + ConvOperator::scratch_bytes(), ssib = 0, sgram = 0;
+  size_t sid = mem::round_up(4096) + ConvOperator::scratch_bytes(d.n), ssib = 0, sgram = 0;
   for (int l = 1; l <= L; ++l) {
     const size_t mk = (size_t)m[l] * k[l];
     z.add_n<z64>(mk);  // U64

@@ -66,8 +66,8 @@ void FFTPlan::init(int M_, hipStream_t s) {
   logM = 0;
   while ((1 << logM) < M) ++logM;
   LSH_REQUIRE((1 << logM) == M && M >= 2 && M <= 4096, -6, "FFT length must be a power of two <= 4096");
-  std::vector<z64> h(M / 2);
-  for (int k = 0; k < M / 2; ++k) {
+  std::vector<z64> h(M);
+  for (int k = 0; k < M; ++k) {
     long double a = -2.0L * 3.141592653589793238462643383279502884L * k / M;
     h[k] = mk((double)std::cos(a), (double)std::sin(a));
   }
@@ -119,9 +119,9 @@ __global__ __launch_bounds__(256) void k_fft_rows(const z64* __restrict__ in, lo
   }
   __syncthreads();
   fft_lds(x, M, logM, W, inv != 0);
-  if (mode == 1) {
-    const z64* sp = spec + r * ldspec;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = x[i] * sp[i];
+  if (mode == 1) {  // spectrum row min(r, M - r), entry min(i, M - i)
+    const z64* sp = spec + (r <= M - r ? r : M - r) * ldspec;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) x[i] = x[i] * sp[i <= M - i ? i : M - i];
     __syncthreads();
     // back to bit-reversed order for the inverse transform
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
@@ -144,12 +144,268 @@ __global__ __launch_bounds__(256) void k_fft_rows(const z64* __restrict__ in, lo
   }
 }
 
+// ---------------------------------------------- Stockham FFT in registers
+// Length M = 2^LOGM >= 64: T = M / 16 threads per row, each holding 16
+// values.  Passes of radix 16 (a last one of radix 2, 4 or 8 when LOGM is not
+// a multiple of 4) in Stockham's self-sorting form: with NS the product of the
+// earlier radices, butterfly j (< M / R) takes x[j + r M / R] (r < R),
+// multiplies entry r by w_M^(r (j mod NS) M / (NS R)), transforms the R values
+// in registers and puts entry r at (j / NS) NS R + (j mod NS) + r NS.  Input
+// and output are in natural order, so the first pass reads global memory and
+// the last writes it, coalesced, and only the exchanges between passes go
+// through LDS (one padded slot per 16 values keeps the radix-16 writes free
+// of bank conflicts).  Thread t runs butterflies t + T q, q < 16 / R.
+namespace fft16 {
+
+constexpr double kC[8] = {1.0,
+                          0.92387953251128675613,
+                          0.70710678118654752440,
+                          0.38268343236508977173,
+                          0.0,
+                          -0.38268343236508977173,
+                          -0.70710678118654752440,
+                          -0.92387953251128675613};  // cos(2 pi p / 16)
+constexpr double kS[8] = {0.0,
+                          0.38268343236508977173,
+                          0.70710678118654752440,
+                          0.92387953251128675613,
+                          1.0,
+                          0.92387953251128675613,
+                          0.70710678118654752440,
+                          0.38268343236508977173};  // sin(2 pi p / 16)
+
+constexpr int brev(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+constexpr int lg(int R) { return R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4; }
+
+// a * w_16^p (forward: w = exp(-2 pi i / 16); inverse: its conjugate)
+template <int P, bool INV>
+__device__ __forceinline__ z64 rot16(z64 a) {
+  if (P == 0) return a;
+  if (P == 4) return INV ? mk(-a.y, a.x) : mk(a.y, -a.x);
+  const double c = kC[P], sn = INV ? kS[P] : -kS[P];
+  return mk(a.x * c - a.y * sn, a.x * sn + a.y * c);
+}
+
+// In-register DFT of v[OFF .. OFF + R): out[k] = sum_r v[r] w_R^(r k), by
+// radix-2 decimation in time (bit-reversed loads, natural-order result).
+template <int R, bool INV, int OFF>
+__device__ __forceinline__ void dft(z64 (&v)[16]) {
+  constexpr int B = lg(R);
+  z64 a[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = v[OFF + brev(i, B)];
+#pragma unroll
+  for (int half = 1; half < R; half <<= 1)
+#pragma unroll
+    for (int i = 0; i < R; i += 2 * half)
+#pragma unroll
+      for (int p = 0; p < half; ++p) {
+        const int e = p * (16 / (2 * half));
+        z64 t;
+        switch (e) {  // compile-time after unrolling
+          case 0: t = rot16<0, INV>(a[i + p + half]); break;
+          case 1: t = rot16<1, INV>(a[i + p + half]); break;
+          case 2: t = rot16<2, INV>(a[i + p + half]); break;
+          case 3: t = rot16<3, INV>(a[i + p + half]); break;
+          case 4: t = rot16<4, INV>(a[i + p + half]); break;
+          case 5: t = rot16<5, INV>(a[i + p + half]); break;
+          case 6: t = rot16<6, INV>(a[i + p + half]); break;
+          default: t = rot16<7, INV>(a[i + p + half]); break;
+        }
+        const z64 u = a[i + p];
+        a[i + p] = u + t;
+        a[i + p + half] = u - t;
+      }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[OFF + i] = a[i];
+}
+
+template <int R, bool INV, int Q = 0>
+__device__ __forceinline__ void dft_all(z64 (&v)[16]) {
+  if constexpr (Q < 16 / R) {
+    dft<R, INV, Q * R>(v);
+    dft_all<R, INV, Q + 1>(v);
+  }
+}
+
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// twiddles of pass (R, NS) for thread t: w[q R + r] = w_M^(r (j mod NS) M / (NS R))
+template <int M, int R, int NS, bool INV>
+__device__ __forceinline__ void load_tw(z64 (&w)[16], int t, const z64* __restrict__ W) {
+  constexpr int T = M / 16, S = M / (NS * R);
+#pragma unroll
+  for (int q = 0; q < 16 / R; ++q) {
+    const int jm = (t + T * q) & (NS - 1);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      z64 x = W[r * jm * S];
+      if (INV) x.y = -x.y;
+      w[q * R + r] = x;
+    }
+  }
+}
+
+// passes from NS on; v holds the inputs of pass (R, NS) for thread t and w
+// its twiddles (loaded before the exchange that filled v, so that their
+// latency overlaps it)
+template <int M, int NS, bool INV>
+__device__ __forceinline__ void passes(z64 (&v)[16], z64 (&w)[16], z64* L, int t, const z64* __restrict__ W) {
+  constexpr int T = M / 16, R = (M / NS >= 16) ? 16 : M / NS;
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int q = 0; q < 16 / R; ++q)
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q * R + r] = v[q * R + r] * w[q * R + r];
+  }
+  dft_all<R, INV>(v);
+  if constexpr (NS * R < M) {
+    constexpr int R2 = (M / (NS * R) >= 16) ? 16 : M / (NS * R);
+    load_tw<M, R2, NS * R, INV>(w, t, W);
+    __syncthreads();  // every read of L by the previous exchange is done
+#pragma unroll
+    for (int q = 0; q < 16 / R; ++q) {
+      const int j = t + T * q, base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+      for (int r = 0; r < R; ++r) L[lpad(base + r * NS)] = v[q * R + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16 / R2; ++q)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[q * R2 + r] = L[lpad(t + T * q + r * (M / R2))];
+    passes<M, NS * R, INV>(v, w, L, t, W);
+  }
+}
+
+// radix and stride of the last pass: thread t ends holding, for q < 16 / RL
+// and r < RL, v[q RL + r] = X[t + T q + r M / RL]
+template <int M>
+struct Last {
+  static constexpr int RL = (M & 0x1111) ? 16 : (M & 0x2222) ? 2 : (M & 0x4444) ? 4 : 8;
+  static constexpr int NSL = M / RL;
+};
+
+}  // namespace fft16
+
+// Same arguments and modes as k_fft_rows; rows = ceil(grid / ...) handled by
+// ROWS rows per workgroup for short lengths.
+template <int LOGM>
+__global__ __launch_bounds__(256) void k_fft16_rows(const z64* __restrict__ in, long ldin, int nin, z64* out,
+                                                    long ldout, int nout, int nrows, const z64* __restrict__ W,
+                                                    int inv, int mode, const z64* __restrict__ spec, long ldspec,
+                                                    const z64* __restrict__ xadd, const double* __restrict__ b,
+                                                    double kb2, const double* __restrict__ preb, double prek) {
+  using namespace fft16;
+  constexpr int M = 1 << LOGM, T = M / 16, ROWS = T >= 64 ? 1 : 64 / T, LR = M + M / 16;
+  constexpr int RL = Last<M>::RL, NSL = Last<M>::NSL;
+  extern __shared__ unsigned char smem_raw[];
+  const int rw = threadIdx.x / T, t = threadIdx.x % T;
+  const long r = (long)blockIdx.x * ROWS + rw;
+  const bool ok = r < nrows;
+  z64* L = reinterpret_cast<z64*>(smem_raw) + rw * LR;
+  z64 v[16];
+  {
+    const z64* src = in + r * ldin;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int k = t + i * T;
+      z64 x = mk(0.0, 0.0);
+      if (ok && k < nin) {
+        x = src[k];
+        if (preb) x = (prek * preb[r * ldin + k]) * x;
+      }
+      v[i] = x;
+    }
+  }
+  z64 w[16];
+  if (inv) passes<M, 1, true>(v, w, L, t, W);
+  else passes<M, 1, false>(v, w, L, t, W);
+  if (mode == 1) {  // times the spectrum row (min(r, M - r), entry min(k, M - k)), then the inverse transform
+    const z64* sp = spec + (r <= M - r ? r : M - r) * ldspec;
+#pragma unroll
+    for (int q = 0; q < 16 / RL; ++q)
+#pragma unroll
+      for (int e = 0; e < RL; ++e) {
+        const int k = t + T * q + e * NSL;
+        if (ok) v[q * RL + e] = v[q * RL + e] * sp[k <= M - k ? k : M - k];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16 / RL; ++q)
+#pragma unroll
+      for (int e = 0; e < RL; ++e) L[lpad(t + T * q + e * NSL)] = v[q * RL + e];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = L[lpad(t + i * T)];
+    passes<M, 1, true>(v, w, L, t, W);
+  }
+  if (!ok) return;
+  z64* dst = out + r * ldout;
+#pragma unroll
+  for (int q = 0; q < 16 / RL; ++q)
+#pragma unroll
+    for (int e = 0; e < RL; ++e) {
+      const int k = t + T * q + e * NSL;
+      if (k >= nout) continue;
+      const z64 x = v[q * RL + e];
+      if (mode == 2) {
+        const long g = r * ldout + k;
+        dst[k] = xadd[g] + (kb2 * b[g]) * x;
+      } else if (mode == 4) {
+        dst[k] = xadd[r * ldout + k] + x;
+      } else {
+        dst[k] = x;
+      }
+    }
+}
+
+// One launch of the row transform (modes as k_fft_rows) on nrows rows.
+static void launch_fft_rows(hipStream_t s, const FFTPlan& P, int nrows, const z64* in, long ldin, int nin, z64* out,
+                            long ldout, int nout, int inv, int mode, const z64* spec, long ldspec, const z64* xadd,
+                            const double* b, double kb2, const double* preb, double prek) {
+  const z64* W = P.tw.as<z64>();
+  if (P.logM < 6) {
+    hipLaunchKernelGGL(k_fft_rows, dim3(nrows), dim3(256), P.M * sizeof(z64), s, in, ldin, nin, out, ldout, nout,
+                       P.M, P.logM, W, inv, mode, spec, ldspec, xadd, b, kb2, preb, prek);
+    LSH_LAUNCH_CHECK();
+    return;
+  }
+  const int T = P.M / 16, rows = T >= 64 ? 1 : 64 / T;
+  const size_t lds = sizeof(z64) * (size_t)rows * (P.M + P.M / 16);
+  const dim3 grid(ceil_div(nrows, rows)), block(rows * T);
+#define LSH_FFT16(LG)                                                                                         \
+  case LG:                                                                                                    \
+    hipLaunchKernelGGL(k_fft16_rows<LG>, grid, block, lds, s, in, ldin, nin, out, ldout, nout, nrows, W, inv, \
+                       mode, spec, ldspec, xadd, b, kb2, preb, prek);                                         \
+    break;
+  if (P.logM == 12) {  // 68 KB of LDS (above the 64 KB default of a launch)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft16_rows<12>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    LSH_HIP(attr);
+  }
+  switch (P.logM) {
+    LSH_FFT16(6)
+    LSH_FFT16(7)
+    LSH_FFT16(8)
+    LSH_FFT16(9)
+    LSH_FFT16(10)
+    LSH_FFT16(11)
+    LSH_FFT16(12)
+    default: LSH_REQUIRE(false, -6, "FFT length must be a power of two <= 4096");
+  }
+#undef LSH_FFT16
+  LSH_LAUNCH_CHECK();
+}
+
 void fft_rows(hipStream_t s, const FFTPlan& P, const z64* in, long ldin, int nin, z64* out, long ldout, int nout,
               int nrows, bool inverse) {
-  hipLaunchKernelGGL(k_fft_rows, dim3(nrows), dim3(256), P.M * sizeof(z64), s, in, ldin, nin, out, ldout, nout,
-                     P.M, P.logM, P.tw.as<z64>(), inverse ? 1 : 0, 0, (const z64*)nullptr, 0L,
-                     (const z64*)nullptr, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0);
-  LSH_LAUNCH_CHECK();
+  launch_fft_rows(s, P, nrows, in, ldin, nin, out, ldout, nout, inverse ? 1 : 0, 0, nullptr, 0L, nullptr, nullptr,
+                  0.0, nullptr, 0.0);
 }
 
 constexpr int TT = 32;
@@ -195,35 +451,48 @@ __global__ void k_add_stencil(z64* C, int M, const int* dxy, const z64* w, int c
   C[(long)iy * M + ix] = C[(long)iy * M + ix] + w[k];
 }
 
-__global__ void k_scale_c(z64* a, long n, double s) {
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i < n) a[i] = s * a[i];
+// khat[a][c] = s Kt[a][c] for a, c <= M / 2 (ld M / 2 + 1)
+__global__ void k_spectrum_quarter(const z64* __restrict__ Kt, int M, double s, z64* khat) {
+  const int H = M / 2 + 1;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)H * H) return;
+  const int a = (int)(e / H), c = (int)(e % H);
+  khat[e] = s * Kt[(long)a * M + c];
+}
+
+static int pad_len(int n) {
+  int M = 1;
+  while (M < 2 * n) M <<= 1;
+  return M;
 }
 
 size_t ConvOperator::bytes(int n) {
-  int M = 1;
-  while (M < 2 * n) M <<= 1;
+  const size_t M = pad_len(n), H = M / 2 + 1;
   mem::Sizer z;
-  z.add_n<z64>(M / 2);             // twiddles
-  z.add_n<z64>((size_t)M * M);     // khatT
+  z.add_n<z64>(M);                 // twiddles
+  z.add_n<z64>(H * H);             // khat (one quarter)
   z.add_n<z64>((size_t)n * M);     // w1
-  z.add_n<z64>((size_t)M * M);     // w2
+  z.add_n<z64>((size_t)n * M);     // w2
   return z.total;
 }
 
-size_t ConvOperator::scratch_bytes() { return 2 * mem::round_up(sizeof(z64) * 64); }
+size_t ConvOperator::scratch_bytes(int n) {
+  const size_t M = pad_len(n);
+  return 2 * mem::round_up(sizeof(z64) * 64) + 2 * mem::round_up(sizeof(z64) * M * M);
+}
 
 void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z64* table, int D,
                         const std::vector<StencilEntry>& stencil, mem::Arena& scr) {
   n = n_;
   kappa = kappa_;
-  M = 1;
-  while (M < 2 * n) M <<= 1;
+  M = pad_len(n);
+  const int H = M / 2 + 1;
   fft.init(M, s);
-  khatT.alloc(sizeof(z64) * (size_t)M * M);
+  khat.alloc(sizeof(z64) * (size_t)H * H);
   w1.alloc(sizeof(z64) * (size_t)n * M);
-  w2.alloc(sizeof(z64) * (size_t)M * M);
-  z64* C = w2.as<z64>();
+  w2.alloc(sizeof(z64) * (size_t)n * M);
+  z64* C = static_cast<z64*>(scr.take(sizeof(z64) * (size_t)M * M));
+  z64* Kt = static_cast<z64*>(scr.take(sizeof(z64) * (size_t)M * M));
   hipLaunchKernelGGL(k_fill_circulant, dim3(ceil_div((long)M * M, 256)), dim3(256), 0, s, C, M, n, table, D);
   LSH_LAUNCH_CHECK();
   std::vector<int> dxy;
@@ -240,23 +509,25 @@ void ConvOperator::init(hipStream_t s, int n_, double h, double kappa_, const z6
   LSH_HIP(hipMemcpyAsync(dw, wv.data(), sizeof(z64) * wv.size(), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_add_stencil, dim3(1), dim3(64), 0, s, C, M, ddxy, dw, (int)wv.size());
   LSH_LAUNCH_CHECK();
-  // full 2-D transform, kept transposed: khatT[k1][k2]
-  z64* Kt = khatT.as<z64>();
+  // full 2-D transform, transposed: Kt[k1][k2].  The kernel is even in each
+  // offset (G depends on |d|; the correction stencil covers whole symmetry
+  // orbits), so its transform is too: Kt[k1][k2] = Kt[M - k1][k2] =
+  // Kt[k1][M - k2] up to rounding, and only the quarter k1, k2 <= M / 2 is kept.
   fft_rows(s, fft, C, M, M, C, M, M, M, false);
   transpose_z(s, C, M, Kt, M, M, M);
   fft_rows(s, fft, Kt, M, M, Kt, M, M, M, false);
-  hipLaunchKernelGGL(k_scale_c, dim3(ceil_div((long)M * M, 256)), dim3(256), 0, s, Kt, (long)M * M,
-                     1.0 / ((double)M * M));
+  hipLaunchKernelGGL(k_spectrum_quarter, dim3(ceil_div((long)H * H, 256)), dim3(256), 0, s, Kt, M,
+                     1.0 / ((double)M * M), khat.as<z64>());
   LSH_LAUNCH_CHECK();
-  LSH_HIP(hipStreamSynchronize(s));  // the small staging buffers die here
+  LSH_HIP(hipStreamSynchronize(s));  // the staging and scratch buffers die here
 }
 
 void ConvOperator::apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs, bool transpose) {
-  // algorithmic bytes: read x (and b), write y, read the spectrum once
-  ProfScope ps("op_fft_operator", s, (double)nrhs * (16.0 * 2 * n * n + (b ? 8.0 * n * n : 0.0)) + 16.0 * M * M);
+  // algorithmic bytes: read x (and b), write y, read the spectrum quarter once
+  const double H = M / 2 + 1;
+  ProfScope ps("op_fft_operator", s, (double)nrhs * (16.0 * 2 * n * n + (b ? 8.0 * n * n : 0.0)) + 16.0 * H * H);
   z64* W1 = w1.as<z64>();
   z64* W2 = w2.as<z64>();
-  const size_t lds = M * sizeof(z64);
   const double k2 = kappa * kappa;
   const z64* nz = nullptr;
   const double* nd = nullptr;
@@ -264,19 +535,15 @@ void ConvOperator::apply(hipStream_t s, const double* b, const z64* x, z64* y, i
     const z64* xr = x + (long)r * n * n;
     z64* yr = y + (long)r * n * n;
     // rows (x1 direction) of the n data rows, padded to M (A^T: scaled by kappa^2 b first)
-    hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, xr, (long)n, n, W1, (long)M, M, M, fft.logM,
-                       fft.tw.as<z64>(), 0, 0, nz, 0L, nz, nd, 0.0, (transpose && b) ? b : nd, k2);
-    LSH_LAUNCH_CHECK();
+    launch_fft_rows(s, fft, n, xr, (long)n, n, W1, (long)M, M, 0, 0, nz, 0L, nz, nd, 0.0,
+                    (transpose && b) ? b : nd, k2);
     transpose_z(s, W1, M, W2, n, n, M);  // W2: M x n
     // columns: transform, multiply by the spectrum, transform back, keep n
-    hipLaunchKernelGGL(k_fft_rows, dim3(M), dim3(256), lds, s, W2, (long)n, n, W2, (long)n, n, M, fft.logM,
-                       fft.tw.as<z64>(), 0, 1, khatT.as<z64>(), (long)M, nz, nd, 0.0, nd, 0.0);
-    LSH_LAUNCH_CHECK();
+    launch_fft_rows(s, fft, M, W2, (long)n, n, W2, (long)n, n, 0, 1, khat.as<z64>(), (long)(M / 2 + 1), nz, nd, 0.0,
+                    nd, 0.0);
     transpose_z(s, W2, n, W1, M, M, n);  // W1: n x M
     const int mode = !b ? 3 : (transpose ? 4 : 2);
-    hipLaunchKernelGGL(k_fft_rows, dim3(n), dim3(256), lds, s, W1, (long)M, M, yr, (long)n, n, M, fft.logM,
-                       fft.tw.as<z64>(), 1, mode, nz, 0L, b ? xr : nz, b, k2, nd, 0.0);
-    LSH_LAUNCH_CHECK();
+    launch_fft_rows(s, fft, n, W1, (long)M, M, yr, (long)n, n, 1, mode, nz, 0L, b ? xr : nz, b, k2, nd, 0.0);
   }
 }
 

@@ -8,7 +8,7 @@ namespace lsh {
 // Power-of-two FP64 FFT of rows held in LDS (length <= 4096).
 struct FFTPlan {
   int M = 0, logM = 0;
-  DevBuf tw;  // exp(-2 pi i k / M), k < M/2
+  DevBuf tw;  // exp(-2 pi i k / M), k < M
   void init(int M_, hipStream_t s);
 };
 
@@ -25,14 +25,14 @@ struct ConvOperator {
   int n = 0, M = 0;
   double kappa = 0;
   FFTPlan fft;
-  DevBuf khatT;     // transposed spectrum of the kernel, scaled by 1/M^2
+  DevBuf khat;      // spectrum of the kernel scaled by 1/M^2, rows and columns 0 .. M/2 (even in both)
   DevBuf w1, w2;    // n x M and M x n work arrays
   // (device memory from the bound arena; scr: staging of the stencil)
   void init(hipStream_t s, int n_, double h, double kappa_, const z64* table, int D,
             const std::vector<StencilEntry>& stencil, mem::Arena& scr);
   // bytes that init takes from the bound arena, and from scr
   static size_t bytes(int n);
-  static size_t scratch_bytes();
+  static size_t scratch_bytes(int n);
   // b == nullptr: y = K * x ; otherwise y = x + kappa^2 b (K * x), or with
   // transpose the transposed operator y = x + K * (kappa^2 b x)
   void apply(hipStream_t s, const double* b, const z64* x, z64* y, int nrhs, bool transpose = false);

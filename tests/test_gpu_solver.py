@@ -70,6 +70,32 @@ def test_operator_matches_dense(n, order, use_b):
         assert np.abs(y[r].reshape(-1) - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,leaf", [(48, 6), (96, 6), (128, 8), (192, 6), (384, 6), (512, 8), (768, 6),
+                                    (1536, 6)])
+def test_operator_matches_oracle_fft(n, leaf):
+    """Every transform length the operator uses, 2n rounded up to a power of
+    two from 128 to 4096 (sides that fill half the padded length and sides
+    that do not), against the oracle's numpy FFT operator; the relative error
+    bound is as for the dense check."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    rng = np.random.default_rng(n)
+    kappa = 0.3 * n
+    b = rng.uniform(-1, 0.9, (n, n))
+    x = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    P = lsh.Plan(n, kappa, op_order=10, leaf=leaf, tol=1e-3, proxy_width=2, prec="fp32")
+    try:
+        y = P.apply_operator(cuda(b), cuda(x)).cpu().numpy()
+        k = P.apply_operator(None, cuda(x)).cpu().numpy()
+    finally:
+        P.close()
+    torch.cuda.empty_cache()
+    op = fftop.FFTOperator(n, kappa, 10)
+    yr, kr = op.apply(b, x), op.conv(x)
+    assert np.abs(y - yr).max() <= 1e-13 * np.abs(yr).max()
+    assert np.abs(k - kr).max() <= 1e-13 * np.abs(kr).max()
+
+
 @pytest.mark.parametrize("n,tol,width,method,alpha", [(32, 1e-10, 3, "panel", 1), (64, 1e-4, 2, "panel", 1),
                                                       (128, 1e-5, 2, "panel", 1), (64, 1e-4, 2, "block", 1),
                                                       (128, 1e-5, 2, "block", 1), (64, 1e-4, 2, "block", 0.75),
