@@ -117,7 +117,6 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
       const int gm = m0 + m, gk = k0 + k;
       cplx<R> v = mk<R>(0, 0);
       if (gm < P.M && gk < P.K) v = aN ? A[(long)gm * P.lda + gk] : A[(long)gk * P.lda + gm];
-      if (aC) v.y = -v.y;
       ra[e] = v;
     }
 #pragma unroll
@@ -129,7 +128,6 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
       const int gn = n0 + n, gk = k0 + k;
       cplx<R> v = mk<R>(0, 0);
       if (gn < P.N && gk < P.K) v = bN ? B[(long)gk * P.ldb + gn] : B[(long)gn * P.ldb + gk];
-      if (bC) v.y = -v.y;
       rb[e] = v;
     }
   };
@@ -141,7 +139,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
       if (aN) { m = idx / GBK; k = idx % GBK; }
       else { k = idx / BM; m = idx % BM; }
       sAr[m][k] = ra[e].x;
-      sAi[m][k] = ra[e].y;
+      sAi[m][k] = aC ? -ra[e].y : ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -150,7 +148,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
       if (bN) { k = idx / BN; n = idx % BN; }
       else { n = idx / GBK; k = idx % GBK; }
       sBr[n][k] = rb[e].x;
-      sBi[n][k] = rb[e].y;
+      sBi[n][k] = bC ? -rb[e].y : rb[e].y;
     }
   };
   load(0);
@@ -261,7 +259,6 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       const int gm = m0 + m, gk = k0 + k;
       cplx<float> v = mk<float>(0, 0);
       if (gm < P.M && gk < P.K) v = aN ? A[(long)gm * P.lda + gk] : A[(long)gk * P.lda + gm];
-      if (aC) v.y = -v.y;
       ra[e] = v;
     }
 #pragma unroll
@@ -273,7 +270,6 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       const int gn = n0 + n, gk = k0 + k;
       cplx<float> v = mk<float>(0, 0);
       if (gn < P.N && gk < P.K) v = bN ? B[(long)gk * P.ldb + gn] : B[(long)gn * P.ldb + gk];
-      if (bC) v.y = -v.y;
       rb[e] = v;
     }
   };
@@ -285,7 +281,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       if (aN) { m = idx / BK; k = idx % BK; }
       else { k = idx / BM; m = idx % BM; }
       sAr[m][k] = ra[e].x;
-      sAi[m][k] = ra[e].y;
+      sAi[m][k] = aC ? -ra[e].y : ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -294,7 +290,7 @@ __device__ __forceinline__ void cgemm_x32_tile(const GemmP<float>& P, long b, in
       if (bN) { k = idx / BN; n = idx % BN; }
       else { n = idx / BK; k = idx % BK; }
       sBr[n][k] = rb[e].x;
-      sBi[n][k] = rb[e].y;
+      sBi[n][k] = bC ? -rb[e].y : rb[e].y;
     }
   };
   load(0);

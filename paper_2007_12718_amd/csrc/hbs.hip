@@ -642,23 +642,6 @@ __global__ __launch_bounds__(256) void k_bp_sc(const z64* Lt, int m, const int* 
   }
 }
 
-// S_C = M[C,C] - sum_c part[c]  (rows/columns past the candidates: zero)
-__global__ void k_bp_sc_reduce(const z64* M, int m, const z64* part, const int* st, z64* S) {
-  if (st[BPS_DONE]) return;
-  const int j = st[BPS_J], nc = st[BPS_NC];
-  const int nch = (j + BP_KCS - 1) / BP_KCS;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= BP_B * BP_B) return;
-  const int a = e / BP_B, b = e % BP_B;
-  const int* cand = st + BPS_CAND;
-  z64 v = mk(0.0, 0.0);
-  if (a < nc && b < nc) {
-    v = M[(long)cand[a] * m + cand[b]];
-    for (int c = 0; c < nch; ++c) v = v - part[(long)c * BP_B * BP_B + e];
-  }
-  S[e] = v;
-}
-
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   return __longlong_as_double(
@@ -666,8 +649,9 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
                   (unsigned)__builtin_amdgcn_readlane((int)bits, lane)));
 }
 
-// Greedy pivoted Cholesky of the candidate block S (first nc rows valid)
-// while the pivot exceeds thr2 and, after the first, is not below alpha * dout; at
+// Greedy pivoted Cholesky of the candidate block S_C = M[C,C] - sum_c
+// part[c] (formed first, in LDS; zero past the nc candidates) while the
+// pivot exceeds thr2 and, after the first, is not below alpha * dout; at
 // most BP_NP pivots.  Writes J[j + q], the pivot count, Lpp (np x np, lower,
 // pivot order) and Linv = Lpp^{-1}, both with ld BP_NP; sets done when no
 // pivot qualifies.
@@ -683,10 +667,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // largest count as ties, won by the lower candidate.  L_PP^{-1} follows by
 // forward substitution inside each wave.
 constexpr int BP_CW = 4, BP_CR = BP_B / BP_CW;  // waves, rows per wave
-__global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, double alpha, int* J, int* st,
-                                                        z64* Lpp, z64* Linv) {
+__global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* M, const z64* part, int m, double alpha, int* J,
+                                                        int* st, z64* Lpp, z64* Linv) {
   static_assert(BP_B <= 64 && BP_NP == 32 && BP_B % BP_CW == 0 && BP_CW * 8 == BP_NP,
                 "one lane per candidate; 8 columns of L_PP^{-1} per wave");
+  __shared__ z64 Ss[BP_B][BP_B + 1];   // S_C
   __shared__ z64 Lb[BP_B][BP_NP + 1];  // factor columns for every candidate row
   __shared__ z64 xs[BP_NP][BP_NP + 1]; // L_PP^{-1}
   __shared__ double rlv[BP_NP];        // 1 / L[t][t]
@@ -697,11 +682,33 @@ __global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, do
   const double dout = alpha * reinterpret_cast<const double*>(st + BPS_DOUT)[0];
   const double thr2 = reinterpret_cast<const double*>(st + BPS_THR)[0];
   const int* cand = st + BPS_CAND;
+  {  // S_C: the Gram entries less the depth chunks' partial products, in chunk order
+    const int nch = (j + BP_KCS - 1) / BP_KCS;
+    constexpr long CS = (long)BP_B * BP_B;
+    for (int e = tid; e < BP_B * BP_B; e += 64 * BP_CW) {
+      const int a = e / BP_B, c2 = e % BP_B;
+      z64 v = mk(0.0, 0.0);
+      if (a < nc && c2 < nc) {
+        v = M[(long)cand[a] * m + cand[c2]];
+        const z64* pp = part + e;
+        int c = 0;
+        for (; c + 4 <= nch; c += 4) {
+          const z64 p0 = pp[(c + 0) * CS], p1 = pp[(c + 1) * CS], p2 = pp[(c + 2) * CS], p3 = pp[(c + 3) * CS];
+          v = v - p0;
+          v = v - p1;
+          v = v - p2;
+          v = v - p3;
+        }
+        for (; c < nch; ++c) v = v - pp[c * CS];
+      }
+      Ss[a][c2] = v;
+    }
+    __syncthreads();
+  }
   z64 col[BP_CR];
 #pragma unroll
-  for (int i = 0; i < BP_CR; ++i)
-    col[i] = (r0 + i < nc && b < nc) ? Sg[(r0 + i) * BP_B + b] : mk(0.0, 0.0);
-  double d = b < nc ? Sg[b * BP_B + b].x : 0.0;
+  for (int i = 0; i < BP_CR; ++i) col[i] = (r0 + i < nc && b < nc) ? Ss[r0 + i][b] : mk(0.0, 0.0);
+  double d = b < nc ? Ss[b][b].x : 0.0;
   unsigned long long picked = 0;  // (the same in every lane)
   auto pick = [&]() -> int {      // largest unpicked diagonal, or -1
     unsigned key = 0;
@@ -811,9 +818,10 @@ __global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* Sg, int m, do
 // rows).  The pivot rows' conjugated values for the chunk sit in LDS (real
 // and imaginary planes); each wave owns 64 rows i and streams their factor
 // entries from HBM (16 consecutive rows per instruction operand, the next
-// four depths in flight).  Four real products per complex step; the second
-// pivot tile is skipped when np <= 16.  Rows already chosen are computed too
-// (the new-columns kernel ignores them).
+// four depths in flight).  Three real products per complex step (Gauss's
+// form: t1 = ar br, t2 = ai bi, t3 = (ar + ai)(br + bi); Re = t1 - t2,
+// Im = t3 - t1 - t2); the second pivot tile is skipped when np <= 16.  Rows
+// already chosen are computed too (the new-columns kernel ignores them).
 // rows per workgroup: four waves of 16 JT rows.  The MFMA work of a
 // workgroup, not the memory, bounds a launch here (FP64 16x16x4 at 64 cycles
 // a wave), and early steps have few depth chunks: small row blocks (JT = 1)
@@ -839,13 +847,14 @@ __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int 
   constexpr int JT = BP_WT_JT;
   const int i0 = blockIdx.x * BP_WT_ROWS + wave * 16 * JT, lr = lane & 15, lk = lane >> 4;
   const bool two = np > 16;
-  d4 wr[2][JT], wi[2][JT];
+  d4 w1[2][JT], w2[2][JT], w3[2][JT];
 #pragma unroll
   for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
     for (int jt = 0; jt < JT; ++jt) {
-      wr[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
-      wi[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
+      w1[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
+      w2[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
+      w3[qt][jt] = d4{0.0, 0.0, 0.0, 0.0};
     }
   // B (the rows' factor entries) streams in stages of WT_DS depths: the next
   // stage's loads are issued before the current stage's MFMAs, so that a
@@ -873,16 +882,18 @@ __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int 
 #pragma unroll
     for (int u = 0; u < WT_SUB; ++u) {
       const int t = s0 + 4 * u + lk;  // (< BP_KC: s0 <= BP_KC - WT_DS, BP_KC % WT_DS == 0)
+      double bs[JT];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) bs[jt] = br[u][jt] + bi[u][jt];
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt) {
         if (qt == 1 && !two) break;
-        const double ar = Apr[16 * qt + lr][t], ai = Api[16 * qt + lr][t], nai = -ai;
+        const double ar = Apr[16 * qt + lr][t], ai = Api[16 * qt + lr][t], as = ar + ai;
 #pragma unroll
         for (int jt = 0; jt < JT; ++jt) {
-          wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br[u][jt], wr[qt][jt], 0, 0, 0);
-          wr[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi[u][jt], wr[qt][jt], 0, 0, 0);
-          wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi[u][jt], wi[qt][jt], 0, 0, 0);
-          wi[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br[u][jt], wi[qt][jt], 0, 0, 0);
+          w1[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br[u][jt], w1[qt][jt], 0, 0, 0);
+          w2[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi[u][jt], w2[qt][jt], 0, 0, 0);
+          w3[qt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bs[jt], w3[qt][jt], 0, 0, 0);
         }
       }
     }
@@ -904,7 +915,10 @@ __global__ __launch_bounds__(256) void k_bp_wt(const z64* Lt, const int* J, int 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int q = 16 * qt + lk + 4 * r, i = i0 + 16 * jt + lr;
-        if (q < np && i < m) pc[(long)q * m + i] = mk(wr[qt][jt][r], wi[qt][jt][r]);
+        if (q < np && i < m) {
+          const double t1 = w1[qt][jt][r], t2 = w2[qt][jt][r];
+          pc[(long)q * m + i] = mk(t1 - t2, w3[qt][jt][r] - t1 - t2);
+        }
       }
   }
 }
@@ -1076,7 +1090,6 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
   int* st = static_cast<int*>(take(sizeof(int) * BPS_WORDS));
   z64* Lpp = static_cast<z64*>(take(sizeof(z64) * BP_NP * BP_NP));
   z64* Linv = static_cast<z64*>(take(sizeof(z64) * BP_NP * BP_NP));
-  z64* Sc = static_cast<z64*>(take(sizeof(z64) * BP_B * BP_B));
   z64* partS = static_cast<z64*>(take(sizeof(z64) * (size_t)nchS * BP_B * BP_B));
   z64* partW = static_cast<z64*>(take(sizeof(z64) * (size_t)nch * BP_NP * m));
   const int DB = 64;
@@ -1112,11 +1125,9 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
       LSH_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_bp_sc, dim3(nchS, 4), dim3(256), 0, s, Lt, m, st, partS);
       LSH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_bp_sc_reduce, dim3(ceil_div(BP_B * BP_B, 256)), dim3(256), 0, s, M, m, partS, st, Sc);
-      LSH_LAUNCH_CHECK();
       {
         ProfScope ps("bp_chol", s, 16.0 * BP_B * BP_B);
-        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(64 * BP_CW), 0, s, Sc, m, alpha, J, st, Lpp, Linv);
+        hipLaunchKernelGGL(k_bp_chol, dim3(1), dim3(64 * BP_CW), 0, s, M, partS, m, alpha, J, st, Lpp, Linv);
       }
       LSH_LAUNCH_CHECK();
       {
