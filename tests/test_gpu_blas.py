@@ -34,6 +34,32 @@ def test_gemm_matches_definition(prec, opA, opB):
     assert np.abs(C - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("offset", [0, 1])
+@pytest.mark.parametrize("opA", [0, 1, 2, 3])
+@pytest.mark.parametrize("opB", [0, 1, 2, 3])
+def test_gemm_interior_tiles_every_layout(opA, opB, offset):
+    """Every operand form on a product with whole interior tiles and a
+    ragged edge in M, N and K, with operands that start 16-byte aligned
+    (offset 0) or not (offset 1 element) and odd and even leading dimensions,
+    against the definition in FP64."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    rng = np.random.default_rng(16 * opA + 4 * opB + offset)
+    M, N, K, B = 197, 131, 263 + offset, 2
+    A = _rand((B, M, K) if opA in (0, 3) else (B, K, M), rng, np.complex64)
+    Bm = _rand((B, K, N) if opB in (0, 3) else (B, N, K), rng, np.complex64)
+
+    def dev(x):  # a device copy whose data starts `offset` elements into its buffer
+        buf = torch.zeros(x.size + offset, dtype=torch.complex64, device="cuda")
+        v = buf[offset:].view(x.shape)
+        v.copy_(torch.from_numpy(x))
+        return v
+
+    C = lsh.dev_gemm(dev(A), dev(Bm), opA, opB, 0.7 - 0.2j).cpu().numpy()
+    ref = (0.7 - 0.2j) * (_op(A.astype(np.complex128), opA) @ _op(Bm.astype(np.complex128), opB))
+    assert np.abs(C - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("opA,opB", [(0, 0), (0, 1), (2, 3)])
 @pytest.mark.parametrize("M,N,K,B", [(300, 379, 502, 1), (128, 70, 1990, 2), (70, 64, 130, 1), (65, 1, 4100, 3),
                                      (300, 379, 100, 1), (4096, 58, 70, 2), (512, 45, 40, 1)])
