@@ -1947,22 +1947,47 @@ __global__ __launch_bounds__(256) void k_merge_level(const MergeLevelDev* G, int
     gemm_all_tiles(gp(r, r, r, -1, W, r2, 0, OP_N, Bw, r, 0, OP_N, 0, nullptr, 0, 0, W + r, r2, 0, 1), 0);
     gemm_all_tiles(gp(r, r, r, -1, Cm, r, 0, OP_N, Bw, r, 0, OP_N, 0, nullptr, 0, 0, W + r * r2 + r, r2, 0, 0), 0);
     if (!g.U) continue;  // (the root has no scattering matrix)
-    // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] with a = [S_a U1; S_b U2], then S = U^T X D U
+    // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] with a = [S_a U1; S_b U2], then S = U^T X D U,
+    // the products with U through its rows off the skeleton (as the separate launches)
     c32* a = g.A12 + t * 2 * ck;
     c32* q = g.Qb + t * 4 * rk;
     c32* y = q + 2 * rk;
-    const c32* U1 = g.U;
-    const c32* U2 = g.U + ck;
-    gemm_all_tiles(gp(c, k, c, 1, Sa, c, 0, OP_N, U1, k, 0, OP_N, 0, nullptr, 0, 0, a, k, 0, 0), 0);
-    gemm_all_tiles(gp(c, k, c, 1, Sa + cc, c, 0, OP_N, U2, k, 0, OP_N, 0, nullptr, 0, 0, a + ck, k, 0, 0), 0);
+    const int nh[2] = {g.n0, g.n1}, nr = g.n0 + g.n1;
+    c32* Gb = g.G + t * (long)c * nr;
+    c32* Rb = g.Rg + t * (long)nr * k;
+    for (int h = 0; h < 2; ++h) {  // a_h: the skeleton columns of S_h placed; S_h[:, rest_h] gathered
+      const c32* Sh = Sa + h * cc;
+      c32* ah = a + h * ck;
+      for (long e = threadIdx.x; e < ck; e += blockDim.x) {
+        const int col = g.skel[e % k] - h * c;
+        ah[e] = (col >= 0 && col < c) ? Sh[(e / k) * c + col] : mk<float>(0, 0);
+      }
+      c32* Gh = Gb + (h ? (long)c * nh[0] : 0L);
+      const int* rh = g.rest + (h ? nh[0] : 0);
+      for (long e = threadIdx.x; e < (long)c * nh[h]; e += blockDim.x)
+        Gh[e] = Sh[(e / nh[h]) * c + rh[e % nh[h]] - h * c];
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h)
+      if (nh[h] > 0)
+        gemm_all_tiles(gp(c, k, nh[h], 1, Gb + (h ? (long)c * nh[0] : 0L), nh[h], 0, OP_N,
+                          g.Ur + (h ? (long)nh[0] * k : 0L), k, 0, OP_N, 1, a + h * ck, k, 0, a + h * ck, k, 0, 0),
+                       0);
     gemm_all_tiles(gp(r, k, c, 1, Lt, c, 0, OP_N, a, k, 0, OP_N, 0, nullptr, 0, 0, q, k, 0, 0), 0);
     gemm_all_tiles(gp(r, k, c, 1, Rt, c, 0, OP_N, a + ck, k, 0, OP_N, 0, nullptr, 0, 0, q + rk, k, 0, 0), 0);
     gemm_all_tiles(gp(2 * r, k, 2 * r, 1, W, r2, 0, OP_N, q, k, 0, OP_N, 0, nullptr, 0, 0, y, k, 0, 0), 0);
     gemm_all_tiles(gp(c, k, r, -1, Pst, r, 0, OP_N, y, k, 0, OP_N, 1, a, k, 0, a, k, 0, 0), 0);
     gemm_all_tiles(gp(c, k, r, -1, Pst + cr, r, 0, OP_N, y + rk, k, 0, OP_N, 1, a + ck, k, 0, a + ck, k, 0, 0), 0);
     c32* S = g.S + t * (long)k * k;
-    gemm_all_tiles(gp(k, k, c, 1, U1, k, 0, OP_T, a, k, 0, OP_N, 0, nullptr, 0, 0, S, k, 0, 0), 0);
-    gemm_all_tiles(gp(k, k, c, 1, U2, k, 0, OP_T, a + ck, k, 0, OP_N, 1, S, k, 0, S, k, 0, 0), 0);
+    // S: the skeleton rows of a placed; a_h[rest_h, :] gathered; then T_h^T of them added
+    for (long e = threadIdx.x; e < (long)k * k; e += blockDim.x) S[e] = a[(long)g.skel[e / k] * k + e % k];
+    for (long e = threadIdx.x; e < (long)nr * k; e += blockDim.x) Rb[e] = a[(long)g.rest[e / k] * k + e % k];
+    __syncthreads();
+    for (int h = 0; h < 2; ++h)
+      if (nh[h] > 0)
+        gemm_all_tiles(gp(k, k, nh[h], 1, g.Ur + (h ? (long)nh[0] * k : 0L), k, 0, OP_T,
+                          Rb + (h ? (long)nh[0] * k : 0L), k, 0, OP_N, 1, S, k, 0, S, k, 0, 0),
+                       0);
   }
 }
 
@@ -1981,8 +2006,9 @@ void merge_levels(hipStream_t s, const std::vector<MergeLevelDev>& levels, DevBu
     total += g.nb;
     rmax = g.r > rmax ? g.r : rmax;
     const double c = g.c, r = g.r, k = g.k;
+    const double nr = g.n0 + g.n1;
     flops += 8.0 * g.nb * (2 * c * r * c + 2 * r * r * c + 4 * r * r * r +
-                           (g.U ? 2 * c * k * c + 2 * r * k * c + 4 * r * r * k + 2 * c * k * r + 2 * k * k * c : 0));
+                           (g.U ? c * k * nr + 2 * r * k * c + 4 * r * r * k + 2 * c * k * r + k * k * nr : 0));
     h.push_back(g);
   }
   if (h.empty()) return;
@@ -2020,6 +2046,56 @@ void ccopy2d(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, lo
   if (total <= 0) return;
   const long g = std::min<long>(ceil_div(total, 256L), 65536L);
   hipLaunchKernelGGL(k_ccopy2d<R>, dim3((unsigned)g), dim3(256), 0, s, rows, cols, src, lds, ss, dst, ldd, sd, total);
+  LSH_LAUNCH_CHECK();
+}
+
+// dst[b][i][j] = src[b][i][idx[j] - off] where 0 <= idx[j] - off < lim, else 0
+template <typename R>
+__global__ void k_gather_cols(int rows, int cols, const cplx<R>* __restrict__ src, long lds, long ss,
+                              const int* __restrict__ idx, int off, int lim, cplx<R>* dst, long ldd, long sd,
+                              long total) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long b = e / ((long)rows * cols), q = e - b * rows * cols;
+    const long i = q / cols, j = q - i * cols;
+    const int col = idx[j] - off;
+    dst[b * sd + i * ldd + j] = (col >= 0 && col < lim) ? src[b * ss + i * lds + col] : mk<R>(0, 0);
+  }
+}
+
+template <typename R>
+void gather_cols(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, long ss, const int* idx, int off,
+                 int lim, cplx<R>* dst, long ldd, long sd, long batch) {
+  const long total = (long)rows * cols * batch;
+  if (total <= 0) return;
+  const long g = std::min<long>(ceil_div(total, 256L), 65536L);
+  hipLaunchKernelGGL(k_gather_cols<R>, dim3((unsigned)g), dim3(256), 0, s, rows, cols, src, lds, ss, idx, off, lim,
+                     dst, ldd, sd, total);
+  LSH_LAUNCH_CHECK();
+}
+
+// dst[b][i][j] = row t = idx[i] - off of [src0[b]; src1[b]] (rows t < c of
+// src0, the others row t - c of src1), column j
+template <typename R>
+__global__ void k_gather_rows2(int rows, int cols, const cplx<R>* __restrict__ src0, const cplx<R>* __restrict__ src1,
+                               int c, long lds, long ss, const int* __restrict__ idx, int off, cplx<R>* dst,
+                               long ldd, long sd, long total) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long b = e / ((long)rows * cols), q = e - b * rows * cols;
+    const long i = q / cols, j = q - i * cols;
+    const int t = idx[i] - off;
+    const cplx<R>* src = t < c ? src0 + b * ss + (long)t * lds : src1 + b * ss + (long)(t - c) * lds;
+    dst[b * sd + i * ldd + j] = src[j];
+  }
+}
+
+template <typename R>
+void gather_rows2(hipStream_t s, int rows, int cols, const cplx<R>* src0, const cplx<R>* src1, int c, long lds,
+                  long ss, const int* idx, int off, cplx<R>* dst, long ldd, long sd, long batch) {
+  const long total = (long)rows * cols * batch;
+  if (total <= 0) return;
+  const long g = std::min<long>(ceil_div(total, 256L), 65536L);
+  hipLaunchKernelGGL(k_gather_rows2<R>, dim3((unsigned)g), dim3(256), 0, s, rows, cols, src0, src1, c, lds, ss, idx,
+                     off, dst, ldd, sd, total);
   LSH_LAUNCH_CHECK();
 }
 
@@ -2094,6 +2170,10 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
   template void cmgemv2<R>(hipStream_t, int, int, long, int, cplx<R>, const cplx<R>*, long, const cplx<R>*,   \
                            long, cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                        \
   template void ccopy2d<R>(hipStream_t, int, int, const cplx<R>*, long, long, cplx<R>*, long, long, long);   \
+  template void gather_cols<R>(hipStream_t, int, int, const cplx<R>*, long, long, const int*, int, int,      \
+                               cplx<R>*, long, long, long);                                                  \
+  template void gather_rows2<R>(hipStream_t, int, int, const cplx<R>*, const cplx<R>*, int, long, long,      \
+                                const int*, int, cplx<R>*, long, long, long);                                \
   template void caxpby<R>(hipStream_t, int, int, cplx<R>, const cplx<R>*, long, cplx<R>, const cplx<R>*, long,  \
                           cplx<R>*, long);                                                                  \
   template size_t inverse_ws_bytes<R>(int, int);                                                           \

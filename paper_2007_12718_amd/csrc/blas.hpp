@@ -136,6 +136,14 @@ struct MergeLevelDev {
   int *info, *perm;
   int c, r, k, nb;
   long item0;
+  // the scattering matrix's products with U skip its identity rows: U's
+  // other rows Ur = U[rest, :] (n0 of them in half 0, n1 in half 1), the
+  // candidate indices rest and skel (= J), and per box the gathered columns
+  // G (c x (n0 + n1)) and rows Rg ((n0 + n1) x k)
+  const c32* Ur;
+  const int *rest, *skel;
+  int n0, n1;
+  c32 *G, *Rg;
 };
 bool merge_level_fits(int r);
 size_t merge_level_table_bytes(size_t levels);
@@ -153,6 +161,18 @@ void caxpby(hipStream_t s, int n, int nv, cplx<R> alpha, const cplx<R>* X, long 
 template <typename R>
 void ccopy2d(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, long ss, cplx<R>* dst, long ldd,
              long sd, long batch = 1);
+
+// dst_b[i][j] = src_b[i][idx[j] - off] where 0 <= idx[j] - off < lim, else 0
+// (rows x cols outputs; leading dimensions lds, ldd; batch strides ss, sd)
+template <typename R>
+void gather_cols(hipStream_t s, int rows, int cols, const cplx<R>* src, long lds, long ss, const int* idx, int off,
+                 int lim, cplx<R>* dst, long ldd, long sd, long batch);
+// dst_b[i][:] = row t = idx[i] - off of [src0_b; src1_b] (rows t < c from
+// src0, the others row t - c of src1; both with leading dimension lds and
+// batch stride ss), cols entries each
+template <typename R>
+void gather_rows2(hipStream_t s, int rows, int cols, const cplx<R>* src0, const cplx<R>* src1, int c, long lds,
+                  long ss, const int* idx, int off, cplx<R>* dst, long ldd, long sd, long batch);
 
 // dst (R2) = src (R1), elementwise, n complex entries
 template <typename R1, typename R2>

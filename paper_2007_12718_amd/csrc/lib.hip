@@ -7,6 +7,7 @@
 //          C = I - Pb Pa:  X [a; b] = [a - Pa y; y], y = C^{-1} (b - Pb a).
 // apply  : Algorithm 2 (up l = L-1..1, root solve, down l = 1..L-1, leaves).
 // solve  : right-preconditioned flexible GMRES on the order-p FFT operator.
+#include <array>
 #include <chrono>
 #include <complex>
 #include <cmath>
@@ -54,6 +55,14 @@ struct Level {
   DevBuf U64, U32;       // m x k
   DevBuf Ut64, Ut32;     // k x m (transpose, for row-streamed products)
   bool ident = false;    // U = I (k = m): the level keeps all its candidates
+  // U is the identity on the skeleton rows J.  For the factor's products
+  // with U (levels 1 .. L-1, candidates of half h: h m/2 .. h m/2 + m/2 - 1):
+  // the other rows ("rest", ascending; nrest0 of them in half 0), and on the
+  // device their indices, J, and T = U[rest, :] ((m - k) x k).
+  std::vector<int> rest;
+  int nrest0 = 0;
+  DevBuf restIdx, skelIdx;
+  DevBuf T64, T32;
   DevBuf Gab64, Gab32;   // sibling block of this parent level (c x c, c = k of level+1)
   DevBuf Gabt64, Gabt32; // its transpose
   int c = 0;
@@ -105,6 +114,10 @@ struct lsh_plan_s {
   const cplx<R>* Ut(int l) const;
   template <typename R>
   const cplx<R>* Gabt(int l) const;
+  template <typename R>
+  const cplx<R>* T(int l) const {
+    return static_cast<const cplx<R>*>(sizeof(R) == 8 ? lev[l].T64.p : lev[l].T32.p);
+  }
   // low-rank sibling factors of parent level l: 0 L, 1 L^T, 2 R, 3 R^T
   // (L and R stacked in [L; R], L^T and R^T in [L^T; R^T])
   template <typename R>
@@ -440,6 +453,38 @@ void plan_init(lsh_plan_s& P, hipStream_t s) {
 }
 
 // row ID of level l (needs level l + 1)
+// The interpolation rows of level l's U (the rows off the skeleton J), for
+// products with U that skip its identity rows.
+void plan_interp_rows(lsh_plan_s& P, int l, hipStream_t s) {
+  Level& lv = P.lev[l];
+  const int m = lv.m, k = lv.k, half = m / 2;
+  std::vector<char> skel(m, 0);
+  for (int q = 0; q < k; ++q) {
+    LSH_REQUIRE(lv.J[q] >= 0 && lv.J[q] < m && !skel[lv.J[q]], -4, "row ID: skeleton rows not distinct");
+    skel[lv.J[q]] = 1;
+  }
+  lv.rest.clear();
+  lv.nrest0 = 0;
+  for (int i = 0; i < m; ++i)
+    if (!skel[i]) {
+      lv.rest.push_back(i);
+      if (i < half) ++lv.nrest0;
+    }
+  const int nr = (int)lv.rest.size();
+  lv.restIdx.alloc(sizeof(int) * std::max(nr, 1));
+  lv.skelIdx.alloc(sizeof(int) * k);
+  if (nr) LSH_HIP(hipMemcpyAsync(lv.restIdx.p, lv.rest.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+  LSH_HIP(hipMemcpyAsync(lv.skelIdx.p, lv.J.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
+  lv.T64.alloc(sizeof(z64) * std::max((size_t)nr * k, (size_t)1));
+  gather_rows2<double>(s, nr, k, lv.U64.as<z64>(), lv.U64.as<z64>(), m, k, 0, lv.restIdx.as<int>(), 0,
+                       lv.T64.as<z64>(), k, 0, 1);
+  if (P.d.hbs_prec == LSH_FP32) {
+    lv.T32.alloc(sizeof(c32) * std::max((size_t)nr * k, (size_t)1));
+    gather_rows2<float>(s, nr, k, lv.U32.as<c32>(), lv.U32.as<c32>(), m, k, 0, lv.restIdx.as<int>(), 0,
+                        lv.T32.as<c32>(), k, 0, 1);
+  }
+}
+
 void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
   const lsh_desc& d = P.d;
   const bool f32 = d.hbs_prec == LSH_FP32;
@@ -474,6 +519,7 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
         lv.Ut32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
         ctranspose<float>(s, lv.U32.as<c32>(), lv.m, lv.k, lv.Ut32.as<c32>());
       }
+      if (l < P.L) plan_interp_rows(P, l, s);
     }
   }
 }
@@ -617,6 +663,7 @@ struct Profile {
   int L = 0, nleaf = 0, mL = 0;
   bool f32 = false;
   std::vector<long> k, c, r;
+  std::vector<long> nr;  // level l: rows of T (both halves), at most (0: U = I)
   std::vector<int> form;
 };
 
@@ -664,6 +711,14 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
     z.add_n<z64>(mk);  // U64
     z.add_n<z64>(mk);  // Ut64
     if (f32) { z.add(e * mk); z.add(e * mk); }
+    if (l < L && !(d.tol == 0 || l <= d.full_levels)) {  // T = U[rest, :] ((m - k) x k, rank k <= k[l]), indices
+      const size_t mm = m[l], kb = k[l];
+      const size_t tb = std::max<size_t>(2 * kb >= mm ? (mm / 2) * (mm - mm / 2) : (mm - kb) * kb, 1);
+      z.add_n<z64>(tb);
+      if (f32) z.add(e * tb);
+      z.add_n<int>(mm);
+      z.add_n<int>(kb);
+    }
     const long ncols = (horder > 4 ? 2 : 1) * np[l];
     mem::Sizer t;
     t.add_n<I2>(m[l]);
@@ -717,9 +772,11 @@ PlanBytes plan_bytes(const lsh_desc& d, Profile* prof) {
     P.k.assign(k.begin(), k.begin() + L + 1);
     P.c.resize(L);
     P.r.resize(L);
+    P.nr.assign(L, 0);
     P.form.resize(L);
     for (int l = 0; l < L; ++l) {
       P.c[l] = k[l + 1];
+      if (l >= 1 && !(d.tol == 0 || l <= d.full_levels)) P.nr[l] = m[l];
       if (!lowrank) { P.form[l] = 1; P.r[l] = 0; }
       else if (d.merge == LSH_MERGE_LOWRANK) { P.form[l] = 2; P.r[l] = P.c[l]; }
       else { P.form[l] = 3; P.r[l] = P.c[l] * 6 / 10; }  // AUTO: Woodbury only where 10 r <= 6 c
@@ -740,7 +797,10 @@ Profile plan_profile(const lsh_plan_s& P) {
   f.r.resize(P.L);
   f.form.resize(P.L);
   for (int l = 0; l <= P.L; ++l) f.k[l] = P.lev[l].k;
+  f.nr.assign(P.L, 0);
   for (int l = 0; l < P.L; ++l) {
+    const Level& v = P.lev[l];
+    if (l >= 1 && !v.ident) f.nr[l] = std::max<long>(1, (long)v.rest.size());
     f.c[l] = P.lev[l].c;
     f.r[l] = P.lev[l].wr;
     f.form[l] = P.lev[l].wr > 0 ? 2 : 1;
@@ -782,6 +842,7 @@ FactorBytes factor_bytes_t(const Profile& f, bool want_T) {
       t.add(merge_level_table_bytes(1));  // (a level in one persistent launch: its table and counter)
       t.add(sizeof(int));
       if (l >= 1) { t.add(e * nb * 2 * c * k); t.add(e * nb * 4 * r * k); }
+      if (l >= 1 && f.nr[l] > 0) { t.add(e * nb * c * f.nr[l]); t.add(e * nb * f.nr[l] * k); }
       keep_l = std::max(keep_l, a.total);
       scr_l = std::max(scr_l, t.total);
     }
@@ -790,6 +851,7 @@ FactorBytes factor_bytes_t(const Profile& f, bool want_T) {
       for (int q = 0; q < (want_T ? 6 : 3); ++q) a.add(e * nb * c * c);
       t.add(inverse_ws_bytes<R>((int)c, (int)nb));
       if (l >= 1) for (int q = 0; q < 3; ++q) t.add(e * nb * c * k);
+      if (l >= 1 && f.nr[l] > 0) { t.add(e * nb * c * f.nr[l]); t.add(e * nb * f.nr[l] * k); }
       keep_l = std::max(keep_l, a.total);
       scr_l = std::max(scr_l, t.total);
     }
@@ -1007,6 +1069,107 @@ void factor_merge(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
   }
 }
 
+// Products with U_l that skip its identity rows (U = I on the skeleton rows
+// J; T = U[rest, :] holds the others, nh[0] of them in half 0, nh[1] in half 1):
+//   a_h = S_h U_h: the columns J of S_h placed (zero elsewhere), plus
+//                  S_h[:, rest_h] T_h                        (both halves h)
+//   S = U^T [b_0; b_1]: the rows J of [b_0; b_1] placed, plus
+//                  T_h^T b_h[rest_h, :]                       (both halves h)
+// over the nb boxes of parent level l.  Each box's S_h (c x c) sits at
+// Sch + 2 c^2 box + c^2 h; a_h and b_h are c x k at stride sa / sb per box.
+// The *_prep functions launch the placements and the gathers of S_h's
+// columns rest_h (into G: nb c x nh[h] blocks per half) or of b_h's rows
+// rest_h (into Rg: nb nh[h] x k blocks per half) on s, and return the
+// products C += A B that complete the result (beta 1, in stream order after
+// the gathers), for one launch each or a grouped launch.
+template <typename R>
+struct ScatterGemm {
+  int M, N, K;
+  const cplx<R>* A;
+  long lda, sA;
+  Op opA;
+  const cplx<R>* B;
+  long ldb, sB;
+  cplx<R>* C;
+  long ldc, sC;
+  int batch;
+};
+
+inline void rest_counts(const Level& lv, int nh[2]) {
+  nh[0] = lv.nrest0;
+  nh[1] = (int)lv.rest.size() - lv.nrest0;
+}
+
+// entries of G (and of Rg per column) that one box needs
+inline long rest_total(const Level& lv) { return std::max<long>(1, (long)lv.rest.size()); }
+
+template <typename R>
+int scatter_su_prep(const lsh_plan_s& P, int l, const cplx<R>* Sch, cplx<R>* a0, cplx<R>* a1, long sa, cplx<R>* G,
+                    hipStream_t s, ScatterGemm<R> out[2]) {
+  const Level& lv = P.lev[l];
+  const int c = lv.c, k = lv.k, nb = 1 << l;
+  const long cc = (long)c * c;
+  int nh[2];
+  rest_counts(lv, nh);
+  cplx<R>* ah[2] = {a0, a1};
+  int n = 0;
+  for (int h = 0; h < 2; ++h) {
+    const cplx<R>* Sh = Sch + h * cc;
+    gather_cols<R>(s, c, k, Sh, c, 2 * cc, lv.skelIdx.as<int>(), h * c, c, ah[h], k, sa, nb);
+    if (nh[h] == 0) continue;
+    const int* rh = lv.restIdx.as<int>() + (h ? nh[0] : 0);
+    cplx<R>* Gh = G + (h ? (long)nb * c * nh[0] : 0L);
+    gather_cols<R>(s, c, nh[h], Sh, c, 2 * cc, rh, h * c, c, Gh, nh[h], (long)c * nh[h], nb);
+    out[n++] = {c, k, nh[h], Gh, nh[h], (long)c * nh[h], OP_N, P.T<R>(l) + (h ? (long)nh[0] * k : 0L), k, 0,
+                ah[h], k, sa, nb};
+  }
+  return n;
+}
+
+template <typename R>
+int scatter_utb_prep(const lsh_plan_s& P, int l, const cplx<R>* b0, const cplx<R>* b1, long sb, cplx<R>* S,
+                     cplx<R>* Rg, hipStream_t s, ScatterGemm<R> out[2]) {
+  const Level& lv = P.lev[l];
+  const int c = lv.c, k = lv.k, nb = 1 << l;
+  const long kk = (long)k * k;
+  int nh[2];
+  rest_counts(lv, nh);
+  gather_rows2<R>(s, k, k, b0, b1, c, k, sb, lv.skelIdx.as<int>(), 0, S, k, kk, nb);
+  const cplx<R>* bh[2] = {b0, b1};
+  int n = 0;
+  for (int h = 0; h < 2; ++h) {
+    if (nh[h] == 0) continue;
+    const int* rh = lv.restIdx.as<int>() + (h ? nh[0] : 0);
+    cplx<R>* Rh = Rg + (h ? (long)nb * nh[0] * k : 0L);
+    gather_rows2<R>(s, nh[h], k, bh[h], bh[h], c, k, sb, rh, h * c, Rh, k, (long)nh[h] * k, nb);
+    out[n++] = {k, k, nh[h], P.T<R>(l) + (h ? (long)nh[0] * k : 0L), k, 0, OP_T, Rh, k, (long)nh[h] * k, S, k, kk,
+                nb};
+  }
+  return n;
+}
+
+template <typename R>
+void run_scatter_gemms(hipStream_t s, const ScatterGemm<R>* g, int n) {
+  const cplx<R> one = mk<R>(1, 0);
+  for (int i = 0; i < n; ++i)
+    cgemm<R>(s, g[i].M, g[i].N, g[i].K, one, g[i].A, g[i].lda, g[i].sA, g[i].opA, g[i].B, g[i].ldb, g[i].sB, OP_N,
+             one, g[i].C, g[i].ldc, g[i].sC, g[i].C, g[i].ldc, g[i].sC, g[i].batch);
+}
+
+template <typename R>
+void scatter_su(const lsh_plan_s& P, int l, const cplx<R>* Sch, cplx<R>* a0, cplx<R>* a1, long sa, cplx<R>* G,
+                hipStream_t s) {
+  ScatterGemm<R> g[2];
+  run_scatter_gemms<R>(s, g, scatter_su_prep<R>(P, l, Sch, a0, a1, sa, G, s, g));
+}
+
+template <typename R>
+void scatter_utb(const lsh_plan_s& P, int l, const cplx<R>* b0, const cplx<R>* b1, long sb, cplx<R>* S,
+                 cplx<R>* Rg, hipStream_t s) {
+  ScatterGemm<R> g[2];
+  run_scatter_gemms<R>(s, g, scatter_utb_prep<R>(P, l, b0, b1, sb, S, Rg, s, g));
+}
+
 // scattering matrices of level l (needs U_l)
 template <typename R>
 void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s) {
@@ -1021,8 +1184,6 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
   const cplx<R>* Ci = F.Ci[l].template as<cplx<R>>();
   const int k = P.lev[l].k;
   const long ck = (long)c * k;
-  const cplx<R>* U1 = P.U<R>(l);
-  const cplx<R>* U2 = U1 + ck;
   if (P.lev[l].ident) {  // U_l = I (k = 2c): the products with U are placements
     F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
     cplx<R>* S = F.S[l].template as<cplx<R>>();
@@ -1052,6 +1213,9 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
     cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, S + ck, k, kk, OP_N, one, S, k, kk, S, k, kk, nb);
     return;
   }
+  const long nrt = rest_total(P.lev[l]);
+  cplx<R>* G = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * c * nrt);
+  cplx<R>* Rg = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * nrt * k);
   if (F.wr[l] > 0) {
     // X [a1; a2] = [a1; a2] - P W' [L^T a1; R^T a2] (a1, a2 interleaved per box in A12)
     const int r = F.wr[l];
@@ -1059,8 +1223,7 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
     cplx<R>* a = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 2 * ck);
     cplx<R>* q = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 4 * rk);
     cplx<R>* yv = q + nb * 2 * rk;
-    cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a, k, 2 * ck, nb);
-    cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a + ck, k, 2 * ck, nb);
+    scatter_su<R>(P, l, Sch, a, a + ck, 2 * ck, G, s);
     cgemm<R>(s, r, k, c, one, P.W<R>(l, 1), c, 0, OP_N, a, k, 2 * ck, OP_N, zero, nullptr, 0, 0, q, k, 2 * rk, nb);
     cgemm<R>(s, r, k, c, one, P.W<R>(l, 3), c, 0, OP_N, a + ck, k, 2 * ck, OP_N, zero, nullptr, 0, 0, q + rk, k,
              2 * rk, nb);
@@ -1068,17 +1231,13 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
              nb);
     cgemm<R>(s, c, k, r, mone, Pa, r, cr, OP_N, yv, k, rk, OP_N, one, a, k, ck, a, k, ck, 2 * nb);
     F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
-    cplx<R>* S = F.S[l].template as<cplx<R>>();
-    cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a, k, 2 * ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
-    cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, a + ck, k, 2 * ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k,
-             nb);
+    scatter_utb<R>(P, l, a, a + ck, 2 * ck, F.S[l].template as<cplx<R>>(), Rg, s);
     return;
   }
   cplx<R>* a1 = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
   cplx<R>* a2 = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
   cplx<R>* y = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * ck);
-  cgemm<R>(s, c, k, c, one, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, zero, nullptr, 0, 0, a1, k, ck, nb);
-  cgemm<R>(s, c, k, c, one, Sch + cc, c, 2 * cc, OP_N, U2, k, 0, OP_N, zero, nullptr, 0, 0, a2, k, ck, nb);
+  scatter_su<R>(P, l, Sch, a1, a2, ck, G, s);
   {
     // a2 <- A2 - Pb A1 ; y = C^{-1} a2 ; a1 <- A1 - Pa y
     cgemm<R>(s, c, k, c, mone, Pb, c, cc, OP_N, a1, k, ck, OP_N, one, a2, k, ck, a2, k, ck, nb);
@@ -1086,9 +1245,7 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
     cgemm<R>(s, c, k, c, mone, Pa, c, cc, OP_N, y, k, ck, OP_N, one, a1, k, ck, a1, k, ck, nb);
   }
   F.S[l].alloc(sizeof(cplx<R>) * nb * (long)k * k);
-  cplx<R>* S = F.S[l].template as<cplx<R>>();
-  cgemm<R>(s, k, k, c, one, U1, k, 0, OP_T, a1, k, ck, OP_N, zero, nullptr, 0, 0, S, k, (long)k * k, nb);
-  cgemm<R>(s, k, k, c, one, U2, k, 0, OP_T, y, k, ck, OP_N, one, S, k, (long)k * k, S, k, (long)k * k, nb);
+  scatter_utb<R>(P, l, a1, y, ck, F.S[l].template as<cplx<R>>(), Rg, s);
 }  // (scratch freed in stream order)
 
 // Woodbury levels whose inverse order fits the in-LDS Gauss-Jordan run as one
@@ -1101,7 +1258,7 @@ int g_fused_min_boxes = kFusedMinBoxes;  // fuse levels with at least this many 
 template <typename R>
 bool level_fused(const lsh_plan_s& P, int l) {
   return sizeof(R) == 4 && g_fused_min_boxes > 0 && (1 << l) >= g_fused_min_boxes && P.lev[l].wr > 0 &&
-         merge_level_fits(P.lev[l].wr);
+         !P.lev[l].ident && merge_level_fits(P.lev[l].wr);
 }
 
 // The level-l entry of a persistent merge launch for one FP32 factor:
@@ -1126,6 +1283,17 @@ MergeLevelDev merge_entry(const lsh_plan_s& P, FactorData<float>& F, int l, mem:
   g.A12 = l >= 1 ? static_cast<c32*>(tmp.take(sizeof(c32) * nb * 2 * ck)) : nullptr;
   g.Qb = l >= 1 ? static_cast<c32*>(tmp.take(sizeof(c32) * nb * 4 * rk)) : nullptr;
   g.perm = static_cast<int*>(tmp.take(sizeof(int) * nb * r));
+  if (l >= 1) {
+    const Level& v = P.lev[l];
+    const long nrt = rest_total(v);
+    g.Ur = P.T<float>(l);
+    g.rest = v.restIdx.as<int>();
+    g.skel = v.skelIdx.as<int>();
+    g.n0 = v.nrest0;
+    g.n1 = (int)v.rest.size() - v.nrest0;
+    g.G = static_cast<c32*>(tmp.take(sizeof(c32) * nb * (long)c * nrt));
+    g.Rg = static_cast<c32*>(tmp.take(sizeof(c32) * nb * nrt * k));
+  }
   g.info = info;
   g.c = c;
   g.r = r;
@@ -2638,7 +2806,7 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
   });
   run();
   // scattering matrices (not at the root): X D U through W'
-  std::vector<DevBuf> A12(n_inst), Qb(n_inst);
+  std::vector<DevBuf> A12(n_inst), Qb(n_inst), Gs(n_inst), Rs(n_inst);
   std::vector<int> sc;
   std::vector<Lv> SL;
   for (size_t q = 0; q < wact.size(); ++q) {
@@ -2647,6 +2815,11 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
     const int i = wact[q];
     A12[i].alloc_in(*v.F->scr, sizeof(c32) * v.nb * 2 * (long)v.c * v.k);
     Qb[i].alloc_in(*v.F->scr, sizeof(c32) * v.nb * 4 * (long)v.r * v.k);
+    if (!v.P->lev[v.l].ident) {
+      const long nrt = rest_total(v.P->lev[v.l]);
+      Gs[i].alloc_in(*v.F->scr, sizeof(c32) * v.nb * (long)v.c * nrt);
+      Rs[i].alloc_in(*v.F->scr, sizeof(c32) * v.nb * nrt * v.k);
+    }
     v.F->S[v.l].alloc_in(*v.F->keep, sizeof(c32) * v.nb * (long)v.k * v.k);
     sc.push_back(i);
     SL.push_back(v);
@@ -2662,15 +2835,28 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
       fn(v, ck, rk, a, qv, qv + v.nb * 2 * rk);
     }
   };
+  // (the products of factor_scatter, grouped over the instances; dense
+  // products with U = I on levels that keep all their candidates)
+  auto push = [&](const ScatterGemm<float>& g) {
+    gi.push_back({g.M, g.N, g.K, one, one, g.A, g.lda, g.sA, g.opA, g.B, g.ldb, g.sB, OP_N, g.C, g.ldc, g.sC, g.C,
+                  g.ldc, g.sC, g.batch, false});
+  };
   each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
     const c32* Sch = v.F->S[v.l + 1].as<c32>();
+    if (!v.P->lev[v.l].ident) {
+      ScatterGemm<float> g[2];
+      const int ng = scatter_su_prep<float>(*v.P, v.l, Sch, a, a + ck, 2 * ck, Gs[sc[&v - SL.data()]].as<c32>(), s,
+                                            g);
+      for (int t = 0; t < ng; ++t) push(g[t]);  // (the halves write different blocks)
+      return;
+    }
     const c32* U1 = v.P->U<float>(v.l);
     gi.push_back({v.c, v.k, v.c, one, zero, Sch, v.c, 2 * v.cc, OP_N, U1, v.k, 0, OP_N, nullptr, 0, 0, a, v.k,
                   2 * ck, v.nb, false});
     gi.push_back({v.c, v.k, v.c, one, zero, Sch + v.cc, v.c, 2 * v.cc, OP_N, U1 + ck, v.k, 0, OP_N, nullptr, 0, 0,
                   a + ck, v.k, 2 * ck, v.nb, false});
   });
-  run();
+  if (!gi.empty()) run();
   each_s([&](const Lv& v, long ck, long rk, c32* a, c32* qv, c32*) {
     gi.push_back({v.r, v.k, v.c, one, zero, v.P->W<float>(v.l, 1), v.c, 0, OP_N, a, v.k, 2 * ck, OP_N, nullptr, 0,
                   0, qv, v.k, 2 * rk, v.nb, false});
@@ -2688,17 +2874,33 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
                   a, v.k, ck, 2 * v.nb, false});
   });
   run();
+  std::vector<std::array<ScatterGemm<float>, 2>> ug(sc.size());
+  std::vector<int> nug(sc.size(), -1);  // -1: dense products with U = I
   each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
+    const size_t q = &v - SL.data();
+    if (!v.P->lev[v.l].ident) {
+      nug[q] = scatter_utb_prep<float>(*v.P, v.l, a, a + ck, 2 * ck, v.F->S[v.l].as<c32>(), Rs[sc[q]].as<c32>(),
+                                       s, ug[q].data());
+      return;
+    }
     gi.push_back({v.k, v.k, v.c, one, zero, v.P->U<float>(v.l), v.k, 0, OP_T, a, v.k, 2 * ck, OP_N, nullptr, 0, 0,
                   v.F->S[v.l].as<c32>(), v.k, (long)v.k * v.k, v.nb, false});
   });
-  run();
+  for (size_t q = 0; q < sc.size(); ++q)
+    if (nug[q] >= 1) push(ug[q][0]);
+  if (!gi.empty()) run();
+  // (both halves add into S: the second ones in a launch of their own)
   each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
+    const size_t q = &v - SL.data();
+    if (!v.P->lev[v.l].ident) {
+      if (nug[q] >= 2) push(ug[q][1]);
+      return;
+    }
     c32* S = v.F->S[v.l].as<c32>();
     gi.push_back({v.k, v.k, v.c, one, one, v.P->U<float>(v.l) + ck, v.k, 0, OP_T, a + ck, v.k, 2 * ck, OP_N, S, v.k,
                   (long)v.k * v.k, S, v.k, (long)v.k * v.k, v.nb, false});
   });
-  run();
+  if (!gi.empty()) run();
   LSH_HIP(hipStreamSynchronize(s));  // scratch and tables die here
 }
 
@@ -2838,7 +3040,7 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
                   "singular merge matrix I - Pb Pa at level " + std::to_string(lev(i)) + " (instance " +
                       std::to_string(i) + ")");
     // scattering matrices (not at the root)
-    std::vector<DevBuf> A1(n_inst), A2(n_inst), Yl(n_inst);
+    std::vector<DevBuf> A1(n_inst), A2(n_inst), Yl(n_inst), Gs(n_inst), Rs(n_inst);
     bool any = false;
     for (int i : act) {
       const lsh_plan_s& P = *Fs[i]->plan;
@@ -2851,6 +3053,11 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
       A1[i].alloc_in(scr, sizeof(c32) * nb * ck);
       A2[i].alloc_in(scr, sizeof(c32) * nb * ck);
       Yl[i].alloc_in(scr, sizeof(c32) * nb * ck);
+      if (!P.lev[l].ident) {
+        const long nrt = rest_total(P.lev[l]);
+        Gs[i].alloc_in(scr, sizeof(c32) * nb * (long)c * nrt);
+        Rs[i].alloc_in(scr, sizeof(c32) * nb * nrt * k);
+      }
       Fs[i]->f32.S[l].alloc_in(Fs[i]->keep, sizeof(c32) * nb * (long)k * k);
     }
     if (any) {
@@ -2863,15 +3070,28 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
           fn(i, P, Fs[i]->f32, l, c, nb, k, (long)c * c, (long)c * k);
         }
       };
+      // (the products of factor_scatter, grouped over the instances; dense
+      // products with U = I on levels that keep all their candidates)
+      auto push = [&](const ScatterGemm<float>& g) {
+        gi.push_back({g.M, g.N, g.K, one, one, g.A, g.lda, g.sA, g.opA, g.B, g.ldb, g.sB, OP_N, g.C, g.ldc, g.sC,
+                      g.C, g.ldc, g.sC, g.batch, false});
+      };
       each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
         const c32* Sch = F.S[l + 1].as<c32>();
+        if (!P.lev[l].ident) {
+          ScatterGemm<float> g[2];
+          const int ng = scatter_su_prep<float>(P, l, Sch, A1[i].as<c32>(), A2[i].as<c32>(), ck, Gs[i].as<c32>(),
+                                                s, g);
+          for (int t = 0; t < ng; ++t) push(g[t]);
+          return;
+        }
         const c32* U1 = P.U<float>(l);
         gi.push_back({c, k, c, one, zero, Sch, c, 2 * cc, OP_N, U1, k, 0, OP_N, nullptr, 0, 0, A1[i].as<c32>(), k,
                       ck, nb, false});
         gi.push_back({c, k, c, one, zero, Sch + cc, c, 2 * cc, OP_N, U1 + ck, k, 0, OP_N, nullptr, 0, 0,
                       A2[i].as<c32>(), k, ck, nb, false});
       });
-      run_gemms(tabs[2]);
+      if (!gi.empty()) run_gemms(tabs[2]);
       each([&](int i, const lsh_plan_s&, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
         gi.push_back({c, k, c, mone, one, F.Pb[l].as<c32>(), c, cc, OP_N, A1[i].as<c32>(), k, ck, OP_N,
                       A2[i].as<c32>(), k, ck, A2[i].as<c32>(), k, ck, nb, false});
@@ -2887,16 +3107,29 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
                       A1[i].as<c32>(), k, ck, A1[i].as<c32>(), k, ck, nb, false});
       });
       run_gemms(tabs[5]);
+      std::vector<std::array<ScatterGemm<float>, 2>> ug(n_inst);
+      std::vector<int> nug(n_inst, -1);  // -1: dense products with U = I
       each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long, long ck) {
+        if (!P.lev[l].ident) {
+          nug[i] = scatter_utb_prep<float>(P, l, A1[i].as<c32>(), Yl[i].as<c32>(), ck, F.S[l].as<c32>(),
+                                           Rs[i].as<c32>(), s, ug[i].data());
+          return;
+        }
         gi.push_back({k, k, c, one, zero, P.U<float>(l), k, 0, OP_T, A1[i].as<c32>(), k, ck, OP_N, nullptr, 0, 0,
                       F.S[l].as<c32>(), k, (long)k * k, nb, false});
       });
-      run_gemms(tabs[6]);
+      for (int i : act)
+        if (nug[i] >= 1) push(ug[i][0]);
+      if (!gi.empty()) run_gemms(tabs[6]);
       each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long, long ck) {
+        if (!P.lev[l].ident) {
+          if (nug[i] >= 2) push(ug[i][1]);
+          return;
+        }
         gi.push_back({k, k, c, one, one, P.U<float>(l) + ck, k, 0, OP_T, Yl[i].as<c32>(), k, ck, OP_N,
                       F.S[l].as<c32>(), k, (long)k * k, F.S[l].as<c32>(), k, (long)k * k, nb, false});
       });
-      run_gemms(tabs[7]);
+      if (!gi.empty()) run_gemms(tabs[7]);
     }
     LSH_HIP(hipStreamSynchronize(s));  // scratch and tables of this level die here
   }
