@@ -472,7 +472,11 @@ static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, cons
                                     : (BM == 128 ? "cgemm_f64_128x64" : "cgemm_f64_64x64");
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     int nb = batch - b0 < 65535 ? batch - b0 : 65535;
-    ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb);
+    // algorithmic bytes: each distinct operand once, the result (and D) once per problem
+    const double e = sizeof(cplx<R>);
+    const double bytes = e * ((double)P.M * P.K * (sA ? nb : 1) + (double)P.K * P.N * (sB ? nb : 1) +
+                              (double)P.M * P.N * nb * (D ? 2 : 1));
+    ProfScope ps(name, s, 8.0 * P.M * P.N * P.K * (double)nb, bytes);
     GemmP<R> Q = P;
     Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
     if (D) Q.D = D + b0 * sD;
