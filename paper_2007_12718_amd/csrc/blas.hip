@@ -2103,6 +2103,48 @@ void gather_rows2(hipStream_t s, int rows, int cols, const cplx<R>* src0, const 
   LSH_LAUNCH_CHECK();
 }
 
+// Many gathers of FP32 blocks in one launch: grid row y takes job y (the
+// elements of gather_cols when its kind is 0, of gather_rows2 when 1, with
+// the same arguments), grid columns stride over the job's elements.
+__global__ __launch_bounds__(256) void k_gather_grouped(const GatherJob* __restrict__ J) {
+  const GatherJob& g = J[blockIdx.y];
+  const long per = (long)g.rows * g.cols, total = per * g.batch;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long b = e / per, q = e - b * per;
+    const long i = q / g.cols, j = q - i * g.cols;
+    c32 v;
+    if (g.kind == 0) {
+      const int col = g.idx[j] - g.off;
+      v = (col >= 0 && col < g.c) ? g.src0[b * g.ss + i * g.lds + col] : mk<float>(0, 0);
+    } else {
+      const int t = g.idx[i] - g.off;
+      v = t < g.c ? g.src0[b * g.ss + (long)t * g.lds + j] : g.src1[b * g.ss + (long)(t - g.c) * g.lds + j];
+    }
+    g.dst[b * g.sd + i * g.ldd + j] = v;
+  }
+}
+
+void gather_grouped(hipStream_t s, const std::vector<GatherJob>& jobs, DevBuf& dev) {
+  std::vector<GatherJob> h;
+  long most = 0;
+  for (GatherJob g : jobs) {
+    const long n = (long)g.rows * g.cols * g.batch;
+    if (n <= 0) continue;
+    most = std::max(most, n);
+    h.push_back(g);
+  }
+  if (h.empty()) return;
+  LSH_REQUIRE(h.size() <= 65535, -6, "gather_grouped: too many jobs");
+  const size_t bytes = sizeof(GatherJob) * h.size();
+  if (dev.bytes < bytes) dev.alloc(bytes);
+  LSH_HIP(hipMemcpyAsync(dev.p, h.data(), bytes, hipMemcpyHostToDevice, s));
+  const long gx = std::min<long>(ceil_div(most, 256L), 1024L);
+  hipLaunchKernelGGL(k_gather_grouped, dim3((unsigned)gx, (unsigned)h.size()), dim3(256), 0, s,
+                     dev.as<GatherJob>());
+  LSH_LAUNCH_CHECK();
+  // (pageable copies are staged before hipMemcpyAsync returns: h may go now)
+}
+
 // Y[v][i] = alpha X[v][i] + beta Z[v][i] for i < n, v < nv (Z may be null)
 template <typename R>
 __global__ void k_caxpby(int n, int nv, cplx<R> alpha, const cplx<R>* __restrict__ X, long ldx, cplx<R> beta,

@@ -174,6 +174,20 @@ template <typename R>
 void gather_rows2(hipStream_t s, int rows, int cols, const cplx<R>* src0, const cplx<R>* src1, int c, long lds,
                   long ss, const int* idx, int off, cplx<R>* dst, long ldd, long sd, long batch);
 
+// One launch of many FP32 gathers (batched factors): kind 0 as gather_cols
+// (c: lim), kind 1 as gather_rows2.
+struct GatherJob {
+  int kind, rows, cols;
+  const c32 *src0, *src1;
+  int c;
+  long lds, ss;
+  const int* idx;
+  int off;
+  c32* dst;
+  long ldd, sd, batch;
+};
+void gather_grouped(hipStream_t s, const std::vector<GatherJob>& jobs, DevBuf& dev);
+
 // dst (R2) = src (R1), elementwise, n complex entries
 template <typename R1, typename R2>
 void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n);

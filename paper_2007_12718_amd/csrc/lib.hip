@@ -1103,9 +1103,25 @@ inline void rest_counts(const Level& lv, int nh[2]) {
 // entries of G (and of Rg per column) that one box needs
 inline long rest_total(const Level& lv) { return std::max<long>(1, (long)lv.rest.size()); }
 
+// one gather (kind 0: gather_cols with lim c; 1: gather_rows2), launched on s
+// or, with a sink (FP32), kept for one grouped launch
+template <typename R>
+void gather_job(std::vector<GatherJob>* sink, hipStream_t s, int kind, int rows, int cols, const cplx<R>* src0,
+                const cplx<R>* src1, int c, long lds, long ss, const int* idx, int off, cplx<R>* dst, long ldd,
+                long sd, long batch) {
+  if constexpr (sizeof(R) == 4) {
+    if (sink) {
+      sink->push_back({kind, rows, cols, src0, src1, c, lds, ss, idx, off, dst, ldd, sd, batch});
+      return;
+    }
+  }
+  if (kind == 0) gather_cols<R>(s, rows, cols, src0, lds, ss, idx, off, c, dst, ldd, sd, batch);
+  else gather_rows2<R>(s, rows, cols, src0, src1, c, lds, ss, idx, off, dst, ldd, sd, batch);
+}
+
 template <typename R>
 int scatter_su_prep(const lsh_plan_s& P, int l, const cplx<R>* Sch, cplx<R>* a0, cplx<R>* a1, long sa, cplx<R>* G,
-                    hipStream_t s, ScatterGemm<R> out[2]) {
+                    hipStream_t s, ScatterGemm<R> out[2], std::vector<GatherJob>* sink = nullptr) {
   const Level& lv = P.lev[l];
   const int c = lv.c, k = lv.k, nb = 1 << l;
   const long cc = (long)c * c;
@@ -1115,11 +1131,11 @@ int scatter_su_prep(const lsh_plan_s& P, int l, const cplx<R>* Sch, cplx<R>* a0,
   int n = 0;
   for (int h = 0; h < 2; ++h) {
     const cplx<R>* Sh = Sch + h * cc;
-    gather_cols<R>(s, c, k, Sh, c, 2 * cc, lv.skelIdx.as<int>(), h * c, c, ah[h], k, sa, nb);
+    gather_job<R>(sink, s, 0, c, k, Sh, nullptr, c, c, 2 * cc, lv.skelIdx.as<int>(), h * c, ah[h], k, sa, nb);
     if (nh[h] == 0) continue;
     const int* rh = lv.restIdx.as<int>() + (h ? nh[0] : 0);
     cplx<R>* Gh = G + (h ? (long)nb * c * nh[0] : 0L);
-    gather_cols<R>(s, c, nh[h], Sh, c, 2 * cc, rh, h * c, c, Gh, nh[h], (long)c * nh[h], nb);
+    gather_job<R>(sink, s, 0, c, nh[h], Sh, nullptr, c, c, 2 * cc, rh, h * c, Gh, nh[h], (long)c * nh[h], nb);
     out[n++] = {c, k, nh[h], Gh, nh[h], (long)c * nh[h], OP_N, P.T<R>(l) + (h ? (long)nh[0] * k : 0L), k, 0,
                 ah[h], k, sa, nb};
   }
@@ -1128,20 +1144,20 @@ int scatter_su_prep(const lsh_plan_s& P, int l, const cplx<R>* Sch, cplx<R>* a0,
 
 template <typename R>
 int scatter_utb_prep(const lsh_plan_s& P, int l, const cplx<R>* b0, const cplx<R>* b1, long sb, cplx<R>* S,
-                     cplx<R>* Rg, hipStream_t s, ScatterGemm<R> out[2]) {
+                     cplx<R>* Rg, hipStream_t s, ScatterGemm<R> out[2], std::vector<GatherJob>* sink = nullptr) {
   const Level& lv = P.lev[l];
   const int c = lv.c, k = lv.k, nb = 1 << l;
   const long kk = (long)k * k;
   int nh[2];
   rest_counts(lv, nh);
-  gather_rows2<R>(s, k, k, b0, b1, c, k, sb, lv.skelIdx.as<int>(), 0, S, k, kk, nb);
+  gather_job<R>(sink, s, 1, k, k, b0, b1, c, k, sb, lv.skelIdx.as<int>(), 0, S, k, kk, nb);
   const cplx<R>* bh[2] = {b0, b1};
   int n = 0;
   for (int h = 0; h < 2; ++h) {
     if (nh[h] == 0) continue;
     const int* rh = lv.restIdx.as<int>() + (h ? nh[0] : 0);
     cplx<R>* Rh = Rg + (h ? (long)nb * nh[0] * k : 0L);
-    gather_rows2<R>(s, nh[h], k, bh[h], bh[h], c, k, sb, rh, h * c, Rh, k, (long)nh[h] * k, nb);
+    gather_job<R>(sink, s, 1, nh[h], k, bh[h], bh[h], c, k, sb, rh, h * c, Rh, k, (long)nh[h] * k, nb);
     out[n++] = {k, k, nh[h], P.T<R>(l) + (h ? (long)nh[0] * k : 0L), k, 0, OP_T, Rh, k, (long)nh[h] * k, S, k, kk,
                 nb};
   }
@@ -2841,12 +2857,13 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
     gi.push_back({g.M, g.N, g.K, one, one, g.A, g.lda, g.sA, g.opA, g.B, g.ldb, g.sB, OP_N, g.C, g.ldc, g.sC, g.C,
                   g.ldc, g.sC, g.batch, false});
   };
+  std::vector<GatherJob> gj;  // (every instance's gathers in one launch)
   each_s([&](const Lv& v, long ck, long, c32* a, c32*, c32*) {
     const c32* Sch = v.F->S[v.l + 1].as<c32>();
     if (!v.P->lev[v.l].ident) {
       ScatterGemm<float> g[2];
       const int ng = scatter_su_prep<float>(*v.P, v.l, Sch, a, a + ck, 2 * ck, Gs[sc[&v - SL.data()]].as<c32>(), s,
-                                            g);
+                                            g, &gj);
       for (int t = 0; t < ng; ++t) push(g[t]);  // (the halves write different blocks)
       return;
     }
@@ -2856,6 +2873,11 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
     gi.push_back({v.c, v.k, v.c, one, zero, Sch + v.cc, v.c, 2 * v.cc, OP_N, U1 + ck, v.k, 0, OP_N, nullptr, 0, 0,
                   a + ck, v.k, 2 * ck, v.nb, false});
   });
+  {
+    DevBuf gtab;
+    gather_grouped(s, gj, gtab);
+    gj.clear();
+  }
   if (!gi.empty()) run();
   each_s([&](const Lv& v, long ck, long rk, c32* a, c32* qv, c32*) {
     gi.push_back({v.r, v.k, v.c, one, zero, v.P->W<float>(v.l, 1), v.c, 0, OP_N, a, v.k, 2 * ck, OP_N, nullptr, 0,
@@ -2880,12 +2902,17 @@ void batch_lowrank_level(std::vector<lsh_factor_s*>& Fs, const std::vector<int>&
     const size_t q = &v - SL.data();
     if (!v.P->lev[v.l].ident) {
       nug[q] = scatter_utb_prep<float>(*v.P, v.l, a, a + ck, 2 * ck, v.F->S[v.l].as<c32>(), Rs[sc[q]].as<c32>(),
-                                       s, ug[q].data());
+                                       s, ug[q].data(), &gj);
       return;
     }
     gi.push_back({v.k, v.k, v.c, one, zero, v.P->U<float>(v.l), v.k, 0, OP_T, a, v.k, 2 * ck, OP_N, nullptr, 0, 0,
                   v.F->S[v.l].as<c32>(), v.k, (long)v.k * v.k, v.nb, false});
   });
+  {
+    DevBuf gtab;
+    gather_grouped(s, gj, gtab);
+    gj.clear();
+  }
   for (size_t q = 0; q < sc.size(); ++q)
     if (nug[q] >= 1) push(ug[q][0]);
   if (!gi.empty()) run();
@@ -3076,12 +3103,14 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
         gi.push_back({g.M, g.N, g.K, one, one, g.A, g.lda, g.sA, g.opA, g.B, g.ldb, g.sB, OP_N, g.C, g.ldc, g.sC,
                       g.C, g.ldc, g.sC, g.batch, false});
       };
+      std::vector<GatherJob> gj;  // (every instance's gathers in one launch)
+      DevBuf gtab1, gtab2;
       each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
         const c32* Sch = F.S[l + 1].as<c32>();
         if (!P.lev[l].ident) {
           ScatterGemm<float> g[2];
           const int ng = scatter_su_prep<float>(P, l, Sch, A1[i].as<c32>(), A2[i].as<c32>(), ck, Gs[i].as<c32>(),
-                                                s, g);
+                                                s, g, &gj);
           for (int t = 0; t < ng; ++t) push(g[t]);
           return;
         }
@@ -3091,6 +3120,8 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
         gi.push_back({c, k, c, one, zero, Sch + cc, c, 2 * cc, OP_N, U1 + ck, k, 0, OP_N, nullptr, 0, 0,
                       A2[i].as<c32>(), k, ck, nb, false});
       });
+      gather_grouped(s, gj, gtab1);
+      gj.clear();
       if (!gi.empty()) run_gemms(tabs[2]);
       each([&](int i, const lsh_plan_s&, FactorData<float>& F, int l, int c, int nb, int k, long cc, long ck) {
         gi.push_back({c, k, c, mone, one, F.Pb[l].as<c32>(), c, cc, OP_N, A1[i].as<c32>(), k, ck, OP_N,
@@ -3112,12 +3143,14 @@ void batch_factor_f32(std::vector<lsh_factor_s*>& Fs, mem::Arena& shared, hipStr
       each([&](int i, const lsh_plan_s& P, FactorData<float>& F, int l, int c, int nb, int k, long, long ck) {
         if (!P.lev[l].ident) {
           nug[i] = scatter_utb_prep<float>(P, l, A1[i].as<c32>(), Yl[i].as<c32>(), ck, F.S[l].as<c32>(),
-                                           Rs[i].as<c32>(), s, ug[i].data());
+                                           Rs[i].as<c32>(), s, ug[i].data(), &gj);
           return;
         }
         gi.push_back({k, k, c, one, zero, P.U<float>(l), k, 0, OP_T, A1[i].as<c32>(), k, ck, OP_N, nullptr, 0, 0,
                       F.S[l].as<c32>(), k, (long)k * k, nb, false});
       });
+      gather_grouped(s, gj, gtab2);
+      gj.clear();
       for (int i : act)
         if (nug[i] >= 1) push(ug[i][0]);
       if (!gi.empty()) run_gemms(tabs[6]);
