@@ -63,15 +63,15 @@ struct GemmP {
 };
 
 // Tile: 2 x 2 wavefronts, each owning WM x WN blocks of 16 x 16 outputs, so the
-// workgroup tile is (32 WM) x (32 WN); K advances 16 at a time.  LDS holds
+// workgroup tile is (32 WM) x (32 WN); K advances GBK (16 or 32) at a time.  LDS holds
 // separate real / imaginary planes laid out [row][k] with stride 17, which
 // keeps both the coalesced global->LDS stores and the MFMA operand reads
 // (16 rows x 4 k per instruction) within one extra bank conflict.  The next
 // K tile is prefetched into registers while the current one is multiplied.
-constexpr int GBK = 16, GLD = GBK + 1;
 
-template <typename R, int WM, int WN>
+template <typename R, int WM, int WN, int GBK = 16>
 __global__ __launch_bounds__(256) void k_cgemm(GemmP<R> P) {
+  constexpr int GLD = GBK + 1;
   using M4 = Mfma<R>;
   using acc_t = typename M4::acc_t;
   constexpr int BM = 32 * WM, BN = 32 * WN;
@@ -464,12 +464,13 @@ static void launch_gemm_x32(hipStream_t s, const GemmP<float>& P, const cplx<flo
   }
 }
 
-template <typename R, int WM, int WN>
+template <typename R, int WM, int WN, int BK = 16>
 static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, const cplx<R>* B, const cplx<R>* D,
                         cplx<R>* C, long sA, long sB, long sD, long sC, int batch) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   const char* name = sizeof(R) == 4 ? (BM == 128 ? "cgemm_f32_128x128" : "cgemm_f32_64x64")
-                                    : (BM == 128 ? "cgemm_f64_128x64" : "cgemm_f64_64x64");
+                                    : (BM == 128 ? "cgemm_f64_128x64" : BK == 32 ? "cgemm_f64_64x64k32"
+                                                                                 : "cgemm_f64_64x64");
   for (int b0 = 0; b0 < batch; b0 += 65535) {
     int nb = batch - b0 < 65535 ? batch - b0 : 65535;
     // algorithmic bytes: each distinct operand once, the result (and D) once per problem
@@ -481,21 +482,22 @@ static void launch_gemm(hipStream_t s, const GemmP<R>& P, const cplx<R>* A, cons
     Q.A = A + b0 * sA; Q.B = B + b0 * sB; Q.C = C + b0 * sC;
     if (D) Q.D = D + b0 * sD;
     dim3 grid(ceil_div(P.N, BN), ceil_div(P.M, BM), nb);
-    hipLaunchKernelGGL((k_cgemm<R, WM, WN>), grid, dim3(256), 0, s, Q);
+    hipLaunchKernelGGL((k_cgemm<R, WM, WN, BK>), grid, dim3(256), 0, s, Q);
     LSH_LAUNCH_CHECK();
   }
 }
 
 // ---- GEMM variants and their choice
 //
-// FP32: tile (64 WM) x (64 WN) with K depth BK.  FP64: 64 x 64 or 128 x 64.
+// FP32: tile (64 WM) x (64 WN) with K depth BK.  FP64: 64 x 64 (16 or 32 deep) or 128 x 64.
 // All variants of one precision add the same products in the same order, so
 // the choice changes the time, never the bits.
 struct GemmVariant { int wm, wn, bk; const char* name; };
 static const GemmVariant kF32Variants[] = {
     {1, 1, 32, "cgemm_f32_64x64"},   {2, 1, 32, "cgemm_f32_128x64"},    {2, 2, 32, "cgemm_f32_128x128"},
     {1, 1, 64, "cgemm_f32_64x64k64"}, {2, 1, 64, "cgemm_f32_128x64k64"}, {1, 2, 32, "cgemm_f32_64x128"}};
-static const GemmVariant kF64Variants[] = {{2, 2, 16, "cgemm_f64_64x64"}, {4, 2, 16, "cgemm_f64_128x64"}};
+static const GemmVariant kF64Variants[] = {
+    {2, 2, 16, "cgemm_f64_64x64"}, {4, 2, 16, "cgemm_f64_128x64"}, {2, 2, 32, "cgemm_f64_64x64k32"}};
 constexpr int kNumF32Variants = sizeof(kF32Variants) / sizeof(kF32Variants[0]);
 constexpr int kNumF64Variants = sizeof(kF64Variants) / sizeof(kF64Variants[0]);
 
@@ -507,13 +509,14 @@ const char* gemm_variant_name(int prec, int v) {
 // Without a tuned entry: a wave-quantisation model for FP32 (a launch takes
 // ceil(tiles / (256 CUs x resident workgroups per CU)) rounds, and a full
 // round costs (resident workgroups x tile area) / (per-CU efficiency of that
-// tile)), and the 64 x 64 tile for FP64 (44-46 against 34-39 TF/s on every
-// measured shape).
+// tile)), and the 32-deep 64 x 64 tile for FP64 (47-50 TF/s alone on the
+// plan's Gram and interpolation shapes, against 45-48 with 16-deep and 23-42
+// with 128 x 64 tiles).
 struct TileModel { int variant, bm, bn, resident; double eff; };
 static const TileModel kF32Model[2] = {{1, 128, 64, 2, 0.60}, {0, 64, 64, 4, 0.69}};
 
 static int model_variant(int prec, int M, int N, int batch) {
-  if (prec != 1) return 0;
+  if (prec != 1) return 2;
   int best = 0;
   double bt = 1e300;
   for (const TileModel& tm : kF32Model) {
@@ -648,8 +651,10 @@ void cgemm(hipStream_t s, int M, int N, int K, cplx<R> alpha,
       default: launch_gemm_x32<1, 1, 32>(s, P, A, B, D, C, sA, sB, sD, sC, batch, nm); break;
     }
   } else {
-    const int v = lower ? 0 : choose_variant(0, M, N, K, batch);
+    // (Hermitian Grams in lower mode: the 32-deep 64 x 64 tile, fastest on every measured shape)
+    const int v = lower ? 2 : choose_variant(0, M, N, K, batch);
     if (v == 1) launch_gemm<R, 4, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
+    else if (v == 2) launch_gemm<R, 2, 2, 32>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
     else launch_gemm<R, 2, 2>(s, P, A, B, D, C, sA, sB, sD, sC, batch);
   }
 }
