@@ -1209,15 +1209,18 @@ void factor_scatter(const lsh_plan_s& P, FactorData<R>& F, int l, hipStream_t s)
     ccopy2d<R>(s, c, c, Sch, c, 2 * cc, S, k, kk, nb);
     ccopy2d<R>(s, c, c, Sch + cc, c, 2 * cc, S + ck + c, k, kk, nb);
     if (F.wr[l] > 0) {  // S <- S - P W' [L^T a1; R^T a2], in place (as below with U = I)
+      // a1 = [S_a, 0] and a2 = [0, S_b], so [L^T a1; R^T a2] = [[L^T S_a, 0], [0, R^T S_b]] and
+      // W' times it is [W'_1 L^T S_a, W'_2 R^T S_b] (W'_1, W'_2: W''s first and last r columns)
       const int r = F.wr[l];
       const long rk = (long)r * k, cr = (long)c * r, w4 = 4L * r * r;
       cplx<R>* q = F.template scratch_buf<cplx<R>>(sizeof(cplx<R>) * nb * 4 * rk);
       cplx<R>* yv = q + nb * 2 * rk;
-      cgemm<R>(s, r, k, c, one, P.W<R>(l, 1), c, 0, OP_N, S, k, kk, OP_N, zero, nullptr, 0, 0, q, k, 2 * rk, nb);
-      cgemm<R>(s, r, k, c, one, P.W<R>(l, 3), c, 0, OP_N, S + ck, k, kk, OP_N, zero, nullptr, 0, 0, q + rk, k,
+      cgemm<R>(s, r, c, c, one, P.W<R>(l, 1), c, 0, OP_N, S, k, kk, OP_N, zero, nullptr, 0, 0, q, k, 2 * rk, nb);
+      cgemm<R>(s, r, c, c, one, P.W<R>(l, 3), c, 0, OP_N, S + ck + c, k, kk, OP_N, zero, nullptr, 0, 0, q + rk + c, k,
                2 * rk, nb);
-      cgemm<R>(s, 2 * r, k, 2 * r, one, Ci, 2 * r, w4, OP_N, q, k, 2 * rk, OP_N, zero, nullptr, 0, 0, yv, k, 2 * rk,
-               nb);
+      cgemm<R>(s, 2 * r, c, r, one, Ci, 2 * r, w4, OP_N, q, k, 2 * rk, OP_N, zero, nullptr, 0, 0, yv, k, 2 * rk, nb);
+      cgemm<R>(s, 2 * r, c, r, one, Ci + r, 2 * r, w4, OP_N, q + rk + c, k, 2 * rk, OP_N, zero, nullptr, 0, 0, yv + c,
+               k, 2 * rk, nb);
       cgemm<R>(s, c, k, r, mone, Pa, r, cr, OP_N, yv, k, rk, OP_N, one, S, k, ck, S, k, ck, 2 * nb);
       return;
     }
