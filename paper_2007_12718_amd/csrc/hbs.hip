@@ -1073,7 +1073,7 @@ static void gram_interp(hipStream_t s, const z64* Lt, int m, int k, int* J, z64*
 }
 
 int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws,
-             bool gram_ready, NextGram* next) {
+             bool gram_ready, NextGram* next, const std::function<void(int)>& on_skel) {
   LSH_REQUIRE(alpha > 0.0 && alpha <= 1.0, -1, "row ID: alpha must lie in (0, 1]");
   LSH_REQUIRE(m <= BP_SEL, -6, "row ID: more than 16384 candidate rows in one level");
   char* p = static_cast<char*>(ws);
@@ -1161,9 +1161,11 @@ int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alph
     LSH_HIP(hipMemcpyAsync(U, &one, sizeof(z64), hipMemcpyHostToDevice, s));
     LSH_HIP(hipStreamSynchronize(s));
     if (next) next_gram_rows(*next, J, 1);
+    if (on_skel) on_skel(1);
     return 1;
   }
   if (next) next_gram_rows(*next, J, j);  // (J is final: the stream was synchronised)
+  if (on_skel) on_skel(j);                // (before the interpolation matrix)
   // (the Gram is no longer needed: it holds L11^{-1}; the pairs' temporaries
   // follow the rest rows in Lr)
   gram_interp(s, Lt, m, j, J, U, rest, L11, Lr, Dinv, M, Lr + (size_t)(m - j) * j);

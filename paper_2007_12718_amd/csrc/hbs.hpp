@@ -1,5 +1,6 @@
 // HBS compression / factor / apply kernels (host launchers).
 #pragma once
+#include <functional>
 #include "blas.hpp"
 
 namespace lsh {
@@ -64,8 +65,10 @@ void next_gram_pack(hipStream_t s, const NextGram& g, int k, z64* M);
 // entries, from next_gram_pack; A unused).  next (or null): the parent
 // level's Gram rows, fed after each batch of steps and at the end.
 // Returns the rank (synchronises on the stream once per batch of steps).
+// on_skel(k), when given, runs once the skeleton J[0..k) is final on the
+// device (s synchronised), before the interpolation matrix U is formed.
 int rowid_bp(hipStream_t s, const z64* A, int m, int np, double tol, double alpha, int* J, z64* U, void* ws,
-             bool gram_ready = false, NextGram* next = nullptr);
+             bool gram_ready = false, NextGram* next = nullptr, const std::function<void(int)>& on_skel = {});
 size_t rowid_bp_ws(int m);
 
 // Leaf factor helpers (R = working precision)

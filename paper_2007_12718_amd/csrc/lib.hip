@@ -55,6 +55,10 @@ struct Level {
   DevBuf U64, U32;       // m x k
   DevBuf Ut64, Ut32;     // k x m (transpose, for row-streamed products)
   bool ident = false;    // U = I (k = m): the level keeps all its candidates
+  // cand, m, J and k are known (set once: the sibling blocks read them while
+  // the interpolation matrix of this level is still being formed)
+  bool skel_known = false;
+  bool host_ready = false;  // an uncompressed level prepared ahead from its children
   // U is the identity on the skeleton rows J.  For the factor's products
   // with U (levels 1 .. L-1, candidates of half h: h m/2 .. h m/2 + m/2 - 1):
   // the other rows ("rest", ascending; nrest0 of them in half 0), and on the
@@ -98,6 +102,10 @@ struct lsh_plan_s {
   // side stream for the parent Gram rows while a plan is built (null: the
   // Gram of each level is formed after its candidates are known)
   hipStream_t gs = nullptr;
+  // called (on the row-ID thread) once the skeleton of a level is known,
+  // before its interpolation matrix: lsh_build starts the sibling blocks
+  // that need it
+  std::function<void(int)> skel_cb;
   NextGram ng;          // the parent Gram in progress or done
   int ng_level = -1;    // the level whose Gram ng holds (-1: none)
   std::vector<I2> ng_prox;  // (host source of its proxy upload)
@@ -245,11 +253,25 @@ int identity_id(int m, std::vector<int>& Jh, DevBuf& U64, hipStream_t s) {
 // block before the pivot steps; it may fill that block (ready = true: A is
 // then unused) and return the parent level's Gram rows to feed (or null).
 int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, DevBuf& U64, mem::Arena& scr,
-                  hipStream_t s, const std::function<NextGram*(z64*, bool&)>& gram = {}) {
-  if (P.d.tol == 0) return identity_id(m, Jh, U64, s);  // exact full-rank form
+                  hipStream_t s, const std::function<NextGram*(z64*, bool&)>& gram = {},
+                  const std::function<void(int)>& on_skel = {}) {
+  if (P.d.tol == 0) {  // exact full-rank form
+    const int k = identity_id(m, Jh, U64, s);
+    if (on_skel) on_skel(k);
+    return k;
+  }
   int* J = static_cast<int*>(scr.take(sizeof(int) * m));
   z64* Ufull = static_cast<z64*>(scr.take(sizeof(z64) * (size_t)m * m));
   int k = 0;
+  // the skeleton to the host once it is final (J is written once), then on_skel
+  bool told = false;
+  auto skel = [&](int kk) {
+    Jh.resize(kk);
+    LSH_HIP(hipMemcpyAsync(Jh.data(), J, sizeof(int) * kk, hipMemcpyDeviceToHost, s));
+    LSH_HIP(hipStreamSynchronize(s));
+    told = true;
+    if (on_skel) on_skel(kk);
+  };
   // Gram + pivoted Cholesky squares the conditioning: FP64 resolves the
   // stopping rule only while tol stays above ~1e-7; below that, CPQR.
   if (P.d.tol < 1e-7) {
@@ -282,11 +304,10 @@ int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, De
       void* ws = scr.take(rowid_bp_ws(m));
       bool ready = false;
       NextGram* next = gram ? gram(static_cast<z64*>(ws), ready) : nullptr;
-      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, ws, ready, next);
+      k = rowid_bp(s, A, m, np, P.d.tol, alpha, J, Ufull, ws, ready, next, skel);
     }
   }
-  Jh.resize(k);
-  LSH_HIP(hipMemcpyAsync(Jh.data(), J, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  if (!told) skel(k);
   U64.alloc(sizeof(z64) * (size_t)m * k);
   LSH_HIP(hipMemcpyAsync(U64.p, Ufull, sizeof(z64) * (size_t)m * k, hipMemcpyDeviceToDevice, s));
   LSH_HIP(hipStreamSynchronize(s));
@@ -330,11 +351,47 @@ bool block_pivots(const lsh_plan_s& P) {
 // stream, the Gram of level l (built during the row ID of level l + 1) is
 // packed instead of formed here, and the rows of level l - 1's Gram are
 // built while this row ID runs.
+// the candidates of level l < L: the skeleton points of its two children, in
+// the coordinates of box 0 of level l
+void level_candidates(const lsh_plan_s& P, int l, Level& lv) {
+  lv.cand.clear();
+  int ox, oy, sx, sy;
+  box_of(P.d.n, l, 0, ox, oy, sx, sy);
+  for (int c = 0; c < 2; ++c) {
+    int cx, cy, csx, csy;
+    box_of(P.d.n, l + 1, c, cx, cy, csx, csy);
+    const Level& ch = P.lev[l + 1];
+    for (int j : ch.J) lv.cand.push_back(I2{ch.cand[j].x + cx - ox, ch.cand[j].y + cy - oy});
+  }
+  lv.m = (int)lv.cand.size();
+}
+
+// level l's skeleton is known: note it, prepare the uncompressed levels above
+// it (their candidates, skeleton and rank follow from it), and tell the plan's
+// owner
+void skeleton_known(lsh_plan_s& P, int l) {
+  P.lev[l].skel_known = true;
+  int top = l;
+  while (top - 1 >= 1 && (P.d.tol == 0 || top - 1 <= P.d.full_levels)) {
+    Level& up = P.lev[top - 1];
+    level_candidates(P, top - 1, up);
+    up.ident = true;
+    up.J.resize(up.m);
+    for (int i = 0; i < up.m; ++i) up.J[i] = i;
+    up.k = up.m;
+    up.host_ready = up.skel_known = true;
+    --top;
+  }
+  if (P.skel_cb) P.skel_cb(top);
+}
+
 void level_id(lsh_plan_s& P, int l, Level& lv, const std::vector<I2>& prox, hipStream_t s) {
   const int m = lv.m, np = (int)prox.size();
-  lv.ident = P.d.tol == 0 || l <= P.d.full_levels;
+  if (!lv.host_ready) lv.ident = P.d.tol == 0 || l <= P.d.full_levels;
   if (lv.ident) {  // every candidate kept (exact form, or an uncompressed top level)
-    lv.k = identity_id(m, lv.J, lv.U64, s);
+    std::vector<int> Jtmp;  // (J and k already set when prepared ahead)
+    const int k = identity_id(m, lv.host_ready ? Jtmp : lv.J, lv.U64, s);
+    if (!lv.host_ready) lv.k = k;
     return;
   }
   pcache::Key key;
@@ -389,7 +446,11 @@ void level_id(lsh_plan_s& P, int l, Level& lv, const std::vector<I2>& prox, hipS
     P.ng_level = l - 1;
     return &g;
   };
-  lv.k = row_id_matrix(P, A, m, ncols, lv.J, lv.U64, P.sid, s, block ? gram : std::function<NextGram*(z64*, bool&)>());
+  row_id_matrix(P, A, m, ncols, lv.J, lv.U64, P.sid, s, block ? gram : std::function<NextGram*(z64*, bool&)>(),
+                [&](int k) {
+                  lv.k = k;
+                  skeleton_known(P, l);
+                });
   if (P.d.plan_cache) pcache::insert(key, lv.cand, lv.J, m, lv.k, lv.U64, s);
 }
 
@@ -493,21 +554,16 @@ void plan_id(lsh_plan_s& P, int l, hipStream_t s) {
     if (P.gs) LSH_HIP(hipStreamSynchronize(P.gs));  // (this level's Gram rows, read from the previous sid)
     P.sid.reset(0);  // (the previous level's temporaries are no longer in use)
     Level& lv = P.lev[l];
-    if (l == P.L) {
-      lv.cand = P.leaf_pts_h;
-    } else {
-      lv.cand.clear();
-      int ox, oy, sx, sy;
-      box_of(d.n, l, 0, ox, oy, sx, sy);
-      for (int c = 0; c < 2; ++c) {
-        int cx, cy, csx, csy;
-        box_of(d.n, l + 1, c, cx, cy, csx, csy);
-        const Level& ch = P.lev[l + 1];
-        for (int j : ch.J) lv.cand.push_back(I2{ch.cand[j].x + cx - ox, ch.cand[j].y + cy - oy});
+    if (!lv.host_ready) {
+      if (l == P.L) {
+        lv.cand = P.leaf_pts_h;
+        lv.m = (int)lv.cand.size();
+      } else {
+        level_candidates(P, l, lv);
       }
     }
-    lv.m = (int)lv.cand.size();
     level_id(P, l, lv, proxy_ring(lv.sx, lv.sy, d.proxy_width), s);
+    if (!lv.skel_known) skeleton_known(P, l);
     if (f32) {
       lv.U32.alloc(sizeof(c32) * (size_t)lv.m * lv.k);
       ccast<double, float>(s, lv.U64.as<z64>(), lv.U32.as<c32>(), (long)lv.m * lv.k);
@@ -2536,6 +2592,7 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
     ~BsGuard() {  // (the side stream's rows read plan memory: drained before the streams go back)
       if (b->pg) (void)hipStreamSynchronize(b->pg);
       P->gs = nullptr;
+      P->skel_cb = nullptr;  // (it refers to this call's thread state)
       BuildStreams::release(b);
     }
   } bsg{bs, P.get()};
@@ -2572,16 +2629,41 @@ int lsh_build(const lsh_desc* desc, const double* b, int flags, void* plan_ws, s
   // Sibling levels are claimed in order by either thread: once its row IDs
   // are done, the first thread takes the next unclaimed one (the last two,
   // typically: they need the same skeletons and run side by side).
-  int nextSib = L - 1;                 // next sibling level to claim
+  // A sibling block needs only the skeleton of the level below it, which is
+  // known before that level's interpolation matrix (skelU: the lowest level
+  // whose skeleton is known).  The root's block is claimed as soon as it can
+  // start (it is the longest, and with level 1 kept whole it needs only the
+  // skeleton of level 2); the others in order.
+  std::vector<char> claimed(L + 1, 0);
   std::vector<char> sibDone(L + 1, 0);
-  auto claim = [&]() -> int {
-    std::lock_guard<std::mutex> g(mu);
-    return failed ? -1 : nextSib--;
+  int skelU = L + 1;
+  P->skel_cb = [&](int l) {
+    { std::lock_guard<std::mutex> g(mu); skelU = std::min(skelU, l); }
+    cv.notify_all();
+  };
+  auto claim = [&]() -> int {  // (waits until a block can start)
+    std::unique_lock<std::mutex> g(mu);
+    for (;;) {
+      if (failed) return -1;
+      if (L >= 1 && !claimed[0] && skelU <= 1) {
+        claimed[0] = 1;
+        return 0;
+      }
+      int next = -1;
+      for (int l = L - 1; l >= 0 && next < 0; --l)
+        if (!claimed[l]) next = l;
+      if (next < 0) return -1;
+      if (skelU <= next + 1) {
+        claimed[next] = 1;
+        return next;
+      }
+      cv.wait(g);
+    }
   };
   auto sibling = [&](int l, hipStream_t st, mem::Arena& tmp, bool drain) {
     {
       std::unique_lock<std::mutex> g(mu);
-      cv.wait(g, [&] { return failed || doneU <= l + 1; });
+      cv.wait(g, [&] { return failed || skelU <= l + 1; });
       if (failed) return false;
     }
     plan_sibling(*P, l, st, tmp);
