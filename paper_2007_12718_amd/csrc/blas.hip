@@ -1089,19 +1089,27 @@ void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, co
                (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * ((R1 < Rr ? 2.0 : 1.0) * C +
                                                                           (Z ? 2.0 : 1.0) * Rr)));
   constexpr int RR = sizeof(R) == 4 ? 4 : 2;  // (FP64: the accumulators in half the rows)
-#define LSH_MG(NVV, WSS) \
-  cmgemv_launch<R, RR, NVV, WSS>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec)
+  // Launches that would give fewer than two workgroups per compute unit take
+  // one row per wave instead (each row's sum is the same either way).
+  const int nvs = nvec == 1 ? 1 : nvec == 2 ? 2 : nvec <= 4 ? 4 : 8;
+  const int rows = C >= 1024 ? RR : 4 * RR;
+  const long wgs = (long)(ceil_div(R1, rows) + ceil_div(Rr - R1, rows)) * ceil_div(nvec, nvs);
+  const bool thin = wgs < 512;
+#define LSH_MG(RRV, NVV, WSS) \
+  cmgemv_launch<R, RRV, NVV, WSS>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec)
+#define LSH_MG_NV(RRV, WSS)           \
+  if (nvs == 1) LSH_MG(RRV, 1, WSS);  \
+  else if (nvs == 2) LSH_MG(RRV, 2, WSS); \
+  else if (nvs == 4) LSH_MG(RRV, 4, WSS); \
+  else LSH_MG(RRV, 8, WSS);
   if (C >= 1024) {
-    if (nvec == 1) LSH_MG(1, 4);
-    else if (nvec == 2) LSH_MG(2, 4);
-    else if (nvec <= 4) LSH_MG(4, 4);
-    else LSH_MG(8, 4);
+    if (thin) { LSH_MG_NV(1, 4) }
+    else { LSH_MG_NV(RR, 4) }
   } else {
-    if (nvec == 1) LSH_MG(1, 1);
-    else if (nvec == 2) LSH_MG(2, 1);
-    else if (nvec <= 4) LSH_MG(4, 1);
-    else LSH_MG(8, 1);
+    if (thin) { LSH_MG_NV(1, 1) }
+    else { LSH_MG_NV(RR, 1) }
   }
+#undef LSH_MG_NV
 #undef LSH_MG
   LSH_LAUNCH_CHECK();
 }
