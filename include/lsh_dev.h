@@ -98,6 +98,16 @@ int lsh_gemm_force_variant(int variant);
  * default. */
 int lsh_fused_levels(int min_boxes);
 
+/* Preconditioner apply (Algorithm 2, M = A^-1 approximately): a Woodbury
+ * level whose box vectors (boxes times right-hand sides) number at least
+ * min_vectors, and whose per-box vectors fit one workgroup's LDS, runs each
+ * pass in one launch with a workgroup per box vector and its intermediates in
+ * LDS; the other levels run the step's six to seven batched products.  The
+ * two forms agree to rounding (different summation orders).  Affects later
+ * applies (lsh_factor_apply, lsh_solve, lsh_build): 0 never fuses, 1 fuses
+ * every such level, -1 restores the default (512). */
+int lsh_apply_fused_levels(int min_vectors);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1546,6 +1546,175 @@ void leaf_tdown(hipStream_t s, const cplx<R>* XT, const cplx<R>* UL, int mL, int
   LSH_LAUNCH_CHECK();
 }
 
+// ------------------------------------------- apply, one Woodbury level fused
+// Rows of one box product inside a workgroup of NT threads: out(i, sum_j
+// A_i[j] x_i[j]) for i < M, j < N, with x_i in LDS.  16 lanes per row (lane s
+// takes columns s + 16u of each 64-column chunk), P rows per 16-lane group at
+// a time with every load issued before the products; column u of a chunk goes
+// to partial sum u, then (s0 + s1) + (s2 + s3) and a DPP butterfly over the
+// 16 lanes.  (The same arithmetic for any NT.)
+template <typename R, int P, int NT, typename RowA, typename RowX, typename Out>
+__device__ __forceinline__ void box_rows(int M, int N, RowA rowA, RowX rowX, Out out) {
+  constexpr int NG = NT / 16;
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  for (int i0 = grp * P; i0 < M; i0 += NG * P) {
+    cplx<R> acc[P][4];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[p][u] = mk<R>(0, 0);
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      cplx<R> a[P][4], x[P][4];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int i = i0 + p < M ? i0 + p : M - 1;
+        const cplx<R>* ar = rowA(i);
+        const cplx<R>* xr = rowX(i);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = j0 + sub + 16 * u;
+          const bool ok = i0 + p < M && jj < N;
+          a[p][u] = ok ? ar[jj] : mk<R>(0, 0);
+          x[p][u] = ok ? xr[jj] : mk<R>(0, 0);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fma_acc(acc[p][u], a[p][u], x[p][u]);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      cplx<R> t = (acc[p][0] + acc[p][1]) + (acc[p][2] + acc[p][3]);
+      t.x = group_sum<16>(t.x);
+      t.y = group_sum<16>(t.y);
+      if (sub == 0 && i0 + p < M) out(i0 + p, t);
+    }
+  }
+}
+
+// Up, one level (Algorithm 2's upward step on a Woodbury level): per box
+// vector v (box v mod nb) with input [rt_a; rt_b] (2c),
+//   q = [L^T rt_a; R^T rt_b], y = W'_b q, t = in - [S_a L y1; S_b R y2],
+//   out_v = U_l^T t (k),
+// every intermediate in LDS: one workgroup of NT threads per box vector.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_level_up(LevelApply<R> A, const cplx<R>* __restrict__ in,
+                                                 cplx<R>* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char lvl_lds[];
+  const int c = A.c, k = A.k, r = A.r;
+  const long v = blockIdx.x;
+  const long b = v % A.nb;
+  cplx<R>* xs = reinterpret_cast<cplx<R>*>(lvl_lds);  // [2c]
+  cplx<R>* q = xs + 2 * c;                             // [2r]
+  cplx<R>* y = q + 2 * r;                              // [2r]
+  cplx<R>* t = y + 2 * r;                              // [2c]
+  const cplx<R>* iv = in + v * 2 * c;
+  for (int i = threadIdx.x; i < 2 * c; i += NT) xs[i] = iv[i];
+  __syncthreads();
+  box_rows<R, 2, NT>(2 * r, c, [&](int i) { return A.Q + (long)i * c; },
+                     [&](int i) { return i < r ? xs : xs + c; }, [&](int i, cplx<R> s) { q[i] = s; });
+  __syncthreads();
+  const cplx<R>* Wb = A.Ci + b * 4 * r * r;
+  box_rows<R, 2, NT>(2 * r, 2 * r, [&](int i) { return Wb + (long)i * 2 * r; },
+                     [&](int) { return (const cplx<R>*)q; }, [&](int i, cplx<R> s) { y[i] = s; });
+  __syncthreads();
+  const cplx<R>* Pb = A.Pa + b * 2 * c * r;  // [S_a L; S_b R] of the two children, rows contiguous
+  box_rows<R, 2, NT>(2 * c, r, [&](int i) { return Pb + (long)i * r; }, [&](int i) { return i < c ? y : y + r; },
+                     [&](int i, cplx<R> s) { t[i] = xs[i] - s; });
+  __syncthreads();
+  cplx<R>* ov = out + v * k;
+  box_rows<R, 2, NT>(k, 2 * c, [&](int i) { return A.Ut + (long)i * 2 * c; },
+                     [&](int) { return (const cplx<R>*)t; }, [&](int i, cplx<R> s) { ov[i] = s; });
+}
+
+// Down, one level: per box vector v with wt_v (k) and the children's rt (2c),
+//   u = U_l wt_v, d = rt - diag(S_a, S_b) u, o = X_tau d (the Woodbury form
+//   as above), wt_children = [G_ab o_b; G_ba o_a] + u,
+// every intermediate in LDS.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_level_down(LevelApply<R> A, const cplx<R>* __restrict__ wt,
+                                                   const cplx<R>* __restrict__ rtc, cplx<R>* __restrict__ wc) {
+  extern __shared__ __align__(16) unsigned char lvl_lds[];
+  const int c = A.c, k = A.k, r = A.r;
+  const long v = blockIdx.x;
+  const long b = v % A.nb;
+  cplx<R>* w = reinterpret_cast<cplx<R>*>(lvl_lds);  // [k]
+  cplx<R>* u = w + k;                                 // [2c]
+  cplx<R>* d = u + 2 * c;                             // [2c]
+  cplx<R>* q = d + 2 * c;                             // [2r]
+  cplx<R>* y = q + 2 * r;                             // [2r]
+  cplx<R>* o = y + 2 * r;                             // [2c]
+  const cplx<R>* wv = wt + v * k;
+  for (int i = threadIdx.x; i < k; i += NT) w[i] = wv[i];
+  __syncthreads();
+  box_rows<R, 2, NT>(2 * c, k, [&](int i) { return A.U + (long)i * k; }, [&](int) { return (const cplx<R>*)w; },
+                     [&](int i, cplx<R> s) { u[i] = s; });
+  __syncthreads();
+  const cplx<R>* Sb = A.S + b * 2 * c * c;  // S_a, S_b of the two children, rows contiguous
+  const cplx<R>* rv = rtc + v * 2 * c;
+  box_rows<R, 2, NT>(2 * c, c, [&](int i) { return Sb + (long)i * c; }, [&](int i) { return i < c ? u : u + c; },
+                     [&](int i, cplx<R> s) { d[i] = rv[i] - s; });
+  __syncthreads();
+  box_rows<R, 2, NT>(2 * r, c, [&](int i) { return A.Q + (long)i * c; }, [&](int i) { return i < r ? d : d + c; },
+                     [&](int i, cplx<R> s) { q[i] = s; });
+  __syncthreads();
+  const cplx<R>* Wb = A.Ci + b * 4 * r * r;
+  box_rows<R, 2, NT>(2 * r, 2 * r, [&](int i) { return Wb + (long)i * 2 * r; },
+                     [&](int) { return (const cplx<R>*)q; }, [&](int i, cplx<R> s) { y[i] = s; });
+  __syncthreads();
+  const cplx<R>* Pb = A.Pa + b * 2 * c * r;
+  box_rows<R, 2, NT>(2 * c, r, [&](int i) { return Pb + (long)i * r; }, [&](int i) { return i < c ? y : y + r; },
+                     [&](int i, cplx<R> s) { o[i] = d[i] - s; });
+  __syncthreads();
+  cplx<R>* ov = wc + v * 2 * c;
+  box_rows<R, 2, NT>(2 * c, c, [&](int i) { return i < c ? A.Gab + (long)i * c : A.Gba + (long)(i - c) * c; },
+                     [&](int i) { return i < c ? o + c : o; }, [&](int i, cplx<R> s) { ov[i] = s + u[i]; });
+}
+
+// threads per box vector: about 8192 waves in all (few vectors: more lanes on
+// each vector's rows)
+static int level_threads(int nvec) { return nvec <= 512 ? 1024 : nvec <= 1024 ? 512 : 256; }
+
+template <typename R>
+static void level_check(const LevelApply<R>& A, int nvec) {
+  LSH_REQUIRE(A.c > 0 && A.k > 0 && A.r > 0 && A.nb > 0 && nvec > 0 && nvec % A.nb == 0, -6,
+              "fused level apply: bad sizes");
+  LSH_REQUIRE((size_t)(A.k + 6 * A.c + 4 * A.r) * sizeof(cplx<R>) <= LEVEL_FUSED_LDS, -6,
+              "fused level apply: the box vectors exceed the workgroup's LDS");
+}
+
+template <typename R>
+void level_up_fused(hipStream_t s, const LevelApply<R>& A, const cplx<R>* in, cplx<R>* out, int nvec) {
+  level_check(A, nvec);
+  const double e = (double)sizeof(cplx<R>);
+  ProfScope ps(sizeof(R) == 4 ? "level_up_f32" : "level_up_f64", s,
+               e * ((double)A.nb * (4.0 * A.r * A.r + 2.0 * A.c * A.r) + 2.0 * A.r * A.c + 2.0 * A.c * A.k +
+                    (double)nvec * (2.0 * A.c + A.k)));
+  const size_t lds = (size_t)(4 * A.c + 4 * A.r) * sizeof(cplx<R>);
+  const int nt = level_threads(nvec);
+  if (nt == 1024) hipLaunchKernelGGL((k_level_up<R, 1024>), dim3(nvec), dim3(1024), lds, s, A, in, out);
+  else if (nt == 512) hipLaunchKernelGGL((k_level_up<R, 512>), dim3(nvec), dim3(512), lds, s, A, in, out);
+  else hipLaunchKernelGGL((k_level_up<R, 256>), dim3(nvec), dim3(256), lds, s, A, in, out);
+  LSH_LAUNCH_CHECK();
+}
+
+template <typename R>
+void level_down_fused(hipStream_t s, const LevelApply<R>& A, const cplx<R>* wt, const cplx<R>* rtc, cplx<R>* wc,
+                      int nvec) {
+  level_check(A, nvec);
+  const double e = (double)sizeof(cplx<R>);
+  ProfScope ps(sizeof(R) == 4 ? "level_down_f32" : "level_down_f64", s,
+               e * ((double)A.nb * (2.0 * A.c * A.c + 4.0 * A.r * A.r + 2.0 * A.c * A.r) + 2.0 * A.c * A.k +
+                    2.0 * A.r * A.c + 2.0 * A.c * A.c + (double)nvec * (A.k + 4.0 * A.c)));
+  const size_t lds = (size_t)(A.k + 6 * A.c + 4 * A.r) * sizeof(cplx<R>);
+  const int nt = level_threads(nvec);
+  if (nt == 1024) hipLaunchKernelGGL((k_level_down<R, 1024>), dim3(nvec), dim3(1024), lds, s, A, wt, rtc, wc);
+  else if (nt == 512) hipLaunchKernelGGL((k_level_down<R, 512>), dim3(nvec), dim3(512), lds, s, A, wt, rtc, wc);
+  else hipLaunchKernelGGL((k_level_down<R, 256>), dim3(nvec), dim3(256), lds, s, A, wt, rtc, wc);
+  LSH_LAUNCH_CHECK();
+}
+
 #define LSH_HBS_INST(R)                                                                                       \
   template void leaf_build<R>(hipStream_t, cplx<R>*, const cplx<R>*, int, const double*, double, const I2*,   \
                               const I2*, int, int);                                                          \
@@ -1556,7 +1725,10 @@ void leaf_tdown(hipStream_t s, const cplx<R>* XT, const cplx<R>* UL, int mL, int
   template void leaf_tdown<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const cplx<R>*, const z64*,  \
                               z64*, const I2*, const I2*, int, int, int);                                    \
   template void leaf_down<R>(hipStream_t, const cplx<R>*, const cplx<R>*, int, int, const cplx<R>*,           \
-                             const cplx<R>*, z64*, const double*, double, const I2*, const I2*, int, int, int);
+                             const cplx<R>*, z64*, const double*, double, const I2*, const I2*, int, int, int);    \
+  template void level_up_fused<R>(hipStream_t, const LevelApply<R>&, const cplx<R>*, cplx<R>*, int);            \
+  template void level_down_fused<R>(hipStream_t, const LevelApply<R>&, const cplx<R>*, const cplx<R>*, cplx<R>*, \
+                                    int);
 LSH_HBS_INST(float)
 LSH_HBS_INST(double)
 

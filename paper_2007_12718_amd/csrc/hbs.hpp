@@ -94,4 +94,24 @@ void leaf_down(hipStream_t s, const cplx<R>* X, const cplx<R>* UL, int mL, int k
                const cplx<R>* r, z64* q, const double* b, double kappa2, const I2* leaf_origin,
                const I2* leaf_pts, int nleaf, int n, int nrhs);
 
+// Apply, one Woodbury level in one launch per pass (a workgroup per box
+// vector, the intermediates in LDS).  Shared: U (2c x k), Ut (k x 2c),
+// Q = [L^T; R^T] (2r x c), Gab, Gba (c x c); per box b < nb: Ci = W' (2r x 2r)
+// and Pa = [S_a L; S_b R] (two c x r blocks); per child: S (c x c).  All
+// row-major and packed.  Box vector v belongs to box v mod nb.
+template <typename R>
+struct LevelApply {
+  int c, k, r, nb;
+  const cplx<R> *U, *Ut, *Q, *Gab, *Gba, *S, *Ci, *Pa;
+};
+// the LDS the box vectors of one workgroup may take (k + 6c + 4r entries)
+constexpr size_t LEVEL_FUSED_LDS = 64 * 1024;
+// out[v] (k) = U^T X_tau in[v] (in: [nvec][2c])
+template <typename R>
+void level_up_fused(hipStream_t s, const LevelApply<R>& A, const cplx<R>* in, cplx<R>* out, int nvec);
+// wc[v] (2c) = Ghat X_tau (rtc[v] - diag(S) U wt[v]) + U wt[v]
+template <typename R>
+void level_down_fused(hipStream_t s, const LevelApply<R>& A, const cplx<R>* wt, const cplx<R>* rtc, cplx<R>* wc,
+                      int nvec);
+
 }  // namespace lsh

@@ -1,3 +1,9 @@
+// Woodbury levels with at least this many box vectors (lsh_apply_fused_levels;
+// 0: never) whose box vectors fit one workgroup's LDS run each apply pass in
+// one launch (level_up_fused / level_down_fused) instead of six to seven.
+constexpr int kApplyFusedMin = 512;
+static int g_apply_fused_min = kApplyFusedMin;
+
 // Host orchestration and the C ABI (include/lsh.h).
 //
 // plan   : tree (Sec. 3.1-3.2), correction weights (Sec. 2.2), kernel table,
@@ -1564,6 +1570,28 @@ void ensure_transposed(const lsh_plan_s& P, FactorData<R>& F, hipStream_t s) {
   F.has_T = true;
 }
 
+// Woodbury levels with at least this many box vectors (LSH_LEVEL_FUSED
+// overrides it) whose box vectors fit one workgroup's LDS run each pass in one
+// launch (level_up_fused / level_down_fused) instead of six to seven.
+int level_fused_min() {
+  static const int v = [] {
+    const char* e = std::getenv("LSH_LEVEL_FUSED");
+    return e && *e ? std::atoi(e) : 512;
+  }();
+  return v;
+}
+
+template <typename R>
+bool level_fused(const lsh_plan_s& P, FactorData<R>& F, int l, int B, LevelApply<R>& A) {
+  if (g_apply_fused_min <= 0 || B < g_apply_fused_min || l < 1 || l >= P.L || P.lev[l].ident || F.wr[l] <= 0)
+    return false;
+  const int c = P.lev[l].c, k = P.lev[l].k, r = F.wr[l];
+  if ((size_t)(k + 6 * c + 4 * r) * sizeof(cplx<R>) > LEVEL_FUSED_LDS) return false;
+  A = {c, k, r, 1 << l, P.U<R>(l), P.Ut<R>(l), P.W<R>(l, 1), P.Gab<R>(l), P.Gabt<R>(l),
+       F.S[l + 1].template as<cplx<R>>(), F.Ci[l].template as<cplx<R>>(), F.Pa[l].template as<cplx<R>>()};
+  return true;
+}
+
 template <typename R>
 void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* f, z64* q, int nrhs,
              hipStream_t s) {
@@ -1580,6 +1608,11 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
   // upward pass
   for (int l = L - 1; l >= 1; --l) {
     const int c = P.lev[l].c, k = P.lev[l].k, B = nrhs << l;
+    LevelApply<R> A;
+    if (level_fused(P, F, l, B, A)) {
+      level_up_fused<R>(s, A, F.rt[l + 1].template as<cplx<R>>(), F.rt[l].template as<cplx<R>>(), B);
+      continue;
+    }
     apply_X<R>(P, F, l, nrhs, F.rt[l + 1].template as<cplx<R>>(), t1, s);
     // rt_l = U_l^T xv
     shared_mv<R>(s, k, 2 * c, one, P.Ut<R>(l), P.U<R>(l), k, OP_N, t1, 2 * c, zero, nullptr, 0,
@@ -1597,6 +1630,12 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
   for (int l = 1; l <= L - 1; ++l) {
     const int c = P.lev[l].c, k = P.lev[l].k, nb = 1 << l, B = nrhs * nb;
     const long cc = (long)c * c;
+    LevelApply<R> A;
+    if (level_fused(P, F, l, B, A)) {
+      level_down_fused<R>(s, A, F.wt[l].template as<cplx<R>>(), F.rt[l + 1].template as<cplx<R>>(),
+                          F.wt[l + 1].template as<cplx<R>>(), B);
+      continue;
+    }
     // u = U_l wt_l  ([B][2c])
     shared_mv<R>(s, 2 * c, k, one, P.U<R>(l), P.U<R>(l), k, OP_T, F.wt[l].template as<cplx<R>>(), k, zero, nullptr,
                  0, t1, 2 * c, B, F.tk, P.lev[l].ident);
@@ -3567,6 +3606,14 @@ int lsh_fused_levels(int min_boxes) {
   API_BEGIN
   LSH_REQUIRE(min_boxes >= -1, LSH_ERR_INVALID_ARG, "min_boxes must be >= -1");
   g_fused_min_boxes = min_boxes < 0 ? kFusedMinBoxes : min_boxes;
+  return LSH_OK;
+  API_END
+}
+
+int lsh_apply_fused_levels(int min_vectors) {
+  API_BEGIN
+  LSH_REQUIRE(min_vectors >= -1, LSH_ERR_INVALID_ARG, "min_vectors must be >= -1");
+  g_apply_fused_min = min_vectors < 0 ? kApplyFusedMin : min_vectors;
   return LSH_OK;
   API_END
 }

@@ -36,6 +36,7 @@ EXPORTED = [
     "lsh_plan_cache_load", "lsh_gemm_variants", "lsh_gemm_tune_workspace", "lsh_gemm_tune", "lsh_gemm_table_save",
     "lsh_gemm_table_load", "lsh_gemm_table_clear", "lsh_gemm_record", "lsh_gemm_recorded",
     "lsh_gemm_force_variant", "lsh_dev_inverse_static", "lsh_fused_levels", "lsh_profile_bytes",
+    "lsh_apply_fused_levels",
 ]
 
 # tuned GEMM variant choices (written by tune_gemm.py on an MI355X); LSH_GEMM_TABLE overrides the path,
@@ -148,6 +149,7 @@ def lib():
         L.lsh_gemm_recorded.argtypes = [POINTER(c_int), POINTER(c_int), c_int]
         L.lsh_gemm_force_variant.argtypes = [c_int]
         L.lsh_fused_levels.argtypes = [c_int]
+        L.lsh_apply_fused_levels.argtypes = [c_int]
         L.lsh_dev_inverse_static.argtypes = [c_int, c_void_p, c_int, c_long, c_long, c_int, c_void_p, c_void_p]
         table = os.environ.get("LSH_GEMM_TABLE", GEMM_TABLE)
         if table != "none" and os.path.exists(table):
@@ -543,6 +545,13 @@ def fused_levels(min_boxes=1):
     """Persistent one-launch levels for later FP32 factors: levels with at least
     min_boxes boxes (0 or False: none; True: every eligible level)."""
     _check(lib().lsh_fused_levels(int(min_boxes)))
+
+
+def apply_fused_levels(min_vectors=-1):
+    """One-launch-per-pass apply levels: Woodbury levels with at least
+    min_vectors box vectors (0: none; 1: every eligible level; -1: the
+    default)."""
+    _check(lib().lsh_apply_fused_levels(int(min_vectors)))
 
 
 def gemm_force_variant(v=-1):

@@ -79,6 +79,62 @@ def test_lowrank_inverse_matches_oracle(prec):
         assert rel(qt[r], M.apply_transpose(x[r])) <= (1e-6 if prec == "fp64" else 2e-5)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_apply_levels_match_oracle(prec):
+    """Every Woodbury level's apply pass in one launch (a workgroup per box
+    vector, intermediates in LDS): M against the oracle's Algorithm 2 on the
+    same factor data, and the full-rank factor against the dense LU."""
+    from paper_2007_12718_amd import lsh
+    w = synth.small(32)
+    tol = 1e-8
+    P = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=tol, proxy_width=3, prec=prec, merge="lowrank")
+    M = hbs.Inverse(hbs.Compression(w.n, w.kappa, 8, tol, 3), w.b, lowrank_tol=tol)
+    sig, _ = dense.DenseSolver(w.n, w.kappa, 4, w.b).solve(w.u_inc)
+    Pf = lsh.Plan(w.n, w.kappa, op_order=4, leaf=8, tol=0.0, proxy_width=2, prec=prec, merge="lowrank")
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, w.n, w.n)) + 1j * rng.standard_normal((2, w.n, w.n))
+    f = dense.rhs(w.b, w.u_inc, w.kappa).reshape(1, w.n, w.n)
+    try:
+        lsh.apply_fused_levels(1)
+        lsh.lsh_profile_only(None)
+        lsh.lsh_profile_enable(True)
+        q = lsh.Factor(P, cuda(w.b)).apply_precond(cuda(x)).cpu().numpy()
+        qf = lsh.Factor(Pf, cuda(w.b)).apply_precond(cuda(f)).cpu().numpy()
+        names = lsh.lsh_profile_names()
+    finally:
+        lsh.lsh_profile_enable(False)
+        lsh.apply_fused_levels(-1)
+    sfx = "f64" if prec == "fp64" else "f32"
+    assert f"level_up_{sfx}" in names and f"level_down_{sfx}" in names
+    for r in range(2):
+        assert rel(q[r], M.apply(x[r])) <= (1e-6 if prec == "fp64" else 2e-5)
+    assert rel(qf[0], sig[0]) <= (1e-11 if prec == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp32", 1), ("fp32", 3)])
+def test_fused_apply_levels_match_separate_launches(prec, nrhs):
+    """The bumps-256 workload (n = 256, 10 levels, tol 1e-4): M x with every
+    Woodbury level fused, with the default choice, and with none fused agree
+    to rounding (the products sum in different orders)."""
+    import torch
+    from paper_2007_12718_amd import lsh
+    w = synth.bumps20()
+    P = lsh.Plan(w.n, w.kappa, op_order=w.op_order, leaf=w.leaf, tol=w.tol, proxy_width=2, prec=prec)
+    F = lsh.Factor(P, cuda(w.b))
+    rng = np.random.default_rng(2)
+    x = cuda(rng.standard_normal((nrhs, w.n, w.n)) + 1j * rng.standard_normal((nrhs, w.n, w.n)))
+    out = {}
+    try:
+        for m in (0, 1, -1):
+            lsh.apply_fused_levels(m)
+            out[m] = F.apply_precond(x).cpu().numpy()
+    finally:
+        lsh.apply_fused_levels(-1)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel(out[1], out[0]) <= tol and rel(out[-1], out[0]) <= tol
+    assert not np.array_equal(out[1], out[0])  # (the fused form did run)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
 def test_lowrank_transpose_dot_product(prec, tol):
     from paper_2007_12718_amd import lsh
