@@ -984,7 +984,8 @@ void cgemv(hipStream_t s, int M, int N, cplx<R> alpha,
 // waves in order.
 template <typename R, int RR, int NV, int WS>
 __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, cplx<R> alpha,
-                                                const cplx<R>* __restrict__ Mat, long ldm,
+                                                const cplx<R>* __restrict__ Mat,
+                                                const cplx<R>* __restrict__ Mat2, long ldm,
                                                 const cplx<R>* __restrict__ X, long ldx, long xoff2, cplx<R> beta,
                                                 const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
   constexpr int ROWS = WS == 4 ? RR : 4 * RR;  // rows per workgroup
@@ -992,6 +993,8 @@ __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int i0, iend;
   const cplx<R>* Xb = X;
+  const cplx<R>* Mb = Mat;
+  int mrow0 = 0;  // the block's first row in Mb
   if ((int)blockIdx.x < wg1) {
     i0 = blockIdx.x * ROWS;
     iend = R1;
@@ -999,12 +1002,14 @@ __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, 
     i0 = R1 + (blockIdx.x - wg1) * ROWS;
     iend = Rr;
     Xb = X + xoff2;
+    Mb = Mat2;  // (row i of the second block is row i - R1 of Mat2)
+    mrow0 = R1;
   }
   if (WS == 1) i0 += wave * RR;
   const int nr = iend - i0 < RR ? iend - i0 : RR;  // (<= 0: this wave has no rows)
   const int v0 = blockIdx.y * NV;
   const int nv = nvec - v0 < NV ? nvec - v0 : NV;
-  const cplx<R>* row0 = Mat + (long)i0 * ldm;
+  const cplx<R>* row0 = Mb + (long)(i0 - mrow0) * ldm;
   const cplx<R>* xv = Xb + (long)v0 * ldx;
   cplx<R> acc[RR][NV];
 #pragma unroll
@@ -1071,20 +1076,22 @@ __global__ __launch_bounds__(256) void k_cmgemv(int Rr, int R1, int wg1, int C, 
 
 template <typename R, int RR, int NV, int WS>
 static void cmgemv_launch(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat,
-                          long ldm, const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y,
-                          long ldy, int nvec) {
+                          const cplx<R>* Mat2, long ldm, const cplx<R>* X, long ldx, cplx<R> beta,
+                          const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
   constexpr int ROWS = WS == 4 ? RR : 4 * RR;
   const int wg1 = ceil_div(R1, ROWS), wg2 = ceil_div(Rr - R1, ROWS);
   LSH_REQUIRE(ceil_div(nvec, NV) <= 65535, -6, "cmgemv: too many vectors");
   hipLaunchKernelGGL((k_cmgemv<R, RR, NV, WS>), dim3(wg1 + wg2, ceil_div(nvec, NV)), dim3(256), 0, s, Rr, R1, wg1,
-                     C, alpha, Mat, ldm, X, ldx, xoff2, beta, Z, ldz, Y, ldy, nvec);
+                     C, alpha, Mat, Mat2, ldm, X, ldx, xoff2, beta, Z, ldz, Y, ldy, nvec);
 }
 
 template <typename R>
 void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm,
-             const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
+             const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec,
+             const cplx<R>* Mat2) {
   if (Rr <= 0 || nvec <= 0) return;
   if (R1 > Rr) R1 = Rr;
+  if (!Mat2) Mat2 = Mat + (long)R1 * ldm;
   ProfScope ps(sizeof(R) == 4 ? "cmgemv_f32" : "cmgemv_f64", s,
                (double)sizeof(cplx<R>) * ((double)Rr * C + (double)nvec * ((R1 < Rr ? 2.0 : 1.0) * C +
                                                                           (Z ? 2.0 : 1.0) * Rr)));
@@ -1096,7 +1103,7 @@ void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, co
   const long wgs = (long)(ceil_div(R1, rows) + ceil_div(Rr - R1, rows)) * ceil_div(nvec, nvs);
   const bool thin = wgs < 512;
 #define LSH_MG(RRV, NVV, WSS) \
-  cmgemv_launch<R, RRV, NVV, WSS>(s, Rr, R1, xoff2, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec)
+  cmgemv_launch<R, RRV, NVV, WSS>(s, Rr, R1, xoff2, C, alpha, Mat, Mat2, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec)
 #define LSH_MG_NV(RRV, WSS)           \
   if (nvs == 1) LSH_MG(RRV, 1, WSS);  \
   else if (nvs == 2) LSH_MG(RRV, 2, WSS); \
@@ -1117,7 +1124,7 @@ void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, co
 template <typename R>
 void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
             cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec) {
-  cmgemv2<R>(s, Rr, Rr, 0, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec);
+  cmgemv2<R>(s, Rr, Rr, 0, C, alpha, Mat, ldm, X, ldx, beta, Z, ldz, Y, ldy, nvec, nullptr);
 }
 
 // ------------------------------------------------- Gauss-Jordan inverse
@@ -2227,7 +2234,7 @@ void ccast(hipStream_t s, const cplx<R1>* src, cplx<R2>* dst, long n) {
                             const cplx<R>*, long, long, Op, cplx<R>, const cplx<R>*, long, long, cplx<R>*,   \
                             long, long, int, void*, size_t);                                                 \
   template void cmgemv2<R>(hipStream_t, int, int, long, int, cplx<R>, const cplx<R>*, long, const cplx<R>*,   \
-                           long, cplx<R>, const cplx<R>*, long, cplx<R>*, long, int);                        \
+                           long, cplx<R>, const cplx<R>*, long, cplx<R>*, long, int, const cplx<R>*);                        \
   template void ccopy2d<R>(hipStream_t, int, int, const cplx<R>*, long, long, cplx<R>*, long, long, long);   \
   template void gather_cols<R>(hipStream_t, int, int, const cplx<R>*, long, long, const int*, int, int,      \
                                cplx<R>*, long, long, long);                                                  \

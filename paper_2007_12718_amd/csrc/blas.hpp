@@ -76,10 +76,12 @@ template <typename R>
 void cmgemv(hipStream_t s, int Rr, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm, const cplx<R>* X, long ldx,
             cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec);
 // The same with the rows split in two blocks: rows i >= R1 read X + xoff2
-// (each vector's second part), rows i < R1 read X.
+// (each vector's second part), rows i < R1 read X; the second block's rows
+// are Mat2's (row i - R1 of Mat2, ld ldm) when Mat2 is given, else Mat's.
 template <typename R>
 void cmgemv2(hipStream_t s, int Rr, int R1, long xoff2, int C, cplx<R> alpha, const cplx<R>* Mat, long ldm,
-             const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec);
+             const cplx<R>* X, long ldx, cplx<R> beta, const cplx<R>* Z, long ldz, cplx<R>* Y, long ldy, int nvec,
+             const cplx<R>* Mat2 = nullptr);
 
 // GEMM variants (tile shape and LDS depth; prec 1 = FP32, 0 = FP64) and
 // their choice per shape: a tuned table keyed by half-octave buckets of

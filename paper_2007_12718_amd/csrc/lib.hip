@@ -1623,8 +1623,8 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     const int c = P.lev[0].c;
     apply_X<R>(P, F, 0, nrhs, F.rt[1].template as<cplx<R>>(), t1, s);
     cplx<R>* w1 = F.wt[1].template as<cplx<R>>();
-    cmgemv<R>(s, c, c, one, P.Gab<R>(0), c, t1 + c, 2 * c, zero, nullptr, 0, w1, 2 * c, nrhs);
-    cmgemv<R>(s, c, c, one, P.Gabt<R>(0), c, t1, 2 * c, zero, nullptr, 0, w1 + c, 2 * c, nrhs);
+    cmgemv2<R>(s, 2 * c, c, -c, c, one, P.Gab<R>(0), c, t1 + c, 2 * c, zero, nullptr, 0, w1, 2 * c, nrhs,
+               P.Gabt<R>(0));
   }
   // downward pass
   for (int l = 1; l <= L - 1; ++l) {
@@ -1646,8 +1646,15 @@ void apply_M(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64* 
     apply_X<R>(P, F, l, nrhs, t2, t3, s);
     // wt_children = Ghat qt + u
     cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
-    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B, F.tk);
-    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c, B, F.tk);
+    if (B <= skinny<R>()) {  // both blocks in one launch
+      cmgemv2<R>(s, 2 * c, c, -c, c, one, P.Gab<R>(l), c, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B,
+                 P.Gabt<R>(l));
+    } else {
+      shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, t3 + c, 2 * c, one, t1, 2 * c, wc, 2 * c, B,
+                   F.tk);
+      shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, t3, 2 * c, one, t1 + c, 2 * c, wc + c, 2 * c,
+                   B, F.tk);
+    }
   }
   leaf_down<R>(s, F.X.template as<cplx<R>>(), P.U<R>(L), P.mL, P.lev[L].k, F.wt[L].template as<cplx<R>>(), r, q,
                b, k2, P.leaf_origin.as<I2>(), P.leaf_pts.as<I2>(), P.nleaf, P.n, nrhs);
@@ -1675,8 +1682,15 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
     const cplx<R>* wc = F.wt[l + 1].template as<cplx<R>>();
     cplx<R>* vb = F.vb[l].template as<cplx<R>>();
     // vb = Ghat wc
-    shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B, F.tk);
-    shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B, F.tk);
+    if (B <= skinny<R>()) {  // both blocks in one launch
+      cmgemv2<R>(s, 2 * c, c, -c, c, one, P.Gab<R>(l), c, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B,
+                 P.Gabt<R>(l));
+    } else {
+      shared_mv<R>(s, c, c, one, P.Gab<R>(l), P.Gab<R>(l), c, OP_T, wc + c, 2 * c, zero, nullptr, 0, vb, 2 * c, B,
+                   F.tk);
+      shared_mv<R>(s, c, c, one, P.Gabt<R>(l), P.Gab<R>(l), c, OP_N, wc, 2 * c, zero, nullptr, 0, vb + c, 2 * c, B,
+                   F.tk);
+    }
     // t3 = X^T vb ; t2 = wc - diag(S_a^T, S_b^T) t3
     apply_X<R>(P, F, l, nrhs, vb, t3, s, true);
     cgemv<R>(s, c, c, mone, F.ST[l + 1].template as<cplx<R>>(), c, cc, 2 * nb, t3, c, one, wc, c, t2, c, 2 * B);
@@ -1688,8 +1702,8 @@ void apply_MT(const lsh_plan_s& P, const double* b, FactorData<R>& F, const z64*
   {
     const int c = P.lev[0].c;
     const cplx<R>* wc = F.wt[1].template as<cplx<R>>();
-    cmgemv<R>(s, c, c, one, P.Gab<R>(0), c, wc + c, 2 * c, zero, nullptr, 0, t1, 2 * c, nrhs);
-    cmgemv<R>(s, c, c, one, P.Gabt<R>(0), c, wc, 2 * c, zero, nullptr, 0, t1 + c, 2 * c, nrhs);
+    cmgemv2<R>(s, 2 * c, c, -c, c, one, P.Gab<R>(0), c, wc + c, 2 * c, zero, nullptr, 0, t1, 2 * c, nrhs,
+               P.Gabt<R>(0));
     apply_X<R>(P, F, 0, nrhs, t1, F.rt[1].template as<cplx<R>>(), s, true);
   }
   // transposed upward pass: rb_children = X^T (vb + U_l rb_l)
