@@ -206,6 +206,9 @@ def kernel_table(lsh):
     for name in lsh.lsh_profile_names():
         n, ms, work = lsh.lsh_profile_query(name)
         rows[name] = {"launches": n, "ms": round(ms, 3), "work": work}
+        nbytes = lsh.lsh_profile_bytes(name)
+        if nbytes > 0:  # (GEMMs: operand and result bytes beside the flops)
+            rows[name]["bytes"] = nbytes
     return rows
 
 
