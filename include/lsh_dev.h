@@ -105,7 +105,7 @@ int lsh_fused_levels(int min_boxes);
  * LDS; the other levels run the step's six to seven batched products.  The
  * two forms agree to rounding (different summation orders).  Affects later
  * applies (lsh_factor_apply, lsh_solve, lsh_build): 0 never fuses, 1 fuses
- * every such level, -1 restores the default (512). */
+ * every such level, -1 restores the default (128). */
 int lsh_apply_fused_levels(int min_vectors);
 
 #ifdef __cplusplus

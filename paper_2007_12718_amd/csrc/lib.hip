@@ -1,7 +1,7 @@
 // Woodbury levels with at least this many box vectors (lsh_apply_fused_levels;
 // 0: never) whose box vectors fit one workgroup's LDS run each apply pass in
 // one launch (level_up_fused / level_down_fused) instead of six to seven.
-constexpr int kApplyFusedMin = 512;
+constexpr int kApplyFusedMin = 128;
 static int g_apply_fused_min = kApplyFusedMin;
 
 // Host orchestration and the C ABI (include/lsh.h).
