@@ -682,26 +682,41 @@ __global__ __launch_bounds__(64 * BP_CW) void k_bp_chol(const z64* M, const z64*
   const double dout = alpha * reinterpret_cast<const double*>(st + BPS_DOUT)[0];
   const double thr2 = reinterpret_cast<const double*>(st + BPS_THR)[0];
   const int* cand = st + BPS_CAND;
-  {  // S_C: the Gram entries less the depth chunks' partial products, in chunk order
+  {  // S_C: the Gram entries less the depth chunks' partial products, in chunk order.  Each thread
+     // holds PE entries and loads CB chunks of all of them at a time (PE * CB loads in flight).
     const int nch = (j + BP_KCS - 1) / BP_KCS;
     constexpr long CS = (long)BP_B * BP_B;
-    for (int e = tid; e < BP_B * BP_B; e += 64 * BP_CW) {
-      const int a = e / BP_B, c2 = e % BP_B;
-      z64 v = mk(0.0, 0.0);
-      if (a < nc && c2 < nc) {
-        v = M[(long)cand[a] * m + cand[c2]];
-        const z64* pp = part + e;
-        int c = 0;
-        for (; c + 4 <= nch; c += 4) {
-          const z64 p0 = pp[(c + 0) * CS], p1 = pp[(c + 1) * CS], p2 = pp[(c + 2) * CS], p3 = pp[(c + 3) * CS];
-          v = v - p0;
-          v = v - p1;
-          v = v - p2;
-          v = v - p3;
-        }
-        for (; c < nch; ++c) v = v - pp[c * CS];
-      }
-      Ss[a][c2] = v;
+    constexpr int PE = BP_B * BP_B / (64 * BP_CW), CB = 4;
+    static_assert(PE * 64 * BP_CW == BP_B * BP_B, "entries per thread");
+    z64 v[PE];
+    bool live[PE];
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+      const int e = tid + i * 64 * BP_CW, a = e / BP_B, c2 = e % BP_B;
+      live[i] = a < nc && c2 < nc;
+      v[i] = live[i] ? M[(long)cand[a] * m + cand[c2]] : mk(0.0, 0.0);
+    }
+    int c = 0;
+    for (; c + CB <= nch; c += CB) {
+      z64 pv[CB][PE];
+#pragma unroll
+      for (int q = 0; q < CB; ++q)
+#pragma unroll
+        for (int i = 0; i < PE; ++i)
+          pv[q][i] = live[i] ? part[(c + q) * CS + tid + i * 64 * BP_CW] : mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < CB; ++q)
+#pragma unroll
+        for (int i = 0; i < PE; ++i) v[i] = v[i] - pv[q][i];
+    }
+    for (; c < nch; ++c)
+#pragma unroll
+      for (int i = 0; i < PE; ++i)
+        if (live[i]) v[i] = v[i] - part[c * CS + tid + i * 64 * BP_CW];
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+      const int e = tid + i * 64 * BP_CW;
+      Ss[e / BP_B][e % BP_B] = v[i];
     }
     __syncthreads();
   }
