@@ -104,8 +104,11 @@ int lsh_fused_levels(int min_boxes);
  * pass in one launch with a workgroup per box vector and its intermediates in
  * LDS; the other levels run the step's six to seven batched products.  The
  * two forms agree to rounding (different summation orders).  Affects later
- * applies (lsh_factor_apply, lsh_solve, lsh_build): 0 never fuses, 1 fuses
- * every such level, -1 restores the default (128). */
+ * applies of M (lsh_apply_precond with transpose = 0, and the
+ * preconditioner inside lsh_solve); M^T (lsh_apply_precond with transpose = 1,
+ * lsh_solve_adjoint) keeps the batched products.  Process-wide setting, not
+ * thread-safe against concurrent applies: 0 never fuses, 1 fuses every such
+ * level, -1 restores the default (128).  Returns LSH_ERR_INVALID_ARG below -1. */
 int lsh_apply_fused_levels(int min_vectors);
 
 #ifdef __cplusplus

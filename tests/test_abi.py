@@ -45,6 +45,11 @@ def test_bad_arguments_are_reported_not_raised():
     with pytest.raises(lsh.LshError) as e:
         lsh.lsh_correction_weights(5, 0.3)
     assert e.value.code == -1
+    # the fused-apply threshold: -1 (the default) and above; a host-only call
+    with pytest.raises(lsh.LshError) as e:
+        lsh.apply_fused_levels(-2)
+    assert e.value.code == -1
+    lsh.apply_fused_levels(-1)
 
 
 def test_library_sources_allocate_no_device_memory():
