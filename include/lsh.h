@@ -146,7 +146,7 @@ typedef struct {
  * Synchronises the stream (ranks are read back level by level).
  * Row-ID method (for tol >= 1e-7; below, column-pivoted QR): environment
  * LSH_ROWID=block (default) pivots several rows per step, accepting a pivot
- * whose Schur diagonal is at least LSH_BP_ALPHA (default 0.75; 1 = greedy)
+ * whose Schur diagonal is at least LSH_BP_ALPHA (default 0.65; 1 = greedy)
  * times the largest; LSH_ROWID=panel pivots greedily one row at a time.
  * Errors: LSH_ERR_INVALID_ARG for a bad descriptor or LSH_BP_ALPHA outside
  * (0, 1]; LSH_ERR_UNSUPPORTED for sizes beyond the kernels' limits;

@@ -297,12 +297,12 @@ int row_id_matrix(lsh_plan_s& P, z64* A, int m, int np, std::vector<int>& Jh, De
     if (k < 1) k = 1;  // (a zero block still gets one skeleton)
   } else {
     // block-pivoted left-looking Cholesky by default (alpha-greedy with
-    // alpha = LSH_BP_ALPHA, default 0.75; 1 = greedy); LSH_ROWID=panel selects
+    // alpha = LSH_BP_ALPHA, default 0.65; 1 = greedy); LSH_ROWID=panel selects
     // the one-pivot-at-a-time panels (greedy)
     const char* e = std::getenv("LSH_ROWID");
     const bool block = !(e && std::string(e) == "panel");
     const char* ea = std::getenv("LSH_BP_ALPHA");
-    const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
+    const double alpha = (ea && *ea) ? std::atof(ea) : 0.65;
     if (!block)
       k = rowid_gram(s, A, m, np, P.d.tol, J, Ufull, scr.take(rowid_gram_ws(m)));
     else {
@@ -335,7 +335,7 @@ pcache::Key cache_key(const lsh_plan_s& P, int kind, int sx, int sy) {
   std::memcpy(&k.tol, &tol, sizeof(double));
   const char* e = std::getenv("LSH_ROWID");
   const char* ea = std::getenv("LSH_BP_ALPHA");
-  const double alpha = (ea && *ea) ? std::atof(ea) : 0.75;
+  const double alpha = (ea && *ea) ? std::atof(ea) : 0.65;
   k.method = tol == 0 ? 0 : tol < 1e-7 ? 1 : (e && std::string(e) == "panel") ? 2 : 3;
   if (k.method == 3) std::memcpy(&k.alpha, &alpha, sizeof(double));
   return k;
